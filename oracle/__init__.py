@@ -1,0 +1,225 @@
+"""ctypes front end of the plain FP64 CPU oracle (``oracle/oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py``.  It shares no code with the HIP library and
+the product path never imports it.
+
+Every function mirrors one step of the method of Honkonen & Honkonen
+(arXiv:1803.07560); the C source names the section or equation each follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+class Lattice(C.Structure):
+    """Parameters of Eq. Gen2: nx space sites (M), nt time slices (L), nu, D, a, tau,
+    plus the test knobs g (nonlinear coupling, 1 in the paper) and m2 (mass term, 0)."""
+
+    _fields_ = [("nx", C.c_int32), ("nt", C.c_int32), ("nu", C.c_double), ("D", C.c_double),
+                ("a", C.c_double), ("tau", C.c_double), ("g", C.c_double), ("m2", C.c_double)]
+
+    @property
+    def d(self) -> int:
+        return int(self.nx) * int(self.nt)
+
+
+def lattice(nx, nt, nu=1.0, D=1.0, a=1.0, tau=1.0, g=1.0, m2=0.0) -> Lattice:
+    return Lattice(int(nx), int(nt), float(nu), float(D), float(a), float(tau), float(g), float(m2))
+
+
+def sums_len(nx: int) -> int:
+    return 3 + 3 * nx
+
+
+def result_len(nx: int) -> int:
+    return 5 + 2 * nx
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _build
+            _build.build()
+        L = C.CDLL(_LIB_PATH)
+        u32p, u64p, dp = C.POINTER(C.c_uint32), C.POINTER(C.c_uint64), C.POINTER(C.c_double)
+        latp = C.POINTER(Lattice)
+        L.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.oracle_philox4x32_10.restype = None
+        L.oracle_words.argtypes = [C.c_int32, C.c_uint64, C.c_uint64, C.c_uint64, u32p]
+        L.oracle_words.restype = None
+        L.oracle_point.argtypes = [C.c_int32, C.c_uint64, C.c_uint64, dp, dp, C.c_uint64, dp]
+        L.oracle_point.restype = None
+        L.oracle_residual.argtypes = [latp, dp, dp]
+        L.oracle_residual.restype = C.c_int
+        L.oracle_action.argtypes = [latp, dp]
+        L.oracle_action.restype = C.c_double
+        L.oracle_action_batch.argtypes = [latp, C.c_size_t, dp, dp]
+        L.oracle_action_batch.restype = C.c_int
+        for name in ("oracle_sums", "oracle_split_sums"):
+            f = getattr(L, name)
+            f.argtypes = [latp, C.c_uint64, C.c_size_t, u64p, dp, dp, u64p, u64p, dp, C.c_int32]
+            f.restype = C.c_int
+        L.oracle_finalize.argtypes = [C.c_int32, C.c_int32, C.c_size_t, dp, dp, dp, dp]
+        L.oracle_finalize.restype = C.c_int
+        L.oracle_plan_uniform.argtypes = [C.c_int32, dp, dp, C.c_int32, u64p, dp, dp]
+        L.oracle_plan_uniform.restype = C.c_int
+        L.oracle_nsphere.argtypes = [C.c_int32, C.c_uint64, C.c_uint64, dp, dp, C.c_uint64, dp]
+        L.oracle_nsphere.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), _ptr(out, C.c_uint32))
+    return out
+
+
+def words(d: int, seed: int, sub_id: int, index: int) -> np.ndarray:
+    out = np.zeros(d, dtype=np.uint32)
+    lib().oracle_words(d, seed, sub_id, index, _ptr(out, C.c_uint32))
+    return out
+
+
+def point(d: int, seed: int, sub_id: int, lo, hi, index: int) -> np.ndarray:
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    out = np.zeros(d, dtype=np.float64)
+    lib().oracle_point(d, seed, sub_id, _ptr(lo, C.c_double), _ptr(hi, C.c_double), index,
+                       _ptr(out, C.c_double))
+    return out
+
+
+def points(d: int, seed: int, sub_id: int, lo, hi, indices) -> np.ndarray:
+    return np.stack([point(d, seed, sub_id, lo, hi, int(i)) for i in indices])
+
+
+def residual(lat: Lattice, u) -> np.ndarray:
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(lat.d, dtype=np.float64)
+    if lib().oracle_residual(C.byref(lat), _ptr(u, C.c_double), _ptr(out, C.c_double)) != 0:
+        raise ValueError("oracle_residual: invalid arguments")
+    return out
+
+
+def action(lat: Lattice, u) -> float:
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    return float(lib().oracle_action(C.byref(lat), _ptr(u, C.c_double)))
+
+
+def action_batch(lat: Lattice, u) -> np.ndarray:
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, lat.d)
+    out = np.zeros(u.shape[0], dtype=np.float64)
+    if lib().oracle_action_batch(C.byref(lat), u.shape[0], _ptr(u, C.c_double),
+                                 _ptr(out, C.c_double)) != 0:
+        raise ValueError("oracle_action_batch: invalid arguments")
+    return out
+
+
+def _subvol_args(lat, ids, lo, hi, n, offset):
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    ns = ids.shape[0]
+    lo = np.ascontiguousarray(lo, dtype=np.float64).reshape(ns, lat.d)
+    hi = np.ascontiguousarray(hi, dtype=np.float64).reshape(ns, lat.d)
+    n = np.ascontiguousarray(np.broadcast_to(np.asarray(n, dtype=np.uint64), (ns,)))
+    offset = np.ascontiguousarray(np.broadcast_to(np.asarray(offset, dtype=np.uint64), (ns,)))
+    return ids, lo, hi, n, offset
+
+
+def sums(lat: Lattice, seed: int, ids, lo, hi, n, offset=0, nthreads: int | None = None):
+    """Per-subvolume sums records (nsub x (3 + 3 nx))."""
+    ids, lo, hi, n, offset = _subvol_args(lat, ids, lo, hi, n, offset)
+    out = np.zeros((ids.shape[0], sums_len(lat.nx)), dtype=np.float64)
+    nt = nthreads or os.cpu_count() or 1
+    rc = lib().oracle_sums(C.byref(lat), seed, ids.shape[0], _ptr(ids, C.c_uint64),
+                           _ptr(lo, C.c_double), _ptr(hi, C.c_double), _ptr(n, C.c_uint64),
+                           _ptr(offset, C.c_uint64), _ptr(out, C.c_double), nt)
+    if rc != 0:
+        raise ValueError(f"oracle_sums failed ({rc})")
+    return out
+
+
+def split_sums(lat: Lattice, seed: int, ids, lo, hi, n, offset=0, nthreads: int | None = None):
+    """Upper-half sums of w and w^2 per dimension (nsub x 2d)."""
+    ids, lo, hi, n, offset = _subvol_args(lat, ids, lo, hi, n, offset)
+    out = np.zeros((ids.shape[0], 2 * lat.d), dtype=np.float64)
+    nt = nthreads or os.cpu_count() or 1
+    rc = lib().oracle_split_sums(C.byref(lat), seed, ids.shape[0], _ptr(ids, C.c_uint64),
+                                 _ptr(lo, C.c_double), _ptr(hi, C.c_double), _ptr(n, C.c_uint64),
+                                 _ptr(offset, C.c_uint64), _ptr(out, C.c_double), nt)
+    if rc != 0:
+        raise ValueError(f"oracle_split_sums failed ({rc})")
+    return out
+
+
+def finalize(nx: int, d: int, lo, hi, sums_records) -> dict:
+    s = np.ascontiguousarray(sums_records, dtype=np.float64).reshape(-1, sums_len(nx))
+    ns = s.shape[0]
+    lo = np.ascontiguousarray(lo, dtype=np.float64).reshape(ns, d)
+    hi = np.ascontiguousarray(hi, dtype=np.float64).reshape(ns, d)
+    out = np.zeros(result_len(nx), dtype=np.float64)
+    rc = lib().oracle_finalize(nx, d, ns, _ptr(lo, C.c_double), _ptr(hi, C.c_double),
+                               _ptr(s, C.c_double), _ptr(out, C.c_double))
+    if rc != 0:
+        raise ValueError(f"oracle_finalize failed ({rc})")
+    return {"Z": out[0], "Z_err": out[1], "log_Z": out[2], "ess": out[3], "n_evals": out[4],
+            "C": out[5:5 + nx].copy(), "C_err": out[5 + nx:5 + 2 * nx].copy()}
+
+
+def plan_uniform(d: int, box_lo, box_hi, k: int):
+    box_lo = np.ascontiguousarray(np.broadcast_to(np.asarray(box_lo, dtype=np.float64), (d,)))
+    box_hi = np.ascontiguousarray(np.broadcast_to(np.asarray(box_hi, dtype=np.float64), (d,)))
+    cnt = 1 << k
+    ids = np.zeros(cnt, dtype=np.uint64)
+    lo = np.zeros((cnt, d), dtype=np.float64)
+    hi = np.zeros((cnt, d), dtype=np.float64)
+    if lib().oracle_plan_uniform(d, _ptr(box_lo, C.c_double), _ptr(box_hi, C.c_double), k,
+                                 _ptr(ids, C.c_uint64), _ptr(lo, C.c_double),
+                                 _ptr(hi, C.c_double)) != 0:
+        raise ValueError("oracle_plan_uniform: invalid arguments")
+    return ids, lo, hi
+
+
+def budget_split(budget: int, count: int) -> np.ndarray:
+    """Samples per subvolume for a total budget over `count` subvolumes in id order:
+    floor(B/count) each, plus one for the first B mod count."""
+    base, extra = divmod(int(budget), int(count))
+    n = np.full(count, base, dtype=np.uint64)
+    n[:extra] += 1
+    return n
+
+
+def integrate_uniform(lat: Lattice, seed: int, box_lo, box_hi, k: int, budget: int,
+                      nthreads: int | None = None) -> dict:
+    """Oracle of the uniform-split convenience entry: plan, sums, finalize."""
+    ids, lo, hi = plan_uniform(lat.d, box_lo, box_hi, k)
+    n = budget_split(budget, len(ids))
+    s = sums(lat, seed, ids, lo, hi, n, 0, nthreads)
+    res = finalize(lat.nx, lat.d, lo, hi, s)
+    res["sums"] = s
+    return res
+
+
+def nsphere(dim: int, seed: int, lo, hi, n: int, sub_id: int = 1) -> dict:
+    lo = np.ascontiguousarray(np.broadcast_to(np.asarray(lo, dtype=np.float64), (dim,)))
+    hi = np.ascontiguousarray(np.broadcast_to(np.asarray(hi, dtype=np.float64), (dim,)))
+    out = np.zeros(5, dtype=np.float64)
+    if lib().oracle_nsphere(dim, seed, sub_id, _ptr(lo, C.c_double), _ptr(hi, C.c_double), n,
+                            _ptr(out, C.c_double)) != 0:
+        raise ValueError("oracle_nsphere: invalid arguments")
+    return {"n": out[0], "sum_f": out[1], "sum_f2": out[2], "result": out[3], "abserr": out[4]}

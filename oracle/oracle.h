@@ -1,0 +1,98 @@
+/*
+ * Plain FP64 CPU oracle for the Monte Carlo lattice functional integral of
+ * Burgers' equation (Honkonen & Honkonen, arXiv:1803.07560).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously correct
+ * statement of what the GPU path computes.  Only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark load it.  It shares no code,
+ * header, constant or helper with the HIP library, and the HIP library never
+ * links or calls it.
+ *
+ * Lattice: nt time slices (the paper's L) by nx space sites (the paper's M);
+ * variable k = l*nx + m holds v(t_l, x_m), 0-based (paper section 2, Eq. Gen2).
+ *
+ * Every function that can fail returns 0 on success and a negative value on
+ * invalid arguments; nothing aborts.
+ */
+#ifndef BURGERS_ORACLE_H
+#define BURGERS_ORACLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Parameters of the discretised action (Eq. Gen2 and the constants after it).
+ * g multiplies the nonlinear term (1 in the paper; 0 gives the Gaussian case)
+ * and m2 adds (m2/2)*sum(u^2) (0 in the paper; a regulator for closed forms). */
+typedef struct {
+    int32_t nx, nt;
+    double nu, D, a, tau;
+    double g, m2;
+} oracle_lattice;
+
+/* Number of doubles in one per-subvolume sums record:
+ * [n, sum w, sum w^2, sum p_r w (nx), sum (p_r w)^2 (nx), sum p_r w^2 (nx)]. */
+#define ORACLE_SUMS_LEN(nx) (3 + 3 * (nx))
+
+/* Number of doubles in the finalize output:
+ * [Z, Z_err, log_Z, ess, n_evals, C (nx), C_err (nx)]. */
+#define ORACLE_RESULT_LEN(nx) (5 + 2 * (nx))
+
+/* Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11). */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* The d uniform 32-bit words of sample `index` of subvolume `id`:
+ * block j uses counter (lo32(q), hi32(q), lo32(id), hi32(id)) with
+ * q = index*ceil(d/4) + j, key = (lo32(seed), hi32(seed)). */
+void oracle_words(int32_t d, uint64_t seed, uint64_t id, uint64_t index, uint32_t *words);
+
+/* Map words to the point u in the box [lo, hi): u_k = lo_k + (x_k + 1/2) * (hi_k - lo_k) / 2^32,
+ * evaluated as fma(x, scale, base) with scale = (hi-lo)*2^-32 and base = lo + scale/2. */
+void oracle_point(int32_t d, uint64_t seed, uint64_t id, const double *lo, const double *hi,
+                  uint64_t index, double *u);
+
+/* Residual R_{l,m} of the discretised Burgers equation at every site (the
+ * bracket squared in Eq. Gen2), periodic in space and time. R has nt*nx entries. */
+int oracle_residual(const oracle_lattice *lat, const double *u, double *R);
+
+/* The action S[u] = sum R^2 / (2 D tau) + (m2/2) sum u^2 (exponent of Eq. Gen2). */
+double oracle_action(const oracle_lattice *lat, const double *u);
+
+/* S for n points stored row-major (n x d). */
+int oracle_action_batch(const oracle_lattice *lat, size_t n, const double *u, double *S);
+
+/* Per-subvolume Monte Carlo sums over samples offset[s] .. offset[s]+n[s]-1 of
+ * subvolume s (boxes lo/hi row-major nsub x d).  Sums are Neumaier-compensated
+ * and taken in sample order; threads split the subvolume list only. */
+int oracle_sums(const oracle_lattice *lat, uint64_t seed, size_t nsub, const uint64_t *id,
+                const double *lo, const double *hi, const uint64_t *n, const uint64_t *offset,
+                double *sums, int32_t nthreads);
+
+/* Split statistics for one subvolume list: for every dimension j, the sums of w
+ * and w^2 over the samples in the upper half of the box along j (word j has its
+ * top bit set).  out is nsub x 2d: [sum_U w (d), sum_U w^2 (d)]. */
+int oracle_split_sums(const oracle_lattice *lat, uint64_t seed, size_t nsub, const uint64_t *id,
+                      const double *lo, const double *hi, const uint64_t *n,
+                      const uint64_t *offset, double *out, int32_t nthreads);
+
+/* Combine per-subvolume sums into Z, C(r) = N(r)/Z and their standard errors. */
+int oracle_finalize(int32_t nx, int32_t d, size_t nsub, const double *lo, const double *hi,
+                    const double *sums, double *result);
+
+/* Uniform split of a box into 2^k subvolumes by bisecting dims 0..k-1 in turn;
+ * heap ids 2^k .. 2^(k+1)-1 in increasing order. */
+int oracle_plan_uniform(int32_t d, const double *box_lo, const double *box_hi, int32_t k,
+                        uint64_t *id, double *lo, double *hi);
+
+/* Plain Monte Carlo of the N-sphere integrand f(x) = sqrt(1 - |x|^2) (0 outside
+ * the unit ball) over a box: out = [n, sum f, sum f^2, result, abserr]. */
+int oracle_nsphere(int32_t dim, uint64_t seed, uint64_t id, const double *lo, const double *hi,
+                   uint64_t n, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
