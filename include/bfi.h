@@ -1,0 +1,297 @@
+/*
+ * bfi.h -- C ABI of the MI355X (gfx950) library for Monte Carlo evaluation of
+ * the lattice functional integral of Burgers' equation (Honkonen & Honkonen,
+ * "Modelling turbulence via numerical functional integration using Burgers'
+ * equation", arXiv:1803.07560).
+ *
+ * What is computed (section 2, Eq. Gen2): over a box of d = nx*nt lattice
+ * variables v(t_l, x_m), periodic in space and time, the normalisation
+ *     Z = integral of exp(-S[u]) du
+ * and the equal-time two-point correlation
+ *     C(r) = integral of u_{0,0} u_{0,r} exp(-S[u]) du / Z,   r = 0 .. nx-1,
+ * normalised as in section 4 (divided by the same integral with the velocity
+ * factors set to 1).  S is the discretised action of Eq. Gen2:
+ *     R_{l,m} = v_{l+1,m} - v_{l,m}
+ *             + tau [ g v_{l,m} (v_{l,m+1} - v_{l,m-1}) / (2a)
+ *                     - nu (v_{l,m+1} - 2 v_{l,m} + v_{l,m-1}) / a^2 ],
+ *     S = sum_{l,m} R_{l,m}^2 / (2 D tau) + (m2/2) sum u^2,
+ * with g = 1 and m2 = 0 in the paper (the two knobs exist for closed-form checks).
+ * The box is split into subvolumes, each an extent per dimension (section 3),
+ * integrated by plain Monte Carlo; the error bar of a subvolume is V s / sqrt(n)
+ * (the serial integrand's "result, absolute error" of section 3).
+ *
+ * Points.  Sample i of subvolume `id` takes ceil(d/4) Philox4x32-10 blocks
+ * (Salmon et al., SC'11), block j with key (lo32(seed), hi32(seed)) and counter
+ * (lo32(q), hi32(q), lo32(id), hi32(id)), q = i*ceil(d/4) + j; word k maps to
+ *     u_k = fma((double)x_k, scale_k, base_k),
+ *     scale_k = (hi_k - lo_k) * 2^-32,  base_k = lo_k + scale_k / 2,
+ * so u_k lies strictly inside (lo_k, hi_k).  Variable k = l*nx + m.
+ *
+ * Conventions for every entry point:
+ *   - Host pointers are caller-owned and only read (or written, for outputs)
+ *     during the call; nothing is retained unless stated.
+ *   - Device pointers (suffix _dev) are caller-owned device memory that must
+ *     stay valid until the work enqueued on the given stream has completed.
+ *   - A stream argument is a hipStream_t passed as void*; NULL is the null stream.
+ *   - Every call returns a bfi_status; on failure bfi_last_error() returns a
+ *     thread-local message.  Nothing aborts, nothing throws across the ABI.
+ *   - A context is not thread-safe; the server API is.
+ */
+#ifndef BFI_H
+#define BFI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BFI_OK = 0,
+    BFI_EINVAL = -1,       /* invalid argument (shape, parameter, box, count) */
+    BFI_ENOMEM = -2,       /* device or host allocation failed */
+    BFI_EDEVICE = -3,      /* a HIP runtime call failed */
+    BFI_EUNSUPPORTED = -4, /* lattice shape or option not compiled in */
+    BFI_EBUSY = -5,        /* server full: no slot or memory for the request now */
+    BFI_ECANCELLED = -6,   /* request was cancelled */
+    BFI_EBUDGET = -7,      /* adaptive run stopped at its evaluation budget */
+    BFI_ENOTFOUND = -8     /* unknown ticket */
+} bfi_status;
+
+/* Arithmetic of the action and the weight.  Sums are FP64 in both forms. */
+typedef enum {
+    BFI_FP64 = 0,         /* action, exp(-S) and sums in FP64 */
+    BFI_FP32_SHIFTED = 1  /* action and exp in FP32 with a per-thread shift sigma:
+                             w = exp(sigma - S), sums in FP64 relative to exp(-sigma) */
+} bfi_precision;
+
+/* Lattice and parameters of Eq. Gen2.  nx = space sites (the paper's M),
+ * nt = time slices (L); the paper's run is nx = 10, nt = 2, a = tau = nu = D = 1. */
+typedef struct {
+    int32_t nx, nt;
+    double nu, D, a, tau;
+    double g;   /* nonlinear coupling, 1 for Burgers */
+    double m2;  /* mass term, 0 for Burgers */
+} bfi_lattice;
+
+/* A list of subvolumes (host arrays, caller-owned).
+ *   id[i]      heap id (root box 1, children 2k and 2k+1); keys the Philox stream
+ *   lo, hi     count x d row-major extents, lo < hi, finite
+ *   n[i]       samples, >= 2
+ *   offset[i]  index of the first sample (a subvolume continues its own stream
+ *              when evaluated again at offset = samples already taken) */
+typedef struct {
+    size_t count;
+    const uint64_t *id;
+    const double *lo;
+    const double *hi;
+    const uint64_t *n;
+    const uint64_t *offset;
+} bfi_subvolumes;
+
+/* Launch shape.  A NULL bfi_launch* takes the tuned (else default) shape for
+ * the lattice and precision; in a given struct, samples_per_thread = 0,
+ * block = 0 and persistent = -1 each take the tuned value.  Work items hold
+ * samples_per_thread * block consecutive samples of one subvolume. */
+typedef struct {
+    int32_t samples_per_thread; /* K: samples each thread takes per work item */
+    int32_t block;              /* threads per block: 64, 128 or 256 */
+    int32_t persistent;         /* 1: persistent kernel draining a device queue;
+                                   0: one block per work item; -1: tuned */
+    int32_t use_graph;          /* 1: replay a captured hipGraph (plans only) */
+} bfi_launch;
+
+/* Number of doubles in one partial record:
+ *   [n, sigma, S_w, S_w2, S_pw[nx], S_pw2[nx], S_pww[nx]]
+ * with sums over the samples of w = exp(-S) scaled by exp(sigma) (first-order
+ * sums: S_w, S_pw) or exp(2 sigma) (second-order: S_w2, S_pw2 = sum (p_r w)^2,
+ * S_pww = sum p_r w^2), p_r = u_{0,0} u_{0,r}.  sigma is 0 in BFI_FP64. */
+#define BFI_PARTIAL_LEN(nx) (4 + 3 * (nx))
+/* Split statistics per subvolume: [sigma, S_U w (d), S_U w^2 (d)], sums over the
+ * samples in the upper half of the subvolume along each dimension (Philox word
+ * with its top bit set), scaled like the partial record of the same sigma. */
+#define BFI_SPLIT_LEN(d) (1 + 2 * (d))
+
+#define BFI_MAX_NX 64
+#define BFI_MAX_D 64
+
+typedef struct {
+    double Z, Z_err;        /* Z and its standard error (may over/underflow; see log_Z) */
+    double log_Z;           /* natural log of Z, finite whenever some weight is nonzero */
+    double ess;             /* effective sample size (sum W)^2 / sum W^2 */
+    double n_evals;         /* integrand evaluations in the estimate */
+    int32_t nx;             /* number of valid entries of C and C_err */
+    double C[BFI_MAX_NX];     /* C(r) = N(r)/Z */
+    double C_err[BFI_MAX_NX]; /* delta-method standard error of C(r) */
+} bfi_result;
+
+typedef struct bfi_context bfi_context;
+typedef struct bfi_plan bfi_plan;
+typedef struct bfi_server bfi_server;
+
+const char *bfi_status_string(bfi_status s);
+/* Message of the last failure on this thread (empty if none). */
+const char *bfi_last_error(void);
+/* BFI_OK if (nx, nt) has compiled kernels, BFI_EUNSUPPORTED otherwise. */
+bfi_status bfi_shape_supported(int32_t nx, int32_t nt);
+/* Writes up to `cap` supported shapes as (nx, nt) pairs; *count = number supported. */
+bfi_status bfi_supported_shapes(int32_t *pairs, int32_t cap, int32_t *count);
+
+/* Context on one HIP device: owns a stream, staging buffers and the tuned
+ * launch table.  Errors: EINVAL (bad device), EDEVICE. */
+bfi_status bfi_context_create(int32_t device, bfi_context **out);
+bfi_status bfi_context_destroy(bfi_context *ctx);
+
+/* Evaluate per-subvolume partial records (paper section 3: the integral over
+ * each subvolume separately).  partials: host, count x BFI_PARTIAL_LEN(nx);
+ * split: host, count x BFI_SPLIT_LEN(d), or NULL to skip split statistics
+ * (supported for d <= 32).  Blocking.  Errors: EINVAL, EUNSUPPORTED, ENOMEM,
+ * EDEVICE. */
+bfi_status bfi_eval(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
+                    uint64_t seed, const bfi_subvolumes *subs, const bfi_launch *launch,
+                    double *partials, double *split);
+
+/* Plans: the subvolume list uploaded once, work items and buffers resident in
+ * device memory, optionally a captured graph; run many times. */
+bfi_status bfi_plan_create(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
+                           const bfi_subvolumes *subs, const bfi_launch *launch,
+                           bfi_plan **out);
+/* Enqueue one evaluation of the whole plan on `stream` (NULL: the context's
+ * stream).  partials_dev: device, count x BFI_PARTIAL_LEN(nx), written when the
+ * stream reaches it; NULL keeps them in the plan's own buffer. */
+bfi_status bfi_plan_run(bfi_plan *plan, uint64_t seed, double *partials_dev, void *stream);
+/* Wait for the plan's last run and copy its partial records to host. */
+bfi_status bfi_plan_partials(bfi_plan *plan, double *partials);
+/* Work items of the plan and the launch shape it resolved to. */
+bfi_status bfi_plan_info(const bfi_plan *plan, uint64_t *n_items, uint64_t *n_evals,
+                         bfi_launch *resolved);
+/* Duration in milliseconds of the Monte Carlo kernel of the plan's last run,
+ * from HIP events recorded around it on the run's stream (waits for it). */
+bfi_status bfi_plan_kernel_ms(bfi_plan *plan, double *ms);
+bfi_status bfi_plan_destroy(bfi_plan *plan);
+
+/* Combine partial records into Z, C(r) and their errors (section 4's
+ * normalisation; delta method for the ratio).  Host only.  The subvolume list
+ * supplies the volumes.  Errors: EINVAL (n < 2, bad box). */
+bfi_status bfi_finalize(const bfi_lattice *lat, const bfi_subvolumes *subs,
+                        const double *partials, bfi_result *out);
+
+/* Convenience: split [box_lo, box_hi] into 2^split_log2 subvolumes by bisecting
+ * dims 0, 1, ... in turn (dim t mod d at level t; heap ids 2^k .. 2^(k+1)-1),
+ * give subvolume i (id order) floor(budget/2^k) + (i < budget mod 2^k) samples
+ * from offset 0, evaluate and finalize.  box_lo/box_hi: host, d doubles. */
+bfi_status bfi_integrate(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
+                         uint64_t seed, const double *box_lo, const double *box_hi,
+                         int32_t split_log2, uint64_t budget, const bfi_launch *launch,
+                         bfi_result *out);
+
+/* Error-driven adaptive refinement (section 3: subvolumes are subdivided until a
+ * convergence criterion holds).  Starts from the uniform 2^split_log2 partition
+ * with n_min samples each; every round ranks leaves by their contribution to the
+ * variance of C, and either splits a leaf at the midpoint of the dimension
+ * minimising sigma_lower + sigma_upper (children start fresh streams) or doubles
+ * its samples (continuing its stream), until max_r sigma_C(r)/|C(0)| <= target or
+ * max_evals is spent.  Leaves keep n_min <= n <= n_max.  out gets the estimate;
+ * the final partition is written to the caller's arrays when non-NULL
+ * (capacity `cap` leaves; *n_leaves gets the count).  Returns BFI_EBUDGET (with a
+ * valid estimate) if the budget ran out first. */
+typedef struct {
+    double target_rel_err;  /* on max_r sigma_C(r) / |C(0)| */
+    uint64_t max_evals;
+    uint64_t n_min, n_max;  /* per-leaf sample bounds, n_min >= 2 */
+    int32_t split_log2;     /* initial uniform partition */
+    int32_t max_rounds;
+    double refine_fraction; /* share of the total variance refined per round, (0, 1] */
+} bfi_adaptive_config;
+
+typedef struct {
+    int32_t rounds;
+    uint64_t leaves;
+    uint64_t evals;
+    double rel_err;         /* achieved max_r sigma_C(r)/|C(0)| */
+} bfi_adaptive_stats;
+
+bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
+                                  uint64_t seed, const double *box_lo, const double *box_hi,
+                                  const bfi_adaptive_config *cfg, const bfi_launch *launch,
+                                  bfi_result *out, bfi_adaptive_stats *stats,
+                                  uint64_t *leaf_id, double *leaf_lo, double *leaf_hi,
+                                  uint64_t *leaf_n, uint64_t *leaf_offset, size_t cap,
+                                  size_t *n_leaves);
+
+/* One refinement decision of the adaptive policy, exposed for host-side tests.
+ * For each leaf: partial record (BFI_PARTIAL_LEN(nx)) and split statistics
+ * (BFI_SPLIT_LEN(d)) of its current samples.  action[i] is set to -1 (keep),
+ * 0 (double the samples) or 1 + j (split along dimension j). */
+bfi_status bfi_adaptive_decide(const bfi_lattice *lat, const bfi_subvolumes *leaves,
+                               const double *partials, const double *split,
+                               const bfi_adaptive_config *cfg, int32_t *action);
+
+/* Continuous-batching request server on one context.  Requests are admitted
+ * while their device state fits `memory_budget` bytes and a slot is free; their
+ * partial sums stay resident on the device; every scheduling step packs chunks
+ * of all admitted requests into persistent kernels, one per lattice shape. */
+typedef struct {
+    uint64_t memory_budget;     /* bytes of request state on the device */
+    int32_t max_requests;       /* admitted requests at once */
+    int32_t chunks_per_step;    /* work items per request per step (fairness) */
+    int32_t max_pending;        /* submitted but not admitted; EBUSY beyond it */
+} bfi_server_config;
+
+typedef struct {
+    bfi_lattice lat;
+    bfi_precision prec;
+    uint64_t seed;
+    double box;               /* box [-box, box]^d */
+    int32_t split_log2;       /* uniform partition */
+    uint64_t budget;          /* total samples */
+} bfi_request;
+
+typedef struct {
+    uint64_t submitted, completed, cancelled, rejected;
+    uint64_t steps, evals;
+    double busy_seconds;      /* time with kernels in flight */
+} bfi_server_stats;
+
+bfi_status bfi_server_create(bfi_context *ctx, const bfi_server_config *cfg, bfi_server **out);
+/* Non-blocking.  Errors: EINVAL, EUNSUPPORTED, EBUSY (pending queue full). */
+bfi_status bfi_server_submit(bfi_server *srv, const bfi_request *req, uint64_t *ticket);
+/* *done = 1 when finished; then out holds the result and the ticket is released.
+ * latency_s (optional) gets submit-to-completion seconds. */
+bfi_status bfi_server_poll(bfi_server *srv, uint64_t ticket, bfi_result *out, int32_t *done,
+                           double *latency_s);
+/* Blocks until done or timeout_s elapses (*done = 0). */
+bfi_status bfi_server_wait(bfi_server *srv, uint64_t ticket, double timeout_s, bfi_result *out,
+                           int32_t *done, double *latency_s);
+bfi_status bfi_server_cancel(bfi_server *srv, uint64_t ticket);
+bfi_status bfi_server_stats_get(bfi_server *srv, bfi_server_stats *out);
+bfi_status bfi_server_destroy(bfi_server *srv);
+
+/* Autotuner: time candidate launch shapes (samples_per_thread x block x
+ * persistent) on a synthetic uniform partition of the lattice with about
+ * `evals_per_trial` samples, keep the fastest for (shape, precision) in the
+ * context, and return it with its rate.  Blocking. */
+bfi_status bfi_autotune(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
+                        uint64_t evals_per_trial, bfi_launch *best, double *best_evals_per_s);
+/* Save / load the context's tuned table as JSON (keyed by device architecture;
+ * entries for another architecture are ignored on load). */
+bfi_status bfi_tune_save(const bfi_context *ctx, const char *path);
+bfi_status bfi_tune_load(bfi_context *ctx, const char *path);
+
+/* Test hooks for bit-exact parity.
+ * bfi_debug_points: the points of samples index[0..n) of one subvolume as the
+ * kernels generate them, FP64 (or, for BFI_FP32_SHIFTED, the FP32 point widened
+ * to double); out: host n x d.  d <= BFI_MAX_D.
+ * bfi_debug_action: S for n points (host, n x d) with the kernels' action
+ * (FP32 form: points rounded to float, S widened); out_S: host, n. */
+bfi_status bfi_debug_points(bfi_context *ctx, int32_t d, bfi_precision prec, uint64_t seed,
+                            uint64_t id, const double *lo, const double *hi,
+                            const uint64_t *index, uint64_t n, double *out);
+bfi_status bfi_debug_action(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
+                            uint64_t n, const double *points, double *out_S);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,458 @@
+"""ctypes binding of ``libbfi.so`` (declared in ``include/bfi.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  There is no fallback -- if the library is missing, loading raises.
+Functions carry the names of the C entry points.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbfi.so")
+
+BFI_FP64 = 0
+BFI_FP32_SHIFTED = 1
+PRECISIONS = {"fp64": BFI_FP64, "fp32": BFI_FP32_SHIFTED, BFI_FP64: BFI_FP64,
+              BFI_FP32_SHIFTED: BFI_FP32_SHIFTED}
+
+STATUS = {0: "BFI_OK", -1: "BFI_EINVAL", -2: "BFI_ENOMEM", -3: "BFI_EDEVICE",
+          -4: "BFI_EUNSUPPORTED", -5: "BFI_EBUSY", -6: "BFI_ECANCELLED", -7: "BFI_EBUDGET",
+          -8: "BFI_ENOTFOUND"}
+MAX_NX = 64
+MAX_D = 64
+
+
+class BfiError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        self.message = message
+
+
+class bfi_lattice(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("nt", C.c_int32), ("nu", C.c_double), ("D", C.c_double),
+                ("a", C.c_double), ("tau", C.c_double), ("g", C.c_double), ("m2", C.c_double)]
+
+    @property
+    def d(self) -> int:
+        return int(self.nx) * int(self.nt)
+
+
+class bfi_subvolumes(C.Structure):
+    _fields_ = [("count", C.c_size_t), ("id", C.POINTER(C.c_uint64)),
+                ("lo", C.POINTER(C.c_double)), ("hi", C.POINTER(C.c_double)),
+                ("n", C.POINTER(C.c_uint64)), ("offset", C.POINTER(C.c_uint64))]
+
+
+class bfi_launch(C.Structure):
+    _fields_ = [("samples_per_thread", C.c_int32), ("block", C.c_int32),
+                ("persistent", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class bfi_result(C.Structure):
+    _fields_ = [("Z", C.c_double), ("Z_err", C.c_double), ("log_Z", C.c_double),
+                ("ess", C.c_double), ("n_evals", C.c_double), ("nx", C.c_int32),
+                ("C", C.c_double * MAX_NX), ("C_err", C.c_double * MAX_NX)]
+
+    def to_dict(self) -> dict:
+        n = int(self.nx)
+        return {"Z": self.Z, "Z_err": self.Z_err, "log_Z": self.log_Z, "ess": self.ess,
+                "n_evals": self.n_evals, "C": np.array(self.C[:n]),
+                "C_err": np.array(self.C_err[:n])}
+
+
+class bfi_adaptive_config(C.Structure):
+    _fields_ = [("target_rel_err", C.c_double), ("max_evals", C.c_uint64),
+                ("n_min", C.c_uint64), ("n_max", C.c_uint64), ("split_log2", C.c_int32),
+                ("max_rounds", C.c_int32), ("refine_fraction", C.c_double)]
+
+
+class bfi_adaptive_stats(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("leaves", C.c_uint64), ("evals", C.c_uint64),
+                ("rel_err", C.c_double)]
+
+
+class bfi_server_config(C.Structure):
+    _fields_ = [("memory_budget", C.c_uint64), ("max_requests", C.c_int32),
+                ("chunks_per_step", C.c_int32), ("max_pending", C.c_int32)]
+
+
+class bfi_request(C.Structure):
+    _fields_ = [("lat", bfi_lattice), ("prec", C.c_int32), ("seed", C.c_uint64),
+                ("box", C.c_double), ("split_log2", C.c_int32), ("budget", C.c_uint64)]
+
+
+class bfi_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("cancelled", C.c_uint64),
+                ("rejected", C.c_uint64), ("steps", C.c_uint64), ("evals", C.c_uint64),
+                ("busy_seconds", C.c_double)]
+
+
+def partial_len(nx: int) -> int:
+    return 4 + 3 * nx
+
+
+def split_len(d: int) -> int:
+    return 1 + 2 * d
+
+
+_P = C.POINTER
+_vp = C.c_void_p
+_SIGNATURES = {
+    "bfi_status_string": ([C.c_int], C.c_char_p),
+    "bfi_last_error": ([], C.c_char_p),
+    "bfi_shape_supported": ([C.c_int32, C.c_int32], C.c_int),
+    "bfi_supported_shapes": ([_P(C.c_int32), C.c_int32, _P(C.c_int32)], C.c_int),
+    "bfi_context_create": ([C.c_int32, _P(_vp)], C.c_int),
+    "bfi_context_destroy": ([_vp], C.c_int),
+    "bfi_eval": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, _P(bfi_subvolumes), _P(bfi_launch),
+                  _P(C.c_double), _P(C.c_double)], C.c_int),
+    "bfi_plan_create": ([_vp, _P(bfi_lattice), C.c_int, _P(bfi_subvolumes), _P(bfi_launch),
+                         _P(_vp)], C.c_int),
+    "bfi_plan_run": ([_vp, C.c_uint64, _vp, _vp], C.c_int),
+    "bfi_plan_partials": ([_vp, _P(C.c_double)], C.c_int),
+    "bfi_plan_info": ([_vp, _P(C.c_uint64), _P(C.c_uint64), _P(bfi_launch)], C.c_int),
+    "bfi_plan_kernel_ms": ([_vp, _P(C.c_double)], C.c_int),
+    "bfi_plan_destroy": ([_vp], C.c_int),
+    "bfi_finalize": ([_P(bfi_lattice), _P(bfi_subvolumes), _P(C.c_double), _P(bfi_result)],
+                     C.c_int),
+    "bfi_integrate": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, _P(C.c_double), _P(C.c_double),
+                       C.c_int32, C.c_uint64, _P(bfi_launch), _P(bfi_result)], C.c_int),
+    "bfi_integrate_adaptive": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, _P(C.c_double),
+                                _P(C.c_double), _P(bfi_adaptive_config), _P(bfi_launch),
+                                _P(bfi_result), _P(bfi_adaptive_stats), _P(C.c_uint64),
+                                _P(C.c_double), _P(C.c_double), _P(C.c_uint64), _P(C.c_uint64),
+                                C.c_size_t, _P(C.c_size_t)], C.c_int),
+    "bfi_adaptive_decide": ([_P(bfi_lattice), _P(bfi_subvolumes), _P(C.c_double), _P(C.c_double),
+                             _P(bfi_adaptive_config), _P(C.c_int32)], C.c_int),
+    "bfi_server_create": ([_vp, _P(bfi_server_config), _P(_vp)], C.c_int),
+    "bfi_server_submit": ([_vp, _P(bfi_request), _P(C.c_uint64)], C.c_int),
+    "bfi_server_poll": ([_vp, C.c_uint64, _P(bfi_result), _P(C.c_int32), _P(C.c_double)], C.c_int),
+    "bfi_server_wait": ([_vp, C.c_uint64, C.c_double, _P(bfi_result), _P(C.c_int32),
+                         _P(C.c_double)], C.c_int),
+    "bfi_server_cancel": ([_vp, C.c_uint64], C.c_int),
+    "bfi_server_stats_get": ([_vp, _P(bfi_server_stats)], C.c_int),
+    "bfi_server_destroy": ([_vp], C.c_int),
+    "bfi_autotune": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, _P(bfi_launch), _P(C.c_double)],
+                     C.c_int),
+    "bfi_tune_save": ([_vp, C.c_char_p], C.c_int),
+    "bfi_tune_load": ([_vp, C.c_char_p], C.c_int),
+    "bfi_debug_points": ([_vp, C.c_int32, C.c_int, C.c_uint64, C.c_uint64, _P(C.c_double),
+                          _P(C.c_double), _P(C.c_uint64), C.c_uint64, _P(C.c_double)], C.c_int),
+    "bfi_debug_action": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, _P(C.c_double),
+                          _P(C.c_double)], C.c_int),
+}
+EXPORTED = tuple(_SIGNATURES)
+
+_lib = None
+
+
+def load():
+    """Load libbfi.so; raises if it has not been built (no CPU fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_1803_07560_amd/build.py` (or __graft_entry__.build())")
+        lib = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = lib
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        msg = load().bfi_last_error()
+        raise BfiError(status, where, msg.decode() if msg else "")
+
+
+def _dp(a):
+    return a.ctypes.data_as(_P(C.c_double))
+
+
+def _u64p(a):
+    return a.ctypes.data_as(_P(C.c_uint64))
+
+
+def _prec(p) -> int:
+    return PRECISIONS[p]
+
+
+def lattice(nx, nt, nu=1.0, D=1.0, a=1.0, tau=1.0, g=1.0, m2=0.0) -> bfi_lattice:
+    return bfi_lattice(int(nx), int(nt), float(nu), float(D), float(a), float(tau), float(g),
+                       float(m2))
+
+
+def launch(samples_per_thread=0, block=0, persistent=-1, use_graph=0) -> bfi_launch:
+    return bfi_launch(int(samples_per_thread), int(block), int(persistent), int(use_graph))
+
+
+class Subvolumes:
+    """Owns contiguous arrays for a bfi_subvolumes view (ids, lo/hi n x d, n, offset)."""
+
+    def __init__(self, ids, lo, hi, n, offset, d: int):
+        self.ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        cnt = self.ids.shape[0]
+        self.lo = np.ascontiguousarray(lo, dtype=np.float64).reshape(cnt, d)
+        self.hi = np.ascontiguousarray(hi, dtype=np.float64).reshape(cnt, d)
+        self.n = np.ascontiguousarray(np.broadcast_to(np.asarray(n, np.uint64), (cnt,)))
+        self.offset = np.ascontiguousarray(np.broadcast_to(np.asarray(offset, np.uint64), (cnt,)))
+        self.view = bfi_subvolumes(cnt, _u64p(self.ids), _dp(self.lo), _dp(self.hi), _u64p(self.n),
+                                   _u64p(self.offset))
+
+    @classmethod
+    def of(cls, obj, d: int) -> "Subvolumes":
+        if isinstance(obj, cls):
+            return obj
+        return cls(obj.ids, obj.lo, obj.hi, obj.n, obj.offset, d)
+
+    def __len__(self):
+        return int(self.ids.shape[0])
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return int(t.data_ptr())
+
+
+# ----------------------------------------------------------------------- API
+
+def bfi_shape_supported(nx: int, nt: int) -> bool:
+    return load().bfi_shape_supported(nx, nt) == 0
+
+
+def bfi_supported_shapes() -> list[tuple[int, int]]:
+    buf = (C.c_int32 * 256)()
+    cnt = C.c_int32()
+    _check(load().bfi_supported_shapes(buf, 128, C.byref(cnt)), "bfi_supported_shapes")
+    return [(buf[2 * i], buf[2 * i + 1]) for i in range(cnt.value)]
+
+
+def bfi_context_create(device: int = 0):
+    h = C.c_void_p()
+    _check(load().bfi_context_create(device, C.byref(h)), "bfi_context_create")
+    return h
+
+
+def bfi_context_destroy(ctx):
+    _check(load().bfi_context_destroy(ctx), "bfi_context_destroy")
+
+
+def bfi_eval(ctx, lat, prec, seed, subs, launch_=None, split=False):
+    sv = Subvolumes.of(subs, lat.d)
+    part = np.zeros((len(sv), partial_len(lat.nx)), dtype=np.float64)
+    spl = np.zeros((len(sv), split_len(lat.d)), dtype=np.float64) if split else None
+    _check(load().bfi_eval(ctx, C.byref(lat), _prec(prec), int(seed), C.byref(sv.view),
+                           C.byref(launch_) if launch_ is not None else None, _dp(part),
+                           _dp(spl) if spl is not None else None), "bfi_eval")
+    return (part, spl) if split else part
+
+
+def bfi_plan_create(ctx, lat, prec, subs, launch_=None):
+    sv = Subvolumes.of(subs, lat.d)
+    h = C.c_void_p()
+    _check(load().bfi_plan_create(ctx, C.byref(lat), _prec(prec), C.byref(sv.view),
+                                  C.byref(launch_) if launch_ is not None else None, C.byref(h)),
+           "bfi_plan_create")
+    return h
+
+
+def bfi_plan_run(plan, seed, partials_dev=None, stream=None):
+    _check(load().bfi_plan_run(plan, int(seed), _dev_ptr(partials_dev), _stream_handle(stream)),
+           "bfi_plan_run")
+
+
+def bfi_plan_info(plan) -> dict:
+    ni, ne, l = C.c_uint64(), C.c_uint64(), bfi_launch()
+    _check(load().bfi_plan_info(plan, C.byref(ni), C.byref(ne), C.byref(l)), "bfi_plan_info")
+    return {"n_items": ni.value, "n_evals": ne.value, "samples_per_thread": l.samples_per_thread,
+            "block": l.block, "persistent": l.persistent, "use_graph": l.use_graph}
+
+
+def bfi_plan_partials(plan, count: int, nx: int) -> np.ndarray:
+    out = np.zeros((count, partial_len(nx)), dtype=np.float64)
+    _check(load().bfi_plan_partials(plan, _dp(out)), "bfi_plan_partials")
+    return out
+
+
+def bfi_plan_kernel_ms(plan) -> float:
+    ms = C.c_double()
+    _check(load().bfi_plan_kernel_ms(plan, C.byref(ms)), "bfi_plan_kernel_ms")
+    return ms.value
+
+
+def bfi_plan_destroy(plan):
+    _check(load().bfi_plan_destroy(plan), "bfi_plan_destroy")
+
+
+def bfi_finalize(lat, subs, partials) -> dict:
+    sv = Subvolumes.of(subs, lat.d)
+    p = np.ascontiguousarray(partials, dtype=np.float64)
+    res = bfi_result()
+    _check(load().bfi_finalize(C.byref(lat), C.byref(sv.view), _dp(p), C.byref(res)),
+           "bfi_finalize")
+    return res.to_dict()
+
+
+def _box(d, box_lo, box_hi):
+    lo = np.ascontiguousarray(np.broadcast_to(np.asarray(box_lo, np.float64), (d,)))
+    hi = np.ascontiguousarray(np.broadcast_to(np.asarray(box_hi, np.float64), (d,)))
+    return lo, hi
+
+
+def bfi_integrate(ctx, lat, prec, seed, box_lo, box_hi, split_log2, budget, launch_=None) -> dict:
+    lo, hi = _box(lat.d, box_lo, box_hi)
+    res = bfi_result()
+    _check(load().bfi_integrate(ctx, C.byref(lat), _prec(prec), int(seed), _dp(lo), _dp(hi),
+                                int(split_log2), int(budget),
+                                C.byref(launch_) if launch_ is not None else None, C.byref(res)),
+           "bfi_integrate")
+    return res.to_dict()
+
+
+def adaptive_config(target_rel_err=1e-3, max_evals=1 << 34, n_min=1 << 12, n_max=1 << 22,
+                    split_log2=10, max_rounds=64, refine_fraction=0.5) -> bfi_adaptive_config:
+    return bfi_adaptive_config(float(target_rel_err), int(max_evals), int(n_min), int(n_max),
+                               int(split_log2), int(max_rounds), float(refine_fraction))
+
+
+def bfi_integrate_adaptive(ctx, lat, prec, seed, box_lo, box_hi, cfg, launch_=None,
+                           leaf_capacity: int = 1 << 20) -> dict:
+    """Returns the estimate, the run statistics, the status name (BFI_OK or
+    BFI_EBUDGET) and the final partition (ids, lo, hi, n, offset)."""
+    lo, hi = _box(lat.d, box_lo, box_hi)
+    res, st = bfi_result(), bfi_adaptive_stats()
+    cap = int(leaf_capacity)
+    ids = np.zeros(cap, np.uint64)
+    llo = np.zeros((cap, lat.d))
+    lhi = np.zeros((cap, lat.d))
+    ln = np.zeros(cap, np.uint64)
+    loff = np.zeros(cap, np.uint64)
+    nl = C.c_size_t()
+    s = load().bfi_integrate_adaptive(ctx, C.byref(lat), _prec(prec), int(seed), _dp(lo), _dp(hi),
+                                      C.byref(cfg),
+                                      C.byref(launch_) if launch_ is not None else None,
+                                      C.byref(res), C.byref(st), _u64p(ids), _dp(llo), _dp(lhi),
+                                      _u64p(ln), _u64p(loff), cap, C.byref(nl))
+    if s not in (0, -7):
+        _check(s, "bfi_integrate_adaptive")
+    k = nl.value
+    out = res.to_dict()
+    out.update({"status": STATUS[s], "rounds": st.rounds, "leaves": st.leaves, "evals": st.evals,
+                "rel_err": st.rel_err,
+                "partition": Subvolumes(ids[:k], llo[:k], lhi[:k], ln[:k], loff[:k], lat.d)})
+    return out
+
+
+def bfi_adaptive_decide(lat, leaves, partials, split, cfg) -> np.ndarray:
+    sv = Subvolumes.of(leaves, lat.d)
+    p = np.ascontiguousarray(partials, dtype=np.float64)
+    s = np.ascontiguousarray(split, dtype=np.float64)
+    act = np.zeros(len(sv), dtype=np.int32)
+    _check(load().bfi_adaptive_decide(C.byref(lat), C.byref(sv.view), _dp(p), _dp(s),
+                                      C.byref(cfg), act.ctypes.data_as(_P(C.c_int32))),
+           "bfi_adaptive_decide")
+    return act
+
+
+def server_config(memory_budget=1 << 30, max_requests=256, chunks_per_step=64,
+                  max_pending=100000) -> bfi_server_config:
+    return bfi_server_config(int(memory_budget), int(max_requests), int(chunks_per_step),
+                             int(max_pending))
+
+
+def request(lat, prec, seed, box, split_log2, budget) -> bfi_request:
+    return bfi_request(lat, _prec(prec), int(seed), float(box), int(split_log2), int(budget))
+
+
+def bfi_server_create(ctx, cfg):
+    h = C.c_void_p()
+    _check(load().bfi_server_create(ctx, C.byref(cfg), C.byref(h)), "bfi_server_create")
+    return h
+
+
+def bfi_server_submit(srv, req) -> int:
+    t = C.c_uint64()
+    _check(load().bfi_server_submit(srv, C.byref(req), C.byref(t)), "bfi_server_submit")
+    return t.value
+
+
+def bfi_server_poll(srv, ticket):
+    res, done, lat = bfi_result(), C.c_int32(), C.c_double()
+    _check(load().bfi_server_poll(srv, int(ticket), C.byref(res), C.byref(done), C.byref(lat)),
+           "bfi_server_poll")
+    return (res.to_dict(), lat.value) if done.value else None
+
+
+def bfi_server_wait(srv, ticket, timeout_s=60.0):
+    res, done, lat = bfi_result(), C.c_int32(), C.c_double()
+    _check(load().bfi_server_wait(srv, int(ticket), float(timeout_s), C.byref(res), C.byref(done),
+                                  C.byref(lat)), "bfi_server_wait")
+    return (res.to_dict(), lat.value) if done.value else None
+
+
+def bfi_server_cancel(srv, ticket):
+    _check(load().bfi_server_cancel(srv, int(ticket)), "bfi_server_cancel")
+
+
+def bfi_server_stats_get(srv) -> dict:
+    st = bfi_server_stats()
+    _check(load().bfi_server_stats_get(srv, C.byref(st)), "bfi_server_stats_get")
+    return {f: getattr(st, f) for f, _ in bfi_server_stats._fields_}
+
+
+def bfi_server_destroy(srv):
+    _check(load().bfi_server_destroy(srv), "bfi_server_destroy")
+
+
+def bfi_autotune(ctx, lat, prec, evals_per_trial=1 << 26):
+    best, rate = bfi_launch(), C.c_double()
+    _check(load().bfi_autotune(ctx, C.byref(lat), _prec(prec), int(evals_per_trial),
+                               C.byref(best), C.byref(rate)), "bfi_autotune")
+    return {"samples_per_thread": best.samples_per_thread, "block": best.block,
+            "persistent": best.persistent, "evals_per_s": rate.value}
+
+
+def bfi_tune_save(ctx, path: str):
+    _check(load().bfi_tune_save(ctx, path.encode()), "bfi_tune_save")
+
+
+def bfi_tune_load(ctx, path: str):
+    _check(load().bfi_tune_load(ctx, path.encode()), "bfi_tune_load")
+
+
+def bfi_debug_points(ctx, d, prec, seed, sub_id, lo, hi, index) -> np.ndarray:
+    lo, hi = _box(d, lo, hi)
+    idx = np.ascontiguousarray(index, dtype=np.uint64)
+    out = np.zeros((idx.shape[0], d), dtype=np.float64)
+    _check(load().bfi_debug_points(ctx, int(d), _prec(prec), int(seed), int(sub_id), _dp(lo),
+                                   _dp(hi), _u64p(idx), idx.shape[0], _dp(out)),
+           "bfi_debug_points")
+    return out
+
+
+def bfi_debug_action(ctx, lat, prec, points) -> np.ndarray:
+    p = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, lat.d)
+    out = np.zeros(p.shape[0], dtype=np.float64)
+    _check(load().bfi_debug_action(ctx, C.byref(lat), _prec(prec), p.shape[0], _dp(p), _dp(out)),
+           "bfi_debug_action")
+    return out

@@ -1,0 +1,118 @@
+// Shape-independent kernels: queue reset, the ordered per-subvolume merge of
+// work-item records, and the point-emitting test hook.
+#include "device.hpp"
+
+namespace bfi {
+namespace {
+
+__global__ void reset_head_kernel(uint32_t *head)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *head = 0u;
+}
+
+// One block per subvolume; thread f merges field f over the subvolume's items
+// in item order with Neumaier compensation, after moving every item to the
+// smallest shift of the subvolume (factor exp(sigma_min - sigma_item) for
+// first-order sums, its square for second-order sums; 1 in FP64 form).
+__global__ void __launch_bounds__(64) merge_kernel(MergeArgs m)
+{
+    const uint32_t s = blockIdx.x;
+    if (s >= m.nsub)
+        return;
+    const int nx = m.nx, d = m.d;
+    const int rec_len = 4 + 3 * nx;
+    const int split_len = m.item_split ? 2 * d : 0;
+    const uint32_t i0 = m.sub_first[s], i1 = m.sub_first[s + 1];
+
+    double sigma = __builtin_inf();
+    for (uint32_t i = i0; i < i1; ++i)
+        sigma = fmin(sigma, m.item_rec[static_cast<size_t>(i) * rec_len + 1]);
+    if (i0 == i1)
+        sigma = 0.0;
+
+    double *out = m.sub_rec + static_cast<size_t>(s) * rec_len;
+    for (int f = threadIdx.x; f < rec_len + split_len; f += blockDim.x) {
+        if (f == 1)
+            continue;
+        int order;
+        if (f < rec_len)
+            order = f == 0 ? 0 : f == 2 ? 1 : f == 3 ? 2 : f < 4 + nx ? 1 : 2;
+        else
+            order = (f - rec_len) < d ? 1 : 2;
+        double sum = 0.0, comp = 0.0;
+        for (uint32_t i = i0; i < i1; ++i) {
+            const double *rec = m.item_rec + static_cast<size_t>(i) * rec_len;
+            double v = f < rec_len ? rec[f]
+                                   : m.item_split[static_cast<size_t>(i) * (2 * d) + (f - rec_len)];
+            if (order != 0) {
+                const double f1 = exp(sigma - rec[1]);
+                v *= order == 1 ? f1 : f1 * f1;
+            }
+            const double t = sum + v;
+            comp += fabs(sum) >= fabs(v) ? (sum - t) + v : (v - t) + sum;
+            sum = t;
+        }
+        if (f < rec_len)
+            out[f] = sum + comp;
+        else
+            m.sub_split[static_cast<size_t>(s) * (1 + 2 * d) + 1 + (f - rec_len)] = sum + comp;
+    }
+    if (threadIdx.x == 0) {
+        out[1] = sigma;
+        if (m.sub_split)
+            m.sub_split[static_cast<size_t>(s) * (1 + 2 * d)] = sigma;
+    }
+}
+
+__global__ void __launch_bounds__(256) debug_points_kernel(DebugPointArgs a)
+{
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.n)
+        return;
+    const int d = a.d;
+    const int nb = (d + 3) / 4;
+    const uint64_t q0 = a.index[i] * static_cast<uint64_t>(nb);
+    const uint32_t id_lo = static_cast<uint32_t>(a.id), id_hi = static_cast<uint32_t>(a.id >> 32);
+    for (int j = 0; j < nb; ++j) {
+        uint32_t blk[4];
+        dev::philox_block(q0 + j, id_lo, id_hi, a.seed_lo, a.seed_hi, blk);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = 4 * j + t;
+            if (k >= d)
+                break;
+            a.out[i * d + k] =
+                a.prec == kFP64
+                    ? dev::map_word(blk[t], a.scale64[k], a.base64[k])
+                    : static_cast<double>(dev::map_word(blk[t], a.scale32[k], a.base32[k]));
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_reset_head(uint32_t *head, hipStream_t stream)
+{
+    hipLaunchKernelGGL(reset_head_kernel, dim3(1), dim3(64), 0, stream, head);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(const MergeArgs &args, hipStream_t stream)
+{
+    if (args.nsub == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(merge_kernel, dim3(args.nsub), dim3(64), 0, stream, args);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_points(const DebugPointArgs &args, hipStream_t stream)
+{
+    const unsigned grid = static_cast<unsigned>((args.n + 255) / 256);
+    if (grid == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(debug_points_kernel, dim3(grid), dim3(256), 0, stream, args);
+    return hipGetLastError();
+}
+
+}  // namespace bfi

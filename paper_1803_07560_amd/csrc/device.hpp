@@ -1,0 +1,151 @@
+// Device building blocks for gfx950: counter-based point generation, the
+// lattice action of Eq. Gen2, and wavefront reductions.  One thread holds one
+// lattice configuration in registers; everything is fully unrolled over the
+// compile-time lattice shape.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace bfi {
+namespace dev {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): round multipliers and the
+// Weyl increments of the key schedule.
+constexpr uint32_t kPhiloxMulA = 0xD2511F53u;
+constexpr uint32_t kPhiloxMulB = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxWeylA = 0x9E3779B9u;
+constexpr uint32_t kPhiloxWeylB = 0xBB67AE85u;
+
+// One Philox4x32-10 block for counter (lo32(q), hi32(q), lo32(id), hi32(id)).
+__device__ __forceinline__ void philox_block(uint64_t q, uint32_t id_lo, uint32_t id_hi,
+                                             uint32_t key_lo, uint32_t key_hi, uint32_t out[4])
+{
+    uint32_t c0 = static_cast<uint32_t>(q), c1 = static_cast<uint32_t>(q >> 32);
+    uint32_t c2 = id_lo, c3 = id_hi;
+    uint32_t k0 = key_lo, k1 = key_hi;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo_a = kPhiloxMulA * c0, hi_a = __umulhi(kPhiloxMulA, c0);
+        const uint32_t lo_b = kPhiloxMulB * c2, hi_b = __umulhi(kPhiloxMulB, c2);
+        c0 = hi_b ^ c1 ^ k0;
+        c2 = hi_a ^ c3 ^ k1;
+        c1 = lo_b;
+        c3 = lo_a;
+        k0 += kPhiloxWeylA;
+        k1 += kPhiloxWeylB;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+// Word -> coordinate: u = fma(x, scale, base), one rounding.
+__device__ __forceinline__ double map_word(uint32_t x, double scale, double base)
+{
+    return __fma_rn(static_cast<double>(x), scale, base);
+}
+__device__ __forceinline__ float map_word(uint32_t x, float scale, float base)
+{
+    return __fmaf_rn(static_cast<float>(x), scale, base);
+}
+
+template <class T>
+struct Coef {
+    T k_diag, c_adv, c_visc, inv_2Dtau, half_m2;
+    __device__ __forceinline__ explicit Coef(const ActionCoef &c)
+        : k_diag(static_cast<T>(c.k_diag)), c_adv(static_cast<T>(c.c_adv)),
+          c_visc(static_cast<T>(c.c_visc)), inv_2Dtau(static_cast<T>(c.inv_2Dtau)),
+          half_m2(static_cast<T>(c.half_m2)) {}
+};
+
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __fma_rn(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+
+// Sum of R^2 over the sites of one time slice: `cur` is slice l, `nxt` slice
+// l+1 (periodic in time), neighbours in space taken periodically.
+template <class T, int NX>
+__device__ __forceinline__ T slice_r2(const T (&cur)[NX], const T (&nxt)[NX], const Coef<T> &c,
+                                      T acc)
+{
+#pragma unroll
+    for (int m = 0; m < NX; ++m) {
+        const T v = cur[m];
+        const T vr = cur[(m + 1) % NX];
+        const T vl = cur[(m + NX - 1) % NX];
+        const T t = fma_t(c.c_adv, vr - vl, c.k_diag);
+        T R = fma_t(v, t, nxt[m]);
+        R = fma_t(-c.c_visc, vr + vl, R);
+        acc = fma_t(R, R, acc);
+    }
+    return acc;
+}
+
+template <class T, int NX>
+__device__ __forceinline__ T slice_u2(const T (&cur)[NX], T acc)
+{
+#pragma unroll
+    for (int m = 0; m < NX; ++m)
+        acc = fma_t(cur[m], cur[m], acc);
+    return acc;
+}
+
+// The action S for one configuration delivered slice by slice:
+// gen(l, out) fills time slice l.  Slice 0 stays live (it closes the time
+// period and carries the observables); at most three slices are live at once.
+template <class T, int NX, int NT, class Gen>
+__device__ __forceinline__ T action(Gen &&gen, T (&first)[NX], const Coef<T> &c, bool mass)
+{
+    gen(0, first);
+    T cur[NX];
+#pragma unroll
+    for (int m = 0; m < NX; ++m)
+        cur[m] = first[m];
+    T r2 = T(0), u2 = T(0);
+#pragma unroll
+    for (int l = 0; l < NT; ++l) {
+        T nxt[NX];
+        if (l + 1 < NT) {
+            gen(l + 1, nxt);
+        } else {
+#pragma unroll
+            for (int m = 0; m < NX; ++m)
+                nxt[m] = first[m];
+        }
+        r2 = slice_r2<T, NX>(cur, nxt, c, r2);
+        if (mass)
+            u2 = slice_u2<T, NX>(cur, u2);
+#pragma unroll
+        for (int m = 0; m < NX; ++m)
+            cur[m] = nxt[m];
+    }
+    T S = r2 * c.inv_2Dtau;
+    if (mass)
+        S = fma_t(c.half_m2, u2, S);
+    return S;
+}
+
+// Butterfly sum across the 64 lanes of a wavefront; every lane ends with the
+// same bits (each step adds the same two operands in both partner lanes).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+}  // namespace dev
+}  // namespace bfi

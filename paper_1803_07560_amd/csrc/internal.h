@@ -1,0 +1,112 @@
+// Internal interface between the host runtime (runtime.cpp) and the per-shape
+// kernel translation units (shape_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bfi {
+
+// Lattice shapes with compiled kernels, as (nx, nt) = (space sites, time slices).
+#define BFI_SHAPES(X)                                                                   \
+    X(1, 1) X(1, 2) X(2, 1) X(2, 2) X(3, 1) X(3, 2) X(4, 1) X(4, 2) X(5, 3) X(8, 2)     \
+    X(10, 2) X(16, 4)
+
+enum Precision : int { kFP64 = 0, kFP32Shifted = 1 };
+
+// One unit of device work: `count` consecutive samples of subvolume `sub`,
+// starting `start` samples after the subvolume's own offset.
+struct WorkItem {
+    uint32_t sub;
+    uint32_t count;
+    uint64_t start;
+};
+
+// Coefficients of the residual rewritten as
+//   R = v_next + v (k_diag + c_adv (v_right - v_left)) - c_visc (v_right + v_left)
+// with c_adv = g tau / (2a), c_visc = nu tau / a^2, k_diag = 2 c_visc - 1;
+// S = inv_2Dtau * sum R^2 + half_m2 * sum u^2.
+struct ActionCoef {
+    double k_diag, c_adv, c_visc, inv_2Dtau, half_m2;
+};
+
+struct McArgs {
+    const double *base64, *scale64;  // nsub x d: point map in FP64
+    const float *base32, *scale32;   // nsub x d: point map in FP32
+    const uint64_t *ids;             // nsub heap ids (Philox counter words 2-3)
+    const uint64_t *offsets;         // nsub first sample index
+    const WorkItem *items;           // nitems
+    double *item_rec;                // nitems x (4 + 3 nx)
+    double *item_split;              // nitems x 2d (split statistics), or null
+    uint32_t *queue_head;            // persistent kernels: next item to take
+    uint32_t nitems;
+    uint32_t samples_per_thread;
+    uint32_t seed_lo, seed_hi;
+    ActionCoef coef;
+};
+
+struct LaunchSpec {
+    int prec;        // Precision
+    int block;       // 64, 128, 256
+    int split;       // 0/1
+    int persistent;  // 0/1
+    uint32_t grid;   // blocks
+};
+
+struct MergeArgs {
+    const double *item_rec;     // nitems x rec_len
+    const double *item_split;   // nitems x 2d or null
+    const uint32_t *sub_first;  // nsub + 1 prefix of item indices
+    double *sub_rec;            // nsub x rec_len
+    double *sub_split;          // nsub x (1 + 2d) or null
+    uint32_t nsub;
+    int32_t nx, d;
+};
+
+struct DebugPointArgs {
+    const double *base64, *scale64;  // d each
+    const float *base32, *scale32;   // d each
+    const uint64_t *index;           // n sample indices
+    double *out;                     // n x d
+    uint64_t id;
+    uint64_t n;
+    uint32_t seed_lo, seed_hi;
+    int32_t d;
+    int32_t prec;
+};
+
+struct DebugActionArgs {
+    const double *points;  // n x d
+    double *out;           // n
+    uint64_t n;
+    ActionCoef coef;
+    int32_t prec;
+};
+
+struct KernelInfo {
+    int vgprs, sgprs, blocks_per_cu;
+};
+
+template <int NX, int NT>
+hipError_t launch_mc_shape(const LaunchSpec &spec, const McArgs &args, hipStream_t stream);
+template <int NX, int NT>
+hipError_t kernel_info_shape(const LaunchSpec &spec, KernelInfo *info);
+template <int NX, int NT>
+hipError_t launch_debug_action_shape(const DebugActionArgs &args, hipStream_t stream);
+
+#define BFI_DECLARE_SHAPE(NX, NT)                                                        \
+    extern template hipError_t launch_mc_shape<NX, NT>(const LaunchSpec &, const McArgs &, \
+                                                       hipStream_t);                     \
+    extern template hipError_t kernel_info_shape<NX, NT>(const LaunchSpec &, KernelInfo *); \
+    extern template hipError_t launch_debug_action_shape<NX, NT>(const DebugActionArgs &,  \
+                                                                 hipStream_t);
+BFI_SHAPES(BFI_DECLARE_SHAPE)
+#undef BFI_DECLARE_SHAPE
+
+// Shape-independent kernels (common_kernels.hip).
+hipError_t launch_reset_head(uint32_t *head, hipStream_t stream);
+hipError_t launch_merge(const MergeArgs &args, hipStream_t stream);
+hipError_t launch_debug_points(const DebugPointArgs &args, hipStream_t stream);
+
+}  // namespace bfi

@@ -1,0 +1,126 @@
+// Host runtime shared by the C ABI translation units (runtime.cpp, adaptive.cpp,
+// server.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "bfi.h"
+#include "internal.h"
+
+namespace bfi {
+
+bfi_status fail(bfi_status s, const char *fmt, ...);
+bfi_status hip_fail(hipError_t e, const char *what);
+void clear_error();
+
+#define BFI_HIP(call)                                 \
+    do {                                              \
+        hipError_t bfi_e_ = (call);                   \
+        if (bfi_e_ != hipSuccess)                     \
+            return ::bfi::hip_fail(bfi_e_, #call);    \
+    } while (0)
+
+#define BFI_TRY(call)                                 \
+    do {                                              \
+        bfi_status bfi_s_ = (call);                   \
+        if (bfi_s_ != BFI_OK)                         \
+            return bfi_s_;                            \
+    } while (0)
+
+bool shape_compiled(int nx, int nt);
+bfi_status check_lattice(const bfi_lattice *lat);
+bfi_status check_subvolumes(const bfi_lattice *lat, const bfi_subvolumes *subs);
+ActionCoef make_coef(const bfi_lattice &lat);
+
+// Owned copy of a subvolume list.
+struct SubList {
+    std::vector<uint64_t> id, n, offset;
+    std::vector<double> lo, hi;  // count x d
+    int d = 0;
+    size_t size() const { return id.size(); }
+    bfi_subvolumes view() const
+    {
+        return bfi_subvolumes{id.size(), id.data(), lo.data(), hi.data(), n.data(), offset.data()};
+    }
+    static SubList copy_of(const bfi_subvolumes &s, int d);
+};
+
+// Uniform bisection of a box: 2^k leaves, level t halves dim t mod d at
+// 0.5 (lo + hi); heap ids 2^k + b; budget split floor(B/2^k) + (b < B mod 2^k).
+SubList uniform_split(int d, const double *box_lo, const double *box_hi, int k, uint64_t budget);
+
+struct TuneKey {
+    int nx, nt, prec;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(nx, nt, prec) < std::tie(o.nx, o.nt, o.prec);
+    }
+};
+struct TuneEntry {
+    bfi_launch launch;
+    double evals_per_s;
+};
+
+// Resolve a requested launch (zeros = tuned or default) for a lattice.
+bfi_launch resolve_launch(const bfi_context *ctx, const bfi_lattice &lat, int prec, bool split,
+                          const bfi_launch *req);
+
+// Host finalize of partial records (see bfi_finalize).
+bfi_status finalize_records(int nx, int d, size_t nsub, const double *lo, const double *hi,
+                            const double *partials, bfi_result *out);
+
+}  // namespace bfi
+
+struct bfi_context {
+    int device = 0;
+    int cu_count = 0;
+    hipStream_t stream = nullptr;
+    std::string arch;
+    std::map<bfi::TuneKey, bfi::TuneEntry> tuned;
+};
+
+// A resident evaluation: descriptors, work items and buffers on the device.
+struct bfi_plan {
+    bfi_context *ctx = nullptr;
+    bfi_lattice lat{};
+    int prec = 0;
+    int d = 0, nx = 0, rec_len = 0;
+    bool split = false;
+    bfi::SubList subs;
+    bfi_launch launch{};
+    uint32_t nitems = 0;
+    uint32_t grid = 0;
+    uint64_t n_evals = 0;
+
+    double *d_base64 = nullptr, *d_scale64 = nullptr;
+    float *d_base32 = nullptr, *d_scale32 = nullptr;
+    uint64_t *d_ids = nullptr, *d_offsets = nullptr;
+    bfi::WorkItem *d_items = nullptr;
+    double *d_item_rec = nullptr, *d_item_split = nullptr;
+    uint32_t *d_sub_first = nullptr;
+    double *d_sub_rec = nullptr, *d_sub_split = nullptr;
+    uint32_t *d_head = nullptr;
+
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_def = nullptr;
+    uint64_t graph_seed = 0;
+    hipStream_t graph_stream = nullptr;
+    double *graph_dst = nullptr;
+    hipStream_t last_stream = nullptr;
+    // bracket the Monte Carlo kernel of every run (timing of the hot kernel)
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+};
+
+namespace bfi {
+bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const SubList &subs,
+                      const bfi_launch *launch, bool split, bfi_plan **out);
+bfi_status plan_enqueue(bfi_plan *p, uint64_t seed, double *dst, hipStream_t stream);
+bfi_status plan_free(bfi_plan *p);
+}  // namespace bfi

@@ -1,0 +1,365 @@
+// Monte Carlo kernels for one lattice shape (compiled once per shape with
+// -DBFI_NX=<space sites> -DBFI_NT=<time slices>).
+//
+// Work decomposition: a work item is `count` consecutive samples of one
+// subvolume; a block of BLOCK threads takes one item, thread t takes samples
+// t, t + BLOCK, t + 2 BLOCK, ... (samples_per_thread of them at most).  Each
+// sample is one lattice configuration held in the thread's registers:
+//   Philox words -> point in the subvolume -> action S (Eq. Gen2)
+//   -> weight exp(-S) -> FP64 sums of w, w^2, p_r w, (p_r w)^2, p_r w^2
+// with p_r = u_{0,0} u_{0,r}.  Per-thread sums are reduced across the
+// wavefront with butterfly shuffles and across the block through LDS in a
+// fixed order, so the item's record is bitwise reproducible for a given launch
+// shape.  Persistent launches take items from a device counter instead of
+// blockIdx.x; the records are the same.
+#include <type_traits>
+
+#include "device.hpp"
+
+#ifndef BFI_NX
+#error "compile with -DBFI_NX=<nx> -DBFI_NT=<nt>"
+#endif
+
+namespace bfi {
+namespace {
+
+// FP32 form: the per-thread shift sigma follows the smallest action seen, but is
+// only moved when a new sample would weigh more than e^64 relative to it, so the
+// FP32 weight exp(sigma - S) stays in (0, e^64] and rescales are rare.
+constexpr float kShiftGap = 64.0f;
+constexpr float kLog2e = 1.44269504088896340736f;
+
+template <int NX, int D, bool SPLIT>
+struct Fields {
+    // reduced fields: [w, w^2, p_r w (NX), (p_r w)^2 (NX), p_r w^2 (NX), U w (D), U w^2 (D)]
+    static constexpr int kMain = 2 + 3 * NX;
+    static constexpr int kCount = kMain + (SPLIT ? 2 * D : 0);
+    // 1 for sums of first order in w, 2 for second order (scaled by the square
+    // of a shift factor)
+    __host__ __device__ static constexpr int order(int i)
+    {
+        return i == 0 ? 1
+               : i == 1 ? 2
+               : i < 2 + NX ? 1
+               : i < kMain ? 2
+               : i < kMain + D ? 1
+                               : 2;
+    }
+};
+
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT>
+__global__ void __launch_bounds__(BLOCK) mc_kernel(McArgs a)
+{
+    using T = std::conditional_t<PREC == kFP64, double, float>;
+    constexpr int D = NX * NT;
+    constexpr int NB = (D + 3) / 4;
+    constexpr int NW = BLOCK / 64;
+    using F = Fields<NX, D, SPLIT>;
+    constexpr int NF = F::kCount;
+    constexpr int REC = 4 + 3 * NX;
+    static_assert(!SPLIT || D <= 32, "split statistics keep one bit per dimension in 32 bits");
+
+    __shared__ double red[NW][NF];
+    __shared__ float red_sigma[NW];
+    __shared__ uint32_t next_item;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const dev::Coef<T> coef(a.coef);
+    const bool mass = a.coef.half_m2 != 0.0;
+
+    uint32_t it;
+    if (a.queue_head) {
+        if (tid == 0)
+            next_item = atomicAdd(a.queue_head, 1u);
+        __syncthreads();
+        it = __builtin_amdgcn_readfirstlane(next_item);
+    } else {
+        it = blockIdx.x;
+    }
+
+    while (it < a.nitems) {
+        const WorkItem wi = a.items[it];
+        const uint32_t s = wi.sub;
+        const uint64_t id = a.ids[s];
+        const uint64_t first_index = a.offsets[s] + wi.start;
+        const uint32_t id_lo = static_cast<uint32_t>(id), id_hi = static_cast<uint32_t>(id >> 32);
+        const T *base;
+        const T *scale;
+        if constexpr (PREC == kFP64) {
+            base = a.base64 + static_cast<size_t>(s) * D;
+            scale = a.scale64 + static_cast<size_t>(s) * D;
+        } else {
+            base = a.base32 + static_cast<size_t>(s) * D;
+            scale = a.scale32 + static_cast<size_t>(s) * D;
+        }
+
+        double acc[NF];
+#pragma unroll
+        for (int i = 0; i < NF; ++i)
+            acc[i] = 0.0;
+        float sigma = __builtin_inff();
+
+        auto rescale = [&](double f1) {
+            const double f2 = f1 * f1;
+#pragma unroll
+            for (int i = 0; i < NF; ++i)
+                acc[i] *= F::order(i) == 1 ? f1 : f2;
+        };
+
+        for (uint32_t k = 0; k < a.samples_per_thread; ++k) {
+            const uint32_t local = k * BLOCK + tid;
+            if (local >= wi.count)
+                break;
+            const uint64_t q0 = (first_index + local) * NB;
+            uint32_t blk[4];
+            uint32_t upper = 0;
+            auto gen = [&](int l, T(&out)[NX]) {
+#pragma unroll
+                for (int m = 0; m < NX; ++m) {
+                    const int kk = l * NX + m;
+                    if ((kk & 3) == 0)
+                        dev::philox_block(q0 + (kk >> 2), id_lo, id_hi, a.seed_lo, a.seed_hi, blk);
+                    const uint32_t x = blk[kk & 3];
+                    if constexpr (SPLIT)
+                        upper |= (x >> 31) << kk;
+                    out[m] = dev::map_word(x, scale[kk], base[kk]);
+                }
+            };
+            T first[NX];
+            const T S = dev::action<T, NX, NT>(gen, first, coef, mass);
+
+            double w;
+            if constexpr (PREC == kFP64) {
+                w = exp(-S);
+                const double t = first[0] * w;
+#pragma unroll
+                for (int r = 0; r < NX; ++r) {
+                    const double v = t * first[r];
+                    acc[2 + r] += v;
+                    acc[2 + NX + r] = __fma_rn(v, v, acc[2 + NX + r]);
+                    acc[2 + 2 * NX + r] = __fma_rn(v, w, acc[2 + 2 * NX + r]);
+                }
+            } else {
+                if (S < sigma - kShiftGap) {
+                    // first sample (sigma = inf: factor 0 on zero sums) or a new
+                    // action far below the shift: move the shift to S
+                    rescale(exp(static_cast<double>(S) - static_cast<double>(sigma)));
+                    sigma = S;
+                }
+                const float w32 = __builtin_amdgcn_exp2f((sigma - S) * kLog2e);
+                w = static_cast<double>(w32);
+                const float t32 = first[0] * w32;
+#pragma unroll
+                for (int r = 0; r < NX; ++r) {
+                    const double v = static_cast<double>(t32 * first[r]);
+                    acc[2 + r] += v;
+                    acc[2 + NX + r] = __fma_rn(v, v, acc[2 + NX + r]);
+                    acc[2 + 2 * NX + r] = __fma_rn(v, w, acc[2 + 2 * NX + r]);
+                }
+            }
+            acc[0] += w;
+            acc[1] = __fma_rn(w, w, acc[1]);
+            if constexpr (SPLIT) {
+                const double w2 = w * w;
+#pragma unroll
+                for (int kk = 0; kk < D; ++kk) {
+                    const bool up = (upper >> kk) & 1u;
+                    acc[F::kMain + kk] += up ? w : 0.0;
+                    acc[F::kMain + D + kk] += up ? w2 : 0.0;
+                }
+            }
+        }
+
+        // ---- reduction: wavefront butterflies, then waves in order through LDS
+        float wave_sigma = 0.0f;
+        if constexpr (PREC != kFP64) {
+            wave_sigma = dev::wave_min(sigma);
+            // lanes that took no sample hold sigma = inf and zero sums
+            rescale(sigma == __builtin_inff()
+                        ? 0.0
+                        : exp(static_cast<double>(wave_sigma) - static_cast<double>(sigma)));
+        }
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const double v = dev::wave_sum(acc[i]);
+            if (lane == 0)
+                red[wave][i] = v;
+        }
+        if (lane == 0)
+            red_sigma[wave] = wave_sigma;
+        __syncthreads();
+
+        float block_sigma = 0.0f;
+        if constexpr (PREC != kFP64) {
+            block_sigma = red_sigma[0];
+#pragma unroll
+            for (int w = 1; w < NW; ++w)
+                block_sigma = fminf(block_sigma, red_sigma[w]);
+        }
+        double *rec = a.item_rec + static_cast<size_t>(it) * REC;
+        for (int i = tid; i < NF; i += BLOCK) {
+            double total = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                double v = red[w][i];
+                if constexpr (PREC != kFP64) {
+                    const float ws = red_sigma[w];
+                    const double f1 = ws == __builtin_inff()
+                                          ? 0.0
+                                          : exp(static_cast<double>(block_sigma) -
+                                                static_cast<double>(ws));
+                    v *= F::order(i) == 1 ? f1 : f1 * f1;
+                }
+                total += v;
+            }
+            if (i < F::kMain)
+                rec[2 + i] = total;
+            else
+                a.item_split[static_cast<size_t>(it) * (2 * D) + (i - F::kMain)] = total;
+        }
+        if (tid == 0) {
+            rec[0] = static_cast<double>(wi.count);
+            rec[1] = static_cast<double>(block_sigma);
+        }
+
+        if (!a.queue_head)
+            break;
+        __syncthreads();  // LDS slots free again before the next item
+        if (tid == 0)
+            next_item = atomicAdd(a.queue_head, 1u);
+        __syncthreads();
+        it = __builtin_amdgcn_readfirstlane(next_item);
+    }
+}
+
+template <int NX, int NT, int PREC>
+__global__ void __launch_bounds__(256) debug_action_kernel(DebugActionArgs a)
+{
+    using T = std::conditional_t<PREC == kFP64, double, float>;
+    constexpr int D = NX * NT;
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.n)
+        return;
+    const double *p = a.points + i * D;
+    auto gen = [&](int l, T(&out)[NX]) {
+#pragma unroll
+        for (int m = 0; m < NX; ++m)
+            out[m] = static_cast<T>(p[l * NX + m]);
+    };
+    T first[NX];
+    const dev::Coef<T> coef(a.coef);
+    a.out[i] = static_cast<double>(dev::action<T, NX, NT>(gen, first, coef, a.coef.half_m2 != 0.0));
+}
+
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT>
+hipError_t launch_one(const LaunchSpec &spec, const McArgs &args, hipStream_t stream)
+{
+    hipLaunchKernelGGL((mc_kernel<NX, NT, PREC, BLOCK, SPLIT>), dim3(spec.grid), dim3(BLOCK), 0,
+                       stream, args);
+    return hipGetLastError();
+}
+
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT>
+hipError_t info_one(KernelInfo *info)
+{
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(
+        &attr, reinterpret_cast<const void *>(&mc_kernel<NX, NT, PREC, BLOCK, SPLIT>));
+    if (e != hipSuccess)
+        return e;
+    int blocks = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, mc_kernel<NX, NT, PREC, BLOCK, SPLIT>,
+                                                     BLOCK, 0);
+    if (e != hipSuccess)
+        return e;
+    info->vgprs = attr.numRegs;
+    info->sgprs = 0;
+    info->blocks_per_cu = blocks;
+    return hipSuccess;
+}
+
+// Dispatch over (precision, block, split) for this shape.  Split statistics
+// are compiled for 256-thread blocks and d <= 32 only.
+template <int NX, int NT, template <int, int, int, int, bool> class Op, class... Args>
+hipError_t dispatch(const LaunchSpec &spec, Args &&...args)
+{
+    constexpr int D = NX * NT;
+    if (spec.split) {
+        if constexpr (D <= 32) {
+            if (spec.block != 256)
+                return hipErrorInvalidValue;
+            return spec.prec == kFP64 ? Op<NX, NT, kFP64, 256, true>::run(spec, args...)
+                                      : Op<NX, NT, kFP32Shifted, 256, true>::run(spec, args...);
+        } else {
+            return hipErrorNotSupported;
+        }
+    }
+    const bool f64 = spec.prec == kFP64;
+    switch (spec.block) {
+    case 64:
+        return f64 ? Op<NX, NT, kFP64, 64, false>::run(spec, args...)
+                   : Op<NX, NT, kFP32Shifted, 64, false>::run(spec, args...);
+    case 128:
+        return f64 ? Op<NX, NT, kFP64, 128, false>::run(spec, args...)
+                   : Op<NX, NT, kFP32Shifted, 128, false>::run(spec, args...);
+    case 256:
+        return f64 ? Op<NX, NT, kFP64, 256, false>::run(spec, args...)
+                   : Op<NX, NT, kFP32Shifted, 256, false>::run(spec, args...);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT>
+struct LaunchOp {
+    static hipError_t run(const LaunchSpec &spec, const McArgs &args, hipStream_t stream)
+    {
+        return launch_one<NX, NT, PREC, BLOCK, SPLIT>(spec, args, stream);
+    }
+};
+
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT>
+struct InfoOp {
+    static hipError_t run(const LaunchSpec &, KernelInfo *info)
+    {
+        return info_one<NX, NT, PREC, BLOCK, SPLIT>(info);
+    }
+};
+
+}  // namespace
+
+template <int NX, int NT>
+hipError_t launch_mc_shape(const LaunchSpec &spec, const McArgs &args, hipStream_t stream)
+{
+    return dispatch<NX, NT, LaunchOp>(spec, args, stream);
+}
+
+template <int NX, int NT>
+hipError_t kernel_info_shape(const LaunchSpec &spec, KernelInfo *info)
+{
+    return dispatch<NX, NT, InfoOp>(spec, info);
+}
+
+template <int NX, int NT>
+hipError_t launch_debug_action_shape(const DebugActionArgs &args, hipStream_t stream)
+{
+    const unsigned grid = static_cast<unsigned>((args.n + 255) / 256);
+    if (grid == 0)
+        return hipSuccess;
+    if (args.prec == kFP64)
+        hipLaunchKernelGGL((debug_action_kernel<NX, NT, kFP64>), dim3(grid), dim3(256), 0, stream,
+                           args);
+    else
+        hipLaunchKernelGGL((debug_action_kernel<NX, NT, kFP32Shifted>), dim3(grid), dim3(256), 0,
+                           stream, args);
+    return hipGetLastError();
+}
+
+template hipError_t launch_mc_shape<BFI_NX, BFI_NT>(const LaunchSpec &, const McArgs &,
+                                                    hipStream_t);
+template hipError_t kernel_info_shape<BFI_NX, BFI_NT>(const LaunchSpec &, KernelInfo *);
+template hipError_t launch_debug_action_shape<BFI_NX, BFI_NT>(const DebugActionArgs &,
+                                                              hipStream_t);
+
+}  // namespace bfi

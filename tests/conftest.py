@@ -18,3 +18,18 @@ def oracle_lib():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def bfi():
+    import paper_1803_07560_amd as bfi_mod
+    bfi_mod.load()
+    return bfi_mod
+
+
+@pytest.fixture(scope="session")
+def ctx(bfi):
+    """A bfi context on device 0 (GPU tests only)."""
+    c = bfi.bfi_context_create(0)
+    yield c
+    bfi.bfi_context_destroy(c)

@@ -1,0 +1,115 @@
+"""The C ABI library loads, exports every entry point ``include/bfi.h``
+declares, and its host-only logic (shape table, validation, finalize) agrees
+with the oracle.  No GPU: nothing here launches a kernel."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bfi.h")
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|bfi_status)\s*(bfi_\w+)\s*\(", txt,
+                                 re.M)))
+
+
+def test_header_declares_entry_points():
+    names = declared_symbols()
+    for n in ("bfi_eval", "bfi_finalize", "bfi_integrate", "bfi_integrate_adaptive",
+              "bfi_plan_run", "bfi_server_submit", "bfi_debug_points", "bfi_debug_action",
+              "bfi_autotune"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(bfi):
+    out = subprocess.run(["nm", "-D", "--defined-only", bfi.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s+(bfi_\w+)", out))
+    missing = [n for n in declared_symbols() if n not in exported]
+    assert not missing, missing
+    # the binding binds exactly the declared entry points
+    assert sorted(bfi.EXPORTED) == declared_symbols()
+
+
+def test_library_has_gfx950_code_objects(bfi):
+    out = subprocess.run(["/opt/rocm/bin/roc-obj-ls", bfi.LIB_PATH], capture_output=True,
+                         text=True)
+    if out.returncode != 0:
+        pytest.skip("roc-obj-ls unavailable")
+    assert "gfx950" in out.stdout
+
+
+def test_supported_shapes(bfi):
+    shapes = bfi.bfi_supported_shapes()
+    for s in [(4, 2), (8, 2), (10, 2), (16, 4), (1, 1), (3, 1)]:
+        assert s in shapes
+        assert bfi.bfi_shape_supported(*s)
+    assert not bfi.bfi_shape_supported(7, 7)
+
+
+def _oracle_case(nx, nt, B=2.0, k=3, per=3000, seed=3):
+    lat = oracle.lattice(nx, nt, nu=0.8)
+    sv = workloads.uniform_partition(nx * nt, B, k, per_sub=per)
+    sums = oracle.sums(lat, seed, sv.ids, sv.lo, sv.hi, sv.n, sv.offset)
+    return lat, sv, sums
+
+
+def _as_partials(sums, nx, sigma):
+    """Oracle sums -> bfi partial records with shift sigma per subvolume:
+    first-order sums times exp(sigma), second-order times exp(2 sigma)."""
+    ns = sums.shape[0]
+    sig = np.broadcast_to(np.asarray(sigma, dtype=np.float64), (ns,))
+    p = np.zeros((ns, 4 + 3 * nx))
+    f1, f2 = np.exp(sig), np.exp(2 * sig)
+    p[:, 0] = sums[:, 0]
+    p[:, 1] = sig
+    p[:, 2] = sums[:, 1] * f1
+    p[:, 3] = sums[:, 2] * f2
+    p[:, 4:4 + nx] = sums[:, 3:3 + nx] * f1[:, None]
+    p[:, 4 + nx:4 + 3 * nx] = sums[:, 3 + nx:3 + 3 * nx] * f2[:, None]
+    return p
+
+
+@pytest.mark.parametrize("shifted", [False, True])
+def test_finalize_matches_oracle(bfi, shifted):
+    nx, nt = 4, 2
+    lat, sv, sums = _oracle_case(nx, nt)
+    want = oracle.finalize(nx, nx * nt, sv.lo, sv.hi, sums)
+    sigma = np.linspace(-30, 40, len(sv)) if shifted else 0.0
+    got = bfi.bfi_finalize(bfi.lattice(nx, nt, nu=0.8), sv, _as_partials(sums, nx, sigma))
+    assert got["log_Z"] == pytest.approx(want["log_Z"], rel=1e-13, abs=1e-13)
+    assert got["Z"] == pytest.approx(want["Z"], rel=1e-12)
+    assert got["Z_err"] == pytest.approx(want["Z_err"], rel=1e-9)
+    assert got["ess"] == pytest.approx(want["ess"], rel=1e-12)
+    assert got["n_evals"] == want["n_evals"]
+    np.testing.assert_allclose(got["C"], want["C"], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(got["C_err"], want["C_err"], rtol=1e-8)
+
+
+def test_finalize_large_shift_keeps_log_z(bfi):
+    """Shifts far beyond the double range still give a finite log Z and C."""
+    nx, nt = 3, 1
+    lat, sv, sums = _oracle_case(nx, nt, k=2)
+    want = oracle.finalize(nx, nx * nt, sv.lo, sv.hi, sums)
+    p = _as_partials(sums, nx, 0.0)
+    p[:, 1] = -800.0            # claim the weights were exp(-800) times larger
+    got = bfi.bfi_finalize(bfi.lattice(nx, nt), sv, p)
+    assert got["log_Z"] == pytest.approx(want["log_Z"] + 800.0, rel=1e-13)
+    np.testing.assert_allclose(got["C"], want["C"], rtol=1e-12)
+
+
+def test_finalize_rejects_short_records(bfi):
+    lat, sv, sums = _oracle_case(2, 1, k=1)
+    p = _as_partials(sums, 2, 0.0)
+    p[0, 0] = 1.0
+    with pytest.raises(bfi.BfiError) as e:
+        bfi.bfi_finalize(bfi.lattice(2, 1), sv, p)
+    assert e.value.name == "BFI_EINVAL"

@@ -1,0 +1,331 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 oracle
+on the same seeded inputs.
+
+Bars:
+  * Philox words and points: bit-exact (FP64 form); the FP32 form's point is the
+    FP64 point to within one FP32 rounding of the map.
+  * Action S: relative 1e-13 in FP64 (the kernel evaluates the residual in a
+    rearranged but algebraically equal form); 1e-5 in the FP32 form.
+  * Per-subvolume sums: relative 1e-10 of each sum's L1 scale (sample order and
+    reduction tree differ from the oracle's sequential order).
+  * Z and C(r): 1e-6 relative (C(r) against C(0), an upper bound of the L1 scale
+    sum |p_r| w / sum w), in FP64; 1e-4 in the FP32 form.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = "fp64", "fp32"
+
+
+def unshift(part, nx):
+    """bfi partial records -> oracle sums layout [n, w, w2, pw, pw2, pww]."""
+    sig = part[:, 1]
+    f1, f2 = np.exp(-sig), np.exp(-2 * sig)
+    out = np.zeros((part.shape[0], 3 + 3 * nx))
+    out[:, 0] = part[:, 0]
+    out[:, 1] = part[:, 2] * f1
+    out[:, 2] = part[:, 3] * f2
+    out[:, 3:3 + nx] = part[:, 4:4 + nx] * f1[:, None]
+    out[:, 3 + nx:3 + 3 * nx] = part[:, 4 + nx:4 + 3 * nx] * f2[:, None]
+    return out
+
+
+def assert_sums_close(got, want, nx, rtol):
+    """Compare sums records elementwise against L1 scales: w and w^2 are
+    positive; |sum p w| <= sqrt(n sum (p w)^2) and |sum p w^2| <=
+    sqrt(sum (p w)^2 sum w^2) by Cauchy-Schwarz."""
+    assert np.array_equal(got[:, 0], want[:, 0])
+    n = want[:, 0:1]
+    pw2 = want[:, 3 + nx:3 + 2 * nx]
+    scale = np.concatenate([want[:, 1:3], np.sqrt(n * pw2), pw2,
+                            np.sqrt(pw2 * want[:, 2:3])], axis=1)
+    err = np.abs(got[:, 1:] - want[:, 1:])
+    bad = err > rtol * scale + 1e-300
+    assert not bad.any(), (np.argwhere(bad)[:5], (err / (scale + 1e-300)).max())
+    return float((err / (scale + 1e-300)).max())
+
+
+def assert_result_close(got, want, tol):
+    assert got["log_Z"] == pytest.approx(want["log_Z"], abs=tol)
+    assert abs(got["Z"] - want["Z"]) <= tol * want["Z"]
+    c0 = abs(want["C"][0])
+    assert np.all(np.abs(got["C"] - want["C"]) <= tol * c0), (got["C"], want["C"])
+
+
+# ---------------------------------------------------------------- points
+
+@pytest.mark.parametrize("d", [1, 3, 4, 8, 20, 64])
+def test_points_bit_exact(bfi, ctx, d):
+    rng = np.random.Generator(np.random.PCG64(d))
+    for sub_id, seed in [(1, 1), (1037, 1), (2**33 + 5, 2**40 + 3), (2**64 - 1, 0)]:
+        lo = rng.uniform(-4, 0, size=d)
+        hi = lo + rng.choice([0.5, 1.0, 4.0, 8.0], size=d)
+        idx = np.array([0, 1, 2, 1023, 2**20 - 1, 2**32 + 7, 2**45 + 11], dtype=np.uint64)
+        got = bfi.bfi_debug_points(ctx, d, F64, seed, sub_id, lo, hi, idx)
+        want = np.stack([oracle.point(d, seed, sub_id, lo, hi, int(i)) for i in idx])
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), (sub_id, seed)
+        assert np.all(got > lo) and np.all(got < hi)
+
+
+def test_fp32_points_round_the_fp64_point(bfi, ctx):
+    d = 20
+    lo, hi = np.full(d, -4.0), np.full(d, 4.0)
+    idx = np.arange(0, 4096, dtype=np.uint64)
+    p64 = bfi.bfi_debug_points(ctx, d, F64, 1, 1024, lo, hi, idx)
+    p32 = bfi.bfi_debug_points(ctx, d, F32, 1, 1024, lo, hi, idx)
+    assert np.all(p32 == p32.astype(np.float32))
+    # (float)x rounds the word to 24 bits, then one FP32 fma: within 2 FP32 ulps of 4
+    assert np.max(np.abs(p32 - p64)) <= 2 * 2.0**-21
+
+
+# ---------------------------------------------------------------- action
+
+SHAPES = [(1, 1), (1, 2), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2), (5, 3), (8, 2),
+          (10, 2), (16, 4)]
+
+
+@pytest.mark.parametrize("nx,nt", SHAPES)
+def test_action_matches_oracle(bfi, ctx, nx, nt):
+    rng = np.random.Generator(np.random.PCG64(100 + nx * nt))
+    d = nx * nt
+    for params in [dict(), dict(nu=0.37, D=1.7, a=0.8, tau=0.6), dict(g=0.0, m2=0.5),
+                   dict(nu=0.05, D=0.5, m2=1.25)]:
+        lat_o = oracle.lattice(nx, nt, **params)
+        lat_g = bfi.lattice(nx, nt, **params)
+        U = rng.uniform(-4, 4, size=(300, d))
+        want = oracle.action_batch(lat_o, U)
+        got = bfi.bfi_debug_action(ctx, lat_g, F64, U)
+        np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-13)
+        got32 = bfi.bfi_debug_action(ctx, lat_g, F32, U)
+        np.testing.assert_allclose(got32, want, rtol=2e-5, atol=1e-4)
+
+
+def test_action_constant_field_is_zero(bfi, ctx):
+    for nx, nt in [(4, 2), (10, 2), (16, 4)]:
+        U = np.outer([0.0, 0.37, -3.99, 2.5], np.ones(nx * nt))
+        for prec in (F64, F32):
+            assert np.all(bfi.bfi_debug_action(ctx, bfi.lattice(nx, nt), prec, U) == 0.0)
+
+
+# ------------------------------------------------------------- sums / eval
+
+def oracle_and_gpu(bfi, ctx, nx, nt, sv, seed, prec=F64, launch=None, params=None, split=False):
+    params = params or {}
+    lat_o = oracle.lattice(nx, nt, **params)
+    want = oracle.sums(lat_o, seed, sv.ids, sv.lo, sv.hi, sv.n, sv.offset)
+    got = bfi.bfi_eval(ctx, bfi.lattice(nx, nt, **params), prec, seed, sv, launch, split=split)
+    return lat_o, want, got
+
+
+def test_config_4x2_full(bfi, ctx):
+    """4x2 lattice, nu = D = 1, box [-4,4]^8, 2^20 points (seed 1) over 16
+    subvolumes bisecting dims 0-3: every subvolume against the oracle."""
+    w = workloads.WORKLOADS["burgers4x2"]
+    sv = workloads.uniform_partition(w.d, w.box, w.split_log2, w.budget // w.n_sub)
+    lat_o, want, got = oracle_and_gpu(bfi, ctx, 4, 2, sv, w.seed)
+    assert_sums_close(unshift(got, 4), want, 4, 1e-10)
+    res_o = oracle.finalize(4, 8, sv.lo, sv.hi, want)
+    res_g = bfi.bfi_finalize(bfi.lattice(4, 2), sv, got)
+    assert_result_close(res_g, res_o, 1e-6)
+    np.testing.assert_allclose(res_g["C_err"], res_o["C_err"], rtol=1e-6)
+    # bfi_integrate makes the same plan
+    res_i = bfi.bfi_integrate(ctx, bfi.lattice(4, 2), F64, w.seed, -w.box, w.box, w.split_log2,
+                              w.budget)
+    assert res_i["Z"] == res_g["Z"] and np.array_equal(res_i["C"], res_g["C"])
+
+
+@pytest.mark.parametrize("nx,nt", [(3, 2), (5, 3), (10, 2), (2, 1), (1, 2)])
+def test_ragged_uneven_partition(bfi, ctx, nx, nt):
+    """Uneven bisection tree, sample counts that are not multiples of the work
+    item (2, 3, item +- 1, several items plus a tail), nonzero offsets."""
+    d = nx * nt
+    sv = workloads.random_partition(d, 4.0, 12, per_sub=1, seed=nx * 10 + nt)
+    item = 64 * 256
+    sv.n[:] = [2, 3, 255, 256, 257, item - 1, item, item + 1, 3 * item + 17, 1000, 77, 5000]
+    sv.offset[:] = [0, 5, 2**20, 3, 0, 2**33, 0, 1, 7, 0, 0, 123456789]
+    lat_o, want, got = oracle_and_gpu(bfi, ctx, nx, nt, sv, 7, params=dict(nu=0.6))
+    assert_sums_close(unshift(got, nx), want, nx, 1e-10)
+
+
+@pytest.mark.parametrize("launch", [
+    dict(samples_per_thread=1, block=64, persistent=0),
+    dict(samples_per_thread=7, block=128, persistent=0),
+    dict(samples_per_thread=64, block=256, persistent=0),
+    dict(samples_per_thread=64, block=256, persistent=1),
+    dict(samples_per_thread=16, block=64, persistent=1),
+    dict(samples_per_thread=256, block=128, persistent=1),
+])
+def test_launch_shapes_agree(bfi, ctx, launch):
+    nx, nt = 10, 2
+    sv = workloads.uniform_partition(20, 4.0, 5, per_sub=40_000)
+    sv.n[3] = 17
+    lat_o, want, got = oracle_and_gpu(bfi, ctx, nx, nt, sv, 1, launch=bfi.launch(**launch))
+    assert_sums_close(unshift(got, nx), want, nx, 1e-10)
+
+
+def test_persistent_equals_grid_bitwise(bfi, ctx):
+    sv = workloads.random_partition(20, 4.0, 40, per_sub=30_000, seed=3)
+    sv.n[::3] = 12_345
+    a = bfi.bfi_eval(ctx, bfi.lattice(10, 2), F64, 5, sv, bfi.launch(32, 256, 0))
+    b = bfi.bfi_eval(ctx, bfi.lattice(10, 2), F64, 5, sv, bfi.launch(32, 256, 1))
+    c = bfi.bfi_eval(ctx, bfi.lattice(10, 2), F64, 5, sv, bfi.launch(32, 256, 1))
+    assert np.array_equal(a, b) and np.array_equal(b, c)
+    a32 = bfi.bfi_eval(ctx, bfi.lattice(10, 2), F32, 5, sv, bfi.launch(32, 256, 0))
+    b32 = bfi.bfi_eval(ctx, bfi.lattice(10, 2), F32, 5, sv, bfi.launch(32, 256, 1))
+    assert np.array_equal(a32, b32)
+
+
+@pytest.mark.parametrize("nx,nt,box", [(4, 2, 4.0), (10, 2, 4.0), (10, 2, 1.0), (16, 4, 3.0),
+                                        (8, 2, 4.0)])
+def test_fp32_shifted_form_error(bfi, ctx, nx, nt, box):
+    """FP32 action and exp, FP64 sums: Z and C(r) within 1e-4 of the FP64 oracle
+    on the same points (stated bound)."""
+    d = nx * nt
+    sv = workloads.uniform_partition(d, box, 4, per_sub=20_000)
+    lat_o, want, got = oracle_and_gpu(bfi, ctx, nx, nt, sv, 1, prec=F32)
+    res_o = oracle.finalize(nx, d, sv.lo, sv.hi, want)
+    res_g = bfi.bfi_finalize(bfi.lattice(nx, nt), sv, got)
+    assert_result_close(res_g, res_o, 1e-4)
+    assert np.all(np.isfinite(got))
+
+
+def test_split_statistics(bfi, ctx):
+    nx, nt = 10, 2
+    sv = workloads.random_partition(20, 4.0, 6, per_sub=25_000, seed=11)
+    sv.n[2] = 999
+    for prec in (F64, F32):
+        part, spl = bfi.bfi_eval(ctx, bfi.lattice(nx, nt), prec, 3, sv, None, split=True)
+        want = oracle.split_sums(oracle.lattice(nx, nt), 3, sv.ids, sv.lo, sv.hi, sv.n, sv.offset)
+        sig = spl[:, 0:1]
+        assert np.array_equal(sig[:, 0], part[:, 1])
+        got = np.concatenate([spl[:, 1:21] * np.exp(-sig), spl[:, 21:41] * np.exp(-2 * sig)], 1)
+        tol = 1e-10 if prec == F64 else 1e-4
+        tot = unshift(part, nx)
+        scale = np.concatenate([np.repeat(tot[:, 1:2], 20, 1), np.repeat(tot[:, 2:3], 20, 1)], 1)
+        assert np.all(np.abs(got - want) <= tol * scale)
+
+
+def test_graph_replays_match_eager(bfi, ctx):
+    nx, nt = 10, 2
+    sv = workloads.uniform_partition(20, 4.0, 6, per_sub=20_000)
+    lat = bfi.lattice(nx, nt)
+    eager = bfi.bfi_eval(ctx, lat, F64, 9, sv, bfi.launch(64, 256, 1))
+    plan = bfi.bfi_plan_create(ctx, lat, F64, sv, bfi.launch(64, 256, 1, use_graph=1))
+    try:
+        for rep in range(4):
+            bfi.bfi_plan_run(plan, 9)
+            got = bfi.bfi_plan_partials(plan, len(sv), nx)
+            assert np.array_equal(got, eager), rep
+            # eager work between replays
+            other = bfi.bfi_eval(ctx, bfi.lattice(4, 2), F64, rep, workloads.uniform_partition(
+                8, 4.0, 2, per_sub=1000))
+            assert np.all(np.isfinite(other))
+        bfi.bfi_plan_run(plan, 10)   # new seed: graph recaptured
+        got10 = bfi.bfi_plan_partials(plan, len(sv), nx)
+        assert np.array_equal(got10, bfi.bfi_eval(ctx, lat, F64, 10, sv, bfi.launch(64, 256, 1)))
+    finally:
+        bfi.bfi_plan_destroy(plan)
+
+
+def test_plan_writes_torch_buffer_on_torch_stream(bfi, ctx):
+    torch = pytest.importorskip("torch")
+    nx, nt = 4, 2
+    sv = workloads.uniform_partition(8, 4.0, 4, per_sub=10_000)
+    lat = bfi.lattice(nx, nt)
+    eager = bfi.bfi_eval(ctx, lat, F64, 1, sv)
+    buf = torch.zeros((len(sv), bfi.partial_len(nx)), dtype=torch.float64, device="cuda:0")
+    stream = torch.cuda.Stream()
+    plan = bfi.bfi_plan_create(ctx, lat, F64, sv)
+    try:
+        bfi.bfi_plan_run(plan, 1, buf, stream)
+        stream.synchronize()
+        assert np.array_equal(buf.cpu().numpy(), eager)
+    finally:
+        bfi.bfi_plan_destroy(plan)
+
+
+# ------------------------------------------------------- full-size samples
+
+def test_config_10x2_full_size_sampled(bfi, ctx):
+    """10x2, nu = 1, box [-4,4]^20, 2^30 points over 1024 subvolumes in the
+    benchmark's launch configuration; 6 subvolumes checked against the oracle."""
+    w = workloads.WORKLOADS["burgers10x2"]
+    sv = workloads.uniform_partition(w.d, w.box, w.split_log2, w.budget // w.n_sub)
+    lat = bfi.lattice(10, 2)
+    for prec in (F64, F32):
+        plan = bfi.bfi_plan_create(ctx, lat, prec, sv)
+        try:
+            bfi.bfi_plan_run(plan, w.seed)
+            got = bfi.bfi_plan_partials(plan, len(sv), 10)
+        finally:
+            bfi.bfi_plan_destroy(plan)
+        pick = np.array([0, 1, 511, 512, 700, 1023])
+        sub = sv.subset(pick)
+        want = oracle.sums(oracle.lattice(10, 2), w.seed, sub.ids, sub.lo, sub.hi, sub.n,
+                           sub.offset)
+        if prec == F64:
+            assert_sums_close(unshift(got[pick], 10), want, 10, 1e-10)
+            f64_result = bfi.bfi_finalize(lat, sv, got)
+        else:
+            r32 = bfi.bfi_finalize(lat, sv, got)
+            # same points: the FP32 form agrees with FP64 within the stated bound
+            assert_result_close(r32, f64_result, 1e-4)
+        assert got[:, 0].sum() == 2**30
+
+
+def test_config_16x4_sampled(bfi, ctx):
+    """16x4, nu = 0.5, box [-3,3]^64, 4096 subvolumes (dims 0-11); 2^26 points
+    (2^14 per subvolume) on the GPU, 3 subvolumes against the oracle."""
+    w = workloads.WORKLOADS["burgers16x4"]
+    sv = workloads.uniform_partition(w.d, w.box, w.split_log2, 1 << 14)
+    lat = bfi.lattice(16, 4, nu=0.5)
+    got = bfi.bfi_eval(ctx, lat, F64, w.seed, sv)
+    pick = np.array([0, 2047, 4095])
+    sub = sv.subset(pick)
+    want = oracle.sums(oracle.lattice(16, 4, nu=0.5), w.seed, sub.ids, sub.lo, sub.hi, sub.n,
+                       sub.offset)
+    assert_sums_close(unshift(got[pick], 16), want, 16, 1e-10)
+    got32 = bfi.bfi_eval(ctx, lat, F32, w.seed, sv)
+    assert_result_close(bfi.bfi_finalize(lat, sv, got32), bfi.bfi_finalize(lat, sv, got), 1e-4)
+
+
+# ------------------------------------------------------------------ edges
+
+def test_invalid_arguments(bfi, ctx):
+    sv = workloads.uniform_partition(8, 4.0, 1, per_sub=100)
+    with pytest.raises(bfi.BfiError) as e:
+        bfi.bfi_eval(ctx, bfi.lattice(7, 7), F64, 1, workloads.uniform_partition(49, 1.0, 0, 10))
+    assert e.value.name == "BFI_EUNSUPPORTED"
+    for bad in (dict(D=0.0), dict(nu=float("nan")), dict(a=-1.0), dict(m2=-1.0)):
+        with pytest.raises(bfi.BfiError) as e:
+            bfi.bfi_eval(ctx, bfi.lattice(4, 2, **bad), F64, 1, sv)
+        assert e.value.name == "BFI_EINVAL"
+    bad = sv.subset([0, 1])
+    bad.n[0] = 1
+    with pytest.raises(bfi.BfiError):
+        bfi.bfi_eval(ctx, bfi.lattice(4, 2), F64, 1, bad)
+    bad = sv.subset([0, 1])
+    bad.hi[1, 3] = bad.lo[1, 3]
+    with pytest.raises(bfi.BfiError):
+        bfi.bfi_eval(ctx, bfi.lattice(4, 2), F64, 1, bad)
+    with pytest.raises(bfi.BfiError):
+        bfi.bfi_eval(ctx, bfi.lattice(4, 2), F64, 1, sv, bfi.launch(64, 96, 0))
+    # the library stays usable after errors
+    assert np.all(np.isfinite(bfi.bfi_eval(ctx, bfi.lattice(4, 2), F64, 1, sv)))
+
+
+def test_empty_list_is_a_no_op(bfi, ctx):
+    empty = workloads.uniform_partition(8, 4.0, 1, per_sub=10).subset([])
+    out = bfi.bfi_eval(ctx, bfi.lattice(4, 2), F64, 1, empty)
+    assert out.shape == (0, 16)
+
+
+def test_minimal_subvolume_two_samples(bfi, ctx):
+    sv = workloads.uniform_partition(3, 2.0, 0, per_sub=2)
+    lat_o, want, got = oracle_and_gpu(bfi, ctx, 3, 1, sv, 1)
+    assert_sums_close(unshift(got, 3), want, 3, 1e-12)
