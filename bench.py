@@ -30,41 +30,48 @@ import workloads  # noqa: E402
 
 METRIC = "integrand evals/s @10x2 lattice, FP32-eval vs FP64 at rel err 1e-3; p99 latency"
 
-# VALU issue model (lane-instruction slots per evaluation), see valu_slots_per_eval.
-# Issue costs relative to a full-rate VALU instruction, measured on gfx950 with
-# an independent-chain microbenchmark (documented with the roofline).
-COST = {"mul32": 1.0, "bitop3": 1.0, "f64": 1.0, "f32": 1.0, "cvt": 1.0, "exp32": 1.0}
-EXP64_SLOTS = 18.0          # instructions of the FP64 exp routine
-PEAK_SLOTS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: full-rate lane slots/s
+# VALU issue roofline.  MI355X: 256 CUs at 2.4 GHz; the published vector peaks
+# (FP64 78.6 TFLOP/s, FP32 157.3 TFLOP/s) fix the issue width per clock and CU:
+# 64 lanes for FP64 arithmetic, and 128 lanes for FP32 arithmetic.  A measured
+# independent-chain probe on gfx950 puts 32-bit integer multiplies
+# (v_mad_u64_u32, v_mul_lo/hi_u32) and conversions at the FP64 rate, and 32-bit
+# logic (v_xor_b32, v_bitop3_b32) and non-packed v_fma_f32 at up to twice it.
+# Work is counted in FP64-rate lane slots: 1 per 64-lane-class instruction,
+# 1/2 per 128-lane-class instruction, 1 per transcendental.
+SLOT = {"f64": 1.0, "mul32": 1.0, "cvt": 1.0, "f32": 0.5, "logic32": 0.5, "trans": 1.0}
+EXP64_OPS = 19              # FP64 exp routine: scale, round, 2 reductions, 11 poly, ldexp, checks
+PEAK_SLOTS = 256 * 64 * 2.4e9   # FP64-rate lane slots per second (= FP64 FMA/s)
 PEAK_FP64 = 78.6e12
 
 
 def valu_slots_per_eval(nx: int, nt: int, prec: str) -> float:
-    """Lane-instruction slots one evaluation needs at the measured issue costs:
-      Philox4x32-10: per block 10 rounds x (2 mulhi + 2 mullo + 2 three-input xor)
+    """FP64-rate lane slots one evaluation needs (algorithmic instruction counts):
+      Philox4x32-10: per block 10 rounds x (2 wide 32x32 multiplies + 2 xor3)
       point map:     per variable one u32->float conversion and one fma
-      action:        per site 6 (two differences, three fma, one fma into S), + 1
-      weight:        FP64 exp routine, or FP32 shift multiply + exp2 (+1 convert)
-      sums:          w, w^2 (2) + per r: product, add, 2 fma (4) + 1 (u_0 w)
-                     (FP32 form: one more conversion per r)"""
+      action:        per site 6 (two sums/differences, three fma, one fma into S), + 1
+      weight:        FP64 exp routine; FP32 form: multiply, exp2, widen to FP64
+      sums:          w, w^2 (2) + u_0 w (1) + per r: product, add, 2 fma (4)
+                     FP32 form: the product in FP32, then one widening per r"""
     d, nb = nx * nt, (nx * nt + 3) // 4
-    philox = nb * 10 * (4 * COST["mul32"] + 2 * COST["bitop3"])
-    fcost = COST["f64"] if prec == "fp64" else COST["f32"]
-    mapping = d * (COST["cvt"] + fcost)
-    action = (6 * d + 1) * fcost
+    philox = nb * 10 * (2 * SLOT["mul32"] + 2 * SLOT["logic32"])
     if prec == "fp64":
-        weight = EXP64_SLOTS
-        sums = (2 + 4 * nx + 1) * COST["f64"]
+        mapping = d * (SLOT["cvt"] + SLOT["f64"])
+        action = (6 * d + 1) * SLOT["f64"]
+        weight = EXP64_OPS * SLOT["f64"]
+        sums = (3 + 4 * nx) * SLOT["f64"]
     else:
-        weight = COST["f32"] + COST["exp32"] + COST["cvt"]
-        sums = (2 + 4 * nx + 1) * COST["f64"] + nx * COST["cvt"]
+        mapping = d * (SLOT["cvt"] * 0.5 + SLOT["f32"])   # u32->f32 is a 32-bit op
+        action = (6 * d + 1) * SLOT["f32"]
+        weight = SLOT["f32"] + SLOT["trans"] + SLOT["cvt"] + SLOT["f32"]  # (sigma-S)*log2e, exp2, widen, compare
+        sums = (2 + 3 * nx) * SLOT["f64"] + nx * (SLOT["f32"] + SLOT["cvt"]) + SLOT["f32"]
     return philox + mapping + action + weight + sums
 
 
 def fp64_flops_per_eval(nx: int, nt: int) -> float:
-    """FP64 floating-point operations (FMA = 2) of one FP64-form evaluation."""
+    """FP64 floating-point operations (FMA = 2) of one FP64-form evaluation:
+    map 2d, action 10 per site + 1, exp ~30, sums 2 + 1 + 7 per r (+ w^2 fma)."""
     d = nx * nt
-    return 2 * d + (2 + 2 + 3 * 2 + 2) * d + 1 + 30 + (2 + 2 * nx * 3 + 2 * nx) + 1
+    return 2 * d + 10 * d + 1 + 30 + (1 + 2) + 1 + 7 * nx
 
 
 def parse():
@@ -73,7 +80,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="burgers10x2", choices=sorted(workloads.WORKLOADS))
-    ap.add_argument("--headline", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--headline", default="fp32", choices=["fp64", "fp32"],
+                    help="form reported as value (fp32: FP32 action/exp, FP64 sums)")
     ap.add_argument("--cpu-samples-log2", type=int, default=17,
                     help="oracle sample: first 2^k samples of every subvolume")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -162,8 +170,9 @@ def main():
     evals_per_launch = head["evals_per_step"]
     achieved = slots * evals_per_launch / (head["kernel_ms"] * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-                "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
-                "kernel": "mc_kernel", "slots_per_eval": slots,
+                "unit": "T FP64-rate lane slots/s", "frac": achieved / PEAK_SLOTS,
+                "traffic": None, "kernel": "mc_kernel (graph replay: reset, kernel, merge)",
+                "slots_per_eval": slots,
                 "kernel_ms": head["kernel_ms"],
                 "fp64_flop_frac": (fp64_flops_per_eval(w.nx, w.nt) * evals_per_launch /
                                    (forms["fp64"]["kernel_ms"] * 1e-3)) / PEAK_FP64}
@@ -186,7 +195,10 @@ def main():
                    "work_items": head["n_items"]},
         "forms": {p: {"evals_per_s": f["evals_per_s"], "ms_per_step": f["ms_per_step"],
                       "kernel_ms": f["kernel_ms"], "kernel_evals_per_s":
-                          f["evals_per_step"] / (f["kernel_ms"] * 1e-3), "launch": f["launch"]}
+                          f["evals_per_step"] / (f["kernel_ms"] * 1e-3),
+                      "valu_frac": valu_slots_per_eval(w.nx, w.nt, p) * f["evals_per_step"] /
+                          (f["kernel_ms"] * 1e-3) / PEAK_SLOTS,
+                      "launch": f["launch"]}
                   for p, f in forms.items()},
         "fp32_speedup_vs_fp64": forms["fp32"]["evals_per_s"] / forms["fp64"]["evals_per_s"],
         "fp32_deviation_vs_fp64": dev,

@@ -166,8 +166,9 @@ bfi_status bfi_plan_partials(bfi_plan *plan, double *partials);
 /* Work items of the plan and the launch shape it resolved to. */
 bfi_status bfi_plan_info(const bfi_plan *plan, uint64_t *n_items, uint64_t *n_evals,
                          bfi_launch *resolved);
-/* Duration in milliseconds of the Monte Carlo kernel of the plan's last run,
- * from HIP events recorded around it on the run's stream (waits for it). */
+/* Duration in milliseconds of the plan's last run on the device, from HIP
+ * events on the run's stream (waits for it): the Monte Carlo kernel alone for
+ * direct launches, the whole replay (queue reset, kernel, merge) for graphs. */
 bfi_status bfi_plan_kernel_ms(bfi_plan *plan, double *ms);
 bfi_status bfi_plan_destroy(bfi_plan *plan);
 

@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbfi.so")
+# BFI_LIBRARY may name another build of the same ABI (e.g. an installed copy)
+LIB_PATH = os.environ.get("BFI_LIBRARY") or os.path.join(_HERE, "libbfi.so")
 
 BFI_FP64 = 0
 BFI_FP32_SHIFTED = 1
@@ -159,6 +160,13 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python paper_1803_07560_amd/build.py` (or __graft_entry__.build())")
+        # PyTorch ships its own HIP runtime (same soname as ROCm's).  Loading it
+        # first makes libbfi.so bind to that copy, so torch tensors, streams and
+        # this library share one runtime in the process.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = C.CDLL(LIB_PATH)
         for name, (args, res) in _SIGNATURES.items():
             f = getattr(lib, name)

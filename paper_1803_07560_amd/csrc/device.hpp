@@ -20,6 +20,17 @@ constexpr uint32_t kPhiloxMulB = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxWeylA = 0x9E3779B9u;
 constexpr uint32_t kPhiloxWeylB = 0xBB67AE85u;
 
+// Full 32x32 -> 64-bit product in one instruction.  On gfx950 v_mad_u64_u32
+// issues at the rate of v_mul_lo_u32 and v_mul_hi_u32 (measured), so one wide
+// multiply replaces the separate low and high halves the compiler would pick.
+// Pure register arithmetic: the carry-out goes to vcc, declared clobbered.
+__device__ __forceinline__ uint64_t mul_wide(uint32_t a, uint32_t b)
+{
+    uint64_t r;
+    asm("v_mad_u64_u32 %0, vcc, %1, %2, 0" : "=v"(r) : "v"(a), "s"(b) : "vcc");
+    return r;
+}
+
 // One Philox4x32-10 block for counter (lo32(q), hi32(q), lo32(id), hi32(id)).
 __device__ __forceinline__ void philox_block(uint64_t q, uint32_t id_lo, uint32_t id_hi,
                                              uint32_t key_lo, uint32_t key_hi, uint32_t out[4])
@@ -29,12 +40,16 @@ __device__ __forceinline__ void philox_block(uint64_t q, uint32_t id_lo, uint32_
     uint32_t k0 = key_lo, k1 = key_hi;
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t lo_a = kPhiloxMulA * c0, hi_a = __umulhi(kPhiloxMulA, c0);
-        const uint32_t lo_b = kPhiloxMulB * c2, hi_b = __umulhi(kPhiloxMulB, c2);
-        c0 = hi_b ^ c1 ^ k0;
-        c2 = hi_a ^ c3 ^ k1;
-        c1 = lo_b;
-        c3 = lo_a;
+        const uint64_t pa = mul_wide(c0, kPhiloxMulA);
+        // round 0 multiplies the subvolume id, uniform across the block: left to
+        // the compiler it becomes a scalar multiply
+        const uint64_t pb = round == 0 ? static_cast<uint64_t>(kPhiloxMulB) * c2
+                                       : mul_wide(c2, kPhiloxMulB);
+        // three-input xor in one v_bitop3_b32 (truth table 0x96)
+        c0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pb >> 32), c1, k0, 0x96);
+        c2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pa >> 32), c3, k1, 0x96);
+        c1 = static_cast<uint32_t>(pb);
+        c3 = static_cast<uint32_t>(pa);
         k0 += kPhiloxWeylA;
         k1 += kPhiloxWeylB;
     }

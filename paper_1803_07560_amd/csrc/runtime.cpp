@@ -447,7 +447,7 @@ bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const 
     return BFI_OK;
 }
 
-bfi_status plan_enqueue(bfi_plan *p, uint64_t seed, double *dst, hipStream_t st)
+bfi_status plan_enqueue(bfi_plan *p, uint64_t seed, double *dst, hipStream_t st, bool timed)
 {
     McArgs a{};
     a.base64 = p->d_base64;
@@ -468,9 +468,11 @@ bfi_status plan_enqueue(bfi_plan *p, uint64_t seed, double *dst, hipStream_t st)
     LaunchSpec spec{p->prec, p->launch.block, p->split ? 1 : 0, p->launch.persistent, p->grid};
     if (p->launch.persistent)
         BFI_HIP(launch_reset_head(p->d_head, st));
-    BFI_HIP(hipEventRecord(p->ev_start, st));
+    if (timed)
+        BFI_HIP(hipEventRecord(p->ev_start, st));
     BFI_HIP(launch_mc(p->lat.nx, p->lat.nt, spec, a, st));
-    BFI_HIP(hipEventRecord(p->ev_stop, st));
+    if (timed)
+        BFI_HIP(hipEventRecord(p->ev_stop, st));
     MergeArgs m{};
     m.item_rec = p->d_item_rec;
     m.item_split = p->d_item_split;
@@ -601,7 +603,7 @@ bfi_status bfi_plan_run(bfi_plan *p, uint64_t seed, double *partials_dev, void *
                 p->graph_def = nullptr;
             }
             BFI_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            bfi_status s = plan_enqueue(p, seed, partials_dev, st);
+            bfi_status s = plan_enqueue(p, seed, partials_dev, st, false);
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(st, &g);
             if (s != BFI_OK) {
@@ -616,9 +618,12 @@ bfi_status bfi_plan_run(bfi_plan *p, uint64_t seed, double *partials_dev, void *
             p->graph_stream = st;
             p->graph_dst = partials_dev;
         }
+        // a replay is timed as a whole: queue reset, kernel and merge
+        BFI_HIP(hipEventRecord(p->ev_start, st));
         BFI_HIP(hipGraphLaunch(p->graph, st));
+        BFI_HIP(hipEventRecord(p->ev_stop, st));
     } else {
-        BFI_TRY(plan_enqueue(p, seed, partials_dev, st));
+        BFI_TRY(plan_enqueue(p, seed, partials_dev, st, true));
     }
     p->last_stream = st;
     return BFI_OK;
@@ -692,7 +697,7 @@ bfi_status bfi_eval(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec
     bfi_launch l = p->launch;
     l.use_graph = 0;
     p->launch = l;
-    bfi_status s = plan_enqueue(p, seed, nullptr, ctx->stream);
+    bfi_status s = plan_enqueue(p, seed, nullptr, ctx->stream, true);
     p->last_stream = ctx->stream;
     if (s == BFI_OK)
         s = bfi_plan_partials(p, partials);

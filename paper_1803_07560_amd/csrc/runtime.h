@@ -121,6 +121,8 @@ struct bfi_plan {
 namespace bfi {
 bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const SubList &subs,
                       const bfi_launch *launch, bool split, bfi_plan **out);
-bfi_status plan_enqueue(bfi_plan *p, uint64_t seed, double *dst, hipStream_t stream);
+// timed: record the plan's events around the Monte Carlo kernel (not inside a
+// graph capture, where recorded events carry no timestamps)
+bfi_status plan_enqueue(bfi_plan *p, uint64_t seed, double *dst, hipStream_t stream, bool timed);
 bfi_status plan_free(bfi_plan *p);
 }  // namespace bfi

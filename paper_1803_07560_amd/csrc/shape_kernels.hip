@@ -59,7 +59,10 @@ __global__ void __launch_bounds__(BLOCK) mc_kernel(McArgs a)
     constexpr int REC = 4 + 3 * NX;
     static_assert(!SPLIT || D <= 32, "split statistics keep one bit per dimension in 32 bits");
 
+    // point map held in registers when 2d values take at most 80 VGPRs
+    constexpr bool kHoist = 2 * D * sizeof(T) / 4 <= 80;
     __shared__ double red[NW][NF];
+    __shared__ T map_lds[2][kHoist ? 1 : D];
     __shared__ float red_sigma[NW];
     __shared__ uint32_t next_item;
 
@@ -84,15 +87,43 @@ __global__ void __launch_bounds__(BLOCK) mc_kernel(McArgs a)
         const uint64_t id = a.ids[s];
         const uint64_t first_index = a.offsets[s] + wi.start;
         const uint32_t id_lo = static_cast<uint32_t>(id), id_hi = static_cast<uint32_t>(id >> 32);
-        const T *base;
-        const T *scale;
+        const T *base_g;
+        const T *scale_g;
         if constexpr (PREC == kFP64) {
-            base = a.base64 + static_cast<size_t>(s) * D;
-            scale = a.scale64 + static_cast<size_t>(s) * D;
+            base_g = a.base64 + static_cast<size_t>(s) * D;
+            scale_g = a.scale64 + static_cast<size_t>(s) * D;
         } else {
-            base = a.base32 + static_cast<size_t>(s) * D;
-            scale = a.scale32 + static_cast<size_t>(s) * D;
+            base_g = a.base32 + static_cast<size_t>(s) * D;
+            scale_g = a.scale32 + static_cast<size_t>(s) * D;
         }
+        // the subvolume's point map stays in registers for the whole item when
+        // it fits (2d values); larger lattices read it from LDS (broadcast)
+        T base_r[kHoist ? D : 1], scale_r[kHoist ? D : 1];
+        if constexpr (kHoist) {
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk) {
+                base_r[kk] = base_g[kk];
+                scale_r[kk] = scale_g[kk];
+            }
+        } else {
+            for (int kk = tid; kk < D; kk += BLOCK) {
+                map_lds[0][kk] = base_g[kk];
+                map_lds[1][kk] = scale_g[kk];
+            }
+            __syncthreads();
+        }
+        auto base_of = [&](int kk) -> T {
+            if constexpr (kHoist)
+                return base_r[kk];
+            else
+                return map_lds[0][kk];
+        };
+        auto scale_of = [&](int kk) -> T {
+            if constexpr (kHoist)
+                return scale_r[kk];
+            else
+                return map_lds[1][kk];
+        };
 
         double acc[NF];
 #pragma unroll
@@ -123,7 +154,7 @@ __global__ void __launch_bounds__(BLOCK) mc_kernel(McArgs a)
                     const uint32_t x = blk[kk & 3];
                     if constexpr (SPLIT)
                         upper |= (x >> 31) << kk;
-                    out[m] = dev::map_word(x, scale[kk], base[kk]);
+                    out[m] = dev::map_word(x, scale_of(kk), base_of(kk));
                 }
             };
             T first[NX];

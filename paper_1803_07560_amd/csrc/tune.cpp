@@ -42,11 +42,11 @@ bfi_status time_candidate(bfi_context *ctx, const bfi_lattice &lat, int prec, co
         plan_free(p);
         return hip_fail(e, "hipEventCreate");
     }
-    s = plan_enqueue(p, 1, nullptr, ctx->stream);
+    s = plan_enqueue(p, 1, nullptr, ctx->stream, false);
     if (s == BFI_OK && (e = hipEventRecord(ev.a, ctx->stream)) != hipSuccess)
         s = hip_fail(e, "hipEventRecord");
     for (int r = 0; r < 3 && s == BFI_OK; ++r)
-        s = plan_enqueue(p, 2 + r, nullptr, ctx->stream);
+        s = plan_enqueue(p, 2 + r, nullptr, ctx->stream, false);
     if (s == BFI_OK && (e = hipEventRecord(ev.b, ctx->stream)) != hipSuccess)
         s = hip_fail(e, "hipEventRecord");
     if (s == BFI_OK && (e = hipEventSynchronize(ev.b)) != hipSuccess)

@@ -72,7 +72,7 @@ class SubvolumeList:
         return int(self.ids.shape[0])
 
     def subset(self, idx) -> "SubvolumeList":
-        idx = np.asarray(idx)
+        idx = np.asarray(idx, dtype=np.int64)
         return SubvolumeList(self.ids[idx].copy(), self.lo[idx].copy(), self.hi[idx].copy(),
                              self.n[idx].copy(), self.offset[idx].copy())
 
