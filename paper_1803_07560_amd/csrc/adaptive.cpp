@@ -1,23 +1,427 @@
-// Error-driven adaptive refinement (placeholder until the policy lands).
+// Error-driven adaptive refinement of the subvolume partition (paper section 3:
+// the volume is subdivided into smaller and smaller subvolumes until the
+// result converges; the integrand suggests the dimension to split).
+//
+// Policy of one round, over the current leaves:
+//   1. Finalize all leaves; each leaf's contribution to the variance of C is
+//      e_s = sum_r [Var N_s(r) - 2 C(r) Cov_s(r) + C(r)^2 Var Z_s] / Z^2.
+//   2. Leaves are ranked by e_s (descending, ties by lower id) and taken until
+//      their contributions reach `refine_fraction` of the total (at least one).
+//   3. A taken leaf is split at the midpoint of the dimension j* minimising
+//      sigma_lower(j) + sigma_upper(j) -- the standard deviations of the weight
+//      in the two halves, from the split statistics (each half holds n/2 samples
+//      in expectation) -- when that sum is below kSplitGain * 2 sigma_leaf or
+//      when doubling would exceed n_max; otherwise its samples are doubled by
+//      continuing its own Philox stream.  Ties in j* go to the lower dimension.
+//   4. Children get fresh streams (ids 2 id and 2 id + 1) with
+//      clamp(n_leaf, n_min, n_max) samples each; the parent's samples are dropped.
+// Rounds repeat until max_r sigma_C(r) / |C(0)| <= target, the evaluation budget
+// or the round limit is reached.  Every round's work list (uneven sample counts)
+// is drained by the persistent kernel through the device queue.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+
 #include "runtime.h"
 
 using namespace bfi;
 
-extern "C" {
+namespace {
 
-bfi_status bfi_integrate_adaptive(bfi_context *, const bfi_lattice *, bfi_precision, uint64_t,
-                                  const double *, const double *, const bfi_adaptive_config *,
-                                  const bfi_launch *, bfi_result *, bfi_adaptive_stats *,
-                                  uint64_t *, double *, double *, uint64_t *, uint64_t *, size_t,
-                                  size_t *)
+constexpr double kSplitGain = 0.9;
+
+struct LeafAnalysis {
+    double e = 0.0;        // contribution to the variance of C
+    int best_dim = 0;      // j*
+    double gain = 1.0;     // (sigma_L + sigma_U)(j*) / (2 sigma)
+};
+
+// Scale factors that move every record to the smallest shift of the list.
+std::vector<double> common_shift_factors(size_t count, const double *partials, int rec_len)
 {
-    return fail(BFI_EUNSUPPORTED, "adaptive refinement not built yet");
+    double sig = std::numeric_limits<double>::infinity();
+    for (size_t s = 0; s < count; ++s)
+        sig = std::min(sig, partials[s * rec_len + 1]);
+    std::vector<double> f(count);
+    for (size_t s = 0; s < count; ++s)
+        f[s] = std::exp(sig - partials[s * rec_len + 1]);
+    return f;
 }
 
-bfi_status bfi_adaptive_decide(const bfi_lattice *, const bfi_subvolumes *, const double *,
-                               const double *, const bfi_adaptive_config *, int32_t *)
+bfi_status analyse(int nx, int d, size_t count, const double *lo, const double *hi,
+                   const double *partials, const double *split, std::vector<LeafAnalysis> *out,
+                   bfi_result *res)
 {
-    return fail(BFI_EUNSUPPORTED, "adaptive refinement not built yet");
+    const int rec_len = BFI_PARTIAL_LEN(nx), split_len = BFI_SPLIT_LEN(d);
+    BFI_TRY(finalize_records(nx, d, count, lo, hi, partials, res));
+    const std::vector<double> f = common_shift_factors(count, partials, rec_len);
+    // Z in the common shift
+    double z = 0.0;
+    std::vector<double> V(count);
+    for (size_t s = 0; s < count; ++s) {
+        double vol = 1.0;
+        for (int k = 0; k < d; ++k)
+            vol *= hi[s * d + k] - lo[s * d + k];
+        V[s] = vol;
+        z += vol * f[s] * partials[s * rec_len + 2] / partials[s * rec_len];
+    }
+    out->assign(count, LeafAnalysis{});
+    for (size_t s = 0; s < count; ++s) {
+        const double *rec = partials + s * rec_len;
+        const double n = rec[0], nn = n * (n - 1.0), v2 = V[s] * V[s];
+        const double a = f[s], a2 = a * a;
+        const double sw = a * rec[2], sw2 = a2 * rec[3];
+        const double var_z = v2 * (sw2 - sw * sw / n) / nn;
+        double e = 0.0;
+        for (int r = 0; r < nx; ++r) {
+            const double C = res->C[r];
+            const double spw = a * rec[4 + r], spw2 = a2 * rec[4 + nx + r],
+                         spww = a2 * rec[4 + 2 * nx + r];
+            const double var_n = v2 * (spw2 - spw * spw / n) / nn;
+            const double cov = v2 * (spww - spw * sw / n) / nn;
+            e += var_n - 2.0 * C * cov + C * C * var_z;
+        }
+        (*out)[s].e = z > 0 ? std::max(e, 0.0) / (z * z) : 0.0;
+        if (!split)
+            continue;
+        // split analysis in the leaf's own shift (the split record shares it)
+        const double *sp = split + s * split_len;
+        const double S = rec[2], Q = rec[3], half = 0.5 * n;
+        const double sigma = std::sqrt(std::max(Q / n - (S / n) * (S / n), 0.0));
+        double best = std::numeric_limits<double>::infinity();
+        int best_j = 0;
+        for (int j = 0; j < d; ++j) {
+            const double su = sp[1 + j], qu = sp[1 + d + j];
+            const double sl = S - su, ql = Q - qu;
+            const double vu = std::max(qu / half - (su / half) * (su / half), 0.0);
+            const double vl = std::max(ql / half - (sl / half) * (sl / half), 0.0);
+            const double sj = std::sqrt(vu) + std::sqrt(vl);
+            if (sj < best) {
+                best = sj;
+                best_j = j;
+            }
+        }
+        (*out)[s].best_dim = best_j;
+        (*out)[s].gain = sigma > 0 ? best / (2.0 * sigma) : 1.0;
+    }
+    return BFI_OK;
+}
+
+double rel_err(const bfi_result &r)
+{
+    double m = 0.0;
+    for (int k = 0; k < r.nx; ++k)
+        m = std::max(m, r.C_err[k]);
+    return r.C[0] != 0.0 ? m / std::fabs(r.C[0]) : std::numeric_limits<double>::infinity();
+}
+
+bool can_split(uint64_t id) { return id < (uint64_t(1) << 62); }
+
+// Decide actions: -1 keep, 0 double, 1 + j split along j.
+void decide(const std::vector<LeafAnalysis> &an, const uint64_t *ids, const uint64_t *n,
+            const bfi_adaptive_config &cfg, int32_t *action)
+{
+    const size_t count = an.size();
+    std::vector<size_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+        if (an[x].e != an[y].e)
+            return an[x].e > an[y].e;
+        return ids[x] < ids[y];
+    });
+    double total = 0.0;
+    for (const auto &a : an)
+        total += a.e;
+    std::fill(action, action + count, -1);
+    double taken = 0.0;
+    for (size_t i = 0; i < count; ++i) {
+        const size_t s = order[i];
+        if (i > 0 && taken >= cfg.refine_fraction * total)
+            break;
+        if (an[s].e <= 0.0 && i > 0)
+            break;
+        taken += an[s].e;
+        const bool doubling_ok = n[s] <= cfg.n_max / 2;
+        const bool split_ok = can_split(ids[s]);
+        if (split_ok && (an[s].gain < kSplitGain || !doubling_ok))
+            action[s] = 1 + an[s].best_dim;
+        else if (doubling_ok)
+            action[s] = 0;
+    }
+}
+
+bfi_status check_config(const bfi_adaptive_config *cfg)
+{
+    if (!cfg)
+        return fail(BFI_EINVAL, "config is NULL");
+    if (!(cfg->target_rel_err > 0) || !std::isfinite(cfg->target_rel_err))
+        return fail(BFI_EINVAL, "target_rel_err must be positive");
+    if (cfg->n_min < 2 || cfg->n_max < cfg->n_min)
+        return fail(BFI_EINVAL, "need 2 <= n_min <= n_max");
+    if (cfg->split_log2 < 0 || cfg->split_log2 > 24)
+        return fail(BFI_EINVAL, "split_log2 must be in [0, 24]");
+    if (!(cfg->refine_fraction > 0) || cfg->refine_fraction > 1)
+        return fail(BFI_EINVAL, "refine_fraction must be in (0, 1]");
+    if (cfg->max_rounds < 0)
+        return fail(BFI_EINVAL, "max_rounds must be >= 0");
+    return BFI_OK;
+}
+
+// Merge record b into a (disjoint samples of the same subvolume): both move to
+// the smaller shift; counts add, first-order sums scale by the shift factor,
+// second-order sums by its square.  first/second list the field ranges.
+void merge_shifted(double *a, const double *b, int sigma_at, const std::vector<int> &first,
+                   const std::vector<int> &second, int count_at)
+{
+    const double sig = std::min(a[sigma_at], b[sigma_at]);
+    const double fa = std::exp(sig - a[sigma_at]), fb = std::exp(sig - b[sigma_at]);
+    for (int i : first)
+        a[i] = fa * a[i] + fb * b[i];
+    for (int i : second)
+        a[i] = fa * fa * a[i] + fb * fb * b[i];
+    if (count_at >= 0)
+        a[count_at] += b[count_at];
+    a[sigma_at] = sig;
+}
+
+struct LeafSet {
+    int d = 0, nx = 0;
+    std::vector<uint64_t> id, n;
+    std::vector<double> lo, hi, rec, split;
+    size_t size() const { return id.size(); }
+};
+
+// Evaluate a work list (with split statistics) on the device.
+bfi_status eval_list(bfi_context *ctx, const bfi_lattice &lat, int prec, uint64_t seed,
+                     const SubList &work, const bfi_launch *launch, std::vector<double> *rec,
+                     std::vector<double> *split)
+{
+    const int d = lat.nx * lat.nt;
+    rec->assign(work.size() * BFI_PARTIAL_LEN(lat.nx), 0.0);
+    split->assign(work.size() * BFI_SPLIT_LEN(d), 0.0);
+    bfi_subvolumes v = work.view();
+    return bfi_eval(ctx, &lat, static_cast<bfi_precision>(prec), seed, &v, launch, rec->data(),
+                    split->data());
+}
+
+}  // namespace
+
+extern "C" {
+
+bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
+                                  uint64_t seed, const double *box_lo, const double *box_hi,
+                                  const bfi_adaptive_config *cfg, const bfi_launch *launch,
+                                  bfi_result *out, bfi_adaptive_stats *stats, uint64_t *leaf_id,
+                                  double *leaf_lo, double *leaf_hi, uint64_t *leaf_n,
+                                  uint64_t *leaf_offset, size_t cap, size_t *n_leaves)
+{
+    if (!ctx || !box_lo || !box_hi || !out)
+        return fail(BFI_EINVAL, "arguments must be non-NULL");
+    if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
+        return fail(BFI_EINVAL, "unknown precision");
+    BFI_TRY(check_lattice(lat));
+    BFI_TRY(check_config(cfg));
+    const int nx = lat->nx, d = nx * lat->nt;
+    if (d > 32)
+        return fail(BFI_EUNSUPPORTED, "adaptive refinement needs d <= 32 (split statistics)");
+    for (int k = 0; k < d; ++k)
+        if (!std::isfinite(box_lo[k]) || !std::isfinite(box_hi[k]) || !(box_lo[k] < box_hi[k]))
+            return fail(BFI_EINVAL, "box dim %d: need finite lo < hi", k);
+    const int rec_len = BFI_PARTIAL_LEN(nx), split_len = BFI_SPLIT_LEN(d);
+    std::vector<int> rec_first{2}, rec_second{3}, split_first, split_second;
+    for (int r = 0; r < nx; ++r) {
+        rec_first.push_back(4 + r);
+        rec_second.push_back(4 + nx + r);
+        rec_second.push_back(4 + 2 * nx + r);
+    }
+    for (int j = 0; j < d; ++j) {
+        split_first.push_back(1 + j);
+        split_second.push_back(1 + d + j);
+    }
+
+    // initial uniform partition with n_min samples per leaf
+    SubList init = uniform_split(d, box_lo, box_hi, cfg->split_log2, 0);
+    std::fill(init.n.begin(), init.n.end(), cfg->n_min);
+    uint64_t evals = static_cast<uint64_t>(init.size()) * cfg->n_min;
+    if (evals > cfg->max_evals)
+        return fail(BFI_EINVAL, "initial partition exceeds max_evals");
+    LeafSet L;
+    L.d = d;
+    L.nx = nx;
+    L.id = init.id;
+    L.n = init.n;
+    L.lo = init.lo;
+    L.hi = init.hi;
+    BFI_TRY(eval_list(ctx, *lat, prec, seed, init, launch, &L.rec, &L.split));
+
+    bfi_status status = BFI_OK;
+    int rounds = 0;
+    bfi_result res{};
+    std::vector<LeafAnalysis> an;
+    for (;;) {
+        BFI_TRY(analyse(nx, d, L.size(), L.lo.data(), L.hi.data(), L.rec.data(), L.split.data(),
+                        &an, &res));
+        if (rel_err(res) <= cfg->target_rel_err)
+            break;
+        if (rounds >= cfg->max_rounds) {
+            status = BFI_EBUDGET;
+            break;
+        }
+        std::vector<int32_t> action(L.size());
+        decide(an, L.id.data(), L.n.data(), *cfg, action.data());
+
+        // cost of each action; trim to the budget in priority order
+        std::vector<size_t> order(L.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+            if (an[x].e != an[y].e)
+                return an[x].e > an[y].e;
+            return L.id[x] < L.id[y];
+        });
+        uint64_t cost = 0;
+        for (size_t s : order) {
+            if (action[s] < 0)
+                continue;
+            const uint64_t child_n = std::min(std::max(L.n[s], cfg->n_min), cfg->n_max);
+            const uint64_t c = action[s] == 0 ? L.n[s] : 2 * child_n;
+            if (evals + cost + c > cfg->max_evals)
+                action[s] = -1;
+            else
+                cost += c;
+        }
+        if (cost == 0) {
+            status = BFI_EBUDGET;
+            break;
+        }
+
+        // work list: children (fresh streams) and continuations
+        SubList work;
+        work.d = d;
+        struct Origin {
+            size_t leaf;
+            int kind;  // 0 continuation, 1 lower child, 2 upper child
+        };
+        std::vector<Origin> origin;
+        for (size_t s = 0; s < L.size(); ++s) {
+            if (action[s] < 0)
+                continue;
+            const double *lo = &L.lo[s * d], *hi = &L.hi[s * d];
+            if (action[s] == 0) {
+                work.id.push_back(L.id[s]);
+                work.n.push_back(L.n[s]);
+                work.offset.push_back(L.n[s]);
+                work.lo.insert(work.lo.end(), lo, lo + d);
+                work.hi.insert(work.hi.end(), hi, hi + d);
+                origin.push_back({s, 0});
+                continue;
+            }
+            const int j = action[s] - 1;
+            const double mid = 0.5 * (lo[j] + hi[j]);
+            const uint64_t child_n = std::min(std::max(L.n[s], cfg->n_min), cfg->n_max);
+            for (int half = 0; half < 2; ++half) {
+                work.id.push_back(2 * L.id[s] + half);
+                work.n.push_back(child_n);
+                work.offset.push_back(0);
+                work.lo.insert(work.lo.end(), lo, lo + d);
+                work.hi.insert(work.hi.end(), hi, hi + d);
+                if (half == 0)
+                    work.hi[(work.id.size() - 1) * d + j] = mid;
+                else
+                    work.lo[(work.id.size() - 1) * d + j] = mid;
+                origin.push_back({s, 1 + half});
+            }
+        }
+        std::vector<double> wrec, wsplit;
+        BFI_TRY(eval_list(ctx, *lat, prec, seed, work, launch, &wrec, &wsplit));
+        evals += cost;
+
+        // fold the results into the leaf set, keeping leaf order (children in place)
+        LeafSet N;
+        N.d = d;
+        N.nx = nx;
+        std::vector<std::vector<size_t>> from(L.size());
+        for (size_t w = 0; w < origin.size(); ++w)
+            from[origin[w].leaf].push_back(w);
+        auto push_leaf = [&](uint64_t id, uint64_t n, const double *lo, const double *hi,
+                             const double *rec, const double *spl) {
+            N.id.push_back(id);
+            N.n.push_back(n);
+            N.lo.insert(N.lo.end(), lo, lo + d);
+            N.hi.insert(N.hi.end(), hi, hi + d);
+            N.rec.insert(N.rec.end(), rec, rec + rec_len);
+            N.split.insert(N.split.end(), spl, spl + split_len);
+        };
+        for (size_t s = 0; s < L.size(); ++s) {
+            if (action[s] < 0) {
+                push_leaf(L.id[s], L.n[s], &L.lo[s * d], &L.hi[s * d], &L.rec[s * rec_len],
+                          &L.split[s * split_len]);
+            } else if (action[s] == 0) {
+                const size_t w = from[s][0];
+                std::vector<double> rec(&L.rec[s * rec_len], &L.rec[s * rec_len] + rec_len);
+                std::vector<double> spl(&L.split[s * split_len],
+                                        &L.split[s * split_len] + split_len);
+                merge_shifted(rec.data(), &wrec[w * rec_len], 1, rec_first, rec_second, 0);
+                merge_shifted(spl.data(), &wsplit[w * split_len], 0, split_first, split_second, -1);
+                push_leaf(L.id[s], 2 * L.n[s], &L.lo[s * d], &L.hi[s * d], rec.data(), spl.data());
+            } else {
+                for (size_t w : from[s])
+                    push_leaf(work.id[w], work.n[w], &work.lo[w * d], &work.hi[w * d],
+                              &wrec[w * rec_len], &wsplit[w * split_len]);
+            }
+        }
+        L = std::move(N);
+        ++rounds;
+    }
+
+    *out = res;
+    if (stats) {
+        stats->rounds = rounds;
+        stats->leaves = L.size();
+        stats->evals = evals;
+        stats->rel_err = rel_err(res);
+    }
+    if (n_leaves)
+        *n_leaves = L.size();
+    const size_t m = std::min(cap, L.size());
+    for (size_t s = 0; s < m; ++s) {
+        if (leaf_id)
+            leaf_id[s] = L.id[s];
+        if (leaf_n)
+            leaf_n[s] = L.n[s];
+        if (leaf_offset)
+            leaf_offset[s] = 0;
+        if (leaf_lo)
+            std::memcpy(leaf_lo + s * d, &L.lo[s * d], d * sizeof(double));
+        if (leaf_hi)
+            std::memcpy(leaf_hi + s * d, &L.hi[s * d], d * sizeof(double));
+    }
+    if (status == BFI_EBUDGET)
+        fail(BFI_EBUDGET, "stopped after %d rounds at relative error %.3g (target %.3g)", rounds,
+             rel_err(res), cfg->target_rel_err);
+    return status;
+}
+
+bfi_status bfi_adaptive_decide(const bfi_lattice *lat, const bfi_subvolumes *leaves,
+                               const double *partials, const double *split,
+                               const bfi_adaptive_config *cfg, int32_t *action)
+{
+    if (!lat || !leaves || !partials || !split || !action)
+        return fail(BFI_EINVAL, "arguments must be non-NULL");
+    BFI_TRY(check_config(cfg));
+    if (lat->nx < 1 || lat->nt < 1 || lat->nx * lat->nt > 32)
+        return fail(BFI_EINVAL, "adaptive refinement needs 1 <= d <= 32");
+    if (leaves->count == 0)
+        return fail(BFI_EINVAL, "no leaves");
+    if (!leaves->id || !leaves->lo || !leaves->hi || !leaves->n)
+        return fail(BFI_EINVAL, "leaf arrays must be non-NULL");
+    std::vector<LeafAnalysis> an;
+    bfi_result res;
+    BFI_TRY(analyse(lat->nx, lat->nx * lat->nt, leaves->count, leaves->lo, leaves->hi, partials,
+                    split, &an, &res));
+    decide(an, leaves->id, leaves->n, *cfg, action);
+    return BFI_OK;
 }
 
 }  // extern "C"

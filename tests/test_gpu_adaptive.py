@@ -1,0 +1,108 @@
+"""GPU: error-driven adaptive refinement (``bfi_integrate_adaptive``).
+
+The final partition is replayed: the oracle evaluates the same leaves and the
+same Philox samples (offset 0, n per leaf), and Z, C(r) must agree with the
+adaptive result within 1e-6 (FP64 form; C(r) against C(0)).  Re-evaluating the
+partition on the GPU in one pass must also agree with the round-by-round merged
+records (continued streams merged on the host) to rounding."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def check_partition(part, d, B):
+    vol = np.prod(part.hi - part.lo, axis=1)
+    assert vol.sum() == pytest.approx((2 * B) ** d, rel=1e-12)
+    depth = np.floor(np.log2(part.ids.astype(np.float64))).astype(int)
+    np.testing.assert_allclose(vol, (2 * B) ** d / 2.0 ** depth, rtol=1e-12)
+    rng = np.random.Generator(np.random.PCG64(0))
+    P = rng.uniform(-B, B, size=(3000, d))
+    inside = np.all((P[:, None, :] >= part.lo[None]) & (P[:, None, :] < part.hi[None]), axis=2)
+    assert np.all(inside.sum(1) == 1)
+    assert len(set(part.ids.tolist())) == len(part)
+
+
+def test_adaptive_small_lattice_replays_on_oracle(bfi, ctx):
+    nx, nt, B, nu = 3, 2, 2.0, 0.7
+    cfg = bfi.adaptive_config(target_rel_err=1e-5, max_evals=1 << 21, n_min=1024,
+                              n_max=1 << 16, split_log2=2, max_rounds=30, refine_fraction=0.5)
+    out = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(nx, nt, nu=nu), "fp64", 3, -B, B, cfg)
+    assert out["status"] in ("BFI_OK", "BFI_EBUDGET")
+    part = out["partition"]
+    assert len(part) == out["leaves"] and out["rounds"] >= 1
+    check_partition(part, nx * nt, B)
+    assert int(part.n.sum()) <= out["evals"] <= cfg.max_evals
+    assert len(set(part.n.tolist())) > 1            # uneven sample counts
+    lat_o = oracle.lattice(nx, nt, nu=nu)
+    sums = oracle.sums(lat_o, 3, part.ids, part.lo, part.hi, part.n, part.offset)
+    ref = oracle.finalize(nx, nx * nt, part.lo, part.hi, sums)
+    assert abs(out["Z"] - ref["Z"]) <= 1e-6 * ref["Z"]
+    assert np.all(np.abs(out["C"] - ref["C"]) <= 1e-6 * abs(ref["C"][0]))
+    np.testing.assert_allclose(out["C_err"], ref["C_err"], rtol=1e-5)
+    rel = np.max(ref["C_err"]) / abs(ref["C"][0])
+    assert out["rel_err"] == pytest.approx(rel, rel=1e-6)
+
+
+def test_adaptive_reaches_an_easy_target(bfi, ctx):
+    """Flat weights (D huge): the error of C(0) falls as 1/sqrt(n), so a 2e-2
+    target is reached well inside the budget."""
+    cfg = bfi.adaptive_config(target_rel_err=2e-2, max_evals=1 << 24, n_min=256, n_max=1 << 20,
+                              split_log2=1, max_rounds=40)
+    out = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(2, 2, D=1e30), "fp64", 1, -2.0, 2.0, cfg)
+    assert out["status"] == "BFI_OK"
+    assert out["rel_err"] <= 2e-2
+    assert out["C"][0] == pytest.approx(4.0 / 3.0, rel=4 * 2e-2)
+
+
+def test_adaptive_budget_stop(bfi, ctx):
+    cfg = bfi.adaptive_config(target_rel_err=1e-9, max_evals=1 << 16, n_min=1024,
+                              n_max=1 << 20, split_log2=3, max_rounds=100)
+    out = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(4, 2), "fp64", 1, -4.0, 4.0, cfg)
+    assert out["status"] == "BFI_EBUDGET"
+    assert out["evals"] <= 1 << 16
+    assert np.isfinite(out["Z"]) and np.isfinite(out["C"][0])
+
+
+@pytest.mark.parametrize("nu", [0.1, 0.5, 1.0])
+def test_adaptive_10x2(bfi, ctx, nu):
+    """10x2 lattice, box [-4,4]^20, start from 1024 subvolumes (dims 0-9) at
+    2^10 samples; per-leaf counts between 2^10 and 2^22; reduced budget."""
+    lat = bfi.lattice(10, 2, nu=nu)
+    cfg = bfi.adaptive_config(target_rel_err=1e-3, max_evals=1 << 24, n_min=1 << 10,
+                              n_max=1 << 22, split_log2=10, max_rounds=12)
+    out = bfi.bfi_integrate_adaptive(ctx, lat, "fp64", 1, -4.0, 4.0, cfg)
+    part = out["partition"]
+    check_partition(part, 20, 4.0)
+    assert part.n.min() >= 1 << 10 and part.n.max() <= 1 << 22
+    # one-pass re-evaluation of the final partition == merged round records
+    again = bfi.bfi_eval(ctx, lat, "fp64", 1, part)
+    res = bfi.bfi_finalize(lat, part, again)
+    assert res["log_Z"] == pytest.approx(out["log_Z"], abs=1e-11)
+    assert np.all(np.abs(res["C"] - out["C"]) <= 1e-9 * abs(res["C"][0]))
+    # sampled leaves against the oracle
+    pick = np.unique(np.linspace(0, len(part) - 1, 6).astype(int))
+    ids, lo, hi, n = part.ids[pick], part.lo[pick], part.hi[pick], part.n[pick]
+    want = oracle.sums(oracle.lattice(10, 2, nu=nu), 1, ids, lo, hi, n, 0)
+    got = again[pick]
+    sig = got[:, 1:2]
+    np.testing.assert_allclose(got[:, 2:4] * np.exp(-np.array([[1, 2]]) * sig), want[:, 1:3],
+                               rtol=1e-10)
+    # the FP32 form on the same partition stays within the stated 1e-4
+    r32 = bfi.bfi_finalize(lat, part, bfi.bfi_eval(ctx, lat, "fp32", 1, part))
+    assert abs(r32["Z"] - res["Z"]) <= 1e-4 * res["Z"]
+    assert np.all(np.abs(r32["C"] - res["C"]) <= 1e-4 * abs(res["C"][0]))
+
+
+def test_adaptive_fp32_form(bfi, ctx):
+    lat = bfi.lattice(4, 2)
+    cfg = bfi.adaptive_config(target_rel_err=1e-4, max_evals=1 << 22, n_min=2048,
+                              n_max=1 << 18, split_log2=4, max_rounds=10)
+    out = bfi.bfi_integrate_adaptive(ctx, lat, "fp32", 2, -4.0, 4.0, cfg)
+    part = out["partition"]
+    ref = bfi.bfi_finalize(lat, part, bfi.bfi_eval(ctx, lat, "fp64", 2, part))
+    assert abs(out["Z"] - ref["Z"]) <= 1e-4 * ref["Z"]
+    assert np.all(np.abs(out["C"] - ref["C"]) <= 1e-4 * abs(ref["C"][0]))
