@@ -85,6 +85,9 @@ def parse():
     ap.add_argument("--cpu-samples-log2", type=int, default=17,
                     help="oracle sample: first 2^k samples of every subvolume")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the Poisson serving run (0 skips it)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1803_07560_amd",
                                                          "tuned_gfx950.json"))
     return ap.parse_args()
@@ -116,6 +119,40 @@ def run_form(bfi, torch, ctx, lat, sv, w, prec, steps, warmup, stream):
             "evals_per_step": evals, "result": res, "partials": part,
             "launch": {k: info[k] for k in ("samples_per_thread", "block", "persistent",
                                             "use_graph")}, "n_items": info["n_items"]}
+
+
+def serve_leg(bfi, ctx, seconds, rate, warmup_s=1.0):
+    """Poisson arrivals of correlation requests (lattice uniform over 4x2, 8x2,
+    10x2, 16x4; nu log-uniform in [0.05, 2]; budgets 2^U(16,26)); FP32 form.
+    Latency is submit-to-result as timed by the server; requests arriving in the
+    first `warmup_s` seconds are served but not counted."""
+    reqs = workloads.serving_requests(rate, seconds, seed=1)
+    srv = bfi.bfi_server_create(ctx, bfi.server_config(memory_budget=8 << 30, max_requests=256))
+    try:
+        t0 = time.perf_counter()
+        tickets = []
+        for r in reqs:
+            while True:
+                dt = r.arrival_s - (time.perf_counter() - t0)
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 0.001))
+            tickets.append(bfi.bfi_server_submit(srv, bfi.request(
+                bfi.lattice(r.nx, r.nt, nu=r.nu, D=r.D), "fp32", r.seed, r.box, r.split_log2,
+                r.budget)))
+        lat = [bfi.bfi_server_wait(srv, t, 120.0)[1] for t in tickets]
+        t1 = time.perf_counter()
+        st = bfi.bfi_server_stats_get(srv)
+    finally:
+        bfi.bfi_server_destroy(srv)
+    counted = np.array([x for x, r in zip(lat, reqs) if r.arrival_s >= warmup_s])
+    evals = sum(r.budget for r in reqs)
+    return {"requests": len(reqs), "counted": int(counted.size), "rate_hz": rate,
+            "seconds": seconds, "p50_ms": float(np.percentile(counted, 50) * 1e3),
+            "p99_ms": float(np.percentile(counted, 99) * 1e3),
+            "max_ms": float(counted.max() * 1e3), "evals_per_s": evals / (t1 - t0),
+            "gpu_busy_frac": st["busy_seconds"] / (t1 - t0), "steps": st["steps"],
+            "form": "fp32"}
 
 
 def cpu_baseline(w, sv, k):
@@ -157,6 +194,11 @@ def main():
         print(f"bench: {w.name} {prec} warmup {args.warmup} steps {args.steps}", file=sys.stderr,
               flush=True)
         forms[prec] = run_form(bfi, torch, ctx, lat, sv, w, prec, args.steps, args.warmup, stream)
+    serving = None
+    if args.serve_seconds > 0:
+        print(f"bench: serving {args.serve_seconds:g} s at {args.serve_rate:g} req/s",
+              file=sys.stderr, flush=True)
+        serving = serve_leg(bfi, ctx, args.serve_seconds, args.serve_rate)
     bfi.bfi_context_destroy(ctx)
 
     head = forms[args.headline]
@@ -206,6 +248,9 @@ def main():
                      "max_rel_err_C": stat, "ess": r64["ess"]},
         "roofline": roofline,
     }
+    if serving is not None:
+        line["p99_latency_ms"] = serving["p99_ms"]
+        line["serving"] = serving
     if not args.no_cpu_baseline:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, sv, args.cpu_samples_log2)

@@ -236,8 +236,11 @@ bfi_status bfi_adaptive_decide(const bfi_lattice *lat, const bfi_subvolumes *lea
 typedef struct {
     uint64_t memory_budget;     /* bytes of request state on the device */
     int32_t max_requests;       /* admitted requests at once */
-    int32_t chunks_per_step;    /* work items per request per step (fairness) */
+    int32_t chunks_per_step;    /* work items per request per step, at least */
     int32_t max_pending;        /* submitted but not admitted; EBUSY beyond it */
+    uint64_t step_evals;        /* target evaluations per step, shared equally by the
+                                   active requests (0: 2^25); bounds the wait of a
+                                   newly admitted request for the running step */
 } bfi_server_config;
 
 typedef struct {

@@ -80,7 +80,8 @@ class bfi_adaptive_stats(C.Structure):
 
 class bfi_server_config(C.Structure):
     _fields_ = [("memory_budget", C.c_uint64), ("max_requests", C.c_int32),
-                ("chunks_per_step", C.c_int32), ("max_pending", C.c_int32)]
+                ("chunks_per_step", C.c_int32), ("max_pending", C.c_int32),
+                ("step_evals", C.c_uint64)]
 
 
 class bfi_request(C.Structure):
@@ -382,10 +383,10 @@ def bfi_adaptive_decide(lat, leaves, partials, split, cfg) -> np.ndarray:
     return act
 
 
-def server_config(memory_budget=1 << 30, max_requests=256, chunks_per_step=64,
-                  max_pending=100000) -> bfi_server_config:
+def server_config(memory_budget=1 << 30, max_requests=256, chunks_per_step=4,
+                  max_pending=100000, step_evals=1 << 25) -> bfi_server_config:
     return bfi_server_config(int(memory_budget), int(max_requests), int(chunks_per_step),
-                             int(max_pending))
+                             int(max_pending), int(step_evals))
 
 
 def request(lat, prec, seed, box, split_log2, budget) -> bfi_request:

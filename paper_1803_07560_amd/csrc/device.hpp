@@ -144,6 +144,22 @@ __device__ __forceinline__ T action(Gen &&gen, T (&first)[NX], const Coef<T> &c,
     return S;
 }
 
+// Load a value every lane of the wavefront reads at the same address and keep
+// it in scalar registers: the struct is read dword by dword and each dword is
+// made wave-uniform, so the compiler holds it in SGPRs instead of VGPRs.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "dword-sized structs only");
+    T out;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+    for (int i = 0; i < static_cast<int>(sizeof(T) / 4); ++i)
+        dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return out;
+}
+
 // Butterfly sum across the 64 lanes of a wavefront; every lane ends with the
 // same bits (each step adds the same two operands in both partner lanes).
 __device__ __forceinline__ double wave_sum(double v)

@@ -15,14 +15,6 @@ namespace bfi {
 
 enum Precision : int { kFP64 = 0, kFP32Shifted = 1 };
 
-// One unit of device work: `count` consecutive samples of subvolume `sub`,
-// starting `start` samples after the subvolume's own offset.
-struct WorkItem {
-    uint32_t sub;
-    uint32_t count;
-    uint64_t start;
-};
-
 // Coefficients of the residual rewritten as
 //   R = v_next + v (k_diag + c_adv (v_right - v_left)) - c_visc (v_right + v_left)
 // with c_adv = g tau / (2a), c_visc = nu tau / a^2, k_diag = 2 c_visc - 1;
@@ -31,19 +23,35 @@ struct ActionCoef {
     double k_diag, c_adv, c_visc, inv_2Dtau, half_m2;
 };
 
-struct McArgs {
+// Everything one evaluation (a plan, or one served request) shares, resident in
+// device memory: the subvolumes' point maps, Philox ids and first sample
+// indices, the action coefficients and the seed.
+struct EvalParams {
     const double *base64, *scale64;  // nsub x d: point map in FP64
     const float *base32, *scale32;   // nsub x d: point map in FP32
     const uint64_t *ids;             // nsub heap ids (Philox counter words 2-3)
     const uint64_t *offsets;         // nsub first sample index
-    const WorkItem *items;           // nitems
-    double *item_rec;                // nitems x (4 + 3 nx)
-    double *item_split;              // nitems x 2d (split statistics), or null
-    uint32_t *queue_head;            // persistent kernels: next item to take
+    ActionCoef coef;
+    uint32_t seed_lo, seed_hi;
+};
+
+// One unit of device work: `count` consecutive samples of subvolume `sub` of
+// `params`, starting `start` samples after the subvolume's own offset; the
+// item's partial record goes to `rec` (4 + 3 nx doubles).
+struct WorkItem {
+    const EvalParams *params;
+    double *rec;
+    uint64_t start;
+    uint32_t sub;
+    uint32_t count;
+};
+
+struct McArgs {
+    const WorkItem *items;   // nitems
+    double *item_split;      // nitems x 2d (split statistics), or null
+    uint32_t *queue_head;    // persistent kernels: next item to take
     uint32_t nitems;
     uint32_t samples_per_thread;
-    uint32_t seed_lo, seed_hi;
-    ActionCoef coef;
 };
 
 struct LaunchSpec {

@@ -47,8 +47,6 @@ bool shape_compiled(int nx, int nt)
     return false;
 }
 
-namespace {
-
 hipError_t launch_mc(int nx, int nt, const LaunchSpec &spec, const McArgs &args, hipStream_t st)
 {
 #define BFI_SHAPE_LAUNCH(NX, NT)                             \
@@ -68,6 +66,8 @@ hipError_t kernel_info(int nx, int nt, const LaunchSpec &spec, KernelInfo *info)
 #undef BFI_SHAPE_INFO
     return hipErrorNotSupported;
 }
+
+namespace {
 
 hipError_t launch_debug_action(int nx, int nt, const DebugActionArgs &args, hipStream_t st)
 {
@@ -308,7 +308,7 @@ bfi_status plan_free(bfi_plan *p)
     if (p->ev_stop)
         (void)hipEventDestroy(p->ev_stop);
     void *bufs[] = {p->d_base64, p->d_scale64, p->d_base32, p->d_scale32, p->d_ids,
-                    p->d_offsets, p->d_items, p->d_item_rec, p->d_item_split, p->d_sub_first,
+                    p->d_offsets, p->d_params, p->d_items, p->d_item_rec, p->d_item_split, p->d_sub_first,
                     p->d_sub_rec, p->d_sub_split, p->d_head};
     for (void *b : bufs)
         if (b)
@@ -350,7 +350,8 @@ bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const 
         first[s] = static_cast<uint32_t>(items.size());
         for (uint64_t start = 0; start < subs.n[s]; start += chunk) {
             const uint64_t cnt = std::min<uint64_t>(chunk, subs.n[s] - start);
-            items.push_back(WorkItem{static_cast<uint32_t>(s), static_cast<uint32_t>(cnt), start});
+            items.push_back(WorkItem{nullptr, nullptr, start, static_cast<uint32_t>(s),
+                                     static_cast<uint32_t>(cnt)});
         }
         n_evals += subs.n[s];
     }
@@ -398,6 +399,7 @@ bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const 
     BFI_ALLOC(d_scale32, float, nd);
     BFI_ALLOC(d_ids, uint64_t, subs.size());
     BFI_ALLOC(d_offsets, uint64_t, subs.size());
+    BFI_ALLOC(d_params, EvalParams, 1);
     BFI_ALLOC(d_items, WorkItem, items.size());
     BFI_ALLOC(d_item_rec, double, items.size() * p->rec_len);
     BFI_ALLOC(d_sub_first, uint32_t, first.size());
@@ -408,6 +410,12 @@ bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const 
         BFI_ALLOC(d_sub_split, double, subs.size() * BFI_SPLIT_LEN(d));
     }
 #undef BFI_ALLOC
+    for (size_t i = 0; i < items.size(); ++i) {
+        items[i].params = p->d_params;
+        items[i].rec = p->d_item_rec + i * p->rec_len;
+    }
+    p->params = EvalParams{p->d_base64, p->d_scale64, p->d_base32, p->d_scale32, p->d_ids,
+                           p->d_offsets, make_coef(lat), 0u, 0u};
     struct Up {
         void *dst;
         const void *src;
@@ -417,7 +425,8 @@ bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const 
                {p->d_ids, subs.id.data(), subs.size() * 8},
                {p->d_offsets, subs.offset.data(), subs.size() * 8},
                {p->d_items, items.data(), items.size() * sizeof(WorkItem)},
-               {p->d_sub_first, first.data(), first.size() * 4}};
+               {p->d_sub_first, first.data(), first.size() * 4},
+               {p->d_params, &p->params, sizeof(EvalParams)}};
     for (const Up &u : ups) {
         e = hipMemcpy(u.dst, u.src, u.bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess)
@@ -447,24 +456,29 @@ bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const 
     return BFI_OK;
 }
 
+bfi_status plan_set_seed(bfi_plan *p, uint64_t seed)
+{
+    const uint32_t lo = static_cast<uint32_t>(seed), hi = static_cast<uint32_t>(seed >> 32);
+    if (p->params.seed_lo == lo && p->params.seed_hi == hi)
+        return BFI_OK;
+    // kernels of earlier runs read the parameters from device memory
+    if (p->last_stream)
+        BFI_HIP(hipStreamSynchronize(p->last_stream));
+    p->params.seed_lo = lo;
+    p->params.seed_hi = hi;
+    BFI_HIP(hipMemcpy(p->d_params, &p->params, sizeof(EvalParams), hipMemcpyHostToDevice));
+    return BFI_OK;
+}
+
 bfi_status plan_enqueue(bfi_plan *p, uint64_t seed, double *dst, hipStream_t st, bool timed)
 {
+    BFI_TRY(plan_set_seed(p, seed));
     McArgs a{};
-    a.base64 = p->d_base64;
-    a.scale64 = p->d_scale64;
-    a.base32 = p->d_base32;
-    a.scale32 = p->d_scale32;
-    a.ids = p->d_ids;
-    a.offsets = p->d_offsets;
     a.items = p->d_items;
-    a.item_rec = p->d_item_rec;
     a.item_split = p->d_item_split;
     a.queue_head = p->launch.persistent ? p->d_head : nullptr;
     a.nitems = p->nitems;
     a.samples_per_thread = static_cast<uint32_t>(p->launch.samples_per_thread);
-    a.seed_lo = static_cast<uint32_t>(seed);
-    a.seed_hi = static_cast<uint32_t>(seed >> 32);
-    a.coef = make_coef(p->lat);
     LaunchSpec spec{p->prec, p->launch.block, p->split ? 1 : 0, p->launch.persistent, p->grid};
     if (p->launch.persistent)
         BFI_HIP(launch_reset_head(p->d_head, st));
@@ -592,8 +606,8 @@ bfi_status bfi_plan_run(bfi_plan *p, uint64_t seed, double *partials_dev, void *
     BFI_HIP(hipSetDevice(p->ctx->device));
     hipStream_t st = stream ? static_cast<hipStream_t>(stream) : p->ctx->stream;
     if (p->launch.use_graph) {
-        if (!p->graph || p->graph_seed != seed || p->graph_stream != st ||
-            p->graph_dst != partials_dev) {
+        BFI_TRY(plan_set_seed(p, seed));
+        if (!p->graph || p->graph_stream != st || p->graph_dst != partials_dev) {
             if (p->graph) {
                 (void)hipGraphExecDestroy(p->graph);
                 p->graph = nullptr;
@@ -614,7 +628,6 @@ bfi_status bfi_plan_run(bfi_plan *p, uint64_t seed, double *partials_dev, void *
             BFI_HIP(e);
             p->graph_def = g;
             BFI_HIP(hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0));
-            p->graph_seed = seed;
             p->graph_stream = st;
             p->graph_dst = partials_dev;
         }

@@ -35,6 +35,9 @@ void clear_error();
     } while (0)
 
 bool shape_compiled(int nx, int nt);
+// Dispatch to the kernels compiled for lattice shape (nx, nt).
+hipError_t launch_mc(int nx, int nt, const LaunchSpec &spec, const McArgs &args, hipStream_t st);
+hipError_t kernel_info(int nx, int nt, const LaunchSpec &spec, KernelInfo *info);
 bfi_status check_lattice(const bfi_lattice *lat);
 bfi_status check_subvolumes(const bfi_lattice *lat, const bfi_subvolumes *subs);
 ActionCoef make_coef(const bfi_lattice &lat);
@@ -102,6 +105,8 @@ struct bfi_plan {
     double *d_base64 = nullptr, *d_scale64 = nullptr;
     float *d_base32 = nullptr, *d_scale32 = nullptr;
     uint64_t *d_ids = nullptr, *d_offsets = nullptr;
+    bfi::EvalParams *d_params = nullptr;
+    bfi::EvalParams params{};  // host copy of *d_params
     bfi::WorkItem *d_items = nullptr;
     double *d_item_rec = nullptr, *d_item_split = nullptr;
     uint32_t *d_sub_first = nullptr;
@@ -110,7 +115,6 @@ struct bfi_plan {
 
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_def = nullptr;
-    uint64_t graph_seed = 0;
     hipStream_t graph_stream = nullptr;
     double *graph_dst = nullptr;
     hipStream_t last_stream = nullptr;
@@ -125,4 +129,6 @@ bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const 
 // graph capture, where recorded events carry no timestamps)
 bfi_status plan_enqueue(bfi_plan *p, uint64_t seed, double *dst, hipStream_t stream, bool timed);
 bfi_status plan_free(bfi_plan *p);
+// Write the seed into the plan's device parameters (waits for earlier runs).
+bfi_status plan_set_seed(bfi_plan *p, uint64_t seed);
 }  // namespace bfi

@@ -56,7 +56,6 @@ __global__ void __launch_bounds__(BLOCK) mc_kernel(McArgs a)
     constexpr int NW = BLOCK / 64;
     using F = Fields<NX, D, SPLIT>;
     constexpr int NF = F::kCount;
-    constexpr int REC = 4 + 3 * NX;
     static_assert(!SPLIT || D <= 32, "split statistics keep one bit per dimension in 32 bits");
 
     // point map held in registers when 2d values take at most 80 VGPRs
@@ -68,8 +67,6 @@ __global__ void __launch_bounds__(BLOCK) mc_kernel(McArgs a)
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u, wave = tid >> 6;
-    const dev::Coef<T> coef(a.coef);
-    const bool mass = a.coef.half_m2 != 0.0;
 
     uint32_t it;
     if (a.queue_head) {
@@ -82,27 +79,36 @@ __global__ void __launch_bounds__(BLOCK) mc_kernel(McArgs a)
     }
 
     while (it < a.nitems) {
-        const WorkItem wi = a.items[it];
+        // the item, its parameters and its point map are the same for the whole
+        // block: keep them in scalar registers
+        const WorkItem wi = dev::load_uniform(a.items + it);
+        const EvalParams P = dev::load_uniform(wi.params);
+        const dev::Coef<T> coef(P.coef);
+        const bool mass = P.coef.half_m2 != 0.0;
+        const uint32_t seed_lo = P.seed_lo, seed_hi = P.seed_hi;
         const uint32_t s = wi.sub;
-        const uint64_t id = a.ids[s];
-        const uint64_t first_index = a.offsets[s] + wi.start;
+        const uint64_t id = P.ids[s];
+        const uint64_t first_index = P.offsets[s] + wi.start;
         const uint32_t id_lo = static_cast<uint32_t>(id), id_hi = static_cast<uint32_t>(id >> 32);
         const T *base_g;
         const T *scale_g;
         if constexpr (PREC == kFP64) {
-            base_g = a.base64 + static_cast<size_t>(s) * D;
-            scale_g = a.scale64 + static_cast<size_t>(s) * D;
+            base_g = P.base64 + static_cast<size_t>(s) * D;
+            scale_g = P.scale64 + static_cast<size_t>(s) * D;
         } else {
-            base_g = a.base32 + static_cast<size_t>(s) * D;
-            scale_g = a.scale32 + static_cast<size_t>(s) * D;
+            base_g = P.base32 + static_cast<size_t>(s) * D;
+            scale_g = P.scale32 + static_cast<size_t>(s) * D;
         }
         // the subvolume's point map stays in registers for the whole item when
-        // it fits (2d values); larger lattices read it from LDS (broadcast)
+        // it fits (2d values): offsets in scalar registers, scales in vector
+        // registers, so each fma of the map reads one scalar operand (measured
+        // faster than both in scalar registers, which spill); larger lattices
+        // read the map from LDS (broadcast)
         T base_r[kHoist ? D : 1], scale_r[kHoist ? D : 1];
         if constexpr (kHoist) {
 #pragma unroll
             for (int kk = 0; kk < D; ++kk) {
-                base_r[kk] = base_g[kk];
+                base_r[kk] = dev::load_uniform(base_g + kk);
                 scale_r[kk] = scale_g[kk];
             }
         } else {
@@ -150,7 +156,7 @@ __global__ void __launch_bounds__(BLOCK) mc_kernel(McArgs a)
                 for (int m = 0; m < NX; ++m) {
                     const int kk = l * NX + m;
                     if ((kk & 3) == 0)
-                        dev::philox_block(q0 + (kk >> 2), id_lo, id_hi, a.seed_lo, a.seed_hi, blk);
+                        dev::philox_block(q0 + (kk >> 2), id_lo, id_hi, seed_lo, seed_hi, blk);
                     const uint32_t x = blk[kk & 3];
                     if constexpr (SPLIT)
                         upper |= (x >> 31) << kk;
@@ -228,7 +234,7 @@ __global__ void __launch_bounds__(BLOCK) mc_kernel(McArgs a)
             for (int w = 1; w < NW; ++w)
                 block_sigma = fminf(block_sigma, red_sigma[w]);
         }
-        double *rec = a.item_rec + static_cast<size_t>(it) * REC;
+        double *rec = wi.rec;
         for (int i = tid; i < NF; i += BLOCK) {
             double total = 0.0;
 #pragma unroll
