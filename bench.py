@@ -88,6 +88,10 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson serving run (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--adaptive-budget-log2", type=int, default=32,
+                    help="evaluation budget of each adaptive 10x2 run (0 skips them)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run one device copy of this size (counter calibration)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1803_07560_amd",
                                                          "tuned_gfx950.json"))
     return ap.parse_args()
@@ -155,6 +159,51 @@ def serve_leg(bfi, ctx, seconds, rate, warmup_s=1.0):
             "form": "fp32"}
 
 
+def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0)):
+    """10x2 lattice, D = 1, box [-4,4]^20: error-driven bisection from the
+    1024-subvolume partition at 2^12 samples per leaf, per-leaf counts in
+    [2^10, 2^22], target max_r sigma_C(r)/|C(0)| <= 1e-3, FP32 form, budget
+    2^budget_log2 evaluations per value of nu."""
+    out = []
+    for nu in nus:
+        cfg = bfi.adaptive_config(target_rel_err=1e-3, max_evals=1 << budget_log2,
+                                  n_min=1 << 12, n_max=1 << 22, split_log2=10, max_rounds=64,
+                                  refine_fraction=0.5)
+        t0 = time.perf_counter()
+        r = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(10, 2, nu=nu), "fp32", 1, -4.0, 4.0, cfg)
+        dt = time.perf_counter() - t0
+        n = r["partition"].n
+        out.append({"nu": nu, "status": r["status"], "rel_err": r["rel_err"],
+                    "rounds": r["rounds"], "leaves": r["leaves"], "evals": r["evals"],
+                    "seconds": dt, "evals_per_s": r["evals"] / dt,
+                    "leaf_n_min": int(n.min()), "leaf_n_max": int(n.max())})
+    return out
+
+
+def kernel_source_digest():
+    """sha256 of the kernel sources: traffic figures apply only to the kernel
+    they were measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1803_07560_amd", "csrc")
+    for name in ("shape_kernels.hip", "device.hpp", "internal.h"):
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, form):
+    """HBM bytes per launch of mc_kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    if the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return rec.get("bytes_per_launch", {}).get(form)
+
+
 def cpu_baseline(w, sv, k):
     import oracle
     sub = sv.subset(np.arange(len(sv)))
@@ -194,6 +243,19 @@ def main():
         print(f"bench: {w.name} {prec} warmup {args.warmup} steps {args.steps}", file=sys.stderr,
               flush=True)
         forms[prec] = run_form(bfi, torch, ctx, lat, sv, w, prec, args.steps, args.warmup, stream)
+    adaptive = None
+    if args.adaptive_budget_log2 > 0:
+        print(f"bench: adaptive 10x2, budget 2^{args.adaptive_budget_log2} per nu",
+              file=sys.stderr, flush=True)
+        adaptive = adaptive_leg(bfi, ctx, args.adaptive_budget_log2)
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib << 20
+        x = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     serving = None
     if args.serve_seconds > 0:
         print(f"bench: serving {args.serve_seconds:g} s at {args.serve_rate:g} req/s",
@@ -213,7 +275,8 @@ def main():
     achieved = slots * evals_per_launch / (head["kernel_ms"] * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                 "unit": "T FP64-rate lane slots/s", "frac": achieved / PEAK_SLOTS,
-                "traffic": None, "kernel": "mc_kernel (graph replay: reset, kernel, merge)",
+                "traffic": measured_traffic(w.name, args.headline),
+                "kernel": "mc_kernel (graph replay: reset, kernel, merge)",
                 "slots_per_eval": slots,
                 "kernel_ms": head["kernel_ms"],
                 "fp64_flop_frac": (fp64_flops_per_eval(w.nx, w.nt) * evals_per_launch /
@@ -251,6 +314,8 @@ def main():
     if serving is not None:
         line["p99_latency_ms"] = serving["p99_ms"]
         line["serving"] = serving
+    if adaptive is not None:
+        line["adaptive"] = adaptive
     if not args.no_cpu_baseline:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, sv, args.cpu_samples_log2)
