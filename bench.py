@@ -162,13 +162,14 @@ def serve_leg(bfi, ctx, seconds, rate, warmup_s=1.0):
 def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0)):
     """10x2 lattice, D = 1, box [-4,4]^20: error-driven bisection from the
     1024-subvolume partition at 2^12 samples per leaf, per-leaf counts in
-    [2^10, 2^22], target max_r sigma_C(r)/|C(0)| <= 1e-3, FP32 form, budget
-    2^budget_log2 evaluations per value of nu."""
+    [2^12, 2^22], target max_r sigma_C(r)/|C(0)| <= 1e-3, FP32 form, budget
+    2^budget_log2 evaluations per value of nu, each round at least 1/32 of it."""
     out = []
     for nu in nus:
         cfg = bfi.adaptive_config(target_rel_err=1e-3, max_evals=1 << budget_log2,
                                   n_min=1 << 12, n_max=1 << 22, split_log2=10, max_rounds=64,
-                                  refine_fraction=0.5)
+                                  refine_fraction=0.5,
+                                  round_evals=max(1 << 24, (1 << budget_log2) >> 5))
         t0 = time.perf_counter()
         r = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(10, 2, nu=nu), "fp32", 1, -4.0, 4.0, cfg)
         dt = time.perf_counter() - t0

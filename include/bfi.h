@@ -193,7 +193,7 @@ bfi_status bfi_integrate(bfi_context *ctx, const bfi_lattice *lat, bfi_precision
  * variance of C, and either splits a leaf at the midpoint of the dimension
  * minimising sigma_lower + sigma_upper (children start fresh streams) or doubles
  * its samples (continuing its stream), until max_r sigma_C(r)/|C(0)| <= target or
- * max_evals is spent.  Leaves keep n_min <= n <= n_max.  out gets the estimate;
+ * max_evals is spent; a round's planned samples are scaled up to round_evals.  Leaves keep n_min <= n <= n_max.  out gets the estimate;
  * the final partition is written to the caller's arrays when non-NULL
  * (capacity `cap` leaves; *n_leaves gets the count).  Returns BFI_EBUDGET (with a
  * valid estimate) if the budget ran out first. */
@@ -204,6 +204,9 @@ typedef struct {
     int32_t split_log2;     /* initial uniform partition */
     int32_t max_rounds;
     double refine_fraction; /* share of the total variance refined per round, (0, 1] */
+    uint64_t round_evals;   /* work floor per round: when the refined leaves' planned
+                               samples fall short of it, their counts are scaled up by a
+                               power of two (within n_max); 0: no floor */
 } bfi_adaptive_config;
 
 typedef struct {

@@ -15,6 +15,10 @@
 //      continuing its own Philox stream.  Ties in j* go to the lower dimension.
 //   4. Children get fresh streams (ids 2 id and 2 id + 1) with
 //      clamp(n_leaf, n_min, n_max) samples each; the parent's samples are dropped.
+//   5. If the round's planned samples fall short of `round_evals`, every planned
+//      count (children, doubled leaves) is multiplied by the smallest power of
+//      two reaching it, within n_max, so each round keeps the chip busy and the
+//      extra samples go where the variance is.
 // Rounds repeat until max_r sigma_C(r) / |C(0)| <= target, the evaluation budget
 // or the round limit is reached.  Every round's work list (uneven sample counts)
 // is drained by the persistent kernel through the device queue.
@@ -119,6 +123,17 @@ double rel_err(const bfi_result &r)
 
 bool can_split(uint64_t id) { return id < (uint64_t(1) << 62); }
 
+// Action of one refined leaf: split along j* when that halves the spread well
+// enough or doubling would exceed n_max, else double; -1 if neither is possible.
+int32_t leaf_action(const LeafAnalysis &a, uint64_t id, uint64_t n, const bfi_adaptive_config &cfg)
+{
+    const bool doubling_ok = n <= cfg.n_max / 2;
+    const bool split_ok = can_split(id);
+    if (split_ok && (a.gain < kSplitGain || !doubling_ok))
+        return 1 + a.best_dim;
+    return doubling_ok ? 0 : -1;
+}
+
 // Decide actions: -1 keep, 0 double, 1 + j split along j.
 void decide(const std::vector<LeafAnalysis> &an, const uint64_t *ids, const uint64_t *n,
             const bfi_adaptive_config &cfg, int32_t *action)
@@ -143,12 +158,7 @@ void decide(const std::vector<LeafAnalysis> &an, const uint64_t *ids, const uint
         if (an[s].e <= 0.0 && i > 0)
             break;
         taken += an[s].e;
-        const bool doubling_ok = n[s] <= cfg.n_max / 2;
-        const bool split_ok = can_split(ids[s]);
-        if (split_ok && (an[s].gain < kSplitGain || !doubling_ok))
-            action[s] = 1 + an[s].best_dim;
-        else if (doubling_ok)
-            action[s] = 0;
+        action[s] = leaf_action(an[s], ids[s], n[s], cfg);
     }
 }
 
@@ -272,7 +282,8 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         std::vector<int32_t> action(L.size());
         decide(an, L.id.data(), L.n.data(), *cfg, action.data());
 
-        // cost of each action; trim to the budget in priority order
+        // planned sample counts: children clamp(n, n_min, n_max) each, doubled
+        // leaves 2n; scaled by a power of two up to the round's work floor
         std::vector<size_t> order(L.size());
         std::iota(order.begin(), order.end(), 0);
         std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
@@ -280,12 +291,59 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                 return an[x].e > an[y].e;
             return L.id[x] < L.id[y];
         });
+        // planned count of a refined leaf at scale factor f (within n_max)
+        std::vector<uint64_t> target(L.size(), 0);  // new per-leaf (or per-child) count
+        auto plan_counts = [&](uint64_t f, bool *grew) {
+            uint64_t planned = 0;
+            for (size_t s = 0; s < L.size(); ++s) {
+                if (action[s] < 0)
+                    continue;
+                const uint64_t base = action[s] == 0 ? 2 * L.n[s]
+                                                      : std::min(std::max(L.n[s], cfg->n_min),
+                                                                 cfg->n_max);
+                const uint64_t t =
+                    std::max(base, std::min(base * f, std::max(cfg->n_max, base)));
+                if (grew && t > target[s])
+                    *grew = true;
+                target[s] = t;
+                planned += action[s] == 0 ? t - L.n[s] : 2 * t;
+            }
+            return planned;
+        };
+        uint64_t f = 1;
+        uint64_t planned = plan_counts(f, nullptr);
+        // work floor: scale the refined leaves by powers of two; once n_max caps
+        // them, refine further leaves in variance order
+        size_t next_leaf = 0;
+        while (cfg->round_evals > 0 && planned < cfg->round_evals) {
+            bool grew = false;
+            const std::vector<uint64_t> keep = target;
+            const uint64_t p2 = plan_counts(2 * f, &grew);
+            if (grew) {
+                f *= 2;
+                planned = p2;
+                continue;
+            }
+            target = keep;
+            while (next_leaf < order.size() && action[order[next_leaf]] != -1)
+                ++next_leaf;
+            if (next_leaf == order.size())
+                break;
+            const size_t s = order[next_leaf];
+            action[s] = leaf_action(an[s], L.id[s], L.n[s], *cfg);
+            if (action[s] < 0)
+                action[s] = -2;  // neither split nor doubling possible: skip it
+            planned = plan_counts(f, nullptr);
+        }
+        for (auto &a : action)
+            if (a == -2)
+                a = -1;
+        // trim to the evaluation budget in priority order
         uint64_t cost = 0;
         for (size_t s : order) {
             if (action[s] < 0)
                 continue;
-            const uint64_t child_n = std::min(std::max(L.n[s], cfg->n_min), cfg->n_max);
-            const uint64_t c = action[s] == 0 ? L.n[s] : 2 * child_n;
+            const uint64_t c = action[s] == 0 ? target[s] - L.n[s] : 2 * target[s];
             if (evals + cost + c > cfg->max_evals)
                 action[s] = -1;
             else
@@ -310,7 +368,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             const double *lo = &L.lo[s * d], *hi = &L.hi[s * d];
             if (action[s] == 0) {
                 work.id.push_back(L.id[s]);
-                work.n.push_back(L.n[s]);
+                work.n.push_back(target[s] - L.n[s]);
                 work.offset.push_back(L.n[s]);
                 work.lo.insert(work.lo.end(), lo, lo + d);
                 work.hi.insert(work.hi.end(), hi, hi + d);
@@ -319,7 +377,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             }
             const int j = action[s] - 1;
             const double mid = 0.5 * (lo[j] + hi[j]);
-            const uint64_t child_n = std::min(std::max(L.n[s], cfg->n_min), cfg->n_max);
+            const uint64_t child_n = target[s];
             for (int half = 0; half < 2; ++half) {
                 work.id.push_back(2 * L.id[s] + half);
                 work.n.push_back(child_n);
@@ -364,7 +422,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                                         &L.split[s * split_len] + split_len);
                 merge_shifted(rec.data(), &wrec[w * rec_len], 1, rec_first, rec_second, 0);
                 merge_shifted(spl.data(), &wsplit[w * split_len], 0, split_first, split_second, -1);
-                push_leaf(L.id[s], 2 * L.n[s], &L.lo[s * d], &L.hi[s * d], rec.data(), spl.data());
+                push_leaf(L.id[s], target[s], &L.lo[s * d], &L.hi[s * d], rec.data(), spl.data());
             } else {
                 for (size_t w : from[s])
                     push_leaf(work.id[w], work.n[w], &work.lo[w * d], &work.hi[w * d],

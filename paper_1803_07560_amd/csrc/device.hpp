@@ -110,12 +110,15 @@ __device__ __forceinline__ T slice_u2(const T (&cur)[NX], T acc)
 }
 
 // The action S for one configuration delivered slice by slice:
-// gen(l, out) fills time slice l.  Slice 0 stays live (it closes the time
-// period and carries the observables); at most three slices are live at once.
+// gen(l, out, token) fills time slice l; `token` is the running sum of R^2,
+// which a generator may tie its work to (see the Monte Carlo kernel) so that
+// slice l+1 is not produced before slice l-1 has been consumed.  Slice 0 stays
+// live (it closes the time period and carries the observables); at most three
+// slices are live at once.
 template <class T, int NX, int NT, class Gen>
 __device__ __forceinline__ T action(Gen &&gen, T (&first)[NX], const Coef<T> &c, bool mass)
 {
-    gen(0, first);
+    gen(0, first, T(0));
     T cur[NX];
 #pragma unroll
     for (int m = 0; m < NX; ++m)
@@ -125,7 +128,7 @@ __device__ __forceinline__ T action(Gen &&gen, T (&first)[NX], const Coef<T> &c,
     for (int l = 0; l < NT; ++l) {
         T nxt[NX];
         if (l + 1 < NT) {
-            gen(l + 1, nxt);
+            gen(l + 1, nxt, r2);
         } else {
 #pragma unroll
             for (int m = 0; m < NX; ++m)

@@ -47,8 +47,14 @@ struct Fields {
     }
 };
 
+// Waves per SIMD the register allocation must leave room for: without a floor
+// the compiler spends the whole register file of one wave on large lattices.
+template <int NX, int NT>
+constexpr int kMinWaves = NX * NT > 32 ? 2 : 1;
+
 template <int NX, int NT, int PREC, int BLOCK, bool SPLIT>
-__global__ void __launch_bounds__(BLOCK) mc_kernel(McArgs a)
+__global__ void __launch_bounds__(BLOCK)
+    __attribute__((amdgpu_waves_per_eu(kMinWaves<NX, NT>))) mc_kernel(McArgs a)
 {
     using T = std::conditional_t<PREC == kFP64, double, float>;
     constexpr int D = NX * NT;
@@ -61,7 +67,7 @@ __global__ void __launch_bounds__(BLOCK) mc_kernel(McArgs a)
     // point map held in registers when 2d values take at most 80 VGPRs
     constexpr bool kHoist = 2 * D * sizeof(T) / 4 <= 80;
     __shared__ double red[NW][NF];
-    __shared__ T map_lds[2][kHoist ? 1 : D];
+    __shared__ T map_lds[2][kHoist ? 1 : D];  // [0]: offsets, [1]: scales
     __shared__ float red_sigma[NW];
     __shared__ uint32_t next_item;
 
@@ -118,17 +124,22 @@ __global__ void __launch_bounds__(BLOCK) mc_kernel(McArgs a)
             }
             __syncthreads();
         }
-        auto base_of = [&](int kk) -> T {
+        // `row` points at the LDS-resident map, offset by a run-time zero that
+        // carries the slice's dependency on the action so far: the compiler can
+        // neither hoist the reads out of the sample loop (4d values live) nor
+        // issue them before the slice is due; reads use immediate offsets
+        using LdsRow = const __attribute__((address_space(3))) T *;
+        auto base_of = [&](int kk, LdsRow row) -> T {
             if constexpr (kHoist)
                 return base_r[kk];
             else
-                return map_lds[0][kk];
+                return row[kk];
         };
-        auto scale_of = [&](int kk) -> T {
+        auto scale_of = [&](int kk, LdsRow row) -> T {
             if constexpr (kHoist)
                 return scale_r[kk];
             else
-                return map_lds[1][kk];
+                return row[D + kk];
         };
 
         double acc[NF];
@@ -151,16 +162,28 @@ __global__ void __launch_bounds__(BLOCK) mc_kernel(McArgs a)
             const uint64_t q0 = (first_index + local) * NB;
             uint32_t blk[4];
             uint32_t upper = 0;
-            auto gen = [&](int l, T(&out)[NX]) {
+            auto gen = [&](int l, T(&out)[NX], T token) {
+                uint64_t qs = q0;
+                uint32_t zoff = 0;
+                LdsRow row = (LdsRow)(&map_lds[0][0]);
+                if constexpr (D > 32) {
+                    // make this slice's counters and map reads depend on the
+                    // action so far, so the compiler cannot generate every slice
+                    // (and read the whole map) up front and keep 2d coordinates
+                    // and 4d map values live
+                    asm volatile("" : "+v"(qs) : "v"(token));
+                    asm volatile("v_mov_b32 %0, 0" : "=v"(zoff) : "v"(token));
+                    row += zoff;
+                }
 #pragma unroll
                 for (int m = 0; m < NX; ++m) {
                     const int kk = l * NX + m;
                     if ((kk & 3) == 0)
-                        dev::philox_block(q0 + (kk >> 2), id_lo, id_hi, seed_lo, seed_hi, blk);
+                        dev::philox_block(qs + (kk >> 2), id_lo, id_hi, seed_lo, seed_hi, blk);
                     const uint32_t x = blk[kk & 3];
                     if constexpr (SPLIT)
                         upper |= (x >> 31) << kk;
-                    out[m] = dev::map_word(x, scale_of(kk), base_of(kk));
+                    out[m] = dev::map_word(x, scale_of(kk, row), base_of(kk, row));
                 }
             };
             T first[NX];
@@ -279,7 +302,7 @@ __global__ void __launch_bounds__(256) debug_action_kernel(DebugActionArgs a)
     if (i >= a.n)
         return;
     const double *p = a.points + i * D;
-    auto gen = [&](int l, T(&out)[NX]) {
+    auto gen = [&](int l, T(&out)[NX], T) {
 #pragma unroll
         for (int m = 0; m < NX; ++m)
             out[m] = static_cast<T>(p[l * NX + m]);

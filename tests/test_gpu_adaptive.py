@@ -106,3 +106,23 @@ def test_adaptive_fp32_form(bfi, ctx):
     ref = bfi.bfi_finalize(lat, part, bfi.bfi_eval(ctx, lat, "fp64", 2, part))
     assert abs(out["Z"] - ref["Z"]) <= 1e-4 * ref["Z"]
     assert np.all(np.abs(out["C"] - ref["C"]) <= 1e-4 * abs(ref["C"][0]))
+
+
+def test_adaptive_round_floor(bfi, ctx):
+    """A work floor per round scales the refined leaves' sample counts (powers of
+    two within n_max); the final partition still replays on the oracle."""
+    nx, nt, B = 3, 2, 2.0
+    cfg = bfi.adaptive_config(target_rel_err=1e-9, max_evals=1 << 23, n_min=512, n_max=1 << 16,
+                              split_log2=2, max_rounds=6, refine_fraction=0.3,
+                              round_evals=1 << 20)
+    out = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(nx, nt, nu=0.7), "fp64", 5, -B, B, cfg)
+    part = out["partition"]
+    check_partition(part, nx * nt, B)
+    # from the third round on there are enough leaves to reach the floor
+    assert out["rounds"] == 6
+    assert out["evals"] >= (out["rounds"] - 2) * (1 << 20)
+    assert part.n.max() <= 1 << 16
+    sums = oracle.sums(oracle.lattice(nx, nt, nu=0.7), 5, part.ids, part.lo, part.hi, part.n, 0)
+    ref = oracle.finalize(nx, nx * nt, part.lo, part.hi, sums)
+    assert abs(out["Z"] - ref["Z"]) <= 1e-6 * ref["Z"]
+    assert np.all(np.abs(out["C"] - ref["C"]) <= 1e-6 * abs(ref["C"][0]))
