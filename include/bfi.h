@@ -232,6 +232,76 @@ bfi_status bfi_adaptive_decide(const bfi_lattice *lat, const bfi_subvolumes *lea
                                const double *partials, const double *split,
                                const bfi_adaptive_config *cfg, int32_t *action);
 
+/* Single integrands on the paper's integrand protocol (section 3): for each
+ * subvolume, the integral over it (result), its absolute error V s / sqrt(n),
+ * and a suggested split dimension (the dimension minimising sigma_lower +
+ * sigma_upper of the integrand over the two halves).
+ *   BFI_INTEGRAND_NSPHERE: f(x) = sqrt(1 - |x|^2) (0 outside the unit ball) over
+ *     `dim` <= 16 dimensions, FP64: half the volume of the unit (dim+1)-ball over
+ *     [-1,1]^dim (section 3, Listings 1 and 2).
+ *   BFI_INTEGRAND_BURGERS_Z: exp(-S) of Eq. Gen2 (the normalisation), d <= 32.
+ *   BFI_INTEGRAND_BURGERS_N: u_{0,0} u_{0,r} exp(-S), r = `distance` (the
+ *     un-normalised correlation; section 4 divides it by the BURGERS_Z integral);
+ *     its split suggestion uses the statistics of exp(-S).
+ * Points are those of bfi_eval (Philox keyed by seed, id, index). */
+typedef enum {
+    BFI_INTEGRAND_NSPHERE = 0,
+    BFI_INTEGRAND_BURGERS_Z = 1,
+    BFI_INTEGRAND_BURGERS_N = 2
+} bfi_integrand_kind;
+
+typedef struct {
+    int32_t kind;       /* bfi_integrand_kind */
+    int32_t dim;        /* N-sphere: dimensions; ignored for the lattice kinds */
+    bfi_lattice lat;    /* lattice kinds */
+    int32_t prec;       /* lattice kinds: bfi_precision */
+    int32_t distance;   /* BURGERS_N: r in [0, nx) */
+} bfi_integrand;
+
+/* One evaluation per listed subvolume; result, abserr (double) and split_dim
+ * (int32, 0-based) are host arrays of subs->count.  Blocking. */
+bfi_status bfi_integrand_eval(bfi_context *ctx, const bfi_integrand *f, uint64_t seed,
+                              const bfi_subvolumes *subs, const bfi_launch *launch,
+                              double *result, double *abserr, int32_t *split_dim);
+
+/* The paper's subdivision (section 3, with the ranges of section 4): every open
+ * subvolume is evaluated twice, with n_initial samples and then with
+ * sample_factor times more (continuing its stream); it is accepted (result and
+ * error of the second evaluation) when one of the criteria holds --
+ *   1. |r2 - r1| <= (rel_diff - 1) max(|r1|, |r2|)      (rel_diff e.g. 1.025 .. 1.085)
+ *   2. |r2 - r1| <= abs_diff                             (e.g. 0.5 .. 2)
+ *   3. max(|r1|, |r2|) <= max_abs                        (e.g. 0.5 .. 2)
+ * (a non-positive threshold disables its criterion) -- else it is split in two
+ * along the suggested dimension and both halves start fresh streams.  A
+ * subvolume at max_depth below the initial partition, or whose children would
+ * exceed max_evals, is accepted unconverged.  All open subvolumes of a
+ * generation are evaluated in one batch.  *result = sum of accepted results,
+ * *abserr = root sum of squares of their errors.  Returns BFI_EBUDGET (with a
+ * valid result) when the budget forced unconverged acceptances. */
+typedef struct {
+    uint64_t n_initial;
+    double sample_factor;
+    double rel_diff;
+    double abs_diff;
+    double max_abs;
+    int32_t split_log2;
+    int32_t max_depth;
+    uint64_t max_evals;
+} bfi_hdi_config;
+
+typedef struct {
+    uint64_t evals;
+    uint64_t accepted;
+    uint64_t unconverged;
+    int32_t generations;
+    int32_t depth;        /* deepest accepted level below the initial partition */
+} bfi_hdi_stats;
+
+bfi_status bfi_integrate_hdi(bfi_context *ctx, const bfi_integrand *f, uint64_t seed,
+                             const double *box_lo, const double *box_hi,
+                             const bfi_hdi_config *cfg, const bfi_launch *launch, double *result,
+                             double *abserr, bfi_hdi_stats *stats);
+
 /* Continuous-batching request server on one context.  Requests are admitted
  * while their device state fits `memory_budget` bytes and a slot is free; their
  * partial sums stay resident on the device; every scheduling step packs chunks

@@ -96,6 +96,31 @@ class bfi_server_stats(C.Structure):
                 ("busy_seconds", C.c_double)]
 
 
+BFI_INTEGRAND_NSPHERE = 0
+BFI_INTEGRAND_BURGERS_Z = 1
+BFI_INTEGRAND_BURGERS_N = 2
+
+
+class bfi_integrand(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("lat", bfi_lattice),
+                ("prec", C.c_int32), ("distance", C.c_int32)]
+
+    @property
+    def d(self) -> int:
+        return int(self.dim) if self.kind == BFI_INTEGRAND_NSPHERE else self.lat.d
+
+
+class bfi_hdi_config(C.Structure):
+    _fields_ = [("n_initial", C.c_uint64), ("sample_factor", C.c_double),
+                ("rel_diff", C.c_double), ("abs_diff", C.c_double), ("max_abs", C.c_double),
+                ("split_log2", C.c_int32), ("max_depth", C.c_int32), ("max_evals", C.c_uint64)]
+
+
+class bfi_hdi_stats(C.Structure):
+    _fields_ = [("evals", C.c_uint64), ("accepted", C.c_uint64), ("unconverged", C.c_uint64),
+                ("generations", C.c_int32), ("depth", C.c_int32)]
+
+
 def partial_len(nx: int) -> int:
     return 4 + 3 * nx
 
@@ -133,6 +158,12 @@ _SIGNATURES = {
                                 C.c_size_t, _P(C.c_size_t)], C.c_int),
     "bfi_adaptive_decide": ([_P(bfi_lattice), _P(bfi_subvolumes), _P(C.c_double), _P(C.c_double),
                              _P(bfi_adaptive_config), _P(C.c_int32)], C.c_int),
+    "bfi_integrand_eval": ([_vp, _P(bfi_integrand), C.c_uint64, _P(bfi_subvolumes),
+                            _P(bfi_launch), _P(C.c_double), _P(C.c_double), _P(C.c_int32)],
+                           C.c_int),
+    "bfi_integrate_hdi": ([_vp, _P(bfi_integrand), C.c_uint64, _P(C.c_double), _P(C.c_double),
+                           _P(bfi_hdi_config), _P(bfi_launch), _P(C.c_double), _P(C.c_double),
+                           _P(bfi_hdi_stats)], C.c_int),
     "bfi_server_create": ([_vp, _P(bfi_server_config), _P(_vp)], C.c_int),
     "bfi_server_submit": ([_vp, _P(bfi_request), _P(C.c_uint64)], C.c_int),
     "bfi_server_poll": ([_vp, C.c_uint64, _P(bfi_result), _P(C.c_int32), _P(C.c_double)], C.c_int),
@@ -384,6 +415,48 @@ def bfi_adaptive_decide(lat, leaves, partials, split, cfg) -> np.ndarray:
                                       C.byref(cfg), act.ctypes.data_as(_P(C.c_int32))),
            "bfi_adaptive_decide")
     return act
+
+
+def integrand_nsphere(dim: int) -> bfi_integrand:
+    return bfi_integrand(BFI_INTEGRAND_NSPHERE, int(dim), bfi_lattice(), BFI_FP64, 0)
+
+
+def integrand_burgers(lat, prec="fp64", distance=None) -> bfi_integrand:
+    """exp(-S) (distance None: the normalisation) or u_{0,0} u_{0,r} exp(-S)."""
+    if distance is None:
+        return bfi_integrand(BFI_INTEGRAND_BURGERS_Z, 0, lat, _prec(prec), 0)
+    return bfi_integrand(BFI_INTEGRAND_BURGERS_N, 0, lat, _prec(prec), int(distance))
+
+
+def bfi_integrand_eval(ctx, f, seed, subs, launch_=None):
+    """(result, abserr, split_dim) arrays, one entry per subvolume."""
+    sv = Subvolumes.of(subs, f.d)
+    res = np.zeros(len(sv))
+    err = np.zeros(len(sv))
+    dim = np.zeros(len(sv), dtype=np.int32)
+    _check(load().bfi_integrand_eval(ctx, C.byref(f), int(seed), C.byref(sv.view),
+                                     C.byref(launch_) if launch_ is not None else None, _dp(res),
+                                     _dp(err), dim.ctypes.data_as(_P(C.c_int32))),
+           "bfi_integrand_eval")
+    return res, err, dim
+
+
+def hdi_config(n_initial=1_000_000, sample_factor=2.0, rel_diff=1.025, abs_diff=0.0,
+               max_abs=0.0, split_log2=0, max_depth=20, max_evals=1 << 34) -> bfi_hdi_config:
+    return bfi_hdi_config(int(n_initial), float(sample_factor), float(rel_diff), float(abs_diff),
+                          float(max_abs), int(split_log2), int(max_depth), int(max_evals))
+
+
+def bfi_integrate_hdi(ctx, f, seed, box_lo, box_hi, cfg, launch_=None) -> dict:
+    lo, hi = _box(f.d, box_lo, box_hi)
+    res, err, st = C.c_double(), C.c_double(), bfi_hdi_stats()
+    s = load().bfi_integrate_hdi(ctx, C.byref(f), int(seed), _dp(lo), _dp(hi), C.byref(cfg),
+                                 C.byref(launch_) if launch_ is not None else None,
+                                 C.byref(res), C.byref(err), C.byref(st))
+    if s not in (0, -7):
+        _check(s, "bfi_integrate_hdi")
+    return {"result": res.value, "abserr": err.value, "status": STATUS[s],
+            **{k: getattr(st, k) for k, _ in bfi_hdi_stats._fields_}}
 
 
 def server_config(memory_budget=1 << 30, max_requests=256, chunks_per_step=4,

@@ -65,6 +65,108 @@ __global__ void __launch_bounds__(64) merge_kernel(MergeArgs m)
     }
 }
 
+// The N-sphere integrand of the paper's examples (section 3, Listings 1 and 2):
+// half the volume of the unit (dim+1)-ball as the integral of sqrt(1 - |x|^2).
+// Same points as the lattice kernels (Philox words, fma map); FP64 sums of f and
+// f^2, and of both over the upper half of the box along each dimension.
+__global__ void __launch_bounds__(256) nsphere_kernel(NsphereArgs na)
+{
+    constexpr int kBlock = 256, kWaves = kBlock / 64, kF = 2 + 2 * kMaxNsphereDim;
+    const McArgs &a = na.mc;
+    const int dim = na.dim;
+    const int nb = (dim + 3) / 4;
+    __shared__ double red[kWaves][kF];
+    __shared__ uint32_t next_item;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+
+    uint32_t it;
+    if (a.queue_head) {
+        if (tid == 0)
+            next_item = atomicAdd(a.queue_head, 1u);
+        __syncthreads();
+        it = __builtin_amdgcn_readfirstlane(next_item);
+    } else {
+        it = blockIdx.x;
+    }
+    while (it < a.nitems) {
+        const WorkItem wi = dev::load_uniform(a.items + it);
+        const EvalParams P = dev::load_uniform(wi.params);
+        const uint64_t id = P.ids[wi.sub];
+        const uint64_t first_index = P.offsets[wi.sub] + wi.start;
+        const double *base = P.base64 + static_cast<size_t>(wi.sub) * dim;
+        const double *scale = P.scale64 + static_cast<size_t>(wi.sub) * dim;
+        const uint32_t id_lo = static_cast<uint32_t>(id), id_hi = static_cast<uint32_t>(id >> 32);
+
+        double acc[kF];
+#pragma unroll
+        for (int i = 0; i < kF; ++i)
+            acc[i] = 0.0;
+        for (uint32_t k = 0; k < a.samples_per_thread; ++k) {
+            const uint32_t local = k * kBlock + tid;
+            if (local >= wi.count)
+                break;
+            const uint64_t q0 = (first_index + local) * static_cast<uint64_t>(nb);
+            double r2 = 0.0;
+            uint32_t upper = 0;
+            for (int j = 0; j < nb; ++j) {
+                uint32_t blk[4];
+                dev::philox_block(q0 + j, id_lo, id_hi, P.seed_lo, P.seed_hi, blk);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int kk = 4 * j + t;
+                    if (kk < dim) {
+                        const double u = dev::map_word(blk[t], scale[kk], base[kk]);
+                        r2 = __fma_rn(u, u, r2);
+                        upper |= (blk[t] >> 31) << kk;
+                    }
+                }
+            }
+            const double f = r2 < 1.0 ? sqrt(1.0 - r2) : 0.0;
+            const double f2 = f * f;
+            acc[0] += f;
+            acc[1] += f2;
+#pragma unroll
+            for (int kk = 0; kk < kMaxNsphereDim; ++kk) {
+                const bool up = kk < dim && ((upper >> kk) & 1u);
+                acc[2 + kk] += up ? f : 0.0;
+                acc[2 + kMaxNsphereDim + kk] += up ? f2 : 0.0;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kF; ++i) {
+            const double v = dev::wave_sum(acc[i]);
+            if (lane == 0)
+                red[wave][i] = v;
+        }
+        __syncthreads();
+        for (int i = tid; i < kF; i += kBlock) {
+            double total = 0.0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w)
+                total += red[w][i];
+            if (i < 2) {
+                wi.rec[2 + i] = total;
+            } else {
+                const int g = i - 2;
+                const int which = g / kMaxNsphereDim, kk = g % kMaxNsphereDim;
+                if (kk < dim)
+                    a.item_split[static_cast<size_t>(it) * (2 * dim) + which * dim + kk] = total;
+            }
+        }
+        if (tid == 0) {
+            wi.rec[0] = static_cast<double>(wi.count);
+            wi.rec[1] = 0.0;
+        }
+        if (!a.queue_head)
+            break;
+        __syncthreads();
+        if (tid == 0)
+            next_item = atomicAdd(a.queue_head, 1u);
+        __syncthreads();
+        it = __builtin_amdgcn_readfirstlane(next_item);
+    }
+}
+
 __global__ void __launch_bounds__(256) debug_points_kernel(DebugPointArgs a)
 {
     const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -95,6 +197,16 @@ __global__ void __launch_bounds__(256) debug_points_kernel(DebugPointArgs a)
 hipError_t launch_reset_head(uint32_t *head, hipStream_t stream)
 {
     hipLaunchKernelGGL(reset_head_kernel, dim3(1), dim3(64), 0, stream, head);
+    return hipGetLastError();
+}
+
+hipError_t launch_nsphere(const NsphereArgs &args, uint32_t grid, hipStream_t stream)
+{
+    if (args.dim < 1 || args.dim > kMaxNsphereDim || !args.mc.item_split)
+        return hipErrorInvalidValue;
+    if (grid == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(nsphere_kernel, dim3(grid), dim3(256), 0, stream, args);
     return hipGetLastError();
 }
 

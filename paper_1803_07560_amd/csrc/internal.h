@@ -112,8 +112,19 @@ hipError_t launch_debug_action_shape(const DebugActionArgs &args, hipStream_t st
 BFI_SHAPES(BFI_DECLARE_SHAPE)
 #undef BFI_DECLARE_SHAPE
 
+// N-sphere test integrand f(x) = sqrt(1 - |x|^2) (0 outside the unit ball) over
+// boxes of `dim` <= kMaxNsphereDim dimensions, FP64.  Records follow the Burgers
+// layout with nx = 0: [n, 0, sum f, sum f^2]; split statistics [sum_U f (dim),
+// sum_U f^2 (dim)] per item.  Blocks of 256 threads.
+constexpr int kMaxNsphereDim = 16;
+struct NsphereArgs {
+    McArgs mc;
+    int32_t dim;
+};
+
 // Shape-independent kernels (common_kernels.hip).
 hipError_t launch_reset_head(uint32_t *head, hipStream_t stream);
+hipError_t launch_nsphere(const NsphereArgs &args, uint32_t grid, hipStream_t stream);
 hipError_t launch_merge(const MergeArgs &args, hipStream_t stream);
 hipError_t launch_debug_points(const DebugPointArgs &args, hipStream_t stream);
 

@@ -317,17 +317,45 @@ bfi_status plan_free(bfi_plan *p)
     return BFI_OK;
 }
 
+namespace {
+
+bfi_status plan_build_core(bfi_context *ctx, int kind, const bfi_lattice &lat, int d, int nx,
+                           int prec, const SubList &subs, const bfi_launch *launch, bool split,
+                           bfi_plan **out);
+
+}  // namespace
+
 bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const SubList &subs,
                       const bfi_launch *launch, bool split, bfi_plan **out)
 {
-    const int d = lat.nx * lat.nt;
-    if (split && d > 32)
+    return plan_build_core(ctx, 0, lat, lat.nx * lat.nt, lat.nx, prec, subs, launch, split, out);
+}
+
+bfi_status plan_build_nsphere(bfi_context *ctx, int dim, const SubList &subs,
+                              const bfi_launch *launch, bfi_plan **out)
+{
+    if (dim < 1 || dim > kMaxNsphereDim)
+        return fail(BFI_EINVAL, "N-sphere dimension must be in [1, %d]", kMaxNsphereDim);
+    bfi_lattice none{};
+    none.nx = 0;
+    none.nt = 1;
+    return plan_build_core(ctx, 1, none, dim, 0, kFP64, subs, launch, true, out);
+}
+
+namespace {
+
+bfi_status plan_build_core(bfi_context *ctx, int kind, const bfi_lattice &lat, int d, int nx,
+                           int prec, const SubList &subs, const bfi_launch *launch, bool split,
+                           bfi_plan **out)
+{
+    if (kind == 0 && split && d > 32)
         return fail(BFI_EUNSUPPORTED, "split statistics need d <= 32 (d = %d)", d);
     if (subs.size() == 0)
         return fail(BFI_EINVAL, "empty subvolume list");
     if (subs.size() > 0xFFFFFFFFull)
         return fail(BFI_EINVAL, "too many subvolumes");
-    bfi_launch l = resolve_launch(ctx, lat, prec, split, launch);
+    bfi_launch l = kind == 0 ? resolve_launch(ctx, lat, prec, split, launch)
+                             : resolve_launch(nullptr, lat, prec, true, launch);
     if (l.block != 64 && l.block != 128 && l.block != 256)
         return fail(BFI_EINVAL, "block must be 64, 128 or 256 (got %d)", l.block);
     if (l.samples_per_thread < 1 || l.samples_per_thread > (1 << 20))
@@ -370,11 +398,12 @@ bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const 
 
     auto *p = new bfi_plan();
     p->ctx = ctx;
+    p->kind = kind;
     p->lat = lat;
     p->prec = prec;
     p->d = d;
-    p->nx = lat.nx;
-    p->rec_len = BFI_PARTIAL_LEN(lat.nx);
+    p->nx = nx;
+    p->rec_len = BFI_PARTIAL_LEN(nx);
     p->split = split;
     p->subs = subs;
     p->launch = l;
@@ -415,7 +444,7 @@ bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const 
         items[i].rec = p->d_item_rec + i * p->rec_len;
     }
     p->params = EvalParams{p->d_base64, p->d_scale64, p->d_base32, p->d_scale32, p->d_ids,
-                           p->d_offsets, make_coef(lat), 0u, 0u};
+                           p->d_offsets, kind == 0 ? make_coef(lat) : ActionCoef{}, 0u, 0u};
     struct Up {
         void *dst;
         const void *src;
@@ -441,11 +470,15 @@ bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const 
 
     // persistent launches fill the chip once: resident blocks per CU x CUs
     if (l.persistent) {
-        LaunchSpec spec{prec, l.block, split ? 1 : 0, 1, 0};
         KernelInfo info{};
-        e = kernel_info(lat.nx, lat.nt, spec, &info);
-        if (e != hipSuccess)
-            return cleanup_fail("kernel occupancy query");
+        if (kind == 0) {
+            LaunchSpec spec{prec, l.block, split ? 1 : 0, 1, 0};
+            e = kernel_info(lat.nx, lat.nt, spec, &info);
+            if (e != hipSuccess)
+                return cleanup_fail("kernel occupancy query");
+        } else {
+            info.blocks_per_cu = 4;  // 104 VGPRs: 4 waves per SIMD, one block per SIMD
+        }
         const uint64_t resident = static_cast<uint64_t>(std::max(info.blocks_per_cu, 1)) *
                                   std::max(ctx->cu_count, 1);
         p->grid = static_cast<uint32_t>(std::min<uint64_t>(resident, items.size()));
@@ -455,6 +488,8 @@ bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const 
     *out = p;
     return BFI_OK;
 }
+
+}  // namespace
 
 bfi_status plan_set_seed(bfi_plan *p, uint64_t seed)
 {
@@ -484,7 +519,10 @@ bfi_status plan_enqueue(bfi_plan *p, uint64_t seed, double *dst, hipStream_t st,
         BFI_HIP(launch_reset_head(p->d_head, st));
     if (timed)
         BFI_HIP(hipEventRecord(p->ev_start, st));
-    BFI_HIP(launch_mc(p->lat.nx, p->lat.nt, spec, a, st));
+    if (p->kind == 1)
+        BFI_HIP(launch_nsphere(NsphereArgs{a, p->d}, p->grid, st));
+    else
+        BFI_HIP(launch_mc(p->lat.nx, p->lat.nt, spec, a, st));
     if (timed)
         BFI_HIP(hipEventRecord(p->ev_stop, st));
     MergeArgs m{};

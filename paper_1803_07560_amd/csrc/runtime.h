@@ -92,6 +92,7 @@ struct bfi_context {
 // A resident evaluation: descriptors, work items and buffers on the device.
 struct bfi_plan {
     bfi_context *ctx = nullptr;
+    int kind = 0;  // 0: lattice action (mc_kernel), 1: N-sphere test integrand
     bfi_lattice lat{};
     int prec = 0;
     int d = 0, nx = 0, rec_len = 0;
@@ -125,6 +126,10 @@ struct bfi_plan {
 namespace bfi {
 bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const SubList &subs,
                       const bfi_launch *launch, bool split, bfi_plan **out);
+// Plan for the N-sphere integrand over `dim`-dimensional boxes (FP64, split
+// statistics always on, 256-thread blocks); records have nx = 0.
+bfi_status plan_build_nsphere(bfi_context *ctx, int dim, const SubList &subs,
+                              const bfi_launch *launch, bfi_plan **out);
 // timed: record the plan's events around the Monte Carlo kernel (not inside a
 // graph capture, where recorded events carry no timestamps)
 bfi_status plan_enqueue(bfi_plan *p, uint64_t seed, double *dst, hipStream_t stream, bool timed);
