@@ -21,18 +21,25 @@ _lib = None
 
 class Lattice(C.Structure):
     """Parameters of Eq. Gen2: nx space sites (M), nt time slices (L), nu, D, a, tau,
-    plus the test knobs g (nonlinear coupling, 1 in the paper) and m2 (mass term, 0)."""
+    plus the test knobs g (nonlinear coupling, 1 in the paper) and m2 (mass term, 0),
+    and the observable behind C(r): 0 anchored at the first site, 1 averaged over
+    all anchors."""
 
     _fields_ = [("nx", C.c_int32), ("nt", C.c_int32), ("nu", C.c_double), ("D", C.c_double),
-                ("a", C.c_double), ("tau", C.c_double), ("g", C.c_double), ("m2", C.c_double)]
+                ("a", C.c_double), ("tau", C.c_double), ("g", C.c_double), ("m2", C.c_double),
+                ("observable", C.c_int32)]
 
     @property
     def d(self) -> int:
         return int(self.nx) * int(self.nt)
 
 
-def lattice(nx, nt, nu=1.0, D=1.0, a=1.0, tau=1.0, g=1.0, m2=0.0) -> Lattice:
-    return Lattice(int(nx), int(nt), float(nu), float(D), float(a), float(tau), float(g), float(m2))
+OBS_ANCHOR, OBS_AVERAGED = 0, 1
+
+
+def lattice(nx, nt, nu=1.0, D=1.0, a=1.0, tau=1.0, g=1.0, m2=0.0, observable=0) -> Lattice:
+    return Lattice(int(nx), int(nt), float(nu), float(D), float(a), float(tau), float(g), float(m2),
+                   int(observable))
 
 
 def sums_len(nx: int) -> int:
@@ -68,6 +75,8 @@ def lib():
         L.oracle_action.restype = C.c_double
         L.oracle_action_batch.argtypes = [latp, C.c_size_t, dp, dp]
         L.oracle_action_batch.restype = C.c_int
+        L.oracle_observable.argtypes = [latp, dp, dp]
+        L.oracle_observable.restype = C.c_int
         for name in ("oracle_sums", "oracle_split_sums"):
             f = getattr(L, name)
             f.argtypes = [latp, C.c_uint64, C.c_size_t, u64p, dp, dp, u64p, u64p, dp, C.c_int32]
@@ -120,6 +129,15 @@ def residual(lat: Lattice, u) -> np.ndarray:
 def action(lat: Lattice, u) -> float:
     u = np.ascontiguousarray(u, dtype=np.float64)
     return float(lib().oracle_action(C.byref(lat), _ptr(u, C.c_double)))
+
+
+def observable(lat: Lattice, u) -> np.ndarray:
+    """p_r, r = 0 .. nx-1, of one configuration (anchored or averaged per lat.observable)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(lat.nx, dtype=np.float64)
+    if lib().oracle_observable(C.byref(lat), _ptr(u, C.c_double), _ptr(out, C.c_double)) != 0:
+        raise ValueError("oracle_observable: invalid arguments")
+    return out
 
 
 def action_batch(lat: Lattice, u) -> np.ndarray:

@@ -106,6 +106,8 @@ static int lattice_ok(const oracle_lattice *lat)
     if (!isfinite(lat->nu) || !isfinite(lat->D) || !isfinite(lat->a) || !isfinite(lat->tau) ||
         !isfinite(lat->g) || !isfinite(lat->m2))
         return 0;
+    if (lat->observable != ORACLE_OBS_ANCHOR && lat->observable != ORACLE_OBS_AVERAGED)
+        return 0;
     return 1;
 }
 
@@ -160,6 +162,29 @@ double oracle_action(const oracle_lattice *lat, const double *u)
     return S;
 }
 
+/* Section 4's equal-time correlation <v(t, x) v(t, x + r)>: either the single
+ * product the paper writes, or its mean over all nx*nt anchors (the action is
+ * invariant under periodic shifts in space and time, so both have the same
+ * expectation). */
+int oracle_observable(const oracle_lattice *lat, const double *u, double *p)
+{
+    if (!lattice_ok(lat) || !u || !p)
+        return -1;
+    const int32_t nx = lat->nx, nt = lat->nt;
+    for (int32_t r = 0; r < nx; ++r) {
+        if (lat->observable == ORACLE_OBS_ANCHOR) {
+            p[r] = site(lat, u, 0, 0) * site(lat, u, 0, r);
+            continue;
+        }
+        double sum = 0.0;
+        for (int32_t l = 0; l < nt; ++l)
+            for (int32_t m = 0; m < nx; ++m)
+                sum += site(lat, u, l, m) * site(lat, u, l, m + r);
+        p[r] = sum / ((double)nx * (double)nt);
+    }
+    return 0;
+}
+
 int oracle_action_batch(const oracle_lattice *lat, size_t n, const double *u, double *S)
 {
     if (!lattice_ok(lat) || (n && (!u || !S)))
@@ -211,6 +236,7 @@ static void subvolume_sums(const sums_job *job, size_t s)
     double *u = (double *)malloc(sizeof(double) * (size_t)d);
     double *scale = (double *)malloc(sizeof(double) * (size_t)d);
     double *base = (double *)malloc(sizeof(double) * (size_t)d);
+    double *p = (double *)malloc(sizeof(double) * (size_t)nx);
     box_map(d, lo, hi, scale, base);
 
     /* record layout: n, w, w^2, p_r w, (p_r w)^2, p_r w^2 -- or, for the split
@@ -236,10 +262,9 @@ static void subvolume_sums(const sums_job *job, size_t s)
         nm_add(&acc[0], 1.0);
         nm_add(&acc[1], w);
         nm_add(&acc[2], w * w);
+        oracle_observable(lat, u, p);
         for (int32_t r = 0; r < nx; ++r) {
-            /* equal-time product anchored at (t_1, x_1): v(t_1,x_1) v(t_1,x_{1+r}) */
-            double p = u[0] * u[r];
-            double pw = p * w;
+            double pw = p[r] * w;
             nm_add(&acc[3 + r], pw);
             nm_add(&acc[3 + nx + r], pw * pw);
             nm_add(&acc[3 + 2 * nx + r], pw * w);
@@ -253,6 +278,7 @@ static void subvolume_sums(const sums_job *job, size_t s)
     free(u);
     free(scale);
     free(base);
+    free(p);
 }
 
 static void *sums_worker(void *arg)

@@ -26,15 +26,26 @@ extern "C" {
 
 /* Parameters of the discretised action (Eq. Gen2 and the constants after it).
  * g multiplies the nonlinear term (1 in the paper; 0 gives the Gaussian case)
- * and m2 adds (m2/2)*sum(u^2) (0 in the paper; a regulator for closed forms). */
+ * and m2 adds (m2/2)*sum(u^2) (0 in the paper; a regulator for closed forms).
+ * observable selects the per-sample product p_r behind C(r) (oracle_observable). */
 typedef struct {
     int32_t nx, nt;
     double nu, D, a, tau;
     double g, m2;
+    int32_t observable;
 } oracle_lattice;
 
+/* p_r as the section 4 correlation is written: the product of the velocity at
+ * the first site of the first time slice with the one r sites to its right. */
+#define ORACLE_OBS_ANCHOR 0
+/* The same product averaged over every anchor (t_l, x_m) of the lattice.  Its
+ * expectation under exp(-S) is the anchored one, because the action of Eq. Gen2
+ * is unchanged by periodic shifts in space and in time. */
+#define ORACLE_OBS_AVERAGED 1
+
 /* Number of doubles in one per-subvolume sums record:
- * [n, sum w, sum w^2, sum p_r w (nx), sum (p_r w)^2 (nx), sum p_r w^2 (nx)]. */
+ * [n, sum w, sum w^2, sum p_r w (nx), sum (p_r w)^2 (nx), sum p_r w^2 (nx)]
+ * with p_r from oracle_observable. */
 #define ORACLE_SUMS_LEN(nx) (3 + 3 * (nx))
 
 /* Number of doubles in the finalize output:
@@ -60,6 +71,12 @@ int oracle_residual(const oracle_lattice *lat, const double *u, double *R);
 
 /* The action S[u] = sum R^2 / (2 D tau) + (m2/2) sum u^2 (exponent of Eq. Gen2). */
 double oracle_action(const oracle_lattice *lat, const double *u);
+
+/* The products p_r, r = 0 .. nx-1, of one configuration u (d = nx*nt values):
+ * anchored:  p_r = u(t_0, x_0) u(t_0, x_r);
+ * averaged:  p_r = (1/(nx nt)) sum over l, m of u(t_l, x_m) u(t_l, x_{m+r}),
+ * space index periodic. */
+int oracle_observable(const oracle_lattice *lat, const double *u, double *p);
 
 /* S for n points stored row-major (n x d). */
 int oracle_action_batch(const oracle_lattice *lat, size_t n, const double *u, double *S);
