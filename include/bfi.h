@@ -66,13 +66,27 @@ typedef enum {
                              w = exp(sigma - S), sums in FP64 relative to exp(-sigma) */
 } bfi_precision;
 
+/* The per-sample product p_r behind N(r) and C(r) = N(r)/Z (section 4's
+ * equal-time correlation). */
+typedef enum {
+    BFI_OBS_ANCHOR = 0,   /* p_r = u_{0,0} u_{0,r}: first time slice, sites 0 and r */
+    BFI_OBS_AVERAGED = 1  /* p_r = (1/(nx nt)) sum_{l,m} u_{l,m} u_{l,m+r} (space index
+                             periodic): the anchored product averaged over every
+                             anchor.  The action of Eq. Gen2 is invariant under
+                             periodic shifts in space and time, so N(r) and C(r) keep
+                             their expectation while their variance drops; p_r is
+                             exactly symmetric in r <-> nx - r.  Costs nx (nx/2 + 1)
+                             multiply-adds per time slice per sample. */
+} bfi_observable;
+
 /* Lattice and parameters of Eq. Gen2.  nx = space sites (the paper's M),
  * nt = time slices (L); the paper's run is nx = 10, nt = 2, a = tau = nu = D = 1. */
 typedef struct {
     int32_t nx, nt;
     double nu, D, a, tau;
-    double g;   /* nonlinear coupling, 1 for Burgers */
-    double m2;  /* mass term, 0 for Burgers */
+    double g;            /* nonlinear coupling, 1 for Burgers */
+    double m2;           /* mass term, 0 for Burgers */
+    int32_t observable;  /* bfi_observable; 0 (anchored) is the paper's product */
 } bfi_lattice;
 
 /* A list of subvolumes (host arrays, caller-owned).
@@ -106,7 +120,8 @@ typedef struct {
  *   [n, sigma, S_w, S_w2, S_pw[nx], S_pw2[nx], S_pww[nx]]
  * with sums over the samples of w = exp(-S) scaled by exp(sigma) (first-order
  * sums: S_w, S_pw) or exp(2 sigma) (second-order: S_w2, S_pw2 = sum (p_r w)^2,
- * S_pww = sum p_r w^2), p_r = u_{0,0} u_{0,r}.  sigma is 0 in BFI_FP64. */
+ * S_pww = sum p_r w^2), p_r as selected by the lattice's observable.  sigma is 0
+ * in BFI_FP64. */
 #define BFI_PARTIAL_LEN(nx) (4 + 3 * (nx))
 /* Split statistics per subvolume: [sigma, S_U w (d), S_U w^2 (d)], sums over the
  * samples in the upper half of the subvolume along each dimension (Philox word

@@ -17,6 +17,8 @@ LIB_PATH = os.environ.get("BFI_LIBRARY") or os.path.join(_HERE, "libbfi.so")
 
 BFI_FP64 = 0
 BFI_FP32_SHIFTED = 1
+BFI_OBS_ANCHOR = 0
+BFI_OBS_AVERAGED = 1
 PRECISIONS = {"fp64": BFI_FP64, "fp32": BFI_FP32_SHIFTED, BFI_FP64: BFI_FP64,
               BFI_FP32_SHIFTED: BFI_FP32_SHIFTED}
 
@@ -37,7 +39,8 @@ class BfiError(RuntimeError):
 
 class bfi_lattice(C.Structure):
     _fields_ = [("nx", C.c_int32), ("nt", C.c_int32), ("nu", C.c_double), ("D", C.c_double),
-                ("a", C.c_double), ("tau", C.c_double), ("g", C.c_double), ("m2", C.c_double)]
+                ("a", C.c_double), ("tau", C.c_double), ("g", C.c_double), ("m2", C.c_double),
+                ("observable", C.c_int32)]
 
     @property
     def d(self) -> int:
@@ -227,9 +230,12 @@ def _prec(p) -> int:
     return PRECISIONS[p]
 
 
-def lattice(nx, nt, nu=1.0, D=1.0, a=1.0, tau=1.0, g=1.0, m2=0.0) -> bfi_lattice:
+def lattice(nx, nt, nu=1.0, D=1.0, a=1.0, tau=1.0, g=1.0, m2=0.0,
+            observable="anchor") -> bfi_lattice:
+    """observable: "anchor" (u_{0,0} u_{0,r}, the paper's) or "averaged" (over all anchors)."""
+    obs = {"anchor": BFI_OBS_ANCHOR, "averaged": BFI_OBS_AVERAGED}.get(observable, observable)
     return bfi_lattice(int(nx), int(nt), float(nu), float(D), float(a), float(tau), float(g),
-                       float(m2))
+                       float(m2), int(obs))
 
 
 def launch(samples_per_thread=0, block=0, persistent=-1, use_graph=0) -> bfi_launch:

@@ -37,7 +37,8 @@ struct EvalParams {
 
 // One unit of device work: `count` consecutive samples of subvolume `sub` of
 // `params`, starting `start` samples after the subvolume's own offset; the
-// item's partial record goes to `rec` (4 + 3 nx doubles).
+// item's partial record goes to `rec` (4 + 3 nx doubles).  Every item of one
+// launch shares the lattice shape, the precision and the observable.
 struct WorkItem {
     const EvalParams *params;
     double *rec;
@@ -60,6 +61,7 @@ struct LaunchSpec {
     int split;       // 0/1
     int persistent;  // 0/1
     uint32_t grid;   // blocks
+    int obs = 0;     // bfi_observable: 0 anchored product, 1 averaged over anchors
 };
 
 struct MergeArgs {

@@ -114,6 +114,8 @@ bfi_status check_lattice(const bfi_lattice *lat)
         return fail(BFI_EINVAL, "D, a and tau must be positive");
     if (lat->m2 < 0)
         return fail(BFI_EINVAL, "m2 must be >= 0");
+    if (lat->observable != BFI_OBS_ANCHOR && lat->observable != BFI_OBS_AVERAGED)
+        return fail(BFI_EINVAL, "unknown observable %d", lat->observable);
     if (!shape_compiled(lat->nx, lat->nt))
         return fail(BFI_EUNSUPPORTED, "lattice %dx%d has no compiled kernel", lat->nx, lat->nt);
     return BFI_OK;
@@ -472,7 +474,7 @@ bfi_status plan_build_core(bfi_context *ctx, int kind, const bfi_lattice &lat, i
     if (l.persistent) {
         KernelInfo info{};
         if (kind == 0) {
-            LaunchSpec spec{prec, l.block, split ? 1 : 0, 1, 0};
+            LaunchSpec spec{prec, l.block, split ? 1 : 0, 1, 0, lat.observable};
             e = kernel_info(lat.nx, lat.nt, spec, &info);
             if (e != hipSuccess)
                 return cleanup_fail("kernel occupancy query");
@@ -514,7 +516,8 @@ bfi_status plan_enqueue(bfi_plan *p, uint64_t seed, double *dst, hipStream_t st,
     a.queue_head = p->launch.persistent ? p->d_head : nullptr;
     a.nitems = p->nitems;
     a.samples_per_thread = static_cast<uint32_t>(p->launch.samples_per_thread);
-    LaunchSpec spec{p->prec, p->launch.block, p->split ? 1 : 0, p->launch.persistent, p->grid};
+    LaunchSpec spec{p->prec,  p->launch.block, p->split ? 1 : 0, p->launch.persistent,
+                    p->grid,  p->lat.observable};
     if (p->launch.persistent)
         BFI_HIP(launch_reset_head(p->d_head, st));
     if (timed)

@@ -123,19 +123,19 @@ struct bfi_server {
 
 namespace {
 
-// Launch shape and persistent grid for (nx, nt, prec); fixed for the server's
-// lifetime so item sizes (and therefore results) never depend on the mix.
+// Launch shape and persistent grid for (nx, nt, prec, observable); fixed for the
+// server's lifetime so item sizes (and therefore results) never depend on the mix.
 bfi_status shape_launch(bfi_server *srv, const bfi_lattice &lat, int prec, bfi_launch *l,
                         uint32_t *grid)
 {
-    const TuneKey key{lat.nx, lat.nt, prec};
+    const TuneKey key{lat.nx, lat.nt, prec + 2 * lat.observable};
     auto it = srv->shapes.find(key);
     if (it == srv->shapes.end()) {
         bfi_launch r = resolve_launch(srv->ctx, lat, prec, false, nullptr);
         r.persistent = 1;
         r.use_graph = 0;
         KernelInfo info{};
-        LaunchSpec spec{prec, r.block, 0, 1, 0};
+        LaunchSpec spec{prec, r.block, 0, 1, 0, lat.observable};
         BFI_HIP(kernel_info(lat.nx, lat.nt, spec, &info));
         const uint32_t g =
             static_cast<uint32_t>(std::max(info.blocks_per_cu, 1) * std::max(srv->ctx->cu_count, 1));
@@ -302,7 +302,7 @@ bfi_status run_step(bfi_server *srv, const std::vector<StepEntry> &entries)
     };
     std::vector<Group> groups;
     size_t total = 0;
-    // group entries by (shape, precision), keeping their order
+    // group entries by (shape, precision, observable), keeping their order
     std::vector<bool> used(entries.size(), false);
     for (size_t i = 0; i < entries.size(); ++i) {
         if (used[i])
@@ -311,7 +311,8 @@ bfi_status run_step(bfi_server *srv, const std::vector<StepEntry> &entries)
         Group g{q.lat, q.prec, total, 0, entries[i].r->launch, entries[i].r->grid};
         for (size_t j = i; j < entries.size(); ++j) {
             const bfi_request &o = entries[j].r->req;
-            if (used[j] || o.lat.nx != q.lat.nx || o.lat.nt != q.lat.nt || o.prec != q.prec)
+            if (used[j] || o.lat.nx != q.lat.nx || o.lat.nt != q.lat.nt || o.prec != q.prec ||
+                o.lat.observable != q.lat.observable)
                 continue;
             used[j] = true;
             const StepEntry &e = entries[j];
@@ -341,7 +342,8 @@ bfi_status run_step(bfi_server *srv, const std::vector<StepEntry> &entries)
         a.nitems = static_cast<uint32_t>(g.count);
         a.samples_per_thread = static_cast<uint32_t>(g.launch.samples_per_thread);
         LaunchSpec spec{g.prec, g.launch.block, 0, 1,
-                        static_cast<uint32_t>(std::min<size_t>(g.grid, g.count))};
+                        static_cast<uint32_t>(std::min<size_t>(g.grid, g.count)),
+                        g.lat.observable};
         BFI_HIP(launch_mc(g.lat.nx, g.lat.nt, spec, a, st));
     }
     for (int k = 0; k < nstreams; ++k)

@@ -7,7 +7,10 @@
 // sample is one lattice configuration held in the thread's registers:
 //   Philox words -> point in the subvolume -> action S (Eq. Gen2)
 //   -> weight exp(-S) -> FP64 sums of w, w^2, p_r w, (p_r w)^2, p_r w^2
-// with p_r = u_{0,0} u_{0,r}.  Per-thread sums are reduced across the
+// with p_r = u_{0,0} u_{0,r} (anchored), or p_r averaged over every anchor
+// (u_{l,m} u_{l,m+r} summed slice by slice as the slices are generated and
+// divided by nx nt; only r = 0 .. nx/2 are accumulated, the rest are their
+// mirror images r <-> nx - r).  Per-thread sums are reduced across the
 // wavefront with butterfly shuffles and across the block through LDS in a
 // fixed order, so the item's record is bitwise reproducible for a given launch
 // shape.  Persistent launches take items from a device counter instead of
@@ -29,21 +32,39 @@ namespace {
 constexpr float kShiftGap = 64.0f;
 constexpr float kLog2e = 1.44269504088896340736f;
 
-template <int NX, int D, bool SPLIT>
+template <int NX, int D, bool SPLIT, bool AVG>
 struct Fields {
-    // reduced fields: [w, w^2, p_r w (NX), (p_r w)^2 (NX), p_r w^2 (NX), U w (D), U w^2 (D)]
-    static constexpr int kMain = 2 + 3 * NX;
+    // distinct products: every r for the anchored product, r = 0 .. NX/2 for
+    // the averaged one (symmetric in r <-> NX - r)
+    static constexpr int kR = AVG ? NX / 2 + 1 : NX;
+    // accumulated fields: [w, w^2, p_r w (kR), (p_r w)^2 (kR), p_r w^2 (kR),
+    //                      U w (D), U w^2 (D)]
+    static constexpr int kMain = 2 + 3 * kR;
     static constexpr int kCount = kMain + (SPLIT ? 2 * D : 0);
+    // written fields: the record's [w, w^2, p_r w (NX), (p_r w)^2 (NX),
+    // p_r w^2 (NX)], then the split statistics
+    static constexpr int kRecord = 2 + 3 * NX;
+    static constexpr int kOut = kRecord + (SPLIT ? 2 * D : 0);
     // 1 for sums of first order in w, 2 for second order (scaled by the square
     // of a shift factor)
     __host__ __device__ static constexpr int order(int i)
     {
         return i == 0 ? 1
                : i == 1 ? 2
-               : i < 2 + NX ? 1
+               : i < 2 + kR ? 1
                : i < kMain ? 2
                : i < kMain + D ? 1
                                : 2;
+    }
+    // accumulated field that written field f comes from
+    __host__ __device__ static constexpr int source(int f)
+    {
+        if (f < 2)
+            return f;
+        if (f >= kRecord)
+            return kMain + (f - kRecord);
+        const int which = (f - 2) / NX, r = (f - 2) % NX;
+        return 2 + which * kR + (AVG && r > NX / 2 ? NX - r : r);
     }
 };
 
@@ -52,7 +73,7 @@ struct Fields {
 template <int NX, int NT>
 constexpr int kMinWaves = NX * NT > 32 ? 2 : 1;
 
-template <int NX, int NT, int PREC, int BLOCK, bool SPLIT>
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG>
 __global__ void __launch_bounds__(BLOCK)
     __attribute__((amdgpu_waves_per_eu(kMinWaves<NX, NT>))) mc_kernel(McArgs a)
 {
@@ -60,8 +81,13 @@ __global__ void __launch_bounds__(BLOCK)
     constexpr int D = NX * NT;
     constexpr int NB = (D + 3) / 4;
     constexpr int NW = BLOCK / 64;
-    using F = Fields<NX, D, SPLIT>;
+    using F = Fields<NX, D, SPLIT, AVG>;
     constexpr int NF = F::kCount;
+    constexpr int NR = F::kR;
+    // at r = NX/2 (NX even) each pair u_m u_{m+r} appears twice in the sum over
+    // m: accumulate half the terms and double (exactly) at the end
+    constexpr bool kHalfPair = AVG && NX % 2 == 0 && NX > 1;
+    const T inv_sites = T(1) / T(D);
     static_assert(!SPLIT || D <= 32, "split statistics keep one bit per dimension in 32 bits");
 
     // point map held in registers when 2d values take at most 80 VGPRs
@@ -162,6 +188,10 @@ __global__ void __launch_bounds__(BLOCK)
             const uint64_t q0 = (first_index + local) * NB;
             uint32_t blk[4];
             uint32_t upper = 0;
+            T pbar[AVG ? NR : 1];
+#pragma unroll
+            for (int r = 0; r < (AVG ? NR : 1); ++r)
+                pbar[r] = T(0);
             auto gen = [&](int l, T(&out)[NX], T token) {
                 uint64_t qs = q0;
                 uint32_t zoff = 0;
@@ -185,20 +215,43 @@ __global__ void __launch_bounds__(BLOCK)
                         upper |= (x >> 31) << kk;
                     out[m] = dev::map_word(x, scale_of(kk, row), base_of(kk, row));
                 }
+                if constexpr (AVG) {
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        const int terms = kHalfPair && 2 * r == NX ? NX / 2 : NX;
+#pragma unroll
+                        for (int m = 0; m < terms; ++m)
+                            pbar[r] = dev::fma_t(out[m], out[(m + r) % NX], pbar[r]);
+                    }
+                }
             };
             T first[NX];
             const T S = dev::action<T, NX, NT>(gen, first, coef, mass);
+            // p_r = pr_scale * pr[r]
+            T pr[NR];
+            T pr_scale;
+            if constexpr (AVG) {
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+                    pr[r] = kHalfPair && 2 * r == NX ? T(2) * pbar[r] : pbar[r];
+                pr_scale = inv_sites;
+            } else {
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+                    pr[r] = first[r];
+                pr_scale = first[0];
+            }
 
             double w;
             if constexpr (PREC == kFP64) {
                 w = exp(-S);
-                const double t = first[0] * w;
+                const double t = pr_scale * w;
 #pragma unroll
-                for (int r = 0; r < NX; ++r) {
-                    const double v = t * first[r];
+                for (int r = 0; r < NR; ++r) {
+                    const double v = t * pr[r];
                     acc[2 + r] += v;
-                    acc[2 + NX + r] = __fma_rn(v, v, acc[2 + NX + r]);
-                    acc[2 + 2 * NX + r] = __fma_rn(v, w, acc[2 + 2 * NX + r]);
+                    acc[2 + NR + r] = __fma_rn(v, v, acc[2 + NR + r]);
+                    acc[2 + 2 * NR + r] = __fma_rn(v, w, acc[2 + 2 * NR + r]);
                 }
             } else {
                 if (S < sigma - kShiftGap) {
@@ -209,13 +262,13 @@ __global__ void __launch_bounds__(BLOCK)
                 }
                 const float w32 = __builtin_amdgcn_exp2f((sigma - S) * kLog2e);
                 w = static_cast<double>(w32);
-                const float t32 = first[0] * w32;
+                const float t32 = pr_scale * w32;
 #pragma unroll
-                for (int r = 0; r < NX; ++r) {
-                    const double v = static_cast<double>(t32 * first[r]);
+                for (int r = 0; r < NR; ++r) {
+                    const double v = static_cast<double>(t32 * pr[r]);
                     acc[2 + r] += v;
-                    acc[2 + NX + r] = __fma_rn(v, v, acc[2 + NX + r]);
-                    acc[2 + 2 * NX + r] = __fma_rn(v, w, acc[2 + 2 * NX + r]);
+                    acc[2 + NR + r] = __fma_rn(v, v, acc[2 + NR + r]);
+                    acc[2 + 2 * NR + r] = __fma_rn(v, w, acc[2 + 2 * NR + r]);
                 }
             }
             acc[0] += w;
@@ -258,25 +311,26 @@ __global__ void __launch_bounds__(BLOCK)
                 block_sigma = fminf(block_sigma, red_sigma[w]);
         }
         double *rec = wi.rec;
-        for (int i = tid; i < NF; i += BLOCK) {
+        for (int i = tid; i < F::kOut; i += BLOCK) {
+            const int src = F::source(i);
             double total = 0.0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
-                double v = red[w][i];
+                double v = red[w][src];
                 if constexpr (PREC != kFP64) {
                     const float ws = red_sigma[w];
                     const double f1 = ws == __builtin_inff()
                                           ? 0.0
                                           : exp(static_cast<double>(block_sigma) -
                                                 static_cast<double>(ws));
-                    v *= F::order(i) == 1 ? f1 : f1 * f1;
+                    v *= F::order(src) == 1 ? f1 : f1 * f1;
                 }
                 total += v;
             }
-            if (i < F::kMain)
+            if (i < F::kRecord)
                 rec[2 + i] = total;
             else
-                a.item_split[static_cast<size_t>(it) * (2 * D) + (i - F::kMain)] = total;
+                a.item_split[static_cast<size_t>(it) * (2 * D) + (i - F::kRecord)] = total;
         }
         if (tid == 0) {
             rec[0] = static_cast<double>(wi.count);
@@ -312,25 +366,25 @@ __global__ void __launch_bounds__(256) debug_action_kernel(DebugActionArgs a)
     a.out[i] = static_cast<double>(dev::action<T, NX, NT>(gen, first, coef, a.coef.half_m2 != 0.0));
 }
 
-template <int NX, int NT, int PREC, int BLOCK, bool SPLIT>
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG>
 hipError_t launch_one(const LaunchSpec &spec, const McArgs &args, hipStream_t stream)
 {
-    hipLaunchKernelGGL((mc_kernel<NX, NT, PREC, BLOCK, SPLIT>), dim3(spec.grid), dim3(BLOCK), 0,
-                       stream, args);
+    hipLaunchKernelGGL((mc_kernel<NX, NT, PREC, BLOCK, SPLIT, AVG>), dim3(spec.grid), dim3(BLOCK),
+                       0, stream, args);
     return hipGetLastError();
 }
 
-template <int NX, int NT, int PREC, int BLOCK, bool SPLIT>
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG>
 hipError_t info_one(KernelInfo *info)
 {
     hipFuncAttributes attr;
     hipError_t e = hipFuncGetAttributes(
-        &attr, reinterpret_cast<const void *>(&mc_kernel<NX, NT, PREC, BLOCK, SPLIT>));
+        &attr, reinterpret_cast<const void *>(&mc_kernel<NX, NT, PREC, BLOCK, SPLIT, AVG>));
     if (e != hipSuccess)
         return e;
     int blocks = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, mc_kernel<NX, NT, PREC, BLOCK, SPLIT>,
-                                                     BLOCK, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &blocks, mc_kernel<NX, NT, PREC, BLOCK, SPLIT, AVG>, BLOCK, 0);
     if (e != hipSuccess)
         return e;
     info->vgprs = attr.numRegs;
@@ -339,18 +393,20 @@ hipError_t info_one(KernelInfo *info)
     return hipSuccess;
 }
 
-// Dispatch over (precision, block, split) for this shape.  Split statistics
-// are compiled for 256-thread blocks and d <= 32 only.
-template <int NX, int NT, template <int, int, int, int, bool> class Op, class... Args>
-hipError_t dispatch(const LaunchSpec &spec, Args &&...args)
+// Dispatch over (precision, block, split) for this shape and observable.
+// Split statistics are compiled for 256-thread blocks and d <= 32 only.
+template <int NX, int NT, bool AVG, template <int, int, int, int, bool, bool> class Op,
+          class... Args>
+hipError_t dispatch_obs(const LaunchSpec &spec, Args &&...args)
 {
     constexpr int D = NX * NT;
     if (spec.split) {
         if constexpr (D <= 32) {
             if (spec.block != 256)
                 return hipErrorInvalidValue;
-            return spec.prec == kFP64 ? Op<NX, NT, kFP64, 256, true>::run(spec, args...)
-                                      : Op<NX, NT, kFP32Shifted, 256, true>::run(spec, args...);
+            return spec.prec == kFP64
+                       ? Op<NX, NT, kFP64, 256, true, AVG>::run(spec, args...)
+                       : Op<NX, NT, kFP32Shifted, 256, true, AVG>::run(spec, args...);
         } else {
             return hipErrorNotSupported;
         }
@@ -358,32 +414,45 @@ hipError_t dispatch(const LaunchSpec &spec, Args &&...args)
     const bool f64 = spec.prec == kFP64;
     switch (spec.block) {
     case 64:
-        return f64 ? Op<NX, NT, kFP64, 64, false>::run(spec, args...)
-                   : Op<NX, NT, kFP32Shifted, 64, false>::run(spec, args...);
+        return f64 ? Op<NX, NT, kFP64, 64, false, AVG>::run(spec, args...)
+                   : Op<NX, NT, kFP32Shifted, 64, false, AVG>::run(spec, args...);
     case 128:
-        return f64 ? Op<NX, NT, kFP64, 128, false>::run(spec, args...)
-                   : Op<NX, NT, kFP32Shifted, 128, false>::run(spec, args...);
+        return f64 ? Op<NX, NT, kFP64, 128, false, AVG>::run(spec, args...)
+                   : Op<NX, NT, kFP32Shifted, 128, false, AVG>::run(spec, args...);
     case 256:
-        return f64 ? Op<NX, NT, kFP64, 256, false>::run(spec, args...)
-                   : Op<NX, NT, kFP32Shifted, 256, false>::run(spec, args...);
+        return f64 ? Op<NX, NT, kFP64, 256, false, AVG>::run(spec, args...)
+                   : Op<NX, NT, kFP32Shifted, 256, false, AVG>::run(spec, args...);
     default:
         return hipErrorInvalidValue;
     }
 }
 
-template <int NX, int NT, int PREC, int BLOCK, bool SPLIT>
+template <int NX, int NT, template <int, int, int, int, bool, bool> class Op, class... Args>
+hipError_t dispatch(const LaunchSpec &spec, Args &&...args)
+{
+    switch (spec.obs) {
+    case 0:
+        return dispatch_obs<NX, NT, false, Op>(spec, args...);
+    case 1:
+        return dispatch_obs<NX, NT, true, Op>(spec, args...);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG>
 struct LaunchOp {
     static hipError_t run(const LaunchSpec &spec, const McArgs &args, hipStream_t stream)
     {
-        return launch_one<NX, NT, PREC, BLOCK, SPLIT>(spec, args, stream);
+        return launch_one<NX, NT, PREC, BLOCK, SPLIT, AVG>(spec, args, stream);
     }
 };
 
-template <int NX, int NT, int PREC, int BLOCK, bool SPLIT>
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG>
 struct InfoOp {
     static hipError_t run(const LaunchSpec &, KernelInfo *info)
     {
-        return info_one<NX, NT, PREC, BLOCK, SPLIT>(info);
+        return info_one<NX, NT, PREC, BLOCK, SPLIT, AVG>(info);
     }
 };
 

@@ -42,8 +42,9 @@ def assert_sums_close(got, want, nx, rtol):
     assert np.array_equal(got[:, 0], want[:, 0])
     n = want[:, 0:1]
     pw2 = want[:, 3 + nx:3 + 2 * nx]
+    # product of square roots: sqrt(pw2 * w2) underflows for weights near 1e-100
     scale = np.concatenate([want[:, 1:3], np.sqrt(n * pw2), pw2,
-                            np.sqrt(pw2 * want[:, 2:3])], axis=1)
+                            np.sqrt(pw2) * np.sqrt(want[:, 2:3])], axis=1)
     err = np.abs(got[:, 1:] - want[:, 1:])
     bad = err > rtol * scale + 1e-300
     assert not bad.any(), (np.argwhere(bad)[:5], (err / (scale + 1e-300)).max())
