@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--adaptive-budget-log2", type=int, default=32,
                     help="evaluation budget of each adaptive 10x2 run (0 skips them)")
+    ap.add_argument("--no-observable-leg", action="store_true",
+                    help="skip the translation-averaged observable leg")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1803_07560_amd",
@@ -181,6 +183,32 @@ def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0)):
     return out
 
 
+def observable_leg(bfi, torch, ctx, w, sv, steps, warmup, stream, accuracy_log2=26):
+    """The translation-averaged product (p_r averaged over every anchor):
+    throughput of both forms on the benchmark workload, and on the paper's
+    integration range [-1, 1]^20 (2^accuracy_log2 points, 64 subvolumes, FP32
+    form) the error bars of both observables on the same points.  The time to
+    reach a given error scales as sigma^2 / rate, so the equal-error speedup
+    per r is (sigma_anchor / sigma_averaged)^2 * rate_averaged / rate_anchor."""
+    lat = bfi.lattice(w.nx, w.nt, nu=w.nu, D=w.D, observable="averaged")
+    forms = {}
+    for prec in ("fp64", "fp32"):
+        print(f"bench: averaged observable {prec}", file=sys.stderr, flush=True)
+        f = run_form(bfi, torch, ctx, lat, sv, w, prec, steps, warmup, stream)
+        forms[prec] = {"evals_per_s": f["evals_per_s"], "ms_per_step": f["ms_per_step"],
+                       "kernel_ms": f["kernel_ms"]}
+    est = {}
+    for obs in ("anchor", "averaged"):
+        est[obs] = bfi.bfi_integrate(ctx, bfi.lattice(w.nx, w.nt, nu=w.nu, D=w.D, observable=obs),
+                                     "fp32", 3, -1.0, 1.0, 6, 1 << accuracy_log2)
+    ratio = np.asarray(est["anchor"]["C_err"]) / np.asarray(est["averaged"]["C_err"])
+    return {"forms": forms, "paper_range": {
+        "box": [-1.0, 1.0], "evals": 1 << accuracy_log2, "form": "fp32",
+        "C_anchor": [float(c) for c in est["anchor"]["C"]],
+        "C_averaged": [float(c) for c in est["averaged"]["C"]],
+        "C_err_ratio": [float(x) for x in ratio]}}
+
+
 def kernel_source_digest():
     """sha256 of the kernel sources: traffic figures apply only to the kernel
     they were measured on."""
@@ -244,6 +272,9 @@ def main():
         print(f"bench: {w.name} {prec} warmup {args.warmup} steps {args.steps}", file=sys.stderr,
               flush=True)
         forms[prec] = run_form(bfi, torch, ctx, lat, sv, w, prec, args.steps, args.warmup, stream)
+    averaged = None
+    if not args.no_observable_leg:
+        averaged = observable_leg(bfi, torch, ctx, w, sv, args.steps, args.warmup, stream)
     adaptive = None
     if args.adaptive_budget_log2 > 0:
         print(f"bench: adaptive 10x2, budget 2^{args.adaptive_budget_log2} per nu",
@@ -312,6 +343,12 @@ def main():
                      "max_rel_err_C": stat, "ess": r64["ess"]},
         "roofline": roofline,
     }
+    if averaged is not None:
+        rate = averaged["forms"][args.headline]["evals_per_s"] / head["evals_per_s"]
+        ratio = np.asarray(averaged["paper_range"]["C_err_ratio"])
+        averaged["equal_error_speedup"] = {"min_r": float(np.min(ratio ** 2) * rate),
+                                           "median_r": float(np.median(ratio ** 2) * rate)}
+        line["observable_averaged"] = averaged
     if serving is not None:
         line["p99_latency_ms"] = serving["p99_ms"]
         line["serving"] = serving
