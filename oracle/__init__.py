@@ -87,6 +87,16 @@ def lib():
         L.oracle_plan_uniform.restype = C.c_int
         L.oracle_nsphere.argtypes = [C.c_int32, C.c_uint64, C.c_uint64, dp, dp, C.c_uint64, dp]
         L.oracle_nsphere.restype = C.c_int
+        i32p = C.POINTER(C.c_int32)
+        L.oracle_is_basis.argtypes = [C.c_int32, C.c_int32, dp]
+        L.oracle_is_basis.restype = C.c_int
+        L.oracle_is_modes.argtypes = [latp, dp, dp, dp, i32p, dp, dp]
+        L.oracle_is_modes.restype = C.c_int
+        L.oracle_is_point.argtypes = [latp, dp, dp, C.c_uint64, C.c_uint64, C.c_uint64, dp, dp]
+        L.oracle_is_point.restype = C.c_int
+        L.oracle_is_sums.argtypes = [latp, C.c_uint64, dp, dp, C.c_double, C.c_size_t, u64p, u64p,
+                                     u64p, dp, C.c_int32]
+        L.oracle_is_sums.restype = C.c_int
         _lib = L
     return _lib
 
@@ -241,3 +251,100 @@ def nsphere(dim: int, seed: int, lo, hi, n: int, sub_id: int = 1) -> dict:
                             _ptr(out, C.c_double)) != 0:
         raise ValueError("oracle_nsphere: invalid arguments")
     return {"n": out[0], "sum_f": out[1], "sum_f2": out[2], "result": out[3], "abserr": out[4]}
+
+
+# ------------------------------------------------ Gaussian-proposal sampling
+
+def _is_box(d, lo, hi):
+    lo = np.ascontiguousarray(np.broadcast_to(np.asarray(lo, dtype=np.float64), (d,)))
+    hi = np.ascontiguousarray(np.broadcast_to(np.asarray(hi, dtype=np.float64), (d,)))
+    return lo, hi
+
+
+def is_basis(nx: int, nt: int) -> np.ndarray:
+    """d x d orthonormal real Fourier basis (rows: lattice variables, columns: modes)."""
+    E = np.zeros((nx * nt, nx * nt))
+    if lib().oracle_is_basis(nx, nt, _ptr(E, C.c_double)) != 0:
+        raise ValueError("oracle_is_basis: invalid arguments")
+    return E
+
+
+def is_modes(lat: Lattice, lo, hi) -> dict:
+    d = lat.d
+    lo, hi = _is_box(d, lo, hi)
+    lam, scale = np.zeros(d), np.zeros(d)
+    uni = np.zeros(d, dtype=np.int32)
+    lk = C.c_double()
+    if lib().oracle_is_modes(C.byref(lat), _ptr(lo, C.c_double), _ptr(hi, C.c_double),
+                             _ptr(lam, C.c_double), _ptr(uni, C.c_int32),
+                             _ptr(scale, C.c_double), C.byref(lk)) != 0:
+        raise ValueError("oracle_is_modes: invalid arguments")
+    return {"lambda": lam, "uniform": uni.astype(bool), "scale": scale, "log_k": lk.value}
+
+
+def is_point(lat: Lattice, lo, hi, seed: int, stream: int, index: int):
+    """(u, sum z^2/2) of one sample of the Gaussian proposal."""
+    d = lat.d
+    lo, hi = _is_box(d, lo, hi)
+    u = np.zeros(d)
+    hz = C.c_double()
+    if lib().oracle_is_point(C.byref(lat), _ptr(lo, C.c_double), _ptr(hi, C.c_double), seed,
+                             stream, index, _ptr(u, C.c_double), C.byref(hz)) != 0:
+        raise ValueError("oracle_is_point: invalid arguments")
+    return u, hz.value
+
+
+IS_UNIFORM_STREAM = 1 << 63
+
+
+def is_sums(lat: Lattice, seed: int, lo, hi, ids, n, offset=0, gaussian_fraction=0.9,
+            nthreads: int | None = None):
+    """Per-stream sums records of the mixture weight W/K (streams with bit 63 of
+    the id set draw from the box's uniform density, the others from the Gaussian)."""
+    d = lat.d
+    lo, hi = _is_box(d, lo, hi)
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    n = np.ascontiguousarray(np.broadcast_to(np.asarray(n, dtype=np.uint64), ids.shape))
+    offset = np.ascontiguousarray(np.broadcast_to(np.asarray(offset, dtype=np.uint64), ids.shape))
+    out = np.zeros((ids.shape[0], sums_len(lat.nx)))
+    nt = nthreads or os.cpu_count() or 1
+    if lib().oracle_is_sums(C.byref(lat), seed, _ptr(lo, C.c_double), _ptr(hi, C.c_double),
+                            float(gaussian_fraction), ids.shape[0], _ptr(ids, C.c_uint64),
+                            _ptr(n, C.c_uint64),
+                            _ptr(offset, C.c_uint64), _ptr(out, C.c_double), nt) != 0:
+        raise ValueError("oracle_is_sums: invalid arguments")
+    return out
+
+
+def is_plan(budget: int, n_streams: int, gaussian_fraction: float):
+    """Streams and sample counts of one run: round(alpha * budget) samples over
+    Gaussian streams 1..n_streams and the rest over uniform streams
+    2^63 + 1 .. 2^63 + n_streams, each share split as budget_split does
+    (a component with no samples has no streams)."""
+    n_g = int(round(gaussian_fraction * budget))
+    ids, n = [], []
+    for base, total in ((0, n_g), (IS_UNIFORM_STREAM, budget - n_g)):
+        if total == 0:
+            continue
+        ids += [base + 1 + i for i in range(n_streams)]
+        n += list(budget_split(total, n_streams))
+    return np.array(ids, dtype=np.uint64), np.array(n, dtype=np.uint64)
+
+
+def integrate_is(lat: Lattice, seed: int, lo, hi, n_streams: int, budget: int,
+                 gaussian_fraction: float = 0.9, nthreads: int | None = None) -> dict:
+    """Z and C(r) by the defensive Gaussian-proposal sampler: Z = K sum W/K / N
+    over all N = budget samples, i.e. finalize with 'volumes' K n_s / N (each
+    stream's mean weighted by its share of the samples; the two components
+    count as strata of the variance)."""
+    m = is_modes(lat, lo, hi)
+    ids, n = is_plan(budget, n_streams, gaussian_fraction)
+    s = is_sums(lat, seed, lo, hi, ids, n, 0, gaussian_fraction, nthreads)
+    d = lat.d
+    vlo = np.zeros((len(ids), d))
+    vhi = np.ones((len(ids), d))
+    vhi[:, 0] = np.exp(m["log_k"]) * n / float(budget)
+    res = finalize(lat.nx, d, vlo, vhi, s)
+    res["sums"] = s
+    res["log_k"] = m["log_k"]
+    return res

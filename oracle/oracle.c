@@ -218,14 +218,17 @@ static double nm_value(const neumaier *acc) { return acc->s + acc->c; }
 typedef struct {
     const oracle_lattice *lat;
     uint64_t seed;
+    double gaussian_fraction; /* Gaussian-proposal records only */
     size_t nsub;
     const uint64_t *id;
     const double *lo, *hi;
     const uint64_t *n, *offset;
     double *out;
-    int split; /* 0: sums record, 1: split statistics */
+    int split; /* 0: sums record, 1: split statistics, 2: Gaussian-proposal record */
     int32_t nthreads, tid;
 } sums_job;
+
+static void is_stream_sums(const sums_job *job, size_t s);
 
 static void subvolume_sums(const sums_job *job, size_t s)
 {
@@ -284,14 +287,19 @@ static void subvolume_sums(const sums_job *job, size_t s)
 static void *sums_worker(void *arg)
 {
     const sums_job *job = (const sums_job *)arg;
-    for (size_t s = (size_t)job->tid; s < job->nsub; s += (size_t)job->nthreads)
-        subvolume_sums(job, s);
+    for (size_t s = (size_t)job->tid; s < job->nsub; s += (size_t)job->nthreads) {
+        if (job->split == 2)
+            is_stream_sums(job, s);
+        else
+            subvolume_sums(job, s);
+    }
     return NULL;
 }
 
 static int run_sums(const oracle_lattice *lat, uint64_t seed, size_t nsub, const uint64_t *id,
                     const double *lo, const double *hi, const uint64_t *n,
-                    const uint64_t *offset, double *out, int32_t nthreads, int split)
+                    const uint64_t *offset, double *out, int32_t nthreads, int split,
+                    double gaussian_fraction)
 {
     if (!lattice_ok(lat))
         return -1;
@@ -300,7 +308,8 @@ static int run_sums(const oracle_lattice *lat, uint64_t seed, size_t nsub, const
     if (!id || !lo || !hi || !n || !offset || !out)
         return -1;
     const int32_t d = lat->nx * lat->nt;
-    for (size_t s = 0; s < nsub; ++s)
+    const size_t rows = split == 2 ? 1 : nsub; /* one box for every stream */
+    for (size_t s = 0; s < rows; ++s)
         for (int32_t k = 0; k < d; ++k)
             if (!(lo[s * d + k] < hi[s * d + k]) || !isfinite(lo[s * d + k]) ||
                 !isfinite(hi[s * d + k]))
@@ -312,7 +321,8 @@ static int run_sums(const oracle_lattice *lat, uint64_t seed, size_t nsub, const
     sums_job *jobs = (sums_job *)calloc((size_t)nthreads, sizeof(sums_job));
     pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
     for (int32_t t = 0; t < nthreads; ++t) {
-        sums_job j = { lat, seed, nsub, id, lo, hi, n, offset, out, split, nthreads, t };
+        sums_job j = { lat,    seed, gaussian_fraction, nsub,  id,       lo, hi,
+                       n,      offset, out,           split, nthreads, t };
         jobs[t] = j;
     }
     int rc = 0;
@@ -337,14 +347,14 @@ int oracle_sums(const oracle_lattice *lat, uint64_t seed, size_t nsub, const uin
                 const double *lo, const double *hi, const uint64_t *n, const uint64_t *offset,
                 double *sums, int32_t nthreads)
 {
-    return run_sums(lat, seed, nsub, id, lo, hi, n, offset, sums, nthreads, 0);
+    return run_sums(lat, seed, nsub, id, lo, hi, n, offset, sums, nthreads, 0, 0.0);
 }
 
 int oracle_split_sums(const oracle_lattice *lat, uint64_t seed, size_t nsub, const uint64_t *id,
                       const double *lo, const double *hi, const uint64_t *n,
                       const uint64_t *offset, double *out, int32_t nthreads)
 {
-    return run_sums(lat, seed, nsub, id, lo, hi, n, offset, out, nthreads, 1);
+    return run_sums(lat, seed, nsub, id, lo, hi, n, offset, out, nthreads, 1, 0.0);
 }
 
 /* ---------------------------------------------------------------- finalize */
@@ -459,4 +469,295 @@ int oracle_nsphere(int32_t dim, uint64_t seed, uint64_t id, const double *lo, co
     out[3] = vol * mean;
     out[4] = vol * sqrt(fmax(var, 0.0) / nn);
     return 0;
+}
+
+/* ------------------------------------------- Gaussian-proposal sampling */
+/*
+ * Importance sampling of exp(-S) over a box with the Gaussian of the action's
+ * quadratic part as proposal, mixed with the uniform density of the box.
+ * Dropping the nonlinear term of Eq. Gen2 leaves S0 = u.P.u / 2 with
+ * P = A^T A / (D tau) + m2 I, A = (T - 1) - (nu tau / a^2) L, T the periodic
+ * shift in time and L the periodic second difference in space.  P is a
+ * polynomial in the shifts, so the real Fourier basis of the lattice (tensor
+ * product of the one-dimensional ones) diagonalises it.  Modes whose Gaussian
+ * would be wider than the box (lambda R^2 < 4, R the largest |u| in the box;
+ * the constant mode always, lambda = 0) are drawn uniformly over [-R, R]
+ * instead.  With a_j = <u, e_j> and z_j = a_j / scale_j the Gaussian proposal
+ * density is q_G(u) = exp(-sum_gaussian z_j^2 / 2) / K,
+ *     K = prod_uniform 2R * prod_gaussian sqrt(2 pi / lambda_j)
+ * (every point of the box has |a_j| <= R).  Defensive mixture (Hesterberg,
+ * Technometrics 1995): a fraction alpha of the samples comes from q_G, the rest
+ * from the uniform density 1/V of the box, and every sample, from either, has
+ * the weight
+ *     W(u) = 1_box(u) exp(-S(u)) / (alpha q_G(u) + (1 - alpha) / V),
+ * whose mean over all samples is Z and which is bounded by V / (1 - alpha):
+ * the Gaussian alone gives heavy-tailed weights wherever the nonlinear term
+ * cancels the linear residual, S ~ 0 where S0 is large.
+ */
+
+/* Vector b of the real orthonormal Fourier basis of period n, component m:
+ * b = 0 constant; b = 2k-1 cosine and b = 2k sine of frequency k < n/2; the
+ * last vector of an even period alternates in sign.  *k_out = frequency. */
+static double fourier_basis(int32_t n, int32_t b, int32_t m, int32_t *k_out)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    const int32_t k = (b + 1) / 2;
+    if (k_out)
+        *k_out = k;
+    if (b == 0)
+        return 1.0 / sqrt((double)n);
+    if (n % 2 == 0 && b == n - 1)
+        return ((m % 2) ? -1.0 : 1.0) / sqrt((double)n);
+    const double angle = two_pi * (double)k * (double)m / (double)n;
+    return sqrt(2.0 / (double)n) * ((b % 2) ? cos(angle) : sin(angle));
+}
+
+int oracle_is_basis(int32_t nx, int32_t nt, double *E)
+{
+    if (nx < 1 || nt < 1 || !E)
+        return -1;
+    const int32_t d = nx * nt;
+    for (int32_t bt = 0; bt < nt; ++bt)
+        for (int32_t bx = 0; bx < nx; ++bx) {
+            const int32_t j = bt * nx + bx;
+            for (int32_t l = 0; l < nt; ++l)
+                for (int32_t m = 0; m < nx; ++m)
+                    E[(size_t)(l * nx + m) * d + j] =
+                        fourier_basis(nt, bt, l, NULL) * fourier_basis(nx, bx, m, NULL);
+        }
+    return 0;
+}
+
+static int is_box_ok(int32_t d, const double *lo, const double *hi)
+{
+    for (int32_t k = 0; k < d; ++k)
+        if (!(lo[k] < hi[k]) || !isfinite(lo[k]) || !isfinite(hi[k]))
+            return 0;
+    return 1;
+}
+
+int oracle_is_modes(const oracle_lattice *lat, const double *lo, const double *hi,
+                    double *lambda, int32_t *uniform, double *scale, double *log_k)
+{
+    if (!lattice_ok(lat) || !lo || !hi || !lambda || !uniform || !scale || !log_k)
+        return -1;
+    const int32_t nx = lat->nx, nt = lat->nt, d = nx * nt;
+    if (!is_box_ok(d, lo, hi))
+        return -1;
+    const double two_pi = 6.283185307179586476925286766559;
+    const double c = lat->nu * lat->tau / (lat->a * lat->a);
+    double R2 = 0.0;
+    for (int32_t k = 0; k < d; ++k)
+        R2 += fmax(lo[k] * lo[k], hi[k] * hi[k]);
+    const double R = sqrt(R2);
+    double lk = 0.0;
+    for (int32_t bt = 0; bt < nt; ++bt)
+        for (int32_t bx = 0; bx < nx; ++bx) {
+            int32_t kt, kx;
+            fourier_basis(nt, bt, 0, &kt);
+            fourier_basis(nx, bx, 0, &kx);
+            /* eigenvalues of the periodic second differences */
+            const double mt = 2.0 * cos(two_pi * kt / nt) - 2.0;
+            const double mx = 2.0 * cos(two_pi * kx / nx) - 2.0;
+            const int32_t j = bt * nx + bx;
+            lambda[j] = (-mt - c * mt * mx + c * c * mx * mx) / (lat->D * lat->tau) + lat->m2;
+            uniform[j] = lambda[j] * R2 < 4.0;
+            if (uniform[j]) {
+                scale[j] = R;
+                lk += log(2.0 * R);
+            } else {
+                scale[j] = 1.0 / sqrt(lambda[j]);
+                lk += 0.5 * log(two_pi / lambda[j]);
+            }
+        }
+    *log_k = lk;
+    return 0;
+}
+
+/* Words per sample: Gaussian modes in mode order take Box-Muller pairs, a
+ * pair per two modes (the second normal of an odd last pair is unused); then
+ * every uniform mode takes one word. */
+static int32_t is_words(int32_t d, const int32_t *uniform)
+{
+    int32_t G = 0;
+    for (int32_t j = 0; j < d; ++j)
+        G += !uniform[j];
+    return 2 * ((G + 1) / 2) + (d - G);
+}
+
+static void is_sample(const oracle_lattice *lat, const int32_t *uniform, const double *scale,
+                      const double *E, uint64_t seed, uint64_t id, uint64_t index, uint32_t *x,
+                      double *a, double *u, double *half_z2)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    const double inv32 = 1.0 / 4294967296.0;
+    const int32_t d = lat->nx * lat->nt;
+    const int32_t W = is_words(d, uniform), nb = (W + 3) / 4;
+    for (int32_t j = 0; j < nb; ++j) {
+        const uint64_t q = index * (uint64_t)nb + (uint64_t)j;
+        const uint32_t ctr[4] = { (uint32_t)q, (uint32_t)(q >> 32), (uint32_t)id,
+                                  (uint32_t)(id >> 32) };
+        const uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+        uint32_t blk[4];
+        oracle_philox4x32_10(ctr, key, blk);
+        for (int32_t t = 0; t < 4 && 4 * j + t < W; ++t)
+            x[4 * j + t] = blk[t];
+    }
+    int32_t n_uniform = 0;
+    for (int32_t j = 0; j < d; ++j)
+        n_uniform += uniform[j] != 0;
+    /* the uniform modes' words follow the Box-Muller pairs */
+    int32_t g = 0, next_uniform_word = W - n_uniform;
+    double hz = 0.0, z_pair[2] = { 0.0, 0.0 };
+    for (int32_t j = 0; j < d; ++j) {
+        if (uniform[j]) {
+            /* uniform over [-R, R]: the word's cell centre */
+            const double v = ((double)x[next_uniform_word++] + 0.5) * inv32;
+            a[j] = scale[j] * (2.0 * v - 1.0);
+            continue;
+        }
+        if (g % 2 == 0) {
+            /* Box-Muller: radius from the first word, angle from the second */
+            const double u1 = ((double)x[g] + 0.5) * inv32;
+            const double u2 = ((double)x[g + 1] + 0.5) * inv32;
+            const double r = sqrt(-2.0 * log(u1));
+            z_pair[0] = r * cos(two_pi * u2);
+            z_pair[1] = r * sin(two_pi * u2);
+        }
+        const double z = z_pair[g % 2];
+        a[j] = scale[j] * z;
+        hz += 0.5 * z * z;
+        ++g;
+    }
+    for (int32_t k = 0; k < d; ++k) {
+        double v = 0.0;
+        for (int32_t j = 0; j < d; ++j)
+            v += E[(size_t)k * d + j] * a[j];
+        u[k] = v;
+    }
+    *half_z2 = hz;
+}
+
+int oracle_is_point(const oracle_lattice *lat, const double *lo, const double *hi, uint64_t seed,
+                    uint64_t id, uint64_t index, double *u, double *half_z2)
+{
+    if (!lattice_ok(lat) || !u || !half_z2)
+        return -1;
+    const int32_t d = lat->nx * lat->nt;
+    double *lambda = (double *)malloc(sizeof(double) * (size_t)d * 3);
+    int32_t *uniform = (int32_t *)malloc(sizeof(int32_t) * (size_t)d);
+    double *E = (double *)malloc(sizeof(double) * (size_t)d * (size_t)d);
+    uint32_t *x = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(2 * d + 4));
+    double lk;
+    /* lambda: [eigenvalues (d), scales (d), coefficients (d)] */
+    int rc = oracle_is_modes(lat, lo, hi, lambda, uniform, lambda + d, &lk);
+    if (rc == 0) {
+        oracle_is_basis(lat->nx, lat->nt, E);
+        is_sample(lat, uniform, lambda + d, E, seed, id, index, x, lambda + 2 * d, u, half_z2);
+    }
+    free(lambda);
+    free(uniform);
+    free(E);
+    free(x);
+    return rc;
+}
+
+/* Stream ids with the top bit set draw from the box's uniform density (the
+ * same point map as the plain sampler), the others from the Gaussian. */
+#define ORACLE_IS_UNIFORM_STREAM (UINT64_C(1) << 63)
+
+static void is_stream_sums(const sums_job *job, size_t s)
+{
+    const oracle_lattice *lat = job->lat;
+    const int32_t nx = lat->nx, d = lat->nx * lat->nt;
+    double *lambda = (double *)malloc(sizeof(double) * (size_t)d);
+    double *scale = (double *)malloc(sizeof(double) * (size_t)d);
+    int32_t *uniform = (int32_t *)malloc(sizeof(int32_t) * (size_t)d);
+    double *E = (double *)malloc(sizeof(double) * (size_t)d * (size_t)d);
+    uint32_t *x = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(2 * d + 4));
+    double *a = (double *)malloc(sizeof(double) * (size_t)d);
+    double *u = (double *)malloc(sizeof(double) * (size_t)d);
+    double *p = (double *)malloc(sizeof(double) * (size_t)nx);
+    double *mscale = (double *)malloc(sizeof(double) * (size_t)d);
+    double *mbase = (double *)malloc(sizeof(double) * (size_t)d);
+    double lk;
+    oracle_is_modes(lat, job->lo, job->hi, lambda, uniform, scale, &lk);
+    oracle_is_basis(nx, lat->nt, E);
+    box_map(d, job->lo, job->hi, mscale, mbase);
+    double log_v = 0.0;
+    for (int32_t k = 0; k < d; ++k)
+        log_v += log(job->hi[k] - job->lo[k]);
+    /* log of the mixture density times K: log(alpha e^{-hz} + (1 - alpha) K / V) */
+    const double alpha = job->gaussian_fraction;
+    const double log_ga = alpha > 0.0 ? log(alpha) : -INFINITY;
+    const double log_un = alpha < 1.0 ? log(1.0 - alpha) + lk - log_v : -INFINITY;
+    const int from_uniform = (job->id[s] & ORACLE_IS_UNIFORM_STREAM) != 0;
+
+    const int32_t len = ORACLE_SUMS_LEN(nx);
+    neumaier *acc = (neumaier *)calloc((size_t)len, sizeof(neumaier));
+    const uint64_t first = job->offset[s], count = job->n[s];
+    for (uint64_t i = 0; i < count; ++i) {
+        double hz = 0.0;
+        if (from_uniform) {
+            oracle_words(d, job->seed, job->id[s], first + i, x);
+            for (int32_t k = 0; k < d; ++k)
+                u[k] = fma((double)x[k], mscale[k], mbase[k]);
+            /* the Gaussian exponent of this point: coefficients along the modes */
+            for (int32_t j = 0; j < d; ++j) {
+                if (uniform[j])
+                    continue;
+                double aj = 0.0;
+                for (int32_t k = 0; k < d; ++k)
+                    aj += E[(size_t)k * d + j] * u[k];
+                const double z = aj / scale[j];
+                hz += 0.5 * z * z;
+            }
+        } else {
+            is_sample(lat, uniform, scale, E, job->seed, job->id[s], first + i, x, a, u, &hz);
+        }
+        int inside = 1;
+        for (int32_t k = 0; k < d; ++k)
+            inside &= job->lo[k] <= u[k] && u[k] <= job->hi[k];
+        double w = 0.0;
+        if (inside) {
+            const double g1 = log_ga - hz, g2 = log_un;
+            const double mx = fmax(g1, g2);
+            const double log_mix = mx + log(exp(g1 - mx) + exp(g2 - mx));
+            w = exp(-oracle_action(lat, u) - log_mix);
+        }
+        oracle_observable(lat, u, p);
+        nm_add(&acc[0], 1.0);
+        nm_add(&acc[1], w);
+        nm_add(&acc[2], w * w);
+        for (int32_t r = 0; r < nx; ++r) {
+            const double pw = p[r] * w;
+            nm_add(&acc[3 + r], pw);
+            nm_add(&acc[3 + nx + r], pw * pw);
+            nm_add(&acc[3 + 2 * nx + r], pw * w);
+        }
+    }
+    double *out = job->out + s * (size_t)len;
+    for (int32_t t = 0; t < len; ++t)
+        out[t] = nm_value(&acc[t]);
+    free(acc);
+    free(lambda);
+    free(scale);
+    free(uniform);
+    free(E);
+    free(x);
+    free(a);
+    free(u);
+    free(p);
+    free(mscale);
+    free(mbase);
+}
+
+int oracle_is_sums(const oracle_lattice *lat, uint64_t seed, const double *lo, const double *hi,
+                   double gaussian_fraction, size_t nstream, const uint64_t *id, const uint64_t *n,
+                   const uint64_t *offset, double *sums, int32_t nthreads)
+{
+    if (!(gaussian_fraction >= 0.0 && gaussian_fraction <= 1.0))
+        return -1;
+    return run_sums(lat, seed, nstream, id, lo, hi, n, offset, sums, nthreads, 2,
+                    gaussian_fraction);
 }

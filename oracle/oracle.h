@@ -104,6 +104,43 @@ int oracle_finalize(int32_t nx, int32_t d, size_t nsub, const double *lo, const 
 int oracle_plan_uniform(int32_t d, const double *box_lo, const double *box_hi, int32_t k,
                         uint64_t *id, double *lo, double *hi);
 
+/* Gaussian-proposal importance sampling of exp(-S) over one box.
+ *
+ * Proposal: the Gaussian of the action's quadratic part S0 = u.P.u/2 (the
+ * nonlinear term dropped), P = A^T A/(D tau) + m2 I with A = (T - 1) -
+ * (nu tau/a^2) L, diagonal in the real Fourier basis of the lattice; modes with
+ * lambda R^2 < 4 (R = the largest |u| in the box) are uniform over [-R, R].
+ * Defensive mixture: a fraction alpha (gaussian_fraction) of the samples comes
+ * from it and the rest from the uniform density 1/V of the box; every sample
+ * has the weight W = 1_box(u) exp(-S(u)) / (alpha q_G(u) + (1 - alpha)/V) with
+ * q_G(u) = exp(-sum z^2/2)/K, so W <= V/(1 - alpha) and the mean of W is Z.
+ *
+ * oracle_is_basis: the d x d orthonormal basis E (row = lattice variable
+ *   k = l*nx + m, column = mode j = bt*nx + bx; column j is the product of the
+ *   time vector bt and the space vector bx; vector b of period n: 0 constant,
+ *   2k-1 cosine and 2k sine of frequency k < n/2, n-1 alternating for even n).
+ * oracle_is_modes: per mode the eigenvalue lambda_j of P, whether it is drawn
+ *   uniformly, its scale (1/sqrt(lambda) for Gaussian modes, R for uniform
+ *   ones), and log K = sum_uniform log 2R + sum_gaussian log sqrt(2 pi/lambda).
+ * oracle_is_point: sample `index` of stream `id`.  Words come from Philox4x32-10
+ *   with counter (lo32(q), hi32(q), lo32(id), hi32(id)), q = index*ceil(W/4) + j,
+ *   key = seed: Gaussian modes in mode order take Box-Muller pairs of words
+ *   (radius sqrt(-2 ln u1), angle 2 pi u2, u = (x + 1/2) 2^-32), uniform modes
+ *   one word each after the pairs.  *half_z2 = sum over Gaussian modes z^2/2.
+ * oracle_is_sums: per stream the sums record of W/K (n, sum w, ...) over
+ *   samples offset .. offset+n-1, one box lo/hi (d each) for every stream.
+ *   Streams whose id has bit 63 set draw from the uniform density with the
+ *   plain sampler's words and point map (oracle_point); the others from the
+ *   Gaussian (oracle_is_point).  Returns -1 unless 0 <= gaussian_fraction <= 1. */
+int oracle_is_basis(int32_t nx, int32_t nt, double *E);
+int oracle_is_modes(const oracle_lattice *lat, const double *lo, const double *hi,
+                    double *lambda, int32_t *uniform, double *scale, double *log_k);
+int oracle_is_point(const oracle_lattice *lat, const double *lo, const double *hi, uint64_t seed,
+                    uint64_t id, uint64_t index, double *u, double *half_z2);
+int oracle_is_sums(const oracle_lattice *lat, uint64_t seed, const double *lo, const double *hi,
+                   double gaussian_fraction, size_t nstream, const uint64_t *id, const uint64_t *n,
+                   const uint64_t *offset, double *sums, int32_t nthreads);
+
 /* Plain Monte Carlo of the N-sphere integrand f(x) = sqrt(1 - |x|^2) (0 outside
  * the unit ball) over a box: out = [n, sum f, sum f^2, result, abserr]. */
 int oracle_nsphere(int32_t dim, uint64_t seed, uint64_t id, const double *lo, const double *hi,
