@@ -495,6 +495,9 @@ int oracle_nsphere(int32_t dim, uint64_t seed, uint64_t id, const double *lo, co
  * cancels the linear residual, S ~ 0 where S0 is large.
  */
 
+/* Modes drawn uniformly at most (their words follow the Box-Muller pairs). */
+#define ORACLE_IS_MAX_UNIFORM 4
+
 /* Vector b of the real orthonormal Fourier basis of period n, component m:
  * b = 0 constant; b = 2k-1 cosine and b = 2k sine of frequency k < n/2; the
  * last vector of an even period alternates in sign.  *k_out = frequency. */
@@ -571,19 +574,18 @@ int oracle_is_modes(const oracle_lattice *lat, const double *lo, const double *h
             }
         }
     *log_k = lk;
-    return 0;
+    int32_t n_uniform = 0;
+    for (int32_t j = 0; j < d; ++j)
+        n_uniform += uniform[j] != 0;
+    return n_uniform <= ORACLE_IS_MAX_UNIFORM ? 0 : -2;
 }
 
-/* Words per sample: Gaussian modes in mode order take Box-Muller pairs, a
- * pair per two modes (the second normal of an odd last pair is unused); then
- * every uniform mode takes one word. */
-static int32_t is_words(int32_t d, const int32_t *uniform)
-{
-    int32_t G = 0;
-    for (int32_t j = 0; j < d; ++j)
-        G += !uniform[j];
-    return 2 * ((G + 1) / 2) + (d - G);
-}
+/* Words per sample: mode j's normal comes from the Box-Muller pair of words
+ * (2 floor(j/2), 2 floor(j/2) + 1), cosine for even j and sine for odd j, so
+ * the pairs take 2 ceil(d/2) words; then ORACLE_IS_MAX_UNIFORM words, the k-th
+ * uniform mode (in mode order) taking word 2 ceil(d/2) + k.  A uniform mode's
+ * normal is drawn and not used. */
+static int32_t is_words(int32_t d) { return 2 * ((d + 1) / 2) + ORACLE_IS_MAX_UNIFORM; }
 
 static void is_sample(const oracle_lattice *lat, const int32_t *uniform, const double *scale,
                       const double *E, uint64_t seed, uint64_t id, uint64_t index, uint32_t *x,
@@ -592,7 +594,7 @@ static void is_sample(const oracle_lattice *lat, const int32_t *uniform, const d
     const double two_pi = 6.283185307179586476925286766559;
     const double inv32 = 1.0 / 4294967296.0;
     const int32_t d = lat->nx * lat->nt;
-    const int32_t W = is_words(d, uniform), nb = (W + 3) / 4;
+    const int32_t W = is_words(d), nb = (W + 3) / 4;
     for (int32_t j = 0; j < nb; ++j) {
         const uint64_t q = index * (uint64_t)nb + (uint64_t)j;
         const uint32_t ctr[4] = { (uint32_t)q, (uint32_t)(q >> 32), (uint32_t)id,
@@ -603,31 +605,27 @@ static void is_sample(const oracle_lattice *lat, const int32_t *uniform, const d
         for (int32_t t = 0; t < 4 && 4 * j + t < W; ++t)
             x[4 * j + t] = blk[t];
     }
-    int32_t n_uniform = 0;
-    for (int32_t j = 0; j < d; ++j)
-        n_uniform += uniform[j] != 0;
     /* the uniform modes' words follow the Box-Muller pairs */
-    int32_t g = 0, next_uniform_word = W - n_uniform;
+    int32_t next_uniform_word = 2 * ((d + 1) / 2);
     double hz = 0.0, z_pair[2] = { 0.0, 0.0 };
     for (int32_t j = 0; j < d; ++j) {
+        if (j % 2 == 0) {
+            /* Box-Muller: radius from the first word, angle from the second */
+            const double u1 = ((double)x[j] + 0.5) * inv32;
+            const double u2 = ((double)x[j + 1] + 0.5) * inv32;
+            const double r = sqrt(-2.0 * log(u1));
+            z_pair[0] = r * cos(two_pi * u2);
+            z_pair[1] = r * sin(two_pi * u2);
+        }
         if (uniform[j]) {
             /* uniform over [-R, R]: the word's cell centre */
             const double v = ((double)x[next_uniform_word++] + 0.5) * inv32;
             a[j] = scale[j] * (2.0 * v - 1.0);
             continue;
         }
-        if (g % 2 == 0) {
-            /* Box-Muller: radius from the first word, angle from the second */
-            const double u1 = ((double)x[g] + 0.5) * inv32;
-            const double u2 = ((double)x[g + 1] + 0.5) * inv32;
-            const double r = sqrt(-2.0 * log(u1));
-            z_pair[0] = r * cos(two_pi * u2);
-            z_pair[1] = r * sin(two_pi * u2);
-        }
-        const double z = z_pair[g % 2];
+        const double z = z_pair[j % 2];
         a[j] = scale[j] * z;
         hz += 0.5 * z * z;
-        ++g;
     }
     for (int32_t k = 0; k < d; ++k) {
         double v = 0.0;
@@ -647,7 +645,7 @@ int oracle_is_point(const oracle_lattice *lat, const double *lo, const double *h
     double *lambda = (double *)malloc(sizeof(double) * (size_t)d * 3);
     int32_t *uniform = (int32_t *)malloc(sizeof(int32_t) * (size_t)d);
     double *E = (double *)malloc(sizeof(double) * (size_t)d * (size_t)d);
-    uint32_t *x = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(2 * d + 4));
+    uint32_t *x = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(d + 12));
     double lk;
     /* lambda: [eigenvalues (d), scales (d), coefficients (d)] */
     int rc = oracle_is_modes(lat, lo, hi, lambda, uniform, lambda + d, &lk);
@@ -674,7 +672,7 @@ static void is_stream_sums(const sums_job *job, size_t s)
     double *scale = (double *)malloc(sizeof(double) * (size_t)d);
     int32_t *uniform = (int32_t *)malloc(sizeof(int32_t) * (size_t)d);
     double *E = (double *)malloc(sizeof(double) * (size_t)d * (size_t)d);
-    uint32_t *x = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(2 * d + 4));
+    uint32_t *x = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(d + 12));
     double *a = (double *)malloc(sizeof(double) * (size_t)d);
     double *u = (double *)malloc(sizeof(double) * (size_t)d);
     double *p = (double *)malloc(sizeof(double) * (size_t)nx);

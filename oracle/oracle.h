@@ -122,11 +122,15 @@ int oracle_plan_uniform(int32_t d, const double *box_lo, const double *box_hi, i
  * oracle_is_modes: per mode the eigenvalue lambda_j of P, whether it is drawn
  *   uniformly, its scale (1/sqrt(lambda) for Gaussian modes, R for uniform
  *   ones), and log K = sum_uniform log 2R + sum_gaussian log sqrt(2 pi/lambda).
+ *   Returns -2 when more than 4 modes would be uniform (the box is then too
+ *   small for the Gaussian to be of use).
  * oracle_is_point: sample `index` of stream `id`.  Words come from Philox4x32-10
  *   with counter (lo32(q), hi32(q), lo32(id), hi32(id)), q = index*ceil(W/4) + j,
- *   key = seed: Gaussian modes in mode order take Box-Muller pairs of words
- *   (radius sqrt(-2 ln u1), angle 2 pi u2, u = (x + 1/2) 2^-32), uniform modes
- *   one word each after the pairs.  *half_z2 = sum over Gaussian modes z^2/2.
+ *   key = seed, W = 2 ceil(d/2) + 4 words: mode j's normal is the cosine (j
+ *   even) or sine (j odd) of the Box-Muller pair of words 2 floor(j/2) and
+ *   2 floor(j/2) + 1 (radius sqrt(-2 ln u1), angle 2 pi u2, u = (x + 1/2) 2^-32);
+ *   the k-th uniform mode takes word 2 ceil(d/2) + k.  *half_z2 = sum over
+ *   Gaussian modes of z^2/2.
  * oracle_is_sums: per stream the sums record of W/K (n, sum w, ...) over
  *   samples offset .. offset+n-1, one box lo/hi (d each) for every stream.
  *   Streams whose id has bit 63 set draw from the uniform density with the

@@ -145,9 +145,10 @@ def test_rejects_bad_boxes(oracle_lib):
 
 def test_mixture_pins(oracle_lib):
     """alpha = 0 is the plain uniform sampler on the same points; alpha < 1
-    bounds the weights by V/(1 - alpha) (so sum W^2 <= bound * sum W); the
-    Gaussian alone (alpha = 1) misses the quadrature value where the nonlinear
-    term can cancel the residual (3x1, nu = 1/2, box [-4, 4])."""
+    bounds the weights by V/(1 - alpha) (so sum W^2 <= bound * sum W), and the
+    mixture matches quadrature on 3x1, nu = 1/2, box [-4, 4], where the nonlinear
+    term can cancel the residual and the Gaussian alone has heavy-tailed weights
+    (depending on the seed, a biased Z or an error bar blown up by one sample)."""
     from test_oracle_estimator import _gauss_legendre_box
     nx, nt, B, nu = 3, 1, 4.0, 0.5
     d = nx * nt
@@ -167,9 +168,8 @@ def test_mixture_pins(oracle_lib):
     ids, n = oracle.is_plan(1 << 16, 4, alpha)
     s = oracle.is_sums(lat, 6, -B, B, ids, n, 0, alpha)
     assert np.all(s[:, 2] <= bound * s[:, 1] * (1 + 1e-12))
-    # the Gaussian alone is biased here; the mixture is not
     Zq, _ = _gauss_legendre_box(lat, B, 8)
-    pure = oracle.integrate_is(lat, 4, -B, B, 8, 1 << 19, gaussian_fraction=1.0)
-    mixed = oracle.integrate_is(lat, 4, -B, B, 8, 1 << 19, gaussian_fraction=alpha)
-    assert abs(pure["Z"] - Zq) > 5 * pure["Z_err"]
-    assert abs(mixed["Z"] - Zq) < 4 * mixed["Z_err"]
+    for seed in (4, 5):
+        mixed = oracle.integrate_is(lat, seed, -B, B, 8, 1 << 19, gaussian_fraction=alpha)
+        assert abs(mixed["Z"] - Zq) < 4 * mixed["Z_err"]
+        assert mixed["Z_err"] < 0.02 * Zq
