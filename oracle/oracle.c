@@ -479,13 +479,16 @@ int oracle_nsphere(int32_t dim, uint64_t seed, uint64_t id, const double *lo, co
  * P = A^T A / (D tau) + m2 I, A = (T - 1) - (nu tau / a^2) L, T the periodic
  * shift in time and L the periodic second difference in space.  P is a
  * polynomial in the shifts, so the real Fourier basis of the lattice (tensor
- * product of the one-dimensional ones) diagonalises it.  Modes whose Gaussian
- * would be wider than the box (lambda R^2 < 4, R the largest |u| in the box;
- * the constant mode always, lambda = 0) are drawn uniformly over [-R, R]
- * instead.  With a_j = <u, e_j> and z_j = a_j / scale_j the Gaussian proposal
- * density is q_G(u) = exp(-sum_gaussian z_j^2 / 2) / K,
- *     K = prod_uniform 2R * prod_gaussian sqrt(2 pi / lambda_j)
- * (every point of the box has |a_j| <= R).  Defensive mixture (Hesterberg,
+ * product of the one-dimensional ones) diagonalises it.  The constant mode
+ * (lambda = m2, 0 in the paper) is drawn uniformly over [-R, R] when its
+ * Gaussian would be wider than the box (lambda R^2 < 4, R the largest |u| in
+ * the box); every other mode is Gaussian with standard deviation
+ * scale_j = min(1/sqrt(lambda_j), R) (a mode with lambda near 0, such as the
+ * checkerboard at nu tau / a^2 = 1/2, gets the box's width).  With a_j = <u, e_j>
+ * and z_j = a_j / scale_j the Gaussian proposal density is
+ *     q_G(u) = exp(-sum_gaussian z_j^2 / 2) / K,
+ *     K = (2R if the constant mode is uniform) * prod_gaussian sqrt(2 pi) scale_j
+ * (every point of the box has |a_0| <= R).  Defensive mixture (Hesterberg,
  * Technometrics 1995): a fraction alpha of the samples comes from q_G, the rest
  * from the uniform density 1/V of the box, and every sample, from either, has
  * the weight
@@ -494,9 +497,6 @@ int oracle_nsphere(int32_t dim, uint64_t seed, uint64_t id, const double *lo, co
  * the Gaussian alone gives heavy-tailed weights wherever the nonlinear term
  * cancels the linear residual, S ~ 0 where S0 is large.
  */
-
-/* Modes drawn uniformly at most (their words follow the Box-Muller pairs). */
-#define ORACLE_IS_MAX_UNIFORM 4
 
 /* Vector b of the real orthonormal Fourier basis of period n, component m:
  * b = 0 constant; b = 2k-1 cosine and b = 2k sine of frequency k < n/2; the
@@ -564,28 +564,24 @@ int oracle_is_modes(const oracle_lattice *lat, const double *lo, const double *h
             const double mx = 2.0 * cos(two_pi * kx / nx) - 2.0;
             const int32_t j = bt * nx + bx;
             lambda[j] = (-mt - c * mt * mx + c * c * mx * mx) / (lat->D * lat->tau) + lat->m2;
-            uniform[j] = lambda[j] * R2 < 4.0;
+            uniform[j] = j == 0 && lambda[j] * R2 < 4.0;
             if (uniform[j]) {
                 scale[j] = R;
                 lk += log(2.0 * R);
             } else {
-                scale[j] = 1.0 / sqrt(lambda[j]);
-                lk += 0.5 * log(two_pi / lambda[j]);
+                scale[j] = lambda[j] * R2 <= 1.0 ? R : 1.0 / sqrt(lambda[j]);
+                lk += 0.5 * log(two_pi) + log(scale[j]);
             }
         }
     *log_k = lk;
-    int32_t n_uniform = 0;
-    for (int32_t j = 0; j < d; ++j)
-        n_uniform += uniform[j] != 0;
-    return n_uniform <= ORACLE_IS_MAX_UNIFORM ? 0 : -2;
+    return 0;
 }
 
 /* Words per sample: mode j's normal comes from the Box-Muller pair of words
  * (2 floor(j/2), 2 floor(j/2) + 1), cosine for even j and sine for odd j, so
- * the pairs take 2 ceil(d/2) words; then ORACLE_IS_MAX_UNIFORM words, the k-th
- * uniform mode (in mode order) taking word 2 ceil(d/2) + k.  A uniform mode's
- * normal is drawn and not used. */
-static int32_t is_words(int32_t d) { return 2 * ((d + 1) / 2) + ORACLE_IS_MAX_UNIFORM; }
+ * the pairs take 2 ceil(d/2) words; the next word is the uniform constant
+ * mode's (whose normal is then drawn and not used). */
+static int32_t is_words(int32_t d) { return 2 * ((d + 1) / 2) + 1; }
 
 static void is_sample(const oracle_lattice *lat, const int32_t *uniform, const double *scale,
                       const double *E, uint64_t seed, uint64_t id, uint64_t index, uint32_t *x,
@@ -605,8 +601,6 @@ static void is_sample(const oracle_lattice *lat, const int32_t *uniform, const d
         for (int32_t t = 0; t < 4 && 4 * j + t < W; ++t)
             x[4 * j + t] = blk[t];
     }
-    /* the uniform modes' words follow the Box-Muller pairs */
-    int32_t next_uniform_word = 2 * ((d + 1) / 2);
     double hz = 0.0, z_pair[2] = { 0.0, 0.0 };
     for (int32_t j = 0; j < d; ++j) {
         if (j % 2 == 0) {
@@ -619,7 +613,7 @@ static void is_sample(const oracle_lattice *lat, const int32_t *uniform, const d
         }
         if (uniform[j]) {
             /* uniform over [-R, R]: the word's cell centre */
-            const double v = ((double)x[next_uniform_word++] + 0.5) * inv32;
+            const double v = ((double)x[2 * ((d + 1) / 2)] + 0.5) * inv32;
             a[j] = scale[j] * (2.0 * v - 1.0);
             continue;
         }

@@ -108,8 +108,10 @@ int oracle_plan_uniform(int32_t d, const double *box_lo, const double *box_hi, i
  *
  * Proposal: the Gaussian of the action's quadratic part S0 = u.P.u/2 (the
  * nonlinear term dropped), P = A^T A/(D tau) + m2 I with A = (T - 1) -
- * (nu tau/a^2) L, diagonal in the real Fourier basis of the lattice; modes with
- * lambda R^2 < 4 (R = the largest |u| in the box) are uniform over [-R, R].
+ * (nu tau/a^2) L, diagonal in the real Fourier basis of the lattice; the
+ * constant mode is uniform over [-R, R] when lambda_0 R^2 < 4 (R = the largest
+ * |u| in the box), every other mode Gaussian with standard deviation
+ * min(1/sqrt(lambda), R).
  * Defensive mixture: a fraction alpha (gaussian_fraction) of the samples comes
  * from it and the rest from the uniform density 1/V of the box; every sample
  * has the weight W = 1_box(u) exp(-S(u)) / (alpha q_G(u) + (1 - alpha)/V) with
@@ -120,16 +122,15 @@ int oracle_plan_uniform(int32_t d, const double *box_lo, const double *box_hi, i
  *   time vector bt and the space vector bx; vector b of period n: 0 constant,
  *   2k-1 cosine and 2k sine of frequency k < n/2, n-1 alternating for even n).
  * oracle_is_modes: per mode the eigenvalue lambda_j of P, whether it is drawn
- *   uniformly, its scale (1/sqrt(lambda) for Gaussian modes, R for uniform
- *   ones), and log K = sum_uniform log 2R + sum_gaussian log sqrt(2 pi/lambda).
- *   Returns -2 when more than 4 modes would be uniform (the box is then too
- *   small for the Gaussian to be of use).
+ *   uniformly (only the constant mode j = 0 can be), its scale (R for the
+ *   uniform mode, min(1/sqrt(lambda), R) for Gaussian ones), and
+ *   log K = (log 2R if mode 0 is uniform) + sum_gaussian log(sqrt(2 pi) scale).
  * oracle_is_point: sample `index` of stream `id`.  Words come from Philox4x32-10
  *   with counter (lo32(q), hi32(q), lo32(id), hi32(id)), q = index*ceil(W/4) + j,
- *   key = seed, W = 2 ceil(d/2) + 4 words: mode j's normal is the cosine (j
+ *   key = seed, W = 2 ceil(d/2) + 1 words: mode j's normal is the cosine (j
  *   even) or sine (j odd) of the Box-Muller pair of words 2 floor(j/2) and
  *   2 floor(j/2) + 1 (radius sqrt(-2 ln u1), angle 2 pi u2, u = (x + 1/2) 2^-32);
- *   the k-th uniform mode takes word 2 ceil(d/2) + k.  *half_z2 = sum over
+ *   a uniform constant mode takes word 2 ceil(d/2).  *half_z2 = sum over
  *   Gaussian modes of z^2/2.
  * oracle_is_sums: per stream the sums record of W/K (n, sum w, ...) over
  *   samples offset .. offset+n-1, one box lo/hi (d each) for every stream.

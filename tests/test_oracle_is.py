@@ -4,14 +4,14 @@ box).  Nothing here comes from the sampler itself:
 
   * the basis is orthonormal and diagonalises P = A^T A/(D tau) + m2 I built
     from periodic shift matrices, with the eigenvalues the mode table reports;
-  * coefficients along Gaussian modes have variance 1/lambda, along uniform
-    modes R^2/3; Box-Muller normals pass a Kolmogorov-Smirnov test; the
+  * coefficients along Gaussian modes have variance min(1/lambda, R^2), along
+    the uniform constant mode R^2/3; Box-Muller normals pass a Kolmogorov-Smirnov test; the
     reported sum z^2/2 equals sum lambda a^2/2 over the Gaussian modes;
   * g = 0 with every mode Gaussian: every in-box weight is exp(0) = 1, and Z is
     the Gaussian integral (2 pi)^(d/2) / sqrt(det P) with C(r) = (P^-1)_{0r};
   * g = 1: Z and C(r) agree with tensor-product quadrature on tiny lattices and
     with the plain uniform estimator on 4x2 (also at nu = 1/2, where the
-    checkerboard mode of an even lattice has lambda = 0 and is drawn uniformly);
+    checkerboard mode of an even lattice has lambda = 0 and gets the box's width);
   * on the 10x2 workload box the effective sample size per point is far above
     the uniform sampler's."""
 import math
@@ -50,16 +50,21 @@ def test_mode_table(oracle_lib):
     m = oracle.is_modes(lat, -B, B)
     R = B * math.sqrt(20)
     lam = m["lambda"]
-    np.testing.assert_array_equal(m["uniform"], lam * R * R < 4)
     assert m["uniform"][0] and m["uniform"].sum() == 1       # only the constant mode
     g = ~m["uniform"]
-    np.testing.assert_allclose(m["scale"][g], 1 / np.sqrt(lam[g]))
-    assert np.all(m["scale"][~g] == R)
-    assert m["log_k"] == pytest.approx(np.log(2 * R) + np.sum(0.5 * np.log(2 * np.pi / lam[g])))
-    # nu = 1/2 on an even lattice: the checkerboard (-1)^(l+m) is a null mode too
+    np.testing.assert_allclose(m["scale"][g], np.minimum(1 / np.sqrt(lam[g]), R))
+    assert m["scale"][0] == R
+    assert m["log_k"] == pytest.approx(np.log(2 * R) + np.sum(np.log(np.sqrt(2 * np.pi) *
+                                                                     m["scale"][g])))
+    # nu = 1/2 on an even lattice: the checkerboard (-1)^(l+m) is a null mode
+    # too; it stays Gaussian with the box's width
     m2 = oracle.is_modes(oracle.lattice(4, 2, nu=0.5), -2.0, 2.0)
     j = 1 * 4 + 3                     # time Nyquist x space Nyquist
-    assert m2["lambda"][j] == pytest.approx(0.0, abs=1e-14) and m2["uniform"][j]
+    assert m2["lambda"][j] == pytest.approx(0.0, abs=1e-14) and not m2["uniform"][j]
+    assert m2["scale"][j] == pytest.approx(2.0 * math.sqrt(8))
+    # m2 > 0 with a wide box: the constant mode is Gaussian as well
+    m3 = oracle.is_modes(oracle.lattice(3, 2, m2=1.0), -6.0, 6.0)
+    assert not m3["uniform"].any()
 
 
 def test_sampler_moments_and_normality(oracle_lib):
@@ -76,12 +81,12 @@ def test_sampler_moments_and_normality(oracle_lib):
     A = U @ E                                 # coefficients along the modes
     g = ~m["uniform"]
     var = A.var(axis=0)
-    np.testing.assert_allclose(var[g], 1 / m["lambda"][g], rtol=0.08)
+    np.testing.assert_allclose(var[g], m["scale"][g] ** 2, rtol=0.08)
     R = B * math.sqrt(8)
     np.testing.assert_allclose(var[~g], R * R / 3, rtol=0.08)
     assert np.all(np.abs(A[:, ~g]) <= R)
-    np.testing.assert_allclose(HZ, 0.5 * (A[:, g] ** 2 * m["lambda"][g]).sum(1), rtol=1e-10)
-    Z = A[:, g] * np.sqrt(m["lambda"][g])
+    np.testing.assert_allclose(HZ, 0.5 * (A[:, g] ** 2 / m["scale"][g] ** 2).sum(1), rtol=1e-10)
+    Z = A[:, g] / m["scale"][g]
     for j in range(Z.shape[1]):
         assert stats.kstest(Z[:, j], "norm").pvalue > 1e-3
     c = np.corrcoef(Z.T)
