@@ -317,6 +317,66 @@ bfi_status bfi_integrate_hdi(bfi_context *ctx, const bfi_integrand *f, uint64_t 
                              const bfi_hdi_config *cfg, const bfi_launch *launch, double *result,
                              double *abserr, bfi_hdi_stats *stats);
 
+/* Gaussian-proposal importance sampling over a cube [box_lo, box_hi]^d, an
+ * extension beyond the paper's plain sampler (d <= 32).
+ *
+ * Dropping the nonlinear term of Eq. Gen2 leaves S0 = u.P.u/2 with
+ * P = A^T A/(D tau) + m2 I, A = (T - 1) - (nu tau/a^2) L (T the periodic time
+ * shift, L the periodic second difference in space), diagonal in the real
+ * Fourier basis of the lattice: mode j = bt*nx + bx is the product of time
+ * vector bt and space vector bx (vector b of period n: 0 constant, 2k-1 cosine
+ * and 2k sine of frequency k < n/2, n-1 alternating for even n, normalised),
+ * with eigenvalue lambda_j = (-mt - c mt mx + c^2 mx^2)/(D tau) + m2,
+ * c = nu tau/a^2, mt = 2 cos(2 pi kt/nt) - 2, mx = 2 cos(2 pi kx/nx) - 2.
+ * Proposal: a_j = scale_j z_j, z_j standard normal by Box-Muller,
+ * scale_j = min(1/sqrt(lambda_j), R), R = sqrt(d) max(|box_lo|, |box_hi|);
+ * the constant mode is instead uniform over [-R, R] when lambda_0 R^2 < 4.
+ * A fraction alpha (gaussian_fraction) of the samples comes from it and the
+ * rest from the cube's uniform density 1/V (a defensive mixture: the Gaussian
+ * alone has heavy-tailed weights where the nonlinear term cancels the linear
+ * residual); every sample of either component weighs
+ *     W = K exp(-S) / (alpha exp(-sum_gaussian z^2/2) + (1 - alpha) K/V) <= V/(1 - alpha),
+ *     K = (2R if mode 0 is uniform) * prod_gaussian sqrt(2 pi) scale_j,
+ * and Z is the mean of W over all samples, C(r) the W-weighted mean of p_r.
+ *
+ * Streams: stream id s keys Philox as a subvolume id does.  Ids with bit 63
+ * set draw from the uniform component with the plain sampler's words and point
+ * map over the cube; the others from the Gaussian: sample i takes
+ * ceil((2 ceil(d/2) + 1)/4) Philox blocks, q = i*blocks + j; mode j's normal is
+ * the cosine (j even) or sine (j odd) of the Box-Muller pair of words
+ * 2 floor(j/2), 2 floor(j/2) + 1 (radius sqrt(-2 ln u1), angle 2 pi u2,
+ * u = (x + 1/2) 2^-32); a uniform constant mode takes word 2 ceil(d/2).
+ * BFI_FP32_SHIFTED computes the normals with the hardware log2, square root and
+ * sine/cosine, the transforms, action and weight in FP32; sums are FP64.
+ *
+ * bfi_is_modes: the mode table (d entries each; uniform[j] = 1 for a uniform
+ *   constant mode) and log K.  Host only.
+ * bfi_is_eval: partial records (count x BFI_PARTIAL_LEN(nx), same layout as
+ *   bfi_eval's) of W/K over samples offset .. offset + n - 1 (n >= 2) of each
+ *   stream, for the given alpha (which enters every weight).
+ * bfi_integrate_is: round(alpha budget) samples over Gaussian streams
+ *   1 .. streams and the rest over uniform streams 2^63 + 1 .. 2^63 + streams,
+ *   each share split floor(b/S) + (i < b mod S) (every stream needs 2 samples);
+ *   result as bfi_finalize's, Z = K sum(W/K)/budget, with the two components as
+ *   strata of the variance.  BFI_EINVAL for a non-finite or empty cube, alpha
+ *   outside [0, 1], or too small a budget; BFI_EUNSUPPORTED for d > 32.
+ * bfi_debug_is_points: the points (n x d, FP64) and sum z^2/2 of one stream at
+ *   the given indices (test hook). */
+bfi_status bfi_is_modes(const bfi_lattice *lat, double box_lo, double box_hi, double *lambda,
+                        int32_t *uniform, double *scale, double *log_k);
+bfi_status bfi_is_eval(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec, uint64_t seed,
+                       double box_lo, double box_hi, double gaussian_fraction, size_t count,
+                       const uint64_t *stream_id, const uint64_t *n, const uint64_t *offset,
+                       const bfi_launch *launch, double *partials);
+bfi_status bfi_integrate_is(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
+                            uint64_t seed, double box_lo, double box_hi, double gaussian_fraction,
+                            uint32_t streams, uint64_t budget, const bfi_launch *launch,
+                            bfi_result *out);
+bfi_status bfi_debug_is_points(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
+                               uint64_t seed, double box_lo, double box_hi, uint64_t stream_id,
+                               const uint64_t *index, uint64_t n, double *u_out,
+                               double *half_z2_out);
+
 /* Continuous-batching request server on one context.  Requests are admitted
  * while their device state fits `memory_budget` bytes and a slot is free; their
  * partial sums stay resident on the device; every scheduling step packs chunks

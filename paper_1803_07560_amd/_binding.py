@@ -167,6 +167,17 @@ _SIGNATURES = {
     "bfi_integrate_hdi": ([_vp, _P(bfi_integrand), C.c_uint64, _P(C.c_double), _P(C.c_double),
                            _P(bfi_hdi_config), _P(bfi_launch), _P(C.c_double), _P(C.c_double),
                            _P(bfi_hdi_stats)], C.c_int),
+    "bfi_is_modes": ([_P(bfi_lattice), C.c_double, C.c_double, _P(C.c_double), _P(C.c_int32),
+                      _P(C.c_double), _P(C.c_double)], C.c_int),
+    "bfi_is_eval": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, C.c_double, C.c_double,
+                     C.c_double, C.c_size_t, _P(C.c_uint64), _P(C.c_uint64), _P(C.c_uint64),
+                     _P(bfi_launch), _P(C.c_double)], C.c_int),
+    "bfi_integrate_is": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, C.c_double, C.c_double,
+                          C.c_double, C.c_uint32, C.c_uint64, _P(bfi_launch), _P(bfi_result)],
+                         C.c_int),
+    "bfi_debug_is_points": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, C.c_double, C.c_double,
+                             C.c_uint64, _P(C.c_uint64), C.c_uint64, _P(C.c_double),
+                             _P(C.c_double)], C.c_int),
     "bfi_server_create": ([_vp, _P(bfi_server_config), _P(_vp)], C.c_int),
     "bfi_server_submit": ([_vp, _P(bfi_request), _P(C.c_uint64)], C.c_int),
     "bfi_server_poll": ([_vp, C.c_uint64, _P(bfi_result), _P(C.c_int32), _P(C.c_double)], C.c_int),
@@ -463,6 +474,57 @@ def bfi_integrate_hdi(ctx, f, seed, box_lo, box_hi, cfg, launch_=None) -> dict:
         _check(s, "bfi_integrate_hdi")
     return {"result": res.value, "abserr": err.value, "status": STATUS[s],
             **{k: getattr(st, k) for k, _ in bfi_hdi_stats._fields_}}
+
+
+IS_UNIFORM_STREAM = 1 << 63
+
+
+def bfi_is_modes(lat, box_lo, box_hi) -> dict:
+    """Mode table of the Gaussian-proposal sampler over the cube [box_lo, box_hi]^d."""
+    d = lat.d
+    lam, scale = np.zeros(d), np.zeros(d)
+    uni = np.zeros(d, dtype=np.int32)
+    lk = C.c_double()
+    _check(load().bfi_is_modes(C.byref(lat), float(box_lo), float(box_hi), _dp(lam),
+                               uni.ctypes.data_as(_P(C.c_int32)), _dp(scale), C.byref(lk)),
+           "bfi_is_modes")
+    return {"lambda": lam, "uniform": uni.astype(bool), "scale": scale, "log_k": lk.value}
+
+
+def bfi_is_eval(ctx, lat, prec, seed, box_lo, box_hi, gaussian_fraction, ids, n, offset=0,
+                launch_=None) -> np.ndarray:
+    """Partial records of W/K per stream (bit 63 of the id: uniform component)."""
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    n = np.ascontiguousarray(np.broadcast_to(np.asarray(n, dtype=np.uint64), ids.shape))
+    offset = np.ascontiguousarray(np.broadcast_to(np.asarray(offset, dtype=np.uint64), ids.shape))
+    out = np.zeros((ids.shape[0], 4 + 3 * lat.nx))
+    _check(load().bfi_is_eval(ctx, C.byref(lat), _prec(prec), int(seed), float(box_lo),
+                              float(box_hi), float(gaussian_fraction), ids.shape[0], _u64p(ids),
+                              _u64p(n), _u64p(offset),
+                              C.byref(launch_) if launch_ is not None else None, _dp(out)),
+           "bfi_is_eval")
+    return out
+
+
+def bfi_integrate_is(ctx, lat, prec, seed, box_lo, box_hi, budget, gaussian_fraction=0.9,
+                     streams=64, launch_=None) -> dict:
+    res = bfi_result()
+    _check(load().bfi_integrate_is(ctx, C.byref(lat), _prec(prec), int(seed), float(box_lo),
+                                   float(box_hi), float(gaussian_fraction), int(streams),
+                                   int(budget), C.byref(launch_) if launch_ is not None else None,
+                                   C.byref(res)), "bfi_integrate_is")
+    return res.to_dict()
+
+
+def bfi_debug_is_points(ctx, lat, prec, seed, box_lo, box_hi, stream, index):
+    """(points n x d, sum z^2/2 per point) of one sampler stream."""
+    idx = np.ascontiguousarray(index, dtype=np.uint64)
+    u = np.zeros((idx.shape[0], lat.d))
+    hz = np.zeros(idx.shape[0])
+    _check(load().bfi_debug_is_points(ctx, C.byref(lat), _prec(prec), int(seed), float(box_lo),
+                                      float(box_hi), int(stream), _u64p(idx), idx.shape[0],
+                                      _dp(u), _dp(hz)), "bfi_debug_is_points")
+    return u, hz
 
 
 def server_config(memory_budget=1 << 30, max_requests=256, chunks_per_step=4,

@@ -1,8 +1,9 @@
 """Build ``libbfi.so`` (HIP kernels for gfx950 + host runtime + C ABI) in-tree.
 
-One object per lattice shape (``shape_kernels.hip`` compiled with -DBFI_NX/-DBFI_NT
-for every shape listed in ``csrc/internal.h``), one for the shape-independent
-kernels, and the host runtime; linked into ``paper_1803_07560_amd/libbfi.so``.
+Two objects per lattice shape (``shape_kernels.hip`` and the sampler's
+``is_kernels.hip``, compiled with -DBFI_NX/-DBFI_NT for every shape listed in
+``csrc/internal.h``), one for the shape-independent kernels, and the host
+runtime; linked into ``paper_1803_07560_amd/libbfi.so``.
 """
 from __future__ import annotations
 
@@ -25,7 +26,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "inclu
 # that it does not know the feature, which is harmless
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops"]
-HOST_SOURCES = ["runtime.cpp", "tune.cpp", "adaptive.cpp", "server.cpp", "integrand.cpp"]
+HOST_SOURCES = ["runtime.cpp", "tune.cpp", "adaptive.cpp", "server.cpp", "integrand.cpp",
+                "sampler.cpp"]
 
 
 def shapes() -> list[tuple[int, int]]:
@@ -61,6 +63,9 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         obj = os.path.join(BUILD, f"shape_{nx}x{nt}.o")
         tasks.append([cc, *COMMON, *DEVICE, f"-DBFI_NX={nx}", f"-DBFI_NT={nt}", "-c",
                       os.path.join(CSRC, "shape_kernels.hip"), "-o", obj])
+        tasks.append([cc, *COMMON, *DEVICE, f"-DBFI_NX={nx}", f"-DBFI_NT={nt}", "-c",
+                      os.path.join(CSRC, "is_kernels.hip"), "-o",
+                      os.path.join(BUILD, f"is_{nx}x{nt}.o")])
     tasks.append([cc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "common_kernels.hip"), "-o",
                   os.path.join(BUILD, "common_kernels.o")])
     for src in HOST_SOURCES:

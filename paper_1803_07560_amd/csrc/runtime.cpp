@@ -67,6 +67,36 @@ hipError_t kernel_info(int nx, int nt, const LaunchSpec &spec, KernelInfo *info)
     return hipErrorNotSupported;
 }
 
+hipError_t launch_is(int nx, int nt, const LaunchSpec &spec, const IsArgs &args, hipStream_t st)
+{
+#define BFI_IS_LAUNCH(NX, NT)                                \
+    if (nx == NX && nt == NT)                                \
+        return launch_is_shape<NX, NT>(spec, args, st);
+    BFI_SHAPES(BFI_IS_LAUNCH)
+#undef BFI_IS_LAUNCH
+    return hipErrorNotSupported;
+}
+
+hipError_t is_kernel_info(int nx, int nt, const LaunchSpec &spec, KernelInfo *info)
+{
+#define BFI_IS_INFO(NX, NT)                                  \
+    if (nx == NX && nt == NT)                                \
+        return is_kernel_info_shape<NX, NT>(spec, info);
+    BFI_SHAPES(BFI_IS_INFO)
+#undef BFI_IS_INFO
+    return hipErrorNotSupported;
+}
+
+hipError_t launch_is_debug(int nx, int nt, const IsDebugArgs &args, hipStream_t st)
+{
+#define BFI_IS_DEBUG(NX, NT)                                 \
+    if (nx == NX && nt == NT)                                \
+        return launch_is_debug_shape<NX, NT>(args, st);
+    BFI_SHAPES(BFI_IS_DEBUG)
+#undef BFI_IS_DEBUG
+    return hipErrorNotSupported;
+}
+
 namespace {
 
 hipError_t launch_debug_action(int nx, int nt, const DebugActionArgs &args, hipStream_t st)
@@ -311,7 +341,7 @@ bfi_status plan_free(bfi_plan *p)
         (void)hipEventDestroy(p->ev_stop);
     void *bufs[] = {p->d_base64, p->d_scale64, p->d_base32, p->d_scale32, p->d_ids,
                     p->d_offsets, p->d_params, p->d_items, p->d_item_rec, p->d_item_split, p->d_sub_first,
-                    p->d_sub_rec, p->d_sub_split, p->d_head};
+                    p->d_sub_rec, p->d_sub_split, p->d_head, p->d_is_table};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -344,6 +374,27 @@ bfi_status plan_build_nsphere(bfi_context *ctx, int dim, const SubList &subs,
     return plan_build_core(ctx, 1, none, dim, 0, kFP64, subs, launch, true, out);
 }
 
+bfi_status plan_build_is(bfi_context *ctx, const bfi_lattice &lat, int prec,
+                         const SubList &streams, const IsTable &table, const bfi_launch *launch,
+                         bfi_plan **out)
+{
+    if (lat.nx * lat.nt > kIsMaxD)
+        return fail(BFI_EUNSUPPORTED, "the Gaussian-proposal sampler is compiled for d <= %d",
+                    kIsMaxD);
+    bfi_plan *p = nullptr;
+    BFI_TRY(plan_build_core(ctx, 2, lat, lat.nx * lat.nt, lat.nx, prec, streams, launch, false,
+                            &p));
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&p->d_is_table), sizeof(IsTable));
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_is_table, &table, sizeof(IsTable), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        plan_free(p);
+        return hip_fail(e, "sampler table upload");
+    }
+    *out = p;
+    return BFI_OK;
+}
+
 namespace {
 
 bfi_status plan_build_core(bfi_context *ctx, int kind, const bfi_lattice &lat, int d, int nx,
@@ -356,7 +407,7 @@ bfi_status plan_build_core(bfi_context *ctx, int kind, const bfi_lattice &lat, i
         return fail(BFI_EINVAL, "empty subvolume list");
     if (subs.size() > 0xFFFFFFFFull)
         return fail(BFI_EINVAL, "too many subvolumes");
-    bfi_launch l = kind == 0 ? resolve_launch(ctx, lat, prec, split, launch)
+    bfi_launch l = kind != 1 ? resolve_launch(ctx, lat, prec, split, launch)
                              : resolve_launch(nullptr, lat, prec, true, launch);
     if (l.block != 64 && l.block != 128 && l.block != 256)
         return fail(BFI_EINVAL, "block must be 64, 128 or 256 (got %d)", l.block);
@@ -446,7 +497,7 @@ bfi_status plan_build_core(bfi_context *ctx, int kind, const bfi_lattice &lat, i
         items[i].rec = p->d_item_rec + i * p->rec_len;
     }
     p->params = EvalParams{p->d_base64, p->d_scale64, p->d_base32, p->d_scale32, p->d_ids,
-                           p->d_offsets, kind == 0 ? make_coef(lat) : ActionCoef{}, 0u, 0u};
+                           p->d_offsets, kind != 1 ? make_coef(lat) : ActionCoef{}, 0u, 0u};
     struct Up {
         void *dst;
         const void *src;
@@ -473,9 +524,10 @@ bfi_status plan_build_core(bfi_context *ctx, int kind, const bfi_lattice &lat, i
     // persistent launches fill the chip once: resident blocks per CU x CUs
     if (l.persistent) {
         KernelInfo info{};
-        if (kind == 0) {
+        if (kind == 0 || kind == 2) {
             LaunchSpec spec{prec, l.block, split ? 1 : 0, 1, 0, lat.observable};
-            e = kernel_info(lat.nx, lat.nt, spec, &info);
+            e = kind == 0 ? kernel_info(lat.nx, lat.nt, spec, &info)
+                          : is_kernel_info(lat.nx, lat.nt, spec, &info);
             if (e != hipSuccess)
                 return cleanup_fail("kernel occupancy query");
         } else {
@@ -524,6 +576,8 @@ bfi_status plan_enqueue(bfi_plan *p, uint64_t seed, double *dst, hipStream_t st,
         BFI_HIP(hipEventRecord(p->ev_start, st));
     if (p->kind == 1)
         BFI_HIP(launch_nsphere(NsphereArgs{a, p->d}, p->grid, st));
+    else if (p->kind == 2)
+        BFI_HIP(launch_is(p->lat.nx, p->lat.nt, spec, IsArgs{a, p->d_is_table}, st));
     else
         BFI_HIP(launch_mc(p->lat.nx, p->lat.nt, spec, a, st));
     if (timed)

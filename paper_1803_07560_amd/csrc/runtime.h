@@ -13,6 +13,7 @@
 
 #include "bfi.h"
 #include "internal.h"
+#include "is_internal.h"
 
 namespace bfi {
 
@@ -38,6 +39,10 @@ bool shape_compiled(int nx, int nt);
 // Dispatch to the kernels compiled for lattice shape (nx, nt).
 hipError_t launch_mc(int nx, int nt, const LaunchSpec &spec, const McArgs &args, hipStream_t st);
 hipError_t kernel_info(int nx, int nt, const LaunchSpec &spec, KernelInfo *info);
+// Gaussian-proposal sampler kernels of shape (nx, nt).
+hipError_t launch_is(int nx, int nt, const LaunchSpec &spec, const IsArgs &args, hipStream_t st);
+hipError_t is_kernel_info(int nx, int nt, const LaunchSpec &spec, KernelInfo *info);
+hipError_t launch_is_debug(int nx, int nt, const IsDebugArgs &args, hipStream_t st);
 bfi_status check_lattice(const bfi_lattice *lat);
 bfi_status check_subvolumes(const bfi_lattice *lat, const bfi_subvolumes *subs);
 ActionCoef make_coef(const bfi_lattice &lat);
@@ -92,7 +97,8 @@ struct bfi_context {
 // A resident evaluation: descriptors, work items and buffers on the device.
 struct bfi_plan {
     bfi_context *ctx = nullptr;
-    int kind = 0;  // 0: lattice action (mc_kernel), 1: N-sphere test integrand
+    int kind = 0;  // 0: lattice action (mc_kernel), 1: N-sphere test integrand,
+                   // 2: Gaussian-proposal sampler (is_kernel) over streams
     bfi_lattice lat{};
     int prec = 0;
     int d = 0, nx = 0, rec_len = 0;
@@ -113,6 +119,7 @@ struct bfi_plan {
     uint32_t *d_sub_first = nullptr;
     double *d_sub_rec = nullptr, *d_sub_split = nullptr;
     uint32_t *d_head = nullptr;
+    bfi::IsTable *d_is_table = nullptr;  // kind 2
 
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_def = nullptr;
@@ -126,6 +133,11 @@ struct bfi_plan {
 namespace bfi {
 bfi_status plan_build(bfi_context *ctx, const bfi_lattice &lat, int prec, const SubList &subs,
                       const bfi_launch *launch, bool split, bfi_plan **out);
+// Plan for the Gaussian-proposal sampler: `streams` lists stream ids (bit 63:
+// uniform component), sample counts and offsets; lo/hi rows are the cube.
+bfi_status plan_build_is(bfi_context *ctx, const bfi_lattice &lat, int prec,
+                         const SubList &streams, const IsTable &table, const bfi_launch *launch,
+                         bfi_plan **out);
 // Plan for the N-sphere integrand over `dim`-dimensional boxes (FP64, split
 // statistics always on, 256-thread blocks); records have nx = 0.
 bfi_status plan_build_nsphere(bfi_context *ctx, int dim, const SubList &subs,

@@ -1,0 +1,153 @@
+"""GPU: the defensive Gaussian-proposal sampler (bfi_is_*) against the oracle's.
+
+Bars: Gaussian-component points within 1e-13 of the cube's scale and sum z^2/2
+within 1e-12 (FP64; the transforms and Box-Muller round differently from the
+oracle's direct sums), uniform-component points bit-exact (the plain point
+map); records within 1e-9 of their L1 scale (FP64); Z and C(r) within 1e-6
+(FP64) and 1e-4 (FP32 form, hardware transcendentals) of the oracle's on the
+same streams.  Then what the sampler is for: the Gaussian integral for g = 0,
+agreement with the plain sampler, and a larger effective sample size on the
+wide 10x2 workload box."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from test_gpu_parity import assert_sums_close, unshift
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = "fp64", "fp32"
+U = oracle.IS_UNIFORM_STREAM
+
+SHAPES = [(1, 1), (2, 1), (3, 2), (4, 2), (5, 3), (8, 2), (10, 2)]
+
+
+def hz_of(lat_o, B, u):
+    m = oracle.is_modes(lat_o, -B, B)
+    E = oracle.is_basis(lat_o.nx, lat_o.nt)
+    a = u @ E
+    g = ~m["uniform"]
+    return 0.5 * ((a[:, g] / m["scale"][g]) ** 2).sum(1)
+
+
+@pytest.mark.parametrize("nx,nt", SHAPES)
+def test_points(bfi, ctx, nx, nt):
+    d, B, seed = nx * nt, 3.0, 9
+    lat = bfi.lattice(nx, nt, nu=0.7)
+    lat_o = oracle.lattice(nx, nt, nu=0.7)
+    idx = np.array([0, 1, 2, 77, 2**20 + 5, 2**40 + 3], np.uint64)
+    for stream in (5, 2**33 + 1):
+        u, hz = bfi.bfi_debug_is_points(ctx, lat, F64, seed, -B, B, stream, idx)
+        for i, k in enumerate(idx):
+            uo, ho = oracle.is_point(lat_o, -B, B, seed, stream, int(k))
+            np.testing.assert_allclose(u[i], uo, rtol=0, atol=1e-13 * B * math.sqrt(d))
+            assert hz[i] == pytest.approx(ho, rel=1e-12, abs=1e-14)
+        u32, hz32 = bfi.bfi_debug_is_points(ctx, lat, F32, seed, -B, B, stream, idx)
+        np.testing.assert_allclose(u32, u, rtol=0, atol=2e-5 * B * math.sqrt(d))
+        np.testing.assert_allclose(hz32, hz, rtol=5e-5, atol=1e-5)
+    # uniform component: the plain sampler's points, bit for bit
+    for stream in (U + 1, U + 2**40):
+        u, hz = bfi.bfi_debug_is_points(ctx, lat, F64, seed, -B, B, stream, idx)
+        want = oracle.points(d, seed, stream, np.full(d, -B), np.full(d, B), idx)
+        assert np.array_equal(u, want)
+        np.testing.assert_allclose(hz, hz_of(lat_o, B, want), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("nx,nt,nu,obs", [(4, 2, 1.0, 0), (10, 2, 1.0, 0), (5, 3, 0.6, 1),
+                                          (8, 2, 0.5, 0), (3, 2, 1.0, 1)])
+def test_records_match_oracle(bfi, ctx, nx, nt, nu, obs):
+    B, seed, alpha = 3.0, 4, 0.8
+    lat = bfi.lattice(nx, nt, nu=nu, observable=obs)
+    lat_o = oracle.lattice(nx, nt, nu=nu, observable=obs)
+    ids = np.array([1, 2, 3, U + 1, U + 2, U + 7], np.uint64)
+    n = np.array([2, 1000, 64 * 256 + 3, 3, 5000, 777], np.uint64)
+    off = np.array([0, 5, 2**33, 0, 9, 2**20], np.uint64)
+    got = bfi.bfi_is_eval(ctx, lat, F64, seed, -B, B, alpha, ids, n, off)
+    want = oracle.is_sums(lat_o, seed, -B, B, ids, n, off, alpha)
+    assert_sums_close(unshift(got, nx), want, nx, 1e-9)
+
+
+@pytest.mark.parametrize("nx,nt,B,nu", [(4, 2, 2.0, 1.0), (10, 2, 4.0, 1.0), (10, 2, 1.0, 1.0),
+                                        (8, 2, 3.0, 0.5)])
+def test_integrate_matches_oracle_and_fp32(bfi, ctx, nx, nt, B, nu):
+    budget, streams, alpha = 200_003, 8, 0.9
+    lat = bfi.lattice(nx, nt, nu=nu)
+    ref = oracle.integrate_is(oracle.lattice(nx, nt, nu=nu), 3, -B, B, streams, budget, alpha)
+    r64 = bfi.bfi_integrate_is(ctx, lat, F64, 3, -B, B, budget, alpha, streams)
+    assert r64["log_Z"] == pytest.approx(ref["log_Z"], abs=1e-6)
+    c0 = abs(ref["C"][0])
+    assert np.all(np.abs(r64["C"] - ref["C"]) <= 1e-6 * c0)
+    np.testing.assert_allclose(r64["C_err"], ref["C_err"], rtol=1e-5)
+    assert r64["ess"] == pytest.approx(ref["ess"], rel=1e-6)
+    assert r64["n_evals"] == budget
+    r32 = bfi.bfi_integrate_is(ctx, lat, F32, 3, -B, B, budget, alpha, streams)
+    assert r32["log_Z"] == pytest.approx(r64["log_Z"], abs=1e-4)
+    assert np.all(np.abs(r32["C"] - r64["C"]) <= 1e-4 * c0)
+
+
+def test_gaussian_integral(bfi, ctx):
+    """g = 0, m2 = 1 over [-6, 6]^6 with the Gaussian alone: weights are 1 in the
+    cube, Z = (2 pi)^(d/2)/sqrt(det P), C(r) = (P^-1)_{0r}."""
+    nx, nt, nu, m2 = 3, 2, 0.5, 1.0
+    d = nx * nt
+    sh = lambda k: np.roll(np.eye(k), 1, axis=1)
+    Tt, Sx = np.kron(sh(nt), np.eye(nx)), np.kron(np.eye(nt), sh(nx))
+    A = (Tt - np.eye(d)) - nu * (Sx + Sx.T - 2 * np.eye(d))
+    P = A.T @ A + m2 * np.eye(d)
+    lat = bfi.lattice(nx, nt, nu=nu, g=0.0, m2=m2)
+    for prec, tol in ((F64, 1e-9), (F32, 1e-4)):
+        r = bfi.bfi_integrate_is(ctx, lat, prec, 2, -6.0, 6.0, 1 << 22, 1.0, 16)
+        Zexact = (2 * np.pi) ** (d / 2) / math.sqrt(np.linalg.det(P))
+        assert abs(r["Z"] - Zexact) < 4 * r["Z_err"] + tol * Zexact
+        assert r["Z_err"] < 1e-4 * Zexact
+        cov = np.linalg.inv(P)
+        for k in range(nx):
+            assert abs(r["C"][k] - cov[0, k]) < 4 * r["C_err"][k] + tol
+        assert r["ess"] > 0.99 * (1 << 22)
+
+
+def test_agrees_with_plain_sampler(bfi, ctx):
+    lat = bfi.lattice(4, 2, nu=0.7)
+    plain = bfi.bfi_integrate(ctx, lat, F64, 1, -2.0, 2.0, 4, 1 << 24)
+    g = bfi.bfi_integrate_is(ctx, lat, F64, 2, -2.0, 2.0, 1 << 22, 0.9, 32)
+    assert abs(plain["Z"] - g["Z"]) < 4 * math.hypot(plain["Z_err"], g["Z_err"])
+    for r in range(4):
+        assert abs(plain["C"][r] - g["C"][r]) < 4 * math.hypot(plain["C_err"][r], g["C_err"][r])
+
+
+def test_effective_sample_size_on_workload_box(bfi, ctx):
+    """10x2, nu = 1, [-4, 4]^20, 2^26 points each: the plain sampler's weight
+    sits on two or three points, the mixture's on at least ten times as many.
+    (Neither converges on this machine at such sizes: rare near-solutions of the
+    discrete equation carry much of the mass.)"""
+    lat = bfi.lattice(10, 2)
+    plain = bfi.bfi_integrate(ctx, lat, F32, 1, -4.0, 4.0, 10, 1 << 26)
+    g = bfi.bfi_integrate_is(ctx, lat, F32, 1, -4.0, 4.0, 1 << 26, 0.9, 64)
+    assert g["ess"] > 10 * plain["ess"]
+    assert g["C"][1] == pytest.approx(g["C"][9], abs=4 * math.hypot(g["C_err"][1], g["C_err"][9]))
+
+
+def test_persistent_equals_grid_bitwise(bfi, ctx):
+    lat = bfi.lattice(10, 2, nu=0.5)
+    ids = np.array([1, 2, U + 1, U + 2], np.uint64)
+    n = np.array([100_000, 70_001, 50_000, 3], np.uint64)
+    for prec in (F64, F32):
+        a = bfi.bfi_is_eval(ctx, lat, prec, 3, -4.0, 4.0, 0.9, ids, n, 0, bfi.launch(32, 256, 0))
+        b = bfi.bfi_is_eval(ctx, lat, prec, 3, -4.0, 4.0, 0.9, ids, n, 0, bfi.launch(32, 256, 1))
+        assert np.array_equal(a, b)
+
+
+def test_invalid_arguments(bfi, ctx):
+    cases = [
+        (bfi.lattice(16, 4), -3.0, 3.0, 0.9, 1 << 16, "BFI_EUNSUPPORTED"),
+        (bfi.lattice(4, 2), -3.0, 3.0, 1.5, 1 << 16, "BFI_EINVAL"),
+        (bfi.lattice(4, 2), 3.0, -3.0, 0.9, 1 << 16, "BFI_EINVAL"),
+        (bfi.lattice(4, 2), -3.0, 3.0, 0.9, 20, "BFI_EINVAL"),
+        (bfi.lattice(4, 2, observable=3), -3.0, 3.0, 0.9, 1 << 16, "BFI_EINVAL"),
+    ]
+    for lat, lo, hi, alpha, budget, name in cases:
+        with pytest.raises(bfi.BfiError) as e:
+            bfi.bfi_integrate_is(ctx, lat, F64, 1, lo, hi, budget, alpha, 8)
+        assert e.value.name == name
