@@ -92,6 +92,8 @@ def parse():
                     help="evaluation budget of each adaptive 10x2 run (0 skips them)")
     ap.add_argument("--no-observable-leg", action="store_true",
                     help="skip the translation-averaged observable leg")
+    ap.add_argument("--no-sampler-leg", action="store_true",
+                    help="skip the Gaussian-proposal sampler leg")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1803_07560_amd",
@@ -209,6 +211,33 @@ def observable_leg(bfi, torch, ctx, w, sv, steps, warmup, stream, accuracy_log2=
         "C_err_ratio": [float(x) for x in ratio]}}
 
 
+def sampler_leg(bfi, ctx, w, budget_log2=28, alpha=0.9, repeats=3):
+    """The defensive Gaussian-proposal sampler against the plain one on the
+    10x2 lattice, same budget, FP32 form, on the benchmark box [-4,4]^20 and on
+    the paper's range [-1,1]^20: effective sample size (sum W)^2 / sum W^2,
+    wall time of the whole call (plan, kernel, finalize), and their ratio."""
+    lat = bfi.lattice(w.nx, w.nt, nu=w.nu, D=w.D)
+    budget = 1 << budget_log2
+    out = []
+    for B in (w.box, 1.0):
+        row = {"box": [-B, B], "evals": budget, "alpha": alpha}
+        for kind in ("plain", "gaussian_mixture"):
+            best, res = None, None
+            for _ in range(repeats):
+                t0 = time.perf_counter()
+                if kind == "plain":
+                    res = bfi.bfi_integrate(ctx, lat, "fp32", 1, -B, B, w.split_log2, budget)
+                else:
+                    res = bfi.bfi_integrate_is(ctx, lat, "fp32", 1, -B, B, budget, alpha, 256)
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            row[kind] = {"seconds": best, "evals_per_s": budget / best, "ess": res["ess"],
+                         "ess_per_s": res["ess"] / best, "Z": res["Z"], "Z_err": res["Z_err"],
+                         "C0": float(res["C"][0]), "C0_err": float(res["C_err"][0])}
+        out.append(row)
+    return out
+
+
 def kernel_source_digest():
     """sha256 of the kernel sources: traffic figures apply only to the kernel
     they were measured on."""
@@ -275,6 +304,10 @@ def main():
     averaged = None
     if not args.no_observable_leg:
         averaged = observable_leg(bfi, torch, ctx, w, sv, args.steps, args.warmup, stream)
+    sampler = None
+    if not args.no_sampler_leg and w.nx * w.nt <= 32:
+        print("bench: Gaussian-proposal sampler", file=sys.stderr, flush=True)
+        sampler = sampler_leg(bfi, ctx, w)
     adaptive = None
     if args.adaptive_budget_log2 > 0:
         print(f"bench: adaptive 10x2, budget 2^{args.adaptive_budget_log2} per nu",
@@ -349,6 +382,8 @@ def main():
         averaged["equal_error_speedup"] = {"min_r": float(np.min(ratio ** 2) * rate),
                                            "median_r": float(np.median(ratio ** 2) * rate)}
         line["observable_averaged"] = averaged
+    if sampler is not None:
+        line["sampler_gaussian_mixture"] = sampler
     if serving is not None:
         line["p99_latency_ms"] = serving["p99_ms"]
         line["serving"] = serving
