@@ -77,8 +77,8 @@ def fp64_flops_per_eval(nx: int, nt: int) -> float:
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="burgers10x2", choices=sorted(workloads.WORKLOADS))
     ap.add_argument("--headline", default="fp32", choices=["fp64", "fp32"],
                     help="form reported as value (fp32: FP32 action/exp, FP64 sums)")
@@ -105,24 +105,28 @@ def run_form(bfi, torch, ctx, lat, sv, w, prec, steps, warmup, stream):
     plan = bfi.bfi_plan_create(ctx, lat, prec, sv, bfi.launch(use_graph=1))
     try:
         info = bfi.bfi_plan_info(plan)
+        part = np.zeros((len(sv), 4 + 3 * w.nx))
         for i in range(warmup):
             bfi.bfi_plan_run(plan, w.seed, None, stream)
-            part = bfi.bfi_plan_partials(plan, len(sv), w.nx)
+            bfi.bfi_plan_partials(plan, len(sv), w.nx, part)
             bfi.bfi_finalize(lat, sv, part)
         torch.cuda.synchronize()
-        kernel_ms = []
+        kernel_ms, step_end = [], []
         t0 = time.perf_counter()
         for i in range(steps):
             bfi.bfi_plan_run(plan, w.seed, None, stream)
-            part = bfi.bfi_plan_partials(plan, len(sv), w.nx)
+            bfi.bfi_plan_partials(plan, len(sv), w.nx, part)
             res = bfi.bfi_finalize(lat, sv, part)
+            step_end.append(time.perf_counter())
             kernel_ms.append(bfi.bfi_plan_kernel_ms(plan))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
     finally:
         bfi.bfi_plan_destroy(plan)
     evals = info["n_evals"]
+    step_ms = 1e3 * np.diff(np.concatenate([[t0], step_end]))
     return {"evals_per_s": steps * evals / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
+            "step_ms_median": float(np.median(step_ms)), "step_ms_max": float(np.max(step_ms)),
             "kernel_ms": float(np.mean(kernel_ms)), "kernel_ms_min": float(np.min(kernel_ms)),
             "evals_per_step": evals, "result": res, "partials": part,
             "launch": {k: info[k] for k in ("samples_per_thread", "block", "persistent",
@@ -364,6 +368,7 @@ def main():
                    "seed": w.seed, "form": args.headline, "launch": head["launch"],
                    "work_items": head["n_items"]},
         "forms": {p: {"evals_per_s": f["evals_per_s"], "ms_per_step": f["ms_per_step"],
+                      "step_ms_median": f["step_ms_median"], "step_ms_max": f["step_ms_max"],
                       "kernel_ms": f["kernel_ms"], "kernel_evals_per_s":
                           f["evals_per_step"] / (f["kernel_ms"] * 1e-3),
                       "valu_frac": valu_slots_per_eval(w.nx, w.nt, p) * f["evals_per_step"] /

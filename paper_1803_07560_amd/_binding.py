@@ -346,8 +346,15 @@ def bfi_plan_info(plan) -> dict:
             "block": l.block, "persistent": l.persistent, "use_graph": l.use_graph}
 
 
-def bfi_plan_partials(plan, count: int, nx: int) -> np.ndarray:
-    out = np.zeros((count, partial_len(nx)), dtype=np.float64)
+def bfi_plan_partials(plan, count: int, nx: int, out: np.ndarray | None = None) -> np.ndarray:
+    """Per-subvolume records of the last run; `out` (count x (4 + 3 nx), float64,
+    C-contiguous) is filled in place when given."""
+    if out is None:
+        out = np.zeros((count, partial_len(nx)), dtype=np.float64)
+    elif out.shape != (count, partial_len(nx)) or out.dtype != np.float64 or \
+            not out.flags.c_contiguous:
+        raise ValueError("out must be a C-contiguous float64 array of shape "
+                         f"({count}, {partial_len(nx)})")
     _check(load().bfi_plan_partials(plan, _dp(out)), "bfi_plan_partials")
     return out
 
