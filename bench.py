@@ -88,7 +88,7 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson serving run (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--adaptive-budget-log2", type=int, default=32,
+    ap.add_argument("--adaptive-budget-log2", type=int, default=36,
                     help="evaluation budget of each adaptive 10x2 run (0 skips them)")
     ap.add_argument("--no-observable-leg", action="store_true",
                     help="skip the translation-averaged observable leg")
@@ -169,50 +169,29 @@ def serve_leg(bfi, ctx, seconds, rate, warmup_s=1.0):
 
 def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0)):
     """10x2 lattice, D = 1, box [-4,4]^20: error-driven bisection from the
-    1024-subvolume partition at 2^12 samples per leaf, per-leaf counts in
-    [2^12, 2^22], target max_r sigma_C(r)/|C(0)| <= 1e-3, FP32 form, budget
-    2^budget_log2 evaluations per value of nu, each round at least 1/32 of it."""
+    1024-subvolume partition at 2^10 samples per leaf, per-leaf counts in
+    [2^10, 2^22], target max_r sigma_C(r)/|C(0)| <= 1e-3 with an effective
+    sample size of at least 100, FP32 form, budget 2^budget_log2 evaluations per
+    value of nu, each round at least 1/32 of it; the anchored product of the
+    paper and the translation-averaged one."""
     out = []
-    for nu in nus:
-        cfg = bfi.adaptive_config(target_rel_err=1e-3, max_evals=1 << budget_log2,
-                                  n_min=1 << 12, n_max=1 << 22, split_log2=10, max_rounds=64,
-                                  refine_fraction=0.5,
-                                  round_evals=max(1 << 24, (1 << budget_log2) >> 5))
-        t0 = time.perf_counter()
-        r = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(10, 2, nu=nu), "fp32", 1, -4.0, 4.0, cfg)
-        dt = time.perf_counter() - t0
-        n = r["partition"].n
-        out.append({"nu": nu, "status": r["status"], "rel_err": r["rel_err"],
-                    "rounds": r["rounds"], "leaves": r["leaves"], "evals": r["evals"],
-                    "seconds": dt, "evals_per_s": r["evals"] / dt,
-                    "leaf_n_min": int(n.min()), "leaf_n_max": int(n.max())})
+    for observable in ("anchor", "averaged"):
+        for nu in nus:
+            cfg = bfi.adaptive_config(target_rel_err=1e-3, max_evals=1 << budget_log2,
+                                      n_min=1 << 10, n_max=1 << 22, split_log2=10,
+                                      max_rounds=128, refine_fraction=0.5,
+                                      round_evals=max(1 << 24, (1 << budget_log2) >> 5))
+            t0 = time.perf_counter()
+            r = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(10, 2, nu=nu, observable=observable),
+                                           "fp32", 1, -4.0, 4.0, cfg, leaf_capacity=1 << 22)
+            dt = time.perf_counter() - t0
+            n = r["partition"].n
+            out.append({"observable": observable, "nu": nu, "status": r["status"],
+                        "rel_err": r["rel_err"], "ess": r["ess"], "rounds": r["rounds"],
+                        "leaves": r["leaves"], "evals": r["evals"], "seconds": dt,
+                        "evals_per_s": r["evals"] / dt, "leaf_n_min": int(n.min()),
+                        "leaf_n_max": int(n.max())})
     return out
-
-
-def observable_leg(bfi, torch, ctx, w, sv, steps, warmup, stream, accuracy_log2=26):
-    """The translation-averaged product (p_r averaged over every anchor):
-    throughput of both forms on the benchmark workload, and on the paper's
-    integration range [-1, 1]^20 (2^accuracy_log2 points, 64 subvolumes, FP32
-    form) the error bars of both observables on the same points.  The time to
-    reach a given error scales as sigma^2 / rate, so the equal-error speedup
-    per r is (sigma_anchor / sigma_averaged)^2 * rate_averaged / rate_anchor."""
-    lat = bfi.lattice(w.nx, w.nt, nu=w.nu, D=w.D, observable="averaged")
-    forms = {}
-    for prec in ("fp64", "fp32"):
-        print(f"bench: averaged observable {prec}", file=sys.stderr, flush=True)
-        f = run_form(bfi, torch, ctx, lat, sv, w, prec, steps, warmup, stream)
-        forms[prec] = {"evals_per_s": f["evals_per_s"], "ms_per_step": f["ms_per_step"],
-                       "kernel_ms": f["kernel_ms"]}
-    est = {}
-    for obs in ("anchor", "averaged"):
-        est[obs] = bfi.bfi_integrate(ctx, bfi.lattice(w.nx, w.nt, nu=w.nu, D=w.D, observable=obs),
-                                     "fp32", 3, -1.0, 1.0, 6, 1 << accuracy_log2)
-    ratio = np.asarray(est["anchor"]["C_err"]) / np.asarray(est["averaged"]["C_err"])
-    return {"forms": forms, "paper_range": {
-        "box": [-1.0, 1.0], "evals": 1 << accuracy_log2, "form": "fp32",
-        "C_anchor": [float(c) for c in est["anchor"]["C"]],
-        "C_averaged": [float(c) for c in est["averaged"]["C"]],
-        "C_err_ratio": [float(x) for x in ratio]}}
 
 
 def sampler_leg(bfi, ctx, w, budget_log2=28, alpha=0.9, repeats=3):

@@ -207,8 +207,12 @@ bfi_status bfi_integrate(bfi_context *ctx, const bfi_lattice *lat, bfi_precision
  * with n_min samples each; every round ranks leaves by their contribution to the
  * variance of C, and either splits a leaf at the midpoint of the dimension
  * minimising sigma_lower + sigma_upper (children start fresh streams) or doubles
- * its samples (continuing its stream), until max_r sigma_C(r)/|C(0)| <= target or
- * max_evals is spent; a round's planned samples are scaled up to round_evals.  Leaves keep n_min <= n <= n_max.  out gets the estimate;
+ * its samples (continuing its stream), until max_r sigma_C(r)/|C(0)| <= target
+ * with an effective sample size (sum W)^2 / sum W^2 of at least min_ess, or
+ * max_evals is spent; a round's planned samples are scaled up to round_evals.
+ * Leaves keep n_min <= n <= n_max.  The effective-size floor guards the stop:
+ * when a few points carry all the weight the delta-method error of C(r) is
+ * itself unreliable (one point alone gives sigma_C = 0).  out gets the estimate;
  * the final partition is written to the caller's arrays when non-NULL
  * (capacity `cap` leaves; *n_leaves gets the count).  Returns BFI_EBUDGET (with a
  * valid estimate) if the budget ran out first. */
@@ -222,6 +226,7 @@ typedef struct {
     uint64_t round_evals;   /* work floor per round: when the refined leaves' planned
                                samples fall short of it, their counts are scaled up by a
                                power of two (within n_max); 0: no floor */
+    double min_ess;         /* effective sample size the stop requires; 0: 100 */
 } bfi_adaptive_config;
 
 typedef struct {

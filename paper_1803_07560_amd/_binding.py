@@ -74,7 +74,7 @@ class bfi_adaptive_config(C.Structure):
     _fields_ = [("target_rel_err", C.c_double), ("max_evals", C.c_uint64),
                 ("n_min", C.c_uint64), ("n_max", C.c_uint64), ("split_log2", C.c_int32),
                 ("max_rounds", C.c_int32), ("refine_fraction", C.c_double),
-                ("round_evals", C.c_uint64)]
+                ("round_evals", C.c_uint64), ("min_ess", C.c_double)]
 
 
 class bfi_adaptive_stats(C.Structure):
@@ -396,10 +396,10 @@ def bfi_integrate(ctx, lat, prec, seed, box_lo, box_hi, split_log2, budget, laun
 
 def adaptive_config(target_rel_err=1e-3, max_evals=1 << 34, n_min=1 << 12, n_max=1 << 22,
                     split_log2=10, max_rounds=64, refine_fraction=0.5,
-                    round_evals=0) -> bfi_adaptive_config:
+                    round_evals=0, min_ess=0.0) -> bfi_adaptive_config:
     return bfi_adaptive_config(float(target_rel_err), int(max_evals), int(n_min), int(n_max),
                                int(split_log2), int(max_rounds), float(refine_fraction),
-                               int(round_evals))
+                               int(round_evals), float(min_ess))
 
 
 def bfi_integrate_adaptive(ctx, lat, prec, seed, box_lo, box_hi, cfg, launch_=None,

@@ -176,6 +176,8 @@ bfi_status check_config(const bfi_adaptive_config *cfg)
         return fail(BFI_EINVAL, "refine_fraction must be in (0, 1]");
     if (cfg->max_rounds < 0)
         return fail(BFI_EINVAL, "max_rounds must be >= 0");
+    if (!(cfg->min_ess >= 0) || !std::isfinite(cfg->min_ess))
+        return fail(BFI_EINVAL, "min_ess must be finite and >= 0");
     return BFI_OK;
 }
 
@@ -267,13 +269,14 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
     BFI_TRY(eval_list(ctx, *lat, prec, seed, init, launch, &L.rec, &L.split));
 
     bfi_status status = BFI_OK;
+    const double min_ess = cfg->min_ess > 0 ? cfg->min_ess : 100.0;
     int rounds = 0;
     bfi_result res{};
     std::vector<LeafAnalysis> an;
     for (;;) {
         BFI_TRY(analyse(nx, d, L.size(), L.lo.data(), L.hi.data(), L.rec.data(), L.split.data(),
                         &an, &res));
-        if (rel_err(res) <= cfg->target_rel_err)
+        if (rel_err(res) <= cfg->target_rel_err && res.ess >= min_ess)
             break;
         if (rounds >= cfg->max_rounds) {
             status = BFI_EBUDGET;

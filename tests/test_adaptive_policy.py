@@ -107,7 +107,7 @@ def test_decide_rejects_bad_config(bfi):
     sv = workloads.uniform_partition(4, 2.0, 1, per_sub=100)
     lat, sums, part, split = records(2, 2, sv, 1)
     for bad in (dict(n_min=1), dict(n_min=100, n_max=10), dict(refine_fraction=0.0),
-                dict(target_rel_err=0.0)):
+                dict(target_rel_err=0.0), dict(min_ess=-1.0), dict(min_ess=float("nan"))):
         cfg = bfi.adaptive_config(**bad)
         with pytest.raises(bfi.BfiError):
             bfi.bfi_adaptive_decide(bfi.lattice(2, 2), sv, part, split, cfg)

@@ -97,6 +97,22 @@ def test_adaptive_10x2(bfi, ctx, nu):
     assert np.all(np.abs(r32["C"] - res["C"]) <= 1e-4 * abs(res["C"][0]))
 
 
+def test_adaptive_stop_needs_effective_samples(bfi, ctx):
+    """10x2, nu = 1, [-4,4]^20 at 2^10 points per leaf: one point carries nearly
+    all the weight, so the delta-method error of C(r) is near zero; the stop must
+    wait for the effective sample size to reach min_ess (default 100)."""
+    lat = bfi.lattice(10, 2)
+    cfg = bfi.adaptive_config(target_rel_err=1e-3, max_evals=1 << 26, n_min=1 << 10,
+                              n_max=1 << 22, split_log2=10, max_rounds=40)
+    out = bfi.bfi_integrate_adaptive(ctx, lat, "fp32", 1, -4.0, 4.0, cfg)
+    assert out["rounds"] >= 1
+    assert out["status"] == "BFI_EBUDGET" or out["ess"] >= 100
+    strict = bfi.adaptive_config(target_rel_err=1.0, max_evals=1 << 26, n_min=1 << 10,
+                                 n_max=1 << 22, split_log2=10, max_rounds=40, min_ess=1e9)
+    out2 = bfi.bfi_integrate_adaptive(ctx, lat, "fp32", 1, -4.0, 4.0, strict)
+    assert out2["status"] == "BFI_EBUDGET"
+
+
 def test_adaptive_fp32_form(bfi, ctx):
     lat = bfi.lattice(4, 2)
     cfg = bfi.adaptive_config(target_rel_err=1e-4, max_evals=1 << 22, n_min=2048,
