@@ -32,13 +32,14 @@ METRIC = "integrand evals/s @10x2 lattice, FP32-eval vs FP64 at rel err 1e-3; p9
 
 # VALU issue roofline.  MI355X: 256 CUs at 2.4 GHz; the published vector peaks
 # (FP64 78.6 TFLOP/s, FP32 157.3 TFLOP/s) fix the issue width per clock and CU:
-# 64 lanes for FP64 arithmetic, and 128 lanes for FP32 arithmetic.  A measured
-# independent-chain probe on gfx950 puts 32-bit integer multiplies
-# (v_mad_u64_u32, v_mul_lo/hi_u32) and conversions at the FP64 rate, and 32-bit
-# logic (v_xor_b32, v_bitop3_b32) and non-packed v_fma_f32 at up to twice it.
-# Work is counted in FP64-rate lane slots: 1 per 64-lane-class instruction,
-# 1/2 per 128-lane-class instruction, 1 per transcendental.
-SLOT = {"f64": 1.0, "mul32": 1.0, "cvt": 1.0, "f32": 0.5, "logic32": 0.5, "trans": 1.0}
+# 64 lanes for FP64 arithmetic, and 128 lanes for FP32 arithmetic.  The
+# independent-chain probe (microbench/issue_rates.hip) puts 32-bit integer
+# multiplies (v_mad_u64_u32, v_mul_lo/hi_u32) and conversions at the FP64 rate,
+# 32-bit logic (v_xor_b32, v_bitop3_b32) and non-packed v_fma_f32 at 1.6-1.7x
+# it, and FP32 transcendentals at half of it.  Work is counted in FP64-rate lane
+# slots: 1 per 64-lane-class instruction, 1/2 per 128-lane-class instruction,
+# 2 per transcendental.
+SLOT = {"f64": 1.0, "mul32": 1.0, "cvt": 1.0, "f32": 0.5, "logic32": 0.5, "trans": 2.0}
 EXP64_OPS = 19              # FP64 exp routine: scale, round, 2 reductions, 11 poly, ldexp, checks
 PEAK_SLOTS = 256 * 64 * 2.4e9   # FP64-rate lane slots per second (= FP64 FMA/s)
 PEAK_FP64 = 78.6e12

@@ -19,6 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbfi.so")
+MICROBENCH = os.path.join(HERE, "microbench", "issue_rates")
 ARCH = os.environ.get("BFI_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
@@ -71,8 +72,13 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     for src in HOST_SOURCES:
         tasks.append([cc, *COMMON, "-c", os.path.join(CSRC, src), "-o",
                       os.path.join(BUILD, src.replace(".cpp", ".o"))])
+    # the issue-rate microbenchmark (a standalone program, not part of the library)
+    bench_task = [cc, "-O3", "-std=c++17", *DEVICE, os.path.join(HERE, "microbench",
+                                                                 "issue_rates.hip"),
+                  "-o", MICROBENCH + ".tmp"]
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        list(ex.map(lambda c: _run(c, verbose), tasks))
+        list(ex.map(lambda c: _run(c, verbose), tasks + [bench_task]))
+    os.replace(MICROBENCH + ".tmp", MICROBENCH)
     objs = [t[t.index("-o") + 1] for t in tasks]
     _run([cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", LIB + ".tmp", *objs,
           "-lpthread"], verbose)
