@@ -160,10 +160,16 @@ bfi_status check_subvolumes(const bfi_lattice *lat, const bfi_subvolumes *subs)
     if (!subs->id || !subs->lo || !subs->hi || !subs->n || !subs->offset)
         return fail(BFI_EINVAL, "subvolume arrays must be non-NULL");
     const int d = lat->nx * lat->nt;
+    // the Philox counter index * ceil(d/4) + j of the last sample must fit in
+    // 64 bits: offset + n <= floor(2^64 / ceil(d/4))
+    const unsigned __int128 index_end = (static_cast<unsigned __int128>(1) << 64) /
+                                        static_cast<unsigned>((d + 3) / 4);
     for (size_t s = 0; s < subs->count; ++s) {
         if (subs->n[s] < 2)
             return fail(BFI_EINVAL, "subvolume %zu: n = %llu < 2", s,
                         static_cast<unsigned long long>(subs->n[s]));
+        if (static_cast<unsigned __int128>(subs->offset[s]) + subs->n[s] > index_end)
+            return fail(BFI_EINVAL, "subvolume %zu: sample indices overflow the Philox counter", s);
         for (int k = 0; k < d; ++k) {
             const double lo = subs->lo[s * d + k], hi = subs->hi[s * d + k];
             if (!std::isfinite(lo) || !std::isfinite(hi) || !(lo < hi))

@@ -123,10 +123,19 @@ bfi_status run_streams(bfi_context *ctx, const bfi_lattice &lat, int prec, uint6
                        double lo, double hi, double alpha, const SubList &streams,
                        const bfi_launch *launch, double *partials, Modes *modes)
 {
-    for (size_t s = 0; s < streams.size(); ++s)
+    // the Philox counter index * blocks + j of the last sample must fit in 64
+    // bits (Gaussian streams take ceil((2 ceil(d/2) + 1)/4) blocks per sample,
+    // more than the uniform ones' ceil(d/4)): offset + n <= floor(2^64 / blocks)
+    const int d = lat.nx * lat.nt;
+    const unsigned __int128 index_end = (static_cast<unsigned __int128>(1) << 64) /
+                                        static_cast<unsigned>((2 * ((d + 1) / 2) + 1 + 3) / 4);
+    for (size_t s = 0; s < streams.size(); ++s) {
         if (streams.n[s] < 2)
             return fail(BFI_EINVAL, "stream %zu has n = %llu < 2", s,
                         static_cast<unsigned long long>(streams.n[s]));
+        if (static_cast<unsigned __int128>(streams.offset[s]) + streams.n[s] > index_end)
+            return fail(BFI_EINVAL, "stream %zu: sample indices overflow the Philox counter", s);
+    }
     BFI_HIP(hipSetDevice(ctx->device));
     const IsTable table = make_table(lat, lo, hi, alpha, seed, modes);
     bfi_plan *p = nullptr;

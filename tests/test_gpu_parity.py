@@ -318,6 +318,14 @@ def test_invalid_arguments(bfi, ctx):
         bfi.bfi_eval(ctx, bfi.lattice(4, 2), F64, 1, sv, bfi.launch(64, 96, 0))
     # the library stays usable after errors
     assert np.all(np.isfinite(bfi.bfi_eval(ctx, bfi.lattice(4, 2), F64, 1, sv)))
+    # sample indices whose Philox counter (index * ceil(d/4) + j) would wrap
+    wrap = workloads.uniform_partition(8, 4.0, 0, per_sub=100)
+    wrap.offset[:] = 2**63 - 99            # last index 2^63: counter 2^64 would wrap
+    with pytest.raises(bfi.BfiError) as e:
+        bfi.bfi_eval(ctx, bfi.lattice(4, 2), F64, 1, wrap)
+    assert e.value.name == "BFI_EINVAL"
+    wrap.offset[:] = 2**63 - 100           # last index 2^63 - 1: counter 2^64 - 1, allowed
+    assert np.all(np.isfinite(bfi.bfi_eval(ctx, bfi.lattice(4, 2), F64, 1, wrap)))
 
 
 def test_empty_list_is_a_no_op(bfi, ctx):
