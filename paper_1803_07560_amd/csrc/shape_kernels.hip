@@ -92,6 +92,11 @@ __global__ void __launch_bounds__(BLOCK)
 
     // point map held in registers when 2d values take at most 80 VGPRs
     constexpr bool kHoist = 2 * D * sizeof(T) / 4 <= 80;
+    // large FP64 lattices park time slice 0 (needed again only to close the
+    // time period and for the observables) in LDS, one column per thread, so
+    // that its registers are free while the other slices are processed
+    constexpr bool kParkFirst = PREC == kFP64 && D > 32;
+    __shared__ double park_lds[kParkFirst ? NX : 1][kParkFirst ? BLOCK : 1];
     __shared__ double red[NW][NF];
     __shared__ T map_lds[2][kHoist ? 1 : D];  // [0]: offsets, [1]: scales
     __shared__ float red_sigma[NW];
@@ -226,7 +231,52 @@ __global__ void __launch_bounds__(BLOCK)
                 }
             };
             T first[NX];
-            const T S = dev::action<T, NX, NT>(gen, first, coef, mass);
+            T S;
+            if constexpr (kParkFirst) {
+                // the action of dev::action, with slice 0 parked in LDS between
+                // its first use and the closing of the period
+                gen(0, first, T(0));
+#pragma unroll
+                for (int m = 0; m < NX; ++m)
+                    park_lds[m][tid] = first[m];
+                T cur[NX];
+#pragma unroll
+                for (int m = 0; m < NX; ++m)
+                    cur[m] = first[m];
+                T r2 = T(0), u2 = T(0);
+#pragma unroll
+                for (int l = 0; l < NT; ++l) {
+                    T nxt[NX];
+                    if (l + 1 < NT) {
+                        gen(l + 1, nxt, r2);
+                    } else {
+                        // reload through an address offset by a run-time zero
+                        // that depends on the action so far: the compiler can
+                        // neither forward the stored registers nor load early
+                        uint32_t zoff;
+                        asm volatile("v_mov_b32 %0, 0" : "=v"(zoff) : "v"(r2));
+                        using LdsD = const __attribute__((address_space(3))) double *;
+                        LdsD col = (LdsD)(&park_lds[0][0]) + zoff + tid;
+#pragma unroll
+                        for (int m = 0; m < NX; ++m)
+                            nxt[m] = col[m * BLOCK];
+                    }
+                    r2 = dev::slice_r2<T, NX>(cur, nxt, coef, r2);
+                    if (mass)
+                        u2 = dev::slice_u2<T, NX>(cur, u2);
+#pragma unroll
+                    for (int m = 0; m < NX; ++m)
+                        cur[m] = nxt[m];
+                }
+#pragma unroll
+                for (int m = 0; m < NX; ++m)
+                    first[m] = cur[m];  // slice 0, reloaded
+                S = r2 * coef.inv_2Dtau;
+                if (mass)
+                    S = dev::fma_t(coef.half_m2, u2, S);
+            } else {
+                S = dev::action<T, NX, NT>(gen, first, coef, mass);
+            }
             // p_r = pr_scale * pr[r]
             T pr[NR];
             T pr_scale;
