@@ -195,6 +195,32 @@ def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0)):
     return out
 
 
+def observable_leg(bfi, torch, ctx, w, sv, steps, warmup, stream, accuracy_log2=26):
+    """The translation-averaged product (p_r averaged over every anchor):
+    throughput of both forms on the benchmark workload, and on the paper's
+    integration range [-1, 1]^20 (2^accuracy_log2 points, 64 subvolumes, FP32
+    form) the error bars of both observables on the same points.  The time to
+    reach a given error scales as sigma^2 / rate, so the equal-error speedup
+    per r is (sigma_anchor / sigma_averaged)^2 * rate_averaged / rate_anchor."""
+    lat = bfi.lattice(w.nx, w.nt, nu=w.nu, D=w.D, observable="averaged")
+    forms = {}
+    for prec in ("fp64", "fp32"):
+        print(f"bench: averaged observable {prec}", file=sys.stderr, flush=True)
+        f = run_form(bfi, torch, ctx, lat, sv, w, prec, steps, warmup, stream)
+        forms[prec] = {"evals_per_s": f["evals_per_s"], "ms_per_step": f["ms_per_step"],
+                       "kernel_ms": f["kernel_ms"]}
+    est = {}
+    for obs in ("anchor", "averaged"):
+        est[obs] = bfi.bfi_integrate(ctx, bfi.lattice(w.nx, w.nt, nu=w.nu, D=w.D, observable=obs),
+                                     "fp32", 3, -1.0, 1.0, 6, 1 << accuracy_log2)
+    ratio = np.asarray(est["anchor"]["C_err"]) / np.asarray(est["averaged"]["C_err"])
+    return {"forms": forms, "paper_range": {
+        "box": [-1.0, 1.0], "evals": 1 << accuracy_log2, "form": "fp32",
+        "C_anchor": [float(c) for c in est["anchor"]["C"]],
+        "C_averaged": [float(c) for c in est["averaged"]["C"]],
+        "C_err_ratio": [float(x) for x in ratio]}}
+
+
 def sampler_leg(bfi, ctx, w, budget_log2=28, alpha=0.9, repeats=3):
     """The defensive Gaussian-proposal sampler against the plain one on the
     10x2 lattice, same budget, FP32 form, on the benchmark box [-4,4]^20 and on
