@@ -187,6 +187,20 @@ bfi_status bfi_plan_info(const bfi_plan *plan, uint64_t *n_items, uint64_t *n_ev
 bfi_status bfi_plan_kernel_ms(bfi_plan *plan, double *ms);
 bfi_status bfi_plan_destroy(bfi_plan *plan);
 
+/* Merge partial records of disjoint sample ranges of the same subvolumes
+ * (section 3: a subvolume's estimate from more samples), record by record:
+ * acc[i] <- acc[i] (+) more[i], both count x BFI_PARTIAL_LEN(nx), host,
+ * caller-owned.  Counts add; the result takes the smaller shift sigma, with
+ * first-order sums rescaled by exp(sigma - sigma_old) and second-order sums by
+ * its square.  A record with n = 0 is empty (its other fields are ignored).
+ * With counter-based points, the records of [offset, offset + n) and
+ * [offset + n, offset + n + m) merge into an estimate over n + m samples: this
+ * is how a run is checkpointed (subvolumes, sample counts, records) and resumed.
+ * Host only.  Errors: EINVAL (nx out of range, NULL arrays, a count that is not
+ * a whole number in [0, 2^53], a non-finite shift in a non-empty record, a
+ * merged count above 2^53); acc is left unchanged on error. */
+bfi_status bfi_partials_merge(int32_t nx, size_t count, double *acc, const double *more);
+
 /* Combine partial records into Z, C(r) and their errors (section 4's
  * normalisation; delta method for the ratio).  Host only.  The subvolume list
  * supplies the volumes.  Errors: EINVAL (n < 2, bad box). */

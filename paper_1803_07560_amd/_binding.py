@@ -150,6 +150,7 @@ _SIGNATURES = {
     "bfi_plan_info": ([_vp, _P(C.c_uint64), _P(C.c_uint64), _P(bfi_launch)], C.c_int),
     "bfi_plan_kernel_ms": ([_vp, _P(C.c_double)], C.c_int),
     "bfi_plan_destroy": ([_vp], C.c_int),
+    "bfi_partials_merge": ([C.c_int32, C.c_size_t, _P(C.c_double), _P(C.c_double)], C.c_int),
     "bfi_finalize": ([_P(bfi_lattice), _P(bfi_subvolumes), _P(C.c_double), _P(bfi_result)],
                      C.c_int),
     "bfi_integrate": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, _P(C.c_double), _P(C.c_double),
@@ -367,6 +368,17 @@ def bfi_plan_kernel_ms(plan) -> float:
 
 def bfi_plan_destroy(plan):
     _check(load().bfi_plan_destroy(plan), "bfi_plan_destroy")
+
+
+def bfi_partials_merge(nx: int, acc, more) -> np.ndarray:
+    """Merged copy of two record arrays of disjoint sample ranges (count x
+    (4 + 3 nx))."""
+    a = np.array(acc, dtype=np.float64, order="C", copy=True)
+    b = np.ascontiguousarray(more, dtype=np.float64)
+    if a.shape != b.shape or a.ndim != 2 or a.shape[1] != partial_len(nx):
+        raise ValueError(f"record arrays must both be count x {partial_len(nx)}")
+    _check(load().bfi_partials_merge(int(nx), a.shape[0], _dp(a), _dp(b)), "bfi_partials_merge")
+    return a
 
 
 def bfi_finalize(lat, subs, partials) -> dict:

@@ -198,6 +198,19 @@ void merge_shifted(double *a, const double *b, int sigma_at, const std::vector<i
     a[sigma_at] = sig;
 }
 
+// Field ranges of a partial record: first-order sums (S_w, S_pw) and
+// second-order sums (S_w2, S_pw2, S_pww).
+void record_fields(int nx, std::vector<int> *first, std::vector<int> *second)
+{
+    *first = {2};
+    *second = {3};
+    for (int r = 0; r < nx; ++r) {
+        first->push_back(4 + r);
+        second->push_back(4 + nx + r);
+        second->push_back(4 + 2 * nx + r);
+    }
+}
+
 struct LeafSet {
     int d = 0, nx = 0;
     std::vector<uint64_t> id, n;
@@ -242,12 +255,8 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         if (!std::isfinite(box_lo[k]) || !std::isfinite(box_hi[k]) || !(box_lo[k] < box_hi[k]))
             return fail(BFI_EINVAL, "box dim %d: need finite lo < hi", k);
     const int rec_len = BFI_PARTIAL_LEN(nx), split_len = BFI_SPLIT_LEN(d);
-    std::vector<int> rec_first{2}, rec_second{3}, split_first, split_second;
-    for (int r = 0; r < nx; ++r) {
-        rec_first.push_back(4 + r);
-        rec_second.push_back(4 + nx + r);
-        rec_second.push_back(4 + 2 * nx + r);
-    }
+    std::vector<int> rec_first, rec_second, split_first, split_second;
+    record_fields(nx, &rec_first, &rec_second);
     for (int j = 0; j < d; ++j) {
         split_first.push_back(1 + j);
         split_second.push_back(1 + d + j);
@@ -482,6 +491,44 @@ bfi_status bfi_adaptive_decide(const bfi_lattice *lat, const bfi_subvolumes *lea
     BFI_TRY(analyse(lat->nx, lat->nx * lat->nt, leaves->count, leaves->lo, leaves->hi, partials,
                     split, &an, &res));
     decide(an, leaves->id, leaves->n, *cfg, action);
+    return BFI_OK;
+}
+
+bfi_status bfi_partials_merge(int32_t nx, size_t count, double *acc, const double *more)
+{
+    if (nx < 1 || nx > BFI_MAX_NX)
+        return fail(BFI_EINVAL, "nx must be in [1, %d]", BFI_MAX_NX);
+    if (count == 0)
+        return BFI_OK;
+    if (!acc || !more)
+        return fail(BFI_EINVAL, "record arrays must be non-NULL");
+    const size_t len = BFI_PARTIAL_LEN(nx);
+    constexpr double kMaxCount = 9007199254740992.0;  // 2^53: counts stay exact
+    for (size_t i = 0; i < count; ++i) {
+        const double *a = acc + i * len, *b = more + i * len;
+        for (const double *r : {a, b}) {
+            if (!(r[0] >= 0) || !(r[0] <= kMaxCount) || r[0] != std::floor(r[0]))
+                return fail(BFI_EINVAL, "record %zu: sample count must be a whole number >= 0",
+                            i);
+            if (r[0] > 0 && !std::isfinite(r[1]))
+                return fail(BFI_EINVAL, "record %zu: shift must be finite", i);
+        }
+        if (a[0] + b[0] > kMaxCount)
+            return fail(BFI_EINVAL, "record %zu: merged sample count exceeds 2^53", i);
+    }
+    std::vector<int> first, second;
+    record_fields(nx, &first, &second);
+    for (size_t i = 0; i < count; ++i) {
+        double *a = acc + i * len;
+        const double *b = more + i * len;
+        if (b[0] == 0)
+            continue;
+        if (a[0] == 0) {
+            std::memcpy(a, b, len * sizeof(double));
+            continue;
+        }
+        merge_shifted(a, b, 1, first, second, 0);
+    }
     return BFI_OK;
 }
 

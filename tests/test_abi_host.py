@@ -113,3 +113,114 @@ def test_finalize_rejects_short_records(bfi):
     with pytest.raises(bfi.BfiError) as e:
         bfi.bfi_finalize(bfi.lattice(2, 1), sv, p)
     assert e.value.name == "BFI_EINVAL"
+
+
+def _unshift(p, nx):
+    """bfi partial records -> oracle sums layout (scaled back by the shift)."""
+    sig = p[:, 1]
+    f1, f2 = np.exp(-sig), np.exp(-2 * sig)
+    s = np.zeros((p.shape[0], 3 + 3 * nx))
+    s[:, 0] = p[:, 0]
+    s[:, 1] = p[:, 2] * f1
+    s[:, 2] = p[:, 3] * f2
+    s[:, 3:3 + nx] = p[:, 4:4 + nx] * f1[:, None]
+    s[:, 3 + nx:] = p[:, 4 + nx:] * f2[:, None]
+    return s
+
+
+def test_partials_merge_is_the_sum_over_both_ranges(bfi):
+    """Records of [0, n) and [n, n + m), each with its own shift, merge into the
+    oracle's record of [0, n + m) (disjoint sample ranges add)."""
+    nx, nt, seed = 3, 2, 5
+    lat = oracle.lattice(nx, nt, nu=0.8)
+    sv = workloads.uniform_partition(nx * nt, 2.0, 3, per_sub=1500)
+    a = oracle.sums(lat, seed, sv.ids, sv.lo, sv.hi, 1500, 0)
+    b = oracle.sums(lat, seed, sv.ids, sv.lo, sv.hi, 2500, 1500)
+    want = oracle.sums(lat, seed, sv.ids, sv.lo, sv.hi, 4000, 0)
+    sig_a = np.linspace(-20, 30, len(sv))
+    sig_b = np.linspace(25, -15, len(sv))
+    got = bfi.bfi_partials_merge(nx, _as_partials(a, nx, sig_a), _as_partials(b, nx, sig_b))
+    assert np.array_equal(got[:, 1], np.minimum(sig_a, sig_b))
+    s = _unshift(got, nx)
+    assert np.array_equal(s[:, 0], want[:, 0])
+    np.testing.assert_allclose(s[:, 1:], want[:, 1:], rtol=1e-12, atol=0)
+
+
+def test_partials_merge_empty_records(bfi):
+    nx = 2
+    lat, sv, sums = _oracle_case(nx, 1, k=1)
+    full = _as_partials(sums, nx, 3.0)
+    empty = np.zeros_like(full)
+    empty[:, 1] = np.nan          # ignored when n = 0
+    assert np.array_equal(bfi.bfi_partials_merge(nx, empty, full), full)
+    assert np.array_equal(bfi.bfi_partials_merge(nx, full, empty), full)
+
+
+def test_partials_merge_rejects_bad_records(bfi):
+    nx = 2
+    lat, sv, sums = _oracle_case(nx, 1, k=1)
+    good = _as_partials(sums, nx, 0.0)
+    bads = []
+    frac = good.copy()
+    frac[1, 0] = 10.5
+    bads.append(frac)
+    neg = good.copy()
+    neg[0, 0] = -2.0
+    bads.append(neg)
+    nan_shift = good.copy()
+    nan_shift[0, 1] = np.nan
+    bads.append(nan_shift)
+    big = good.copy()
+    big[:, 0] = 2.0**53
+    bads.append(big)
+    for bad in bads:
+        with pytest.raises(bfi.BfiError) as e:
+            bfi.bfi_partials_merge(nx, good, bad)
+        assert e.value.name == "BFI_EINVAL"
+    acc = good.copy()
+    rc = bfi.load().bfi_partials_merge(nx, acc.shape[0], bfi._binding._dp(acc),
+                                       bfi._binding._dp(frac))
+    assert rc == -1 and np.array_equal(acc, good)   # unchanged on error
+    with pytest.raises(bfi.BfiError):
+        bfi.bfi_partials_merge(0, good[:, :4], good[:, :4])
+
+
+def test_checkpoint_json_round_trip_is_exact(bfi):
+    """A run state survives save/load bit for bit, and its estimate is the
+    oracle's for the records it holds."""
+    from paper_1803_07560_amd import checkpoint
+    nx, nt = 4, 2
+    lat_o, sv, sums = _oracle_case(nx, nt)
+    lat = bfi.lattice(nx, nt, nu=0.8, observable="averaged")
+    lat.D = 0.1 + 2.0**-40
+    part = _as_partials(sums, nx, np.linspace(-700.0, 3.0, len(sv)))
+    subs = bfi.Subvolumes(sv.ids + np.uint64(2**63), sv.lo / 3.0, sv.hi / 7.0, sv.n,
+                          sv.offset + np.uint64(2**40 + 1), nx * nt)
+    st = checkpoint.RunState(lat, "fp32", 2**64 - 1, subs, part)
+    back = checkpoint.from_json(checkpoint.to_json(st))
+    for f in checkpoint._LATTICE_FIELDS:
+        assert getattr(back.lat, f) == getattr(lat, f)
+    assert back.prec == "fp32" and back.seed == 2**64 - 1
+    for f in ("ids", "lo", "hi", "n", "offset"):
+        assert np.array_equal(getattr(back.subs, f), getattr(subs, f))
+    assert np.array_equal(back.partials, part)
+    doc = checkpoint.to_json(st)
+    with pytest.raises(ValueError):
+        checkpoint.from_json(doc.replace('"count": 8', '"count": 9'))
+    with pytest.raises(ValueError):
+        checkpoint.from_json(doc.replace(checkpoint.FORMAT, "other"))
+
+
+def test_checkpoint_result_matches_oracle(bfi, tmp_path):
+    from paper_1803_07560_amd import checkpoint
+    nx, nt = 4, 2
+    lat_o, sv, sums = _oracle_case(nx, nt)
+    lat = bfi.lattice(nx, nt, nu=0.8)
+    st = checkpoint.RunState(lat, "fp64", 3, bfi.Subvolumes.of(sv, nx * nt),
+                             _as_partials(sums, nx, 0.0))
+    path = str(tmp_path / "run.json")
+    checkpoint.save(st, path)
+    got = checkpoint.result(checkpoint.load(path))
+    want = oracle.finalize(nx, nx * nt, sv.lo, sv.hi, sums)
+    assert got["log_Z"] == pytest.approx(want["log_Z"], rel=1e-13)
+    np.testing.assert_allclose(got["C"], want["C"], rtol=1e-12, atol=1e-14)

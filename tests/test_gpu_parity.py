@@ -259,7 +259,7 @@ def test_config_10x2_full_size_sampled(bfi, ctx):
     sv = workloads.uniform_partition(w.d, w.box, w.split_log2, w.budget // w.n_sub)
     lat = bfi.lattice(10, 2)
     for prec in (F64, F32):
-        plan = bfi.bfi_plan_create(ctx, lat, prec, sv)
+        plan = bfi.bfi_plan_create(ctx, lat, prec, sv, bfi.launch(use_graph=1))
         try:
             bfi.bfi_plan_run(plan, w.seed)
             got = bfi.bfi_plan_partials(plan, len(sv), 10)
@@ -279,20 +279,37 @@ def test_config_10x2_full_size_sampled(bfi, ctx):
         assert got[:, 0].sum() == 2**30
 
 
-def test_config_16x4_sampled(bfi, ctx):
-    """16x4, nu = 0.5, box [-3,3]^64, 4096 subvolumes (dims 0-11); 2^26 points
-    (2^14 per subvolume) on the GPU, 3 subvolumes against the oracle."""
+def test_config_16x4_full_size_sampled(bfi, ctx):
+    """16x4, nu = 0.5, box [-3,3]^64, 2^34 points over 4096 subvolumes (dims
+    0-11), in the benchmark's launch configuration (resident plan, tuned
+    shape): 3 whole subvolumes (2^22 points each) against the oracle, the FP32
+    form against FP64 on the same points."""
     w = workloads.WORKLOADS["burgers16x4"]
-    sv = workloads.uniform_partition(w.d, w.box, w.split_log2, 1 << 14)
+    sv = workloads.uniform_partition(w.d, w.box, w.split_log2, w.budget // w.n_sub)
     lat = bfi.lattice(16, 4, nu=0.5)
-    got = bfi.bfi_eval(ctx, lat, F64, w.seed, sv)
-    pick = np.array([0, 2047, 4095])
-    sub = sv.subset(pick)
-    want = oracle.sums(oracle.lattice(16, 4, nu=0.5), w.seed, sub.ids, sub.lo, sub.hi, sub.n,
-                       sub.offset)
-    assert_sums_close(unshift(got[pick], 16), want, 16, 1e-10)
-    got32 = bfi.bfi_eval(ctx, lat, F32, w.seed, sv)
-    assert_result_close(bfi.bfi_finalize(lat, sv, got32), bfi.bfi_finalize(lat, sv, got), 1e-4)
+    res = {}
+    for prec in (F64, F32):
+        plan = bfi.bfi_plan_create(ctx, lat, prec, sv, bfi.launch(use_graph=1))
+        try:
+            bfi.bfi_plan_run(plan, w.seed)
+            got = bfi.bfi_plan_partials(plan, len(sv), 16)
+        finally:
+            bfi.bfi_plan_destroy(plan)
+        assert got[:, 0].sum() == 2**34
+        res[prec] = bfi.bfi_finalize(lat, sv, got)
+        if prec == F64:
+            # each picked subvolume's 2^22 points as 16 consecutive chunks of
+            # the oracle's (records of disjoint sample ranges add)
+            pick = np.array([0, 2047, 4095])
+            sub = sv.subset(pick)
+            chunks = 16
+            m = int(sub.n[0]) // chunks
+            want = oracle.sums(oracle.lattice(16, 4, nu=0.5), w.seed, np.repeat(sub.ids, chunks),
+                               np.repeat(sub.lo, chunks, axis=0), np.repeat(sub.hi, chunks, axis=0),
+                               m, np.tile(np.arange(chunks, dtype=np.uint64) * m, len(pick)))
+            want = want.reshape(len(pick), chunks, -1).sum(1)
+            assert_sums_close(unshift(got[pick], 16), want, 16, 1e-10)
+    assert_result_close(res[F32], res[F64], 1e-4)
 
 
 # ------------------------------------------------------------------ edges
