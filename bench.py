@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -83,8 +84,9 @@ def parse():
     ap.add_argument("--workload", default="burgers10x2", choices=sorted(workloads.WORKLOADS))
     ap.add_argument("--headline", default="fp32", choices=["fp64", "fp32"],
                     help="form reported as value (fp32: FP32 action/exp, FP64 sums)")
-    ap.add_argument("--cpu-samples-log2", type=int, default=17,
-                    help="oracle sample: first 2^k samples of every subvolume")
+    ap.add_argument("--cpu-samples-log2", type=int, default=None,
+                    help="oracle sample: first 2^k samples of every subvolume (default: about "
+                         "2^29 x 20/d evaluations in all, 10-15 s on 16 host threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson serving run (0 skips it)")
@@ -275,6 +277,8 @@ def measured_traffic(workload, form):
 def cpu_baseline(w, sv, k):
     import oracle
     sub = sv.subset(np.arange(len(sv)))
+    if k is None:
+        k = max(int(math.floor(math.log2(2**29 * 20 / w.d / len(sub)))), 1)
     per = min(int(sub.n[0]), 1 << k)
     sub.n[:] = per
     threads = min(16, os.cpu_count() or 1)

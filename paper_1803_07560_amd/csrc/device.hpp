@@ -59,6 +59,75 @@ __device__ __forceinline__ void philox_block(uint64_t q, uint32_t id_lo, uint32_
     out[3] = c3;
 }
 
+// The share of Philox4x32-10 that is the same for every block of a work item
+// whose counters keep one upper word c1 = hi32(q): round 0 multiplies the id
+// word, so word 0 after it, and round 1's product of that word, are the
+// item's; round 2's word 3 is too.  Computed once per item (scalar registers).
+struct PhiloxItem {
+    uint32_t w1_r1;    // word 1 after round 0: lo(B id_lo)
+    uint32_t x2_r0;    // round 0, word 2: id_hi ^ k1
+    uint32_t x0_r1;    // round 1, word 0: w1_r1 ^ (k0 + Weyl A)
+    uint32_t x2_r1;    // round 1, word 2: hi(A w0_r1) ^ (k1 + Weyl B)
+    uint32_t x2_r2;    // round 2, word 2: lo(A w0_r1) ^ (k1 + 2 Weyl B)
+    uint32_t k0, k1;   // key
+};
+
+__device__ __forceinline__ PhiloxItem philox_item(uint32_t c1, uint32_t id_lo, uint32_t id_hi,
+                                                  uint32_t key_lo, uint32_t key_hi)
+{
+    PhiloxItem p;
+    const uint64_t b0 = static_cast<uint64_t>(kPhiloxMulB) * id_lo;
+    const uint32_t w0_r1 = static_cast<uint32_t>(b0 >> 32) ^ c1 ^ key_lo;
+    const uint64_t a1 = static_cast<uint64_t>(kPhiloxMulA) * w0_r1;
+    p.w1_r1 = static_cast<uint32_t>(b0);
+    p.x2_r0 = id_hi ^ key_hi;
+    p.x0_r1 = p.w1_r1 ^ (key_lo + kPhiloxWeylA);
+    p.x2_r1 = static_cast<uint32_t>(a1 >> 32) ^ (key_hi + kPhiloxWeylB);
+    p.x2_r2 = static_cast<uint32_t>(a1) ^ (key_hi + 2u * kPhiloxWeylB);
+    p.k0 = key_lo;
+    p.k1 = key_hi;
+    return p;
+}
+
+// philox_block for counter (c0, c1, id_lo, id_hi) with the item's share `p`
+// (same c1, id and key): the same words, two wide multiplies and one xor fewer.
+__device__ __forceinline__ void philox_block_item(uint32_t c0, const PhiloxItem &p,
+                                                  uint32_t out[4])
+{
+    // round 0: only word 2's product depends on the block
+    const uint64_t a0 = mul_wide(c0, kPhiloxMulA);
+    const uint32_t w2 = static_cast<uint32_t>(a0 >> 32) ^ p.x2_r0;
+    const uint32_t w3 = static_cast<uint32_t>(a0);
+    // round 1: word 0 and its product are the item's
+    const uint64_t b1 = mul_wide(w2, kPhiloxMulB);
+    const uint32_t v0 = static_cast<uint32_t>(b1 >> 32) ^ p.x0_r1;
+    const uint32_t v1 = static_cast<uint32_t>(b1);
+    const uint32_t v2 = w3 ^ p.x2_r1;
+    // round 2: word 3 is the item's
+    uint32_t k0 = p.k0 + 2u * kPhiloxWeylA, k1 = p.k1 + 2u * kPhiloxWeylB;
+    const uint64_t a2 = mul_wide(v0, kPhiloxMulA);
+    const uint64_t b2 = mul_wide(v2, kPhiloxMulB);
+    uint32_t c0n = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(b2 >> 32), v1, k0, 0x96);
+    uint32_t c2n = static_cast<uint32_t>(a2 >> 32) ^ p.x2_r2;
+    uint32_t c1n = static_cast<uint32_t>(b2);
+    uint32_t c3n = static_cast<uint32_t>(a2);
+#pragma unroll
+    for (int round = 3; round < 10; ++round) {
+        k0 += kPhiloxWeylA;
+        k1 += kPhiloxWeylB;
+        const uint64_t pa = mul_wide(c0n, kPhiloxMulA);
+        const uint64_t pb = mul_wide(c2n, kPhiloxMulB);
+        c0n = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pb >> 32), c1n, k0, 0x96);
+        c2n = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pa >> 32), c3n, k1, 0x96);
+        c1n = static_cast<uint32_t>(pb);
+        c3n = static_cast<uint32_t>(pa);
+    }
+    out[0] = c0n;
+    out[1] = c1n;
+    out[2] = c2n;
+    out[3] = c3n;
+}
+
 // Word -> coordinate: u = fma(x, scale, base), one rounding.
 __device__ __forceinline__ double map_word(uint32_t x, double scale, double base)
 {

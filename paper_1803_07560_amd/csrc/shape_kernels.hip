@@ -186,11 +186,24 @@ __global__ void __launch_bounds__(BLOCK)
                 acc[i] *= F::order(i) == 1 ? f1 : f2;
         };
 
+        // counters of the item: q = (index) NB + block.  When they all share
+        // one upper word (every item short of a 2^32 boundary of q), part of
+        // Philox is the item's and is computed once (PhiloxItem)
+        const uint64_t q_first = first_index * NB;
+        const uint64_t q_end = (first_index + wi.count) * NB;  // host: no wrap
+        const bool same_hi = (q_first >> 32) == ((q_end - 1) >> 32);
+        const dev::PhiloxItem pitem = dev::philox_item(static_cast<uint32_t>(q_first >> 32),
+                                                       id_lo, id_hi, seed_lo, seed_hi);
+        const uint32_t q_first_lo = static_cast<uint32_t>(q_first);
+
+        auto samples = [&](auto same_hi_tag) {
+        constexpr bool kSameHi = decltype(same_hi_tag)::value;
         for (uint32_t k = 0; k < a.samples_per_thread; ++k) {
             const uint32_t local = k * BLOCK + tid;
             if (local >= wi.count)
                 break;
             const uint64_t q0 = (first_index + local) * NB;
+            const uint32_t q0_lo = q_first_lo + local * static_cast<uint32_t>(NB);
             uint32_t blk[4];
             uint32_t upper = 0;
             T pbar[AVG ? NR : 1];
@@ -199,6 +212,7 @@ __global__ void __launch_bounds__(BLOCK)
                 pbar[r] = T(0);
             auto gen = [&](int l, T(&out)[NX], T token) {
                 uint64_t qs = q0;
+                uint32_t qs_lo = q0_lo;
                 uint32_t zoff = 0;
                 LdsRow row = (LdsRow)(&map_lds[0][0]);
                 if constexpr (D > 32) {
@@ -206,15 +220,24 @@ __global__ void __launch_bounds__(BLOCK)
                     // action so far, so the compiler cannot generate every slice
                     // (and read the whole map) up front and keep 2d coordinates
                     // and 4d map values live
-                    asm volatile("" : "+v"(qs) : "v"(token));
+                    if constexpr (kSameHi)
+                        asm volatile("" : "+v"(qs_lo) : "v"(token));
+                    else
+                        asm volatile("" : "+v"(qs) : "v"(token));
                     asm volatile("v_mov_b32 %0, 0" : "=v"(zoff) : "v"(token));
                     row += zoff;
                 }
 #pragma unroll
                 for (int m = 0; m < NX; ++m) {
                     const int kk = l * NX + m;
-                    if ((kk & 3) == 0)
-                        dev::philox_block(qs + (kk >> 2), id_lo, id_hi, seed_lo, seed_hi, blk);
+                    if ((kk & 3) == 0) {
+                        if constexpr (kSameHi)
+                            dev::philox_block_item(qs_lo + static_cast<uint32_t>(kk >> 2), pitem,
+                                                   blk);
+                        else
+                            dev::philox_block(qs + (kk >> 2), id_lo, id_hi, seed_lo, seed_hi,
+                                              blk);
+                    }
                     const uint32_t x = blk[kk & 3];
                     if constexpr (SPLIT)
                         upper |= (x >> 31) << kk;
@@ -333,6 +356,11 @@ __global__ void __launch_bounds__(BLOCK)
                 }
             }
         }
+        };
+        if (same_hi)
+            samples(std::true_type{});
+        else
+            samples(std::false_type{});
 
         // ---- reduction: wavefront butterflies, then waves in order through LDS
         float wave_sigma = 0.0f;

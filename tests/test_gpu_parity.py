@@ -153,6 +153,33 @@ def test_ragged_uneven_partition(bfi, ctx, nx, nt):
     assert_sums_close(unshift(got, nx), want, nx, 1e-10)
 
 
+@pytest.mark.parametrize("nx,nt,obs", [(10, 2, 0), (10, 2, 1), (3, 1, 0), (16, 4, 0), (5, 3, 0)])
+def test_counter_upper_word_boundaries(bfi, ctx, nx, nt, obs):
+    """Work items whose Philox counters q = index * ceil(d/4) + block cross a
+    multiple of 2^32 (the upper counter word changes inside the item, and for
+    ceil(d/4) not a power of two inside one sample) beside items that do not:
+    both kinds against the oracle, both precision forms."""
+    d = nx * nt
+    nb = (d + 3) // 4
+    sv = workloads.random_partition(d, 3.0, 8, per_sub=1, seed=d)
+    sv.n[:] = [3000, 20_000, 2, 5, 70_000, 1000, 64 * 256 + 1, 333]
+    starts = []
+    for k, n in zip([1, 2, 5, 7, 1, 3, 2**20, 1], sv.n):
+        b = -(-(k << 32) // nb)          # first sample index with q >= k 2^32
+        starts.append(b - int(n) // 2)   # the range straddles that boundary
+    starts[1] = 0                        # far from any boundary
+    starts[5] = 2**33 // nb              # ends short of it
+    sv.offset[:] = starts
+    lat_o = oracle.lattice(nx, nt, nu=0.7, observable=obs)
+    want = oracle.sums(lat_o, 11, sv.ids, sv.lo, sv.hi, sv.n, sv.offset)
+    lat = bfi.lattice(nx, nt, nu=0.7, observable=obs)
+    got = bfi.bfi_eval(ctx, lat, F64, 11, sv, bfi.launch(8, 64, 0))
+    assert_sums_close(unshift(got, nx), want, nx, 1e-10)
+    got32 = bfi.bfi_eval(ctx, lat, F32, 11, sv, bfi.launch(8, 64, 1))
+    assert_result_close(bfi.bfi_finalize(lat, sv, got32), oracle.finalize(nx, d, sv.lo, sv.hi, want),
+                        1e-4)
+
+
 @pytest.mark.parametrize("launch", [
     dict(samples_per_thread=1, block=64, persistent=0),
     dict(samples_per_thread=7, block=128, persistent=0),
