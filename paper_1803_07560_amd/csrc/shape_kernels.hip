@@ -98,7 +98,12 @@ __global__ void __launch_bounds__(BLOCK)
     constexpr bool kParkFirst = PREC == kFP64 && D > 32;
     __shared__ double park_lds[kParkFirst ? NX : 1][kParkFirst ? BLOCK : 1];
     __shared__ double red[NW][NF];
-    __shared__ T map_lds[2][kHoist ? 1 : D];  // [0]: offsets, [1]: scales
+    // (offset, scale) of each variable side by side: one LDS read with an
+    // immediate offset fetches both
+    struct alignas(2 * sizeof(T)) T2 {
+        T x, y;  // offset, scale
+    };
+    __shared__ T2 map_lds[kHoist ? 1 : D];
     __shared__ float red_sigma[NW];
     __shared__ uint32_t next_item;
 
@@ -150,8 +155,7 @@ __global__ void __launch_bounds__(BLOCK)
             }
         } else {
             for (int kk = tid; kk < D; kk += BLOCK) {
-                map_lds[0][kk] = base_g[kk];
-                map_lds[1][kk] = scale_g[kk];
+                map_lds[kk] = T2{base_g[kk], scale_g[kk]};
             }
             __syncthreads();
         }
@@ -159,18 +163,12 @@ __global__ void __launch_bounds__(BLOCK)
         // carries the slice's dependency on the action so far: the compiler can
         // neither hoist the reads out of the sample loop (4d values live) nor
         // issue them before the slice is due; reads use immediate offsets
-        using LdsRow = const __attribute__((address_space(3))) T *;
-        auto base_of = [&](int kk, LdsRow row) -> T {
+        using LdsRow = const __attribute__((address_space(3))) T2 *;
+        auto map_of = [&](int kk, LdsRow row) -> T2 {
             if constexpr (kHoist)
-                return base_r[kk];
+                return T2{base_r[kk], scale_r[kk]};
             else
-                return row[kk];
-        };
-        auto scale_of = [&](int kk, LdsRow row) -> T {
-            if constexpr (kHoist)
-                return scale_r[kk];
-            else
-                return row[D + kk];
+                return T2{row[kk].x, row[kk].y};  // merged into one LDS read
         };
 
         double acc[NF];
@@ -214,7 +212,7 @@ __global__ void __launch_bounds__(BLOCK)
                 uint64_t qs = q0;
                 uint32_t qs_lo = q0_lo;
                 uint32_t zoff = 0;
-                LdsRow row = (LdsRow)(&map_lds[0][0]);
+                LdsRow row = (LdsRow)(&map_lds[0]);
                 if constexpr (D > 32) {
                     // make this slice's counters and map reads depend on the
                     // action so far, so the compiler cannot generate every slice
@@ -241,7 +239,8 @@ __global__ void __launch_bounds__(BLOCK)
                     const uint32_t x = blk[kk & 3];
                     if constexpr (SPLIT)
                         upper |= (x >> 31) << kk;
-                    out[m] = dev::map_word(x, scale_of(kk, row), base_of(kk, row));
+                    const T2 mp = map_of(kk, row);
+                    out[m] = dev::map_word(x, mp.y, mp.x);
                 }
                 if constexpr (AVG) {
 #pragma unroll
