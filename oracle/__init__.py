@@ -22,12 +22,13 @@ _lib = None
 class Lattice(C.Structure):
     """Parameters of Eq. Gen2: nx space sites (M), nt time slices (L), nu, D, a, tau,
     plus the test knobs g (nonlinear coupling, 1 in the paper) and m2 (mass term, 0),
-    and the observable behind C(r): 0 anchored at the first site, 1 averaged over
-    all anchors."""
+    the observable behind C(r): 0 anchored at the first site, 1 averaged over
+    all anchors, and antithetic: 1 makes every sample index a pair of points (the
+    point of its words and of the complemented words) whose means the records sum."""
 
     _fields_ = [("nx", C.c_int32), ("nt", C.c_int32), ("nu", C.c_double), ("D", C.c_double),
                 ("a", C.c_double), ("tau", C.c_double), ("g", C.c_double), ("m2", C.c_double),
-                ("observable", C.c_int32)]
+                ("observable", C.c_int32), ("antithetic", C.c_int32)]
 
     @property
     def d(self) -> int:
@@ -37,9 +38,10 @@ class Lattice(C.Structure):
 OBS_ANCHOR, OBS_AVERAGED = 0, 1
 
 
-def lattice(nx, nt, nu=1.0, D=1.0, a=1.0, tau=1.0, g=1.0, m2=0.0, observable=0) -> Lattice:
+def lattice(nx, nt, nu=1.0, D=1.0, a=1.0, tau=1.0, g=1.0, m2=0.0, observable=0,
+            antithetic=0) -> Lattice:
     return Lattice(int(nx), int(nt), float(nu), float(D), float(a), float(tau), float(g), float(m2),
-                   int(observable))
+                   int(observable), int(antithetic))
 
 
 def sums_len(nx: int) -> int:
@@ -195,7 +197,9 @@ def split_sums(lat: Lattice, seed: int, ids, lo, hi, n, offset=0, nthreads: int 
     return out
 
 
-def finalize(nx: int, d: int, lo, hi, sums_records) -> dict:
+def finalize(nx: int, d: int, lo, hi, sums_records, evals_per_sample: int = 1) -> dict:
+    """Z, C(r) and their errors; n_evals counts evals_per_sample integrand
+    evaluations per record sample (2 for antithetic pairs)."""
     s = np.ascontiguousarray(sums_records, dtype=np.float64).reshape(-1, sums_len(nx))
     ns = s.shape[0]
     lo = np.ascontiguousarray(lo, dtype=np.float64).reshape(ns, d)
@@ -205,7 +209,8 @@ def finalize(nx: int, d: int, lo, hi, sums_records) -> dict:
                                _ptr(s, C.c_double), _ptr(out, C.c_double))
     if rc != 0:
         raise ValueError(f"oracle_finalize failed ({rc})")
-    return {"Z": out[0], "Z_err": out[1], "log_Z": out[2], "ess": out[3], "n_evals": out[4],
+    return {"Z": out[0], "Z_err": out[1], "log_Z": out[2], "ess": out[3],
+            "n_evals": out[4] * evals_per_sample,
             "C": out[5:5 + nx].copy(), "C_err": out[5 + nx:5 + 2 * nx].copy()}
 
 
@@ -234,11 +239,14 @@ def budget_split(budget: int, count: int) -> np.ndarray:
 
 def integrate_uniform(lat: Lattice, seed: int, box_lo, box_hi, k: int, budget: int,
                       nthreads: int | None = None) -> dict:
-    """Oracle of the uniform-split convenience entry: plan, sums, finalize."""
+    """Oracle of the uniform-split convenience entry: plan, sums, finalize.  The
+    budget counts integrand evaluations: with antithetic pairs, budget // 2 pairs
+    are split over the subvolumes."""
     ids, lo, hi = plan_uniform(lat.d, box_lo, box_hi, k)
-    n = budget_split(budget, len(ids))
+    per = 2 if lat.antithetic else 1
+    n = budget_split(budget // per, len(ids))
     s = sums(lat, seed, ids, lo, hi, n, 0, nthreads)
-    res = finalize(lat.nx, lat.d, lo, hi, s)
+    res = finalize(lat.nx, lat.d, lo, hi, s, per)
     res["sums"] = s
     return res
 

@@ -108,6 +108,8 @@ static int lattice_ok(const oracle_lattice *lat)
         return 0;
     if (lat->observable != ORACLE_OBS_ANCHOR && lat->observable != ORACLE_OBS_AVERAGED)
         return 0;
+    if (lat->antithetic != 0 && lat->antithetic != 1)
+        return 0;
     return 1;
 }
 
@@ -240,7 +242,10 @@ static void subvolume_sums(const sums_job *job, size_t s)
     double *scale = (double *)malloc(sizeof(double) * (size_t)d);
     double *base = (double *)malloc(sizeof(double) * (size_t)d);
     double *p = (double *)malloc(sizeof(double) * (size_t)nx);
+    double *ub = (double *)malloc(sizeof(double) * (size_t)d);
+    double *pb = (double *)malloc(sizeof(double) * (size_t)nx);
     box_map(d, lo, hi, scale, base);
+    const int pairs = lat->antithetic && !job->split;
 
     /* record layout: n, w, w^2, p_r w, (p_r w)^2, p_r w^2 -- or, for the split
      * statistics, sum_U w and sum_U w^2 per dimension */
@@ -262,10 +267,29 @@ static void subvolume_sums(const sums_job *job, size_t s)
             }
             continue;
         }
+        oracle_observable(lat, u, p);
+        if (pairs) {
+            /* the partner point: the complemented words through the same map */
+            for (int32_t k = 0; k < d; ++k)
+                ub[k] = fma((double)(0xFFFFFFFFu - x[k]), scale[k], base[k]);
+            const double wb = exp(-oracle_action(lat, ub));
+            oracle_observable(lat, ub, pb);
+            for (int32_t r = 0; r < nx; ++r)
+                p[r] = 0.5 * (p[r] * w + pb[r] * wb); /* now the pair's p_r w */
+            w = 0.5 * (w + wb);
+            nm_add(&acc[0], 1.0);
+            nm_add(&acc[1], w);
+            nm_add(&acc[2], w * w);
+            for (int32_t r = 0; r < nx; ++r) {
+                nm_add(&acc[3 + r], p[r]);
+                nm_add(&acc[3 + nx + r], p[r] * p[r]);
+                nm_add(&acc[3 + 2 * nx + r], p[r] * w);
+            }
+            continue;
+        }
         nm_add(&acc[0], 1.0);
         nm_add(&acc[1], w);
         nm_add(&acc[2], w * w);
-        oracle_observable(lat, u, p);
         for (int32_t r = 0; r < nx; ++r) {
             double pw = p[r] * w;
             nm_add(&acc[3 + r], pw);
@@ -282,6 +306,8 @@ static void subvolume_sums(const sums_job *job, size_t s)
     free(scale);
     free(base);
     free(p);
+    free(ub);
+    free(pb);
 }
 
 static void *sums_worker(void *arg)
@@ -302,6 +328,8 @@ static int run_sums(const oracle_lattice *lat, uint64_t seed, size_t nsub, const
                     double gaussian_fraction)
 {
     if (!lattice_ok(lat))
+        return -1;
+    if (split && lat->antithetic) /* pairs: plain sums records only */
         return -1;
     if (nsub == 0)
         return 0;

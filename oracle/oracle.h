@@ -27,12 +27,15 @@ extern "C" {
 /* Parameters of the discretised action (Eq. Gen2 and the constants after it).
  * g multiplies the nonlinear term (1 in the paper; 0 gives the Gaussian case)
  * and m2 adds (m2/2)*sum(u^2) (0 in the paper; a regulator for closed forms).
- * observable selects the per-sample product p_r behind C(r) (oracle_observable). */
+ * observable selects the per-sample product p_r behind C(r) (oracle_observable).
+ * antithetic = 1 turns each sample index into a pair of points (see
+ * ORACLE_SUMS_LEN). */
 typedef struct {
     int32_t nx, nt;
     double nu, D, a, tau;
     double g, m2;
     int32_t observable;
+    int32_t antithetic;
 } oracle_lattice;
 
 /* p_r as the section 4 correlation is written: the product of the velocity at
@@ -45,7 +48,14 @@ typedef struct {
 
 /* Number of doubles in one per-subvolume sums record:
  * [n, sum w, sum w^2, sum p_r w (nx), sum (p_r w)^2 (nx), sum p_r w^2 (nx)]
- * with p_r from oracle_observable. */
+ * with p_r from oracle_observable.
+ * Antithetic pairs (lattice antithetic = 1; antithetic variates applied to the
+ * plain estimate of section 3): sample index i gives the point u of its words x
+ * and the point u' of the complemented words 0xFFFFFFFF - x, which the same map
+ * places at lo + hi - u (the reflection through the subvolume's centre).  The
+ * record then runs over pairs: n counts pairs, w stands for the pair mean
+ * (w(u) + w(u'))/2 and p_r w for (p_r(u) w(u) + p_r(u') w(u'))/2; the products
+ * are those of these means.  Each pair is two integrand evaluations. */
 #define ORACLE_SUMS_LEN(nx) (3 + 3 * (nx))
 
 /* Number of doubles in the finalize output:
