@@ -87,6 +87,20 @@ typedef struct {
     double g;            /* nonlinear coupling, 1 for Burgers */
     double m2;           /* mass term, 0 for Burgers */
     int32_t observable;  /* bfi_observable; 0 (anchored) is the paper's product */
+    int32_t antithetic;  /* 0: one point per sample index (the paper's plain Monte
+                            Carlo, section 3).  1: antithetic pairs: sample index i
+                            gives the point of its Philox words x and the point of
+                            the complemented words 0xFFFFFFFF - x, which the same map
+                            puts at lo + hi - u (the reflection through the
+                            subvolume's centre); records then run over pairs (n
+                            counts pairs, w and p_r w are the pair means) and each
+                            pair is two integrand evaluations.  The two points share
+                            one Philox evaluation; their weights are nearly
+                            uncorrelated on subvolumes that are not centred at 0 (on
+                            a box centred at 0, u' = -u only flips the sign of the
+                            nonlinear term).  Supported by bfi_eval (without split
+                            statistics), plans, bfi_integrate and bfi_finalize, for
+                            d <= 32; the other entry points return EUNSUPPORTED. */
 } bfi_lattice;
 
 /* A list of subvolumes (host arrays, caller-owned).
@@ -203,14 +217,17 @@ bfi_status bfi_partials_merge(int32_t nx, size_t count, double *acc, const doubl
 
 /* Combine partial records into Z, C(r) and their errors (section 4's
  * normalisation; delta method for the ratio).  Host only.  The subvolume list
- * supplies the volumes.  Errors: EINVAL (n < 2, bad box). */
+ * supplies the volumes; n_evals counts two evaluations per record sample when
+ * lat->antithetic is set.  Errors: EINVAL (n < 2, bad box). */
 bfi_status bfi_finalize(const bfi_lattice *lat, const bfi_subvolumes *subs,
                         const double *partials, bfi_result *out);
 
 /* Convenience: split [box_lo, box_hi] into 2^split_log2 subvolumes by bisecting
  * dims 0, 1, ... in turn (dim t mod d at level t; heap ids 2^k .. 2^(k+1)-1),
  * give subvolume i (id order) floor(budget/2^k) + (i < budget mod 2^k) samples
- * from offset 0, evaluate and finalize.  box_lo/box_hi: host, d doubles. */
+ * from offset 0, evaluate and finalize.  box_lo/box_hi: host, d doubles.  The
+ * budget counts integrand evaluations: with antithetic pairs, budget/2 (rounded
+ * down) sample indices are split that way. */
 bfi_status bfi_integrate(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
                          uint64_t seed, const double *box_lo, const double *box_hi,
                          int32_t split_log2, uint64_t budget, const bfi_launch *launch,

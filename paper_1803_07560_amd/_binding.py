@@ -40,7 +40,7 @@ class BfiError(RuntimeError):
 class bfi_lattice(C.Structure):
     _fields_ = [("nx", C.c_int32), ("nt", C.c_int32), ("nu", C.c_double), ("D", C.c_double),
                 ("a", C.c_double), ("tau", C.c_double), ("g", C.c_double), ("m2", C.c_double),
-                ("observable", C.c_int32)]
+                ("observable", C.c_int32), ("antithetic", C.c_int32)]
 
     @property
     def d(self) -> int:
@@ -243,11 +243,12 @@ def _prec(p) -> int:
 
 
 def lattice(nx, nt, nu=1.0, D=1.0, a=1.0, tau=1.0, g=1.0, m2=0.0,
-            observable="anchor") -> bfi_lattice:
-    """observable: "anchor" (u_{0,0} u_{0,r}, the paper's) or "averaged" (over all anchors)."""
+            observable="anchor", antithetic=False) -> bfi_lattice:
+    """observable: "anchor" (u_{0,0} u_{0,r}, the paper's) or "averaged" (over all anchors);
+    antithetic: each sample index gives a pair of points (see bfi_lattice)."""
     obs = {"anchor": BFI_OBS_ANCHOR, "averaged": BFI_OBS_AVERAGED}.get(observable, observable)
     return bfi_lattice(int(nx), int(nt), float(nu), float(D), float(a), float(tau), float(g),
-                       float(m2), int(obs))
+                       float(m2), int(obs), int(antithetic))
 
 
 def launch(samples_per_thread=0, block=0, persistent=-1, use_graph=0) -> bfi_launch:

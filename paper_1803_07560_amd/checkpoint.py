@@ -3,8 +3,8 @@
 Every point is addressed by (seed, subvolume id, sample index) through the
 counter-based Philox stream, so the whole state of a run (paper section 3: each
 subvolume's integral is estimated from its own samples) is
-  * the lattice (the parameters of Eq. Gen2 and the observable), the precision
-    and the seed,
+  * the lattice (the parameters of Eq. Gen2, the observable and the sampler:
+    single points or antithetic pairs), the precision and the seed,
   * the subvolume list (ids, boxes) with the range of sample indices evaluated
     so far, [offset, offset + n) per subvolume,
   * the partial records of those samples.
@@ -24,7 +24,7 @@ import numpy as np
 from . import _binding as _b
 
 FORMAT = "bfi-checkpoint-1"
-_LATTICE_FIELDS = ("nx", "nt", "nu", "D", "a", "tau", "g", "m2", "observable")
+_LATTICE_FIELDS = ("nx", "nt", "nu", "D", "a", "tau", "g", "m2", "observable", "antithetic")
 
 
 @dataclass
@@ -37,7 +37,7 @@ class RunState:
 
     @property
     def evals(self) -> int:
-        return int(self.subs.n.sum())
+        return int(self.subs.n.sum()) * (2 if self.lat.antithetic else 1)
 
 
 def _prec_name(prec) -> str:
@@ -107,7 +107,7 @@ def from_json(text: str) -> RunState:
     L = doc["lattice"]
     lat = _b.bfi_lattice(int(L["nx"]), int(L["nt"]),
                          *(float.fromhex(L[f]) for f in ("nu", "D", "a", "tau", "g", "m2")),
-                         int(L["observable"]))
+                         int(L["observable"]), int(L.get("antithetic", 0)))
     cnt, d, nx = int(doc["count"]), lat.d, lat.nx
     sizes = {"id": cnt, "lo": cnt * d, "hi": cnt * d, "n": cnt, "offset": cnt,
              "partials": cnt * _b.partial_len(nx)}

@@ -248,6 +248,8 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         return fail(BFI_EINVAL, "unknown precision");
     BFI_TRY(check_lattice(lat));
     BFI_TRY(check_config(cfg));
+    if (lat->antithetic)
+        return fail(BFI_EUNSUPPORTED, "adaptive refinement uses single points (antithetic = 0)");
     const int nx = lat->nx, d = nx * lat->nt;
     if (d > 32)
         return fail(BFI_EUNSUPPORTED, "adaptive refinement needs d <= 32 (split statistics)");
@@ -480,6 +482,8 @@ bfi_status bfi_adaptive_decide(const bfi_lattice *lat, const bfi_subvolumes *lea
     if (!lat || !leaves || !partials || !split || !action)
         return fail(BFI_EINVAL, "arguments must be non-NULL");
     BFI_TRY(check_config(cfg));
+    if (lat->antithetic)
+        return fail(BFI_EUNSUPPORTED, "adaptive refinement uses single points (antithetic = 0)");
     if (lat->nx < 1 || lat->nt < 1 || lat->nx * lat->nt > 32)
         return fail(BFI_EINVAL, "adaptive refinement needs 1 <= d <= 32");
     if (leaves->count == 0)

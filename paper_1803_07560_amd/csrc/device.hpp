@@ -216,6 +216,52 @@ __device__ __forceinline__ T action(Gen &&gen, T (&first)[NX], const Coef<T> &c,
     return S;
 }
 
+// The actions of an antithetic pair: gen(l, a, b, token) writes time slice l of
+// both points (from the same words), slice by slice as in action().
+template <class T, int NX, int NT, class Gen>
+__device__ __forceinline__ void action_pair(Gen &&gen, T (&first_a)[NX], T (&first_b)[NX],
+                                            const Coef<T> &c, bool mass, T &s_a, T &s_b)
+{
+    gen(0, first_a, first_b, T(0));
+    T cur_a[NX], cur_b[NX];
+#pragma unroll
+    for (int m = 0; m < NX; ++m) {
+        cur_a[m] = first_a[m];
+        cur_b[m] = first_b[m];
+    }
+    T r2a = T(0), r2b = T(0), u2a = T(0), u2b = T(0);
+#pragma unroll
+    for (int l = 0; l < NT; ++l) {
+        T nxt_a[NX], nxt_b[NX];
+        if (l + 1 < NT) {
+            gen(l + 1, nxt_a, nxt_b, r2a + r2b);
+        } else {
+#pragma unroll
+            for (int m = 0; m < NX; ++m) {
+                nxt_a[m] = first_a[m];
+                nxt_b[m] = first_b[m];
+            }
+        }
+        r2a = slice_r2<T, NX>(cur_a, nxt_a, c, r2a);
+        r2b = slice_r2<T, NX>(cur_b, nxt_b, c, r2b);
+        if (mass) {
+            u2a = slice_u2<T, NX>(cur_a, u2a);
+            u2b = slice_u2<T, NX>(cur_b, u2b);
+        }
+#pragma unroll
+        for (int m = 0; m < NX; ++m) {
+            cur_a[m] = nxt_a[m];
+            cur_b[m] = nxt_b[m];
+        }
+    }
+    s_a = r2a * c.inv_2Dtau;
+    s_b = r2b * c.inv_2Dtau;
+    if (mass) {
+        s_a = fma_t(c.half_m2, u2a, s_a);
+        s_b = fma_t(c.half_m2, u2b, s_b);
+    }
+}
+
 // Load a value every lane of the wavefront reads at the same address and keep
 // it in scalar registers: the struct is read dword by dword and each dword is
 // made wave-uniform, so the compiler holds it in SGPRs instead of VGPRs.

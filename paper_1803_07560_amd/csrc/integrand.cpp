@@ -29,6 +29,8 @@ bfi_status check_integrand(const bfi_integrand *f, int *d)
     case BFI_INTEGRAND_BURGERS_Z:
     case BFI_INTEGRAND_BURGERS_N:
         BFI_TRY(check_lattice(&f->lat));
+        if (f->lat.antithetic)
+            return fail(BFI_EUNSUPPORTED, "the integrand protocol uses single points");
         if (f->prec != BFI_FP64 && f->prec != BFI_FP32_SHIFTED)
             return fail(BFI_EINVAL, "unknown precision");
         *d = f->lat.nx * f->lat.nt;

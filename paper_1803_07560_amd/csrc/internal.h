@@ -62,7 +62,11 @@ struct LaunchSpec {
     int persistent;  // 0/1
     uint32_t grid;   // blocks
     int obs = 0;     // bfi_observable: 0 anchored product, 1 averaged over anchors
+    int pair = 0;    // 1: antithetic pairs (d <= kMaxPairD, no split statistics)
 };
+
+// Largest lattice the antithetic-pair kernels are compiled for.
+constexpr int kMaxPairD = 32;
 
 struct MergeArgs {
     const double *item_rec;     // nitems x rec_len

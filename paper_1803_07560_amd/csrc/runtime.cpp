@@ -146,8 +146,12 @@ bfi_status check_lattice(const bfi_lattice *lat)
         return fail(BFI_EINVAL, "m2 must be >= 0");
     if (lat->observable != BFI_OBS_ANCHOR && lat->observable != BFI_OBS_AVERAGED)
         return fail(BFI_EINVAL, "unknown observable %d", lat->observable);
+    if (lat->antithetic != 0 && lat->antithetic != 1)
+        return fail(BFI_EINVAL, "antithetic must be 0 or 1 (got %d)", lat->antithetic);
     if (!shape_compiled(lat->nx, lat->nt))
         return fail(BFI_EUNSUPPORTED, "lattice %dx%d has no compiled kernel", lat->nx, lat->nt);
+    if (lat->antithetic && lat->nx * lat->nt > kMaxPairD)
+        return fail(BFI_EUNSUPPORTED, "antithetic pairs are compiled for d <= %d", kMaxPairD);
     return BFI_OK;
 }
 
@@ -257,7 +261,7 @@ bfi_launch resolve_launch(const bfi_context *ctx, const bfi_lattice &lat, int pr
 }
 
 bfi_status finalize_records(int nx, int d, size_t nsub, const double *lo, const double *hi,
-                            const double *partials, bfi_result *out)
+                            const double *partials, bfi_result *out, int evals_per_sample)
 {
     if (!out)
         return fail(BFI_EINVAL, "result is NULL");
@@ -306,7 +310,7 @@ bfi_status finalize_records(int nx, int d, size_t nsub, const double *lo, const 
     out->Z = std::exp(out->log_Z);
     out->Z_err = std::sqrt(std::max(varZ.v(), 0.0)) * std::exp(-sig);
     out->ess = wsq.v() > 0 ? z * z / wsq.v() : 0.0;
-    out->n_evals = nev.v();
+    out->n_evals = nev.v() * evals_per_sample;
     for (int r = 0; r < nx; ++r) {
         Nm N;
         for (size_t s = 0; s < nsub; ++s) {
@@ -442,6 +446,8 @@ bfi_status plan_build_core(bfi_context *ctx, int kind, const bfi_lattice &lat, i
         }
         n_evals += subs.n[s];
     }
+    if (lat.antithetic)
+        n_evals *= 2;  // two points per sample index
     first[subs.size()] = static_cast<uint32_t>(items.size());
 
     // point map descriptors: scale = (hi - lo) 2^-32, base = lo + scale/2
@@ -531,7 +537,8 @@ bfi_status plan_build_core(bfi_context *ctx, int kind, const bfi_lattice &lat, i
     if (l.persistent) {
         KernelInfo info{};
         if (kind == 0 || kind == 2) {
-            LaunchSpec spec{prec, l.block, split ? 1 : 0, 1, 0, lat.observable};
+            LaunchSpec spec{prec, l.block, split ? 1 : 0, 1, 0, lat.observable,
+                            lat.antithetic};
             e = kind == 0 ? kernel_info(lat.nx, lat.nt, spec, &info)
                           : is_kernel_info(lat.nx, lat.nt, spec, &info);
             if (e != hipSuccess)
@@ -574,8 +581,8 @@ bfi_status plan_enqueue(bfi_plan *p, uint64_t seed, double *dst, hipStream_t st,
     a.queue_head = p->launch.persistent ? p->d_head : nullptr;
     a.nitems = p->nitems;
     a.samples_per_thread = static_cast<uint32_t>(p->launch.samples_per_thread);
-    LaunchSpec spec{p->prec,  p->launch.block, p->split ? 1 : 0, p->launch.persistent,
-                    p->grid,  p->lat.observable};
+    LaunchSpec spec{p->prec,  p->launch.block,    p->split ? 1 : 0, p->launch.persistent,
+                    p->grid,  p->lat.observable, p->lat.antithetic};
     if (p->launch.persistent)
         BFI_HIP(launch_reset_head(p->d_head, st));
     if (timed)
@@ -802,6 +809,8 @@ bfi_status bfi_eval(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec
         return fail(BFI_EINVAL, "unknown precision %d", static_cast<int>(prec));
     BFI_TRY(check_lattice(lat));
     BFI_TRY(check_subvolumes(lat, subs));
+    if (lat->antithetic && split)
+        return fail(BFI_EUNSUPPORTED, "antithetic pairs have no split statistics");
     if (subs->count == 0)
         return BFI_OK;
     BFI_HIP(hipSetDevice(ctx->device));
@@ -835,8 +844,10 @@ bfi_status bfi_finalize(const bfi_lattice *lat, const bfi_subvolumes *subs,
         return fail(BFI_EINVAL, "lattice out of range");
     if (subs->count && (!subs->lo || !subs->hi))
         return fail(BFI_EINVAL, "subvolume boxes must be non-NULL");
+    if (lat->antithetic != 0 && lat->antithetic != 1)
+        return fail(BFI_EINVAL, "antithetic must be 0 or 1 (got %d)", lat->antithetic);
     return finalize_records(lat->nx, lat->nx * lat->nt, subs->count, subs->lo, subs->hi,
-                            partials, out);
+                            partials, out, lat->antithetic ? 2 : 1);
 }
 
 bfi_status bfi_integrate(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
@@ -853,14 +864,16 @@ bfi_status bfi_integrate(bfi_context *ctx, const bfi_lattice *lat, bfi_precision
     for (int k = 0; k < d; ++k)
         if (!std::isfinite(box_lo[k]) || !std::isfinite(box_hi[k]) || !(box_lo[k] < box_hi[k]))
             return fail(BFI_EINVAL, "box dim %d: need finite lo < hi", k);
-    if (budget < 2 * (uint64_t(1) << split_log2))
+    // the budget counts integrand evaluations: two per antithetic pair
+    const uint64_t per = lat->antithetic ? 2 : 1;
+    if (budget / per < 2 * (uint64_t(1) << split_log2))
         return fail(BFI_EINVAL, "budget must give every subvolume at least 2 samples");
-    SubList subs = uniform_split(d, box_lo, box_hi, split_log2, budget);
+    SubList subs = uniform_split(d, box_lo, box_hi, split_log2, budget / per);
     std::vector<double> partials(subs.size() * BFI_PARTIAL_LEN(lat->nx));
     bfi_subvolumes v = subs.view();
     BFI_TRY(bfi_eval(ctx, lat, prec, seed, &v, launch, partials.data(), nullptr));
     return finalize_records(lat->nx, d, subs.size(), subs.lo.data(), subs.hi.data(),
-                            partials.data(), out);
+                            partials.data(), out, static_cast<int>(per));
 }
 
 bfi_status bfi_debug_points(bfi_context *ctx, int32_t d, bfi_precision prec, uint64_t seed,

@@ -81,8 +81,10 @@ bfi_launch resolve_launch(const bfi_context *ctx, const bfi_lattice &lat, int pr
                           const bfi_launch *req);
 
 // Host finalize of partial records (see bfi_finalize).
+// evals_per_sample: integrand evaluations behind one record sample (2 for
+// antithetic pairs), for n_evals.
 bfi_status finalize_records(int nx, int d, size_t nsub, const double *lo, const double *hi,
-                            const double *partials, bfi_result *out);
+                            const double *partials, bfi_result *out, int evals_per_sample = 1);
 
 }  // namespace bfi
 

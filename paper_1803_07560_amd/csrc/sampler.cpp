@@ -64,6 +64,8 @@ void modes_of(const bfi_lattice &lat, double lo, double hi, Modes *m)
 bfi_status check_args(const bfi_lattice *lat, int prec, double lo, double hi, double alpha)
 {
     BFI_TRY(check_lattice(lat));
+    if (lat->antithetic)
+        return fail(BFI_EUNSUPPORTED, "the Gaussian-proposal sampler draws single points");
     if (lat->nx * lat->nt > kIsMaxD)
         return fail(BFI_EUNSUPPORTED, "the Gaussian-proposal sampler is compiled for d <= %d",
                     kIsMaxD);

@@ -70,12 +70,14 @@ struct Fields {
 
 // Waves per SIMD the register allocation must leave room for: without a floor
 // the compiler spends the whole register file of one wave on large lattices.
-template <int NX, int NT>
-constexpr int kMinWaves = NX * NT > 32 ? 2 : 1;
+// FP32-form antithetic pairs (two points in registers) are held to three waves
+// per SIMD, the occupancy of the single-point kernel.
+template <int NX, int NT, int PREC, bool PAIR>
+constexpr int kMinWaves = NX * NT > 32 ? 2 : (PAIR && PREC != kFP64 ? 3 : 1);
 
-template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG>
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG, bool PAIR>
 __global__ void __launch_bounds__(BLOCK)
-    __attribute__((amdgpu_waves_per_eu(kMinWaves<NX, NT>))) mc_kernel(McArgs a)
+    __attribute__((amdgpu_waves_per_eu(kMinWaves<NX, NT, PREC, PAIR>))) mc_kernel(McArgs a)
 {
     using T = std::conditional_t<PREC == kFP64, double, float>;
     constexpr int D = NX * NT;
@@ -89,6 +91,7 @@ __global__ void __launch_bounds__(BLOCK)
     constexpr bool kHalfPair = AVG && NX % 2 == 0 && NX > 1;
     const T inv_sites = T(1) / T(D);
     static_assert(!SPLIT || D <= 32, "split statistics keep one bit per dimension in 32 bits");
+    static_assert(!PAIR || (!SPLIT && D <= kMaxPairD), "antithetic pairs: d <= 32, no split");
 
     // point map held in registers when 2d values take at most 80 VGPRs
     constexpr bool kHoist = 2 * D * sizeof(T) / 4 <= 80;
@@ -202,6 +205,97 @@ __global__ void __launch_bounds__(BLOCK)
                 break;
             const uint64_t q0 = (first_index + local) * NB;
             const uint32_t q0_lo = q_first_lo + local * static_cast<uint32_t>(NB);
+            if constexpr (PAIR) {
+                // antithetic pair: the point of the words and the point of the
+                // complemented words, i.e. its reflection through the centre of
+                // the subvolume; the record sums the pair means
+                T pbar_a[AVG ? NR : 1], pbar_b[AVG ? NR : 1];
+#pragma unroll
+                for (int r = 0; r < (AVG ? NR : 1); ++r)
+                    pbar_a[r] = pbar_b[r] = T(0);
+                uint32_t wb[4];
+                const LdsRow row = (LdsRow)(&map_lds[0]);
+                auto gen2 = [&](int l, T(&oa)[NX], T(&ob)[NX], T) {
+#pragma unroll
+                    for (int m = 0; m < NX; ++m) {
+                        const int kk = l * NX + m;
+                        if ((kk & 3) == 0) {
+                            if constexpr (kSameHi)
+                                dev::philox_block_item(q0_lo + static_cast<uint32_t>(kk >> 2),
+                                                       pitem, wb);
+                            else
+                                dev::philox_block(q0 + (kk >> 2), id_lo, id_hi, seed_lo,
+                                                  seed_hi, wb);
+                        }
+                        const uint32_t x = wb[kk & 3];
+                        const T2 mp = map_of(kk, row);
+                        oa[m] = dev::map_word(x, mp.y, mp.x);
+                        ob[m] = dev::map_word(~x, mp.y, mp.x);
+                    }
+                    if constexpr (AVG) {
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) {
+                            const int terms = kHalfPair && 2 * r == NX ? NX / 2 : NX;
+#pragma unroll
+                            for (int m = 0; m < terms; ++m) {
+                                pbar_a[r] = dev::fma_t(oa[m], oa[(m + r) % NX], pbar_a[r]);
+                                pbar_b[r] = dev::fma_t(ob[m], ob[(m + r) % NX], pbar_b[r]);
+                            }
+                        }
+                    }
+                };
+                T fa[NX], fb[NX], sa, sb;
+                dev::action_pair<T, NX, NT>(gen2, fa, fb, coef, mass, sa, sb);
+                T pra[NR], prb[NR], psa, psb;
+                if constexpr (AVG) {
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        const bool dbl = kHalfPair && 2 * r == NX;
+                        pra[r] = dbl ? T(2) * pbar_a[r] : pbar_a[r];
+                        prb[r] = dbl ? T(2) * pbar_b[r] : pbar_b[r];
+                    }
+                    psa = psb = inv_sites;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        pra[r] = fa[r];
+                        prb[r] = fb[r];
+                    }
+                    psa = fa[0];
+                    psb = fb[0];
+                }
+                double w, v[NR];
+                if constexpr (PREC == kFP64) {
+                    const double wa = exp(-sa), wbt = exp(-sb);
+                    w = 0.5 * (wa + wbt);
+                    const double ta = psa * wa, tb = psb * wbt;
+#pragma unroll
+                    for (int r = 0; r < NR; ++r)
+                        v[r] = 0.5 * __fma_rn(ta, pra[r], tb * prb[r]);
+                } else {
+                    const float smin = fminf(sa, sb);
+                    if (smin < sigma - kShiftGap) {
+                        rescale(exp(static_cast<double>(smin) - static_cast<double>(sigma)));
+                        sigma = smin;
+                    }
+                    const float wa = __builtin_amdgcn_exp2f((sigma - sa) * kLog2e);
+                    const float wbt = __builtin_amdgcn_exp2f((sigma - sb) * kLog2e);
+                    w = static_cast<double>(0.5f * (wa + wbt));
+                    const float ta = psa * wa, tb = psb * wbt;
+#pragma unroll
+                    for (int r = 0; r < NR; ++r)
+                        v[r] = static_cast<double>(0.5f * __fmaf_rn(ta, pra[r], tb * prb[r]));
+                }
+                acc[0] += w;
+                acc[1] = __fma_rn(w, w, acc[1]);
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    acc[2 + r] += v[r];
+                    acc[2 + NR + r] = __fma_rn(v[r], v[r], acc[2 + NR + r]);
+                    acc[2 + 2 * NR + r] = __fma_rn(v[r], w, acc[2 + 2 * NR + r]);
+                }
+                continue;
+            }
             uint32_t blk[4];
             uint32_t upper = 0;
             T pbar[AVG ? NR : 1];
@@ -443,25 +537,25 @@ __global__ void __launch_bounds__(256) debug_action_kernel(DebugActionArgs a)
     a.out[i] = static_cast<double>(dev::action<T, NX, NT>(gen, first, coef, a.coef.half_m2 != 0.0));
 }
 
-template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG>
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG, bool PAIR>
 hipError_t launch_one(const LaunchSpec &spec, const McArgs &args, hipStream_t stream)
 {
-    hipLaunchKernelGGL((mc_kernel<NX, NT, PREC, BLOCK, SPLIT, AVG>), dim3(spec.grid), dim3(BLOCK),
-                       0, stream, args);
+    hipLaunchKernelGGL((mc_kernel<NX, NT, PREC, BLOCK, SPLIT, AVG, PAIR>), dim3(spec.grid),
+                       dim3(BLOCK), 0, stream, args);
     return hipGetLastError();
 }
 
-template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG>
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG, bool PAIR>
 hipError_t info_one(KernelInfo *info)
 {
     hipFuncAttributes attr;
     hipError_t e = hipFuncGetAttributes(
-        &attr, reinterpret_cast<const void *>(&mc_kernel<NX, NT, PREC, BLOCK, SPLIT, AVG>));
+        &attr, reinterpret_cast<const void *>(&mc_kernel<NX, NT, PREC, BLOCK, SPLIT, AVG, PAIR>));
     if (e != hipSuccess)
         return e;
     int blocks = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &blocks, mc_kernel<NX, NT, PREC, BLOCK, SPLIT, AVG>, BLOCK, 0);
+        &blocks, mc_kernel<NX, NT, PREC, BLOCK, SPLIT, AVG, PAIR>, BLOCK, 0);
     if (e != hipSuccess)
         return e;
     info->vgprs = attr.numRegs;
@@ -470,66 +564,76 @@ hipError_t info_one(KernelInfo *info)
     return hipSuccess;
 }
 
-// Dispatch over (precision, block, split) for this shape and observable.
-// Split statistics are compiled for 256-thread blocks and d <= 32 only.
-template <int NX, int NT, bool AVG, template <int, int, int, int, bool, bool> class Op,
+// Dispatch over (precision, block, split) for this shape, observable and
+// sampler.  Split statistics are compiled for 256-thread blocks and d <= 32
+// only; antithetic pairs for d <= kMaxPairD and without split statistics.
+template <int NX, int NT, bool AVG, bool PAIR, template <int, int, int, int, bool, bool, bool> class Op,
           class... Args>
 hipError_t dispatch_obs(const LaunchSpec &spec, Args &&...args)
 {
     constexpr int D = NX * NT;
     if (spec.split) {
-        if constexpr (D <= 32) {
+        if constexpr (D <= 32 && !PAIR) {
             if (spec.block != 256)
                 return hipErrorInvalidValue;
             return spec.prec == kFP64
-                       ? Op<NX, NT, kFP64, 256, true, AVG>::run(spec, args...)
-                       : Op<NX, NT, kFP32Shifted, 256, true, AVG>::run(spec, args...);
+                       ? Op<NX, NT, kFP64, 256, true, AVG, false>::run(spec, args...)
+                       : Op<NX, NT, kFP32Shifted, 256, true, AVG, false>::run(spec, args...);
         } else {
             return hipErrorNotSupported;
         }
     }
-    const bool f64 = spec.prec == kFP64;
-    switch (spec.block) {
-    case 64:
-        return f64 ? Op<NX, NT, kFP64, 64, false, AVG>::run(spec, args...)
-                   : Op<NX, NT, kFP32Shifted, 64, false, AVG>::run(spec, args...);
-    case 128:
-        return f64 ? Op<NX, NT, kFP64, 128, false, AVG>::run(spec, args...)
-                   : Op<NX, NT, kFP32Shifted, 128, false, AVG>::run(spec, args...);
-    case 256:
-        return f64 ? Op<NX, NT, kFP64, 256, false, AVG>::run(spec, args...)
-                   : Op<NX, NT, kFP32Shifted, 256, false, AVG>::run(spec, args...);
-    default:
-        return hipErrorInvalidValue;
+    if constexpr (PAIR && D > kMaxPairD) {
+        return hipErrorNotSupported;
+    } else {
+        const bool f64 = spec.prec == kFP64;
+        switch (spec.block) {
+        case 64:
+            return f64 ? Op<NX, NT, kFP64, 64, false, AVG, PAIR>::run(spec, args...)
+                       : Op<NX, NT, kFP32Shifted, 64, false, AVG, PAIR>::run(spec, args...);
+        case 128:
+            return f64 ? Op<NX, NT, kFP64, 128, false, AVG, PAIR>::run(spec, args...)
+                       : Op<NX, NT, kFP32Shifted, 128, false, AVG, PAIR>::run(spec, args...);
+        case 256:
+            return f64 ? Op<NX, NT, kFP64, 256, false, AVG, PAIR>::run(spec, args...)
+                       : Op<NX, NT, kFP32Shifted, 256, false, AVG, PAIR>::run(spec, args...);
+        default:
+            return hipErrorInvalidValue;
+        }
     }
 }
 
-template <int NX, int NT, template <int, int, int, int, bool, bool> class Op, class... Args>
+template <int NX, int NT, template <int, int, int, int, bool, bool, bool> class Op,
+          class... Args>
 hipError_t dispatch(const LaunchSpec &spec, Args &&...args)
 {
+    if (spec.pair != 0 && spec.pair != 1)
+        return hipErrorInvalidValue;
     switch (spec.obs) {
     case 0:
-        return dispatch_obs<NX, NT, false, Op>(spec, args...);
+        return spec.pair ? dispatch_obs<NX, NT, false, true, Op>(spec, args...)
+                         : dispatch_obs<NX, NT, false, false, Op>(spec, args...);
     case 1:
-        return dispatch_obs<NX, NT, true, Op>(spec, args...);
+        return spec.pair ? dispatch_obs<NX, NT, true, true, Op>(spec, args...)
+                         : dispatch_obs<NX, NT, true, false, Op>(spec, args...);
     default:
         return hipErrorInvalidValue;
     }
 }
 
-template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG>
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG, bool PAIR>
 struct LaunchOp {
     static hipError_t run(const LaunchSpec &spec, const McArgs &args, hipStream_t stream)
     {
-        return launch_one<NX, NT, PREC, BLOCK, SPLIT, AVG>(spec, args, stream);
+        return launch_one<NX, NT, PREC, BLOCK, SPLIT, AVG, PAIR>(spec, args, stream);
     }
 };
 
-template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG>
+template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG, bool PAIR>
 struct InfoOp {
     static hipError_t run(const LaunchSpec &, KernelInfo *info)
     {
-        return info_one<NX, NT, PREC, BLOCK, SPLIT, AVG>(info);
+        return info_one<NX, NT, PREC, BLOCK, SPLIT, AVG, PAIR>(info);
     }
 };
 

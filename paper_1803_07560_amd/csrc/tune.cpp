@@ -73,6 +73,8 @@ bfi_status bfi_autotune(bfi_context *ctx, const bfi_lattice *lat, bfi_precision 
     if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
         return fail(BFI_EINVAL, "unknown precision");
     BFI_TRY(check_lattice(lat));
+    if (lat->antithetic)
+        return fail(BFI_EUNSUPPORTED, "launch shapes are tuned on single points");
     if (evals_per_trial < (uint64_t(1) << 16))
         return fail(BFI_EINVAL, "evals_per_trial must be at least 2^16");
     BFI_HIP(hipSetDevice(ctx->device));

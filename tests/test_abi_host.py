@@ -224,3 +224,18 @@ def test_checkpoint_result_matches_oracle(bfi, tmp_path):
     want = oracle.finalize(nx, nx * nt, sv.lo, sv.hi, sums)
     assert got["log_Z"] == pytest.approx(want["log_Z"], rel=1e-13)
     np.testing.assert_allclose(got["C"], want["C"], rtol=1e-12, atol=1e-14)
+
+
+def test_finalize_counts_two_evaluations_per_pair(bfi):
+    nx, nt = 4, 2
+    lat_o, sv, sums = _oracle_case(nx, nt)
+    p = _as_partials(sums, nx, 0.0)
+    single = bfi.bfi_finalize(bfi.lattice(nx, nt, nu=0.8), sv, p)
+    pairs = bfi.bfi_finalize(bfi.lattice(nx, nt, nu=0.8, antithetic=True), sv, p)
+    assert pairs["n_evals"] == 2 * single["n_evals"]
+    assert pairs["Z"] == single["Z"] and np.array_equal(pairs["C"], single["C"])
+    bad = bfi.lattice(nx, nt, nu=0.8)
+    bad.antithetic = 3
+    with pytest.raises(bfi.BfiError) as e:
+        bfi.bfi_finalize(bad, sv, p)
+    assert e.value.name == "BFI_EINVAL"

@@ -1,0 +1,166 @@
+"""GPU: antithetic pairs (lattice antithetic = 1) against the oracle's.
+
+Each sample index gives the point of its Philox words and the point of the
+complemented words (the reflection through the subvolume's centre); records
+sum the pair means.  Bars as for single points: FP64 records within 1e-10 of
+their L1 scales, Z and C(r) within 1e-6 (FP64) and 1e-4 (FP32 form) of the
+oracle's on the same pairs; launch shapes, persistent and grid kernels, plans
+and graph replays agree bit for bit; the entry points without pair support
+refuse it.  Then what the pairs are for: the same error bar as single points
+at equal evaluations on the subvolumes of a partition."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from test_gpu_parity import assert_result_close, assert_sums_close, unshift
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = "fp64", "fp32"
+
+
+def oracle_pairs(nx, nt, sv, seed, **kw):
+    lat_o = oracle.lattice(nx, nt, antithetic=1, **kw)
+    return lat_o, oracle.sums(lat_o, seed, sv.ids, sv.lo, sv.hi, sv.n, sv.offset)
+
+
+@pytest.mark.parametrize("obs", [0, 1])
+@pytest.mark.parametrize("nx,nt", [(1, 1), (2, 1), (3, 2), (5, 3), (8, 2), (10, 2)])
+def test_records_match_oracle(bfi, ctx, nx, nt, obs):
+    d = nx * nt
+    sv = workloads.random_partition(d, 3.0, 10, per_sub=1, seed=nx * 7 + nt)
+    item = 64 * 256
+    sv.n[:] = [2, 3, 255, 257, item - 1, item + 1, 3 * item + 17, 1000, 77, 5000]
+    sv.offset[:] = [0, 5, 2**20, 3, 0, 2**33, 1, 7, 0, 123456789]
+    lat_o, want = oracle_pairs(nx, nt, sv, 9, nu=0.6, observable=obs)
+    lat = bfi.lattice(nx, nt, nu=0.6, observable=obs, antithetic=True)
+    got = bfi.bfi_eval(ctx, lat, F64, 9, sv)
+    assert np.array_equal(got[:, 0], sv.n.astype(np.float64))
+    assert_sums_close(unshift(got, nx), want, nx, 1e-10)
+    res_o = oracle.finalize(nx, d, sv.lo, sv.hi, want, 2)
+    res = bfi.bfi_finalize(lat, sv, got)
+    assert_result_close(res, res_o, 1e-6)
+    assert res["n_evals"] == 2 * sv.n.sum() == res_o["n_evals"]
+    got32 = bfi.bfi_eval(ctx, lat, F32, 9, sv)
+    assert_result_close(bfi.bfi_finalize(lat, sv, got32), res_o, 1e-4)
+
+
+@pytest.mark.parametrize("nx,nt", [(10, 2), (3, 1)])
+def test_counter_boundaries(bfi, ctx, nx, nt):
+    """Items whose counters cross a multiple of 2^32 (general Philox path) beside
+    items that do not."""
+    d = nx * nt
+    nb = (d + 3) // 4
+    sv = workloads.random_partition(d, 3.0, 4, per_sub=1, seed=d)
+    sv.n[:] = [3000, 20_000, 5, 70_000]
+    starts = []
+    for k, n in zip([1, 2, 3, 5], sv.n):
+        starts.append(-(-(k << 32) // nb) - int(n) // 2)
+    starts[1] = 0
+    sv.offset[:] = starts
+    lat_o, want = oracle_pairs(nx, nt, sv, 11, nu=0.7)
+    got = bfi.bfi_eval(ctx, bfi.lattice(nx, nt, nu=0.7, antithetic=True), F64, 11, sv,
+                       bfi.launch(8, 64, 0))
+    assert_sums_close(unshift(got, nx), want, nx, 1e-10)
+
+
+@pytest.mark.parametrize("launch", [
+    dict(samples_per_thread=1, block=64, persistent=0),
+    dict(samples_per_thread=7, block=128, persistent=1),
+    dict(samples_per_thread=64, block=256, persistent=0),
+    dict(samples_per_thread=256, block=256, persistent=1),
+])
+def test_launch_shapes(bfi, ctx, launch):
+    nx, nt = 10, 2
+    sv = workloads.uniform_partition(20, 4.0, 5, per_sub=30_000)
+    sv.n[3] = 17
+    lat_o, want = oracle_pairs(nx, nt, sv, 1)
+    got = bfi.bfi_eval(ctx, bfi.lattice(nx, nt, antithetic=True), F64, 1, sv,
+                       bfi.launch(**launch))
+    assert_sums_close(unshift(got, nx), want, nx, 1e-10)
+
+
+def test_persistent_equals_grid_and_plans_bitwise(bfi, ctx):
+    sv = workloads.random_partition(20, 4.0, 40, per_sub=30_000, seed=3)
+    sv.n[::3] = 12_345
+    for obs in ("anchor", "averaged"):
+        lat = bfi.lattice(10, 2, nu=0.5, observable=obs, antithetic=True)
+        for prec in (F64, F32):
+            a = bfi.bfi_eval(ctx, lat, prec, 5, sv, bfi.launch(32, 256, 0))
+            b = bfi.bfi_eval(ctx, lat, prec, 5, sv, bfi.launch(32, 256, 1))
+            assert np.array_equal(a, b)
+            plan = bfi.bfi_plan_create(ctx, lat, prec, sv, bfi.launch(32, 256, 1, use_graph=1))
+            try:
+                info = bfi.bfi_plan_info(plan)
+                assert info["n_evals"] == 2 * int(sv.n.sum())
+                for _ in range(3):
+                    bfi.bfi_plan_run(plan, 5)
+                    assert np.array_equal(bfi.bfi_plan_partials(plan, len(sv), 10), b)
+            finally:
+                bfi.bfi_plan_destroy(plan)
+
+
+def test_integrate_counts_evaluations(bfi, ctx):
+    lat = bfi.lattice(4, 2, antithetic=True)
+    r = bfi.bfi_integrate(ctx, lat, F64, 1, -4.0, 4.0, 4, 1 << 20)
+    assert r["n_evals"] == 1 << 20
+    ref = oracle.integrate_uniform(oracle.lattice(4, 2, antithetic=1), 1, -4.0, 4.0, 4, 1 << 20)
+    assert r["n_evals"] == ref["n_evals"]
+    assert_result_close(r, ref, 1e-6)
+    with pytest.raises(bfi.BfiError) as e:
+        bfi.bfi_integrate(ctx, lat, F64, 1, -4.0, 4.0, 4, 63)   # 31 pairs for 16 subvolumes
+    assert e.value.name == "BFI_EINVAL"
+
+
+def test_unsupported_paths_refuse_pairs(bfi, ctx):
+    lat = bfi.lattice(4, 2, antithetic=True)
+    sv = workloads.uniform_partition(8, 2.0, 2, per_sub=1000)
+    calls = [
+        lambda: bfi.bfi_eval(ctx, bfi.lattice(16, 4, antithetic=True), F64, 1,
+                             workloads.uniform_partition(64, 3.0, 2, per_sub=100)),
+        lambda: bfi.bfi_eval(ctx, lat, F64, 1, sv, split=True),
+        lambda: bfi.bfi_integrate_adaptive(ctx, lat, F64, 1, -2.0, 2.0,
+                                           bfi.adaptive_config(split_log2=2, n_min=64,
+                                                               max_evals=1 << 16)),
+        lambda: bfi.bfi_integrate_is(ctx, lat, F64, 1, -2.0, 2.0, 1 << 16, 0.9, 8),
+        lambda: bfi.bfi_integrand_eval(ctx, bfi.integrand_burgers(lat), 1, sv),
+        lambda: bfi.bfi_autotune(ctx, lat, F64),
+    ]
+    for call in calls:
+        with pytest.raises(bfi.BfiError) as e:
+            call()
+        assert e.value.name == "BFI_EUNSUPPORTED"
+    srv = bfi.bfi_server_create(ctx, bfi.server_config())
+    try:
+        with pytest.raises(bfi.BfiError) as e:
+            bfi.bfi_server_submit(srv, bfi.request(lat, F64, 1, 2.0, 2, 4096))
+        assert e.value.name == "BFI_EUNSUPPORTED"
+    finally:
+        bfi.bfi_server_destroy(srv)
+    bad = bfi.lattice(4, 2)
+    bad.antithetic = 2
+    with pytest.raises(bfi.BfiError) as e:
+        bfi.bfi_eval(ctx, bad, F64, 1, sv)
+    assert e.value.name == "BFI_EINVAL"
+
+
+def test_error_bar_at_equal_evaluations(bfi, ctx):
+    """10x2, nu = 1, the paper's range [-1,1]^20 in 64 subvolumes (dims 0-5
+    halved): 2^19 pairs per subvolume against 2^20 single points.  The two
+    weights of a pair are nearly uncorrelated on subvolumes that are not centred
+    at 0, so the error bars agree; the estimates agree within them."""
+    sv = workloads.uniform_partition(20, 1.0, 6, per_sub=1 << 20)
+    plain = bfi.bfi_finalize(bfi.lattice(10, 2), sv,
+                             bfi.bfi_eval(ctx, bfi.lattice(10, 2), F32, 1, sv))
+    half = bfi.Subvolumes(sv.ids, sv.lo, sv.hi, sv.n // 2, sv.offset, 20)
+    lat = bfi.lattice(10, 2, antithetic=True)
+    pair = bfi.bfi_finalize(lat, half, bfi.bfi_eval(ctx, lat, F32, 2, half))
+    assert pair["n_evals"] == plain["n_evals"]
+    assert 0.85 < pair["Z_err"] / plain["Z_err"] < 1.15
+    assert abs(pair["Z"] - plain["Z"]) < 4 * math.hypot(pair["Z_err"], plain["Z_err"])
+    for r in range(10):
+        assert abs(pair["C"][r] - plain["C"][r]) < 4 * math.hypot(pair["C_err"][r],
+                                                                  plain["C_err"][r])
