@@ -97,6 +97,8 @@ def parse():
                     help="skip the translation-averaged observable leg")
     ap.add_argument("--no-sampler-leg", action="store_true",
                     help="skip the Gaussian-proposal sampler leg")
+    ap.add_argument("--no-antithetic-leg", action="store_true",
+                    help="skip the antithetic-pair leg")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1803_07560_amd",
@@ -223,6 +225,41 @@ def observable_leg(bfi, torch, ctx, w, sv, steps, warmup, stream, accuracy_log2=
         "C_err_ratio": [float(x) for x in ratio]}}
 
 
+def antithetic_leg(bfi, torch, ctx, w, sv, steps, warmup, stream, accuracy_log2=26):
+    """Antithetic pairs: every sample index evaluates the point of its Philox
+    words and of the complemented words (its reflection through the subvolume's
+    centre), sharing one Philox evaluation.  Throughput of both forms on the
+    benchmark workload (the same evaluations: half the sample indices, two
+    points each), and the error bars of pairs and single points at equal
+    evaluations (2^accuracy_log2, FP32 form) on the paper's range [-1,1]^20 (64
+    subvolumes) and on the benchmark box.  Time to a given error scales as
+    sigma^2 / rate: the equal-error speedup is
+    (sigma_single / sigma_pairs)^2 rate_pairs / rate_single."""
+    lat = bfi.lattice(w.nx, w.nt, nu=w.nu, D=w.D, antithetic=True)
+    half = bfi.Subvolumes(sv.ids, sv.lo, sv.hi, sv.n // 2, sv.offset, w.d)
+    forms = {}
+    for prec in ("fp64", "fp32"):
+        print(f"bench: antithetic pairs {prec}", file=sys.stderr, flush=True)
+        f = run_form(bfi, torch, ctx, lat, half, w, prec, steps, warmup, stream)
+        forms[prec] = {"evals_per_s": f["evals_per_s"], "ms_per_step": f["ms_per_step"],
+                       "kernel_ms": f["kernel_ms"], "evals_per_step": f["evals_per_step"]}
+    boxes = []
+    for B, k in ((1.0, 6), (w.box, w.split_log2)):
+        est = {}
+        for kind, anti in (("single", False), ("pairs", True)):
+            est[kind] = bfi.bfi_integrate(
+                ctx, bfi.lattice(w.nx, w.nt, nu=w.nu, D=w.D, antithetic=anti), "fp32", 5, -B, B,
+                k, 1 << accuracy_log2)
+        boxes.append({
+            "box": [-B, B], "subvolumes": 1 << k, "evals": 1 << accuracy_log2, "form": "fp32",
+            "Z_err_ratio": est["single"]["Z_err"] / est["pairs"]["Z_err"],
+            "C_err_ratio": [float(a / b) for a, b in zip(est["single"]["C_err"],
+                                                         est["pairs"]["C_err"])],
+            "Z": [est["single"]["Z"], est["pairs"]["Z"]],
+            "Z_err": [est["single"]["Z_err"], est["pairs"]["Z_err"]]})
+    return {"forms": forms, "error_at_equal_evals": boxes}
+
+
 def sampler_leg(bfi, ctx, w, budget_log2=28, alpha=0.9, repeats=3):
     """The defensive Gaussian-proposal sampler against the plain one on the
     10x2 lattice, same budget, FP32 form, on the benchmark box [-4,4]^20 and on
@@ -318,6 +355,9 @@ def main():
     averaged = None
     if not args.no_observable_leg:
         averaged = observable_leg(bfi, torch, ctx, w, sv, args.steps, args.warmup, stream)
+    pairs = None
+    if not args.no_antithetic_leg and w.nx * w.nt <= 32:
+        pairs = antithetic_leg(bfi, torch, ctx, w, sv, args.steps, args.warmup, stream)
     sampler = None
     if not args.no_sampler_leg and w.nx * w.nt <= 32:
         print("bench: Gaussian-proposal sampler", file=sys.stderr, flush=True)
@@ -397,6 +437,14 @@ def main():
         averaged["equal_error_speedup"] = {"min_r": float(np.min(ratio ** 2) * rate),
                                            "median_r": float(np.median(ratio ** 2) * rate)}
         line["observable_averaged"] = averaged
+    if pairs is not None:
+        rate = pairs["forms"][args.headline]["evals_per_s"] / head["evals_per_s"]
+        for b in pairs["error_at_equal_evals"]:
+            b["equal_error_speedup_Z"] = b["Z_err_ratio"] ** 2 * rate
+            b["equal_error_speedup_C_median_r"] = float(np.median(
+                np.asarray(b["C_err_ratio"]) ** 2) * rate)
+        pairs["rate_vs_single"] = rate
+        line["antithetic_pairs"] = pairs
     if sampler is not None:
         line["sampler_gaussian_mixture"] = sampler
     if serving is not None:
