@@ -99,8 +99,9 @@ typedef struct {
                             uncorrelated on subvolumes that are not centred at 0 (on
                             a box centred at 0, u' = -u only flips the sign of the
                             nonlinear term).  Supported by bfi_eval (without split
-                            statistics), plans, bfi_integrate and bfi_finalize, for
-                            d <= 32; the other entry points return EUNSUPPORTED. */
+                            statistics), plans, bfi_integrate, bfi_finalize and the
+                            server, for d <= 32; the other entry points return
+                            EUNSUPPORTED. */
 } bfi_lattice;
 
 /* A list of subvolumes (host arrays, caller-owned).
@@ -433,7 +434,8 @@ typedef struct {
     uint64_t seed;
     double box;               /* box [-box, box]^d */
     int32_t split_log2;       /* uniform partition */
-    uint64_t budget;          /* total samples */
+    uint64_t budget;          /* total integrand evaluations (antithetic pairs: budget/2
+                                 sample indices, split as in bfi_integrate) */
 } bfi_request;
 
 typedef struct {

@@ -123,19 +123,20 @@ struct bfi_server {
 
 namespace {
 
-// Launch shape and persistent grid for (nx, nt, prec, observable); fixed for the
-// server's lifetime so item sizes (and therefore results) never depend on the mix.
+// Launch shape and persistent grid for (nx, nt, prec, observable, pairs); fixed
+// for the server's lifetime so item sizes (and therefore results) never depend on
+// the mix.
 bfi_status shape_launch(bfi_server *srv, const bfi_lattice &lat, int prec, bfi_launch *l,
                         uint32_t *grid)
 {
-    const TuneKey key{lat.nx, lat.nt, prec + 2 * lat.observable};
+    const TuneKey key{lat.nx, lat.nt, prec + 2 * lat.observable + 4 * lat.antithetic};
     auto it = srv->shapes.find(key);
     if (it == srv->shapes.end()) {
         bfi_launch r = resolve_launch(srv->ctx, lat, prec, false, nullptr);
         r.persistent = 1;
         r.use_graph = 0;
         KernelInfo info{};
-        LaunchSpec spec{prec, r.block, 0, 1, 0, lat.observable};
+        LaunchSpec spec{prec, r.block, 0, 1, 0, lat.observable, lat.antithetic};
         BFI_HIP(kernel_info(lat.nx, lat.nt, spec, &info));
         const uint32_t g =
             static_cast<uint32_t>(std::max(info.blocks_per_cu, 1) * std::max(srv->ctx->cu_count, 1));
@@ -271,7 +272,8 @@ void complete(bfi_server *srv)
             continue;
         }
         bfi_status s = finalize_records(r->nx, r->d, r->subs.size(), r->subs.lo.data(),
-                                        r->subs.hi.data(), sub.data(), &r->result);
+                                        r->subs.hi.data(), sub.data(), &r->result,
+                                        r->req.lat.antithetic ? 2 : 1);
         bool finite = std::isfinite(r->result.log_Z);
         for (int k = 0; k < r->nx; ++k)
             finite = finite && std::isfinite(r->result.C[k]);
@@ -302,7 +304,7 @@ bfi_status run_step(bfi_server *srv, const std::vector<StepEntry> &entries)
     };
     std::vector<Group> groups;
     size_t total = 0;
-    // group entries by (shape, precision, observable), keeping their order
+    // group entries by (shape, precision, observable, pairs), keeping their order
     std::vector<bool> used(entries.size(), false);
     for (size_t i = 0; i < entries.size(); ++i) {
         if (used[i])
@@ -312,7 +314,7 @@ bfi_status run_step(bfi_server *srv, const std::vector<StepEntry> &entries)
         for (size_t j = i; j < entries.size(); ++j) {
             const bfi_request &o = entries[j].r->req;
             if (used[j] || o.lat.nx != q.lat.nx || o.lat.nt != q.lat.nt || o.prec != q.prec ||
-                o.lat.observable != q.lat.observable)
+                o.lat.observable != q.lat.observable || o.lat.antithetic != q.lat.antithetic)
                 continue;
             used[j] = true;
             const StepEntry &e = entries[j];
@@ -343,7 +345,7 @@ bfi_status run_step(bfi_server *srv, const std::vector<StepEntry> &entries)
         a.samples_per_thread = static_cast<uint32_t>(g.launch.samples_per_thread);
         LaunchSpec spec{g.prec, g.launch.block, 0, 1,
                         static_cast<uint32_t>(std::min<size_t>(g.grid, g.count)),
-                        g.lat.observable};
+                        g.lat.observable, g.lat.antithetic};
         BFI_HIP(launch_mc(g.lat.nx, g.lat.nt, spec, a, st));
     }
     for (int k = 0; k < nstreams; ++k)
@@ -372,8 +374,9 @@ void worker_loop(bfi_server *srv)
             if (r->cancel || r->next_item >= r->items.size())
                 continue;
             // equal share of the step's evaluations, at least chunks_per_step items
-            const uint64_t chunk =
-                static_cast<uint64_t>(r->launch.samples_per_thread) * r->launch.block;
+            // (an item of antithetic pairs makes two evaluations per sample index)
+            const uint64_t chunk = static_cast<uint64_t>(r->launch.samples_per_thread) *
+                                   r->launch.block * (r->req.lat.antithetic ? 2 : 1);
             const uint64_t share = step_evals / std::max<size_t>(active, 1);
             const size_t quota = std::max<size_t>(static_cast<size_t>(srv->cfg.chunks_per_step),
                                                   static_cast<size_t>((share + chunk - 1) / chunk));
@@ -404,7 +407,8 @@ void worker_loop(bfi_server *srv)
             if (s == BFI_OK) {
                 e.r->done_items += e.count;
                 for (size_t i = e.first; i < e.first + e.count; ++i)
-                    srv->stats.evals += e.r->items[i].count;
+                    srv->stats.evals +=
+                        e.r->items[i].count * static_cast<uint64_t>(e.r->req.lat.antithetic ? 2 : 1);
             } else if (!terminal(e.r->state)) {
                 e.r->cancel = true;  // released by complete(); reported as failed below
                 e.r->status = s;
@@ -502,15 +506,15 @@ bfi_status bfi_server_submit(bfi_server *srv, const bfi_request *req, uint64_t *
     if (!srv || !req || !ticket)
         return fail(BFI_EINVAL, "arguments must be non-NULL");
     BFI_TRY(check_lattice(&req->lat));
-    if (req->lat.antithetic)
-        return fail(BFI_EUNSUPPORTED, "served requests use single points (antithetic = 0)");
     if (req->prec != BFI_FP64 && req->prec != BFI_FP32_SHIFTED)
         return fail(BFI_EINVAL, "unknown precision");
     if (!(req->box > 0) || !std::isfinite(req->box))
         return fail(BFI_EINVAL, "box must be positive and finite");
     if (req->split_log2 < 0 || req->split_log2 > 20)
         return fail(BFI_EINVAL, "split_log2 must be in [0, 20]");
-    if (req->budget < 2 * (uint64_t(1) << req->split_log2))
+    // the budget counts integrand evaluations: two per antithetic pair
+    const uint64_t per = req->lat.antithetic ? 2 : 1;
+    if (req->budget / per < 2 * (uint64_t(1) << req->split_log2))
         return fail(BFI_EINVAL, "budget must give every subvolume at least 2 samples");
 
     auto r = std::make_unique<Request>();
@@ -519,7 +523,7 @@ bfi_status bfi_server_submit(bfi_server *srv, const bfi_request *req, uint64_t *
     r->d = req->lat.nx * req->lat.nt;
     r->rec_len = BFI_PARTIAL_LEN(r->nx);
     std::vector<double> lo(r->d, -req->box), hi(r->d, req->box);
-    r->subs = uniform_split(r->d, lo.data(), hi.data(), req->split_log2, req->budget);
+    r->subs = uniform_split(r->d, lo.data(), hi.data(), req->split_log2, req->budget / per);
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         BFI_TRY(shape_launch(srv, req->lat, req->prec, &r->launch, &r->grid));

@@ -133,13 +133,6 @@ def test_unsupported_paths_refuse_pairs(bfi, ctx):
         with pytest.raises(bfi.BfiError) as e:
             call()
         assert e.value.name == "BFI_EUNSUPPORTED"
-    srv = bfi.bfi_server_create(ctx, bfi.server_config())
-    try:
-        with pytest.raises(bfi.BfiError) as e:
-            bfi.bfi_server_submit(srv, bfi.request(lat, F64, 1, 2.0, 2, 4096))
-        assert e.value.name == "BFI_EUNSUPPORTED"
-    finally:
-        bfi.bfi_server_destroy(srv)
     bad = bfi.lattice(4, 2)
     bad.antithetic = 2
     with pytest.raises(bfi.BfiError) as e:
@@ -164,3 +157,71 @@ def test_error_bar_at_equal_evaluations(bfi, ctx):
     for r in range(10):
         assert abs(pair["C"][r] - plain["C"][r]) < 4 * math.hypot(pair["C_err"][r],
                                                                   plain["C_err"][r])
+
+
+def test_full_size_sampled_in_bench_configuration(bfi, ctx):
+    """The benchmark's pair launch: 10x2, nu = 1, [-4,4]^20, 2^29 pairs over 1024
+    subvolumes through a resident graph plan; 3 whole subvolumes (2^19 pairs
+    each) against the oracle, the FP32 form against FP64."""
+    w = workloads.WORKLOADS["burgers10x2"]
+    sv = workloads.uniform_partition(w.d, w.box, w.split_log2, w.budget // w.n_sub // 2)
+    lat = bfi.lattice(10, 2, antithetic=True)
+    res = {}
+    for prec in (F64, F32):
+        plan = bfi.bfi_plan_create(ctx, lat, prec, sv, bfi.launch(use_graph=1))
+        try:
+            assert bfi.bfi_plan_info(plan)["n_evals"] == w.budget
+            bfi.bfi_plan_run(plan, w.seed)
+            got = bfi.bfi_plan_partials(plan, len(sv), 10)
+        finally:
+            bfi.bfi_plan_destroy(plan)
+        res[prec] = bfi.bfi_finalize(lat, sv, got)
+        if prec == F64:
+            pick = np.array([0, 511, 1023])
+            sub = sv.subset(pick)
+            chunks = 16
+            m = int(sub.n[0]) // chunks
+            want = oracle.sums(oracle.lattice(10, 2, antithetic=1), w.seed,
+                               np.repeat(sub.ids, chunks), np.repeat(sub.lo, chunks, axis=0),
+                               np.repeat(sub.hi, chunks, axis=0), m,
+                               np.tile(np.arange(chunks, dtype=np.uint64) * m, len(pick)))
+            want = want.reshape(len(pick), chunks, -1).sum(1)
+            assert_sums_close(unshift(got[pick], 10), want, 10, 1e-10)
+    assert res[F64]["n_evals"] == w.budget
+    assert_result_close(res[F32], res[F64], 1e-4)
+
+
+def test_served_pairs(bfi, ctx):
+    """Served pair requests: the oracle's result on the same pairs, two
+    evaluations per pair, and the same records whether served alone or mixed
+    with single-point requests of the same shape."""
+    srv = bfi.bfi_server_create(ctx, bfi.server_config(memory_budget=1 << 30, max_requests=64,
+                                                       chunks_per_step=16))
+    try:
+        nx, nt, B, k, budget = 4, 2, 4.0, 4, 200_004
+        pair_req = bfi.request(bfi.lattice(nx, nt, nu=0.5, antithetic=True), F64, 7, B, k, budget)
+        t = bfi.bfi_server_submit(srv, pair_req)
+        res = bfi.bfi_server_wait(srv, t, 60.0)[0]
+        ref = oracle.integrate_uniform(oracle.lattice(nx, nt, nu=0.5, antithetic=1), 7, -B, B, k,
+                                       budget)
+        assert res["n_evals"] == budget == ref["n_evals"]
+        assert_result_close(res, ref, 1e-6)
+        mix = []
+        for i in range(12):
+            lat = bfi.lattice(10, 2, nu=0.3 + 0.1 * i, antithetic=bool(i % 2))
+            mix.append(bfi.request(lat, F32, i + 1, 2.0, 4, 1 << 18))
+        tickets = [bfi.bfi_server_submit(srv, r) for r in mix]
+        mixed = [bfi.bfi_server_wait(srv, t, 60.0)[0] for t in tickets]
+        st = bfi.bfi_server_stats_get(srv)
+        assert st["evals"] >= budget + 12 * (1 << 18)
+    finally:
+        bfi.bfi_server_destroy(srv)
+    for i in (0, 1, 5):
+        alone_srv = bfi.bfi_server_create(ctx, bfi.server_config(memory_budget=1 << 30))
+        try:
+            alone = bfi.bfi_server_wait(alone_srv, bfi.bfi_server_submit(alone_srv, mix[i]),
+                                        60.0)[0]
+        finally:
+            bfi.bfi_server_destroy(alone_srv)
+        assert alone["Z"] == mixed[i]["Z"] and np.array_equal(alone["C"], mixed[i]["C"]), i
+        assert alone["n_evals"] == 1 << 18
