@@ -113,13 +113,14 @@ def test_split_statistics(bfi, ctx):
 
 def test_10x2_full_size_sampled(bfi, ctx):
     """The benchmark workload (2^30 points, 1024 subvolumes) with the averaged
-    product; 4 subvolumes against the oracle, FP32 form against FP64."""
+    product, in the benchmark's launch configuration (resident plan replayed as a
+    graph); 4 subvolumes against the oracle, FP32 form against FP64."""
     w = workloads.WORKLOADS["burgers10x2"]
     sv = workloads.uniform_partition(w.d, w.box, w.split_log2, w.budget // w.n_sub)
     lat = bfi.lattice(10, 2, observable=AVG)
     res = {}
     for prec in (F64, F32):
-        plan = bfi.bfi_plan_create(ctx, lat, prec, sv)
+        plan = bfi.bfi_plan_create(ctx, lat, prec, sv, bfi.launch(use_graph=1))
         try:
             bfi.bfi_plan_run(plan, w.seed)
             got = bfi.bfi_plan_partials(plan, len(sv), 10)
