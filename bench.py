@@ -107,25 +107,62 @@ def parse():
 
 
 def run_form(bfi, torch, ctx, lat, sv, w, prec, steps, warmup, stream):
+    """Time `steps` steps of one form: each step replays the plan's graph (queue
+    reset, Monte Carlo kernel, merge, copy of the records to a device buffer),
+    copies the records to the host and finalizes them.  The timed steps are
+    pipelined: step i+1 is enqueued before step i's records come back (on a
+    second stream, into pinned host memory) and are finalized, so the GPU does
+    not wait for the host between steps.  Two device buffers alternate (the plan
+    keeps one captured replay per buffer); a buffer is reused only after its
+    copy has been waited for.  Replay durations come from events recorded on the
+    launch stream around every replay."""
     plan = bfi.bfi_plan_create(ctx, lat, prec, sv, bfi.launch(use_graph=1))
     try:
         info = bfi.bfi_plan_info(plan)
-        part = np.zeros((len(sv), 4 + 3 * w.nx))
+        shape = (len(sv), 4 + 3 * w.nx)
+        dev = [torch.empty(shape, dtype=torch.float64, device="cuda") for _ in range(2)]
+        host = [torch.empty(shape, dtype=torch.float64, pin_memory=True) for _ in range(2)]
+        copy_stream = torch.cuda.Stream()
+        copied = [torch.cuda.Event() for _ in range(2)]
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+
+        def launch(i, timed):
+            b = i % 2
+            if timed:
+                ev[i][0].record(stream)
+            bfi.bfi_plan_run(plan, w.seed, dev[b], stream)
+            done = torch.cuda.Event()
+            done.record(stream)
+            if timed:
+                ev[i][1].record(stream)
+            copy_stream.wait_event(done)
+            with torch.cuda.stream(copy_stream):
+                host[b].copy_(dev[b], non_blocking=True)
+                copied[b].record(copy_stream)
+
+        def finish(i):
+            b = i % 2
+            copied[b].synchronize()
+            return bfi.bfi_finalize(lat, sv, host[b].numpy())
+
         for i in range(warmup):
-            bfi.bfi_plan_run(plan, w.seed, None, stream)
-            bfi.bfi_plan_partials(plan, len(sv), w.nx, part)
-            bfi.bfi_finalize(lat, sv, part)
+            launch(i, False)
+            finish(i)
         torch.cuda.synchronize()
-        kernel_ms, step_end = [], []
+        step_end = []
         t0 = time.perf_counter()
-        for i in range(steps):
-            bfi.bfi_plan_run(plan, w.seed, None, stream)
-            bfi.bfi_plan_partials(plan, len(sv), w.nx, part)
-            res = bfi.bfi_finalize(lat, sv, part)
+        launch(0, True)
+        for i in range(1, steps):
+            launch(i, True)
+            res = finish(i - 1)
             step_end.append(time.perf_counter())
-            kernel_ms.append(bfi.bfi_plan_kernel_ms(plan))
+        res = finish(steps - 1)
+        step_end.append(time.perf_counter())
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        kernel_ms = [a.elapsed_time(b) for a, b in ev]
+        part = host[(steps - 1) % 2].numpy().copy()
     finally:
         bfi.bfi_plan_destroy(plan)
     evals = info["n_evals"]
@@ -395,7 +432,7 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                 "unit": "T FP64-rate lane slots/s", "frac": achieved / PEAK_SLOTS,
                 "traffic": measured_traffic(w.name, args.headline),
-                "kernel": "mc_kernel (graph replay: reset, kernel, merge)",
+                "kernel": "mc_kernel (graph replay: reset, kernel, merge, record copy)",
                 "slots_per_eval": slots,
                 "kernel_ms": head["kernel_ms"],
                 "fp64_flop_frac": (fp64_flops_per_eval(w.nx, w.nt) * evals_per_launch /

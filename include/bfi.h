@@ -189,7 +189,12 @@ bfi_status bfi_plan_create(bfi_context *ctx, const bfi_lattice *lat, bfi_precisi
                            bfi_plan **out);
 /* Enqueue one evaluation of the whole plan on `stream` (NULL: the context's
  * stream).  partials_dev: device, count x BFI_PARTIAL_LEN(nx), written when the
- * stream reaches it; NULL keeps them in the plan's own buffer. */
+ * stream reaches it; NULL keeps them in the plan's own buffer.  With use_graph,
+ * the sequence is captured once per (stream, partials_dev) pair and replayed
+ * (the four pairs used last are kept), so a caller may alternate output buffers
+ * to overlap reading one run's records with the next run.  Runs of one plan
+ * share its work buffers: they must not overlap in time (one stream, or events
+ * ordering the streams). */
 bfi_status bfi_plan_run(bfi_plan *plan, uint64_t seed, double *partials_dev, void *stream);
 /* Wait for the plan's last run and copy its partial records to host. */
 bfi_status bfi_plan_partials(bfi_plan *plan, double *partials);

@@ -341,10 +341,10 @@ bfi_status plan_free(bfi_plan *p)
 {
     if (!p)
         return BFI_OK;
-    if (p->graph)
-        (void)hipGraphExecDestroy(p->graph);
-    if (p->graph_def)
-        (void)hipGraphDestroy(p->graph_def);
+    for (const bfi_plan::Replay &r : p->replays) {
+        (void)hipGraphExecDestroy(r.exec);
+        (void)hipGraphDestroy(r.def);
+    }
     if (p->ev_start)
         (void)hipEventDestroy(p->ev_start);
     if (p->ev_stop)
@@ -715,14 +715,20 @@ bfi_status bfi_plan_run(bfi_plan *p, uint64_t seed, double *partials_dev, void *
     hipStream_t st = stream ? static_cast<hipStream_t>(stream) : p->ctx->stream;
     if (p->launch.use_graph) {
         BFI_TRY(plan_set_seed(p, seed));
-        if (!p->graph || p->graph_stream != st || p->graph_dst != partials_dev) {
-            if (p->graph) {
-                (void)hipGraphExecDestroy(p->graph);
-                p->graph = nullptr;
-            }
-            if (p->graph_def) {
-                (void)hipGraphDestroy(p->graph_def);
-                p->graph_def = nullptr;
+        const bfi_plan::Replay *rp = nullptr;
+        for (const bfi_plan::Replay &r : p->replays)
+            if (r.stream == st && r.dst == partials_dev)
+                rp = &r;
+        if (!rp) {
+            if (p->replays.size() >= bfi_plan::kMaxReplays) {
+                // replays of this plan run in order on their streams, and the
+                // host waits for the oldest before dropping it
+                if (p->last_stream)
+                    BFI_HIP(hipStreamSynchronize(p->last_stream));
+                BFI_HIP(hipStreamSynchronize(p->replays.front().stream));
+                (void)hipGraphExecDestroy(p->replays.front().exec);
+                (void)hipGraphDestroy(p->replays.front().def);
+                p->replays.erase(p->replays.begin());
             }
             BFI_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             bfi_status s = plan_enqueue(p, seed, partials_dev, st, false);
@@ -734,14 +740,21 @@ bfi_status bfi_plan_run(bfi_plan *p, uint64_t seed, double *partials_dev, void *
                 return s;
             }
             BFI_HIP(e);
-            p->graph_def = g;
-            BFI_HIP(hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0));
-            p->graph_stream = st;
-            p->graph_dst = partials_dev;
+            bfi_plan::Replay r;
+            r.def = g;
+            e = hipGraphInstantiate(&r.exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+            r.stream = st;
+            r.dst = partials_dev;
+            p->replays.push_back(r);
+            rp = &p->replays.back();
         }
         // a replay is timed as a whole: queue reset, kernel and merge
         BFI_HIP(hipEventRecord(p->ev_start, st));
-        BFI_HIP(hipGraphLaunch(p->graph, st));
+        BFI_HIP(hipGraphLaunch(rp->exec, st));
         BFI_HIP(hipEventRecord(p->ev_stop, st));
     } else {
         BFI_TRY(plan_enqueue(p, seed, partials_dev, st, true));

@@ -123,10 +123,17 @@ struct bfi_plan {
     uint32_t *d_head = nullptr;
     bfi::IsTable *d_is_table = nullptr;  // kind 2
 
-    hipGraphExec_t graph = nullptr;
-    hipGraph_t graph_def = nullptr;
-    hipStream_t graph_stream = nullptr;
-    double *graph_dst = nullptr;
+    // captured replays (queue reset, kernel, merge, copy to the destination), one
+    // per (stream, destination) pair, the most recently created kMaxReplays kept:
+    // alternating output buffers replays without capturing again
+    struct Replay {
+        hipGraphExec_t exec = nullptr;
+        hipGraph_t def = nullptr;
+        hipStream_t stream = nullptr;
+        double *dst = nullptr;
+    };
+    static constexpr size_t kMaxReplays = 4;
+    std::vector<Replay> replays;
     hipStream_t last_stream = nullptr;
     // bracket the Monte Carlo kernel of every run (timing of the hot kernel)
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_called_functions_exist():
     tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
-    defined = {n.name for n in tree.body if isinstance(n, ast.FunctionDef)}
+    defined = {n.name for n in ast.walk(tree) if isinstance(n, ast.FunctionDef)}
     imported = set()
     for n in ast.walk(tree):
         if isinstance(n, ast.Import):

@@ -260,6 +260,34 @@ def test_graph_replays_match_eager(bfi, ctx):
         bfi.bfi_plan_destroy(plan)
 
 
+def test_graph_replays_per_destination(bfi, ctx):
+    """A graph plan writing to alternating device buffers (one captured replay per
+    buffer), then to six buffers in turn (more than the four replays kept):
+    every replay's records equal the eager evaluation, with eager work and host
+    reads between replays."""
+    torch = pytest.importorskip("torch")
+    nx, nt = 10, 2
+    sv = workloads.uniform_partition(20, 4.0, 6, per_sub=20_000)
+    lat = bfi.lattice(nx, nt)
+    eager = bfi.bfi_eval(ctx, lat, F32, 4, sv, bfi.launch(64, 256, 1))
+    bufs = [torch.full((len(sv), bfi.partial_len(nx)), -1.0, dtype=torch.float64,
+                       device="cuda:0") for _ in range(6)]
+    stream = torch.cuda.Stream()
+    plan = bfi.bfi_plan_create(ctx, lat, F32, sv, bfi.launch(64, 256, 1, use_graph=1))
+    try:
+        for rep, b in enumerate([0, 1, 0, 1, 0, 1, 2, 3, 4, 5, 0, 1, 2]):
+            bufs[b].fill_(-1.0)
+            torch.cuda.synchronize()
+            bfi.bfi_plan_run(plan, 4, bufs[b], stream)
+            stream.synchronize()
+            assert np.array_equal(bufs[b].cpu().numpy(), eager), (rep, b)
+            other = bfi.bfi_eval(ctx, bfi.lattice(4, 2), F64, rep, workloads.uniform_partition(
+                8, 4.0, 2, per_sub=1000))
+            assert np.all(np.isfinite(other))
+    finally:
+        bfi.bfi_plan_destroy(plan)
+
+
 def test_plan_writes_torch_buffer_on_torch_stream(bfi, ctx):
     torch = pytest.importorskip("torch")
     nx, nt = 4, 2
