@@ -71,13 +71,19 @@ struct Fields {
 // Waves per SIMD the register allocation must leave room for: without a floor
 // the compiler spends the whole register file of one wave on large lattices.
 // FP32-form antithetic pairs (two points in registers) are held to three waves
-// per SIMD, the occupancy of the single-point kernel.
-template <int NX, int NT, int PREC, bool PAIR>
-constexpr int kMinWaves = NX * NT > 32 ? 2 : (PAIR && PREC != kFP64 ? 3 : 1);
+// per SIMD, the occupancy of the single-point kernel; the FP32 form with split
+// statistics (2d more accumulators) to two (measured 1.4x faster than one wave;
+// the FP64 form spills too much at two).
+template <int NX, int NT, int PREC, bool SPLIT, bool PAIR>
+constexpr int kMinWaves = NX * NT > 32             ? 2
+                          : PREC == kFP64          ? 1
+                          : SPLIT                  ? 2
+                          : PAIR                   ? 3
+                                                   : 1;
 
 template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG, bool PAIR>
 __global__ void __launch_bounds__(BLOCK)
-    __attribute__((amdgpu_waves_per_eu(kMinWaves<NX, NT, PREC, PAIR>))) mc_kernel(McArgs a)
+    __attribute__((amdgpu_waves_per_eu(kMinWaves<NX, NT, PREC, SPLIT, PAIR>))) mc_kernel(McArgs a)
 {
     using T = std::conditional_t<PREC == kFP64, double, float>;
     constexpr int D = NX * NT;
