@@ -127,6 +127,13 @@ def run_form(bfi, torch, ctx, lat, sv, w, prec, steps, warmup, stream):
         host = [torch.empty(shape, dtype=torch.float64, pin_memory=True) for _ in range(2)]
         copy_stream = torch.cuda.Stream()
         copied = [torch.cuda.Event() for _ in range(2)]
+        # first use of each stream before any launch: a stream's hardware queue
+        # is set up when it first takes work, which would interrupt a running
+        # kernel (its waves saved and restored) and count against that launch
+        for st in (stream, copy_stream):
+            with torch.cuda.stream(st):
+                host[0].copy_(dev[0], non_blocking=True)
+        torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
 
@@ -388,6 +395,10 @@ def main():
     if os.path.exists(args.tune_cache):
         bfi.bfi_tune_load(ctx, args.tune_cache)
     stream = torch.cuda.Stream()
+    # torch's first device allocation runs start-up work on the GPU; let it finish
+    # before the first form, so it overlaps no measured launch
+    torch.zeros(1 << 20, device="cuda:0").sum().item()
+    torch.cuda.synchronize()
     forms = {}
     for prec in ("fp64", "fp32"):
         print(f"bench: {w.name} {prec} warmup {args.warmup} steps {args.steps}", file=sys.stderr,
