@@ -619,7 +619,10 @@ extern "C" {
 
 const char *bfi_status_string(bfi_status s)
 {
-    switch (s) {
+    // a C caller may pass any int: read it as one, not as the enumeration
+    int32_t v = 0;
+    std::memcpy(&v, &s, sizeof v < sizeof s ? sizeof v : sizeof s);
+    switch (v) {
     case BFI_OK: return "ok";
     case BFI_EINVAL: return "invalid argument";
     case BFI_ENOMEM: return "out of memory";
