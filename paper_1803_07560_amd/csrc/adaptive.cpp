@@ -242,298 +242,304 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                                   double *leaf_lo, double *leaf_hi, uint64_t *leaf_n,
                                   uint64_t *leaf_offset, size_t cap, size_t *n_leaves)
 {
-    if (!ctx || !box_lo || !box_hi || !out)
-        return fail(BFI_EINVAL, "arguments must be non-NULL");
-    if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
-        return fail(BFI_EINVAL, "unknown precision");
-    BFI_TRY(check_lattice(lat));
-    BFI_TRY(check_config(cfg));
-    if (lat->antithetic)
-        return fail(BFI_EUNSUPPORTED, "adaptive refinement uses single points (antithetic = 0)");
-    const int nx = lat->nx, d = nx * lat->nt;
-    if (d > 32)
-        return fail(BFI_EUNSUPPORTED, "adaptive refinement needs d <= 32 (split statistics)");
-    for (int k = 0; k < d; ++k)
-        if (!std::isfinite(box_lo[k]) || !std::isfinite(box_hi[k]) || !(box_lo[k] < box_hi[k]))
-            return fail(BFI_EINVAL, "box dim %d: need finite lo < hi", k);
-    const int rec_len = BFI_PARTIAL_LEN(nx), split_len = BFI_SPLIT_LEN(d);
-    std::vector<int> rec_first, rec_second, split_first, split_second;
-    record_fields(nx, &rec_first, &rec_second);
-    for (int j = 0; j < d; ++j) {
-        split_first.push_back(1 + j);
-        split_second.push_back(1 + d + j);
-    }
-
-    // initial uniform partition with n_min samples per leaf
-    SubList init = uniform_split(d, box_lo, box_hi, cfg->split_log2, 0);
-    std::fill(init.n.begin(), init.n.end(), cfg->n_min);
-    uint64_t evals = static_cast<uint64_t>(init.size()) * cfg->n_min;
-    if (evals > cfg->max_evals)
-        return fail(BFI_EINVAL, "initial partition exceeds max_evals");
-    LeafSet L;
-    L.d = d;
-    L.nx = nx;
-    L.id = init.id;
-    L.n = init.n;
-    L.lo = init.lo;
-    L.hi = init.hi;
-    BFI_TRY(eval_list(ctx, *lat, prec, seed, init, launch, &L.rec, &L.split));
-
-    bfi_status status = BFI_OK;
-    const double min_ess = cfg->min_ess > 0 ? cfg->min_ess : 100.0;
-    int rounds = 0;
-    bfi_result res{};
-    std::vector<LeafAnalysis> an;
-    for (;;) {
-        BFI_TRY(analyse(nx, d, L.size(), L.lo.data(), L.hi.data(), L.rec.data(), L.split.data(),
-                        &an, &res));
-        if (rel_err(res) <= cfg->target_rel_err && res.ess >= min_ess)
-            break;
-        if (rounds >= cfg->max_rounds) {
-            status = BFI_EBUDGET;
-            break;
+    return guarded([&]() -> bfi_status {
+        if (!ctx || !box_lo || !box_hi || !out)
+            return fail(BFI_EINVAL, "arguments must be non-NULL");
+        if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
+            return fail(BFI_EINVAL, "unknown precision");
+        BFI_TRY(check_lattice(lat));
+        BFI_TRY(check_config(cfg));
+        if (lat->antithetic)
+            return fail(BFI_EUNSUPPORTED, "adaptive refinement uses single points (antithetic = 0)");
+        const int nx = lat->nx, d = nx * lat->nt;
+        if (d > 32)
+            return fail(BFI_EUNSUPPORTED, "adaptive refinement needs d <= 32 (split statistics)");
+        for (int k = 0; k < d; ++k)
+            if (!std::isfinite(box_lo[k]) || !std::isfinite(box_hi[k]) || !(box_lo[k] < box_hi[k]))
+                return fail(BFI_EINVAL, "box dim %d: need finite lo < hi", k);
+        const int rec_len = BFI_PARTIAL_LEN(nx), split_len = BFI_SPLIT_LEN(d);
+        std::vector<int> rec_first, rec_second, split_first, split_second;
+        record_fields(nx, &rec_first, &rec_second);
+        for (int j = 0; j < d; ++j) {
+            split_first.push_back(1 + j);
+            split_second.push_back(1 + d + j);
         }
-        std::vector<int32_t> action(L.size());
-        decide(an, L.id.data(), L.n.data(), *cfg, action.data());
 
-        // planned sample counts: children clamp(n, n_min, n_max) each, doubled
-        // leaves 2n; scaled by a power of two up to the round's work floor
-        std::vector<size_t> order(L.size());
-        std::iota(order.begin(), order.end(), 0);
-        std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-            if (an[x].e != an[y].e)
-                return an[x].e > an[y].e;
-            return L.id[x] < L.id[y];
-        });
-        // planned count of a refined leaf at scale factor f (within n_max)
-        std::vector<uint64_t> target(L.size(), 0);  // new per-leaf (or per-child) count
-        auto plan_counts = [&](uint64_t f, bool *grew) {
-            uint64_t planned = 0;
+        // initial uniform partition with n_min samples per leaf
+        SubList init = uniform_split(d, box_lo, box_hi, cfg->split_log2, 0);
+        std::fill(init.n.begin(), init.n.end(), cfg->n_min);
+        uint64_t evals = static_cast<uint64_t>(init.size()) * cfg->n_min;
+        if (evals > cfg->max_evals)
+            return fail(BFI_EINVAL, "initial partition exceeds max_evals");
+        LeafSet L;
+        L.d = d;
+        L.nx = nx;
+        L.id = init.id;
+        L.n = init.n;
+        L.lo = init.lo;
+        L.hi = init.hi;
+        BFI_TRY(eval_list(ctx, *lat, prec, seed, init, launch, &L.rec, &L.split));
+
+        bfi_status status = BFI_OK;
+        const double min_ess = cfg->min_ess > 0 ? cfg->min_ess : 100.0;
+        int rounds = 0;
+        bfi_result res{};
+        std::vector<LeafAnalysis> an;
+        for (;;) {
+            BFI_TRY(analyse(nx, d, L.size(), L.lo.data(), L.hi.data(), L.rec.data(), L.split.data(),
+                            &an, &res));
+            if (rel_err(res) <= cfg->target_rel_err && res.ess >= min_ess)
+                break;
+            if (rounds >= cfg->max_rounds) {
+                status = BFI_EBUDGET;
+                break;
+            }
+            std::vector<int32_t> action(L.size());
+            decide(an, L.id.data(), L.n.data(), *cfg, action.data());
+
+            // planned sample counts: children clamp(n, n_min, n_max) each, doubled
+            // leaves 2n; scaled by a power of two up to the round's work floor
+            std::vector<size_t> order(L.size());
+            std::iota(order.begin(), order.end(), 0);
+            std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+                if (an[x].e != an[y].e)
+                    return an[x].e > an[y].e;
+                return L.id[x] < L.id[y];
+            });
+            // planned count of a refined leaf at scale factor f (within n_max)
+            std::vector<uint64_t> target(L.size(), 0);  // new per-leaf (or per-child) count
+            auto plan_counts = [&](uint64_t f, bool *grew) {
+                uint64_t planned = 0;
+                for (size_t s = 0; s < L.size(); ++s) {
+                    if (action[s] < 0)
+                        continue;
+                    const uint64_t base = action[s] == 0 ? 2 * L.n[s]
+                                                          : std::min(std::max(L.n[s], cfg->n_min),
+                                                                     cfg->n_max);
+                    const uint64_t t =
+                        std::max(base, std::min(base * f, std::max(cfg->n_max, base)));
+                    if (grew && t > target[s])
+                        *grew = true;
+                    target[s] = t;
+                    planned += action[s] == 0 ? t - L.n[s] : 2 * t;
+                }
+                return planned;
+            };
+            uint64_t f = 1;
+            uint64_t planned = plan_counts(f, nullptr);
+            // work floor: scale the refined leaves by powers of two; once n_max caps
+            // them, refine further leaves in variance order
+            size_t next_leaf = 0;
+            while (cfg->round_evals > 0 && planned < cfg->round_evals) {
+                bool grew = false;
+                const std::vector<uint64_t> keep = target;
+                const uint64_t p2 = plan_counts(2 * f, &grew);
+                if (grew) {
+                    f *= 2;
+                    planned = p2;
+                    continue;
+                }
+                target = keep;
+                while (next_leaf < order.size() && action[order[next_leaf]] != -1)
+                    ++next_leaf;
+                if (next_leaf == order.size())
+                    break;
+                const size_t s = order[next_leaf];
+                action[s] = leaf_action(an[s], L.id[s], L.n[s], *cfg);
+                if (action[s] < 0)
+                    action[s] = -2;  // neither split nor doubling possible: skip it
+                planned = plan_counts(f, nullptr);
+            }
+            for (auto &a : action)
+                if (a == -2)
+                    a = -1;
+            // trim to the evaluation budget in priority order
+            uint64_t cost = 0;
+            for (size_t s : order) {
+                if (action[s] < 0)
+                    continue;
+                const uint64_t c = action[s] == 0 ? target[s] - L.n[s] : 2 * target[s];
+                if (evals + cost + c > cfg->max_evals)
+                    action[s] = -1;
+                else
+                    cost += c;
+            }
+            if (cost == 0) {
+                status = BFI_EBUDGET;
+                break;
+            }
+
+            // work list: children (fresh streams) and continuations
+            SubList work;
+            work.d = d;
+            struct Origin {
+                size_t leaf;
+                int kind;  // 0 continuation, 1 lower child, 2 upper child
+            };
+            std::vector<Origin> origin;
             for (size_t s = 0; s < L.size(); ++s) {
                 if (action[s] < 0)
                     continue;
-                const uint64_t base = action[s] == 0 ? 2 * L.n[s]
-                                                      : std::min(std::max(L.n[s], cfg->n_min),
-                                                                 cfg->n_max);
-                const uint64_t t =
-                    std::max(base, std::min(base * f, std::max(cfg->n_max, base)));
-                if (grew && t > target[s])
-                    *grew = true;
-                target[s] = t;
-                planned += action[s] == 0 ? t - L.n[s] : 2 * t;
+                const double *lo = &L.lo[s * d], *hi = &L.hi[s * d];
+                if (action[s] == 0) {
+                    work.id.push_back(L.id[s]);
+                    work.n.push_back(target[s] - L.n[s]);
+                    work.offset.push_back(L.n[s]);
+                    work.lo.insert(work.lo.end(), lo, lo + d);
+                    work.hi.insert(work.hi.end(), hi, hi + d);
+                    origin.push_back({s, 0});
+                    continue;
+                }
+                const int j = action[s] - 1;
+                const double mid = 0.5 * (lo[j] + hi[j]);
+                const uint64_t child_n = target[s];
+                for (int half = 0; half < 2; ++half) {
+                    work.id.push_back(2 * L.id[s] + half);
+                    work.n.push_back(child_n);
+                    work.offset.push_back(0);
+                    work.lo.insert(work.lo.end(), lo, lo + d);
+                    work.hi.insert(work.hi.end(), hi, hi + d);
+                    if (half == 0)
+                        work.hi[(work.id.size() - 1) * d + j] = mid;
+                    else
+                        work.lo[(work.id.size() - 1) * d + j] = mid;
+                    origin.push_back({s, 1 + half});
+                }
             }
-            return planned;
-        };
-        uint64_t f = 1;
-        uint64_t planned = plan_counts(f, nullptr);
-        // work floor: scale the refined leaves by powers of two; once n_max caps
-        // them, refine further leaves in variance order
-        size_t next_leaf = 0;
-        while (cfg->round_evals > 0 && planned < cfg->round_evals) {
-            bool grew = false;
-            const std::vector<uint64_t> keep = target;
-            const uint64_t p2 = plan_counts(2 * f, &grew);
-            if (grew) {
-                f *= 2;
-                planned = p2;
-                continue;
+            std::vector<double> wrec, wsplit;
+            BFI_TRY(eval_list(ctx, *lat, prec, seed, work, launch, &wrec, &wsplit));
+            evals += cost;
+
+            // fold the results into the leaf set, keeping leaf order (children in place)
+            LeafSet N;
+            N.d = d;
+            N.nx = nx;
+            std::vector<std::vector<size_t>> from(L.size());
+            for (size_t w = 0; w < origin.size(); ++w)
+                from[origin[w].leaf].push_back(w);
+            auto push_leaf = [&](uint64_t id, uint64_t n, const double *lo, const double *hi,
+                                 const double *rec, const double *spl) {
+                N.id.push_back(id);
+                N.n.push_back(n);
+                N.lo.insert(N.lo.end(), lo, lo + d);
+                N.hi.insert(N.hi.end(), hi, hi + d);
+                N.rec.insert(N.rec.end(), rec, rec + rec_len);
+                N.split.insert(N.split.end(), spl, spl + split_len);
+            };
+            for (size_t s = 0; s < L.size(); ++s) {
+                if (action[s] < 0) {
+                    push_leaf(L.id[s], L.n[s], &L.lo[s * d], &L.hi[s * d], &L.rec[s * rec_len],
+                              &L.split[s * split_len]);
+                } else if (action[s] == 0) {
+                    const size_t w = from[s][0];
+                    std::vector<double> rec(&L.rec[s * rec_len], &L.rec[s * rec_len] + rec_len);
+                    std::vector<double> spl(&L.split[s * split_len],
+                                            &L.split[s * split_len] + split_len);
+                    merge_shifted(rec.data(), &wrec[w * rec_len], 1, rec_first, rec_second, 0);
+                    merge_shifted(spl.data(), &wsplit[w * split_len], 0, split_first, split_second, -1);
+                    push_leaf(L.id[s], target[s], &L.lo[s * d], &L.hi[s * d], rec.data(), spl.data());
+                } else {
+                    for (size_t w : from[s])
+                        push_leaf(work.id[w], work.n[w], &work.lo[w * d], &work.hi[w * d],
+                                  &wrec[w * rec_len], &wsplit[w * split_len]);
+                }
             }
-            target = keep;
-            while (next_leaf < order.size() && action[order[next_leaf]] != -1)
-                ++next_leaf;
-            if (next_leaf == order.size())
-                break;
-            const size_t s = order[next_leaf];
-            action[s] = leaf_action(an[s], L.id[s], L.n[s], *cfg);
-            if (action[s] < 0)
-                action[s] = -2;  // neither split nor doubling possible: skip it
-            planned = plan_counts(f, nullptr);
-        }
-        for (auto &a : action)
-            if (a == -2)
-                a = -1;
-        // trim to the evaluation budget in priority order
-        uint64_t cost = 0;
-        for (size_t s : order) {
-            if (action[s] < 0)
-                continue;
-            const uint64_t c = action[s] == 0 ? target[s] - L.n[s] : 2 * target[s];
-            if (evals + cost + c > cfg->max_evals)
-                action[s] = -1;
-            else
-                cost += c;
-        }
-        if (cost == 0) {
-            status = BFI_EBUDGET;
-            break;
+            L = std::move(N);
+            ++rounds;
         }
 
-        // work list: children (fresh streams) and continuations
-        SubList work;
-        work.d = d;
-        struct Origin {
-            size_t leaf;
-            int kind;  // 0 continuation, 1 lower child, 2 upper child
-        };
-        std::vector<Origin> origin;
-        for (size_t s = 0; s < L.size(); ++s) {
-            if (action[s] < 0)
-                continue;
-            const double *lo = &L.lo[s * d], *hi = &L.hi[s * d];
-            if (action[s] == 0) {
-                work.id.push_back(L.id[s]);
-                work.n.push_back(target[s] - L.n[s]);
-                work.offset.push_back(L.n[s]);
-                work.lo.insert(work.lo.end(), lo, lo + d);
-                work.hi.insert(work.hi.end(), hi, hi + d);
-                origin.push_back({s, 0});
-                continue;
-            }
-            const int j = action[s] - 1;
-            const double mid = 0.5 * (lo[j] + hi[j]);
-            const uint64_t child_n = target[s];
-            for (int half = 0; half < 2; ++half) {
-                work.id.push_back(2 * L.id[s] + half);
-                work.n.push_back(child_n);
-                work.offset.push_back(0);
-                work.lo.insert(work.lo.end(), lo, lo + d);
-                work.hi.insert(work.hi.end(), hi, hi + d);
-                if (half == 0)
-                    work.hi[(work.id.size() - 1) * d + j] = mid;
-                else
-                    work.lo[(work.id.size() - 1) * d + j] = mid;
-                origin.push_back({s, 1 + half});
-            }
+        *out = res;
+        if (stats) {
+            stats->rounds = rounds;
+            stats->leaves = L.size();
+            stats->evals = evals;
+            stats->rel_err = rel_err(res);
         }
-        std::vector<double> wrec, wsplit;
-        BFI_TRY(eval_list(ctx, *lat, prec, seed, work, launch, &wrec, &wsplit));
-        evals += cost;
-
-        // fold the results into the leaf set, keeping leaf order (children in place)
-        LeafSet N;
-        N.d = d;
-        N.nx = nx;
-        std::vector<std::vector<size_t>> from(L.size());
-        for (size_t w = 0; w < origin.size(); ++w)
-            from[origin[w].leaf].push_back(w);
-        auto push_leaf = [&](uint64_t id, uint64_t n, const double *lo, const double *hi,
-                             const double *rec, const double *spl) {
-            N.id.push_back(id);
-            N.n.push_back(n);
-            N.lo.insert(N.lo.end(), lo, lo + d);
-            N.hi.insert(N.hi.end(), hi, hi + d);
-            N.rec.insert(N.rec.end(), rec, rec + rec_len);
-            N.split.insert(N.split.end(), spl, spl + split_len);
-        };
-        for (size_t s = 0; s < L.size(); ++s) {
-            if (action[s] < 0) {
-                push_leaf(L.id[s], L.n[s], &L.lo[s * d], &L.hi[s * d], &L.rec[s * rec_len],
-                          &L.split[s * split_len]);
-            } else if (action[s] == 0) {
-                const size_t w = from[s][0];
-                std::vector<double> rec(&L.rec[s * rec_len], &L.rec[s * rec_len] + rec_len);
-                std::vector<double> spl(&L.split[s * split_len],
-                                        &L.split[s * split_len] + split_len);
-                merge_shifted(rec.data(), &wrec[w * rec_len], 1, rec_first, rec_second, 0);
-                merge_shifted(spl.data(), &wsplit[w * split_len], 0, split_first, split_second, -1);
-                push_leaf(L.id[s], target[s], &L.lo[s * d], &L.hi[s * d], rec.data(), spl.data());
-            } else {
-                for (size_t w : from[s])
-                    push_leaf(work.id[w], work.n[w], &work.lo[w * d], &work.hi[w * d],
-                              &wrec[w * rec_len], &wsplit[w * split_len]);
-            }
+        if (n_leaves)
+            *n_leaves = L.size();
+        const size_t m = std::min(cap, L.size());
+        for (size_t s = 0; s < m; ++s) {
+            if (leaf_id)
+                leaf_id[s] = L.id[s];
+            if (leaf_n)
+                leaf_n[s] = L.n[s];
+            if (leaf_offset)
+                leaf_offset[s] = 0;
+            if (leaf_lo)
+                std::memcpy(leaf_lo + s * d, &L.lo[s * d], d * sizeof(double));
+            if (leaf_hi)
+                std::memcpy(leaf_hi + s * d, &L.hi[s * d], d * sizeof(double));
         }
-        L = std::move(N);
-        ++rounds;
-    }
-
-    *out = res;
-    if (stats) {
-        stats->rounds = rounds;
-        stats->leaves = L.size();
-        stats->evals = evals;
-        stats->rel_err = rel_err(res);
-    }
-    if (n_leaves)
-        *n_leaves = L.size();
-    const size_t m = std::min(cap, L.size());
-    for (size_t s = 0; s < m; ++s) {
-        if (leaf_id)
-            leaf_id[s] = L.id[s];
-        if (leaf_n)
-            leaf_n[s] = L.n[s];
-        if (leaf_offset)
-            leaf_offset[s] = 0;
-        if (leaf_lo)
-            std::memcpy(leaf_lo + s * d, &L.lo[s * d], d * sizeof(double));
-        if (leaf_hi)
-            std::memcpy(leaf_hi + s * d, &L.hi[s * d], d * sizeof(double));
-    }
-    if (status == BFI_EBUDGET)
-        fail(BFI_EBUDGET, "stopped after %d rounds at relative error %.3g (target %.3g)", rounds,
-             rel_err(res), cfg->target_rel_err);
-    return status;
+        if (status == BFI_EBUDGET)
+            fail(BFI_EBUDGET, "stopped after %d rounds at relative error %.3g (target %.3g)", rounds,
+                 rel_err(res), cfg->target_rel_err);
+        return status;
+    });
 }
 
 bfi_status bfi_adaptive_decide(const bfi_lattice *lat, const bfi_subvolumes *leaves,
                                const double *partials, const double *split,
                                const bfi_adaptive_config *cfg, int32_t *action)
 {
-    if (!lat || !leaves || !partials || !split || !action)
-        return fail(BFI_EINVAL, "arguments must be non-NULL");
-    BFI_TRY(check_config(cfg));
-    if (lat->antithetic)
-        return fail(BFI_EUNSUPPORTED, "adaptive refinement uses single points (antithetic = 0)");
-    if (lat->nx < 1 || lat->nt < 1 || lat->nx * lat->nt > 32)
-        return fail(BFI_EINVAL, "adaptive refinement needs 1 <= d <= 32");
-    if (leaves->count == 0)
-        return fail(BFI_EINVAL, "no leaves");
-    if (!leaves->id || !leaves->lo || !leaves->hi || !leaves->n)
-        return fail(BFI_EINVAL, "leaf arrays must be non-NULL");
-    std::vector<LeafAnalysis> an;
-    bfi_result res;
-    BFI_TRY(analyse(lat->nx, lat->nx * lat->nt, leaves->count, leaves->lo, leaves->hi, partials,
-                    split, &an, &res));
-    decide(an, leaves->id, leaves->n, *cfg, action);
-    return BFI_OK;
+    return guarded([&]() -> bfi_status {
+        if (!lat || !leaves || !partials || !split || !action)
+            return fail(BFI_EINVAL, "arguments must be non-NULL");
+        BFI_TRY(check_config(cfg));
+        if (lat->antithetic)
+            return fail(BFI_EUNSUPPORTED, "adaptive refinement uses single points (antithetic = 0)");
+        if (lat->nx < 1 || lat->nt < 1 || lat->nx * lat->nt > 32)
+            return fail(BFI_EINVAL, "adaptive refinement needs 1 <= d <= 32");
+        if (leaves->count == 0)
+            return fail(BFI_EINVAL, "no leaves");
+        if (!leaves->id || !leaves->lo || !leaves->hi || !leaves->n)
+            return fail(BFI_EINVAL, "leaf arrays must be non-NULL");
+        std::vector<LeafAnalysis> an;
+        bfi_result res;
+        BFI_TRY(analyse(lat->nx, lat->nx * lat->nt, leaves->count, leaves->lo, leaves->hi, partials,
+                        split, &an, &res));
+        decide(an, leaves->id, leaves->n, *cfg, action);
+        return BFI_OK;
+    });
 }
 
 bfi_status bfi_partials_merge(int32_t nx, size_t count, double *acc, const double *more)
 {
-    if (nx < 1 || nx > BFI_MAX_NX)
-        return fail(BFI_EINVAL, "nx must be in [1, %d]", BFI_MAX_NX);
-    if (count == 0)
+    return guarded([&]() -> bfi_status {
+        if (nx < 1 || nx > BFI_MAX_NX)
+            return fail(BFI_EINVAL, "nx must be in [1, %d]", BFI_MAX_NX);
+        if (count == 0)
+            return BFI_OK;
+        if (!acc || !more)
+            return fail(BFI_EINVAL, "record arrays must be non-NULL");
+        const size_t len = BFI_PARTIAL_LEN(nx);
+        constexpr double kMaxCount = 9007199254740992.0;  // 2^53: counts stay exact
+        for (size_t i = 0; i < count; ++i) {
+            const double *a = acc + i * len, *b = more + i * len;
+            for (const double *r : {a, b}) {
+                if (!(r[0] >= 0) || !(r[0] <= kMaxCount) || r[0] != std::floor(r[0]))
+                    return fail(BFI_EINVAL, "record %zu: sample count must be a whole number >= 0",
+                                i);
+                if (r[0] > 0 && !std::isfinite(r[1]))
+                    return fail(BFI_EINVAL, "record %zu: shift must be finite", i);
+            }
+            if (a[0] + b[0] > kMaxCount)
+                return fail(BFI_EINVAL, "record %zu: merged sample count exceeds 2^53", i);
+        }
+        std::vector<int> first, second;
+        record_fields(nx, &first, &second);
+        for (size_t i = 0; i < count; ++i) {
+            double *a = acc + i * len;
+            const double *b = more + i * len;
+            if (b[0] == 0)
+                continue;
+            if (a[0] == 0) {
+                std::memcpy(a, b, len * sizeof(double));
+                continue;
+            }
+            merge_shifted(a, b, 1, first, second, 0);
+        }
         return BFI_OK;
-    if (!acc || !more)
-        return fail(BFI_EINVAL, "record arrays must be non-NULL");
-    const size_t len = BFI_PARTIAL_LEN(nx);
-    constexpr double kMaxCount = 9007199254740992.0;  // 2^53: counts stay exact
-    for (size_t i = 0; i < count; ++i) {
-        const double *a = acc + i * len, *b = more + i * len;
-        for (const double *r : {a, b}) {
-            if (!(r[0] >= 0) || !(r[0] <= kMaxCount) || r[0] != std::floor(r[0]))
-                return fail(BFI_EINVAL, "record %zu: sample count must be a whole number >= 0",
-                            i);
-            if (r[0] > 0 && !std::isfinite(r[1]))
-                return fail(BFI_EINVAL, "record %zu: shift must be finite", i);
-        }
-        if (a[0] + b[0] > kMaxCount)
-            return fail(BFI_EINVAL, "record %zu: merged sample count exceeds 2^53", i);
-    }
-    std::vector<int> first, second;
-    record_fields(nx, &first, &second);
-    for (size_t i = 0; i < count; ++i) {
-        double *a = acc + i * len;
-        const double *b = more + i * len;
-        if (b[0] == 0)
-            continue;
-        if (a[0] == 0) {
-            std::memcpy(a, b, len * sizeof(double));
-            continue;
-        }
-        merge_shifted(a, b, 1, first, second, 0);
-    }
-    return BFI_OK;
+    });
 }
 
 }  // extern "C"

@@ -431,11 +431,12 @@ bfi_status plan_build_core(bfi_context *ctx, int kind, const bfi_lattice &lat, i
     std::vector<WorkItem> items;
     std::vector<uint32_t> first(subs.size() + 1, 0);
     uint64_t total_items = 0, n_evals = 0;
-    for (size_t s = 0; s < subs.size(); ++s)
-        total_items += (subs.n[s] + chunk - 1) / chunk;
-    if (total_items > 0x7FFFFFFFull)
-        return fail(BFI_EINVAL, "%llu work items exceed 2^31; raise samples_per_thread",
-                    static_cast<unsigned long long>(total_items));
+    for (size_t s = 0; s < subs.size(); ++s) {
+        // checked per subvolume, so the running count cannot wrap
+        total_items += subs.n[s] / chunk + (subs.n[s] % chunk != 0);
+        if (total_items > 0x7FFFFFFFull)
+            return fail(BFI_EINVAL, "more than 2^31 work items; raise samples_per_thread");
+    }
     items.reserve(total_items);
     for (size_t s = 0; s < subs.size(); ++s) {
         first[s] = static_cast<uint32_t>(items.size());
@@ -640,230 +641,261 @@ const char *bfi_last_error(void) { return g_last_error.c_str(); }
 
 bfi_status bfi_shape_supported(int32_t nx, int32_t nt)
 {
-    return shape_compiled(nx, nt) ? BFI_OK : BFI_EUNSUPPORTED;
+    return guarded([&]() -> bfi_status {
+        return shape_compiled(nx, nt) ? BFI_OK : BFI_EUNSUPPORTED;
+    });
 }
 
 bfi_status bfi_supported_shapes(int32_t *pairs, int32_t cap, int32_t *count)
 {
-    if (!count || (cap > 0 && !pairs))
-        return fail(BFI_EINVAL, "bad arguments");
-    int32_t n = 0;
-#define BFI_SHAPE_LIST(NX, NT)      \
-    if (n < cap) {                  \
-        pairs[2 * n] = NX;          \
-        pairs[2 * n + 1] = NT;      \
-    }                               \
-    ++n;
-    BFI_SHAPES(BFI_SHAPE_LIST)
-#undef BFI_SHAPE_LIST
-    *count = n;
-    return BFI_OK;
+    return guarded([&]() -> bfi_status {
+        if (!count || (cap > 0 && !pairs))
+            return fail(BFI_EINVAL, "bad arguments");
+        int32_t n = 0;
+    #define BFI_SHAPE_LIST(NX, NT)      \
+        if (n < cap) {                  \
+            pairs[2 * n] = NX;          \
+            pairs[2 * n + 1] = NT;      \
+        }                               \
+        ++n;
+        BFI_SHAPES(BFI_SHAPE_LIST)
+    #undef BFI_SHAPE_LIST
+        *count = n;
+        return BFI_OK;
+    });
 }
 
 bfi_status bfi_context_create(int32_t device, bfi_context **out)
 {
-    if (!out)
-        return fail(BFI_EINVAL, "out is NULL");
-    int ndev = 0;
-    BFI_HIP(hipGetDeviceCount(&ndev));
-    if (device < 0 || device >= ndev)
-        return fail(BFI_EINVAL, "device %d out of range (%d devices)", device, ndev);
-    BFI_HIP(hipSetDevice(device));
-    hipDeviceProp_t prop;
-    BFI_HIP(hipGetDeviceProperties(&prop, device));
-    auto *ctx = new bfi_context();
-    ctx->device = device;
-    ctx->cu_count = prop.multiProcessorCount;
-    ctx->arch = prop.gcnArchName;
-    hipError_t e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        delete ctx;
-        return hip_fail(e, "hipStreamCreateWithFlags");
-    }
-    *out = ctx;
-    return BFI_OK;
+    return guarded([&]() -> bfi_status {
+        if (!out)
+            return fail(BFI_EINVAL, "out is NULL");
+        int ndev = 0;
+        BFI_HIP(hipGetDeviceCount(&ndev));
+        if (device < 0 || device >= ndev)
+            return fail(BFI_EINVAL, "device %d out of range (%d devices)", device, ndev);
+        BFI_HIP(hipSetDevice(device));
+        hipDeviceProp_t prop;
+        BFI_HIP(hipGetDeviceProperties(&prop, device));
+        auto *ctx = new bfi_context();
+        ctx->device = device;
+        ctx->cu_count = prop.multiProcessorCount;
+        ctx->arch = prop.gcnArchName;
+        hipError_t e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete ctx;
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        }
+        *out = ctx;
+        return BFI_OK;
+    });
 }
 
 bfi_status bfi_context_destroy(bfi_context *ctx)
 {
-    if (!ctx)
+    return guarded([&]() -> bfi_status {
+        if (!ctx)
+            return BFI_OK;
+        if (ctx->stream) {
+            (void)hipStreamSynchronize(ctx->stream);
+            (void)hipStreamDestroy(ctx->stream);
+        }
+        delete ctx;
         return BFI_OK;
-    if (ctx->stream) {
-        (void)hipStreamSynchronize(ctx->stream);
-        (void)hipStreamDestroy(ctx->stream);
-    }
-    delete ctx;
-    return BFI_OK;
+    });
 }
 
 bfi_status bfi_plan_create(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
                            const bfi_subvolumes *subs, const bfi_launch *launch, bfi_plan **out)
 {
-    if (!ctx || !out)
-        return fail(BFI_EINVAL, "context and out must be non-NULL");
-    if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
-        return fail(BFI_EINVAL, "unknown precision %d", static_cast<int>(prec));
-    BFI_TRY(check_lattice(lat));
-    BFI_TRY(check_subvolumes(lat, subs));
-    BFI_HIP(hipSetDevice(ctx->device));
-    return plan_build(ctx, *lat, prec, SubList::copy_of(*subs, lat->nx * lat->nt), launch, false,
-                      out);
+    return guarded([&]() -> bfi_status {
+        if (!ctx || !out)
+            return fail(BFI_EINVAL, "context and out must be non-NULL");
+        if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
+            return fail(BFI_EINVAL, "unknown precision %d", static_cast<int>(prec));
+        BFI_TRY(check_lattice(lat));
+        BFI_TRY(check_subvolumes(lat, subs));
+        BFI_HIP(hipSetDevice(ctx->device));
+        return plan_build(ctx, *lat, prec, SubList::copy_of(*subs, lat->nx * lat->nt), launch, false,
+                          out);
+    });
 }
 
 bfi_status bfi_plan_run(bfi_plan *p, uint64_t seed, double *partials_dev, void *stream)
 {
-    if (!p)
-        return fail(BFI_EINVAL, "plan is NULL");
-    BFI_HIP(hipSetDevice(p->ctx->device));
-    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : p->ctx->stream;
-    if (p->launch.use_graph) {
-        BFI_TRY(plan_set_seed(p, seed));
-        const bfi_plan::Replay *rp = nullptr;
-        for (const bfi_plan::Replay &r : p->replays)
-            if (r.stream == st && r.dst == partials_dev)
-                rp = &r;
-        if (!rp) {
-            if (p->replays.size() >= bfi_plan::kMaxReplays) {
-                // replays of this plan run in order on their streams, and the
-                // host waits for the oldest before dropping it
-                if (p->last_stream)
-                    BFI_HIP(hipStreamSynchronize(p->last_stream));
-                BFI_HIP(hipStreamSynchronize(p->replays.front().stream));
-                (void)hipGraphExecDestroy(p->replays.front().exec);
-                (void)hipGraphDestroy(p->replays.front().def);
-                p->replays.erase(p->replays.begin());
+    return guarded([&]() -> bfi_status {
+        if (!p)
+            return fail(BFI_EINVAL, "plan is NULL");
+        BFI_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t st = stream ? static_cast<hipStream_t>(stream) : p->ctx->stream;
+        if (p->launch.use_graph) {
+            BFI_TRY(plan_set_seed(p, seed));
+            // the replays are kept in order of last use: a hit moves to the back
+            const bfi_plan::Replay *rp = nullptr;
+            for (size_t i = 0; i < p->replays.size(); ++i) {
+                if (p->replays[i].stream == st && p->replays[i].dst == partials_dev) {
+                    const bfi_plan::Replay hit = p->replays[i];
+                    p->replays.erase(p->replays.begin() + static_cast<std::ptrdiff_t>(i));
+                    p->replays.push_back(hit);
+                    rp = &p->replays.back();
+                    break;
+                }
             }
-            BFI_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            bfi_status s = plan_enqueue(p, seed, partials_dev, st, false);
-            hipGraph_t g = nullptr;
-            hipError_t e = hipStreamEndCapture(st, &g);
-            if (s != BFI_OK) {
-                if (g)
+            if (!rp) {
+                if (p->replays.size() >= bfi_plan::kMaxReplays) {
+                    // drop the least recently used replay; the host waits for the
+                    // plan's work on both streams before destroying it
+                    if (p->last_stream)
+                        BFI_HIP(hipStreamSynchronize(p->last_stream));
+                    BFI_HIP(hipStreamSynchronize(p->replays.front().stream));
+                    (void)hipGraphExecDestroy(p->replays.front().exec);
+                    (void)hipGraphDestroy(p->replays.front().def);
+                    p->replays.erase(p->replays.begin());
+                }
+                BFI_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                bfi_status s = plan_enqueue(p, seed, partials_dev, st, false);
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(st, &g);
+                if (s != BFI_OK) {
+                    if (g)
+                        (void)hipGraphDestroy(g);
+                    return s;
+                }
+                BFI_HIP(e);
+                bfi_plan::Replay r;
+                r.def = g;
+                e = hipGraphInstantiate(&r.exec, g, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
                     (void)hipGraphDestroy(g);
-                return s;
+                    return hip_fail(e, "hipGraphInstantiate");
+                }
+                r.stream = st;
+                r.dst = partials_dev;
+                p->replays.push_back(r);
+                rp = &p->replays.back();
             }
-            BFI_HIP(e);
-            bfi_plan::Replay r;
-            r.def = g;
-            e = hipGraphInstantiate(&r.exec, g, nullptr, nullptr, 0);
-            if (e != hipSuccess) {
-                (void)hipGraphDestroy(g);
-                return hip_fail(e, "hipGraphInstantiate");
-            }
-            r.stream = st;
-            r.dst = partials_dev;
-            p->replays.push_back(r);
-            rp = &p->replays.back();
+            // a replay is timed as a whole: queue reset, kernel and merge
+            BFI_HIP(hipEventRecord(p->ev_start, st));
+            BFI_HIP(hipGraphLaunch(rp->exec, st));
+            BFI_HIP(hipEventRecord(p->ev_stop, st));
+        } else {
+            BFI_TRY(plan_enqueue(p, seed, partials_dev, st, true));
         }
-        // a replay is timed as a whole: queue reset, kernel and merge
-        BFI_HIP(hipEventRecord(p->ev_start, st));
-        BFI_HIP(hipGraphLaunch(rp->exec, st));
-        BFI_HIP(hipEventRecord(p->ev_stop, st));
-    } else {
-        BFI_TRY(plan_enqueue(p, seed, partials_dev, st, true));
-    }
-    p->last_stream = st;
-    return BFI_OK;
+        p->last_stream = st;
+        return BFI_OK;
+    });
 }
 
 bfi_status bfi_plan_partials(bfi_plan *p, double *partials)
 {
-    if (!p || !partials)
-        return fail(BFI_EINVAL, "plan and partials must be non-NULL");
-    BFI_HIP(hipSetDevice(p->ctx->device));
-    if (p->last_stream)
-        BFI_HIP(hipStreamSynchronize(p->last_stream));
-    BFI_HIP(hipMemcpy(partials, p->d_sub_rec, p->subs.size() * p->rec_len * sizeof(double),
-                      hipMemcpyDeviceToHost));
-    return BFI_OK;
+    return guarded([&]() -> bfi_status {
+        if (!p || !partials)
+            return fail(BFI_EINVAL, "plan and partials must be non-NULL");
+        BFI_HIP(hipSetDevice(p->ctx->device));
+        if (p->last_stream)
+            BFI_HIP(hipStreamSynchronize(p->last_stream));
+        BFI_HIP(hipMemcpy(partials, p->d_sub_rec, p->subs.size() * p->rec_len * sizeof(double),
+                          hipMemcpyDeviceToHost));
+        return BFI_OK;
+    });
 }
 
 bfi_status bfi_plan_info(const bfi_plan *p, uint64_t *n_items, uint64_t *n_evals,
                          bfi_launch *resolved)
 {
-    if (!p)
-        return fail(BFI_EINVAL, "plan is NULL");
-    if (n_items)
-        *n_items = p->nitems;
-    if (n_evals)
-        *n_evals = p->n_evals;
-    if (resolved)
-        *resolved = p->launch;
-    return BFI_OK;
+    return guarded([&]() -> bfi_status {
+        if (!p)
+            return fail(BFI_EINVAL, "plan is NULL");
+        if (n_items)
+            *n_items = p->nitems;
+        if (n_evals)
+            *n_evals = p->n_evals;
+        if (resolved)
+            *resolved = p->launch;
+        return BFI_OK;
+    });
 }
 
 bfi_status bfi_plan_kernel_ms(bfi_plan *p, double *ms)
 {
-    if (!p || !ms)
-        return fail(BFI_EINVAL, "plan and ms must be non-NULL");
-    if (!p->last_stream)
-        return fail(BFI_EINVAL, "plan has not run");
-    BFI_HIP(hipSetDevice(p->ctx->device));
-    BFI_HIP(hipEventSynchronize(p->ev_stop));
-    float f = 0.0f;
-    BFI_HIP(hipEventElapsedTime(&f, p->ev_start, p->ev_stop));
-    *ms = f;
-    return BFI_OK;
+    return guarded([&]() -> bfi_status {
+        if (!p || !ms)
+            return fail(BFI_EINVAL, "plan and ms must be non-NULL");
+        if (!p->last_stream)
+            return fail(BFI_EINVAL, "plan has not run");
+        BFI_HIP(hipSetDevice(p->ctx->device));
+        BFI_HIP(hipEventSynchronize(p->ev_stop));
+        float f = 0.0f;
+        BFI_HIP(hipEventElapsedTime(&f, p->ev_start, p->ev_stop));
+        *ms = f;
+        return BFI_OK;
+    });
 }
 
 bfi_status bfi_plan_destroy(bfi_plan *p)
 {
-    if (p && p->ctx)
-        (void)hipSetDevice(p->ctx->device);
-    if (p && p->last_stream)
-        (void)hipStreamSynchronize(p->last_stream);
-    return plan_free(p);
+    return guarded([&]() -> bfi_status {
+        if (p && p->ctx)
+            (void)hipSetDevice(p->ctx->device);
+        if (p && p->last_stream)
+            (void)hipStreamSynchronize(p->last_stream);
+        return plan_free(p);
+    });
 }
 
 bfi_status bfi_eval(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec, uint64_t seed,
                     const bfi_subvolumes *subs, const bfi_launch *launch, double *partials,
                     double *split)
 {
-    if (!ctx || !partials)
-        return fail(BFI_EINVAL, "context and partials must be non-NULL");
-    if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
-        return fail(BFI_EINVAL, "unknown precision %d", static_cast<int>(prec));
-    BFI_TRY(check_lattice(lat));
-    BFI_TRY(check_subvolumes(lat, subs));
-    if (lat->antithetic && split)
-        return fail(BFI_EUNSUPPORTED, "antithetic pairs have no split statistics");
-    if (subs->count == 0)
-        return BFI_OK;
-    BFI_HIP(hipSetDevice(ctx->device));
-    bfi_plan *p = nullptr;
-    BFI_TRY(plan_build(ctx, *lat, prec, SubList::copy_of(*subs, lat->nx * lat->nt), launch,
-                       split != nullptr, &p));
-    bfi_launch l = p->launch;
-    l.use_graph = 0;
-    p->launch = l;
-    bfi_status s = plan_enqueue(p, seed, nullptr, ctx->stream, true);
-    p->last_stream = ctx->stream;
-    if (s == BFI_OK)
-        s = bfi_plan_partials(p, partials);
-    if (s == BFI_OK && split) {
-        hipError_t e = hipMemcpy(split, p->d_sub_split,
-                                 subs->count * BFI_SPLIT_LEN(p->d) * sizeof(double),
-                                 hipMemcpyDeviceToHost);
-        if (e != hipSuccess)
-            s = hip_fail(e, "hipMemcpy(split)");
-    }
-    plan_free(p);
-    return s;
+    return guarded([&]() -> bfi_status {
+        if (!ctx || !partials)
+            return fail(BFI_EINVAL, "context and partials must be non-NULL");
+        if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
+            return fail(BFI_EINVAL, "unknown precision %d", static_cast<int>(prec));
+        BFI_TRY(check_lattice(lat));
+        BFI_TRY(check_subvolumes(lat, subs));
+        if (lat->antithetic && split)
+            return fail(BFI_EUNSUPPORTED, "antithetic pairs have no split statistics");
+        if (subs->count == 0)
+            return BFI_OK;
+        BFI_HIP(hipSetDevice(ctx->device));
+        bfi_plan *p = nullptr;
+        BFI_TRY(plan_build(ctx, *lat, prec, SubList::copy_of(*subs, lat->nx * lat->nt), launch,
+                           split != nullptr, &p));
+        bfi_launch l = p->launch;
+        l.use_graph = 0;
+        p->launch = l;
+        bfi_status s = plan_enqueue(p, seed, nullptr, ctx->stream, true);
+        p->last_stream = ctx->stream;
+        if (s == BFI_OK)
+            s = bfi_plan_partials(p, partials);
+        if (s == BFI_OK && split) {
+            hipError_t e = hipMemcpy(split, p->d_sub_split,
+                                     subs->count * BFI_SPLIT_LEN(p->d) * sizeof(double),
+                                     hipMemcpyDeviceToHost);
+            if (e != hipSuccess)
+                s = hip_fail(e, "hipMemcpy(split)");
+        }
+        plan_free(p);
+        return s;
+    });
 }
 
 bfi_status bfi_finalize(const bfi_lattice *lat, const bfi_subvolumes *subs,
                         const double *partials, bfi_result *out)
 {
-    if (!lat || !subs || !partials || !out)
-        return fail(BFI_EINVAL, "arguments must be non-NULL");
-    if (lat->nx < 1 || lat->nt < 1 || lat->nx > BFI_MAX_NX || lat->nx * lat->nt > BFI_MAX_D)
-        return fail(BFI_EINVAL, "lattice out of range");
-    if (subs->count && (!subs->lo || !subs->hi))
-        return fail(BFI_EINVAL, "subvolume boxes must be non-NULL");
-    if (lat->antithetic != 0 && lat->antithetic != 1)
-        return fail(BFI_EINVAL, "antithetic must be 0 or 1 (got %d)", lat->antithetic);
-    return finalize_records(lat->nx, lat->nx * lat->nt, subs->count, subs->lo, subs->hi,
-                            partials, out, lat->antithetic ? 2 : 1);
+    return guarded([&]() -> bfi_status {
+        if (!lat || !subs || !partials || !out)
+            return fail(BFI_EINVAL, "arguments must be non-NULL");
+        if (lat->nx < 1 || lat->nt < 1 || lat->nx > BFI_MAX_NX || lat->nx * lat->nt > BFI_MAX_D)
+            return fail(BFI_EINVAL, "lattice out of range");
+        if (subs->count && (!subs->lo || !subs->hi))
+            return fail(BFI_EINVAL, "subvolume boxes must be non-NULL");
+        if (lat->antithetic != 0 && lat->antithetic != 1)
+            return fail(BFI_EINVAL, "antithetic must be 0 or 1 (got %d)", lat->antithetic);
+        return finalize_records(lat->nx, lat->nx * lat->nt, subs->count, subs->lo, subs->hi,
+                                partials, out, lat->antithetic ? 2 : 1);
+    });
 }
 
 bfi_status bfi_integrate(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
@@ -871,108 +903,114 @@ bfi_status bfi_integrate(bfi_context *ctx, const bfi_lattice *lat, bfi_precision
                          int32_t split_log2, uint64_t budget, const bfi_launch *launch,
                          bfi_result *out)
 {
-    if (!ctx || !box_lo || !box_hi || !out)
-        return fail(BFI_EINVAL, "arguments must be non-NULL");
-    BFI_TRY(check_lattice(lat));
-    if (split_log2 < 0 || split_log2 > 24)
-        return fail(BFI_EINVAL, "split_log2 must be in [0, 24]");
-    const int d = lat->nx * lat->nt;
-    for (int k = 0; k < d; ++k)
-        if (!std::isfinite(box_lo[k]) || !std::isfinite(box_hi[k]) || !(box_lo[k] < box_hi[k]))
-            return fail(BFI_EINVAL, "box dim %d: need finite lo < hi", k);
-    // the budget counts integrand evaluations: two per antithetic pair
-    const uint64_t per = lat->antithetic ? 2 : 1;
-    if (budget / per < 2 * (uint64_t(1) << split_log2))
-        return fail(BFI_EINVAL, "budget must give every subvolume at least 2 samples");
-    SubList subs = uniform_split(d, box_lo, box_hi, split_log2, budget / per);
-    std::vector<double> partials(subs.size() * BFI_PARTIAL_LEN(lat->nx));
-    bfi_subvolumes v = subs.view();
-    BFI_TRY(bfi_eval(ctx, lat, prec, seed, &v, launch, partials.data(), nullptr));
-    return finalize_records(lat->nx, d, subs.size(), subs.lo.data(), subs.hi.data(),
-                            partials.data(), out, static_cast<int>(per));
+    return guarded([&]() -> bfi_status {
+        if (!ctx || !box_lo || !box_hi || !out)
+            return fail(BFI_EINVAL, "arguments must be non-NULL");
+        BFI_TRY(check_lattice(lat));
+        if (split_log2 < 0 || split_log2 > 24)
+            return fail(BFI_EINVAL, "split_log2 must be in [0, 24]");
+        const int d = lat->nx * lat->nt;
+        for (int k = 0; k < d; ++k)
+            if (!std::isfinite(box_lo[k]) || !std::isfinite(box_hi[k]) || !(box_lo[k] < box_hi[k]))
+                return fail(BFI_EINVAL, "box dim %d: need finite lo < hi", k);
+        // the budget counts integrand evaluations: two per antithetic pair
+        const uint64_t per = lat->antithetic ? 2 : 1;
+        if (budget / per < 2 * (uint64_t(1) << split_log2))
+            return fail(BFI_EINVAL, "budget must give every subvolume at least 2 samples");
+        SubList subs = uniform_split(d, box_lo, box_hi, split_log2, budget / per);
+        std::vector<double> partials(subs.size() * BFI_PARTIAL_LEN(lat->nx));
+        bfi_subvolumes v = subs.view();
+        BFI_TRY(bfi_eval(ctx, lat, prec, seed, &v, launch, partials.data(), nullptr));
+        return finalize_records(lat->nx, d, subs.size(), subs.lo.data(), subs.hi.data(),
+                                partials.data(), out, static_cast<int>(per));
+    });
 }
 
 bfi_status bfi_debug_points(bfi_context *ctx, int32_t d, bfi_precision prec, uint64_t seed,
                             uint64_t id, const double *lo, const double *hi,
                             const uint64_t *index, uint64_t n, double *out)
 {
-    if (!ctx || !lo || !hi || (n && (!index || !out)))
-        return fail(BFI_EINVAL, "arguments must be non-NULL");
-    if (d < 1 || d > BFI_MAX_D)
-        return fail(BFI_EINVAL, "d out of range");
-    if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
-        return fail(BFI_EINVAL, "unknown precision");
-    for (int k = 0; k < d; ++k)
-        if (!std::isfinite(lo[k]) || !std::isfinite(hi[k]) || !(lo[k] < hi[k]))
-            return fail(BFI_EINVAL, "box dim %d: need finite lo < hi", k);
-    if (n == 0)
+    return guarded([&]() -> bfi_status {
+        if (!ctx || !lo || !hi || (n && (!index || !out)))
+            return fail(BFI_EINVAL, "arguments must be non-NULL");
+        if (d < 1 || d > BFI_MAX_D)
+            return fail(BFI_EINVAL, "d out of range");
+        if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
+            return fail(BFI_EINVAL, "unknown precision");
+        for (int k = 0; k < d; ++k)
+            if (!std::isfinite(lo[k]) || !std::isfinite(hi[k]) || !(lo[k] < hi[k]))
+                return fail(BFI_EINVAL, "box dim %d: need finite lo < hi", k);
+        if (n == 0)
+            return BFI_OK;
+        BFI_HIP(hipSetDevice(ctx->device));
+        std::vector<double> b64(d), s64(d);
+        std::vector<float> b32(d), s32(d);
+        for (int k = 0; k < d; ++k) {
+            s64[k] = (hi[k] - lo[k]) * 0x1p-32;
+            b64[k] = lo[k] + 0.5 * s64[k];
+            s32[k] = static_cast<float>(s64[k]);
+            b32[k] = static_cast<float>(b64[k]);
+        }
+        DevBuf db64, ds64, db32, ds32, didx, dout;
+        BFI_HIP(hipMalloc(&db64.p, d * 8));
+        BFI_HIP(hipMalloc(&ds64.p, d * 8));
+        BFI_HIP(hipMalloc(&db32.p, d * 4));
+        BFI_HIP(hipMalloc(&ds32.p, d * 4));
+        BFI_HIP(hipMalloc(&didx.p, n * 8));
+        BFI_HIP(hipMalloc(&dout.p, n * d * 8));
+        BFI_HIP(hipMemcpy(db64.p, b64.data(), d * 8, hipMemcpyHostToDevice));
+        BFI_HIP(hipMemcpy(ds64.p, s64.data(), d * 8, hipMemcpyHostToDevice));
+        BFI_HIP(hipMemcpy(db32.p, b32.data(), d * 4, hipMemcpyHostToDevice));
+        BFI_HIP(hipMemcpy(ds32.p, s32.data(), d * 4, hipMemcpyHostToDevice));
+        BFI_HIP(hipMemcpy(didx.p, index, n * 8, hipMemcpyHostToDevice));
+        DebugPointArgs a{};
+        a.base64 = static_cast<double *>(db64.p);
+        a.scale64 = static_cast<double *>(ds64.p);
+        a.base32 = static_cast<float *>(db32.p);
+        a.scale32 = static_cast<float *>(ds32.p);
+        a.index = static_cast<uint64_t *>(didx.p);
+        a.out = static_cast<double *>(dout.p);
+        a.id = id;
+        a.n = n;
+        a.seed_lo = static_cast<uint32_t>(seed);
+        a.seed_hi = static_cast<uint32_t>(seed >> 32);
+        a.d = d;
+        a.prec = prec;
+        BFI_HIP(launch_debug_points(a, ctx->stream));
+        BFI_HIP(hipStreamSynchronize(ctx->stream));
+        BFI_HIP(hipMemcpy(out, dout.p, n * d * 8, hipMemcpyDeviceToHost));
         return BFI_OK;
-    BFI_HIP(hipSetDevice(ctx->device));
-    std::vector<double> b64(d), s64(d);
-    std::vector<float> b32(d), s32(d);
-    for (int k = 0; k < d; ++k) {
-        s64[k] = (hi[k] - lo[k]) * 0x1p-32;
-        b64[k] = lo[k] + 0.5 * s64[k];
-        s32[k] = static_cast<float>(s64[k]);
-        b32[k] = static_cast<float>(b64[k]);
-    }
-    DevBuf db64, ds64, db32, ds32, didx, dout;
-    BFI_HIP(hipMalloc(&db64.p, d * 8));
-    BFI_HIP(hipMalloc(&ds64.p, d * 8));
-    BFI_HIP(hipMalloc(&db32.p, d * 4));
-    BFI_HIP(hipMalloc(&ds32.p, d * 4));
-    BFI_HIP(hipMalloc(&didx.p, n * 8));
-    BFI_HIP(hipMalloc(&dout.p, n * d * 8));
-    BFI_HIP(hipMemcpy(db64.p, b64.data(), d * 8, hipMemcpyHostToDevice));
-    BFI_HIP(hipMemcpy(ds64.p, s64.data(), d * 8, hipMemcpyHostToDevice));
-    BFI_HIP(hipMemcpy(db32.p, b32.data(), d * 4, hipMemcpyHostToDevice));
-    BFI_HIP(hipMemcpy(ds32.p, s32.data(), d * 4, hipMemcpyHostToDevice));
-    BFI_HIP(hipMemcpy(didx.p, index, n * 8, hipMemcpyHostToDevice));
-    DebugPointArgs a{};
-    a.base64 = static_cast<double *>(db64.p);
-    a.scale64 = static_cast<double *>(ds64.p);
-    a.base32 = static_cast<float *>(db32.p);
-    a.scale32 = static_cast<float *>(ds32.p);
-    a.index = static_cast<uint64_t *>(didx.p);
-    a.out = static_cast<double *>(dout.p);
-    a.id = id;
-    a.n = n;
-    a.seed_lo = static_cast<uint32_t>(seed);
-    a.seed_hi = static_cast<uint32_t>(seed >> 32);
-    a.d = d;
-    a.prec = prec;
-    BFI_HIP(launch_debug_points(a, ctx->stream));
-    BFI_HIP(hipStreamSynchronize(ctx->stream));
-    BFI_HIP(hipMemcpy(out, dout.p, n * d * 8, hipMemcpyDeviceToHost));
-    return BFI_OK;
+    });
 }
 
 bfi_status bfi_debug_action(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
                             uint64_t n, const double *points, double *out_S)
 {
-    if (!ctx || (n && (!points || !out_S)))
-        return fail(BFI_EINVAL, "arguments must be non-NULL");
-    if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
-        return fail(BFI_EINVAL, "unknown precision");
-    BFI_TRY(check_lattice(lat));
-    if (n == 0)
+    return guarded([&]() -> bfi_status {
+        if (!ctx || (n && (!points || !out_S)))
+            return fail(BFI_EINVAL, "arguments must be non-NULL");
+        if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
+            return fail(BFI_EINVAL, "unknown precision");
+        BFI_TRY(check_lattice(lat));
+        if (n == 0)
+            return BFI_OK;
+        BFI_HIP(hipSetDevice(ctx->device));
+        const int d = lat->nx * lat->nt;
+        DevBuf dp, ds;
+        BFI_HIP(hipMalloc(&dp.p, n * d * 8));
+        BFI_HIP(hipMalloc(&ds.p, n * 8));
+        BFI_HIP(hipMemcpy(dp.p, points, n * d * 8, hipMemcpyHostToDevice));
+        DebugActionArgs a{};
+        a.points = static_cast<double *>(dp.p);
+        a.out = static_cast<double *>(ds.p);
+        a.n = n;
+        a.coef = make_coef(*lat);
+        a.prec = prec;
+        BFI_HIP(launch_debug_action(lat->nx, lat->nt, a, ctx->stream));
+        BFI_HIP(hipStreamSynchronize(ctx->stream));
+        BFI_HIP(hipMemcpy(out_S, ds.p, n * 8, hipMemcpyDeviceToHost));
         return BFI_OK;
-    BFI_HIP(hipSetDevice(ctx->device));
-    const int d = lat->nx * lat->nt;
-    DevBuf dp, ds;
-    BFI_HIP(hipMalloc(&dp.p, n * d * 8));
-    BFI_HIP(hipMalloc(&ds.p, n * 8));
-    BFI_HIP(hipMemcpy(dp.p, points, n * d * 8, hipMemcpyHostToDevice));
-    DebugActionArgs a{};
-    a.points = static_cast<double *>(dp.p);
-    a.out = static_cast<double *>(ds.p);
-    a.n = n;
-    a.coef = make_coef(*lat);
-    a.prec = prec;
-    BFI_HIP(launch_debug_action(lat->nx, lat->nt, a, ctx->stream));
-    BFI_HIP(hipStreamSynchronize(ctx->stream));
-    BFI_HIP(hipMemcpy(out_S, ds.p, n * 8, hipMemcpyDeviceToHost));
-    return BFI_OK;
+    });
 }
 
 }  // extern "C"

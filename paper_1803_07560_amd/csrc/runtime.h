@@ -6,7 +6,9 @@
 
 #include <cstdarg>
 #include <cstdint>
+#include <exception>
 #include <map>
+#include <new>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -76,6 +78,22 @@ struct TuneEntry {
     double evals_per_s;
 };
 
+// Runs the body of a C ABI entry point: C++ exceptions (host allocation
+// failure above all) become status codes, so nothing unwinds into a C caller.
+template <class F>
+bfi_status guarded(F &&body) noexcept
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail(BFI_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(BFI_EINVAL, "%s", e.what());
+    } catch (...) {
+        return fail(BFI_EINVAL, "unexpected exception");
+    }
+}
+
 // Resolve a requested launch (zeros = tuned or default) for a lattice.
 bfi_launch resolve_launch(const bfi_context *ctx, const bfi_lattice &lat, int prec, bool split,
                           const bfi_launch *req);
@@ -124,8 +142,8 @@ struct bfi_plan {
     bfi::IsTable *d_is_table = nullptr;  // kind 2
 
     // captured replays (queue reset, kernel, merge, copy to the destination), one
-    // per (stream, destination) pair, the most recently created kMaxReplays kept:
-    // alternating output buffers replays without capturing again
+    // per (stream, destination) pair, the kMaxReplays used last kept (ordered by
+    // last use): alternating output buffers replays without capturing again
     struct Replay {
         hipGraphExec_t exec = nullptr;
         hipGraph_t def = nullptr;

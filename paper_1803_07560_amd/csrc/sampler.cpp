@@ -158,19 +158,21 @@ extern "C" {
 bfi_status bfi_is_modes(const bfi_lattice *lat, double box_lo, double box_hi, double *lambda,
                         int32_t *uniform, double *scale, double *log_k)
 {
-    BFI_TRY(check_args(lat, BFI_FP64, box_lo, box_hi, 0.5));
-    if (!lambda || !uniform || !scale || !log_k)
-        return fail(BFI_EINVAL, "outputs must be non-NULL");
-    Modes m;
-    modes_of(*lat, box_lo, box_hi, &m);
-    const int d = lat->nx * lat->nt;
-    for (int j = 0; j < d; ++j) {
-        lambda[j] = m.lambda[j];
-        scale[j] = m.scale[j];
-        uniform[j] = (j == 0 && m.uniform0) ? 1 : 0;
-    }
-    *log_k = m.log_k;
-    return BFI_OK;
+    return guarded([&]() -> bfi_status {
+        BFI_TRY(check_args(lat, BFI_FP64, box_lo, box_hi, 0.5));
+        if (!lambda || !uniform || !scale || !log_k)
+            return fail(BFI_EINVAL, "outputs must be non-NULL");
+        Modes m;
+        modes_of(*lat, box_lo, box_hi, &m);
+        const int d = lat->nx * lat->nt;
+        for (int j = 0; j < d; ++j) {
+            lambda[j] = m.lambda[j];
+            scale[j] = m.scale[j];
+            uniform[j] = (j == 0 && m.uniform0) ? 1 : 0;
+        }
+        *log_k = m.log_k;
+        return BFI_OK;
+    });
 }
 
 bfi_status bfi_is_eval(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec, uint64_t seed,
@@ -178,18 +180,20 @@ bfi_status bfi_is_eval(bfi_context *ctx, const bfi_lattice *lat, bfi_precision p
                        const uint64_t *stream_id, const uint64_t *n, const uint64_t *offset,
                        const bfi_launch *launch, double *partials)
 {
-    if (!ctx)
-        return fail(BFI_EINVAL, "context is NULL");
-    BFI_TRY(check_args(lat, prec, box_lo, box_hi, gaussian_fraction));
-    if (count == 0)
-        return BFI_OK;
-    if (!stream_id || !n || !offset || !partials)
-        return fail(BFI_EINVAL, "stream arrays and partials must be non-NULL");
-    Modes m;
-    const SubList streams =
-        stream_list(lat->nx * lat->nt, box_lo, box_hi, count, stream_id, n, offset);
-    return run_streams(ctx, *lat, prec, seed, box_lo, box_hi, gaussian_fraction, streams, launch,
-                       partials, &m);
+    return guarded([&]() -> bfi_status {
+        if (!ctx)
+            return fail(BFI_EINVAL, "context is NULL");
+        BFI_TRY(check_args(lat, prec, box_lo, box_hi, gaussian_fraction));
+        if (count == 0)
+            return BFI_OK;
+        if (!stream_id || !n || !offset || !partials)
+            return fail(BFI_EINVAL, "stream arrays and partials must be non-NULL");
+        Modes m;
+        const SubList streams =
+            stream_list(lat->nx * lat->nt, box_lo, box_hi, count, stream_id, n, offset);
+        return run_streams(ctx, *lat, prec, seed, box_lo, box_hi, gaussian_fraction, streams, launch,
+                           partials, &m);
+    });
 }
 
 bfi_status bfi_integrate_is(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
@@ -197,44 +201,46 @@ bfi_status bfi_integrate_is(bfi_context *ctx, const bfi_lattice *lat, bfi_precis
                             uint32_t streams, uint64_t budget, const bfi_launch *launch,
                             bfi_result *out)
 {
-    if (!ctx || !out)
-        return fail(BFI_EINVAL, "context and result must be non-NULL");
-    BFI_TRY(check_args(lat, prec, box_lo, box_hi, gaussian_fraction));
-    if (streams < 1)
-        return fail(BFI_EINVAL, "need at least one stream");
-    // round(alpha B) samples over Gaussian streams 1..S, the rest over uniform
-    // streams 2^63 + 1..S; each share split floor(b/S) + (i < b mod S)
-    const uint64_t n_g = static_cast<uint64_t>(
-        std::llround(gaussian_fraction * static_cast<double>(budget)));
-    std::vector<uint64_t> ids, ns, offs;
-    const uint64_t shares[2] = {n_g, budget - n_g};
-    for (int comp = 0; comp < 2; ++comp) {
-        if (shares[comp] == 0)
-            continue;
-        const uint64_t base = comp == 0 ? 0 : kIsUniformStream;
-        for (uint32_t i = 0; i < streams; ++i) {
-            const uint64_t k = shares[comp] / streams + (i < shares[comp] % streams ? 1 : 0);
-            if (k < 2)
-                return fail(BFI_EINVAL, "budget too small: every stream needs 2 samples");
-            ids.push_back(base + 1 + i);
-            ns.push_back(k);
-            offs.push_back(0);
+    return guarded([&]() -> bfi_status {
+        if (!ctx || !out)
+            return fail(BFI_EINVAL, "context and result must be non-NULL");
+        BFI_TRY(check_args(lat, prec, box_lo, box_hi, gaussian_fraction));
+        if (streams < 1)
+            return fail(BFI_EINVAL, "need at least one stream");
+        // round(alpha B) samples over Gaussian streams 1..S, the rest over uniform
+        // streams 2^63 + 1..S; each share split floor(b/S) + (i < b mod S)
+        const uint64_t n_g = static_cast<uint64_t>(
+            std::llround(gaussian_fraction * static_cast<double>(budget)));
+        std::vector<uint64_t> ids, ns, offs;
+        const uint64_t shares[2] = {n_g, budget - n_g};
+        for (int comp = 0; comp < 2; ++comp) {
+            if (shares[comp] == 0)
+                continue;
+            const uint64_t base = comp == 0 ? 0 : kIsUniformStream;
+            for (uint32_t i = 0; i < streams; ++i) {
+                const uint64_t k = shares[comp] / streams + (i < shares[comp] % streams ? 1 : 0);
+                if (k < 2)
+                    return fail(BFI_EINVAL, "budget too small: every stream needs 2 samples");
+                ids.push_back(base + 1 + i);
+                ns.push_back(k);
+                offs.push_back(0);
+            }
         }
-    }
-    const int d = lat->nx * lat->nt, nx = lat->nx;
-    const SubList list = stream_list(d, box_lo, box_hi, ids.size(), ids.data(), ns.data(),
-                                     offs.data());
-    std::vector<double> rec(ids.size() * BFI_PARTIAL_LEN(nx));
-    Modes m;
-    BFI_TRY(run_streams(ctx, *lat, prec, seed, box_lo, box_hi, gaussian_fraction, list, launch,
-                        rec.data(), &m));
-    // stream "volume" K n_s / N folded into the record's shift
-    const double log_total = std::log(static_cast<double>(budget));
-    for (size_t s = 0; s < ids.size(); ++s)
-        rec[s * BFI_PARTIAL_LEN(nx) + 1] -=
-            m.log_k + std::log(static_cast<double>(ns[s])) - log_total;
-    std::vector<double> unit_lo(ids.size() * d, 0.0), unit_hi(ids.size() * d, 1.0);
-    return finalize_records(nx, d, ids.size(), unit_lo.data(), unit_hi.data(), rec.data(), out);
+        const int d = lat->nx * lat->nt, nx = lat->nx;
+        const SubList list = stream_list(d, box_lo, box_hi, ids.size(), ids.data(), ns.data(),
+                                         offs.data());
+        std::vector<double> rec(ids.size() * BFI_PARTIAL_LEN(nx));
+        Modes m;
+        BFI_TRY(run_streams(ctx, *lat, prec, seed, box_lo, box_hi, gaussian_fraction, list, launch,
+                            rec.data(), &m));
+        // stream "volume" K n_s / N folded into the record's shift
+        const double log_total = std::log(static_cast<double>(budget));
+        for (size_t s = 0; s < ids.size(); ++s)
+            rec[s * BFI_PARTIAL_LEN(nx) + 1] -=
+                m.log_k + std::log(static_cast<double>(ns[s])) - log_total;
+        std::vector<double> unit_lo(ids.size() * d, 0.0), unit_hi(ids.size() * d, 1.0);
+        return finalize_records(nx, d, ids.size(), unit_lo.data(), unit_hi.data(), rec.data(), out);
+    });
 }
 
 bfi_status bfi_debug_is_points(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
@@ -242,44 +248,46 @@ bfi_status bfi_debug_is_points(bfi_context *ctx, const bfi_lattice *lat, bfi_pre
                                const uint64_t *index, uint64_t n, double *u_out,
                                double *half_z2_out)
 {
-    if (!ctx)
-        return fail(BFI_EINVAL, "context is NULL");
-    BFI_TRY(check_args(lat, prec, box_lo, box_hi, 0.5));
-    if (n == 0)
+    return guarded([&]() -> bfi_status {
+        if (!ctx)
+            return fail(BFI_EINVAL, "context is NULL");
+        BFI_TRY(check_args(lat, prec, box_lo, box_hi, 0.5));
+        if (n == 0)
+            return BFI_OK;
+        if (!index || !u_out || !half_z2_out)
+            return fail(BFI_EINVAL, "index and outputs must be non-NULL");
+        BFI_HIP(hipSetDevice(ctx->device));
+        const int d = lat->nx * lat->nt;
+        Modes m;
+        const IsTable table = make_table(*lat, box_lo, box_hi, 0.5, seed, &m);
+        struct Buf {
+            void *p = nullptr;
+            ~Buf()
+            {
+                if (p)
+                    (void)hipFree(p);
+            }
+        } dt, di, du, dh;
+        BFI_HIP(hipMalloc(&dt.p, sizeof(IsTable)));
+        BFI_HIP(hipMalloc(&di.p, n * 8));
+        BFI_HIP(hipMalloc(&du.p, n * d * 8));
+        BFI_HIP(hipMalloc(&dh.p, n * 8));
+        BFI_HIP(hipMemcpy(dt.p, &table, sizeof(IsTable), hipMemcpyHostToDevice));
+        BFI_HIP(hipMemcpy(di.p, index, n * 8, hipMemcpyHostToDevice));
+        IsDebugArgs a{};
+        a.table = static_cast<const IsTable *>(dt.p);
+        a.index = static_cast<const uint64_t *>(di.p);
+        a.u_out = static_cast<double *>(du.p);
+        a.hz_out = static_cast<double *>(dh.p);
+        a.n = n;
+        a.id = stream_id;
+        a.prec = prec;
+        BFI_HIP(launch_is_debug(lat->nx, lat->nt, a, ctx->stream));
+        BFI_HIP(hipStreamSynchronize(ctx->stream));
+        BFI_HIP(hipMemcpy(u_out, du.p, n * d * 8, hipMemcpyDeviceToHost));
+        BFI_HIP(hipMemcpy(half_z2_out, dh.p, n * 8, hipMemcpyDeviceToHost));
         return BFI_OK;
-    if (!index || !u_out || !half_z2_out)
-        return fail(BFI_EINVAL, "index and outputs must be non-NULL");
-    BFI_HIP(hipSetDevice(ctx->device));
-    const int d = lat->nx * lat->nt;
-    Modes m;
-    const IsTable table = make_table(*lat, box_lo, box_hi, 0.5, seed, &m);
-    struct Buf {
-        void *p = nullptr;
-        ~Buf()
-        {
-            if (p)
-                (void)hipFree(p);
-        }
-    } dt, di, du, dh;
-    BFI_HIP(hipMalloc(&dt.p, sizeof(IsTable)));
-    BFI_HIP(hipMalloc(&di.p, n * 8));
-    BFI_HIP(hipMalloc(&du.p, n * d * 8));
-    BFI_HIP(hipMalloc(&dh.p, n * 8));
-    BFI_HIP(hipMemcpy(dt.p, &table, sizeof(IsTable), hipMemcpyHostToDevice));
-    BFI_HIP(hipMemcpy(di.p, index, n * 8, hipMemcpyHostToDevice));
-    IsDebugArgs a{};
-    a.table = static_cast<const IsTable *>(dt.p);
-    a.index = static_cast<const uint64_t *>(di.p);
-    a.u_out = static_cast<double *>(du.p);
-    a.hz_out = static_cast<double *>(dh.p);
-    a.n = n;
-    a.id = stream_id;
-    a.prec = prec;
-    BFI_HIP(launch_is_debug(lat->nx, lat->nt, a, ctx->stream));
-    BFI_HIP(hipStreamSynchronize(ctx->stream));
-    BFI_HIP(hipMemcpy(u_out, du.p, n * d * 8, hipMemcpyDeviceToHost));
-    BFI_HIP(hipMemcpy(half_z2_out, dh.p, n * 8, hipMemcpyDeviceToHost));
-    return BFI_OK;
+    });
 }
 
 }  // extern "C"

@@ -396,7 +396,8 @@ void worker_loop(bfi_server *srv)
         }
         lk.unlock();
         const auto t0 = Clock::now();
-        bfi_status s = run_step(srv, entries);
+        // a failed step (an exception included) fails its requests, not the server
+        bfi_status s = guarded([&]() -> bfi_status { return run_step(srv, entries); });
         const auto t1 = Clock::now();
         std::string msg = s == BFI_OK ? "" : bfi_last_error();
         lk.lock();
@@ -464,182 +465,208 @@ extern "C" {
 
 bfi_status bfi_server_create(bfi_context *ctx, const bfi_server_config *cfg, bfi_server **out)
 {
-    if (!ctx || !cfg || !out)
-        return fail(BFI_EINVAL, "arguments must be non-NULL");
-    if (cfg->max_requests < 1 || cfg->chunks_per_step < 1 || cfg->max_pending < 0 ||
-        cfg->memory_budget == 0)
-        return fail(BFI_EINVAL, "bad server configuration");
-    BFI_HIP(hipSetDevice(ctx->device));
-    auto srv = std::make_unique<bfi_server>();
-    srv->ctx = ctx;
-    srv->cfg = *cfg;
-    // room for every admitted request's minimum share plus the step target in items
-    srv->step_cap = static_cast<size_t>(cfg->max_requests) * cfg->chunks_per_step + 65536;
-    BFI_HIP(hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking));
-    srv->group_streams[0] = srv->stream;
-    for (int k = 1; k < bfi_server::kStreams; ++k)
-        BFI_HIP(hipStreamCreateWithFlags(&srv->group_streams[k], hipStreamNonBlocking));
-    BFI_HIP(hipEventCreateWithFlags(&srv->staged, hipEventDisableTiming));
-    hipError_t e = hipMalloc(&srv->d_step, srv->step_cap * sizeof(WorkItem));
-    if (e == hipSuccess)
-        e = hipHostMalloc(&srv->h_step, srv->step_cap * sizeof(WorkItem), hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipMalloc(&srv->d_heads, bfi_server::kMaxGroups * sizeof(uint32_t));
-    if (e != hipSuccess) {
-        if (srv->d_step)
-            (void)hipFree(srv->d_step);
-        if (srv->h_step)
-            (void)hipHostFree(srv->h_step);
-        for (int k = 0; k < bfi_server::kStreams; ++k)
-            (void)hipStreamDestroy(srv->group_streams[k]);
-        (void)hipEventDestroy(srv->staged);
-        return hip_fail(e, "server buffers");
-    }
-    bfi_server *p = srv.release();
-    p->worker = std::thread(worker_loop, p);
-    *out = p;
-    return BFI_OK;
+    return guarded([&]() -> bfi_status {
+        if (!ctx || !cfg || !out)
+            return fail(BFI_EINVAL, "arguments must be non-NULL");
+        if (cfg->max_requests < 1 || cfg->chunks_per_step < 1 || cfg->max_pending < 0 ||
+            cfg->memory_budget == 0)
+            return fail(BFI_EINVAL, "bad server configuration");
+        BFI_HIP(hipSetDevice(ctx->device));
+        auto srv = std::make_unique<bfi_server>();
+        srv->ctx = ctx;
+        srv->cfg = *cfg;
+        // room for every admitted request's minimum share plus the step target in items
+        srv->step_cap = static_cast<size_t>(cfg->max_requests) * cfg->chunks_per_step + 65536;
+        BFI_HIP(hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking));
+        srv->group_streams[0] = srv->stream;
+        for (int k = 1; k < bfi_server::kStreams; ++k)
+            BFI_HIP(hipStreamCreateWithFlags(&srv->group_streams[k], hipStreamNonBlocking));
+        BFI_HIP(hipEventCreateWithFlags(&srv->staged, hipEventDisableTiming));
+        hipError_t e = hipMalloc(&srv->d_step, srv->step_cap * sizeof(WorkItem));
+        if (e == hipSuccess)
+            e = hipHostMalloc(&srv->h_step, srv->step_cap * sizeof(WorkItem), hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipMalloc(&srv->d_heads, bfi_server::kMaxGroups * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            if (srv->d_step)
+                (void)hipFree(srv->d_step);
+            if (srv->h_step)
+                (void)hipHostFree(srv->h_step);
+            for (int k = 0; k < bfi_server::kStreams; ++k)
+                (void)hipStreamDestroy(srv->group_streams[k]);
+            (void)hipEventDestroy(srv->staged);
+            return hip_fail(e, "server buffers");
+        }
+        bfi_server *p = srv.release();
+        p->worker = std::thread(worker_loop, p);
+        *out = p;
+        return BFI_OK;
+    });
 }
 
 bfi_status bfi_server_submit(bfi_server *srv, const bfi_request *req, uint64_t *ticket)
 {
-    if (!srv || !req || !ticket)
-        return fail(BFI_EINVAL, "arguments must be non-NULL");
-    BFI_TRY(check_lattice(&req->lat));
-    if (req->prec != BFI_FP64 && req->prec != BFI_FP32_SHIFTED)
-        return fail(BFI_EINVAL, "unknown precision");
-    if (!(req->box > 0) || !std::isfinite(req->box))
-        return fail(BFI_EINVAL, "box must be positive and finite");
-    if (req->split_log2 < 0 || req->split_log2 > 20)
-        return fail(BFI_EINVAL, "split_log2 must be in [0, 20]");
-    // the budget counts integrand evaluations: two per antithetic pair
-    const uint64_t per = req->lat.antithetic ? 2 : 1;
-    if (req->budget / per < 2 * (uint64_t(1) << req->split_log2))
-        return fail(BFI_EINVAL, "budget must give every subvolume at least 2 samples");
+    return guarded([&]() -> bfi_status {
+        if (!srv || !req || !ticket)
+            return fail(BFI_EINVAL, "arguments must be non-NULL");
+        BFI_TRY(check_lattice(&req->lat));
+        if (req->prec != BFI_FP64 && req->prec != BFI_FP32_SHIFTED)
+            return fail(BFI_EINVAL, "unknown precision");
+        if (!(req->box > 0) || !std::isfinite(req->box))
+            return fail(BFI_EINVAL, "box must be positive and finite");
+        if (req->split_log2 < 0 || req->split_log2 > 20)
+            return fail(BFI_EINVAL, "split_log2 must be in [0, 20]");
+        // the budget counts integrand evaluations: two per antithetic pair
+        const uint64_t per = req->lat.antithetic ? 2 : 1;
+        if (req->budget / per < 2 * (uint64_t(1) << req->split_log2))
+            return fail(BFI_EINVAL, "budget must give every subvolume at least 2 samples");
 
-    auto r = std::make_unique<Request>();
-    r->req = *req;
-    r->nx = req->lat.nx;
-    r->d = req->lat.nx * req->lat.nt;
-    r->rec_len = BFI_PARTIAL_LEN(r->nx);
-    std::vector<double> lo(r->d, -req->box), hi(r->d, req->box);
-    r->subs = uniform_split(r->d, lo.data(), hi.data(), req->split_log2, req->budget / per);
-    {
+        auto r = std::make_unique<Request>();
+        r->req = *req;
+        r->nx = req->lat.nx;
+        r->d = req->lat.nx * req->lat.nt;
+        r->rec_len = BFI_PARTIAL_LEN(r->nx);
+        std::vector<double> lo(r->d, -req->box), hi(r->d, req->box);
+        r->subs = uniform_split(r->d, lo.data(), hi.data(), req->split_log2, req->budget / per);
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            BFI_TRY(shape_launch(srv, req->lat, req->prec, &r->launch, &r->grid));
+        }
+        const uint64_t chunk = static_cast<uint64_t>(r->launch.samples_per_thread) * r->launch.block;
+        // size the request before building it: work items and device state
+        uint64_t nitems = 0;
+        for (size_t s = 0; s < r->subs.size(); ++s) {
+            nitems += r->subs.n[s] / chunk + (r->subs.n[s] % chunk != 0);
+            if (nitems > 0x7FFFFFFFull)
+                return fail(BFI_EINVAL, "request needs more than 2^31 work items");
+        }
+        {
+            const Layout need = layout_of(r->subs.size(), r->d, static_cast<size_t>(nitems),
+                                          r->rec_len);
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (need.total > srv->cfg.memory_budget) {
+                ++srv->stats.rejected;
+                return fail(BFI_EBUSY, "request needs %zu bytes of device state, budget is %llu",
+                            need.total, static_cast<unsigned long long>(srv->cfg.memory_budget));
+            }
+        }
+        r->items.reserve(static_cast<size_t>(nitems));
+        r->sub_first.assign(r->subs.size() + 1, 0);
+        for (size_t s = 0; s < r->subs.size(); ++s) {
+            r->sub_first[s] = static_cast<uint32_t>(r->items.size());
+            for (uint64_t start = 0; start < r->subs.n[s]; start += chunk)
+                r->items.push_back(WorkItem{nullptr, nullptr, start, static_cast<uint32_t>(s),
+                                            static_cast<uint32_t>(
+                                                std::min<uint64_t>(chunk, r->subs.n[s] - start))});
+        }
+        r->sub_first[r->subs.size()] = static_cast<uint32_t>(r->items.size());
+
         std::lock_guard<std::mutex> lk(srv->mu);
-        BFI_TRY(shape_launch(srv, req->lat, req->prec, &r->launch, &r->grid));
-    }
-    const uint64_t chunk = static_cast<uint64_t>(r->launch.samples_per_thread) * r->launch.block;
-    r->sub_first.assign(r->subs.size() + 1, 0);
-    for (size_t s = 0; s < r->subs.size(); ++s) {
-        r->sub_first[s] = static_cast<uint32_t>(r->items.size());
-        for (uint64_t start = 0; start < r->subs.n[s]; start += chunk)
-            r->items.push_back(WorkItem{nullptr, nullptr, start, static_cast<uint32_t>(s),
-                                        static_cast<uint32_t>(
-                                            std::min<uint64_t>(chunk, r->subs.n[s] - start))});
-    }
-    r->sub_first[r->subs.size()] = static_cast<uint32_t>(r->items.size());
-    const Layout L = layout_of(r->subs.size(), r->d, r->items.size(), r->rec_len);
-
-    std::lock_guard<std::mutex> lk(srv->mu);
-    if (L.total > srv->cfg.memory_budget) {
-        ++srv->stats.rejected;
-        return fail(BFI_EBUSY, "request needs %zu bytes of device state, budget is %llu", L.total,
-                    static_cast<unsigned long long>(srv->cfg.memory_budget));
-    }
-    if (static_cast<int32_t>(srv->pending.size()) >= srv->cfg.max_pending) {
-        ++srv->stats.rejected;
-        return fail(BFI_EBUSY, "pending queue full (%d)", srv->cfg.max_pending);
-    }
-    r->ticket = srv->next_ticket++;
-    r->t_submit = Clock::now();
-    *ticket = r->ticket;
-    srv->pending.push_back(r->ticket);
-    srv->reqs.emplace(r->ticket, std::move(r));
-    ++srv->stats.submitted;
-    srv->work_cv.notify_one();
-    return BFI_OK;
+        if (static_cast<int32_t>(srv->pending.size()) >= srv->cfg.max_pending) {
+            ++srv->stats.rejected;
+            return fail(BFI_EBUSY, "pending queue full (%d)", srv->cfg.max_pending);
+        }
+        r->ticket = srv->next_ticket++;
+        r->t_submit = Clock::now();
+        *ticket = r->ticket;
+        srv->pending.push_back(r->ticket);
+        srv->reqs.emplace(r->ticket, std::move(r));
+        ++srv->stats.submitted;
+        srv->work_cv.notify_one();
+        return BFI_OK;
+    });
 }
 
 bfi_status bfi_server_poll(bfi_server *srv, uint64_t ticket, bfi_result *out, int32_t *done,
                            double *latency_s)
 {
-    if (!srv || !done)
-        return fail(BFI_EINVAL, "arguments must be non-NULL");
-    std::lock_guard<std::mutex> lk(srv->mu);
-    return take_result(srv, ticket, out, done, latency_s);
+    return guarded([&]() -> bfi_status {
+        if (!srv || !done)
+            return fail(BFI_EINVAL, "arguments must be non-NULL");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        return take_result(srv, ticket, out, done, latency_s);
+    });
 }
 
 bfi_status bfi_server_wait(bfi_server *srv, uint64_t ticket, double timeout_s, bfi_result *out,
                            int32_t *done, double *latency_s)
 {
-    if (!srv || !done)
-        return fail(BFI_EINVAL, "arguments must be non-NULL");
-    std::unique_lock<std::mutex> lk(srv->mu);
-    const auto until = Clock::now() + std::chrono::duration_cast<Clock::duration>(
-                                          std::chrono::duration<double>(std::max(timeout_s, 0.0)));
-    srv->done_cv.wait_until(lk, until, [&] {
-        auto it = srv->reqs.find(ticket);
-        return it == srv->reqs.end() || terminal(it->second->state);
+    return guarded([&]() -> bfi_status {
+        if (!srv || !done)
+            return fail(BFI_EINVAL, "arguments must be non-NULL");
+        std::unique_lock<std::mutex> lk(srv->mu);
+        const auto until = Clock::now() + std::chrono::duration_cast<Clock::duration>(
+                                              std::chrono::duration<double>(std::max(timeout_s, 0.0)));
+        srv->done_cv.wait_until(lk, until, [&] {
+            auto it = srv->reqs.find(ticket);
+            return it == srv->reqs.end() || terminal(it->second->state);
+        });
+        return take_result(srv, ticket, out, done, latency_s);
     });
-    return take_result(srv, ticket, out, done, latency_s);
 }
 
 bfi_status bfi_server_cancel(bfi_server *srv, uint64_t ticket)
 {
-    if (!srv)
-        return fail(BFI_EINVAL, "server is NULL");
-    std::lock_guard<std::mutex> lk(srv->mu);
-    auto it = srv->reqs.find(ticket);
-    if (it == srv->reqs.end())
-        return fail(BFI_ENOTFOUND, "unknown ticket");
-    Request *r = it->second.get();
-    if (terminal(r->state))
+    return guarded([&]() -> bfi_status {
+        if (!srv)
+            return fail(BFI_EINVAL, "server is NULL");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        auto it = srv->reqs.find(ticket);
+        if (it == srv->reqs.end())
+            return fail(BFI_ENOTFOUND, "unknown ticket");
+        Request *r = it->second.get();
+        if (terminal(r->state))
+            return BFI_OK;
+        ++srv->stats.cancelled;
+        if (r->state == State::Pending) {
+            srv->pending.erase(std::find(srv->pending.begin(), srv->pending.end(), ticket));
+            finish(srv, r, State::Cancelled, BFI_ECANCELLED, "cancelled");
+            return BFI_OK;
+        }
+        r->cancel = true;  // the worker releases it once no step holds its items
+        srv->work_cv.notify_one();
         return BFI_OK;
-    ++srv->stats.cancelled;
-    if (r->state == State::Pending) {
-        srv->pending.erase(std::find(srv->pending.begin(), srv->pending.end(), ticket));
-        finish(srv, r, State::Cancelled, BFI_ECANCELLED, "cancelled");
-        return BFI_OK;
-    }
-    r->cancel = true;  // the worker releases it once no step holds its items
-    srv->work_cv.notify_one();
-    return BFI_OK;
+    });
 }
 
 bfi_status bfi_server_stats_get(bfi_server *srv, bfi_server_stats *out)
 {
-    if (!srv || !out)
-        return fail(BFI_EINVAL, "arguments must be non-NULL");
-    std::lock_guard<std::mutex> lk(srv->mu);
-    *out = srv->stats;
-    return BFI_OK;
+    return guarded([&]() -> bfi_status {
+        if (!srv || !out)
+            return fail(BFI_EINVAL, "arguments must be non-NULL");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        *out = srv->stats;
+        return BFI_OK;
+    });
 }
 
 bfi_status bfi_server_destroy(bfi_server *srv)
 {
-    if (!srv)
+    return guarded([&]() -> bfi_status {
+        if (!srv)
+            return BFI_OK;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->stop = true;
+            for (uint64_t t : srv->admitted)
+                srv->reqs.at(t)->cancel = true;
+            srv->pending.clear();
+        }
+        srv->work_cv.notify_all();
+        if (srv->worker.joinable())
+            srv->worker.join();
+        (void)hipSetDevice(srv->ctx->device);
+        for (auto &kv : srv->reqs)
+            free_device(srv, kv.second.get());
+        (void)hipFree(srv->d_step);
+        (void)hipHostFree(srv->h_step);
+        (void)hipFree(srv->d_heads);
+        for (int k = 0; k < bfi_server::kStreams; ++k)
+            (void)hipStreamDestroy(srv->group_streams[k]);
+        (void)hipEventDestroy(srv->staged);
+        delete srv;
         return BFI_OK;
-    {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        srv->stop = true;
-        for (uint64_t t : srv->admitted)
-            srv->reqs.at(t)->cancel = true;
-        srv->pending.clear();
-    }
-    srv->work_cv.notify_all();
-    if (srv->worker.joinable())
-        srv->worker.join();
-    (void)hipSetDevice(srv->ctx->device);
-    for (auto &kv : srv->reqs)
-        free_device(srv, kv.second.get());
-    (void)hipFree(srv->d_step);
-    (void)hipHostFree(srv->h_step);
-    (void)hipFree(srv->d_heads);
-    for (int k = 0; k < bfi_server::kStreams; ++k)
-        (void)hipStreamDestroy(srv->group_streams[k]);
-    (void)hipEventDestroy(srv->staged);
-    delete srv;
-    return BFI_OK;
+    });
 }
 
 }  // extern "C"

@@ -148,6 +148,13 @@ def test_invalid_requests(bfi, server):
     with pytest.raises(bfi.BfiError) as e:
         bfi.bfi_server_poll(server, 123456789)
     assert e.value.name == "BFI_ENOTFOUND"
+    # a request far too large is refused before anything is built for it
+    with pytest.raises(bfi.BfiError) as e:
+        bfi.bfi_server_submit(server, req(bfi, 10, 2, 1.0, "fp32", 1, 4.0, 2, 1 << 62))
+    assert e.value.name in ("BFI_EINVAL", "BFI_EBUSY")
+    st = bfi.bfi_server_stats_get(server)
+    t = bfi.bfi_server_submit(server, req(bfi, 4, 2, 1.0, "fp64", 1, 4.0, 2, 4096))
+    assert bfi.bfi_server_wait(server, t, 60.0) is not None
 
 
 def test_poisson_burst_latency(bfi, server):
