@@ -32,7 +32,8 @@
  *     during the call; nothing is retained unless stated.
  *   - Device pointers (suffix _dev) are caller-owned device memory that must
  *     stay valid until the work enqueued on the given stream has completed.
- *   - A stream argument is a hipStream_t passed as void*; NULL is the null stream.
+ *   - A stream argument is a hipStream_t passed as void*; NULL selects the
+ *     context's own stream.
  *   - Every call returns a bfi_status; on failure bfi_last_error() returns a
  *     thread-local message.  Nothing aborts, nothing throws across the ABI.
  *   - A context is not thread-safe; the server API is.
