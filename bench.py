@@ -16,6 +16,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload burgers10
 from __future__ import annotations
 
 import argparse
+import itertools
 import json
 import math
 import os
@@ -219,31 +220,35 @@ def serve_leg(bfi, ctx, seconds, rate, warmup_s=1.0):
             "form": "fp32"}
 
 
-def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0), observables=("anchor", "averaged")):
+def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0), observables=("anchor", "averaged"),
+                 forms=("fp32",)):
     """10x2 lattice, D = 1, box [-4,4]^20: error-driven bisection from the
     1024-subvolume partition at 2^10 samples per leaf, per-leaf counts in
     [2^10, 2^22], target max_r sigma_C(r)/|C(0)| <= 1e-3 with an effective
-    sample size of at least 100, FP32 form, budget 2^budget_log2 evaluations per
-    value of nu, each round at least 1/32 of it; the anchored product of the
-    paper and the translation-averaged one.  status BFI_OK: the target was met,
-    and `seconds` is the time to it."""
+    sample size of at least 100, in the given forms, budget 2^budget_log2
+    evaluations per value of nu, each round at least 1/32 of it; split statistics
+    from the first 2^16 samples of each leaf; the anchored product of the paper
+    and the translation-averaged one.  status BFI_OK: the target was met, and
+    `seconds` is the time to it."""
     out = []
-    for observable in observables:
-        for nu in nus:
-            cfg = bfi.adaptive_config(target_rel_err=1e-3, max_evals=1 << budget_log2,
-                                      n_min=1 << 10, n_max=1 << 22, split_log2=10,
-                                      max_rounds=128, refine_fraction=0.5,
-                                      round_evals=max(1 << 24, (1 << budget_log2) >> 5))
-            t0 = time.perf_counter()
-            r = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(10, 2, nu=nu, observable=observable),
-                                           "fp32", 1, -4.0, 4.0, cfg, leaf_capacity=1 << 22)
-            dt = time.perf_counter() - t0
-            n = r["partition"].n
-            out.append({"observable": observable, "nu": nu, "status": r["status"],
-                        "rel_err": r["rel_err"], "ess": r["ess"], "rounds": r["rounds"],
-                        "leaves": r["leaves"], "evals": r["evals"], "seconds": dt,
-                        "evals_per_s": r["evals"] / dt, "leaf_n_min": int(n.min()),
-                        "leaf_n_max": int(n.max())})
+    for form, observable, nu in itertools.product(forms, observables, nus):
+        cfg = bfi.adaptive_config(target_rel_err=1e-3, max_evals=1 << budget_log2,
+                                  n_min=1 << 10, n_max=1 << 22, split_log2=10,
+                                  max_rounds=128, refine_fraction=0.5,
+                                  round_evals=max(1 << 24, (1 << budget_log2) >> 5),
+                                  split_samples=1 << 16)
+        t0 = time.perf_counter()
+        r = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(10, 2, nu=nu, observable=observable),
+                                       form, 1, -4.0, 4.0, cfg, leaf_capacity=1 << 22)
+        dt = time.perf_counter() - t0
+        print(f"bench: adaptive {form} {observable} nu={nu}: {r['status']} "
+              f"rel_err {r['rel_err']:.3g} in {dt:.2f} s", file=sys.stderr, flush=True)
+        n = r["partition"].n
+        out.append({"form": form, "observable": observable, "nu": nu, "status": r["status"],
+                    "rel_err": r["rel_err"], "ess": r["ess"], "rounds": r["rounds"],
+                    "leaves": r["leaves"], "evals": r["evals"], "seconds": dt,
+                    "evals_per_s": r["evals"] / dt, "leaf_n_min": int(n.min()),
+                    "leaf_n_max": int(n.max()), "split_samples": cfg.split_samples})
     return out
 
 
@@ -424,7 +429,7 @@ def main():
         print(f"bench: adaptive 10x2 to target, averaged observable, budget "
               f"2^{args.adaptive_target_budget_log2} per nu", file=sys.stderr, flush=True)
         adaptive_target = adaptive_leg(bfi, ctx, args.adaptive_target_budget_log2,
-                                       observables=("averaged",))
+                                       observables=("averaged",), forms=("fp32", "fp64"))
     if args.calibrate_copy_mib > 0:
         n = args.calibrate_copy_mib << 20
         x = torch.ones(n, dtype=torch.uint8, device="cuda:0")
@@ -512,6 +517,12 @@ def main():
         line["adaptive"] = adaptive
     if adaptive_target is not None:
         line["adaptive_to_target"] = adaptive_target
+        # time to the same error in both forms: FP64 seconds / FP32 seconds per nu
+        secs = {(a["form"], a["nu"]): a["seconds"] for a in adaptive_target
+                if a["status"] == "BFI_OK"}
+        line["fp32_speedup_at_target"] = {
+            str(nu): secs[("fp64", nu)] / secs[("fp32", nu)]
+            for (form, nu) in secs if form == "fp32" and ("fp64", nu) in secs}
     if not args.no_cpu_baseline:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, sv, args.cpu_samples_log2)

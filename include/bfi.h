@@ -265,6 +265,11 @@ typedef struct {
                                samples fall short of it, their counts are scaled up by a
                                power of two (within n_max); 0: no floor */
     double min_ess;         /* effective sample size the stop requires; 0: 100 */
+    uint64_t split_samples; /* the split statistics (and the leaf spread they are
+                               compared with) cover the first split_samples samples of
+                               each leaf's stream, which run through the kernel variant
+                               that accumulates them; later samples run through the
+                               plain kernel.  0: all samples; else >= 2 */
 } bfi_adaptive_config;
 
 typedef struct {
@@ -283,12 +288,16 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                                   size_t *n_leaves);
 
 /* One refinement decision of the adaptive policy, exposed for host-side tests.
- * For each leaf: partial record (BFI_PARTIAL_LEN(nx)) and split statistics
- * (BFI_SPLIT_LEN(d)) of its current samples.  action[i] is set to -1 (keep),
- * 0 (double the samples) or 1 + j (split along dimension j). */
+ * For each leaf: partial record (BFI_PARTIAL_LEN(nx)) of its current samples,
+ * which ranks it, and split statistics (BFI_SPLIT_LEN(d)) with split_base, the
+ * partial record of the samples they cover (its shift, count, sum of w and of
+ * w^2 give the spread the split is judged against).  split_base NULL: the
+ * statistics cover the same samples as `partials`.  action[i] is set to -1
+ * (keep), 0 (double the samples) or 1 + j (split along dimension j). */
 bfi_status bfi_adaptive_decide(const bfi_lattice *lat, const bfi_subvolumes *leaves,
                                const double *partials, const double *split,
-                               const bfi_adaptive_config *cfg, int32_t *action);
+                               const double *split_base, const bfi_adaptive_config *cfg,
+                               int32_t *action);
 
 /* Single integrands on the paper's integrand protocol (section 3): for each
  * subvolume, the integral over it (result), its absolute error V s / sqrt(n),

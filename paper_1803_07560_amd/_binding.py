@@ -74,7 +74,8 @@ class bfi_adaptive_config(C.Structure):
     _fields_ = [("target_rel_err", C.c_double), ("max_evals", C.c_uint64),
                 ("n_min", C.c_uint64), ("n_max", C.c_uint64), ("split_log2", C.c_int32),
                 ("max_rounds", C.c_int32), ("refine_fraction", C.c_double),
-                ("round_evals", C.c_uint64), ("min_ess", C.c_double)]
+                ("round_evals", C.c_uint64), ("min_ess", C.c_double),
+                ("split_samples", C.c_uint64)]
 
 
 class bfi_adaptive_stats(C.Structure):
@@ -161,7 +162,7 @@ _SIGNATURES = {
                                 _P(C.c_double), _P(C.c_double), _P(C.c_uint64), _P(C.c_uint64),
                                 C.c_size_t, _P(C.c_size_t)], C.c_int),
     "bfi_adaptive_decide": ([_P(bfi_lattice), _P(bfi_subvolumes), _P(C.c_double), _P(C.c_double),
-                             _P(bfi_adaptive_config), _P(C.c_int32)], C.c_int),
+                             _P(C.c_double), _P(bfi_adaptive_config), _P(C.c_int32)], C.c_int),
     "bfi_integrand_eval": ([_vp, _P(bfi_integrand), C.c_uint64, _P(bfi_subvolumes),
                             _P(bfi_launch), _P(C.c_double), _P(C.c_double), _P(C.c_int32)],
                            C.c_int),
@@ -409,10 +410,10 @@ def bfi_integrate(ctx, lat, prec, seed, box_lo, box_hi, split_log2, budget, laun
 
 def adaptive_config(target_rel_err=1e-3, max_evals=1 << 34, n_min=1 << 12, n_max=1 << 22,
                     split_log2=10, max_rounds=64, refine_fraction=0.5,
-                    round_evals=0, min_ess=0.0) -> bfi_adaptive_config:
+                    round_evals=0, min_ess=0.0, split_samples=1 << 16) -> bfi_adaptive_config:
     return bfi_adaptive_config(float(target_rel_err), int(max_evals), int(n_min), int(n_max),
                                int(split_log2), int(max_rounds), float(refine_fraction),
-                               int(round_evals), float(min_ess))
+                               int(round_evals), float(min_ess), int(split_samples))
 
 
 def bfi_integrate_adaptive(ctx, lat, prec, seed, box_lo, box_hi, cfg, launch_=None,
@@ -443,13 +444,19 @@ def bfi_integrate_adaptive(ctx, lat, prec, seed, box_lo, box_hi, cfg, launch_=No
     return out
 
 
-def bfi_adaptive_decide(lat, leaves, partials, split, cfg) -> np.ndarray:
+def bfi_adaptive_decide(lat, leaves, partials, split, cfg, split_base=None) -> np.ndarray:
+    """split_base: records of the samples the split statistics cover (None: the
+    same samples as `partials`)."""
     sv = Subvolumes.of(leaves, lat.d)
     p = np.ascontiguousarray(partials, dtype=np.float64)
     s = np.ascontiguousarray(split, dtype=np.float64)
+    b = None if split_base is None else np.ascontiguousarray(split_base, dtype=np.float64)
+    if b is not None and b.shape != p.shape:
+        raise ValueError("split_base must have the shape of partials")
     act = np.zeros(len(sv), dtype=np.int32)
     _check(load().bfi_adaptive_decide(C.byref(lat), C.byref(sv.view), _dp(p), _dp(s),
-                                      C.byref(cfg), act.ctypes.data_as(_P(C.c_int32))),
+                                      None if b is None else _dp(b), C.byref(cfg),
+                                      act.ctypes.data_as(_P(C.c_int32))),
            "bfi_adaptive_decide")
     return act
 

@@ -9,10 +9,13 @@
 //      their contributions reach `refine_fraction` of the total (at least one).
 //   3. A taken leaf is split at the midpoint of the dimension j* minimising
 //      sigma_lower(j) + sigma_upper(j) -- the standard deviations of the weight
-//      in the two halves, from the split statistics (each half holds n/2 samples
-//      in expectation) -- when that sum is below kSplitGain * 2 sigma_leaf or
-//      when doubling would exceed n_max; otherwise its samples are doubled by
-//      continuing its own Philox stream.  Ties in j* go to the lower dimension.
+//      in the two halves, from the split statistics of m samples (each half holds
+//      m/2 in expectation) -- when that sum is below kSplitGain * 2 sigma_leaf
+//      (sigma_leaf over the same m samples) or when doubling would exceed n_max;
+//      otherwise its samples are doubled by continuing its own Philox stream.
+//      Ties in j* go to the lower dimension.  m is the leaf's sample count, or
+//      at most `split_samples`: the statistics then come from the first samples
+//      of the stream only, and the rest run through the plain kernel.
 //   4. Children get fresh streams (ids 2 id and 2 id + 1) with
 //      clamp(n_leaf, n_min, n_max) samples each; the parent's samples are dropped.
 //   5. If the round's planned samples fall short of `round_evals`, every planned
@@ -54,9 +57,11 @@ std::vector<double> common_shift_factors(size_t count, const double *partials, i
     return f;
 }
 
+// `split_base` is the record of the samples the split statistics cover (the
+// whole leaf, or its first split_samples samples); `partials` covers all of them.
 bfi_status analyse(int nx, int d, size_t count, const double *lo, const double *hi,
-                   const double *partials, const double *split, std::vector<LeafAnalysis> *out,
-                   bfi_result *res)
+                   const double *partials, const double *split, const double *split_base,
+                   std::vector<LeafAnalysis> *out, bfi_result *res)
 {
     const int rec_len = BFI_PARTIAL_LEN(nx), split_len = BFI_SPLIT_LEN(d);
     BFI_TRY(finalize_records(nx, d, count, lo, hi, partials, res));
@@ -90,10 +95,11 @@ bfi_status analyse(int nx, int d, size_t count, const double *lo, const double *
         (*out)[s].e = z > 0 ? std::max(e, 0.0) / (z * z) : 0.0;
         if (!split)
             continue;
-        // split analysis in the leaf's own shift (the split record shares it)
-        const double *sp = split + s * split_len;
-        const double S = rec[2], Q = rec[3], half = 0.5 * n;
-        const double sigma = std::sqrt(std::max(Q / n - (S / n) * (S / n), 0.0));
+        // split analysis in the shift of the covered samples (the split record
+        // shares it)
+        const double *sp = split + s * split_len, *base = split_base + s * rec_len;
+        const double S = base[2], Q = base[3], m = base[0], half = 0.5 * m;
+        const double sigma = std::sqrt(std::max(Q / m - (S / m) * (S / m), 0.0));
         double best = std::numeric_limits<double>::infinity();
         int best_j = 0;
         for (int j = 0; j < d; ++j) {
@@ -178,6 +184,8 @@ bfi_status check_config(const bfi_adaptive_config *cfg)
         return fail(BFI_EINVAL, "max_rounds must be >= 0");
     if (!(cfg->min_ess >= 0) || !std::isfinite(cfg->min_ess))
         return fail(BFI_EINVAL, "min_ess must be finite and >= 0");
+    if (cfg->split_samples == 1)
+        return fail(BFI_EINVAL, "split_samples must be 0 (all samples) or >= 2");
     return BFI_OK;
 }
 
@@ -214,21 +222,82 @@ void record_fields(int nx, std::vector<int> *first, std::vector<int> *second)
 struct LeafSet {
     int d = 0, nx = 0;
     std::vector<uint64_t> id, n;
-    std::vector<double> lo, hi, rec, split;
+    // rec: all samples; split and base: split statistics and the record of the
+    // samples they cover (the first split_samples of the leaf's stream)
+    std::vector<double> lo, hi, rec, split, base;
     size_t size() const { return id.size(); }
 };
 
-// Evaluate a work list (with split statistics) on the device.
-bfi_status eval_list(bfi_context *ctx, const bfi_lattice &lat, int prec, uint64_t seed,
-                     const SubList &work, const bfi_launch *launch, std::vector<double> *rec,
-                     std::vector<double> *split)
+// Merge record b into a when both may be empty (count 0: nothing to add).
+void merge_record(double *a, const double *b, int len, const std::vector<int> &first,
+                  const std::vector<int> &second)
 {
-    const int d = lat.nx * lat.nt;
-    rec->assign(work.size() * BFI_PARTIAL_LEN(lat.nx), 0.0);
-    split->assign(work.size() * BFI_SPLIT_LEN(d), 0.0);
-    bfi_subvolumes v = work.view();
-    return bfi_eval(ctx, &lat, static_cast<bfi_precision>(prec), seed, &v, launch, rec->data(),
-                    split->data());
+    if (b[0] == 0)
+        return;
+    if (a[0] == 0) {
+        std::copy(b, b + len, a);
+        return;
+    }
+    merge_shifted(a, b, 1, first, second, 0);
+}
+
+// Evaluate a work list on the device.  The samples below index `split_samples`
+// of each stream (all of them when 0) go through the kernel variant with split
+// statistics, the rest through the plain kernel.  Per entry: rec covers all its
+// samples, base and split the ones with statistics (count 0 and zeros if none).
+bfi_status eval_list(bfi_context *ctx, const bfi_lattice &lat, int prec, uint64_t seed,
+                     const SubList &work, uint64_t split_samples, const bfi_launch *launch,
+                     std::vector<double> *rec, std::vector<double> *split,
+                     std::vector<double> *base)
+{
+    const int d = lat.nx * lat.nt, rec_len = BFI_PARTIAL_LEN(lat.nx), split_len = BFI_SPLIT_LEN(d);
+    const size_t count = work.size();
+    rec->assign(count * rec_len, 0.0);
+    split->assign(count * split_len, 0.0);
+    base->assign(count * rec_len, 0.0);
+    // the two lists: entry w's covered part [offset, min(end, P)) and the rest
+    SubList with, without;
+    with.d = without.d = d;
+    std::vector<size_t> with_of, without_of;
+    for (size_t w = 0; w < count; ++w) {
+        const uint64_t off = work.offset[w], end = off + work.n[w];
+        const uint64_t cut = split_samples == 0 ? end : std::min(std::max(split_samples, off), end);
+        const uint64_t parts[2][2] = {{off, cut}, {cut, end}};
+        for (int k = 0; k < 2; ++k) {
+            if (parts[k][1] <= parts[k][0])
+                continue;
+            SubList &dst = k == 0 ? with : without;
+            (k == 0 ? with_of : without_of).push_back(w);
+            dst.id.push_back(work.id[w]);
+            dst.offset.push_back(parts[k][0]);
+            dst.n.push_back(parts[k][1] - parts[k][0]);
+            dst.lo.insert(dst.lo.end(), &work.lo[w * d], &work.lo[w * d] + d);
+            dst.hi.insert(dst.hi.end(), &work.hi[w * d], &work.hi[w * d] + d);
+        }
+    }
+    std::vector<int> first, second;
+    record_fields(lat.nx, &first, &second);
+    if (with.size() > 0) {
+        std::vector<double> r(with.size() * rec_len), sp(with.size() * split_len);
+        bfi_subvolumes v = with.view();
+        BFI_TRY(bfi_eval(ctx, &lat, static_cast<bfi_precision>(prec), seed, &v, launch, r.data(),
+                         sp.data()));
+        for (size_t i = 0; i < with.size(); ++i) {
+            const size_t w = with_of[i];
+            std::copy(&r[i * rec_len], &r[i * rec_len] + rec_len, &(*base)[w * rec_len]);
+            std::copy(&r[i * rec_len], &r[i * rec_len] + rec_len, &(*rec)[w * rec_len]);
+            std::copy(&sp[i * split_len], &sp[i * split_len] + split_len, &(*split)[w * split_len]);
+        }
+    }
+    if (without.size() > 0) {
+        std::vector<double> r(without.size() * rec_len);
+        bfi_subvolumes v = without.view();
+        BFI_TRY(bfi_eval(ctx, &lat, static_cast<bfi_precision>(prec), seed, &v, launch, r.data(),
+                         nullptr));
+        for (size_t i = 0; i < without.size(); ++i)
+            merge_record(&(*rec)[without_of[i] * rec_len], &r[i * rec_len], rec_len, first, second);
+    }
+    return BFI_OK;
 }
 
 }  // namespace
@@ -278,7 +347,8 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         L.n = init.n;
         L.lo = init.lo;
         L.hi = init.hi;
-        BFI_TRY(eval_list(ctx, *lat, prec, seed, init, launch, &L.rec, &L.split));
+        BFI_TRY(eval_list(ctx, *lat, prec, seed, init, cfg->split_samples, launch, &L.rec,
+                          &L.split, &L.base));
 
         bfi_status status = BFI_OK;
         const double min_ess = cfg->min_ess > 0 ? cfg->min_ess : 100.0;
@@ -287,7 +357,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         std::vector<LeafAnalysis> an;
         for (;;) {
             BFI_TRY(analyse(nx, d, L.size(), L.lo.data(), L.hi.data(), L.rec.data(), L.split.data(),
-                            &an, &res));
+                            L.base.data(), &an, &res));
             if (rel_err(res) <= cfg->target_rel_err && res.ess >= min_ess)
                 break;
             if (rounds >= cfg->max_rounds) {
@@ -306,49 +376,61 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                     return an[x].e > an[y].e;
                 return L.id[x] < L.id[y];
             });
-            // planned count of a refined leaf at scale factor f (within n_max)
+            // planned count of a refined leaf at scale factor f (within n_max):
+            // children clamp(n, n_min, n_max) each, doubled leaves 2n, times f
             std::vector<uint64_t> target(L.size(), 0);  // new per-leaf (or per-child) count
-            auto plan_counts = [&](uint64_t f, bool *grew) {
-                uint64_t planned = 0;
+            auto leaf_target = [&](size_t s, uint64_t f) {
+                const uint64_t base = action[s] == 0 ? 2 * L.n[s]
+                                                      : std::min(std::max(L.n[s], cfg->n_min),
+                                                                 cfg->n_max);
+                const uint64_t cap = std::max(cfg->n_max, base);
+                return base > cap / f ? cap : std::max(base, std::min(base * f, cap));
+            };
+            auto leaf_cost = [&](size_t s) {
+                return action[s] == 0 ? target[s] - L.n[s] : 2 * target[s];
+            };
+            // refined leaves whose count would still grow at 2f
+            auto grows = [&](size_t s, uint64_t f) {
+                return f <= std::numeric_limits<uint64_t>::max() / 2 &&
+                       leaf_target(s, 2 * f) > target[s];
+            };
+            uint64_t f = 1, planned = 0;
+            size_t growable = 0;
+            auto plan_all = [&]() {
+                planned = 0;
+                growable = 0;
                 for (size_t s = 0; s < L.size(); ++s) {
                     if (action[s] < 0)
                         continue;
-                    const uint64_t base = action[s] == 0 ? 2 * L.n[s]
-                                                          : std::min(std::max(L.n[s], cfg->n_min),
-                                                                     cfg->n_max);
-                    const uint64_t t =
-                        std::max(base, std::min(base * f, std::max(cfg->n_max, base)));
-                    if (grew && t > target[s])
-                        *grew = true;
-                    target[s] = t;
-                    planned += action[s] == 0 ? t - L.n[s] : 2 * t;
+                    target[s] = leaf_target(s, f);
+                    planned += leaf_cost(s);
+                    growable += grows(s, f);
                 }
-                return planned;
             };
-            uint64_t f = 1;
-            uint64_t planned = plan_counts(f, nullptr);
+            plan_all();
             // work floor: scale the refined leaves by powers of two; once n_max caps
-            // them, refine further leaves in variance order
+            // them all, refine further leaves in variance order (each at the current
+            // factor; the next pass doubles again if one of them can still grow)
             size_t next_leaf = 0;
             while (cfg->round_evals > 0 && planned < cfg->round_evals) {
-                bool grew = false;
-                const std::vector<uint64_t> keep = target;
-                const uint64_t p2 = plan_counts(2 * f, &grew);
-                if (grew) {
+                if (growable > 0) {
                     f *= 2;
-                    planned = p2;
+                    plan_all();
                     continue;
                 }
-                target = keep;
                 while (next_leaf < order.size() && action[order[next_leaf]] != -1)
                     ++next_leaf;
                 if (next_leaf == order.size())
                     break;
                 const size_t s = order[next_leaf];
                 action[s] = leaf_action(an[s], L.id[s], L.n[s], *cfg);
-                if (action[s] < 0)
+                if (action[s] < 0) {
                     action[s] = -2;  // neither split nor doubling possible: skip it
-                planned = plan_counts(f, nullptr);
+                    continue;
+                }
+                target[s] = leaf_target(s, f);
+                planned += leaf_cost(s);
+                growable += grows(s, f);
             }
             for (auto &a : action)
                 if (a == -2)
@@ -406,8 +488,9 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                     origin.push_back({s, 1 + half});
                 }
             }
-            std::vector<double> wrec, wsplit;
-            BFI_TRY(eval_list(ctx, *lat, prec, seed, work, launch, &wrec, &wsplit));
+            std::vector<double> wrec, wsplit, wbase;
+            BFI_TRY(eval_list(ctx, *lat, prec, seed, work, cfg->split_samples, launch, &wrec,
+                              &wsplit, &wbase));
             evals += cost;
 
             // fold the results into the leaf set, keeping leaf order (children in place)
@@ -418,30 +501,39 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             for (size_t w = 0; w < origin.size(); ++w)
                 from[origin[w].leaf].push_back(w);
             auto push_leaf = [&](uint64_t id, uint64_t n, const double *lo, const double *hi,
-                                 const double *rec, const double *spl) {
+                                 const double *rec, const double *spl, const double *base) {
                 N.id.push_back(id);
                 N.n.push_back(n);
                 N.lo.insert(N.lo.end(), lo, lo + d);
                 N.hi.insert(N.hi.end(), hi, hi + d);
                 N.rec.insert(N.rec.end(), rec, rec + rec_len);
                 N.split.insert(N.split.end(), spl, spl + split_len);
+                N.base.insert(N.base.end(), base, base + rec_len);
             };
             for (size_t s = 0; s < L.size(); ++s) {
                 if (action[s] < 0) {
                     push_leaf(L.id[s], L.n[s], &L.lo[s * d], &L.hi[s * d], &L.rec[s * rec_len],
-                              &L.split[s * split_len]);
+                              &L.split[s * split_len], &L.base[s * rec_len]);
                 } else if (action[s] == 0) {
                     const size_t w = from[s][0];
                     std::vector<double> rec(&L.rec[s * rec_len], &L.rec[s * rec_len] + rec_len);
                     std::vector<double> spl(&L.split[s * split_len],
                                             &L.split[s * split_len] + split_len);
+                    std::vector<double> base(&L.base[s * rec_len], &L.base[s * rec_len] + rec_len);
                     merge_shifted(rec.data(), &wrec[w * rec_len], 1, rec_first, rec_second, 0);
-                    merge_shifted(spl.data(), &wsplit[w * split_len], 0, split_first, split_second, -1);
-                    push_leaf(L.id[s], target[s], &L.lo[s * d], &L.hi[s * d], rec.data(), spl.data());
+                    if (wbase[w * rec_len] > 0) {
+                        // the continuation still lies below split_samples
+                        merge_shifted(spl.data(), &wsplit[w * split_len], 0, split_first,
+                                      split_second, -1);
+                        merge_shifted(base.data(), &wbase[w * rec_len], 1, rec_first, rec_second,
+                                      0);
+                    }
+                    push_leaf(L.id[s], target[s], &L.lo[s * d], &L.hi[s * d], rec.data(), spl.data(),
+                              base.data());
                 } else {
                     for (size_t w : from[s])
                         push_leaf(work.id[w], work.n[w], &work.lo[w * d], &work.hi[w * d],
-                                  &wrec[w * rec_len], &wsplit[w * split_len]);
+                                  &wrec[w * rec_len], &wsplit[w * split_len], &wbase[w * rec_len]);
                 }
             }
             L = std::move(N);
@@ -479,7 +571,8 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
 
 bfi_status bfi_adaptive_decide(const bfi_lattice *lat, const bfi_subvolumes *leaves,
                                const double *partials, const double *split,
-                               const bfi_adaptive_config *cfg, int32_t *action)
+                               const double *split_base, const bfi_adaptive_config *cfg,
+                               int32_t *action)
 {
     return guarded([&]() -> bfi_status {
         if (!lat || !leaves || !partials || !split || !action)
@@ -496,7 +589,7 @@ bfi_status bfi_adaptive_decide(const bfi_lattice *lat, const bfi_subvolumes *lea
         std::vector<LeafAnalysis> an;
         bfi_result res;
         BFI_TRY(analyse(lat->nx, lat->nx * lat->nt, leaves->count, leaves->lo, leaves->hi, partials,
-                        split, &an, &res));
+                        split, split_base ? split_base : partials, &an, &res));
         decide(an, leaves->id, leaves->n, *cfg, action);
         return BFI_OK;
     });

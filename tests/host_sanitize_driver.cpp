@@ -89,12 +89,20 @@ int main()
             cfg.max_rounds = 8;
             cfg.refine_fraction = 0.5;
             std::vector<int32_t> action(ns, 7);
-            EXPECT(bfi_adaptive_decide(&lat, &sv, rec.data(), split.data(), &cfg,
+            EXPECT(bfi_adaptive_decide(&lat, &sv, rec.data(), split.data(), nullptr, &cfg,
                                        action.data()) == BFI_OK);
             for (int32_t a : action)
                 EXPECT(a >= -1 && a <= d);
+            std::vector<int32_t> again(ns, 7);
+            EXPECT(bfi_adaptive_decide(&lat, &sv, rec.data(), split.data(), rec.data(), &cfg,
+                                       again.data()) == BFI_OK);
+            EXPECT(again == action);
+            cfg.split_samples = 1;
+            EXPECT(bfi_adaptive_decide(&lat, &sv, rec.data(), split.data(), nullptr, &cfg,
+                                       action.data()) == BFI_EINVAL);
+            cfg.split_samples = 0;
             cfg.refine_fraction = 2.0;
-            EXPECT(bfi_adaptive_decide(&lat, &sv, rec.data(), split.data(), &cfg,
+            EXPECT(bfi_adaptive_decide(&lat, &sv, rec.data(), split.data(), nullptr, &cfg,
                                        action.data()) == BFI_EINVAL);
         }
         rec[0] = 1.0;  // n < 2

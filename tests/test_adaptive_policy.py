@@ -7,6 +7,8 @@ fed per-leaf records built from the oracle's sums, it must
   * double the samples instead when a split gains little and n <= n_max / 2,
     and split when doubling would exceed n_max.
 No GPU: the policy is host code."""
+import copy
+
 import numpy as np
 import pytest
 
@@ -43,9 +45,10 @@ def contributions(nx, d, sv, sums):
     return np.maximum(e, 0) / Z**2
 
 
-def brute_force_split(lat, seed, sv, s):
+def brute_force_split(lat, seed, sv, s, count=None):
     d = lat.d
-    U = oracle.points(d, seed, int(sv.ids[s]), sv.lo[s], sv.hi[s], range(int(sv.n[s])))
+    n = int(sv.n[s]) if count is None else min(int(sv.n[s]), count)
+    U = oracle.points(d, seed, int(sv.ids[s]), sv.lo[s], sv.hi[s], range(n))
     w = np.exp(-oracle.action_batch(lat, U))
     mid = 0.5 * (sv.lo[s] + sv.hi[s])
     n = len(w)
@@ -91,6 +94,38 @@ def test_selection_and_split_dimension(bfi, fraction):
             assert act[i] == 0 and gain >= 0.9 - 1e-9
 
 
+def test_split_statistics_of_first_samples(bfi):
+    """With split statistics over the first m samples of each leaf (what the
+    driver gathers when split_samples = m), the split dimension and gain come
+    from those m samples alone, judged against their own spread (split_base);
+    the ranking still uses every sample.  Without split_base the same
+    statistics would be judged against the spread of all n samples."""
+    nx, nt, seed, m = 3, 2, 4, 300
+    sv = workloads.random_partition(6, 2.0, 10, per_sub=1, seed=5)
+    sv.n[:] = [400, 800, 1600, 400, 3200, 800, 1600, 400, 800, 6400]
+    lat, sums, part, _ = records(nx, nt, sv, seed)
+    head = copy.deepcopy(sv)
+    head.n[:] = np.minimum(sv.n, m)
+    _, _, base, split = records(nx, nt, head, seed)
+    cfg = bfi.adaptive_config(target_rel_err=1e-6, n_min=256, n_max=1 << 20, refine_fraction=1.0)
+    act = bfi.bfi_adaptive_decide(bfi.lattice(nx, nt, nu=0.7), sv, part, split, cfg,
+                                  split_base=base)
+    e = contributions(nx, 6, sv, sums)
+    assert set(np.nonzero(act >= 0)[0]) == set(np.nonzero(e > 0)[0])
+    for i in np.nonzero(act >= 0)[0]:
+        j, gain = brute_force_split(lat, seed, sv, i, count=m)
+        if act[i] >= 1:
+            assert act[i] - 1 == j
+            assert gain < 0.9
+        else:
+            assert act[i] == 0 and gain >= 0.9 - 1e-9
+    # split_base equal to the partials is the default
+    np.testing.assert_array_equal(
+        bfi.bfi_adaptive_decide(bfi.lattice(nx, nt, nu=0.7), sv, part, split, cfg,
+                                split_base=part),
+        bfi.bfi_adaptive_decide(bfi.lattice(nx, nt, nu=0.7), sv, part, split, cfg))
+
+
 def test_split_forced_at_n_max(bfi):
     nx, nt = 2, 2
     sv = workloads.uniform_partition(4, 2.0, 2, per_sub=2048)
@@ -107,7 +142,8 @@ def test_decide_rejects_bad_config(bfi):
     sv = workloads.uniform_partition(4, 2.0, 1, per_sub=100)
     lat, sums, part, split = records(2, 2, sv, 1)
     for bad in (dict(n_min=1), dict(n_min=100, n_max=10), dict(refine_fraction=0.0),
-                dict(target_rel_err=0.0), dict(min_ess=-1.0), dict(min_ess=float("nan"))):
+                dict(target_rel_err=0.0), dict(min_ess=-1.0), dict(min_ess=float("nan")),
+                dict(split_samples=1)):
         cfg = bfi.adaptive_config(**bad)
         with pytest.raises(bfi.BfiError):
             bfi.bfi_adaptive_decide(bfi.lattice(2, 2), sv, part, split, cfg)

@@ -142,3 +142,54 @@ def test_adaptive_round_floor(bfi, ctx):
     ref = oracle.finalize(nx, nx * nt, part.lo, part.hi, sums)
     assert abs(out["Z"] - ref["Z"]) <= 1e-6 * ref["Z"]
     assert np.all(np.abs(out["C"] - ref["C"]) <= 1e-6 * abs(ref["C"][0]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_adaptive_split_statistics_of_first_samples(bfi, ctx, prec):
+    """split_samples = m below n_min: the first m samples of every leaf run through
+    the kernel variant with split statistics, the rest through the plain kernel.
+    After one round the partition must be the one bfi_adaptive_decide gives on
+    those records: the leaf records merged from both parts (ranking) and the split
+    statistics judged against the record of the first m samples."""
+    nx, nt, B, nu, m, n0, k = 3, 2, 2.0, 0.7, 512, 2048, 3
+    d = nx * nt
+    lat = bfi.lattice(nx, nt, nu=nu)
+    cfg = bfi.adaptive_config(target_rel_err=1e-12, max_evals=1 << 24, n_min=n0, n_max=1 << 16,
+                              split_log2=k, max_rounds=1, refine_fraction=0.5, split_samples=m)
+    out = bfi.bfi_integrate_adaptive(ctx, lat, prec, 3, -B, B, cfg)
+    assert out["status"] == "BFI_EBUDGET" and out["rounds"] == 1
+    head = workloads.uniform_partition(d, B, k, per_sub=m)
+    tail = workloads.uniform_partition(d, B, k, per_sub=n0 - m, offset=m)
+    init = workloads.uniform_partition(d, B, k, per_sub=n0)
+    head_rec, head_split = bfi.bfi_eval(ctx, lat, prec, 3, head, split=True)
+    full = bfi.bfi_partials_merge(nx, head_rec, bfi.bfi_eval(ctx, lat, prec, 3, tail))
+    act = bfi.bfi_adaptive_decide(lat, init, full, head_split, cfg, split_base=head_rec)
+    assert np.any(act >= 1) and np.any(act == -1)
+    want = {}
+    for i, a in enumerate(act):
+        hid, lo, hi = int(init.ids[i]), init.lo[i], init.hi[i]
+        if a < 0:
+            want[hid] = (n0, lo, hi)
+        elif a == 0:
+            want[hid] = (2 * n0, lo, hi)
+        else:
+            j = a - 1
+            mid = 0.5 * (lo[j] + hi[j])
+            hi_l, lo_u = hi.copy(), lo.copy()
+            hi_l[j], lo_u[j] = mid, mid
+            want[2 * hid] = (n0, lo, hi_l)
+            want[2 * hid + 1] = (n0, lo_u, hi)
+    part = out["partition"]
+    assert sorted(int(i) for i in part.ids) == sorted(want)
+    for i, hid in enumerate(part.ids):
+        n, lo, hi = want[int(hid)]
+        assert int(part.n[i]) == n
+        np.testing.assert_array_equal(part.lo[i], lo)
+        np.testing.assert_array_equal(part.hi[i], hi)
+    # the final estimate replays on the oracle (every leaf's samples from 0)
+    if prec == "fp64":
+        sums = oracle.sums(oracle.lattice(nx, nt, nu=nu), 3, part.ids, part.lo, part.hi, part.n,
+                           part.offset)
+        ref = oracle.finalize(nx, d, part.lo, part.hi, sums)
+        assert abs(out["Z"] - ref["Z"]) <= 1e-6 * ref["Z"]
+        assert np.all(np.abs(out["C"] - ref["C"]) <= 1e-6 * abs(ref["C"][0]))
