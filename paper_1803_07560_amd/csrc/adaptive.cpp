@@ -57,13 +57,11 @@ std::vector<double> common_shift_factors(size_t count, const double *partials, i
     return f;
 }
 
-// `split_base` is the record of the samples the split statistics cover (the
-// whole leaf, or its first split_samples samples); `partials` covers all of them.
+// Contribution of every leaf to the variance of C, and the estimate itself.
 bfi_status analyse(int nx, int d, size_t count, const double *lo, const double *hi,
-                   const double *partials, const double *split, const double *split_base,
-                   std::vector<LeafAnalysis> *out, bfi_result *res)
+                   const double *partials, std::vector<LeafAnalysis> *out, bfi_result *res)
 {
-    const int rec_len = BFI_PARTIAL_LEN(nx), split_len = BFI_SPLIT_LEN(d);
+    const int rec_len = BFI_PARTIAL_LEN(nx);
     BFI_TRY(finalize_records(nx, d, count, lo, hi, partials, res));
     const std::vector<double> f = common_shift_factors(count, partials, rec_len);
     // Z in the common shift
@@ -93,30 +91,41 @@ bfi_status analyse(int nx, int d, size_t count, const double *lo, const double *
             e += var_n - 2.0 * C * cov + C * C * var_z;
         }
         (*out)[s].e = z > 0 ? std::max(e, 0.0) / (z * z) : 0.0;
-        if (!split)
-            continue;
-        // split analysis in the shift of the covered samples (the split record
-        // shares it)
-        const double *sp = split + s * split_len, *base = split_base + s * rec_len;
-        const double S = base[2], Q = base[3], m = base[0], half = 0.5 * m;
-        const double sigma = std::sqrt(std::max(Q / m - (S / m) * (S / m), 0.0));
-        double best = std::numeric_limits<double>::infinity();
-        int best_j = 0;
-        for (int j = 0; j < d; ++j) {
-            const double su = sp[1 + j], qu = sp[1 + d + j];
-            const double sl = S - su, ql = Q - qu;
-            const double vu = std::max(qu / half - (su / half) * (su / half), 0.0);
-            const double vl = std::max(ql / half - (sl / half) * (sl / half), 0.0);
-            const double sj = std::sqrt(vu) + std::sqrt(vl);
-            if (sj < best) {
-                best = sj;
-                best_j = j;
-            }
-        }
-        (*out)[s].best_dim = best_j;
-        (*out)[s].gain = sigma > 0 ? best / (2.0 * sigma) : 1.0;
     }
     return BFI_OK;
+}
+
+// Split statistics of the leaves: `split` (BFI_SPLIT_LEN(d) per leaf) and `base`,
+// the record of the samples they cover (the whole leaf, or its first
+// split_samples samples).
+struct SplitStats {
+    int d, rec_len;
+    const double *split, *base;
+};
+
+// j* and the gain of leaf s, in the shift of the covered samples (the split
+// record shares it).
+void split_choice(const SplitStats &st, size_t s, LeafAnalysis *a)
+{
+    const int d = st.d;
+    const double *sp = st.split + s * BFI_SPLIT_LEN(d), *base = st.base + s * st.rec_len;
+    const double S = base[2], Q = base[3], m = base[0], half = 0.5 * m;
+    const double sigma = std::sqrt(std::max(Q / m - (S / m) * (S / m), 0.0));
+    double best = std::numeric_limits<double>::infinity();
+    int best_j = 0;
+    for (int j = 0; j < d; ++j) {
+        const double su = sp[1 + j], qu = sp[1 + d + j];
+        const double sl = S - su, ql = Q - qu;
+        const double vu = std::max(qu / half - (su / half) * (su / half), 0.0);
+        const double vl = std::max(ql / half - (sl / half) * (sl / half), 0.0);
+        const double sj = std::sqrt(vu) + std::sqrt(vl);
+        if (sj < best) {
+            best = sj;
+            best_j = j;
+        }
+    }
+    a->best_dim = best_j;
+    a->gain = sigma > 0 ? best / (2.0 * sigma) : 1.0;
 }
 
 double rel_err(const bfi_result &r)
@@ -129,25 +138,32 @@ double rel_err(const bfi_result &r)
 
 bool can_split(uint64_t id) { return id < (uint64_t(1) << 62); }
 
-// Action of one refined leaf: split along j* when that halves the spread well
+// Action of refined leaf s: split along j* when that halves the spread well
 // enough or doubling would exceed n_max, else double; -1 if neither is possible.
-int32_t leaf_action(const LeafAnalysis &a, uint64_t id, uint64_t n, const bfi_adaptive_config &cfg)
+// The split analysis is done here, for the leaves that are refined only.
+int32_t leaf_action(std::vector<LeafAnalysis> &an, const SplitStats &st, size_t s, uint64_t id,
+                    uint64_t n, const bfi_adaptive_config &cfg)
 {
     const bool doubling_ok = n <= cfg.n_max / 2;
-    const bool split_ok = can_split(id);
-    if (split_ok && (a.gain < kSplitGain || !doubling_ok))
-        return 1 + a.best_dim;
+    if (can_split(id)) {
+        split_choice(st, s, &an[s]);
+        if (an[s].gain < kSplitGain || !doubling_ok)
+            return 1 + an[s].best_dim;
+    }
     return doubling_ok ? 0 : -1;
 }
 
 // Decide actions: -1 keep, 0 double, 1 + j split along j.
-void decide(const std::vector<LeafAnalysis> &an, const uint64_t *ids, const uint64_t *n,
-            const bfi_adaptive_config &cfg, int32_t *action)
+// Decide actions: -1 keep, 0 double, 1 + j split along j.  *order gets the
+// leaves in ranking order (descending e, ties by lower id).
+void decide(std::vector<LeafAnalysis> &an, const SplitStats &st, const uint64_t *ids,
+            const uint64_t *n, const bfi_adaptive_config &cfg, int32_t *action,
+            std::vector<size_t> *order)
 {
     const size_t count = an.size();
-    std::vector<size_t> order(count);
-    std::iota(order.begin(), order.end(), 0);
-    std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+    order->resize(count);
+    std::iota(order->begin(), order->end(), 0);
+    std::sort(order->begin(), order->end(), [&](size_t x, size_t y) {
         if (an[x].e != an[y].e)
             return an[x].e > an[y].e;
         return ids[x] < ids[y];
@@ -158,13 +174,13 @@ void decide(const std::vector<LeafAnalysis> &an, const uint64_t *ids, const uint
     std::fill(action, action + count, -1);
     double taken = 0.0;
     for (size_t i = 0; i < count; ++i) {
-        const size_t s = order[i];
+        const size_t s = (*order)[i];
         if (i > 0 && taken >= cfg.refine_fraction * total)
             break;
         if (an[s].e <= 0.0 && i > 0)
             break;
         taken += an[s].e;
-        action[s] = leaf_action(an[s], ids[s], n[s], cfg);
+        action[s] = leaf_action(an, st, s, ids[s], n[s], cfg);
     }
 }
 
@@ -356,26 +372,20 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         bfi_result res{};
         std::vector<LeafAnalysis> an;
         for (;;) {
-            BFI_TRY(analyse(nx, d, L.size(), L.lo.data(), L.hi.data(), L.rec.data(), L.split.data(),
-                            L.base.data(), &an, &res));
+            BFI_TRY(analyse(nx, d, L.size(), L.lo.data(), L.hi.data(), L.rec.data(), &an, &res));
             if (rel_err(res) <= cfg->target_rel_err && res.ess >= min_ess)
                 break;
             if (rounds >= cfg->max_rounds) {
                 status = BFI_EBUDGET;
                 break;
             }
+            const SplitStats st{d, rec_len, L.split.data(), L.base.data()};
             std::vector<int32_t> action(L.size());
-            decide(an, L.id.data(), L.n.data(), *cfg, action.data());
+            std::vector<size_t> order;
+            decide(an, st, L.id.data(), L.n.data(), *cfg, action.data(), &order);
 
             // planned sample counts: children clamp(n, n_min, n_max) each, doubled
             // leaves 2n; scaled by a power of two up to the round's work floor
-            std::vector<size_t> order(L.size());
-            std::iota(order.begin(), order.end(), 0);
-            std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-                if (an[x].e != an[y].e)
-                    return an[x].e > an[y].e;
-                return L.id[x] < L.id[y];
-            });
             // planned count of a refined leaf at scale factor f (within n_max):
             // children clamp(n, n_min, n_max) each, doubled leaves 2n, times f
             std::vector<uint64_t> target(L.size(), 0);  // new per-leaf (or per-child) count
@@ -423,7 +433,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                 if (next_leaf == order.size())
                     break;
                 const size_t s = order[next_leaf];
-                action[s] = leaf_action(an[s], L.id[s], L.n[s], *cfg);
+                action[s] = leaf_action(an, st, s, L.id[s], L.n[s], *cfg);
                 if (action[s] < 0) {
                     action[s] = -2;  // neither split nor doubling possible: skip it
                     continue;
@@ -493,50 +503,51 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                               &wsplit, &wbase));
             evals += cost;
 
-            // fold the results into the leaf set, keeping leaf order (children in place)
-            LeafSet N;
-            N.d = d;
-            N.nx = nx;
-            std::vector<std::vector<size_t>> from(L.size());
-            for (size_t w = 0; w < origin.size(); ++w)
-                from[origin[w].leaf].push_back(w);
-            auto push_leaf = [&](uint64_t id, uint64_t n, const double *lo, const double *hi,
-                                 const double *rec, const double *spl, const double *base) {
-                N.id.push_back(id);
-                N.n.push_back(n);
-                N.lo.insert(N.lo.end(), lo, lo + d);
-                N.hi.insert(N.hi.end(), hi, hi + d);
-                N.rec.insert(N.rec.end(), rec, rec + rec_len);
-                N.split.insert(N.split.end(), spl, spl + split_len);
-                N.base.insert(N.base.end(), base, base + rec_len);
-            };
-            for (size_t s = 0; s < L.size(); ++s) {
-                if (action[s] < 0) {
-                    push_leaf(L.id[s], L.n[s], &L.lo[s * d], &L.hi[s * d], &L.rec[s * rec_len],
-                              &L.split[s * split_len], &L.base[s * rec_len]);
-                } else if (action[s] == 0) {
-                    const size_t w = from[s][0];
-                    std::vector<double> rec(&L.rec[s * rec_len], &L.rec[s * rec_len] + rec_len);
-                    std::vector<double> spl(&L.split[s * split_len],
-                                            &L.split[s * split_len] + split_len);
-                    std::vector<double> base(&L.base[s * rec_len], &L.base[s * rec_len] + rec_len);
-                    merge_shifted(rec.data(), &wrec[w * rec_len], 1, rec_first, rec_second, 0);
-                    if (wbase[w * rec_len] > 0) {
+            // fold the results into the leaf set in place: a doubled leaf merges
+            // its continuation, a split leaf becomes its lower child and its upper
+            // child is appended (work proportional to the round's work list)
+            size_t uppers = 0;
+            for (const Origin &o : origin)
+                uppers += o.kind == 2;
+            const size_t grown = L.size() + uppers;
+            L.id.reserve(grown);
+            L.n.reserve(grown);
+            L.lo.reserve(grown * d);
+            L.hi.reserve(grown * d);
+            L.rec.reserve(grown * rec_len);
+            L.split.reserve(grown * split_len);
+            L.base.reserve(grown * rec_len);
+            for (size_t w = 0; w < origin.size(); ++w) {
+                const size_t s = origin[w].leaf;
+                const double *wr = &wrec[w * rec_len], *ws = &wsplit[w * split_len],
+                             *wb = &wbase[w * rec_len];
+                if (origin[w].kind == 0) {
+                    merge_shifted(&L.rec[s * rec_len], wr, 1, rec_first, rec_second, 0);
+                    if (wb[0] > 0) {
                         // the continuation still lies below split_samples
-                        merge_shifted(spl.data(), &wsplit[w * split_len], 0, split_first,
-                                      split_second, -1);
-                        merge_shifted(base.data(), &wbase[w * rec_len], 1, rec_first, rec_second,
-                                      0);
+                        merge_shifted(&L.split[s * split_len], ws, 0, split_first, split_second,
+                                      -1);
+                        merge_shifted(&L.base[s * rec_len], wb, 1, rec_first, rec_second, 0);
                     }
-                    push_leaf(L.id[s], target[s], &L.lo[s * d], &L.hi[s * d], rec.data(), spl.data(),
-                              base.data());
+                    L.n[s] = target[s];
+                } else if (origin[w].kind == 1) {
+                    L.id[s] = work.id[w];
+                    L.n[s] = work.n[w];
+                    std::copy(&work.lo[w * d], &work.lo[w * d] + d, &L.lo[s * d]);
+                    std::copy(&work.hi[w * d], &work.hi[w * d] + d, &L.hi[s * d]);
+                    std::copy(wr, wr + rec_len, &L.rec[s * rec_len]);
+                    std::copy(ws, ws + split_len, &L.split[s * split_len]);
+                    std::copy(wb, wb + rec_len, &L.base[s * rec_len]);
                 } else {
-                    for (size_t w : from[s])
-                        push_leaf(work.id[w], work.n[w], &work.lo[w * d], &work.hi[w * d],
-                                  &wrec[w * rec_len], &wsplit[w * split_len], &wbase[w * rec_len]);
+                    L.id.push_back(work.id[w]);
+                    L.n.push_back(work.n[w]);
+                    L.lo.insert(L.lo.end(), &work.lo[w * d], &work.lo[w * d] + d);
+                    L.hi.insert(L.hi.end(), &work.hi[w * d], &work.hi[w * d] + d);
+                    L.rec.insert(L.rec.end(), wr, wr + rec_len);
+                    L.split.insert(L.split.end(), ws, ws + split_len);
+                    L.base.insert(L.base.end(), wb, wb + rec_len);
                 }
             }
-            L = std::move(N);
             ++rounds;
         }
 
@@ -586,11 +597,13 @@ bfi_status bfi_adaptive_decide(const bfi_lattice *lat, const bfi_subvolumes *lea
             return fail(BFI_EINVAL, "no leaves");
         if (!leaves->id || !leaves->lo || !leaves->hi || !leaves->n)
             return fail(BFI_EINVAL, "leaf arrays must be non-NULL");
+        const int d = lat->nx * lat->nt;
         std::vector<LeafAnalysis> an;
         bfi_result res;
-        BFI_TRY(analyse(lat->nx, lat->nx * lat->nt, leaves->count, leaves->lo, leaves->hi, partials,
-                        split, split_base ? split_base : partials, &an, &res));
-        decide(an, leaves->id, leaves->n, *cfg, action);
+        BFI_TRY(analyse(lat->nx, d, leaves->count, leaves->lo, leaves->hi, partials, &an, &res));
+        const SplitStats st{d, BFI_PARTIAL_LEN(lat->nx), split, split_base ? split_base : partials};
+        std::vector<size_t> order;
+        decide(an, st, leaves->id, leaves->n, *cfg, action, &order);
         return BFI_OK;
     });
 }
