@@ -221,7 +221,7 @@ def serve_leg(bfi, ctx, seconds, rate, warmup_s=1.0):
 
 
 def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0), observables=("anchor", "averaged"),
-                 forms=("fp32",)):
+                 forms=("fp32",), holdout_forms=()):
     """10x2 lattice, D = 1, box [-4,4]^20: error-driven bisection from the
     1024-subvolume partition at 2^10 samples per leaf, per-leaf counts in
     [2^10, 2^22], target max_r sigma_C(r)/|C(0)| <= 1e-3 with an effective
@@ -229,7 +229,11 @@ def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0), observables=("ancho
     evaluations per value of nu, each round at least 1/32 of it; split statistics
     from the first 2^16 samples of each leaf; the anchored product of the paper
     and the translation-averaged one.  status BFI_OK: the target was met, and
-    `seconds` is the time to it."""
+    `seconds` is the time to it.  For runs in `holdout_forms` the final partition
+    is also evaluated on a fresh pass (each leaf's stream continued over n more
+    samples, which no refinement decision has seen): `holdout_rel_err` is that
+    pass's max_r sigma_C(r)/|C(0)|, free of the selection that makes the stopping
+    estimate optimistic."""
     out = []
     for form, observable, nu in itertools.product(forms, observables, nus):
         cfg = bfi.adaptive_config(target_rel_err=1e-3, max_evals=1 << budget_log2,
@@ -243,12 +247,23 @@ def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0), observables=("ancho
         dt = time.perf_counter() - t0
         print(f"bench: adaptive {form} {observable} nu={nu}: {r['status']} "
               f"rel_err {r['rel_err']:.3g} in {dt:.2f} s", file=sys.stderr, flush=True)
-        n = r["partition"].n
-        out.append({"form": form, "observable": observable, "nu": nu, "status": r["status"],
-                    "rel_err": r["rel_err"], "ess": r["ess"], "rounds": r["rounds"],
-                    "leaves": r["leaves"], "evals": r["evals"], "seconds": dt,
-                    "evals_per_s": r["evals"] / dt, "leaf_n_min": int(n.min()),
-                    "leaf_n_max": int(n.max()), "split_samples": cfg.split_samples})
+        part = r["partition"]
+        n = part.n
+        rec = {"form": form, "observable": observable, "nu": nu, "status": r["status"],
+               "rel_err": r["rel_err"], "ess": r["ess"], "rounds": r["rounds"],
+               "leaves": r["leaves"], "evals": r["evals"], "seconds": dt,
+               "evals_per_s": r["evals"] / dt, "leaf_n_min": int(n.min()),
+               "leaf_n_max": int(n.max()), "split_samples": cfg.split_samples}
+        if form in holdout_forms:
+            lat = bfi.lattice(10, 2, nu=nu, observable=observable)
+            fresh = bfi.Subvolumes(part.ids, part.lo, part.hi, n, n, lat.d)
+            h = bfi.bfi_finalize(lat, fresh, bfi.bfi_eval(ctx, lat, form, 1, fresh))
+            rec["holdout_rel_err"] = float(np.max(h["C_err"]) / abs(h["C"][0]))
+            rec["holdout_ess"] = float(h["ess"])
+            rec["holdout_C_dev"] = float(np.max(np.abs(h["C"] - r["C"])) / abs(r["C"][0]))
+            print(f"bench: holdout pass rel_err {rec['holdout_rel_err']:.3g}", file=sys.stderr,
+                  flush=True)
+        out.append(rec)
     return out
 
 
@@ -429,7 +444,8 @@ def main():
         print(f"bench: adaptive 10x2 to target, averaged observable, budget "
               f"2^{args.adaptive_target_budget_log2} per nu", file=sys.stderr, flush=True)
         adaptive_target = adaptive_leg(bfi, ctx, args.adaptive_target_budget_log2,
-                                       observables=("averaged",), forms=("fp32", "fp64"))
+                                       observables=("averaged",), forms=("fp32", "fp64"),
+                                       holdout_forms=("fp32",))
     if args.calibrate_copy_mib > 0:
         n = args.calibrate_copy_mib << 20
         x = torch.ones(n, dtype=torch.uint8, device="cuda:0")

@@ -270,6 +270,15 @@ typedef struct {
                                each leaf's stream, which run through the kernel variant
                                that accumulates them; later samples run through the
                                plain kernel.  0: all samples; else >= 2 */
+    int32_t holdout;        /* 0: stop when the running estimate meets the target.
+                               1: confirm it on a holdout pass first -- every leaf's n
+                               samples drawn afresh under seed + k * 0x9E3779B97F4A7C15
+                               (k = 1, 2, ... per check), which no refinement decision
+                               has seen.  The run stops when the holdout estimate meets
+                               the target (out then holds that estimate); otherwise the
+                               running target is tightened by min(1/2, target / holdout
+                               error) and refinement goes on.  Holdout evaluations count
+                               against max_evals. */
 } bfi_adaptive_config;
 
 typedef struct {
@@ -277,6 +286,12 @@ typedef struct {
     uint64_t leaves;
     uint64_t evals;
     double rel_err;         /* achieved max_r sigma_C(r)/|C(0)| */
+    int32_t holdout_checks; /* holdout passes run (holdout = 1) */
+    int32_t holdout_used;   /* 1: out holds the last holdout pass's estimate, whose
+                               samples are the partition's leaves (offset 0, n) under
+                               holdout_seed */
+    uint64_t holdout_seed;
+    double holdout_rel_err; /* max_r sigma_C(r)/|C(0)| of the last holdout pass (0: none) */
 } bfi_adaptive_stats;
 
 bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,

@@ -75,12 +75,14 @@ class bfi_adaptive_config(C.Structure):
                 ("n_min", C.c_uint64), ("n_max", C.c_uint64), ("split_log2", C.c_int32),
                 ("max_rounds", C.c_int32), ("refine_fraction", C.c_double),
                 ("round_evals", C.c_uint64), ("min_ess", C.c_double),
-                ("split_samples", C.c_uint64)]
+                ("split_samples", C.c_uint64), ("holdout", C.c_int32)]
 
 
 class bfi_adaptive_stats(C.Structure):
     _fields_ = [("rounds", C.c_int32), ("leaves", C.c_uint64), ("evals", C.c_uint64),
-                ("rel_err", C.c_double)]
+                ("rel_err", C.c_double), ("holdout_checks", C.c_int32),
+                ("holdout_used", C.c_int32), ("holdout_seed", C.c_uint64),
+                ("holdout_rel_err", C.c_double)]
 
 
 class bfi_server_config(C.Structure):
@@ -410,10 +412,12 @@ def bfi_integrate(ctx, lat, prec, seed, box_lo, box_hi, split_log2, budget, laun
 
 def adaptive_config(target_rel_err=1e-3, max_evals=1 << 34, n_min=1 << 12, n_max=1 << 22,
                     split_log2=10, max_rounds=64, refine_fraction=0.5,
-                    round_evals=0, min_ess=0.0, split_samples=1 << 16) -> bfi_adaptive_config:
+                    round_evals=0, min_ess=0.0, split_samples=1 << 16,
+                    holdout=False) -> bfi_adaptive_config:
     return bfi_adaptive_config(float(target_rel_err), int(max_evals), int(n_min), int(n_max),
                                int(split_log2), int(max_rounds), float(refine_fraction),
-                               int(round_evals), float(min_ess), int(split_samples))
+                               int(round_evals), float(min_ess), int(split_samples),
+                               int(bool(holdout)))
 
 
 def bfi_integrate_adaptive(ctx, lat, prec, seed, box_lo, box_hi, cfg, launch_=None,
@@ -439,7 +443,9 @@ def bfi_integrate_adaptive(ctx, lat, prec, seed, box_lo, box_hi, cfg, launch_=No
     k = nl.value
     out = res.to_dict()
     out.update({"status": STATUS[s], "rounds": st.rounds, "leaves": st.leaves, "evals": st.evals,
-                "rel_err": st.rel_err,
+                "rel_err": st.rel_err, "holdout_checks": st.holdout_checks,
+                "holdout_used": bool(st.holdout_used), "holdout_seed": st.holdout_seed,
+                "holdout_rel_err": st.holdout_rel_err,
                 "partition": Subvolumes(ids[:k], llo[:k], lhi[:k], ln[:k], loff[:k], lat.d)})
     return out
 

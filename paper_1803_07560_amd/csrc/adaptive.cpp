@@ -25,6 +25,12 @@
 // Rounds repeat until max_r sigma_C(r) / |C(0)| <= target, the evaluation budget
 // or the round limit is reached.  Every round's work list (uneven sample counts)
 // is drained by the persistent kernel through the device queue.
+//
+// The running estimate is judged on the samples that steered the refinement:
+// leaves whose samples happened to miss the rare large weights look quiet and
+// are left alone, so its error bar is optimistic when the weights are heavy
+// tailed.  With `holdout` the stop is confirmed on the same leaves sampled
+// afresh under another seed; a failed check tightens the running target.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -202,6 +208,8 @@ bfi_status check_config(const bfi_adaptive_config *cfg)
         return fail(BFI_EINVAL, "min_ess must be finite and >= 0");
     if (cfg->split_samples == 1)
         return fail(BFI_EINVAL, "split_samples must be 0 (all samples) or >= 2");
+    if (cfg->holdout != 0 && cfg->holdout != 1)
+        return fail(BFI_EINVAL, "holdout must be 0 or 1");
     return BFI_OK;
 }
 
@@ -368,13 +376,55 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
 
         bfi_status status = BFI_OK;
         const double min_ess = cfg->min_ess > 0 ? cfg->min_ess : 100.0;
-        int rounds = 0;
+        int rounds = 0, checks = 0;
+        bool holdout_used = false;
+        uint64_t holdout_seed = 0;
+        double holdout_err = 0.0;
+        double run_target = cfg->target_rel_err;  // tightened by failed holdout checks
         bfi_result res{};
         std::vector<LeafAnalysis> an;
         for (;;) {
             BFI_TRY(analyse(nx, d, L.size(), L.lo.data(), L.hi.data(), L.rec.data(), &an, &res));
-            if (rel_err(res) <= cfg->target_rel_err && res.ess >= min_ess)
-                break;
+            if (rel_err(res) <= run_target && res.ess >= min_ess) {
+                if (!cfg->holdout)
+                    break;
+                // holdout check: the same leaves, samples drawn afresh under a
+                // seed of their own, so no refinement decision has seen them
+                uint64_t cost = 0;
+                for (uint64_t n : L.n)
+                    cost += n;
+                if (cost > cfg->max_evals - evals) {
+                    status = BFI_EBUDGET;
+                    break;
+                }
+                ++checks;
+                const uint64_t hseed = seed + static_cast<uint64_t>(checks) * 0x9E3779B97F4A7C15ull;
+                SubList fresh;
+                fresh.d = d;
+                fresh.id = L.id;
+                fresh.n = L.n;
+                fresh.offset.assign(L.size(), 0);
+                fresh.lo = L.lo;
+                fresh.hi = L.hi;
+                std::vector<double> hrec(L.size() * rec_len);
+                bfi_subvolumes v = fresh.view();
+                BFI_TRY(bfi_eval(ctx, lat, prec, hseed, &v, launch, hrec.data(), nullptr));
+                evals += cost;
+                bfi_result hres{};
+                BFI_TRY(finalize_records(nx, d, L.size(), L.lo.data(), L.hi.data(), hrec.data(),
+                                         &hres));
+                const double herr = rel_err(hres);
+                holdout_err = herr;
+                if (herr <= cfg->target_rel_err && hres.ess >= min_ess) {
+                    res = hres;
+                    holdout_used = true;
+                    holdout_seed = hseed;
+                    break;
+                }
+                // the running estimate was optimistic: ask more of it
+                run_target *= std::min(0.5, cfg->target_rel_err / herr);
+                continue;
+            }
             if (rounds >= cfg->max_rounds) {
                 status = BFI_EBUDGET;
                 break;
@@ -557,6 +607,10 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             stats->leaves = L.size();
             stats->evals = evals;
             stats->rel_err = rel_err(res);
+            stats->holdout_checks = checks;
+            stats->holdout_used = holdout_used ? 1 : 0;
+            stats->holdout_seed = holdout_seed;
+            stats->holdout_rel_err = holdout_err;
         }
         if (n_leaves)
             *n_leaves = L.size();

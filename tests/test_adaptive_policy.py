@@ -147,3 +147,7 @@ def test_decide_rejects_bad_config(bfi):
         cfg = bfi.adaptive_config(**bad)
         with pytest.raises(bfi.BfiError):
             bfi.bfi_adaptive_decide(bfi.lattice(2, 2), sv, part, split, cfg)
+    cfg = bfi.adaptive_config()
+    cfg.holdout = 2
+    with pytest.raises(bfi.BfiError):
+        bfi.bfi_adaptive_decide(bfi.lattice(2, 2), sv, part, split, cfg)

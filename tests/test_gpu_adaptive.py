@@ -193,3 +193,48 @@ def test_adaptive_split_statistics_of_first_samples(bfi, ctx, prec):
         ref = oracle.finalize(nx, d, part.lo, part.hi, sums)
         assert abs(out["Z"] - ref["Z"]) <= 1e-6 * ref["Z"]
         assert np.all(np.abs(out["C"] - ref["C"]) <= 1e-6 * abs(ref["C"][0]))
+
+
+def test_adaptive_holdout_stop(bfi, ctx):
+    """holdout = 1: the stop is confirmed on the final leaves sampled afresh under
+    holdout_seed; the reported estimate is that pass's, so it replays on the oracle
+    with that seed over (offset 0, n) per leaf, and its error meets the target.
+    Every check's evaluations are charged to the budget."""
+    nx, nt, B, nu = 3, 2, 2.0, 0.7
+    lat = bfi.lattice(nx, nt, nu=nu)
+    cfg = bfi.adaptive_config(target_rel_err=3e-3, max_evals=1 << 26, n_min=1024,
+                              n_max=1 << 18, split_log2=2, max_rounds=60, refine_fraction=0.5,
+                              holdout=True)
+    out = bfi.bfi_integrate_adaptive(ctx, lat, "fp64", 11, -B, B, cfg)
+    assert out["status"] == "BFI_OK"
+    assert out["holdout_used"] and out["holdout_checks"] >= 1
+    assert out["holdout_seed"] == (11 + out["holdout_checks"] * 0x9E3779B97F4A7C15) % (1 << 64)
+    assert out["rel_err"] <= 3e-3 and out["holdout_rel_err"] == out["rel_err"]
+    part = out["partition"]
+    check_partition(part, nx * nt, B)
+    assert np.all(part.offset == 0)
+    assert out["evals"] >= out["holdout_checks"] * int(part.n.sum())
+    sums = oracle.sums(oracle.lattice(nx, nt, nu=nu), out["holdout_seed"], part.ids, part.lo,
+                       part.hi, part.n, part.offset)
+    ref = oracle.finalize(nx, nx * nt, part.lo, part.hi, sums)
+    assert abs(out["Z"] - ref["Z"]) <= 1e-6 * ref["Z"]
+    assert np.all(np.abs(out["C"] - ref["C"]) <= 1e-6 * abs(ref["C"][0]))
+    rel = np.max(ref["C_err"]) / abs(ref["C"][0])
+    assert out["rel_err"] == pytest.approx(rel, rel=1e-6)
+    # without the holdout the same run stops on its running estimate, earlier
+    cfg.holdout = 0
+    plain = bfi.bfi_integrate_adaptive(ctx, lat, "fp64", 11, -B, B, cfg)
+    assert plain["status"] == "BFI_OK" and not plain["holdout_used"]
+    assert plain["holdout_checks"] == 0 and plain["evals"] <= out["evals"]
+    assert plain["holdout_rel_err"] == 0.0
+
+
+def test_adaptive_holdout_over_budget(bfi, ctx):
+    """A holdout check that the budget cannot pay for ends the run with
+    BFI_EBUDGET and the running estimate."""
+    cfg = bfi.adaptive_config(target_rel_err=0.5, max_evals=(1 << 14) + 100, n_min=1 << 12,
+                              n_max=1 << 16, split_log2=2, max_rounds=10, holdout=True)
+    out = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(2, 2, D=1e30), "fp64", 1, -2.0, 2.0, cfg)
+    assert out["status"] == "BFI_EBUDGET"
+    assert not out["holdout_used"] and out["holdout_checks"] == 0
+    assert out["evals"] == 1 << 14
