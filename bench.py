@@ -361,7 +361,7 @@ def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1803_07560_amd", "csrc")
-    for name in ("shape_kernels.hip", "device.hpp", "internal.h"):
+    for name in ("shape_kernels.hip", "device.hpp", "exp64.hpp", "internal.h"):
         h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()
 

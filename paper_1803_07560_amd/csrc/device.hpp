@@ -12,6 +12,24 @@
 
 namespace bfi {
 namespace dev {
+// v_fma_f64 with all three sources in VGPRs.  Left to itself the compiler keeps
+// loop-invariant polynomial coefficients in VGPRs and then rewrites each step as
+// a register copy plus the two-address v_fmac_f64, one extra instruction per step.
+__device__ __forceinline__ double fma_vop3(double a, double b, double c)
+{
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+}  // namespace dev
+}  // namespace bfi
+
+#define BFI_HD __device__
+#define BFI_POLY_FMA(a, b, c) ::bfi::dev::fma_vop3(a, b, c)
+#include "exp64.hpp"
+
+namespace bfi {
+namespace dev {
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): round multipliers and the
 // Weyl increments of the key schedule.

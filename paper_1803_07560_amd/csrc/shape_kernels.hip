@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(BLOCK)
                 }
                 double w, v[NR];
                 if constexpr (PREC == kFP64) {
-                    const double wa = exp(-sa), wbt = exp(-sb);
+                    const double wa = exp_weight(-sa), wbt = exp_weight(-sb);
                     w = 0.5 * (wa + wbt);
                     const double ta = psa * wa, tb = psb * wbt;
 #pragma unroll
@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(BLOCK)
 
             double w;
             if constexpr (PREC == kFP64) {
-                w = exp(-S);
+                w = exp_weight(-S);
                 const double t = pr_scale * w;
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
