@@ -12,20 +12,35 @@
 
 namespace bfi {
 namespace dev {
-// v_fma_f64 with all three sources in VGPRs.  Left to itself the compiler keeps
-// loop-invariant polynomial coefficients in VGPRs and then rewrites each step as
-// a register copy plus the two-address v_fmac_f64, one extra instruction per step.
-__device__ __forceinline__ double fma_vop3(double a, double b, double c)
-{
-    double d;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-    return d;
-}
+// Polynomial steps of the FP64 weight's exponential as one three-operand
+// v_fma_f64 each.  Left to itself the compiler keeps the loop-invariant
+// coefficients in VGPRs and rewrites every step as a register copy plus the
+// two-address v_fmac_f64, one more vector instruction per step.
+//   FmaVgprCoef: the coefficient (the addend) stays in a VGPR pair -- the faster
+//     choice where registers are to spare (d <= 32);
+//   FmaSgprCoef: scalar moves rematerialize it in an SGPR pair before each step,
+//     which holds no VGPRs (the 16x4 kernels then do not spill) at the cost of
+//     those scalar moves.
+struct FmaVgprCoef {
+    __device__ static double step(double a, double b, double c)
+    {
+        double d;
+        asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+        return d;
+    }
+};
+struct FmaSgprCoef {
+    __device__ static double step(double a, double b, double c)
+    {
+        double d;
+        asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+        return d;
+    }
+};
 }  // namespace dev
 }  // namespace bfi
 
 #define BFI_HD __device__
-#define BFI_POLY_FMA(a, b, c) ::bfi::dev::fma_vop3(a, b, c)
 #include "exp64.hpp"
 
 namespace bfi {

@@ -17,10 +17,6 @@
 #ifndef BFI_HD
 #define BFI_HD
 #endif
-// fused multiply-add of the polynomial steps (the includer may pin its encoding)
-#ifndef BFI_POLY_FMA
-#define BFI_POLY_FMA(a, b, c) __builtin_fma(a, b, c)
-#endif
 
 namespace bfi {
 namespace expk {
@@ -35,6 +31,13 @@ constexpr double kInvFact[12] = {
     0x1.27e4fb7789f5cp-22, 0x1.ae64567f544e4p-26, 0x1.1eed8eff8d898p-29, 0x1.6124613a86d09p-33};
 }  // namespace expk
 
+// The fused multiply-add of the polynomial steps; a caller may pass its own
+// (same arithmetic, another encoding), as the GPU kernels do.
+struct BuiltinFma {
+    BFI_HD static double step(double a, double b, double c) { return __builtin_fma(a, b, c); }
+};
+
+template <class Fma = BuiltinFma>
 BFI_HD inline double exp_weight(double x)
 {
     x = x < -746.0 ? -746.0 : x;
@@ -43,9 +46,9 @@ BFI_HD inline double exp_weight(double x)
     r = __builtin_fma(-k, expk::kLn2Lo, r);
     double p = expk::kInvFact[11];
     for (int j = 10; j >= 0; --j)
-        p = BFI_POLY_FMA(p, r, expk::kInvFact[j]);
-    p = BFI_POLY_FMA(p, r, 1.0);
-    p = BFI_POLY_FMA(p, r, 1.0);
+        p = Fma::step(p, r, expk::kInvFact[j]);
+    p = Fma::step(p, r, 1.0);
+    p = Fma::step(p, r, 1.0);
     return __builtin_ldexp(p, static_cast<int>(k));
 }
 }  // namespace bfi

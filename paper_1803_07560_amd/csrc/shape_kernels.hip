@@ -96,6 +96,8 @@ __global__ void __launch_bounds__(BLOCK)
     // m: accumulate half the terms and double (exactly) at the end
     constexpr bool kHalfPair = AVG && NX % 2 == 0 && NX > 1;
     const T inv_sites = T(1) / T(D);
+    // register class of the exponential's polynomial coefficients (FP64 weights)
+    using ExpFma = std::conditional_t<(D > 32), dev::FmaSgprCoef, dev::FmaVgprCoef>;
     static_assert(!SPLIT || D <= 32, "split statistics keep one bit per dimension in 32 bits");
     static_assert(!PAIR || (!SPLIT && D <= kMaxPairD), "antithetic pairs: d <= 32, no split");
 
@@ -272,7 +274,7 @@ __global__ void __launch_bounds__(BLOCK)
                 }
                 double w, v[NR];
                 if constexpr (PREC == kFP64) {
-                    const double wa = exp_weight(-sa), wbt = exp_weight(-sb);
+                    const double wa = exp_weight<ExpFma>(-sa), wbt = exp_weight<ExpFma>(-sb);
                     w = 0.5 * (wa + wbt);
                     const double ta = psa * wa, tb = psb * wbt;
 #pragma unroll
@@ -416,7 +418,7 @@ __global__ void __launch_bounds__(BLOCK)
 
             double w;
             if constexpr (PREC == kFP64) {
-                w = exp_weight(-S);
+                w = exp_weight<ExpFma>(-S);
                 const double t = pr_scale * w;
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
