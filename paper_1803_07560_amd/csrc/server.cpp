@@ -271,10 +271,20 @@ void complete(bfi_server *srv)
             finish(srv, r, State::Failed, BFI_EDEVICE, hipGetErrorString(e));
             continue;
         }
+        // records that overflowed (an action beyond the range of the precision:
+        // every subvolume has samples, so even the shift is finite in a sound
+        // record) fail this request only
+        bool finite = true;
+        for (size_t i = 0; i < sub.size() && finite; ++i)
+            finite = std::isfinite(sub[i]);
+        if (!finite) {
+            finish(srv, r, State::Failed, BFI_EDEVICE, "non-finite sums");
+            continue;
+        }
         bfi_status s = finalize_records(r->nx, r->d, r->subs.size(), r->subs.lo.data(),
                                         r->subs.hi.data(), sub.data(), &r->result,
                                         r->req.lat.antithetic ? 2 : 1);
-        bool finite = std::isfinite(r->result.log_Z);
+        finite = std::isfinite(r->result.log_Z);
         for (int k = 0; k < r->nx; ++k)
             finite = finite && std::isfinite(r->result.C[k]);
         if (s != BFI_OK)

@@ -135,6 +135,33 @@ def test_cancel_running_request(bfi, server):
     assert bfi.bfi_server_wait(server, t2, 60.0) is not None
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_nonfinite_request_is_isolated(bfi, ctx, server, prec):
+    """A request whose sums come out non-finite (a box of 1e200, where the action
+    overflows) fails alone with BFI_EDEVICE; requests served beside it are
+    bit-identical to their results alone, and the server keeps serving."""
+    good = [req(bfi, 4, 2, 0.5, "fp64", 3, 4.0, 3, 1 << 18),
+            req(bfi, 10, 2, 1.0, "fp32", 4, 4.0, 4, 1 << 20)]
+    alone = []
+    for r in good:
+        srv = bfi.bfi_server_create(ctx, bfi.server_config(memory_budget=1 << 30))
+        try:
+            alone.append(bfi.bfi_server_wait(srv, bfi.bfi_server_submit(srv, r), 60.0)[0])
+        finally:
+            bfi.bfi_server_destroy(srv)
+    bad = bfi.bfi_server_submit(server, req(bfi, 4, 2, 0.5, prec, 5, 1e200, 3, 1 << 18))
+    tickets = [bfi.bfi_server_submit(server, r) for r in good]
+    with pytest.raises(bfi.BfiError) as e:
+        bfi.bfi_server_wait(server, bad, 60.0)
+    assert e.value.name == "BFI_EDEVICE"
+    for t, ref in zip(tickets, alone):
+        res = bfi.bfi_server_wait(server, t, 60.0)[0]
+        assert res["Z"] == ref["Z"]
+        assert np.array_equal(res["C"], ref["C"])
+    t = bfi.bfi_server_submit(server, good[0])
+    assert bfi.bfi_server_wait(server, t, 60.0)[0]["Z"] == alone[0]["Z"]
+
+
 def test_invalid_requests(bfi, server):
     with pytest.raises(bfi.BfiError) as e:
         bfi.bfi_server_submit(server, req(bfi, 7, 7, 1.0, "fp64", 1, 4.0, 2, 4096))
