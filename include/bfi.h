@@ -478,7 +478,11 @@ bfi_status bfi_server_create(bfi_context *ctx, const bfi_server_config *cfg, bfi
 /* Non-blocking.  Errors: EINVAL, EUNSUPPORTED, EBUSY (pending queue full). */
 bfi_status bfi_server_submit(bfi_server *srv, const bfi_request *req, uint64_t *ticket);
 /* *done = 1 when finished; then out holds the result and the ticket is released.
- * latency_s (optional) gets submit-to-completion seconds. */
+ * latency_s (optional) gets submit-to-completion seconds.  A finished request
+ * that failed returns its own status (with *done = 1) and releases the ticket,
+ * e.g. ECANCELLED after bfi_server_cancel, EDEVICE when a HIP call failed or its
+ * sums came out non-finite (an action beyond the range of the precision).  A
+ * failed request affects no other. */
 bfi_status bfi_server_poll(bfi_server *srv, uint64_t ticket, bfi_result *out, int32_t *done,
                            double *latency_s);
 /* Blocks until done or timeout_s elapses (*done = 0). */
