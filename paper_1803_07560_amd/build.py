@@ -81,7 +81,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.replace(MICROBENCH + ".tmp", MICROBENCH)
     objs = [t[t.index("-o") + 1] for t in tasks]
     _run([cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", LIB + ".tmp", *objs,
-          "-lpthread"], verbose)
+          "-lrocprofiler-sdk-roctx", "-lpthread"], verbose)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

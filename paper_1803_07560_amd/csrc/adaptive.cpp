@@ -302,6 +302,7 @@ bfi_status eval_list(bfi_context *ctx, const bfi_lattice &lat, int prec, uint64_
     std::vector<int> first, second;
     record_fields(lat.nx, &first, &second);
     if (with.size() > 0) {
+        TraceRange tr("adaptive: samples with split statistics");
         std::vector<double> r(with.size() * rec_len), sp(with.size() * split_len);
         bfi_subvolumes v = with.view();
         BFI_TRY(bfi_eval(ctx, &lat, static_cast<bfi_precision>(prec), seed, &v, launch, r.data(),
@@ -314,6 +315,7 @@ bfi_status eval_list(bfi_context *ctx, const bfi_lattice &lat, int prec, uint64_
         }
     }
     if (without.size() > 0) {
+        TraceRange tr("adaptive: samples through the plain kernel");
         std::vector<double> r(without.size() * rec_len);
         bfi_subvolumes v = without.view();
         BFI_TRY(bfi_eval(ctx, &lat, static_cast<bfi_precision>(prec), seed, &v, launch, r.data(),
@@ -336,6 +338,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                                   uint64_t *leaf_offset, size_t cap, size_t *n_leaves)
 {
     return guarded([&]() -> bfi_status {
+        TraceRange trace("bfi_integrate_adaptive");
         if (!ctx || !box_lo || !box_hi || !out)
             return fail(BFI_EINVAL, "arguments must be non-NULL");
         if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
@@ -384,10 +387,12 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         bfi_result res{};
         std::vector<LeafAnalysis> an;
         for (;;) {
+            TracePhases phase("adaptive: analyse");
             BFI_TRY(analyse(nx, d, L.size(), L.lo.data(), L.hi.data(), L.rec.data(), &an, &res));
             if (rel_err(res) <= run_target && res.ess >= min_ess) {
                 if (!cfg->holdout)
                     break;
+                phase.next("adaptive: holdout pass");
                 // holdout check: the same leaves, samples drawn afresh under a
                 // seed of their own, so no refinement decision has seen them
                 uint64_t cost = 0;
@@ -429,6 +434,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                 status = BFI_EBUDGET;
                 break;
             }
+            phase.next("adaptive: decide and plan");
             const SplitStats st{d, rec_len, L.split.data(), L.base.data()};
             std::vector<int32_t> action(L.size());
             std::vector<size_t> order;
@@ -548,11 +554,13 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                     origin.push_back({s, 1 + half});
                 }
             }
+            phase.next("adaptive: evaluate");
             std::vector<double> wrec, wsplit, wbase;
             BFI_TRY(eval_list(ctx, *lat, prec, seed, work, cfg->split_samples, launch, &wrec,
                               &wsplit, &wbase));
             evals += cost;
 
+            phase.next("adaptive: fold");
             // fold the results into the leaf set in place: a doubled leaf merges
             // its continuation, a split leaf becomes its lower child and its upper
             // child is appended (work proportional to the round's work list)

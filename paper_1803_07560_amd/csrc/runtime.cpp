@@ -709,6 +709,7 @@ bfi_status bfi_plan_create(bfi_context *ctx, const bfi_lattice *lat, bfi_precisi
                            const bfi_subvolumes *subs, const bfi_launch *launch, bfi_plan **out)
 {
     return guarded([&]() -> bfi_status {
+        TraceRange trace("bfi_plan_create");
         if (!ctx || !out)
             return fail(BFI_EINVAL, "context and out must be non-NULL");
         if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
@@ -724,6 +725,7 @@ bfi_status bfi_plan_create(bfi_context *ctx, const bfi_lattice *lat, bfi_precisi
 bfi_status bfi_plan_run(bfi_plan *p, uint64_t seed, double *partials_dev, void *stream)
 {
     return guarded([&]() -> bfi_status {
+        TraceRange trace("bfi_plan_run");
         if (!p)
             return fail(BFI_EINVAL, "plan is NULL");
         BFI_HIP(hipSetDevice(p->ctx->device));
@@ -848,6 +850,7 @@ bfi_status bfi_eval(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec
                     double *split)
 {
     return guarded([&]() -> bfi_status {
+        TraceRange trace("bfi_eval");
         if (!ctx || !partials)
             return fail(BFI_EINVAL, "context and partials must be non-NULL");
         if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
@@ -860,8 +863,11 @@ bfi_status bfi_eval(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec
             return BFI_OK;
         BFI_HIP(hipSetDevice(ctx->device));
         bfi_plan *p = nullptr;
-        BFI_TRY(plan_build(ctx, *lat, prec, SubList::copy_of(*subs, lat->nx * lat->nt), launch,
-                           split != nullptr, &p));
+        {
+            TraceRange tb("bfi_eval: plan build and upload");
+            BFI_TRY(plan_build(ctx, *lat, prec, SubList::copy_of(*subs, lat->nx * lat->nt), launch,
+                               split != nullptr, &p));
+        }
         bfi_launch l = p->launch;
         l.use_graph = 0;
         p->launch = l;
@@ -904,6 +910,7 @@ bfi_status bfi_integrate(bfi_context *ctx, const bfi_lattice *lat, bfi_precision
                          bfi_result *out)
 {
     return guarded([&]() -> bfi_status {
+        TraceRange trace("bfi_integrate");
         if (!ctx || !box_lo || !box_hi || !out)
             return fail(BFI_EINVAL, "arguments must be non-NULL");
         BFI_TRY(check_lattice(lat));

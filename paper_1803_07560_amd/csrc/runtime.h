@@ -13,6 +13,8 @@
 #include <tuple>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "bfi.h"
 #include "internal.h"
 #include "is_internal.h"
@@ -93,6 +95,28 @@ bfi_status guarded(F &&body) noexcept
         return fail(BFI_EINVAL, "unexpected exception");
     }
 }
+
+// A named range of host work on the calling thread, visible to rocprofv3
+// --marker-trace (roctx); without a tool attached the calls return at once.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
+// Consecutive phases of one loop body: next() closes the current range and
+// opens the following one; leaving the scope closes the last.
+struct TracePhases {
+    explicit TracePhases(const char *first) { roctxRangePushA(first); }
+    void next(const char *name)
+    {
+        roctxRangePop();
+        roctxRangePushA(name);
+    }
+    ~TracePhases() { roctxRangePop(); }
+    TracePhases(const TracePhases &) = delete;
+    TracePhases &operator=(const TracePhases &) = delete;
+};
 
 // Resolve a requested launch (zeros = tuned or default) for a lattice.
 bfi_launch resolve_launch(const bfi_context *ctx, const bfi_lattice &lat, int prec, bool split,

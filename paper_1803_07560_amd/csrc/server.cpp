@@ -253,6 +253,7 @@ void complete(bfi_server *srv)
             keep.push_back(t);
             continue;
         }
+        TraceRange trace("server: merge and finalize a request");
         MergeArgs m{};
         m.item_rec = r->d_item_rec;
         m.sub_first = r->d_sub_first;
@@ -366,6 +367,7 @@ bfi_status run_step(bfi_server *srv, const std::vector<StepEntry> &entries)
 void worker_loop(bfi_server *srv)
 {
     (void)hipSetDevice(srv->ctx->device);
+    roctxNameOsThread("bfi server worker");
     std::unique_lock<std::mutex> lk(srv->mu);
     for (;;) {
         admit(srv);
@@ -407,7 +409,10 @@ void worker_loop(bfi_server *srv)
         lk.unlock();
         const auto t0 = Clock::now();
         // a failed step (an exception included) fails its requests, not the server
-        bfi_status s = guarded([&]() -> bfi_status { return run_step(srv, entries); });
+        bfi_status s = guarded([&]() -> bfi_status {
+            TraceRange trace("server: step");
+            return run_step(srv, entries);
+        });
         const auto t1 = Clock::now();
         std::string msg = s == BFI_OK ? "" : bfi_last_error();
         lk.lock();

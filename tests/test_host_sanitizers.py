@@ -45,7 +45,8 @@ def test_host_entry_points_under_asan_ubsan(tmp_path):
                         drv], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     exe = str(tmp_path / "driver")
-    r = subprocess.run([hipcc, "-o", exe, drv, *objs, *device, *HOST_SAN, "-lpthread"],
+    r = subprocess.run([hipcc, "-o", exe, drv, *objs, *device, *HOST_SAN,
+                        "-lrocprofiler-sdk-roctx", "-lpthread"],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1",
