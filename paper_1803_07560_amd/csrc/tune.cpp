@@ -1,6 +1,6 @@
 // Launch-shape autotuner and its JSON cache.
 //
-// Candidates: samples_per_thread K in {16, 32, 64, 128, 256} x block in
+// Candidates: samples_per_thread K in {16, 32, ..., 1024} x block in
 // {64, 128, 256} x {one block per item, persistent queue}.  Each candidate runs
 // a resident plan over a uniform partition of [-4, 4]^d (1024 subvolumes, or
 // fewer for tiny budgets) once to warm up and three times under HIP events on
@@ -84,7 +84,7 @@ bfi_status bfi_autotune(bfi_context *ctx, const bfi_lattice *lat, bfi_precision 
         std::vector<double> lo(d, -4.0), hi(d, 4.0);
         SubList subs = uniform_split(d, lo.data(), hi.data(), std::max(k, 0), evals_per_trial);
 
-        const int Ks[] = {16, 32, 64, 128, 256};
+        const int Ks[] = {16, 32, 64, 128, 256, 512, 1024};
         const int blocks[] = {64, 128, 256};
         bfi_launch top{};
         double top_rate = -1.0;
