@@ -456,6 +456,11 @@ typedef struct {
     uint64_t step_evals;        /* target evaluations per step, shared equally by the
                                    active requests (0: 2^25); bounds the wait of a
                                    newly admitted request for the running step */
+    int32_t max_samples_per_thread; /* cap on the tuned samples per thread of served
+                                   work items (0: 128).  An item is the unit of a
+                                   request's progress: small items spread a small
+                                   request over many blocks, which keeps its latency
+                                   low, where batch runs prefer large ones */
 } bfi_server_config;
 
 typedef struct {
@@ -492,10 +497,12 @@ bfi_status bfi_server_cancel(bfi_server *srv, uint64_t ticket);
 bfi_status bfi_server_stats_get(bfi_server *srv, bfi_server_stats *out);
 bfi_status bfi_server_destroy(bfi_server *srv);
 
-/* Autotuner: time candidate launch shapes (samples_per_thread x block x
- * persistent) on a synthetic uniform partition of the lattice with about
- * `evals_per_trial` samples, keep the fastest for (shape, precision) in the
- * context, and return it with its rate.  Blocking. */
+/* Autotuner: time candidate launch shapes (samples_per_thread in 16..1024 x
+ * block x persistent) on a synthetic uniform partition of the lattice with about
+ * `evals_per_trial` evaluations, keep the fastest for (shape, precision, single
+ * points or antithetic pairs -- lat->antithetic) in the context, and return it
+ * with its rate.  Pair plans without an entry of their own use the single-point
+ * one.  Blocking. */
 bfi_status bfi_autotune(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
                         uint64_t evals_per_trial, bfi_launch *best, double *best_evals_per_s);
 /* Save / load the context's tuned table as JSON (keyed by device architecture;

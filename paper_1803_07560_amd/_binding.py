@@ -88,7 +88,7 @@ class bfi_adaptive_stats(C.Structure):
 class bfi_server_config(C.Structure):
     _fields_ = [("memory_budget", C.c_uint64), ("max_requests", C.c_int32),
                 ("chunks_per_step", C.c_int32), ("max_pending", C.c_int32),
-                ("step_evals", C.c_uint64)]
+                ("step_evals", C.c_uint64), ("max_samples_per_thread", C.c_int32)]
 
 
 class bfi_request(C.Structure):
@@ -561,9 +561,10 @@ def bfi_debug_is_points(ctx, lat, prec, seed, box_lo, box_hi, stream, index):
 
 
 def server_config(memory_budget=1 << 30, max_requests=256, chunks_per_step=4,
-                  max_pending=100000, step_evals=1 << 25) -> bfi_server_config:
+                  max_pending=100000, step_evals=1 << 25,
+                  max_samples_per_thread=0) -> bfi_server_config:
     return bfi_server_config(int(memory_budget), int(max_requests), int(chunks_per_step),
-                             int(max_pending), int(step_evals))
+                             int(max_pending), int(step_evals), int(max_samples_per_thread))
 
 
 def request(lat, prec, seed, box, split_log2, budget) -> bfi_request:

@@ -241,7 +241,10 @@ bfi_launch resolve_launch(const bfi_context *ctx, const bfi_lattice &lat, int pr
     // defaults: 256-thread blocks, 64 samples per thread, persistent queue
     bfi_launch l{64, 256, 1, 0};
     if (ctx) {
-        auto it = ctx->tuned.find(TuneKey{lat.nx, lat.nt, prec});
+        // the pair kernel's own entry, else the single-point one
+        auto it = ctx->tuned.find(TuneKey{lat.nx, lat.nt, prec, lat.antithetic ? 1 : 0});
+        if (it == ctx->tuned.end())
+            it = ctx->tuned.find(TuneKey{lat.nx, lat.nt, prec, 0});
         if (it != ctx->tuned.end())
             l = it->second.launch;
     }
@@ -417,8 +420,28 @@ bfi_status plan_build_core(bfi_context *ctx, int kind, const bfi_lattice &lat, i
         return fail(BFI_EINVAL, "empty subvolume list");
     if (subs.size() > 0xFFFFFFFFull)
         return fail(BFI_EINVAL, "too many subvolumes");
-    bfi_launch l = kind != 1 ? resolve_launch(ctx, lat, prec, split, launch)
-                             : resolve_launch(nullptr, lat, prec, true, launch);
+    // the tuned table holds mc_kernel shapes; the Gaussian-proposal sampler's
+    // kernel (more work per sample) keeps 256 samples per thread and 256-thread
+    // persistent blocks unless the caller asks otherwise
+    bfi_launch l;
+    if (kind == 0) {
+        l = resolve_launch(ctx, lat, prec, split, launch);
+    } else if (kind == 2) {
+        const bfi_launch dflt{256, 256, 1, 0};
+        bfi_launch want = dflt;
+        if (launch) {
+            if (launch->samples_per_thread > 0)
+                want.samples_per_thread = launch->samples_per_thread;
+            if (launch->block > 0)
+                want.block = launch->block;
+            if (launch->persistent >= 0)
+                want.persistent = launch->persistent != 0;
+            want.use_graph = launch->use_graph != 0;
+        }
+        l = resolve_launch(nullptr, lat, prec, split, &want);
+    } else {
+        l = resolve_launch(nullptr, lat, prec, true, launch);
+    }
     if (l.block != 64 && l.block != 128 && l.block != 256)
         return fail(BFI_EINVAL, "block must be 64, 128 or 256 (got %d)", l.block);
     if (l.samples_per_thread < 1 || l.samples_per_thread > (1 << 20))

@@ -70,9 +70,10 @@ SubList uniform_split(int d, const double *box_lo, const double *box_hi, int k, 
 
 struct TuneKey {
     int nx, nt, prec;
+    int pairs = 0;  // antithetic pairs: a kernel of its own, tuned apart
     bool operator<(const TuneKey &o) const
     {
-        return std::tie(nx, nt, prec) < std::tie(o.nx, o.nt, o.prec);
+        return std::tie(nx, nt, prec, pairs) < std::tie(o.nx, o.nt, o.prec, o.pairs);
     }
 };
 struct TuneEntry {

@@ -133,6 +133,8 @@ bfi_status shape_launch(bfi_server *srv, const bfi_lattice &lat, int prec, bfi_l
     auto it = srv->shapes.find(key);
     if (it == srv->shapes.end()) {
         bfi_launch r = resolve_launch(srv->ctx, lat, prec, false, nullptr);
+        const int cap = srv->cfg.max_samples_per_thread > 0 ? srv->cfg.max_samples_per_thread : 128;
+        r.samples_per_thread = std::min(r.samples_per_thread, cap);
         r.persistent = 1;
         r.use_graph = 0;
         KernelInfo info{};
@@ -484,7 +486,8 @@ bfi_status bfi_server_create(bfi_context *ctx, const bfi_server_config *cfg, bfi
         if (!ctx || !cfg || !out)
             return fail(BFI_EINVAL, "arguments must be non-NULL");
         if (cfg->max_requests < 1 || cfg->chunks_per_step < 1 || cfg->max_pending < 0 ||
-            cfg->memory_budget == 0)
+            cfg->memory_budget == 0 || cfg->max_samples_per_thread < 0 ||
+            cfg->max_samples_per_thread > (1 << 20))
             return fail(BFI_EINVAL, "bad server configuration");
         BFI_HIP(hipSetDevice(ctx->device));
         auto srv = std::make_unique<bfi_server>();

@@ -4,7 +4,9 @@
 // {64, 128, 256} x {one block per item, persistent queue}.  Each candidate runs
 // a resident plan over a uniform partition of [-4, 4]^d (1024 subvolumes, or
 // fewer for tiny budgets) once to warm up and three times under HIP events on
-// the context's stream; the fastest rate is kept for (nx, nt, precision).
+// the context's stream; the fastest rate is kept for (nx, nt, precision, single
+// points or antithetic pairs).  Pair plans fall back to the single-point entry
+// when their own is missing.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -74,15 +76,15 @@ bfi_status bfi_autotune(bfi_context *ctx, const bfi_lattice *lat, bfi_precision 
         if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
             return fail(BFI_EINVAL, "unknown precision");
         BFI_TRY(check_lattice(lat));
-        if (lat->antithetic)
-            return fail(BFI_EUNSUPPORTED, "launch shapes are tuned on single points");
         if (evals_per_trial < (uint64_t(1) << 16))
             return fail(BFI_EINVAL, "evals_per_trial must be at least 2^16");
         BFI_HIP(hipSetDevice(ctx->device));
         const int d = lat->nx * lat->nt;
         const int k = static_cast<int>(std::min<uint64_t>(10, std::log2(evals_per_trial / 1024.0)));
         std::vector<double> lo(d, -4.0), hi(d, 4.0);
-        SubList subs = uniform_split(d, lo.data(), hi.data(), std::max(k, 0), evals_per_trial);
+        // antithetic pairs: two evaluations per sample index
+        SubList subs = uniform_split(d, lo.data(), hi.data(), std::max(k, 0),
+                                     lat->antithetic ? evals_per_trial / 2 : evals_per_trial);
 
         const int Ks[] = {16, 32, 64, 128, 256, 512, 1024};
         const int blocks[] = {64, 128, 256};
@@ -104,7 +106,8 @@ bfi_status bfi_autotune(bfi_context *ctx, const bfi_lattice *lat, bfi_precision 
                 }
         if (top_rate <= 0)
             return fail(BFI_EDEVICE, "no launch shape could be timed");
-        ctx->tuned[TuneKey{lat->nx, lat->nt, prec}] = TuneEntry{top, top_rate};
+        ctx->tuned[TuneKey{lat->nx, lat->nt, prec, lat->antithetic ? 1 : 0}] =
+            TuneEntry{top, top_rate};
         if (best)
             *best = top;
         if (best_evals_per_s)
@@ -128,10 +131,12 @@ bfi_status bfi_tune_save(const bfi_context *ctx, const char *path)
             firstEntry = false;
             char line[256];
             std::snprintf(line, sizeof(line),
-                          "    {\"nx\": %d, \"nt\": %d, \"prec\": %d, \"samples_per_thread\": %d, "
-                          "\"block\": %d, \"persistent\": %d, \"evals_per_s\": %.6e}",
-                          kv.first.nx, kv.first.nt, kv.first.prec, kv.second.launch.samples_per_thread,
-                          kv.second.launch.block, kv.second.launch.persistent, kv.second.evals_per_s);
+                          "    {\"nx\": %d, \"nt\": %d, \"prec\": %d, \"pairs\": %d, "
+                          "\"samples_per_thread\": %d, \"block\": %d, \"persistent\": %d, "
+                          "\"evals_per_s\": %.6e}",
+                          kv.first.nx, kv.first.nt, kv.first.prec, kv.first.pairs,
+                          kv.second.launch.samples_per_thread, kv.second.launch.block,
+                          kv.second.launch.persistent, kv.second.evals_per_s);
             f << line;
         }
         f << "\n  ]\n}\n";
@@ -178,16 +183,20 @@ bfi_status bfi_tune_load(bfi_context *ctx, const char *path)
             if (o == std::string::npos || c == std::string::npos)
                 break;
             const std::string obj = txt.substr(o, c - o + 1);
-            double nx, nt, prec, K, block, pers, rate;
+            double nx, nt, prec, K, block, pers, rate, pairs = 0;
+            if (!field(obj, "pairs", &pairs))
+                pairs = 0;  // entries written before pairs were tuned apart
             if (field(obj, "nx", &nx) && field(obj, "nt", &nt) && field(obj, "prec", &prec) &&
                 field(obj, "samples_per_thread", &K) && field(obj, "block", &block) &&
                 field(obj, "persistent", &pers) && field(obj, "evals_per_s", &rate)) {
                 const int b = static_cast<int>(block);
                 if (shape_compiled(static_cast<int>(nx), static_cast<int>(nt)) && K >= 1 &&
-                    (b == 64 || b == 128 || b == 256) && (prec == 0 || prec == 1)) {
+                    K <= (1 << 20) && (b == 64 || b == 128 || b == 256) &&
+                    (prec == 0 || prec == 1) && (pairs == 0 || pairs == 1)) {
                     bfi_launch l{static_cast<int32_t>(K), b, pers != 0 ? 1 : 0, 0};
                     ctx->tuned[TuneKey{static_cast<int>(nx), static_cast<int>(nt),
-                                       static_cast<int>(prec)}] = TuneEntry{l, rate};
+                                       static_cast<int>(prec), static_cast<int>(pairs)}] =
+                        TuneEntry{l, rate};
                 }
             }
             pos = c + 1;

@@ -8,6 +8,7 @@ oracle's on the same pairs; launch shapes, persistent and grid kernels, plans
 and graph replays agree bit for bit; the entry points without pair support
 refuse it.  Then what the pairs are for: the same error bar as single points
 at equal evaluations on the subvolumes of a partition."""
+import json
 import math
 
 import numpy as np
@@ -127,7 +128,6 @@ def test_unsupported_paths_refuse_pairs(bfi, ctx):
                                                                max_evals=1 << 16)),
         lambda: bfi.bfi_integrate_is(ctx, lat, F64, 1, -2.0, 2.0, 1 << 16, 0.9, 8),
         lambda: bfi.bfi_integrand_eval(ctx, bfi.integrand_burgers(lat), 1, sv),
-        lambda: bfi.bfi_autotune(ctx, lat, F64),
     ]
     for call in calls:
         with pytest.raises(bfi.BfiError) as e:
@@ -225,3 +225,39 @@ def test_served_pairs(bfi, ctx):
             bfi.bfi_server_destroy(alone_srv)
         assert alone["Z"] == mixed[i]["Z"] and np.array_equal(alone["C"], mixed[i]["C"]), i
         assert alone["n_evals"] == 1 << 18
+
+
+def test_pairs_tuned_apart(bfi, tmp_path):
+    """The pair kernel gets a tuning entry of its own (pairs = 1 in the saved
+    table), which a reload restores beside the single-point entry; a tuned pair
+    plan still matches the oracle.  Private contexts: the shared one keeps its
+    default launches."""
+    lat = bfi.lattice(4, 2, antithetic=True)
+    path = str(tmp_path / "tuned.json")
+    tctx = bfi.bfi_context_create(0)
+    try:
+        got = bfi.bfi_autotune(tctx, lat, F64, 1 << 18)
+        single = bfi.bfi_autotune(tctx, bfi.lattice(4, 2), F64, 1 << 18)
+        bfi.bfi_tune_save(tctx, path)
+    finally:
+        bfi.bfi_context_destroy(tctx)
+    assert got["samples_per_thread"] >= 16 and got["block"] in (64, 128, 256)
+    entries = json.load(open(path))["entries"]
+    mine = [e for e in entries if (e["nx"], e["nt"], e["prec"]) == (4, 2, 0)]
+    assert sorted(e["pairs"] for e in mine) == [0, 1]
+    pair = next(e for e in mine if e["pairs"] == 1)
+    assert (pair["samples_per_thread"], pair["block"]) == (got["samples_per_thread"], got["block"])
+    one = next(e for e in mine if e["pairs"] == 0)
+    assert (one["samples_per_thread"], one["block"]) == (single["samples_per_thread"],
+                                                          single["block"])
+    ctx2 = bfi.bfi_context_create(0)
+    try:
+        bfi.bfi_tune_load(ctx2, path)
+        sv = workloads.uniform_partition(8, 2.0, 3, per_sub=5000)
+        rec = bfi.bfi_eval(ctx2, lat, F64, 4, sv)
+        want = oracle.sums(oracle.lattice(4, 2, antithetic=1), 4, sv.ids, sv.lo, sv.hi, sv.n,
+                           sv.offset)
+        np.testing.assert_allclose(rec[:, 2:4] * np.exp(-np.array([[1, 2]]) * rec[:, 1:2]),
+                                   want[:, 1:3], rtol=1e-10)
+    finally:
+        bfi.bfi_context_destroy(ctx2)
