@@ -500,9 +500,10 @@ bfi_status bfi_server_destroy(bfi_server *srv);
 /* Autotuner: time candidate launch shapes (samples_per_thread in 16..1024 x
  * block x persistent) on a synthetic uniform partition of the lattice with about
  * `evals_per_trial` evaluations, keep the fastest for (shape, precision, single
- * points or antithetic pairs -- lat->antithetic) in the context, and return it
- * with its rate.  Pair plans without an entry of their own use the single-point
- * one.  Blocking. */
+ * points or antithetic pairs, observable -- lat->antithetic, lat->observable) in
+ * the context, and return it with its rate.  A plan without an entry of its own
+ * takes the anchored-product entry of its sampler, then the single-point one.
+ * Blocking. */
 bfi_status bfi_autotune(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
                         uint64_t evals_per_trial, bfi_launch *best, double *best_evals_per_s);
 /* Save / load the context's tuned table as JSON (keyed by device architecture;

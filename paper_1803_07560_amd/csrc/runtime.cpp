@@ -241,10 +241,14 @@ bfi_launch resolve_launch(const bfi_context *ctx, const bfi_lattice &lat, int pr
     // defaults: 256-thread blocks, 64 samples per thread, persistent queue
     bfi_launch l{64, 256, 1, 0};
     if (ctx) {
-        // the pair kernel's own entry, else the single-point one
-        auto it = ctx->tuned.find(TuneKey{lat.nx, lat.nt, prec, lat.antithetic ? 1 : 0});
+        // the kernel variant's own entry (pairs, observable), else the entry of
+        // the same sampler with the anchored product, else the single-point one
+        const int pairs = lat.antithetic ? 1 : 0;
+        auto it = ctx->tuned.find(TuneKey{lat.nx, lat.nt, prec, pairs, lat.observable});
         if (it == ctx->tuned.end())
-            it = ctx->tuned.find(TuneKey{lat.nx, lat.nt, prec, 0});
+            it = ctx->tuned.find(TuneKey{lat.nx, lat.nt, prec, pairs, 0});
+        if (it == ctx->tuned.end())
+            it = ctx->tuned.find(TuneKey{lat.nx, lat.nt, prec, 0, 0});
         if (it != ctx->tuned.end())
             l = it->second.launch;
     }

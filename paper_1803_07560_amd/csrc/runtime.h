@@ -71,9 +71,10 @@ SubList uniform_split(int d, const double *box_lo, const double *box_hi, int k, 
 struct TuneKey {
     int nx, nt, prec;
     int pairs = 0;  // antithetic pairs: a kernel of its own, tuned apart
+    int obs = 0;    // observable (anchored or averaged), likewise
     bool operator<(const TuneKey &o) const
     {
-        return std::tie(nx, nt, prec, pairs) < std::tie(o.nx, o.nt, o.prec, o.pairs);
+        return std::tie(nx, nt, prec, pairs, obs) < std::tie(o.nx, o.nt, o.prec, o.pairs, o.obs);
     }
 };
 struct TuneEntry {

@@ -5,8 +5,8 @@
 // a resident plan over a uniform partition of [-4, 4]^d (1024 subvolumes, or
 // fewer for tiny budgets) once to warm up and three times under HIP events on
 // the context's stream; the fastest rate is kept for (nx, nt, precision, single
-// points or antithetic pairs).  Pair plans fall back to the single-point entry
-// when their own is missing.
+// points or antithetic pairs, observable).  A plan without an entry of its own
+// takes its sampler's anchored-product entry, then the single-point one.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -106,7 +106,7 @@ bfi_status bfi_autotune(bfi_context *ctx, const bfi_lattice *lat, bfi_precision 
                 }
         if (top_rate <= 0)
             return fail(BFI_EDEVICE, "no launch shape could be timed");
-        ctx->tuned[TuneKey{lat->nx, lat->nt, prec, lat->antithetic ? 1 : 0}] =
+        ctx->tuned[TuneKey{lat->nx, lat->nt, prec, lat->antithetic ? 1 : 0, lat->observable}] =
             TuneEntry{top, top_rate};
         if (best)
             *best = top;
@@ -132,9 +132,9 @@ bfi_status bfi_tune_save(const bfi_context *ctx, const char *path)
             char line[256];
             std::snprintf(line, sizeof(line),
                           "    {\"nx\": %d, \"nt\": %d, \"prec\": %d, \"pairs\": %d, "
-                          "\"samples_per_thread\": %d, \"block\": %d, \"persistent\": %d, "
-                          "\"evals_per_s\": %.6e}",
-                          kv.first.nx, kv.first.nt, kv.first.prec, kv.first.pairs,
+                          "\"observable\": %d, \"samples_per_thread\": %d, \"block\": %d, "
+                          "\"persistent\": %d, \"evals_per_s\": %.6e}",
+                          kv.first.nx, kv.first.nt, kv.first.prec, kv.first.pairs, kv.first.obs,
                           kv.second.launch.samples_per_thread, kv.second.launch.block,
                           kv.second.launch.persistent, kv.second.evals_per_s);
             f << line;
@@ -183,19 +183,23 @@ bfi_status bfi_tune_load(bfi_context *ctx, const char *path)
             if (o == std::string::npos || c == std::string::npos)
                 break;
             const std::string obj = txt.substr(o, c - o + 1);
-            double nx, nt, prec, K, block, pers, rate, pairs = 0;
+            double nx, nt, prec, K, block, pers, rate, pairs = 0, obs = 0;
             if (!field(obj, "pairs", &pairs))
                 pairs = 0;  // entries written before pairs were tuned apart
+            if (!field(obj, "observable", &obs))
+                obs = 0;
             if (field(obj, "nx", &nx) && field(obj, "nt", &nt) && field(obj, "prec", &prec) &&
                 field(obj, "samples_per_thread", &K) && field(obj, "block", &block) &&
                 field(obj, "persistent", &pers) && field(obj, "evals_per_s", &rate)) {
                 const int b = static_cast<int>(block);
                 if (shape_compiled(static_cast<int>(nx), static_cast<int>(nt)) && K >= 1 &&
                     K <= (1 << 20) && (b == 64 || b == 128 || b == 256) &&
-                    (prec == 0 || prec == 1) && (pairs == 0 || pairs == 1)) {
+                    (prec == 0 || prec == 1) && (pairs == 0 || pairs == 1) &&
+                    (obs == 0 || obs == 1)) {
                     bfi_launch l{static_cast<int32_t>(K), b, pers != 0 ? 1 : 0, 0};
                     ctx->tuned[TuneKey{static_cast<int>(nx), static_cast<int>(nt),
-                                       static_cast<int>(prec), static_cast<int>(pairs)}] =
+                                       static_cast<int>(prec), static_cast<int>(pairs),
+                                       static_cast<int>(obs)}] =
                         TuneEntry{l, rate};
                 }
             }
