@@ -261,3 +261,38 @@ def test_pairs_tuned_apart(bfi, tmp_path):
                                    want[:, 1:3], rtol=1e-10)
     finally:
         bfi.bfi_context_destroy(ctx2)
+
+
+def test_launch_table_lookup_order(bfi, ctx, tmp_path):
+    """A plan takes the table entry of its own kernel variant (pairs,
+    observable); without one, the entry of its sampler with the anchored
+    product; then the single-point entry.  Architecture as the context reports it,
+    read back from a table the context itself saved."""
+    arch_path = str(tmp_path / "arch.json")
+    bfi.bfi_tune_save(ctx, arch_path)
+    arch = json.load(open(arch_path))["arch"]
+    entries = [  # (pairs, observable) -> samples per thread; blocks distinct too
+        {"pairs": 0, "observable": 0, "samples_per_thread": 48, "block": 64},
+        {"pairs": 1, "observable": 0, "samples_per_thread": 80, "block": 128},
+        {"pairs": 0, "observable": 1, "samples_per_thread": 112, "block": 256},
+    ]
+    table = {"arch": arch, "entries": [
+        dict(nx=4, nt=2, prec=0, persistent=1, evals_per_s=1.0, **e) for e in entries]}
+    path = str(tmp_path / "table.json")
+    json.dump(table, open(path, "w"))
+    c = bfi.bfi_context_create(0)
+    try:
+        bfi.bfi_tune_load(c, path)
+        sv = workloads.uniform_partition(8, 2.0, 2, per_sub=4096)
+        want = {(False, "anchor"): (48, 64), (True, "anchor"): (80, 128),
+                (False, "averaged"): (112, 256), (True, "averaged"): (80, 128)}
+        for (pairs, obs), shape in want.items():
+            plan = bfi.bfi_plan_create(c, bfi.lattice(4, 2, observable=obs, antithetic=pairs),
+                                       F64, sv)
+            try:
+                info = bfi.bfi_plan_info(plan)
+            finally:
+                bfi.bfi_plan_destroy(plan)
+            assert (info["samples_per_thread"], info["block"]) == shape, (pairs, obs)
+    finally:
+        bfi.bfi_context_destroy(c)
