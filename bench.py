@@ -92,6 +92,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson serving run (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-max-samples-per-thread", type=int, default=0,
+                    help="cap on samples per thread of served items (0: the server's 128)")
     ap.add_argument("--adaptive-budget-log2", type=int, default=36,
                     help="evaluation budget of each adaptive 10x2 run (0 skips them)")
     ap.add_argument("--adaptive-target-budget-log2", type=int, default=40,
@@ -186,13 +188,14 @@ def run_form(bfi, torch, ctx, lat, sv, w, prec, steps, warmup, stream):
                                             "use_graph")}, "n_items": info["n_items"]}
 
 
-def serve_leg(bfi, ctx, seconds, rate, warmup_s=1.0):
+def serve_leg(bfi, ctx, seconds, rate, warmup_s=1.0, max_samples_per_thread=0):
     """Poisson arrivals of correlation requests (lattice uniform over 4x2, 8x2,
     10x2, 16x4; nu log-uniform in [0.05, 2]; budgets 2^U(16,26)); FP32 form.
     Latency is submit-to-result as timed by the server; requests arriving in the
     first `warmup_s` seconds are served but not counted."""
     reqs = workloads.serving_requests(rate, seconds, seed=1)
-    srv = bfi.bfi_server_create(ctx, bfi.server_config(memory_budget=8 << 30, max_requests=256))
+    srv = bfi.bfi_server_create(ctx, bfi.server_config(
+        memory_budget=8 << 30, max_requests=256, max_samples_per_thread=max_samples_per_thread))
     try:
         t0 = time.perf_counter()
         tickets = []
@@ -477,7 +480,8 @@ def main():
     if args.serve_seconds > 0:
         print(f"bench: serving {args.serve_seconds:g} s at {args.serve_rate:g} req/s",
               file=sys.stderr, flush=True)
-        serving = serve_leg(bfi, ctx, args.serve_seconds, args.serve_rate)
+        serving = serve_leg(bfi, ctx, args.serve_seconds, args.serve_rate,
+                            max_samples_per_thread=args.serve_max_samples_per_thread)
     bfi.bfi_context_destroy(ctx)
 
     head = forms[args.headline]
