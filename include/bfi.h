@@ -254,6 +254,18 @@ bfi_status bfi_integrate(bfi_context *ctx, const bfi_lattice *lat, bfi_precision
  * the final partition is written to the caller's arrays when non-NULL
  * (capacity `cap` leaves; *n_leaves gets the count).  Returns BFI_EBUDGET (with a
  * valid estimate) if the budget ran out first. */
+/* Progress of an adaptive run, reported once per round after the leaves are
+ * analysed and after every holdout pass (see bfi_adaptive_config.progress). */
+typedef struct {
+    int32_t round;           /* rounds completed */
+    int32_t holdout_checks;  /* holdout passes run so far */
+    uint64_t leaves;
+    uint64_t evals;          /* evaluations spent so far, holdout passes included */
+    double rel_err;          /* running max_r sigma_C(r)/|C(0)| */
+    double holdout_rel_err;  /* of the last holdout pass (0: none yet) */
+} bfi_adaptive_progress;
+typedef void (*bfi_adaptive_progress_fn)(const bfi_adaptive_progress *p, void *user);
+
 typedef struct {
     double target_rel_err;  /* on max_r sigma_C(r) / |C(0)| */
     uint64_t max_evals;
@@ -279,6 +291,9 @@ typedef struct {
                                running target is tightened by min(1/2, target / holdout
                                error) and refinement goes on.  Holdout evaluations count
                                against max_evals. */
+    bfi_adaptive_progress_fn progress; /* called on the caller's thread during the run
+                                   (NULL: none); must not call back into the library */
+    void *progress_user;        /* passed to progress unchanged */
 } bfi_adaptive_config;
 
 typedef struct {

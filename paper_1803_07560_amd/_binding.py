@@ -70,12 +70,21 @@ class bfi_result(C.Structure):
                 "C_err": np.array(self.C_err[:n])}
 
 
+class bfi_adaptive_progress(C.Structure):
+    _fields_ = [("round", C.c_int32), ("holdout_checks", C.c_int32), ("leaves", C.c_uint64),
+                ("evals", C.c_uint64), ("rel_err", C.c_double), ("holdout_rel_err", C.c_double)]
+
+
+ADAPTIVE_PROGRESS_FN = C.CFUNCTYPE(None, C.POINTER(bfi_adaptive_progress), C.c_void_p)
+
+
 class bfi_adaptive_config(C.Structure):
     _fields_ = [("target_rel_err", C.c_double), ("max_evals", C.c_uint64),
                 ("n_min", C.c_uint64), ("n_max", C.c_uint64), ("split_log2", C.c_int32),
                 ("max_rounds", C.c_int32), ("refine_fraction", C.c_double),
                 ("round_evals", C.c_uint64), ("min_ess", C.c_double),
-                ("split_samples", C.c_uint64), ("holdout", C.c_int32)]
+                ("split_samples", C.c_uint64), ("holdout", C.c_int32),
+                ("progress", ADAPTIVE_PROGRESS_FN), ("progress_user", C.c_void_p)]
 
 
 class bfi_adaptive_stats(C.Structure):
@@ -413,11 +422,19 @@ def bfi_integrate(ctx, lat, prec, seed, box_lo, box_hi, split_log2, budget, laun
 def adaptive_config(target_rel_err=1e-3, max_evals=1 << 34, n_min=1 << 12, n_max=1 << 22,
                     split_log2=10, max_rounds=64, refine_fraction=0.5,
                     round_evals=0, min_ess=0.0, split_samples=1 << 16,
-                    holdout=False) -> bfi_adaptive_config:
-    return bfi_adaptive_config(float(target_rel_err), int(max_evals), int(n_min), int(n_max),
-                               int(split_log2), int(max_rounds), float(refine_fraction),
-                               int(round_evals), float(min_ess), int(split_samples),
-                               int(bool(holdout)))
+                    holdout=False, progress=None) -> bfi_adaptive_config:
+    """progress: optional callable taking a dict (round, holdout_checks, leaves,
+    evals, rel_err, holdout_rel_err), called once per round and per holdout pass."""
+    cfg = bfi_adaptive_config(float(target_rel_err), int(max_evals), int(n_min), int(n_max),
+                              int(split_log2), int(max_rounds), float(refine_fraction),
+                              int(round_evals), float(min_ess), int(split_samples),
+                              int(bool(holdout)))
+    if progress is not None:
+        def _cb(p, _user):
+            progress({f: getattr(p.contents, f) for f, _ in bfi_adaptive_progress._fields_})
+        cfg.progress = ADAPTIVE_PROGRESS_FN(_cb)
+        cfg._keep = cfg.progress  # the C function pointer lives as long as the config
+    return cfg
 
 
 def bfi_integrate_adaptive(ctx, lat, prec, seed, box_lo, box_hi, cfg, launch_=None,

@@ -386,9 +386,16 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         double run_target = cfg->target_rel_err;  // tightened by failed holdout checks
         bfi_result res{};
         std::vector<LeafAnalysis> an;
+        auto report = [&](double running) {
+            if (!cfg->progress)
+                return;
+            bfi_adaptive_progress p{rounds, checks, L.size(), evals, running, holdout_err};
+            cfg->progress(&p, cfg->progress_user);
+        };
         for (;;) {
             TracePhases phase("adaptive: analyse");
             BFI_TRY(analyse(nx, d, L.size(), L.lo.data(), L.hi.data(), L.rec.data(), &an, &res));
+            report(rel_err(res));
             if (rel_err(res) <= run_target && res.ess >= min_ess) {
                 if (!cfg->holdout)
                     break;
@@ -420,6 +427,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                                          &hres));
                 const double herr = rel_err(hres);
                 holdout_err = herr;
+                report(rel_err(res));
                 if (herr <= cfg->target_rel_err && hres.ess >= min_ess) {
                     res = hres;
                     holdout_used = true;

@@ -202,10 +202,18 @@ def test_adaptive_holdout_stop(bfi, ctx):
     Every check's evaluations are charged to the budget."""
     nx, nt, B, nu = 3, 2, 2.0, 0.7
     lat = bfi.lattice(nx, nt, nu=nu)
+    seen = []
     cfg = bfi.adaptive_config(target_rel_err=3e-3, max_evals=1 << 26, n_min=1024,
                               n_max=1 << 18, split_log2=2, max_rounds=60, refine_fraction=0.5,
-                              holdout=True)
+                              holdout=True, progress=seen.append)
     out = bfi.bfi_integrate_adaptive(ctx, lat, "fp64", 11, -B, B, cfg)
+    # progress: once per analysed round and once per holdout pass, in order
+    assert len(seen) == out["rounds"] + 1 + out["holdout_checks"]
+    assert [p["round"] for p in seen] == sorted(p["round"] for p in seen)
+    assert all(a["evals"] <= b["evals"] for a, b in zip(seen, seen[1:]))
+    assert seen[-1]["evals"] == out["evals"] and seen[-1]["leaves"] == out["leaves"]
+    assert seen[-1]["holdout_checks"] == out["holdout_checks"]
+    assert seen[-1]["holdout_rel_err"] == out["holdout_rel_err"]
     assert out["status"] == "BFI_OK"
     assert out["holdout_used"] and out["holdout_checks"] >= 1
     assert out["holdout_seed"] == (11 + out["holdout_checks"] * 0x9E3779B97F4A7C15) % (1 << 64)
