@@ -396,9 +396,15 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             TracePhases phase("adaptive: analyse");
             BFI_TRY(analyse(nx, d, L.size(), L.lo.data(), L.hi.data(), L.rec.data(), &an, &res));
             report(rel_err(res));
-            if (rel_err(res) <= run_target && res.ess >= min_ess) {
-                if (!cfg->holdout)
+            // stop check; with holdout, a failed check tightens the running target
+            // and is retried on the same leaves only while the running estimate
+            // still meets it
+            bool stop = false;
+            while (!stop && rel_err(res) <= run_target && res.ess >= min_ess) {
+                if (!cfg->holdout) {
+                    stop = true;
                     break;
+                }
                 phase.next("adaptive: holdout pass");
                 // holdout check: the same leaves, samples drawn afresh under a
                 // seed of their own, so no refinement decision has seen them
@@ -407,6 +413,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                     cost += n;
                 if (cost > cfg->max_evals - evals) {
                     status = BFI_EBUDGET;
+                    stop = true;
                     break;
                 }
                 ++checks;
@@ -432,12 +439,14 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                     res = hres;
                     holdout_used = true;
                     holdout_seed = hseed;
+                    stop = true;
                     break;
                 }
                 // the running estimate was optimistic: ask more of it
                 run_target *= std::min(0.5, cfg->target_rel_err / herr);
-                continue;
             }
+            if (stop)
+                break;
             if (rounds >= cfg->max_rounds) {
                 status = BFI_EBUDGET;
                 break;
