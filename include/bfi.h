@@ -183,6 +183,30 @@ bfi_status bfi_eval(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec
                     uint64_t seed, const bfi_subvolumes *subs, const bfi_launch *launch,
                     double *partials, double *split);
 
+/* bfi_eval for callers that cannot allocate: code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, validation,
+ * launch resolution, kernels and results as bfi_eval (with the same launch
+ * shape the records are bitwise equal); blocking on the context's stream.  It
+ * calls no hipMalloc, hipFree or other allocating routine: the copied
+ * subvolume list, point maps, work items, item and subvolume records and the
+ * queue head live in one static device array of BFI_NOALLOC_SCRATCH_BYTES per
+ * device, held from library load until the process ends (its device address is
+ * taken when a context is created on the device).  Layout, 256-byte aligned
+ * regions: ids, n, offsets (8 B each per subvolume), lo, hi and the FP64 map
+ * (8 B each per subvolume and dimension), the FP32 map (4 B each), the
+ * parameter block, (count + 1) first-item indices, work items (32 B), item
+ * records (BFI_PARTIAL_LEN(nx) doubles each, plus 2d with split statistics),
+ * subvolume records (plus BFI_SPLIT_LEN(d) with split statistics), the queue
+ * head.  Items hold samples_per_thread * block samples of one subvolume.
+ * Every call on a device shares that device's array: calls that overlap in
+ * time on one device (from two threads or two contexts) race.  Errors: those
+ * of bfi_eval, and EINVAL (with the bytes needed) when the layout exceeds the
+ * array; EDEVICE if the array's address could not be taken. */
+#define BFI_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+bfi_status bfi_eval_noalloc(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
+                            uint64_t seed, const bfi_subvolumes *subs, const bfi_launch *launch,
+                            double *partials, double *split);
+
 /* Plans: the subvolume list uploaded once, work items and buffers resident in
  * device memory, optionally a captured graph; run many times. */
 bfi_status bfi_plan_create(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,

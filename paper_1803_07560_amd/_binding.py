@@ -155,6 +155,8 @@ _SIGNATURES = {
     "bfi_context_destroy": ([_vp], C.c_int),
     "bfi_eval": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, _P(bfi_subvolumes), _P(bfi_launch),
                   _P(C.c_double), _P(C.c_double)], C.c_int),
+    "bfi_eval_noalloc": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, _P(bfi_subvolumes),
+                          _P(bfi_launch), _P(C.c_double), _P(C.c_double)], C.c_int),
     "bfi_plan_create": ([_vp, _P(bfi_lattice), C.c_int, _P(bfi_subvolumes), _P(bfi_launch),
                          _P(_vp)], C.c_int),
     "bfi_plan_run": ([_vp, C.c_uint64, _vp, _vp], C.c_int),
@@ -336,6 +338,17 @@ def bfi_eval(ctx, lat, prec, seed, subs, launch_=None, split=False):
     _check(load().bfi_eval(ctx, C.byref(lat), _prec(prec), int(seed), C.byref(sv.view),
                            C.byref(launch_) if launch_ is not None else None, _dp(part),
                            _dp(spl) if spl is not None else None), "bfi_eval")
+    return (part, spl) if split else part
+
+
+def bfi_eval_noalloc(ctx, lat, prec, seed, subs, launch_=None, split=False):
+    """bfi_eval through the allocation-free entry point (static device scratch)."""
+    sv = Subvolumes.of(subs, lat.d)
+    part = np.zeros((len(sv), partial_len(lat.nx)), dtype=np.float64)
+    spl = np.zeros((len(sv), split_len(lat.d)), dtype=np.float64) if split else None
+    _check(load().bfi_eval_noalloc(ctx, C.byref(lat), _prec(prec), int(seed), C.byref(sv.view),
+                                   C.byref(launch_) if launch_ is not None else None, _dp(part),
+                                   _dp(spl) if spl is not None else None), "bfi_eval_noalloc")
     return (part, spl) if split else part
 
 

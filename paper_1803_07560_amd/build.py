@@ -67,8 +67,9 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         tasks.append([cc, *COMMON, *DEVICE, f"-DBFI_NX={nx}", f"-DBFI_NT={nt}", "-c",
                       os.path.join(CSRC, "is_kernels.hip"), "-o",
                       os.path.join(BUILD, f"is_{nx}x{nt}.o")])
-    tasks.append([cc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "common_kernels.hip"), "-o",
-                  os.path.join(BUILD, "common_kernels.o")])
+    for src in ("common_kernels.hip", "noalloc.hip"):
+        tasks.append([cc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o",
+                      os.path.join(BUILD, src.replace(".hip", ".o"))])
     for src in HOST_SOURCES:
         tasks.append([cc, *COMMON, "-c", os.path.join(CSRC, src), "-o",
                       os.path.join(BUILD, src.replace(".cpp", ".o"))])

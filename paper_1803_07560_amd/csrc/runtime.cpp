@@ -15,7 +15,9 @@
 namespace bfi {
 
 namespace {
-thread_local std::string g_last_error;
+// fixed buffer: setting an error allocates nothing (the allocation-free entry
+// point reports its errors through it too)
+thread_local char g_last_error[512];
 }
 
 bfi_status fail(bfi_status s, const char *fmt, ...)
@@ -25,7 +27,7 @@ bfi_status fail(bfi_status s, const char *fmt, ...)
     va_start(ap, fmt);
     std::vsnprintf(buf, sizeof(buf), fmt, ap);
     va_end(ap);
-    g_last_error = buf;
+    std::memcpy(g_last_error, buf, sizeof(buf));
     return s;
 }
 
@@ -35,7 +37,7 @@ bfi_status hip_fail(hipError_t e, const char *what)
                 hipGetErrorString(e));
 }
 
-void clear_error() { g_last_error.clear(); }
+void clear_error() { g_last_error[0] = 0; }
 
 bool shape_compiled(int nx, int nt)
 {
@@ -664,7 +666,7 @@ const char *bfi_status_string(bfi_status s)
     return "unknown status";
 }
 
-const char *bfi_last_error(void) { return g_last_error.c_str(); }
+const char *bfi_last_error(void) { return g_last_error; }
 
 bfi_status bfi_shape_supported(int32_t nx, int32_t nt)
 {
@@ -712,6 +714,13 @@ bfi_status bfi_context_create(int32_t device, bfi_context **out)
         if (e != hipSuccess) {
             delete ctx;
             return hip_fail(e, "hipStreamCreateWithFlags");
+        }
+        // device address of the allocation-free entry point's scratch array
+        const bfi_status st = noalloc_setup(device);
+        if (st != BFI_OK) {
+            (void)hipStreamDestroy(ctx->stream);
+            delete ctx;
+            return st;
         }
         *out = ctx;
         return BFI_OK;

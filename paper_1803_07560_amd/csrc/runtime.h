@@ -130,6 +130,10 @@ bfi_launch resolve_launch(const bfi_context *ctx, const bfi_lattice &lat, int pr
 bfi_status finalize_records(int nx, int d, size_t nsub, const double *lo, const double *hi,
                             const double *partials, bfi_result *out, int evals_per_sample = 1);
 
+// Take the device address of the allocation-free entry point's scratch array on
+// `device` (which must be current); once per device, later calls return at once.
+bfi_status noalloc_setup(int device);
+
 }  // namespace bfi
 
 struct bfi_context {
