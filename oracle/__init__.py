@@ -79,12 +79,15 @@ def lib():
         L.oracle_action_batch.restype = C.c_int
         L.oracle_observable.argtypes = [latp, dp, dp]
         L.oracle_observable.restype = C.c_int
-        for name in ("oracle_sums", "oracle_split_sums"):
+        for name in ("oracle_sums", "oracle_split_sums", "oracle_sums_l1", "oracle_sums_shifted",
+                     "oracle_sums_shifted_l1"):
             f = getattr(L, name)
             f.argtypes = [latp, C.c_uint64, C.c_size_t, u64p, dp, dp, u64p, u64p, dp, C.c_int32]
             f.restype = C.c_int
-        L.oracle_finalize.argtypes = [C.c_int32, C.c_int32, C.c_size_t, dp, dp, dp, dp]
-        L.oracle_finalize.restype = C.c_int
+        for name in ("oracle_finalize", "oracle_finalize_shifted"):
+            f = getattr(L, name)
+            f.argtypes = [C.c_int32, C.c_int32, C.c_size_t, dp, dp, dp, dp]
+            f.restype = C.c_int
         L.oracle_plan_uniform.argtypes = [C.c_int32, dp, dp, C.c_int32, u64p, dp, dp]
         L.oracle_plan_uniform.restype = C.c_int
         L.oracle_nsphere.argtypes = [C.c_int32, C.c_uint64, C.c_uint64, dp, dp, C.c_uint64, dp]
@@ -184,6 +187,40 @@ def sums(lat: Lattice, seed: int, ids, lo, hi, n, offset=0, nthreads: int | None
     return out
 
 
+def _sums_call(name, width, lat, seed, ids, lo, hi, n, offset, nthreads):
+    ids, lo, hi, n, offset = _subvol_args(lat, ids, lo, hi, n, offset)
+    out = np.zeros((ids.shape[0], width), dtype=np.float64)
+    nt = nthreads or os.cpu_count() or 1
+    rc = getattr(lib(), name)(C.byref(lat), seed, ids.shape[0], _ptr(ids, C.c_uint64),
+                              _ptr(lo, C.c_double), _ptr(hi, C.c_double), _ptr(n, C.c_uint64),
+                              _ptr(offset, C.c_uint64), _ptr(out, C.c_double), nt)
+    if rc != 0:
+        raise ValueError(f"{name} failed ({rc})")
+    return out
+
+
+def sums_l1(lat: Lattice, seed: int, ids, lo, hi, n, offset=0, nthreads: int | None = None):
+    """Sums records with nx more fields, sum |p_r w| per r (nsub x (3 + 4 nx))."""
+    return _sums_call("oracle_sums_l1", sums_len(lat.nx) + lat.nx, lat, seed, ids, lo, hi, n,
+                      offset, nthreads)
+
+
+def sums_shifted(lat: Lattice, seed: int, ids, lo, hi, n, offset=0,
+                 nthreads: int | None = None):
+    """Shifted records [n, sigma, sum w, ...] with w = exp(sigma - S), sigma the
+    smallest action of the subvolume's samples (nsub x (4 + 3 nx))."""
+    return _sums_call("oracle_sums_shifted", sums_len(lat.nx) + 1, lat, seed, ids, lo, hi, n,
+                      offset, nthreads)
+
+
+def sums_shifted_l1(lat: Lattice, seed: int, ids, lo, hi, n, offset=0,
+                    nthreads: int | None = None):
+    """Shifted records with nx more fields, sum |p_r w| of the shifted weights
+    (nsub x (4 + 4 nx))."""
+    return _sums_call("oracle_sums_shifted_l1", sums_len(lat.nx) + 1 + lat.nx, lat, seed, ids, lo,
+                      hi, n, offset, nthreads)
+
+
 def split_sums(lat: Lattice, seed: int, ids, lo, hi, n, offset=0, nthreads: int | None = None):
     """Upper-half sums of w and w^2 per dimension (nsub x 2d)."""
     ids, lo, hi, n, offset = _subvol_args(lat, ids, lo, hi, n, offset)
@@ -209,6 +246,22 @@ def finalize(nx: int, d: int, lo, hi, sums_records, evals_per_sample: int = 1) -
                                _ptr(s, C.c_double), _ptr(out, C.c_double))
     if rc != 0:
         raise ValueError(f"oracle_finalize failed ({rc})")
+    return {"Z": out[0], "Z_err": out[1], "log_Z": out[2], "ess": out[3],
+            "n_evals": out[4] * evals_per_sample,
+            "C": out[5:5 + nx].copy(), "C_err": out[5 + nx:5 + 2 * nx].copy()}
+
+
+def finalize_shifted(nx: int, d: int, lo, hi, shifted_records, evals_per_sample: int = 1) -> dict:
+    """finalize over shifted records: log_Z stays finite where Z underflows."""
+    s = np.ascontiguousarray(shifted_records, dtype=np.float64).reshape(-1, sums_len(nx) + 1)
+    ns = s.shape[0]
+    lo = np.ascontiguousarray(lo, dtype=np.float64).reshape(ns, d)
+    hi = np.ascontiguousarray(hi, dtype=np.float64).reshape(ns, d)
+    out = np.zeros(result_len(nx), dtype=np.float64)
+    rc = lib().oracle_finalize_shifted(nx, d, ns, _ptr(lo, C.c_double), _ptr(hi, C.c_double),
+                                       _ptr(s, C.c_double), _ptr(out, C.c_double))
+    if rc != 0:
+        raise ValueError(f"oracle_finalize_shifted failed ({rc})")
     return {"Z": out[0], "Z_err": out[1], "log_Z": out[2], "ess": out[3],
             "n_evals": out[4] * evals_per_sample,
             "C": out[5:5 + nx].copy(), "C_err": out[5 + nx:5 + 2 * nx].copy()}

@@ -227,6 +227,8 @@ typedef struct {
     const uint64_t *n, *offset;
     double *out;
     int split; /* 0: sums record, 1: split statistics, 2: Gaussian-proposal record */
+    int l1;      /* sums records: append sum |p_r w| per r */
+    int shifted; /* sums records: weights exp(sigma - S), sigma = the smallest S */
     int32_t nthreads, tid;
 } sums_job;
 
@@ -247,17 +249,35 @@ static void subvolume_sums(const sums_job *job, size_t s)
     box_map(d, lo, hi, scale, base);
     const int pairs = lat->antithetic && !job->split;
 
-    /* record layout: n, w, w^2, p_r w, (p_r w)^2, p_r w^2 -- or, for the split
-     * statistics, sum_U w and sum_U w^2 per dimension */
-    const int32_t len = job->split ? 2 * d : ORACLE_SUMS_LEN(nx);
+    /* record layout: n, w, w^2, p_r w, (p_r w)^2, p_r w^2 [, |p_r w|] -- or, for
+     * the split statistics, sum_U w and sum_U w^2 per dimension */
+    const int32_t len = job->split ? 2 * d : ORACLE_SUMS_LEN(nx) + (job->l1 ? nx : 0);
     neumaier *acc = (neumaier *)calloc((size_t)len, sizeof(neumaier));
 
     const uint64_t first = job->offset[s], count = job->n[s];
+    /* shifted weights: a first pass finds the smallest action of the
+     * subvolume's points (both points of a pair), which every weight is taken
+     * relative to; plain weights use sigma = 0, and 0 - S is -S exactly */
+    double sigma = 0.0;
+    if (job->shifted) {
+        sigma = INFINITY;
+        for (uint64_t i = 0; i < count; ++i) {
+            oracle_words(d, job->seed, job->id[s], first + i, x);
+            for (int32_t k = 0; k < d; ++k)
+                u[k] = fma((double)x[k], scale[k], base[k]);
+            sigma = fmin(sigma, oracle_action(lat, u));
+            if (pairs) {
+                for (int32_t k = 0; k < d; ++k)
+                    ub[k] = fma((double)(0xFFFFFFFFu - x[k]), scale[k], base[k]);
+                sigma = fmin(sigma, oracle_action(lat, ub));
+            }
+        }
+    }
     for (uint64_t i = 0; i < count; ++i) {
         oracle_words(d, job->seed, job->id[s], first + i, x);
         for (int32_t k = 0; k < d; ++k)
             u[k] = fma((double)x[k], scale[k], base[k]);
-        double w = exp(-oracle_action(lat, u));
+        double w = exp(sigma - oracle_action(lat, u));
         if (job->split) {
             for (int32_t k = 0; k < d; ++k) {
                 if (x[k] >> 31) { /* upper half of the box along k */
@@ -272,7 +292,7 @@ static void subvolume_sums(const sums_job *job, size_t s)
             /* the partner point: the complemented words through the same map */
             for (int32_t k = 0; k < d; ++k)
                 ub[k] = fma((double)(0xFFFFFFFFu - x[k]), scale[k], base[k]);
-            const double wb = exp(-oracle_action(lat, ub));
+            const double wb = exp(sigma - oracle_action(lat, ub));
             oracle_observable(lat, ub, pb);
             for (int32_t r = 0; r < nx; ++r)
                 p[r] = 0.5 * (p[r] * w + pb[r] * wb); /* now the pair's p_r w */
@@ -284,6 +304,8 @@ static void subvolume_sums(const sums_job *job, size_t s)
                 nm_add(&acc[3 + r], p[r]);
                 nm_add(&acc[3 + nx + r], p[r] * p[r]);
                 nm_add(&acc[3 + 2 * nx + r], p[r] * w);
+                if (job->l1)
+                    nm_add(&acc[3 + 3 * nx + r], fabs(p[r]));
             }
             continue;
         }
@@ -295,11 +317,22 @@ static void subvolume_sums(const sums_job *job, size_t s)
             nm_add(&acc[3 + r], pw);
             nm_add(&acc[3 + nx + r], pw * pw);
             nm_add(&acc[3 + 2 * nx + r], pw * w);
+            if (job->l1)
+                nm_add(&acc[3 + 3 * nx + r], fabs(pw));
         }
     }
-    double *out = job->out + s * (size_t)len;
-    for (int32_t t = 0; t < len; ++t)
-        out[t] = nm_value(&acc[t]);
+    if (job->shifted) {
+        /* [n, sigma, the rest of the sums record] */
+        double *out = job->out + s * (size_t)(len + 1);
+        out[0] = nm_value(&acc[0]);
+        out[1] = sigma;
+        for (int32_t t = 1; t < len; ++t)
+            out[t + 1] = nm_value(&acc[t]);
+    } else {
+        double *out = job->out + s * (size_t)len;
+        for (int32_t t = 0; t < len; ++t)
+            out[t] = nm_value(&acc[t]);
+    }
     free(acc);
     free(x);
     free(u);
@@ -325,7 +358,7 @@ static void *sums_worker(void *arg)
 static int run_sums(const oracle_lattice *lat, uint64_t seed, size_t nsub, const uint64_t *id,
                     const double *lo, const double *hi, const uint64_t *n,
                     const uint64_t *offset, double *out, int32_t nthreads, int split,
-                    double gaussian_fraction)
+                    double gaussian_fraction, int l1, int shifted)
 {
     if (!lattice_ok(lat))
         return -1;
@@ -349,8 +382,8 @@ static int run_sums(const oracle_lattice *lat, uint64_t seed, size_t nsub, const
     sums_job *jobs = (sums_job *)calloc((size_t)nthreads, sizeof(sums_job));
     pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
     for (int32_t t = 0; t < nthreads; ++t) {
-        sums_job j = { lat,    seed, gaussian_fraction, nsub,  id,       lo, hi,
-                       n,      offset, out,           split, nthreads, t };
+        sums_job j = { lat, seed, gaussian_fraction, nsub, id, lo, hi, n, offset, out,
+                       split, l1, shifted, nthreads, t };
         jobs[t] = j;
     }
     int rc = 0;
@@ -375,14 +408,36 @@ int oracle_sums(const oracle_lattice *lat, uint64_t seed, size_t nsub, const uin
                 const double *lo, const double *hi, const uint64_t *n, const uint64_t *offset,
                 double *sums, int32_t nthreads)
 {
-    return run_sums(lat, seed, nsub, id, lo, hi, n, offset, sums, nthreads, 0, 0.0);
+    return run_sums(lat, seed, nsub, id, lo, hi, n, offset, sums, nthreads, 0, 0.0, 0, 0);
+}
+
+int oracle_sums_l1(const oracle_lattice *lat, uint64_t seed, size_t nsub, const uint64_t *id,
+                   const double *lo, const double *hi, const uint64_t *n, const uint64_t *offset,
+                   double *sums, int32_t nthreads)
+{
+    return run_sums(lat, seed, nsub, id, lo, hi, n, offset, sums, nthreads, 0, 0.0, 1, 0);
+}
+
+int oracle_sums_shifted(const oracle_lattice *lat, uint64_t seed, size_t nsub,
+                        const uint64_t *id, const double *lo, const double *hi, const uint64_t *n,
+                        const uint64_t *offset, double *sums, int32_t nthreads)
+{
+    return run_sums(lat, seed, nsub, id, lo, hi, n, offset, sums, nthreads, 0, 0.0, 0, 1);
+}
+
+int oracle_sums_shifted_l1(const oracle_lattice *lat, uint64_t seed, size_t nsub,
+                           const uint64_t *id, const double *lo, const double *hi,
+                           const uint64_t *n, const uint64_t *offset, double *sums,
+                           int32_t nthreads)
+{
+    return run_sums(lat, seed, nsub, id, lo, hi, n, offset, sums, nthreads, 0, 0.0, 1, 1);
 }
 
 int oracle_split_sums(const oracle_lattice *lat, uint64_t seed, size_t nsub, const uint64_t *id,
                       const double *lo, const double *hi, const uint64_t *n,
                       const uint64_t *offset, double *out, int32_t nthreads)
 {
-    return run_sums(lat, seed, nsub, id, lo, hi, n, offset, out, nthreads, 1, 0.0);
+    return run_sums(lat, seed, nsub, id, lo, hi, n, offset, out, nthreads, 1, 0.0, 0, 0);
 }
 
 /* ---------------------------------------------------------------- finalize */
@@ -438,6 +493,48 @@ int oracle_finalize(int32_t nx, int32_t d, size_t nsub, const double *lo, const 
         result[5 + nx + r] = sqrt(fmax(nm_value(&var), 0.0)) / fabs(z);
     }
     free(V);
+    return 0;
+}
+
+/* Shifted records [n, sigma, sums record without n] stand for the plain record
+ * with first-order sums times exp(-sigma) and second-order sums times
+ * exp(-2 sigma).  Every record is moved to the smallest sigma of the list (a
+ * factor exp(sigma_min - sigma) <= 1, squared for second-order sums) and the
+ * plain finalize runs on those; Z carries the factor exp(sigma_min), so
+ * log Z = log(that Z) - sigma_min, while C(r), its errors and the effective
+ * sample size are ratios in which the factor cancels. */
+int oracle_finalize_shifted(int32_t nx, int32_t d, size_t nsub, const double *lo,
+                            const double *hi, const double *sums, double *result)
+{
+    if (nx < 1 || d < nx || !result || nsub == 0 || !lo || !hi || !sums)
+        return -1;
+    const int32_t len = ORACLE_SUMS_LEN(nx), slen = len + 1;
+    double smin = INFINITY;
+    for (size_t s = 0; s < nsub; ++s)
+        smin = fmin(smin, sums[s * (size_t)slen + 1]);
+    if (!isfinite(smin))
+        return -1;
+    double *plain = (double *)malloc(sizeof(double) * nsub * (size_t)len);
+    for (size_t s = 0; s < nsub; ++s) {
+        const double *rec = sums + s * (size_t)slen;
+        double *out = plain + s * (size_t)len;
+        const double f1 = exp(smin - rec[1]), f2 = f1 * f1;
+        out[0] = rec[0];
+        out[1] = rec[2] * f1;
+        out[2] = rec[3] * f2;
+        for (int32_t r = 0; r < nx; ++r) {
+            out[3 + r] = rec[4 + r] * f1;
+            out[3 + nx + r] = rec[4 + nx + r] * f2;
+            out[3 + 2 * nx + r] = rec[4 + 2 * nx + r] * f2;
+        }
+    }
+    const int rc = oracle_finalize(nx, d, nsub, lo, hi, plain, result);
+    free(plain);
+    if (rc != 0)
+        return rc;
+    result[2] -= smin;             /* log Z */
+    result[0] = exp(result[2]);    /* Z (may underflow; log Z does not) */
+    result[1] *= exp(-smin);       /* Z_err */
     return 0;
 }
 
@@ -779,5 +876,5 @@ int oracle_is_sums(const oracle_lattice *lat, uint64_t seed, const double *lo, c
     if (!(gaussian_fraction >= 0.0 && gaussian_fraction <= 1.0))
         return -1;
     return run_sums(lat, seed, nstream, id, lo, hi, n, offset, sums, nthreads, 2,
-                    gaussian_fraction);
+                    gaussian_fraction, 0, 0);
 }

@@ -98,6 +98,31 @@ int oracle_sums(const oracle_lattice *lat, uint64_t seed, size_t nsub, const uin
                 const double *lo, const double *hi, const uint64_t *n, const uint64_t *offset,
                 double *sums, int32_t nthreads);
 
+/* oracle_sums with nx more fields per record: sum |p_r w| (pairs: the absolute
+ * value of the pair's mean p_r w), the L1 scale against which the signed sums
+ * and C(r) are compared.  Record length ORACLE_SUMS_LEN(nx) + nx; the first
+ * ORACLE_SUMS_LEN(nx) fields are oracle_sums' own. */
+int oracle_sums_l1(const oracle_lattice *lat, uint64_t seed, size_t nsub, const uint64_t *id,
+                   const double *lo, const double *hi, const uint64_t *n, const uint64_t *offset,
+                   double *sums, int32_t nthreads);
+
+/* Shifted weights: per subvolume sigma = the smallest action S of its samples
+ * (a first pass over them), then the sums record of w = exp(sigma - S), which
+ * cannot underflow for every sample of a subvolume at once.  Record:
+ * [n, sigma, sum w, sum w^2, sum p_r w (nx), sum (p_r w)^2 (nx), sum p_r w^2 (nx)]
+ * (ORACLE_SUMS_LEN(nx) + 1 doubles); the true first-order sums are these times
+ * exp(-sigma), the second-order ones times exp(-2 sigma). */
+int oracle_sums_shifted(const oracle_lattice *lat, uint64_t seed, size_t nsub,
+                        const uint64_t *id, const double *lo, const double *hi, const uint64_t *n,
+                        const uint64_t *offset, double *sums, int32_t nthreads);
+
+/* oracle_sums_shifted with nx more fields, sum |p_r w| of the shifted weights
+ * (true values: times exp(-sigma)); record length ORACLE_SUMS_LEN(nx) + 1 + nx. */
+int oracle_sums_shifted_l1(const oracle_lattice *lat, uint64_t seed, size_t nsub,
+                           const uint64_t *id, const double *lo, const double *hi,
+                           const uint64_t *n, const uint64_t *offset, double *sums,
+                           int32_t nthreads);
+
 /* Split statistics for one subvolume list: for every dimension j, the sums of w
  * and w^2 over the samples in the upper half of the box along j (word j has its
  * top bit set).  out is nsub x 2d: [sum_U w (d), sum_U w^2 (d)]. */
@@ -108,6 +133,11 @@ int oracle_split_sums(const oracle_lattice *lat, uint64_t seed, size_t nsub, con
 /* Combine per-subvolume sums into Z, C(r) = N(r)/Z and their standard errors. */
 int oracle_finalize(int32_t nx, int32_t d, size_t nsub, const double *lo, const double *hi,
                     const double *sums, double *result);
+
+/* oracle_finalize over shifted records (oracle_sums_shifted): log Z is finite
+ * whenever some weight is, even where Z itself underflows. */
+int oracle_finalize_shifted(int32_t nx, int32_t d, size_t nsub, const double *lo,
+                            const double *hi, const double *sums, double *result);
 
 /* Uniform split of a box into 2^k subvolumes by bisecting dims 0..k-1 in turn;
  * heap ids 2^k .. 2^(k+1)-1 in increasing order. */
