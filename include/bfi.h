@@ -63,8 +63,15 @@ typedef enum {
 /* Arithmetic of the action and the weight.  Sums are FP64 in both forms. */
 typedef enum {
     BFI_FP64 = 0,         /* action, exp(-S) and sums in FP64 */
-    BFI_FP32_SHIFTED = 1  /* action and exp in FP32 with a per-thread shift sigma:
+    BFI_FP32_SHIFTED = 1, /* action and exp in FP32 with a per-thread shift sigma:
                              w = exp(sigma - S), sums in FP64 relative to exp(-sigma) */
+    BFI_FP64_SHIFTED = 2  /* action, exp and sums in FP64 with the same per-thread
+                             shift (sigma = an action of the thread's samples, moved
+                             when a later one is more than 64 below it): no weight
+                             underflows relative to the largest one, so Z and C(r)
+                             stay defined where every plain exp(-S) is 0 (S > ~745);
+                             bfi_result.log_Z carries Z then.  Not supported by the
+                             Gaussian-proposal sampler (EUNSUPPORTED). */
 } bfi_precision;
 
 /* The per-sample product p_r behind N(r) and C(r) = N(r)/Z (section 4's

@@ -6,5 +6,5 @@ this package is its ctypes binding.  Importing it does not touch the GPU; the
 first call loads the library and fails loudly if it is not built.
 """
 from ._binding import *  # noqa: F401,F403
-from ._binding import (BFI_FP32_SHIFTED, BFI_FP64, EXPORTED, LIB_PATH, BfiError, Subvolumes,  # noqa
+from ._binding import (BFI_FP32_SHIFTED, BFI_FP64, BFI_FP64_SHIFTED, EXPORTED, LIB_PATH, BfiError, Subvolumes,  # noqa
                        load, partial_len, split_len)

@@ -17,10 +17,12 @@ LIB_PATH = os.environ.get("BFI_LIBRARY") or os.path.join(_HERE, "libbfi.so")
 
 BFI_FP64 = 0
 BFI_FP32_SHIFTED = 1
+BFI_FP64_SHIFTED = 2
 BFI_OBS_ANCHOR = 0
 BFI_OBS_AVERAGED = 1
-PRECISIONS = {"fp64": BFI_FP64, "fp32": BFI_FP32_SHIFTED, BFI_FP64: BFI_FP64,
-              BFI_FP32_SHIFTED: BFI_FP32_SHIFTED}
+PRECISIONS = {"fp64": BFI_FP64, "fp32": BFI_FP32_SHIFTED, "fp64s": BFI_FP64_SHIFTED,
+              BFI_FP64: BFI_FP64, BFI_FP32_SHIFTED: BFI_FP32_SHIFTED,
+              BFI_FP64_SHIFTED: BFI_FP64_SHIFTED}
 
 STATUS = {0: "BFI_OK", -1: "BFI_EINVAL", -2: "BFI_ENOMEM", -3: "BFI_EDEVICE",
           -4: "BFI_EUNSUPPORTED", -5: "BFI_EBUSY", -6: "BFI_ECANCELLED", -7: "BFI_EBUDGET",

@@ -341,7 +341,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         TraceRange trace("bfi_integrate_adaptive");
         if (!ctx || !box_lo || !box_hi || !out)
             return fail(BFI_EINVAL, "arguments must be non-NULL");
-        if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
+        if (!known_precision(prec))
             return fail(BFI_EINVAL, "unknown precision");
         BFI_TRY(check_lattice(lat));
         BFI_TRY(check_config(cfg));

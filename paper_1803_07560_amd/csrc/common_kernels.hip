@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(256) debug_points_kernel(DebugPointArgs a)
             if (k >= d)
                 break;
             a.out[i * d + k] =
-                a.prec == kFP64
+                a.prec != kFP32Shifted
                     ? dev::map_word(blk[t], a.scale64[k], a.base64[k])
                     : static_cast<double>(dev::map_word(blk[t], a.scale32[k], a.base32[k]));
         }

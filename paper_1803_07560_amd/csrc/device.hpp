@@ -329,5 +329,13 @@ __device__ __forceinline__ float wave_min(float v)
     return v;
 }
 
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
 }  // namespace dev
 }  // namespace bfi

@@ -31,7 +31,7 @@ bfi_status check_integrand(const bfi_integrand *f, int *d)
         BFI_TRY(check_lattice(&f->lat));
         if (f->lat.antithetic)
             return fail(BFI_EUNSUPPORTED, "the integrand protocol uses single points");
-        if (f->prec != BFI_FP64 && f->prec != BFI_FP32_SHIFTED)
+        if (!known_precision(f->prec))
             return fail(BFI_EINVAL, "unknown precision");
         *d = f->lat.nx * f->lat.nt;
         if (*d > 32)

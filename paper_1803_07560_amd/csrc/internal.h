@@ -13,7 +13,9 @@ namespace bfi {
     X(1, 1) X(1, 2) X(2, 1) X(2, 2) X(3, 1) X(3, 2) X(4, 1) X(4, 2) X(5, 3) X(8, 2)     \
     X(10, 2) X(16, 4)
 
-enum Precision : int { kFP64 = 0, kFP32Shifted = 1 };
+// kFP64: plain weights exp(-S); kFP32Shifted: FP32 action and exp with a
+// per-thread shift; kFP64Shifted: FP64 action and exp with a per-thread shift.
+enum Precision : int { kFP64 = 0, kFP32Shifted = 1, kFP64Shifted = 2 };
 
 // Coefficients of the residual rewritten as
 //   R = v_next + v (k_diag + c_adv (v_right - v_left)) - c_visc (v_right + v_left)

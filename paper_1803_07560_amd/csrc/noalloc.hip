@@ -176,7 +176,7 @@ extern "C" bfi_status bfi_eval_noalloc(bfi_context *ctx, const bfi_lattice *lat,
     return guarded([&]() -> bfi_status {
         if (!ctx || !partials)
             return fail(BFI_EINVAL, "context and partials must be non-NULL");
-        if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
+        if (!known_precision(prec))
             return fail(BFI_EINVAL, "unknown precision %d", static_cast<int>(prec));
         BFI_TRY(check_lattice(lat));
         BFI_TRY(check_subvolumes(lat, subs));

@@ -245,12 +245,18 @@ bfi_launch resolve_launch(const bfi_context *ctx, const bfi_lattice &lat, int pr
     if (ctx) {
         // the kernel variant's own entry (pairs, observable), else the entry of
         // the same sampler with the anchored product, else the single-point one
+        // (the shifted FP64 form, untuned, takes the FP64 form's entries: the same
+        // arithmetic and registers plus one shift)
         const int pairs = lat.antithetic ? 1 : 0;
-        auto it = ctx->tuned.find(TuneKey{lat.nx, lat.nt, prec, pairs, lat.observable});
-        if (it == ctx->tuned.end())
-            it = ctx->tuned.find(TuneKey{lat.nx, lat.nt, prec, pairs, 0});
-        if (it == ctx->tuned.end())
-            it = ctx->tuned.find(TuneKey{lat.nx, lat.nt, prec, 0, 0});
+        auto it = ctx->tuned.end();
+        for (int p : {prec, prec == kFP64Shifted ? int(kFP64) : prec}) {
+            if (it == ctx->tuned.end())
+                it = ctx->tuned.find(TuneKey{lat.nx, lat.nt, p, pairs, lat.observable});
+            if (it == ctx->tuned.end())
+                it = ctx->tuned.find(TuneKey{lat.nx, lat.nt, p, pairs, 0});
+            if (it == ctx->tuned.end())
+                it = ctx->tuned.find(TuneKey{lat.nx, lat.nt, p, 0, 0});
+        }
         if (it != ctx->tuned.end())
             l = it->second.launch;
     }
@@ -748,7 +754,7 @@ bfi_status bfi_plan_create(bfi_context *ctx, const bfi_lattice *lat, bfi_precisi
         TraceRange trace("bfi_plan_create");
         if (!ctx || !out)
             return fail(BFI_EINVAL, "context and out must be non-NULL");
-        if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
+        if (!known_precision(prec))
             return fail(BFI_EINVAL, "unknown precision %d", static_cast<int>(prec));
         BFI_TRY(check_lattice(lat));
         BFI_TRY(check_subvolumes(lat, subs));
@@ -889,7 +895,7 @@ bfi_status bfi_eval(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec
         TraceRange trace("bfi_eval");
         if (!ctx || !partials)
             return fail(BFI_EINVAL, "context and partials must be non-NULL");
-        if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
+        if (!known_precision(prec))
             return fail(BFI_EINVAL, "unknown precision %d", static_cast<int>(prec));
         BFI_TRY(check_lattice(lat));
         BFI_TRY(check_subvolumes(lat, subs));
@@ -978,7 +984,7 @@ bfi_status bfi_debug_points(bfi_context *ctx, int32_t d, bfi_precision prec, uin
             return fail(BFI_EINVAL, "arguments must be non-NULL");
         if (d < 1 || d > BFI_MAX_D)
             return fail(BFI_EINVAL, "d out of range");
-        if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
+        if (!known_precision(prec))
             return fail(BFI_EINVAL, "unknown precision");
         for (int k = 0; k < d; ++k)
             if (!std::isfinite(lo[k]) || !std::isfinite(hi[k]) || !(lo[k] < hi[k]))
@@ -1032,7 +1038,7 @@ bfi_status bfi_debug_action(bfi_context *ctx, const bfi_lattice *lat, bfi_precis
     return guarded([&]() -> bfi_status {
         if (!ctx || (n && (!points || !out_S)))
             return fail(BFI_EINVAL, "arguments must be non-NULL");
-        if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
+        if (!known_precision(prec))
             return fail(BFI_EINVAL, "unknown precision");
         BFI_TRY(check_lattice(lat));
         if (n == 0)

@@ -40,6 +40,11 @@ void clear_error();
     } while (0)
 
 bool shape_compiled(int nx, int nt);
+// BFI_FP64, BFI_FP32_SHIFTED or BFI_FP64_SHIFTED
+inline bool known_precision(int prec)
+{
+    return prec == BFI_FP64 || prec == BFI_FP32_SHIFTED || prec == BFI_FP64_SHIFTED;
+}
 // Dispatch to the kernels compiled for lattice shape (nx, nt).
 hipError_t launch_mc(int nx, int nt, const LaunchSpec &spec, const McArgs &args, hipStream_t st);
 hipError_t kernel_info(int nx, int nt, const LaunchSpec &spec, KernelInfo *info);

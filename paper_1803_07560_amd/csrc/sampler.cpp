@@ -69,7 +69,9 @@ bfi_status check_args(const bfi_lattice *lat, int prec, double lo, double hi, do
     if (lat->nx * lat->nt > kIsMaxD)
         return fail(BFI_EUNSUPPORTED, "the Gaussian-proposal sampler is compiled for d <= %d",
                     kIsMaxD);
-    if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
+    if (prec == BFI_FP64_SHIFTED)
+        return fail(BFI_EUNSUPPORTED, "the Gaussian-proposal sampler has no shifted FP64 form");
+    if (!known_precision(prec))
         return fail(BFI_EINVAL, "unknown precision %d", prec);
     if (!std::isfinite(lo) || !std::isfinite(hi) || !(lo < hi))
         return fail(BFI_EINVAL, "cube: need finite lo < hi");

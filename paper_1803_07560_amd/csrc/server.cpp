@@ -528,7 +528,7 @@ bfi_status bfi_server_submit(bfi_server *srv, const bfi_request *req, uint64_t *
         if (!srv || !req || !ticket)
             return fail(BFI_EINVAL, "arguments must be non-NULL");
         BFI_TRY(check_lattice(&req->lat));
-        if (req->prec != BFI_FP64 && req->prec != BFI_FP32_SHIFTED)
+        if (!known_precision(req->prec))
             return fail(BFI_EINVAL, "unknown precision");
         if (!(req->box > 0) || !std::isfinite(req->box))
             return fail(BFI_EINVAL, "box must be positive and finite");

@@ -26,9 +26,10 @@
 namespace bfi {
 namespace {
 
-// FP32 form: the per-thread shift sigma follows the smallest action seen, but is
-// only moved when a new sample would weigh more than e^64 relative to it, so the
-// FP32 weight exp(sigma - S) stays in (0, e^64] and rescales are rare.
+// Shifted forms: the per-thread shift sigma follows the smallest action seen,
+// but is only moved when a new sample would weigh more than e^64 relative to it,
+// so the weight exp(sigma - S) stays in (0, e^64] (FP32: within range; FP64:
+// squares and their sums far from overflow) and rescales are rare.
 constexpr float kShiftGap = 64.0f;
 constexpr float kLog2e = 1.44269504088896340736f;
 
@@ -76,7 +77,7 @@ struct Fields {
 // the FP64 form spills too much at two).
 template <int NX, int NT, int PREC, bool SPLIT, bool PAIR>
 constexpr int kMinWaves = NX * NT > 32             ? 2
-                          : PREC == kFP64          ? 1
+                          : PREC != kFP32Shifted   ? 1
                           : SPLIT                  ? 2
                           : PAIR                   ? 3
                                                    : 1;
@@ -85,7 +86,10 @@ template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG, bool PAIR>
 __global__ void __launch_bounds__(BLOCK)
     __attribute__((amdgpu_waves_per_eu(kMinWaves<NX, NT, PREC, SPLIT, PAIR>))) mc_kernel(McArgs a)
 {
-    using T = std::conditional_t<PREC == kFP64, double, float>;
+    using T = std::conditional_t<PREC == kFP32Shifted, float, double>;
+    // the shift's type: FP32 in the FP32 form, FP64 in the shifted FP64 form
+    using Sig = std::conditional_t<PREC == kFP64Shifted, double, float>;
+    constexpr bool kShifted = PREC != kFP64;
     constexpr int D = NX * NT;
     constexpr int NB = (D + 3) / 4;
     constexpr int NW = BLOCK / 64;
@@ -106,7 +110,7 @@ __global__ void __launch_bounds__(BLOCK)
     // large FP64 lattices park time slice 0 (needed again only to close the
     // time period and for the observables) in LDS, one column per thread, so
     // that its registers are free while the other slices are processed
-    constexpr bool kParkFirst = PREC == kFP64 && D > 32;
+    constexpr bool kParkFirst = PREC != kFP32Shifted && D > 32;
     __shared__ double park_lds[kParkFirst ? NX : 1][kParkFirst ? BLOCK : 1];
     __shared__ double red[NW][NF];
     // (offset, scale) of each variable side by side: one LDS read with an
@@ -115,7 +119,7 @@ __global__ void __launch_bounds__(BLOCK)
         T x, y;  // offset, scale
     };
     __shared__ T2 map_lds[kHoist ? 1 : D];
-    __shared__ float red_sigma[NW];
+    __shared__ Sig red_sigma[NW];
     __shared__ uint32_t next_item;
 
     const uint32_t tid = threadIdx.x;
@@ -145,7 +149,7 @@ __global__ void __launch_bounds__(BLOCK)
         const uint32_t id_lo = static_cast<uint32_t>(id), id_hi = static_cast<uint32_t>(id >> 32);
         const T *base_g;
         const T *scale_g;
-        if constexpr (PREC == kFP64) {
+        if constexpr (PREC != kFP32Shifted) {
             base_g = P.base64 + static_cast<size_t>(s) * D;
             scale_g = P.scale64 + static_cast<size_t>(s) * D;
         } else {
@@ -186,7 +190,10 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
         for (int i = 0; i < NF; ++i)
             acc[i] = 0.0;
-        float sigma = __builtin_inff();
+        // no sample yet: +inf (FP32 form), or the largest finite double (FP64
+        // form), against which an infinite action still weighs exp(-inf) = 0
+        Sig sigma = PREC == kFP64Shifted ? static_cast<Sig>(__DBL_MAX__)
+                                         : static_cast<Sig>(__builtin_inff());
 
         auto rescale = [&](double f1) {
             const double f2 = f1 * f1;
@@ -273,8 +280,20 @@ __global__ void __launch_bounds__(BLOCK)
                     psb = fb[0];
                 }
                 double w, v[NR];
-                if constexpr (PREC == kFP64) {
-                    const double wa = exp_weight<ExpFma>(-sa), wbt = exp_weight<ExpFma>(-sb);
+                if constexpr (PREC != kFP32Shifted) {
+                    double wa, wbt;
+                    if constexpr (PREC == kFP64Shifted) {
+                        const double smin = fmin(sa, sb);
+                        if (smin < sigma - static_cast<double>(kShiftGap)) {
+                            rescale(exp(smin - sigma));
+                            sigma = smin;
+                        }
+                        wa = exp_weight<ExpFma>(sigma - sa);
+                        wbt = exp_weight<ExpFma>(sigma - sb);
+                    } else {
+                        wa = exp_weight<ExpFma>(-sa);
+                        wbt = exp_weight<ExpFma>(-sb);
+                    }
                     w = 0.5 * (wa + wbt);
                     const double ta = psa * wa, tb = psb * wbt;
 #pragma unroll
@@ -417,8 +436,18 @@ __global__ void __launch_bounds__(BLOCK)
             }
 
             double w;
-            if constexpr (PREC == kFP64) {
-                w = exp_weight<ExpFma>(-S);
+            if constexpr (PREC != kFP32Shifted) {
+                if constexpr (PREC == kFP64Shifted) {
+                    if (S < sigma - static_cast<double>(kShiftGap)) {
+                        // first sample (sigma = inf) or a new action far below
+                        // the shift: move the shift to S
+                        rescale(exp(S - sigma));
+                        sigma = S;
+                    }
+                    w = exp_weight<ExpFma>(sigma - S);
+                } else {
+                    w = exp_weight<ExpFma>(-S);
+                }
                 const double t = pr_scale * w;
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
@@ -464,11 +493,11 @@ __global__ void __launch_bounds__(BLOCK)
             samples(std::false_type{});
 
         // ---- reduction: wavefront butterflies, then waves in order through LDS
-        float wave_sigma = 0.0f;
-        if constexpr (PREC != kFP64) {
+        Sig wave_sigma = Sig(0);
+        if constexpr (kShifted) {
             wave_sigma = dev::wave_min(sigma);
             // lanes that took no sample hold sigma = inf and zero sums
-            rescale(sigma == __builtin_inff()
+            rescale(sigma == static_cast<Sig>(__builtin_inff())
                         ? 0.0
                         : exp(static_cast<double>(wave_sigma) - static_cast<double>(sigma)));
         }
@@ -482,12 +511,12 @@ __global__ void __launch_bounds__(BLOCK)
             red_sigma[wave] = wave_sigma;
         __syncthreads();
 
-        float block_sigma = 0.0f;
-        if constexpr (PREC != kFP64) {
+        Sig block_sigma = Sig(0);
+        if constexpr (kShifted) {
             block_sigma = red_sigma[0];
 #pragma unroll
             for (int w = 1; w < NW; ++w)
-                block_sigma = fminf(block_sigma, red_sigma[w]);
+                block_sigma = block_sigma < red_sigma[w] ? block_sigma : red_sigma[w];
         }
         double *rec = wi.rec;
         for (int i = tid; i < F::kOut; i += BLOCK) {
@@ -496,9 +525,9 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
                 double v = red[w][src];
-                if constexpr (PREC != kFP64) {
-                    const float ws = red_sigma[w];
-                    const double f1 = ws == __builtin_inff()
+                if constexpr (kShifted) {
+                    const Sig ws = red_sigma[w];
+                    const double f1 = ws == static_cast<Sig>(__builtin_inff())
                                           ? 0.0
                                           : exp(static_cast<double>(block_sigma) -
                                                 static_cast<double>(ws));
@@ -529,7 +558,7 @@ __global__ void __launch_bounds__(BLOCK)
 template <int NX, int NT, int PREC>
 __global__ void __launch_bounds__(256) debug_action_kernel(DebugActionArgs a)
 {
-    using T = std::conditional_t<PREC == kFP64, double, float>;
+    using T = std::conditional_t<PREC == kFP32Shifted, float, double>;
     constexpr int D = NX * NT;
     const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= a.n)
@@ -572,6 +601,22 @@ hipError_t info_one(KernelInfo *info)
     return hipSuccess;
 }
 
+template <int NX, int NT, int BLOCK, bool SPLIT, bool AVG, bool PAIR,
+          template <int, int, int, int, bool, bool, bool> class Op, class... Args>
+hipError_t by_prec(const LaunchSpec &spec, Args &&...args)
+{
+    switch (spec.prec) {
+    case kFP64:
+        return Op<NX, NT, kFP64, BLOCK, SPLIT, AVG, PAIR>::run(spec, args...);
+    case kFP32Shifted:
+        return Op<NX, NT, kFP32Shifted, BLOCK, SPLIT, AVG, PAIR>::run(spec, args...);
+    case kFP64Shifted:
+        return Op<NX, NT, kFP64Shifted, BLOCK, SPLIT, AVG, PAIR>::run(spec, args...);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
 // Dispatch over (precision, block, split) for this shape, observable and
 // sampler.  Split statistics are compiled for 256-thread blocks and d <= 32
 // only; antithetic pairs for d <= kMaxPairD and without split statistics.
@@ -584,9 +629,7 @@ hipError_t dispatch_obs(const LaunchSpec &spec, Args &&...args)
         if constexpr (D <= 32 && !PAIR) {
             if (spec.block != 256)
                 return hipErrorInvalidValue;
-            return spec.prec == kFP64
-                       ? Op<NX, NT, kFP64, 256, true, AVG, false>::run(spec, args...)
-                       : Op<NX, NT, kFP32Shifted, 256, true, AVG, false>::run(spec, args...);
+            return by_prec<NX, NT, 256, true, AVG, false, Op>(spec, args...);
         } else {
             return hipErrorNotSupported;
         }
@@ -594,17 +637,13 @@ hipError_t dispatch_obs(const LaunchSpec &spec, Args &&...args)
     if constexpr (PAIR && D > kMaxPairD) {
         return hipErrorNotSupported;
     } else {
-        const bool f64 = spec.prec == kFP64;
         switch (spec.block) {
         case 64:
-            return f64 ? Op<NX, NT, kFP64, 64, false, AVG, PAIR>::run(spec, args...)
-                       : Op<NX, NT, kFP32Shifted, 64, false, AVG, PAIR>::run(spec, args...);
+            return by_prec<NX, NT, 64, false, AVG, PAIR, Op>(spec, args...);
         case 128:
-            return f64 ? Op<NX, NT, kFP64, 128, false, AVG, PAIR>::run(spec, args...)
-                       : Op<NX, NT, kFP32Shifted, 128, false, AVG, PAIR>::run(spec, args...);
+            return by_prec<NX, NT, 128, false, AVG, PAIR, Op>(spec, args...);
         case 256:
-            return f64 ? Op<NX, NT, kFP64, 256, false, AVG, PAIR>::run(spec, args...)
-                       : Op<NX, NT, kFP32Shifted, 256, false, AVG, PAIR>::run(spec, args...);
+            return by_prec<NX, NT, 256, false, AVG, PAIR, Op>(spec, args...);
         default:
             return hipErrorInvalidValue;
         }
@@ -665,7 +704,7 @@ hipError_t launch_debug_action_shape(const DebugActionArgs &args, hipStream_t st
     const unsigned grid = static_cast<unsigned>((args.n + 255) / 256);
     if (grid == 0)
         return hipSuccess;
-    if (args.prec == kFP64)
+    if (args.prec != kFP32Shifted)
         hipLaunchKernelGGL((debug_action_kernel<NX, NT, kFP64>), dim3(grid), dim3(256), 0, stream,
                            args);
     else

@@ -73,7 +73,7 @@ bfi_status bfi_autotune(bfi_context *ctx, const bfi_lattice *lat, bfi_precision 
     return guarded([&]() -> bfi_status {
         if (!ctx)
             return fail(BFI_EINVAL, "context is NULL");
-        if (prec != BFI_FP64 && prec != BFI_FP32_SHIFTED)
+        if (!known_precision(prec))
             return fail(BFI_EINVAL, "unknown precision");
         BFI_TRY(check_lattice(lat));
         if (evals_per_trial < (uint64_t(1) << 16))
@@ -194,7 +194,7 @@ bfi_status bfi_tune_load(bfi_context *ctx, const char *path)
                 const int b = static_cast<int>(block);
                 if (shape_compiled(static_cast<int>(nx), static_cast<int>(nt)) && K >= 1 &&
                     K <= (1 << 20) && (b == 64 || b == 128 || b == 256) &&
-                    (prec == 0 || prec == 1) && (pairs == 0 || pairs == 1) &&
+                    (prec == 0 || prec == 1 || prec == 2) && (pairs == 0 || pairs == 1) &&
                     (obs == 0 || obs == 1)) {
                     bfi_launch l{static_cast<int32_t>(K), b, pers != 0 ? 1 : 0, 0};
                     ctx->tuned[TuneKey{static_cast<int>(nx), static_cast<int>(nt),

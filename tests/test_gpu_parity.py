@@ -8,13 +8,17 @@ Bars:
     rearranged but algebraically equal form); 1e-5 in the FP32 form.
   * Per-subvolume sums: relative 1e-10 of each sum's L1 scale (sample order and
     reduction tree differ from the oracle's sequential order).
-  * Z and C(r): 1e-6 relative (C(r) against C(0), an upper bound of the L1 scale
-    sum |p_r| w / sum w), in FP64; 1e-4 in the FP32 form.
+  * Z and C(r) against the oracle: Z (through log Z) within 1e-6 relative, C(r)
+    within 1e-6 of its L1 scale sum_s V_s/n_s sum |p_r w| / Z from the oracle's
+    L1 sums, in FP64; 1e-4 in the FP32 form (assert_result_close_l1).  GPU-vs-GPU
+    comparisons in other files measure C(r) against |C(0)|, an empirical scale.
+The benchmark's workloads at full size are in test_gpu_workloads.py.
 """
 import numpy as np
 import pytest
 
 import oracle
+import parity_util
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -52,10 +56,23 @@ def assert_sums_close(got, want, nx, rtol):
 
 
 def assert_result_close(got, want, tol):
+    """Z and C(r) within tol, C(r) measured against |C(0)|.  |C(0)| is an
+    empirical scale, not a bound of the L1 scale sum |p_r| w / sum w (with few
+    effective samples sum u_r^2 w can exceed sum u_0^2 w); the oracle
+    comparisons of this file use assert_result_close_l1 instead."""
     assert got["log_Z"] == pytest.approx(want["log_Z"], abs=tol)
     assert abs(got["Z"] - want["Z"]) <= tol * want["Z"]
     c0 = abs(want["C"][0])
     assert np.all(np.abs(got["C"] - want["C"]) <= tol * c0), (got["C"], want["C"])
+
+
+def assert_result_close_l1(got, want, tol, lat_o, sv, seed):
+    """Z, C(r) and C_err against the oracle's result, C(r) against its L1 scale
+    from the oracle's L1 sums over the same points."""
+    rec = oracle.sums_l1(lat_o, seed, sv.ids, sv.lo, sv.hi, sv.n, sv.offset)
+    L = oracle.sums_len(lat_o.nx)
+    scale = parity_util.c_scale(sv.lo, sv.hi, rec[:, :L], rec[:, L:])
+    parity_util.assert_result_close(got, want, scale, tol)
 
 
 # ---------------------------------------------------------------- points
@@ -132,7 +149,7 @@ def test_config_4x2_full(bfi, ctx):
     assert_sums_close(unshift(got, 4), want, 4, 1e-10)
     res_o = oracle.finalize(4, 8, sv.lo, sv.hi, want)
     res_g = bfi.bfi_finalize(bfi.lattice(4, 2), sv, got)
-    assert_result_close(res_g, res_o, 1e-6)
+    assert_result_close_l1(res_g, res_o, 1e-6, lat_o, sv, w.seed)
     np.testing.assert_allclose(res_g["C_err"], res_o["C_err"], rtol=1e-6)
     # bfi_integrate makes the same plan
     res_i = bfi.bfi_integrate(ctx, bfi.lattice(4, 2), F64, w.seed, -w.box, w.box, w.split_log2,
@@ -176,8 +193,8 @@ def test_counter_upper_word_boundaries(bfi, ctx, nx, nt, obs):
     got = bfi.bfi_eval(ctx, lat, F64, 11, sv, bfi.launch(8, 64, 0))
     assert_sums_close(unshift(got, nx), want, nx, 1e-10)
     got32 = bfi.bfi_eval(ctx, lat, F32, 11, sv, bfi.launch(8, 64, 1))
-    assert_result_close(bfi.bfi_finalize(lat, sv, got32), oracle.finalize(nx, d, sv.lo, sv.hi, want),
-                        1e-4)
+    assert_result_close_l1(bfi.bfi_finalize(lat, sv, got32),
+                           oracle.finalize(nx, d, sv.lo, sv.hi, want), 1e-4, lat_o, sv, 11)
 
 
 @pytest.mark.parametrize("launch", [
@@ -218,7 +235,7 @@ def test_fp32_shifted_form_error(bfi, ctx, nx, nt, box):
     lat_o, want, got = oracle_and_gpu(bfi, ctx, nx, nt, sv, 1, prec=F32)
     res_o = oracle.finalize(nx, d, sv.lo, sv.hi, want)
     res_g = bfi.bfi_finalize(bfi.lattice(nx, nt), sv, got)
-    assert_result_close(res_g, res_o, 1e-4)
+    assert_result_close_l1(res_g, res_o, 1e-4, lat_o, sv, 1)
     assert np.all(np.isfinite(got))
 
 
@@ -303,68 +320,6 @@ def test_plan_writes_torch_buffer_on_torch_stream(bfi, ctx):
         assert np.array_equal(buf.cpu().numpy(), eager)
     finally:
         bfi.bfi_plan_destroy(plan)
-
-
-# ------------------------------------------------------- full-size samples
-
-def test_config_10x2_full_size_sampled(bfi, ctx):
-    """10x2, nu = 1, box [-4,4]^20, 2^30 points over 1024 subvolumes in the
-    benchmark's launch configuration; 6 subvolumes checked against the oracle."""
-    w = workloads.WORKLOADS["burgers10x2"]
-    sv = workloads.uniform_partition(w.d, w.box, w.split_log2, w.budget // w.n_sub)
-    lat = bfi.lattice(10, 2)
-    for prec in (F64, F32):
-        plan = bfi.bfi_plan_create(ctx, lat, prec, sv, bfi.launch(use_graph=1))
-        try:
-            bfi.bfi_plan_run(plan, w.seed)
-            got = bfi.bfi_plan_partials(plan, len(sv), 10)
-        finally:
-            bfi.bfi_plan_destroy(plan)
-        pick = np.array([0, 1, 511, 512, 700, 1023])
-        sub = sv.subset(pick)
-        want = oracle.sums(oracle.lattice(10, 2), w.seed, sub.ids, sub.lo, sub.hi, sub.n,
-                           sub.offset)
-        if prec == F64:
-            assert_sums_close(unshift(got[pick], 10), want, 10, 1e-10)
-            f64_result = bfi.bfi_finalize(lat, sv, got)
-        else:
-            r32 = bfi.bfi_finalize(lat, sv, got)
-            # same points: the FP32 form agrees with FP64 within the stated bound
-            assert_result_close(r32, f64_result, 1e-4)
-        assert got[:, 0].sum() == 2**30
-
-
-def test_config_16x4_full_size_sampled(bfi, ctx):
-    """16x4, nu = 0.5, box [-3,3]^64, 2^34 points over 4096 subvolumes (dims
-    0-11), in the benchmark's launch configuration (resident plan, tuned
-    shape): 3 whole subvolumes (2^22 points each) against the oracle, the FP32
-    form against FP64 on the same points."""
-    w = workloads.WORKLOADS["burgers16x4"]
-    sv = workloads.uniform_partition(w.d, w.box, w.split_log2, w.budget // w.n_sub)
-    lat = bfi.lattice(16, 4, nu=0.5)
-    res = {}
-    for prec in (F64, F32):
-        plan = bfi.bfi_plan_create(ctx, lat, prec, sv, bfi.launch(use_graph=1))
-        try:
-            bfi.bfi_plan_run(plan, w.seed)
-            got = bfi.bfi_plan_partials(plan, len(sv), 16)
-        finally:
-            bfi.bfi_plan_destroy(plan)
-        assert got[:, 0].sum() == 2**34
-        res[prec] = bfi.bfi_finalize(lat, sv, got)
-        if prec == F64:
-            # each picked subvolume's 2^22 points as 16 consecutive chunks of
-            # the oracle's (records of disjoint sample ranges add)
-            pick = np.array([0, 2047, 4095])
-            sub = sv.subset(pick)
-            chunks = 16
-            m = int(sub.n[0]) // chunks
-            want = oracle.sums(oracle.lattice(16, 4, nu=0.5), w.seed, np.repeat(sub.ids, chunks),
-                               np.repeat(sub.lo, chunks, axis=0), np.repeat(sub.hi, chunks, axis=0),
-                               m, np.tile(np.arange(chunks, dtype=np.uint64) * m, len(pick)))
-            want = want.reshape(len(pick), chunks, -1).sum(1)
-            assert_sums_close(unshift(got[pick], 16), want, 16, 1e-10)
-    assert_result_close(res[F32], res[F64], 1e-4)
 
 
 # ------------------------------------------------------------------ edges

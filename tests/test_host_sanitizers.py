@@ -1,6 +1,7 @@
 """The C ABI's host code under the compilers' sanitizers: the runtime sources
 are compiled with AddressSanitizer + UndefinedBehaviorSanitizer on the host side
-only (the device objects of the regular build are linked unchanged), and a
+only (the device objects of the regular build, and the allocation-free entry
+point's object, are linked unchanged), and a
 driver (`host_sanitize_driver.cpp`) calls the host-only entry points (status
 strings, shape table, finalize, record merging, the adaptive decision and their
 argument checks).  Any report fails the test.  No GPU: nothing here launches a
@@ -28,7 +29,7 @@ def test_host_entry_points_under_asan_ubsan(tmp_path):
         pytest.skip("hipcc not available")
     device = sorted(glob.glob(os.path.join(BUILD, "shape_*.o")) +
                     glob.glob(os.path.join(BUILD, "is_*.o")) +
-                    [os.path.join(BUILD, "common_kernels.o")])
+                    [os.path.join(BUILD, "common_kernels.o"), os.path.join(BUILD, "noalloc.o")])
     if not all(os.path.exists(p) for p in device) or len(device) < 3:
         pytest.skip("library not built")
     common = ["-O1", "-g", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
