@@ -83,8 +83,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="burgers10x2", choices=sorted(workloads.WORKLOADS))
-    ap.add_argument("--headline", default="fp32", choices=["fp64", "fp32"],
-                    help="form reported as value (fp32: FP32 action/exp, FP64 sums)")
+    ap.add_argument("--headline", default="fp64", choices=["fp64", "fp32"],
+                    help="form reported as value (fp64: the paper's double-precision "
+                         "arithmetic; fp32: FP32 action/exp, FP64 sums)")
     ap.add_argument("--cpu-samples-log2", type=int, default=None,
                     help="oracle sample: first 2^k samples of every subvolume (default: about "
                          "2^29 x 20/d evaluations in all, 10-15 s on 16 host threads)")
@@ -182,6 +183,8 @@ def run_form(bfi, torch, ctx, lat, sv, w, prec, steps, warmup, stream):
     step_ms = 1e3 * np.diff(np.concatenate([[t0], step_end]))
     return {"evals_per_s": steps * evals / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
             "step_ms_median": float(np.median(step_ms)), "step_ms_max": float(np.max(step_ms)),
+            "step_ms_each": [round(float(x), 3) for x in step_ms[:200]],
+            "kernel_ms_each": [round(float(x), 3) for x in kernel_ms[:200]],
             "kernel_ms": float(np.mean(kernel_ms)), "kernel_ms_min": float(np.min(kernel_ms)),
             "evals_per_step": evals, "result": res, "partials": part,
             "launch": {k: info[k] for k in ("samples_per_thread", "block", "persistent",
@@ -400,22 +403,71 @@ def measured_traffic(workload, form):
     return rec.get("bytes_per_launch", {}).get(form)
 
 
-def cpu_baseline(w, sv, k):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, sv, k, k_single=12):
+    """The FP64 oracle (plain C, one subvolume per thread at a time) on the first
+    2^k samples of every subvolume, on the host's CPU share: the CPUs this
+    process may run on, at most 16 (one GPU's share of the box).  Also timed on
+    one thread over the first 2^k_single samples.  Returns the baseline and the
+    oracle's sums over the sample (with the L1 fields), which the GPU forms are
+    then checked against on the same points."""
     import oracle
     sub = sv.subset(np.arange(len(sv)))
     if k is None:
         k = max(int(math.floor(math.log2(2**29 * 20 / w.d / len(sub)))), 1)
     per = min(int(sub.n[0]), 1 << k)
     sub.n[:] = per
-    threads = min(16, os.cpu_count() or 1)
+    avail = len(os.sched_getaffinity(0))
+    threads = max(1, min(16, avail))
+    lat = oracle.lattice(w.nx, w.nt, nu=w.nu, D=w.D)
     t0 = time.perf_counter()
-    oracle.sums(oracle.lattice(w.nx, w.nt, nu=w.nu, D=w.D), w.seed, sub.ids, sub.lo, sub.hi,
-                sub.n, sub.offset, nthreads=threads)
+    rec = oracle.sums_l1(lat, w.seed, sub.ids, sub.lo, sub.hi, sub.n, sub.offset,
+                         nthreads=threads)
     dt = time.perf_counter() - t0
     n = per * len(sub)
-    return {"value": n / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+    one = sub.subset(np.arange(len(sub)))
+    per1 = min(per, 1 << k_single)
+    one.n[:] = per1
+    t1 = time.perf_counter()
+    oracle.sums_l1(lat, w.seed, one.ids, one.lo, one.hi, one.n, one.offset, nthreads=1)
+    dt1 = time.perf_counter() - t1
+    base = {"value": n / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"first 2^{per.bit_length() - 1} samples of each of the {len(sub)} "
-                      f"subvolumes ({n} evals, {dt:.1f} s, FP64 scalar C, pthreads)"}
+                      f"subvolumes ({n} evals, {dt:.1f} s, FP64 scalar C oracle with L1 sums, "
+                      f"{threads} pthreads)",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(), "cpus_available": avail,
+            "value_1_thread": per1 * len(one) / dt1,
+            "sample_1_thread": f"first 2^{per1.bit_length() - 1} samples of each subvolume "
+                               f"({per1 * len(one)} evals, {dt1:.1f} s)"}
+    return base, sub, rec
+
+
+def error_vs_oracle(bfi, ctx, w, sub, rec):
+    """Each form on the GPU over the oracle's sample (same points): Z's relative
+    error, and the largest C(r) error over its L1 scale sum_s V_s/n_s sum |p_r w| / Z."""
+    import oracle
+    L = oracle.sums_len(w.nx)
+    plain, l1 = rec[:, :L], rec[:, L:]
+    ref = oracle.finalize(w.nx, w.d, sub.lo, sub.hi, plain)
+    v = np.prod(sub.hi - sub.lo, axis=1) / plain[:, 0]
+    scale = np.sum(v[:, None] * l1, axis=0) / np.sum(v * plain[:, 1])
+    lat = bfi.lattice(w.nx, w.nt, nu=w.nu, D=w.D)
+    out = {"points": int(sub.n.sum()), "oracle_Z": float(ref["Z"]),
+           "oracle_C": [float(c) for c in ref["C"]]}
+    for prec in ("fp64", "fp64s", "fp32"):
+        res = bfi.bfi_finalize(lat, sub, bfi.bfi_eval(ctx, lat, prec, w.seed, sub))
+        out[prec] = {"Z_rel": abs(res["log_Z"] - ref["log_Z"]),
+                     "C_over_L1_max": float(np.max(np.abs(res["C"] - ref["C"]) / scale))}
+    return out
 
 
 def main():
@@ -441,7 +493,11 @@ def main():
     torch.zeros(1 << 20, device="cuda:0").sum().item()
     torch.cuda.synchronize()
     forms = {}
-    for prec in ("fp64", "fp32"):
+    # the other form first: its steps bring the device to its running clocks, so
+    # no early step of the headline form pays for the ramp (a replay of 17-49 ms
+    # instead of 12 ms was seen among the first timed steps of the form run first)
+    order = ("fp32", "fp64") if args.headline == "fp64" else ("fp64", "fp32")
+    for prec in order:
         print(f"bench: {w.name} {prec} warmup {args.warmup} steps {args.steps}", file=sys.stderr,
               flush=True)
         forms[prec] = run_form(bfi, torch, ctx, lat, sv, w, prec, args.steps, args.warmup, stream)
@@ -497,9 +553,11 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                 "unit": "T FP64-rate lane slots/s", "frac": achieved / PEAK_SLOTS,
                 "traffic": measured_traffic(w.name, args.headline),
-                "kernel": "mc_kernel (graph replay: reset, kernel, merge, record copy)",
+                "kernel": f"mc_kernel {w.nx}x{w.nt} {args.headline} (graph replay: queue reset, "
+                          "kernel, merge, record copy; HIP events on the launch stream)",
                 "slots_per_eval": slots,
                 "kernel_ms": head["kernel_ms"],
+                "fp64_flops_per_eval": fp64_flops_per_eval(w.nx, w.nt),
                 "fp64_flop_frac": (fp64_flops_per_eval(w.nx, w.nt) * evals_per_launch /
                                    (forms["fp64"]["kernel_ms"] * 1e-3)) / PEAK_FP64}
     line = {
@@ -521,6 +579,7 @@ def main():
                    "work_items": head["n_items"]},
         "forms": {p: {"evals_per_s": f["evals_per_s"], "ms_per_step": f["ms_per_step"],
                       "step_ms_median": f["step_ms_median"], "step_ms_max": f["step_ms_max"],
+                      "step_ms_each": f["step_ms_each"], "kernel_ms_each": f["kernel_ms_each"],
                       "kernel_ms": f["kernel_ms"], "kernel_evals_per_s":
                           f["evals_per_step"] / (f["kernel_ms"] * 1e-3),
                       "valu_frac": valu_slots_per_eval(w.nx, w.nt, p) * f["evals_per_step"] /
@@ -565,7 +624,13 @@ def main():
             for (form, nu) in secs if form == "fp32" and ("fp64", nu) in secs}
     if not args.no_cpu_baseline:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(w, sv, args.cpu_samples_log2)
+        base, sub, rec = cpu_baseline(w, sv, args.cpu_samples_log2)
+        line["cpu_baseline"] = base
+        ctx = bfi.bfi_context_create(0)
+        if os.path.exists(args.tune_cache):
+            bfi.bfi_tune_load(ctx, args.tune_cache)
+        line["error_vs_oracle"] = error_vs_oracle(bfi, ctx, w, sub, rec)
+        bfi.bfi_context_destroy(ctx)
     print(json.dumps(line), flush=True)
 
 

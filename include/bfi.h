@@ -320,8 +320,9 @@ typedef struct {
                                has seen.  The run stops when the holdout estimate meets
                                the target (out then holds that estimate); otherwise the
                                running target is tightened by min(1/2, target / holdout
-                               error) and refinement goes on.  Holdout evaluations count
-                               against max_evals. */
+                               error) and refinement goes on: at most one check per
+                               round, so a failed check is never redrawn on the same
+                               leaves.  Holdout evaluations count against max_evals. */
     bfi_adaptive_progress_fn progress; /* called on the caller's thread during the run
                                    (NULL: none); must not call back into the library */
     void *progress_user;        /* passed to progress unchanged */
@@ -338,6 +339,12 @@ typedef struct {
                                holdout_seed */
     uint64_t holdout_seed;
     double holdout_rel_err; /* max_r sigma_C(r)/|C(0)| of the last holdout pass (0: none) */
+    double device_seconds;  /* time the device spent on the run's evaluations (events
+                               around each replay of the captured round sequence) */
+    int32_t graph_instantiations; /* executable graphs built: one per kernel variant
+                                     unless an in-place update was refused */
+    int32_t graph_updates;  /* replays after an in-place update of the captured
+                               sequence (one per evaluated list after the first) */
 } bfi_adaptive_stats;
 
 bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,

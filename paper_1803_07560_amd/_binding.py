@@ -93,7 +93,8 @@ class bfi_adaptive_stats(C.Structure):
     _fields_ = [("rounds", C.c_int32), ("leaves", C.c_uint64), ("evals", C.c_uint64),
                 ("rel_err", C.c_double), ("holdout_checks", C.c_int32),
                 ("holdout_used", C.c_int32), ("holdout_seed", C.c_uint64),
-                ("holdout_rel_err", C.c_double)]
+                ("holdout_rel_err", C.c_double), ("device_seconds", C.c_double),
+                ("graph_instantiations", C.c_int32), ("graph_updates", C.c_int32)]
 
 
 class bfi_server_config(C.Structure):
@@ -477,7 +478,9 @@ def bfi_integrate_adaptive(ctx, lat, prec, seed, box_lo, box_hi, cfg, launch_=No
     out.update({"status": STATUS[s], "rounds": st.rounds, "leaves": st.leaves, "evals": st.evals,
                 "rel_err": st.rel_err, "holdout_checks": st.holdout_checks,
                 "holdout_used": bool(st.holdout_used), "holdout_seed": st.holdout_seed,
-                "holdout_rel_err": st.holdout_rel_err,
+                "holdout_rel_err": st.holdout_rel_err, "device_seconds": st.device_seconds,
+                "graph_instantiations": st.graph_instantiations,
+                "graph_updates": st.graph_updates,
                 "partition": Subvolumes(ids[:k], llo[:k], lhi[:k], ln[:k], loff[:k], lat.d)})
     return out
 

@@ -28,7 +28,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "inclu
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops"]
 HOST_SOURCES = ["runtime.cpp", "tune.cpp", "adaptive.cpp", "server.cpp", "integrand.cpp",
-                "sampler.cpp"]
+                "sampler.cpp", "resident.cpp"]
 
 
 def shapes() -> list[tuple[int, int]]:

@@ -33,7 +33,9 @@
 // afresh under another seed; a failed check tightens the running target.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <limits>
 #include <numeric>
 
@@ -45,59 +47,34 @@ namespace {
 
 constexpr double kSplitGain = 0.9;
 
+// Product of the extents, in dimension order (the finalize's own volume).
+double box_volume(const double *lo, const double *hi, int d)
+{
+    double v = 1.0;
+    for (int k = 0; k < d; ++k)
+        v *= hi[k] - lo[k];
+    return v;
+}
+
 struct LeafAnalysis {
     double e = 0.0;        // contribution to the variance of C
     int best_dim = 0;      // j*
     double gain = 1.0;     // (sigma_L + sigma_U)(j*) / (2 sigma)
 };
 
-// Scale factors that move every record to the smallest shift of the list.
-std::vector<double> common_shift_factors(size_t count, const double *partials, int rec_len)
-{
-    double sig = std::numeric_limits<double>::infinity();
-    for (size_t s = 0; s < count; ++s)
-        sig = std::min(sig, partials[s * rec_len + 1]);
-    std::vector<double> f(count);
-    for (size_t s = 0; s < count; ++s)
-        f[s] = std::exp(sig - partials[s * rec_len + 1]);
-    return f;
-}
-
-// Contribution of every leaf to the variance of C, and the estimate itself.
+// Contribution of every leaf to the variance of C, and the estimate itself
+// (both from the finalize's two passes over the records).
 bfi_status analyse(int nx, int d, size_t count, const double *lo, const double *hi,
-                   const double *partials, std::vector<LeafAnalysis> *out, bfi_result *res)
+                   const double *partials, std::vector<LeafAnalysis> *out, bfi_result *res,
+                   const double *vol = nullptr)
 {
-    const int rec_len = BFI_PARTIAL_LEN(nx);
-    BFI_TRY(finalize_records(nx, d, count, lo, hi, partials, res));
-    const std::vector<double> f = common_shift_factors(count, partials, rec_len);
-    // Z in the common shift
-    double z = 0.0;
-    std::vector<double> V(count);
-    for (size_t s = 0; s < count; ++s) {
-        double vol = 1.0;
-        for (int k = 0; k < d; ++k)
-            vol *= hi[s * d + k] - lo[s * d + k];
-        V[s] = vol;
-        z += vol * f[s] * partials[s * rec_len + 2] / partials[s * rec_len];
-    }
-    out->assign(count, LeafAnalysis{});
-    for (size_t s = 0; s < count; ++s) {
-        const double *rec = partials + s * rec_len;
-        const double n = rec[0], nn = n * (n - 1.0), v2 = V[s] * V[s];
-        const double a = f[s], a2 = a * a;
-        const double sw = a * rec[2], sw2 = a2 * rec[3];
-        const double var_z = v2 * (sw2 - sw * sw / n) / nn;
-        double e = 0.0;
-        for (int r = 0; r < nx; ++r) {
-            const double C = res->C[r];
-            const double spw = a * rec[4 + r], spw2 = a2 * rec[4 + nx + r],
-                         spww = a2 * rec[4 + 2 * nx + r];
-            const double var_n = v2 * (spw2 - spw * spw / n) / nn;
-            const double cov = v2 * (spww - spw * sw / n) / nn;
-            e += var_n - 2.0 * C * cov + C * C * var_z;
-        }
-        (*out)[s].e = z > 0 ? std::max(e, 0.0) / (z * z) : 0.0;
-    }
+    thread_local std::vector<double> e;  // reused across rounds
+    if (e.size() < count)
+        e.resize(count);
+    BFI_TRY(finalize_records(nx, d, count, lo, hi, partials, res, 1, e.data(), vol));
+    out->resize(count);
+    for (size_t s = 0; s < count; ++s)
+        (*out)[s] = LeafAnalysis{e[s] >= 0.0 ? e[s] : 0.0, 0, 1.0};  // NaN ranks last
     return BFI_OK;
 }
 
@@ -159,28 +136,133 @@ int32_t leaf_action(std::vector<LeafAnalysis> &an, const SplitStats &st, size_t 
     return doubling_ok ? 0 : -1;
 }
 
-// Decide actions: -1 keep, 0 double, 1 + j split along j.
-// Decide actions: -1 keep, 0 double, 1 + j split along j.  *order gets the
-// leaves in ranking order (descending e, ties by lower id).
-void decide(std::vector<LeafAnalysis> &an, const SplitStats &st, const uint64_t *ids,
-            const uint64_t *n, const bfi_adaptive_config &cfg, int32_t *action,
-            std::vector<size_t> *order)
+// Leaves in ranking order (descending contribution e, ties by lower id), built
+// lazily: for e >= 0 the IEEE bit pattern orders like the value, so one
+// parallel pass counts the leaves per bucket of its top bits; a read at rank i
+// gathers whole buckets from the top (at least twice what was gathered before)
+// and sorts only those.  Whole buckets keep the order exact: the result is the
+// full sort's, but a round that refines the top few percent of millions of
+// leaves never sorts the rest.
+class Ranking {
+public:
+    Ranking(const std::vector<LeafAnalysis> &an, const uint64_t *ids) : an_(an), ids_(ids)
+    {
+        const size_t n = an.size();
+        nchunks_ = (n + kChunk - 1) / kChunk;
+        part_.assign(nchunks_, {});
+        std::vector<double> sums(nchunks_, 0.0);
+        for_chunks(nchunks_, [&](size_t c) {
+            part_[c].assign(kBuckets, 0);
+            const size_t i1 = std::min(n, (c + 1) * kChunk);
+            double sum = 0.0;
+            for (size_t s = c * kChunk; s < i1; ++s) {
+                ++part_[c][bucket(an[s].e)];
+                sum += an[s].e;
+            }
+            sums[c] = sum;
+        });
+        hist_.assign(kBuckets, 0);
+        for (const auto &h : part_)
+            for (size_t b = 0; b < kBuckets; ++b)
+                hist_[b] += h[b];
+        total_ = 0.0;
+        for (double x : sums)
+            total_ += x;
+        top_ = kBuckets;
+    }
+    size_t size() const { return an_.size(); }
+    // sum of e over every leaf (per-chunk sums in chunk order)
+    double total() const { return total_; }
+    // the leaf at rank i
+    size_t operator[](size_t i)
+    {
+        if (i >= keys_.size())
+            extend(i + 1);
+        return keys_[i].leaf;
+    }
+    // ranks read so far (every rank below it is final)
+    size_t sorted() const { return keys_.size(); }
+
+private:
+    static constexpr size_t kBuckets = size_t(1) << 15;  // sign bit 0: 15 top bits
+    static constexpr size_t kChunk = size_t(1) << 18;
+    struct Key {
+        double e;
+        uint64_t id;
+        size_t leaf;
+    };
+    static size_t bucket(double e)
+    {
+        uint64_t bits;
+        std::memcpy(&bits, &e, sizeof bits);
+        return static_cast<size_t>(bits >> 48);  // e >= 0 and not NaN (analyse)
+    }
+    static bool before(const Key &x, const Key &y)
+    {
+        return x.e != y.e ? x.e > y.e : x.id < y.id;
+    }
+    // Append buckets [lo, top_) in descending bucket order: every key goes
+    // straight to its place (bucket offset + the counts of earlier chunks in that
+    // bucket), then each bucket is sorted on its own; chunks and buckets run in
+    // parallel.
+    void extend(size_t want)
+    {
+        const size_t n = an_.size();
+        const size_t target = std::min(n, std::max({want, 2 * keys_.size(), size_t(4096)}));
+        size_t have = keys_.size(), lo = top_;
+        while (lo > 0 && have < target)
+            have += hist_[--lo];
+        const size_t hi = top_, start = keys_.size(), span = hi - lo;
+        std::vector<size_t> first(span + 1);  // start of bucket hi-1-k at first[k]
+        first[0] = start;
+        for (size_t k = 0; k < span; ++k)
+            first[k + 1] = first[k] + hist_[hi - 1 - k];
+        keys_.resize(first[span]);
+        for_chunks(nchunks_, [&](size_t c) {
+            std::vector<size_t> at(span);
+            for (size_t k = 0; k < span; ++k) {
+                size_t o = first[k];
+                for (size_t cc = 0; cc < c; ++cc)
+                    o += part_[cc][hi - 1 - k];
+                at[k] = o;
+            }
+            const size_t i1 = std::min(n, (c + 1) * kChunk);
+            for (size_t s = c * kChunk; s < i1; ++s) {
+                const size_t b = bucket(an_[s].e);
+                if (b >= lo && b < hi)
+                    keys_[at[hi - 1 - b]++] = Key{an_[s].e, ids_[s], s};
+            }
+        });
+        for_chunks(span, [&](size_t k) {
+            if (first[k + 1] - first[k] > 1)
+                std::sort(keys_.begin() + static_cast<std::ptrdiff_t>(first[k]),
+                          keys_.begin() + static_cast<std::ptrdiff_t>(first[k + 1]), before);
+        });
+        top_ = lo;
+    }
+    const std::vector<LeafAnalysis> &an_;
+    const uint64_t *ids_;
+    size_t nchunks_ = 0;
+    std::vector<std::vector<uint32_t>> part_;  // per chunk: leaves per bucket
+    std::vector<uint32_t> hist_;
+    std::vector<Key> keys_;
+    double total_ = 0.0;
+    size_t top_;  // buckets at or above it are in keys_
+};
+
+// Decide actions: -1 keep, 0 double, 1 + j split along j, for the leaves in
+// ranking order until their contributions reach refine_fraction of the total.
+// Returns the number of ranks examined; the refined leaves are among them.
+size_t decide(std::vector<LeafAnalysis> &an, const SplitStats &st, const uint64_t *ids,
+              const uint64_t *n, const bfi_adaptive_config &cfg, int32_t *action, Ranking &order)
 {
     const size_t count = an.size();
-    order->resize(count);
-    std::iota(order->begin(), order->end(), 0);
-    std::sort(order->begin(), order->end(), [&](size_t x, size_t y) {
-        if (an[x].e != an[y].e)
-            return an[x].e > an[y].e;
-        return ids[x] < ids[y];
-    });
-    double total = 0.0;
-    for (const auto &a : an)
-        total += a.e;
-    std::fill(action, action + count, -1);
+    const double total = order.total();
+    parallel_range(count, size_t(1) << 18, [&](size_t s) { action[s] = -1; });
     double taken = 0.0;
-    for (size_t i = 0; i < count; ++i) {
-        const size_t s = (*order)[i];
+    size_t i = 0;
+    for (; i < count; ++i) {
+        const size_t s = order[i];
         if (i > 0 && taken >= cfg.refine_fraction * total)
             break;
         if (an[s].e <= 0.0 && i > 0)
@@ -188,6 +270,7 @@ void decide(std::vector<LeafAnalysis> &an, const SplitStats &st, const uint64_t 
         taken += an[s].e;
         action[s] = leaf_action(an, st, s, ids[s], n[s], cfg);
     }
+    return i;
 }
 
 bfi_status check_config(const bfi_adaptive_config *cfg)
@@ -243,12 +326,82 @@ void record_fields(int nx, std::vector<int> *first, std::vector<int> *second)
     }
 }
 
+// An allocator whose default construction leaves elements uninitialized: the
+// leaf set and the round buffers write every element before reading it, so
+// growing them costs no fill.
+template <class T>
+struct NoInit : std::allocator<T> {
+    using std::allocator<T>::allocator;
+    template <class U>
+    struct rebind {
+        using other = NoInit<U>;
+    };
+    template <class U>
+    void construct(U *) noexcept
+    {
+    }
+    template <class U, class... A>
+    void construct(U *p, A &&...a)
+    {
+        ::new (static_cast<void *>(p)) U(std::forward<A>(a)...);
+    }
+};
+template <class T>
+using RawVec = std::vector<T, NoInit<T>>;
+
+// A growable array of trivially copyable elements on malloc/realloc: past the
+// allocator's mmap threshold, growth remaps pages instead of copying them, so a
+// leaf set of gigabytes grows without being copied; new elements are not
+// initialised.
+template <class T>
+class GrowArray {
+public:
+    GrowArray() = default;
+    GrowArray(const GrowArray &) = delete;
+    GrowArray &operator=(const GrowArray &) = delete;
+    ~GrowArray() { std::free(p_); }
+    size_t size() const { return n_; }
+    size_t capacity() const { return cap_; }
+    T *data() { return p_; }
+    const T *data() const { return p_; }
+    T &operator[](size_t i) { return p_[i]; }
+    const T &operator[](size_t i) const { return p_[i]; }
+    T *begin() { return p_; }
+    T *end() { return p_ + n_; }
+    const T *begin() const { return p_; }
+    const T *end() const { return p_ + n_; }
+    void resize(size_t n)
+    {
+        if (n > cap_) {
+            const size_t c = std::max(n, 2 * cap_);
+            void *q = std::realloc(p_, c * sizeof(T));
+            if (!q)
+                throw std::bad_alloc();
+            p_ = static_cast<T *>(q);
+            cap_ = c;
+        }
+        n_ = n;
+    }
+    template <class It>
+    void assign(It b, It e)
+    {
+        resize(static_cast<size_t>(e - b));
+        std::copy(b, e, p_);
+    }
+
+private:
+    static_assert(std::is_trivially_copyable<T>::value, "plain data only");
+    T *p_ = nullptr;
+    size_t n_ = 0, cap_ = 0;
+};
+
 struct LeafSet {
     int d = 0, nx = 0;
-    std::vector<uint64_t> id, n;
+    GrowArray<uint64_t> id, n;
     // rec: all samples; split and base: split statistics and the record of the
     // samples they cover (the first split_samples of the leaf's stream)
-    std::vector<double> lo, hi, rec, split, base;
+    GrowArray<double> lo, hi, rec, split, base;
+    GrowArray<double> vol;  // product of the extents, computed once per leaf
     size_t size() const { return id.size(); }
 };
 
@@ -265,64 +418,90 @@ void merge_record(double *a, const double *b, int len, const std::vector<int> &f
     merge_shifted(a, b, 1, first, second, 0);
 }
 
+// The two resident evaluators of a run: the kernel variant with split
+// statistics and the plain kernel, each with its buffers and captured graph
+// kept from round to round; and the host buffers of their results.
+struct Evaluators {
+    ResidentEval with, without;
+    RawVec<double> r_with, sp_with, r_without;
+    // the round's work list results, kept between rounds so their pages are
+    // mapped once (fresh buffers of this size would fault in every round)
+    GrowArray<double> wrec, wsplit, wbase;
+    double device_ms = 0.0;  // replay time of every list so far
+};
+
+constexpr size_t kGrain = 2048;  // entries per chunk of the parallel host loops
+
 // Evaluate a work list on the device.  The samples below index `split_samples`
 // of each stream (all of them when 0) go through the kernel variant with split
 // statistics, the rest through the plain kernel.  Per entry: rec covers all its
 // samples, base and split the ones with statistics (count 0 and zeros if none).
-bfi_status eval_list(bfi_context *ctx, const bfi_lattice &lat, int prec, uint64_t seed,
-                     const SubList &work, uint64_t split_samples, const bfi_launch *launch,
-                     std::vector<double> *rec, std::vector<double> *split,
-                     std::vector<double> *base)
+bfi_status eval_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, const SubList &work,
+                     uint64_t split_samples, GrowArray<double> *rec, GrowArray<double> *split,
+                     GrowArray<double> *base)
 {
     const int d = lat.nx * lat.nt, rec_len = BFI_PARTIAL_LEN(lat.nx), split_len = BFI_SPLIT_LEN(d);
     const size_t count = work.size();
-    rec->assign(count * rec_len, 0.0);
-    split->assign(count * split_len, 0.0);
-    base->assign(count * rec_len, 0.0);
-    // the two lists: entry w's covered part [offset, min(end, P)) and the rest
-    SubList with, without;
-    with.d = without.d = d;
-    std::vector<size_t> with_of, without_of;
+    // entry w's covered part [offset, min(end, P)) goes to the first list at
+    // wpos[w], the rest to the second at opos[w] (-1: no such part)
+    std::vector<int64_t> wpos(count, -1), opos(count, -1);
+    std::vector<uint64_t> cut(count);
+    int64_t nw = 0, no = 0;
     for (size_t w = 0; w < count; ++w) {
         const uint64_t off = work.offset[w], end = off + work.n[w];
-        const uint64_t cut = split_samples == 0 ? end : std::min(std::max(split_samples, off), end);
-        const uint64_t parts[2][2] = {{off, cut}, {cut, end}};
-        for (int k = 0; k < 2; ++k) {
-            if (parts[k][1] <= parts[k][0])
-                continue;
-            SubList &dst = k == 0 ? with : without;
-            (k == 0 ? with_of : without_of).push_back(w);
-            dst.id.push_back(work.id[w]);
-            dst.offset.push_back(parts[k][0]);
-            dst.n.push_back(parts[k][1] - parts[k][0]);
-            dst.lo.insert(dst.lo.end(), &work.lo[w * d], &work.lo[w * d] + d);
-            dst.hi.insert(dst.hi.end(), &work.hi[w * d], &work.hi[w * d] + d);
-        }
+        cut[w] = split_samples == 0 ? end : std::min(std::max(split_samples, off), end);
+        if (cut[w] > off)
+            wpos[w] = nw++;
+        if (end > cut[w])
+            opos[w] = no++;
+    }
+    BFI_TRY(ev->with.stage(static_cast<size_t>(nw)));
+    BFI_TRY(ev->without.stage(static_cast<size_t>(no)));
+    parallel_range(count, kGrain, [&](size_t w) {
+        const uint64_t off = work.offset[w], end = off + work.n[w];
+        const double *lo = &work.lo[w * d], *hi = &work.hi[w * d];
+        if (wpos[w] >= 0)
+            ev->with.set(static_cast<size_t>(wpos[w]), work.id[w], off, cut[w] - off, lo, hi);
+        if (opos[w] >= 0)
+            ev->without.set(static_cast<size_t>(opos[w]), work.id[w], cut[w], end - cut[w], lo, hi);
+    });
+    if (nw > 0) {
+        TraceRange tr("adaptive: samples with split statistics");
+        ev->r_with.resize(static_cast<size_t>(nw) * rec_len);
+        ev->sp_with.resize(static_cast<size_t>(nw) * split_len);
+        double ms = 0.0;
+        BFI_TRY(ev->with.run(seed, ev->r_with.data(), ev->sp_with.data(), &ms));
+        ev->device_ms += ms;
+    }
+    if (no > 0) {
+        TraceRange tr("adaptive: samples through the plain kernel");
+        ev->r_without.resize(static_cast<size_t>(no) * rec_len);
+        double ms = 0.0;
+        BFI_TRY(ev->without.run(seed, ev->r_without.data(), nullptr, &ms));
+        ev->device_ms += ms;
     }
     std::vector<int> first, second;
     record_fields(lat.nx, &first, &second);
-    if (with.size() > 0) {
-        TraceRange tr("adaptive: samples with split statistics");
-        std::vector<double> r(with.size() * rec_len), sp(with.size() * split_len);
-        bfi_subvolumes v = with.view();
-        BFI_TRY(bfi_eval(ctx, &lat, static_cast<bfi_precision>(prec), seed, &v, launch, r.data(),
-                         sp.data()));
-        for (size_t i = 0; i < with.size(); ++i) {
-            const size_t w = with_of[i];
-            std::copy(&r[i * rec_len], &r[i * rec_len] + rec_len, &(*base)[w * rec_len]);
-            std::copy(&r[i * rec_len], &r[i * rec_len] + rec_len, &(*rec)[w * rec_len]);
-            std::copy(&sp[i * split_len], &sp[i * split_len] + split_len, &(*split)[w * split_len]);
+    rec->resize(count * rec_len);
+    split->resize(count * split_len);
+    base->resize(count * rec_len);
+    parallel_range(count, kGrain, [&](size_t w) {
+        double *R = &(*rec)[w * rec_len], *B = &(*base)[w * rec_len], *P = &(*split)[w * split_len];
+        if (wpos[w] >= 0) {
+            const double *r = &ev->r_with[static_cast<size_t>(wpos[w]) * rec_len];
+            std::copy(r, r + rec_len, B);
+            std::copy(r, r + rec_len, R);
+            const double *sp = &ev->sp_with[static_cast<size_t>(wpos[w]) * split_len];
+            std::copy(sp, sp + split_len, P);
+        } else {
+            std::fill(B, B + rec_len, 0.0);
+            std::fill(R, R + rec_len, 0.0);
+            std::fill(P, P + split_len, 0.0);
         }
-    }
-    if (without.size() > 0) {
-        TraceRange tr("adaptive: samples through the plain kernel");
-        std::vector<double> r(without.size() * rec_len);
-        bfi_subvolumes v = without.view();
-        BFI_TRY(bfi_eval(ctx, &lat, static_cast<bfi_precision>(prec), seed, &v, launch, r.data(),
-                         nullptr));
-        for (size_t i = 0; i < without.size(); ++i)
-            merge_record(&(*rec)[without_of[i] * rec_len], &r[i * rec_len], rec_len, first, second);
-    }
+        if (opos[w] >= 0)
+            merge_record(R, &ev->r_without[static_cast<size_t>(opos[w]) * rec_len], rec_len, first,
+                         second);
+    });
     return BFI_OK;
 }
 
@@ -370,12 +549,18 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         LeafSet L;
         L.d = d;
         L.nx = nx;
-        L.id = init.id;
-        L.n = init.n;
-        L.lo = init.lo;
-        L.hi = init.hi;
-        BFI_TRY(eval_list(ctx, *lat, prec, seed, init, cfg->split_samples, launch, &L.rec,
-                          &L.split, &L.base));
+        L.id.assign(init.id.begin(), init.id.end());
+        L.n.assign(init.n.begin(), init.n.end());
+        L.lo.assign(init.lo.begin(), init.lo.end());
+        L.hi.assign(init.hi.begin(), init.hi.end());
+        L.vol.resize(L.size());
+        for (size_t s = 0; s < L.size(); ++s)
+            L.vol[s] = box_volume(&L.lo[s * d], &L.hi[s * d], d);
+        BFI_HIP(hipSetDevice(ctx->device));
+        Evaluators ev;
+        BFI_TRY(ev.with.init(ctx, *lat, prec, true, launch));
+        BFI_TRY(ev.without.init(ctx, *lat, prec, false, launch));
+        BFI_TRY(eval_list(&ev, *lat, seed, init, cfg->split_samples, &L.rec, &L.split, &L.base));
 
         bfi_status status = BFI_OK;
         const double min_ess = cfg->min_ess > 0 ? cfg->min_ess : 100.0;
@@ -392,58 +577,69 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             bfi_adaptive_progress p{rounds, checks, L.size(), evals, running, holdout_err};
             cfg->progress(&p, cfg->progress_user);
         };
+        // round buffers, kept between rounds (their pages stay mapped)
+        struct Origin {
+            size_t leaf;
+            int kind;  // 0 continuation, 1 lower child, 2 upper child
+        };
+        SubList work;
+        std::vector<Origin> origin;
+        std::vector<size_t> first_entry, dst, refined;
+        std::vector<int32_t> action;
+        std::vector<uint64_t> target;
         for (;;) {
             TracePhases phase("adaptive: analyse");
-            BFI_TRY(analyse(nx, d, L.size(), L.lo.data(), L.hi.data(), L.rec.data(), &an, &res));
+            BFI_TRY(analyse(nx, d, L.size(), L.lo.data(), L.hi.data(), L.rec.data(), &an, &res,
+                            L.vol.data()));
             report(rel_err(res));
             // stop check; with holdout, a failed check tightens the running target
-            // and is retried on the same leaves only while the running estimate
-            // still meets it
+            // and refinement goes on: the next check comes after at least one more
+            // round, never on the same leaves again (a fresh draw over unchanged
+            // leaves until one meets the target would select among draws)
             bool stop = false;
-            while (!stop && rel_err(res) <= run_target && res.ess >= min_ess) {
+            if (rel_err(res) <= run_target && res.ess >= min_ess) {
                 if (!cfg->holdout) {
                     stop = true;
-                    break;
+                } else {
+                    phase.next("adaptive: holdout pass");
+                    // holdout check: the same leaves, samples drawn afresh under a
+                    // seed of their own, so no refinement decision has seen them
+                    uint64_t cost = 0;
+                    for (uint64_t n : L.n)
+                        cost += n;
+                    if (cost > cfg->max_evals - evals) {
+                        status = BFI_EBUDGET;
+                        stop = true;
+                    } else {
+                        ++checks;
+                        const uint64_t hseed =
+                            seed + static_cast<uint64_t>(checks) * 0x9E3779B97F4A7C15ull;
+                        std::vector<double> hrec(L.size() * rec_len);
+                        BFI_TRY(ev.without.stage(L.size()));
+                        parallel_range(L.size(), kGrain, [&](size_t s) {
+                            ev.without.set(s, L.id[s], 0, L.n[s], &L.lo[s * d], &L.hi[s * d]);
+                        });
+                        double hms = 0.0;
+                        BFI_TRY(ev.without.run(hseed, hrec.data(), nullptr, &hms));
+                        ev.device_ms += hms;
+                        evals += cost;
+                        bfi_result hres{};
+                        BFI_TRY(finalize_records(nx, d, L.size(), L.lo.data(), L.hi.data(),
+                                                 hrec.data(), &hres, 1, nullptr, L.vol.data()));
+                        const double herr = rel_err(hres);
+                        holdout_err = herr;
+                        report(rel_err(res));
+                        if (herr <= cfg->target_rel_err && hres.ess >= min_ess) {
+                            res = hres;
+                            holdout_used = true;
+                            holdout_seed = hseed;
+                            stop = true;
+                        } else {
+                            // the running estimate was optimistic: ask more of it
+                            run_target *= std::min(0.5, cfg->target_rel_err / herr);
+                        }
+                    }
                 }
-                phase.next("adaptive: holdout pass");
-                // holdout check: the same leaves, samples drawn afresh under a
-                // seed of their own, so no refinement decision has seen them
-                uint64_t cost = 0;
-                for (uint64_t n : L.n)
-                    cost += n;
-                if (cost > cfg->max_evals - evals) {
-                    status = BFI_EBUDGET;
-                    stop = true;
-                    break;
-                }
-                ++checks;
-                const uint64_t hseed = seed + static_cast<uint64_t>(checks) * 0x9E3779B97F4A7C15ull;
-                SubList fresh;
-                fresh.d = d;
-                fresh.id = L.id;
-                fresh.n = L.n;
-                fresh.offset.assign(L.size(), 0);
-                fresh.lo = L.lo;
-                fresh.hi = L.hi;
-                std::vector<double> hrec(L.size() * rec_len);
-                bfi_subvolumes v = fresh.view();
-                BFI_TRY(bfi_eval(ctx, lat, prec, hseed, &v, launch, hrec.data(), nullptr));
-                evals += cost;
-                bfi_result hres{};
-                BFI_TRY(finalize_records(nx, d, L.size(), L.lo.data(), L.hi.data(), hrec.data(),
-                                         &hres));
-                const double herr = rel_err(hres);
-                holdout_err = herr;
-                report(rel_err(res));
-                if (herr <= cfg->target_rel_err && hres.ess >= min_ess) {
-                    res = hres;
-                    holdout_used = true;
-                    holdout_seed = hseed;
-                    stop = true;
-                    break;
-                }
-                // the running estimate was optimistic: ask more of it
-                run_target *= std::min(0.5, cfg->target_rel_err / herr);
             }
             if (stop)
                 break;
@@ -453,15 +649,21 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             }
             phase.next("adaptive: decide and plan");
             const SplitStats st{d, rec_len, L.split.data(), L.base.data()};
-            std::vector<int32_t> action(L.size());
-            std::vector<size_t> order;
-            decide(an, st, L.id.data(), L.n.data(), *cfg, action.data(), &order);
+            action.resize(L.size());
+            Ranking order(an, L.id.data());
+            const size_t examined =
+                decide(an, st, L.id.data(), L.n.data(), *cfg, action.data(), order);
+            // the refined leaves in rank order (planning loops over these only)
+            refined.clear();
+            for (size_t i = 0; i < examined; ++i)
+                if (action[order[i]] >= 0)
+                    refined.push_back(order[i]);
 
             // planned sample counts: children clamp(n, n_min, n_max) each, doubled
             // leaves 2n; scaled by a power of two up to the round's work floor
             // planned count of a refined leaf at scale factor f (within n_max):
             // children clamp(n, n_min, n_max) each, doubled leaves 2n, times f
-            std::vector<uint64_t> target(L.size(), 0);  // new per-leaf (or per-child) count
+            target.resize(L.size());  // new per-leaf (or per-child) count, refined leaves
             auto leaf_target = [&](size_t s, uint64_t f) {
                 const uint64_t base = action[s] == 0 ? 2 * L.n[s]
                                                       : std::min(std::max(L.n[s], cfg->n_min),
@@ -482,9 +684,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             auto plan_all = [&]() {
                 planned = 0;
                 growable = 0;
-                for (size_t s = 0; s < L.size(); ++s) {
-                    if (action[s] < 0)
-                        continue;
+                for (size_t s : refined) {
                     target[s] = leaf_target(s, f);
                     planned += leaf_cost(s);
                     growable += grows(s, f);
@@ -511,16 +711,19 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                     action[s] = -2;  // neither split nor doubling possible: skip it
                     continue;
                 }
+                refined.push_back(s);
                 target[s] = leaf_target(s, f);
                 planned += leaf_cost(s);
                 growable += grows(s, f);
             }
-            for (auto &a : action)
-                if (a == -2)
-                    a = -1;
-            // trim to the evaluation budget in priority order
+            for (size_t i = 0; i < order.sorted(); ++i)
+                if (action[order[i]] == -2)
+                    action[order[i]] = -1;
+            // trim to the evaluation budget in priority order (every refined leaf
+            // lies in the part of the ranking read so far)
             uint64_t cost = 0;
-            for (size_t s : order) {
+            for (size_t i = 0; i < order.sorted(); ++i) {
+                const size_t s = order[i];
                 if (action[s] < 0)
                     continue;
                 const uint64_t c = action[s] == 0 ? target[s] - L.n[s] : 2 * target[s];
@@ -534,66 +737,80 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                 break;
             }
 
-            // work list: children (fresh streams) and continuations
-            SubList work;
-            work.d = d;
-            struct Origin {
-                size_t leaf;
-                int kind;  // 0 continuation, 1 lower child, 2 upper child
-            };
-            std::vector<Origin> origin;
+            // work list: children (fresh streams) and continuations, each refined
+            // leaf's entries at a precomputed position, filled in parallel
+            phase.next("adaptive: work list");
+            first_entry.resize(L.size());
+            size_t entries = 0;
             for (size_t s = 0; s < L.size(); ++s) {
+                first_entry[s] = entries;
+                if (action[s] >= 0)
+                    entries += action[s] == 0 ? 1 : 2;
+            }
+            work.d = d;
+            work.id.resize(entries);
+            work.n.resize(entries);
+            work.offset.resize(entries);
+            work.lo.resize(entries * d);
+            work.hi.resize(entries * d);
+            origin.resize(entries);
+            parallel_range(L.size(), kGrain, [&](size_t s) {
                 if (action[s] < 0)
-                    continue;
+                    return;
                 const double *lo = &L.lo[s * d], *hi = &L.hi[s * d];
+                const size_t e = first_entry[s];
                 if (action[s] == 0) {
-                    work.id.push_back(L.id[s]);
-                    work.n.push_back(target[s] - L.n[s]);
-                    work.offset.push_back(L.n[s]);
-                    work.lo.insert(work.lo.end(), lo, lo + d);
-                    work.hi.insert(work.hi.end(), hi, hi + d);
-                    origin.push_back({s, 0});
-                    continue;
+                    work.id[e] = L.id[s];
+                    work.n[e] = target[s] - L.n[s];
+                    work.offset[e] = L.n[s];
+                    std::copy(lo, lo + d, &work.lo[e * d]);
+                    std::copy(hi, hi + d, &work.hi[e * d]);
+                    origin[e] = {s, 0};
+                    return;
                 }
                 const int j = action[s] - 1;
                 const double mid = 0.5 * (lo[j] + hi[j]);
-                const uint64_t child_n = target[s];
                 for (int half = 0; half < 2; ++half) {
-                    work.id.push_back(2 * L.id[s] + half);
-                    work.n.push_back(child_n);
-                    work.offset.push_back(0);
-                    work.lo.insert(work.lo.end(), lo, lo + d);
-                    work.hi.insert(work.hi.end(), hi, hi + d);
+                    const size_t w = e + half;
+                    work.id[w] = 2 * L.id[s] + half;
+                    work.n[w] = target[s];
+                    work.offset[w] = 0;
+                    std::copy(lo, lo + d, &work.lo[w * d]);
+                    std::copy(hi, hi + d, &work.hi[w * d]);
                     if (half == 0)
-                        work.hi[(work.id.size() - 1) * d + j] = mid;
+                        work.hi[w * d + j] = mid;
                     else
-                        work.lo[(work.id.size() - 1) * d + j] = mid;
-                    origin.push_back({s, 1 + half});
+                        work.lo[w * d + j] = mid;
+                    origin[w] = {s, 1 + half};
                 }
-            }
+            });
             phase.next("adaptive: evaluate");
-            std::vector<double> wrec, wsplit, wbase;
-            BFI_TRY(eval_list(ctx, *lat, prec, seed, work, cfg->split_samples, launch, &wrec,
-                              &wsplit, &wbase));
+            GrowArray<double> &wrec = ev.wrec, &wsplit = ev.wsplit, &wbase = ev.wbase;
+            BFI_TRY(eval_list(&ev, *lat, seed, work, cfg->split_samples, &wrec, &wsplit, &wbase));
             evals += cost;
 
             phase.next("adaptive: fold");
             // fold the results into the leaf set in place: a doubled leaf merges
             // its continuation, a split leaf becomes its lower child and its upper
-            // child is appended (work proportional to the round's work list)
-            size_t uppers = 0;
-            for (const Origin &o : origin)
-                uppers += o.kind == 2;
-            const size_t grown = L.size() + uppers;
-            L.id.reserve(grown);
-            L.n.reserve(grown);
-            L.lo.reserve(grown * d);
-            L.hi.reserve(grown * d);
-            L.rec.reserve(grown * rec_len);
-            L.split.reserve(grown * split_len);
-            L.base.reserve(grown * rec_len);
-            for (size_t w = 0; w < origin.size(); ++w) {
-                const size_t s = origin[w].leaf;
+            // child is appended; every entry has its own destination, so the
+            // entries are folded in parallel
+            dst.resize(origin.size());
+            size_t grown = L.size();
+            for (size_t w = 0; w < origin.size(); ++w)
+                dst[w] = origin[w].kind == 2 ? grown++ : origin[w].leaf;
+            // capacity grows geometrically and by remapping: an exact reserve, or a
+            // copying one, would move the whole leaf set (gigabytes at millions of
+            // leaves) every round
+            L.id.resize(grown);
+            L.n.resize(grown);
+            L.lo.resize(grown * d);
+            L.hi.resize(grown * d);
+            L.rec.resize(grown * rec_len);
+            L.split.resize(grown * split_len);
+            L.base.resize(grown * rec_len);
+            L.vol.resize(grown);
+            parallel_range(origin.size(), kGrain, [&](size_t w) {
+                const size_t s = dst[w];
                 const double *wr = &wrec[w * rec_len], *ws = &wsplit[w * split_len],
                              *wb = &wbase[w * rec_len];
                 if (origin[w].kind == 0) {
@@ -605,24 +822,17 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                         merge_shifted(&L.base[s * rec_len], wb, 1, rec_first, rec_second, 0);
                     }
                     L.n[s] = target[s];
-                } else if (origin[w].kind == 1) {
-                    L.id[s] = work.id[w];
-                    L.n[s] = work.n[w];
-                    std::copy(&work.lo[w * d], &work.lo[w * d] + d, &L.lo[s * d]);
-                    std::copy(&work.hi[w * d], &work.hi[w * d] + d, &L.hi[s * d]);
-                    std::copy(wr, wr + rec_len, &L.rec[s * rec_len]);
-                    std::copy(ws, ws + split_len, &L.split[s * split_len]);
-                    std::copy(wb, wb + rec_len, &L.base[s * rec_len]);
-                } else {
-                    L.id.push_back(work.id[w]);
-                    L.n.push_back(work.n[w]);
-                    L.lo.insert(L.lo.end(), &work.lo[w * d], &work.lo[w * d] + d);
-                    L.hi.insert(L.hi.end(), &work.hi[w * d], &work.hi[w * d] + d);
-                    L.rec.insert(L.rec.end(), wr, wr + rec_len);
-                    L.split.insert(L.split.end(), ws, ws + split_len);
-                    L.base.insert(L.base.end(), wb, wb + rec_len);
+                    return;
                 }
-            }
+                L.id[s] = work.id[w];
+                L.n[s] = work.n[w];
+                std::copy(&work.lo[w * d], &work.lo[w * d] + d, &L.lo[s * d]);
+                std::copy(&work.hi[w * d], &work.hi[w * d] + d, &L.hi[s * d]);
+                L.vol[s] = box_volume(&L.lo[s * d], &L.hi[s * d], d);
+                std::copy(wr, wr + rec_len, &L.rec[s * rec_len]);
+                std::copy(ws, ws + split_len, &L.split[s * split_len]);
+                std::copy(wb, wb + rec_len, &L.base[s * rec_len]);
+            });
             ++rounds;
         }
 
@@ -636,6 +846,9 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             stats->holdout_used = holdout_used ? 1 : 0;
             stats->holdout_seed = holdout_seed;
             stats->holdout_rel_err = holdout_err;
+            stats->device_seconds = ev.device_ms * 1e-3;
+            stats->graph_instantiations = ev.with.instantiations() + ev.without.instantiations();
+            stats->graph_updates = ev.with.updates() + ev.without.updates();
         }
         if (n_leaves)
             *n_leaves = L.size();
@@ -681,8 +894,8 @@ bfi_status bfi_adaptive_decide(const bfi_lattice *lat, const bfi_subvolumes *lea
         bfi_result res;
         BFI_TRY(analyse(lat->nx, d, leaves->count, leaves->lo, leaves->hi, partials, &an, &res));
         const SplitStats st{d, BFI_PARTIAL_LEN(lat->nx), split, split_base ? split_base : partials};
-        std::vector<size_t> order;
-        decide(an, st, leaves->id, leaves->n, *cfg, action, &order);
+        Ranking order(an, leaves->id);
+        decide(an, st, leaves->id, leaves->n, *cfg, action, order);
         return BFI_OK;
     });
 }

@@ -1,9 +1,69 @@
-// Shape-independent kernels: queue reset, the ordered per-subvolume merge of
-// work-item records, and the point-emitting test hook.
+// Shape-independent kernels: work items and point maps built on the device, queue
+// reset, the ordered per-subvolume merge of work-item records, and the
+// point-emitting test hook.
 #include "device.hpp"
 
 namespace bfi {
 namespace {
+
+// First work item of every subvolume: an exclusive prefix sum of
+// ceil(n_s / chunk) in tiles of the block, one block for the whole list.
+constexpr int kScanBlock = 1024;
+__global__ void __launch_bounds__(kScanBlock)
+    first_items_kernel(const uint64_t *n, uint32_t nsub, uint64_t chunk, uint32_t *sub_first)
+{
+    __shared__ uint32_t tile[kScanBlock];
+    uint32_t carry = 0;
+    const uint32_t t = threadIdx.x;
+    for (uint32_t base = 0; base < nsub; base += kScanBlock) {
+        const uint32_t s = base + t;
+        const uint32_t cnt =
+            s < nsub ? static_cast<uint32_t>(n[s] / chunk + (n[s] % chunk != 0)) : 0u;
+        tile[t] = cnt;
+        __syncthreads();
+        // inclusive Hillis-Steele scan of the tile
+        for (uint32_t off = 1; off < kScanBlock; off <<= 1) {
+            const uint32_t add = t >= off ? tile[t - off] : 0u;
+            __syncthreads();
+            tile[t] += add;
+            __syncthreads();
+        }
+        if (s < nsub)
+            sub_first[s] = carry + tile[t] - cnt;
+        const uint32_t tile_total = tile[kScanBlock - 1];
+        __syncthreads();  // every read of the tile done before the next one is written
+        carry += tile_total;
+    }
+    if (t == 0)
+        sub_first[nsub] = carry;
+}
+
+// Point maps (scale = (hi - lo) 2^-32, base = lo + scale/2, then the FP32
+// copies) and work items of each subvolume: block b takes subvolumes b, b +
+// grid, ...  The arithmetic is the host's in bfi_eval, operation for operation.
+
+__global__ void __launch_bounds__(256) build_kernel(BuildArgs a)
+{
+    for (uint32_t s = blockIdx.x; s < a.nsub; s += gridDim.x) {
+        const size_t row = static_cast<size_t>(s) * a.d;
+        for (int k = threadIdx.x; k < a.d; k += blockDim.x) {
+            const double scale = (a.hi[row + k] - a.lo[row + k]) * 0x1p-32;
+            const double base = __dadd_rn(a.lo[row + k], 0.5 * scale);
+            a.scale64[row + k] = scale;
+            a.base64[row + k] = base;
+            a.scale32[row + k] = static_cast<float>(scale);
+            a.base32[row + k] = static_cast<float>(base);
+        }
+        const uint32_t i0 = a.sub_first[s], i1 = a.sub_first[s + 1];
+        const uint64_t n = a.n[s];
+        for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+            const uint64_t start = static_cast<uint64_t>(i - i0) * a.chunk;
+            const uint64_t cnt = n - start < a.chunk ? n - start : a.chunk;
+            a.items[i] = WorkItem{a.params, a.item_rec + static_cast<size_t>(i) * a.rec_len, start,
+                                  s, static_cast<uint32_t>(cnt)};
+        }
+    }
+}
 
 __global__ void reset_head_kernel(uint32_t *head)
 {
@@ -193,6 +253,20 @@ __global__ void __launch_bounds__(256) debug_points_kernel(DebugPointArgs a)
 }
 
 }  // namespace
+
+hipError_t launch_build_items(const BuildArgs &args, hipStream_t stream)
+{
+    if (args.nsub == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(first_items_kernel, dim3(1), dim3(kScanBlock), 0, stream, args.n, args.nsub,
+                       args.chunk, args.sub_first);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const uint32_t grid = args.nsub < 4096 ? args.nsub : 4096u;
+    hipLaunchKernelGGL(build_kernel, dim3(grid), dim3(256), 0, stream, args);
+    return hipGetLastError();
+}
 
 hipError_t launch_reset_head(uint32_t *head, hipStream_t stream)
 {

@@ -130,7 +130,27 @@ struct NsphereArgs {
     int32_t dim;
 };
 
+// Work items and point maps built on the device from a copied subvolume list
+// (n, lo, hi): sub_first[s] = first item of subvolume s (nsub + 1 entries, a
+// prefix sum of ceil(n_s / chunk)), then per subvolume the FP64 and FP32 maps
+// (scale = (hi - lo) 2^-32, base = lo + scale/2, as the host computes them) and
+// items of `chunk` consecutive samples whose records go to item_rec.
+struct BuildArgs {
+    const double *lo, *hi;
+    const uint64_t *n;
+    uint32_t *sub_first;
+    double *base64, *scale64;
+    float *base32, *scale32;
+    WorkItem *items;
+    const EvalParams *params;
+    double *item_rec;
+    uint64_t chunk;
+    uint32_t nsub;
+    int32_t d, rec_len;
+};
+
 // Shape-independent kernels (common_kernels.hip).
+hipError_t launch_build_items(const BuildArgs &args, hipStream_t stream);
 hipError_t launch_reset_head(uint32_t *head, hipStream_t stream);
 hipError_t launch_nsphere(const NsphereArgs &args, uint32_t grid, hipStream_t stream);
 hipError_t launch_merge(const MergeArgs &args, hipStream_t stream);

@@ -9,8 +9,8 @@
 // device with hipGetSymbolAddress when a context is created on that device
 // (noalloc_setup) and only that address is passed to kernels and copies: in
 // host code the array's name is a host-side stand-in, not device memory.
-// Point maps and work items are built on the device from the copied list, so
-// the host needs no staging either.  The kernels that evaluate, reduce and
+// Point maps and work items are built on the device from the copied list
+// (launch_build_items), so the host needs no staging either.  The kernels that evaluate, reduce and
 // merge are bfi_eval's own, so with the same launch shape the records are the
 // same bits.
 //
@@ -71,78 +71,6 @@ Layout layout_for(size_t nsub, int d, int rec_len, uint64_t nitems, bool split)
     L.head = take(4);
     L.total = at;
     return L;
-}
-
-// First work item of every subvolume: an exclusive prefix sum of
-// ceil(n_s / chunk) in tiles of the block, one block for the whole list.
-constexpr int kScanBlock = 1024;
-__global__ void __launch_bounds__(kScanBlock)
-    first_items_kernel(const uint64_t *n, uint32_t nsub, uint64_t chunk, uint32_t *sub_first)
-{
-    __shared__ uint32_t tile[kScanBlock];
-    uint32_t carry = 0;
-    const uint32_t t = threadIdx.x;
-    for (uint32_t base = 0; base < nsub; base += kScanBlock) {
-        const uint32_t s = base + t;
-        const uint32_t cnt =
-            s < nsub ? static_cast<uint32_t>(n[s] / chunk + (n[s] % chunk != 0)) : 0u;
-        tile[t] = cnt;
-        __syncthreads();
-        // inclusive Hillis-Steele scan of the tile
-        for (uint32_t off = 1; off < kScanBlock; off <<= 1) {
-            const uint32_t add = t >= off ? tile[t - off] : 0u;
-            __syncthreads();
-            tile[t] += add;
-            __syncthreads();
-        }
-        if (s < nsub)
-            sub_first[s] = carry + tile[t] - cnt;
-        const uint32_t tile_total = tile[kScanBlock - 1];
-        __syncthreads();  // every read of the tile done before the next one is written
-        carry += tile_total;
-    }
-    if (t == 0)
-        sub_first[nsub] = carry;
-}
-
-// Point maps (scale = (hi - lo) 2^-32, base = lo + scale/2, then the FP32
-// copies) and work items of each subvolume: block b takes subvolumes b, b +
-// grid, ...  The arithmetic is the host's in bfi_eval, operation for operation.
-struct BuildArgs {
-    const double *lo, *hi;
-    const uint64_t *n;
-    const uint32_t *sub_first;
-    double *base64, *scale64;
-    float *base32, *scale32;
-    WorkItem *items;
-    const EvalParams *params;
-    double *item_rec;
-    uint64_t chunk;
-    uint32_t nsub;
-    int32_t d, rec_len;
-};
-
-__global__ void __launch_bounds__(256) build_kernel(BuildArgs a)
-{
-    for (uint32_t s = blockIdx.x; s < a.nsub; s += gridDim.x) {
-        const size_t row = static_cast<size_t>(s) * a.d;
-        for (int k = threadIdx.x; k < a.d; k += blockDim.x) {
-            const double scale = (a.hi[row + k] - a.lo[row + k]) * 0x1p-32;
-            const double base = __dadd_rn(a.lo[row + k], 0.5 * scale);
-            a.scale64[row + k] = scale;
-            a.base64[row + k] = base;
-            a.scale32[row + k] = static_cast<float>(scale);
-            a.base32[row + k] = static_cast<float>(base);
-        }
-        const uint32_t i0 = a.sub_first[s], i1 = a.sub_first[s + 1];
-        const uint64_t n = a.n[s];
-        for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-            const uint64_t start = static_cast<uint64_t>(i - i0) * a.chunk;
-            const uint64_t cnt = n - start < a.chunk ? n - start : a.chunk;
-            a.items[i] = WorkItem{a.params, a.item_rec + static_cast<size_t>(i) * a.rec_len, start,
-                                  s, static_cast<uint32_t>(cnt)};
-        }
-    }
 }
 
 }  // namespace
@@ -250,17 +178,11 @@ extern "C" bfi_status bfi_eval_noalloc(bfi_context *ctx, const bfi_lattice *lat,
         auto *sub_split = split ? static_cast<double *>(at(L.sub_split)) : nullptr;
         auto *head = static_cast<uint32_t *>(at(L.head));
 
-        hipLaunchKernelGGL(first_items_kernel, dim3(1), dim3(kScanBlock), 0, st,
-                           static_cast<const uint64_t *>(at(L.n)), static_cast<uint32_t>(nsub),
-                           chunk, sub_first);
-        BFI_HIP(hipGetLastError());
         BuildArgs ba{static_cast<const double *>(at(L.lo)), static_cast<const double *>(at(L.hi)),
                      static_cast<const uint64_t *>(at(L.n)), sub_first, base64, scale64, base32,
                      scale32, items, params, item_rec, chunk, static_cast<uint32_t>(nsub), d,
                      rec_len};
-        const uint32_t build_grid = static_cast<uint32_t>(std::min<size_t>(nsub, 4096));
-        hipLaunchKernelGGL(build_kernel, dim3(build_grid), dim3(256), 0, st, ba);
-        BFI_HIP(hipGetLastError());
+        BFI_HIP(launch_build_items(ba, st));
 
         LaunchSpec spec{prec, l.block, split ? 1 : 0, l.persistent, 0, lat->observable,
                         lat->antithetic};

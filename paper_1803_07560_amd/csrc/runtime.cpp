@@ -4,6 +4,7 @@
 #include "runtime.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -11,6 +12,7 @@
 #include <fstream>
 #include <limits>
 #include <sstream>
+#include <thread>
 
 namespace bfi {
 
@@ -275,8 +277,32 @@ bfi_launch resolve_launch(const bfi_context *ctx, const bfi_lattice &lat, int pr
     return l;
 }
 
+namespace {
+
+// Neumaier-compensated sum.
+struct Nm {
+    double s = 0, c = 0;
+    void add(double x)
+    {
+        const double t = s + x;
+        c += std::fabs(s) >= std::fabs(x) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    void add(const Nm &o)
+    {
+        add(o.s);
+        add(o.c);
+    }
+    double v() const { return s + c; }
+};
+
+constexpr size_t kFinalizeChunk = 8192;  // leaves per chunk of the per-leaf sums
+
+}  // namespace
+
 bfi_status finalize_records(int nx, int d, size_t nsub, const double *lo, const double *hi,
-                            const double *partials, bfi_result *out, int evals_per_sample)
+                            const double *partials, bfi_result *out, int evals_per_sample,
+                            double *leaf_var, const double *volumes)
 {
     if (!out)
         return fail(BFI_EINVAL, "result is NULL");
@@ -287,38 +313,67 @@ bfi_status finalize_records(int nx, int d, size_t nsub, const double *lo, const 
     const int rec_len = BFI_PARTIAL_LEN(nx);
     // common shift: the smallest sigma of the subvolumes
     double sig = std::numeric_limits<double>::infinity();
-    for (size_t s = 0; s < nsub; ++s)
+    for (size_t s = 0; s < nsub; ++s) {
         sig = std::min(sig, partials[s * rec_len + 1]);
+        if (!(partials[s * rec_len] >= 2.0))
+            return fail(BFI_EINVAL, "subvolume %zu has n = %g < 2", s, partials[s * rec_len]);
+    }
     if (!std::isfinite(sig))
         return fail(BFI_EINVAL, "partial records carry no finite shift");
 
-    struct Nm {
-        double s = 0, c = 0;
-        void add(double x)
-        {
-            const double t = s + x;
-            c += std::fabs(s) >= std::fabs(x) ? (s - t) + x : (x - t) + s;
-            s = t;
-        }
-        double v() const { return s + c; }
+    // Two passes over the records, every distance r in the same pass; per-leaf
+    // terms summed in fixed chunks of leaves, the chunk sums in chunk order.
+    const size_t nchunks = (nsub + kFinalizeChunk - 1) / kFinalizeChunk;
+    // per-subvolume volumes and shift factors; the buffers stay with the thread,
+    // so repeated finalizes of large lists (adaptive rounds) reuse their pages
+    // (plain pointers below: the chunks run on worker threads, where the names
+    // would denote those threads' own, empty buffers)
+    thread_local std::vector<double> V_buf, f1_buf;
+    if (V_buf.size() < nsub) {
+        V_buf.resize(nsub);
+        f1_buf.resize(nsub);
+    }
+    double *const V = V_buf.data(), *const f1 = f1_buf.data();
+    struct First {
+        Nm Z, varZ, wsq, nev;
+        std::vector<Nm> N;
     };
-    std::vector<double> V(nsub), f1(nsub);
+    std::vector<First> first(nchunks);
+    for_chunks(nchunks, [&](size_t c) {
+        First &acc = first[c];
+        acc.N.assign(nx, Nm{});
+        const size_t s1 = std::min(nsub, (c + 1) * kFinalizeChunk);
+        for (size_t s = c * kFinalizeChunk; s < s1; ++s) {
+            const double *rec = partials + s * rec_len;
+            double vol = 1.0;
+            if (volumes) {
+                vol = volumes[s];
+            } else {
+                for (int k = 0; k < d; ++k)
+                    vol *= hi[s * d + k] - lo[s * d + k];
+            }
+            V[s] = vol;
+            const double n = rec[0];
+            const double a = std::exp(sig - rec[1]);
+            f1[s] = a;
+            const double sw = a * rec[2], sw2 = a * a * rec[3];
+            acc.Z.add(vol * sw / n);
+            acc.varZ.add(vol * vol * (sw2 - sw * sw / n) / (n * (n - 1.0)));
+            acc.wsq.add((vol / n) * (vol / n) * sw2);
+            acc.nev.add(n);
+            for (int r = 0; r < nx; ++r)
+                acc.N[r].add(vol * a * rec[4 + r] / n);
+        }
+    });
     Nm Z, varZ, wsq, nev;
-    for (size_t s = 0; s < nsub; ++s) {
-        const double *rec = partials + s * rec_len;
-        double vol = 1.0;
-        for (int k = 0; k < d; ++k)
-            vol *= hi[s * d + k] - lo[s * d + k];
-        V[s] = vol;
-        const double n = rec[0];
-        if (!(n >= 2.0))
-            return fail(BFI_EINVAL, "subvolume %zu has n = %g < 2", s, n);
-        f1[s] = std::exp(sig - rec[1]);
-        const double sw = f1[s] * rec[2], sw2 = f1[s] * f1[s] * rec[3];
-        Z.add(vol * sw / n);
-        varZ.add(vol * vol * (sw2 - sw * sw / n) / (n * (n - 1.0)));
-        wsq.add((vol / n) * (vol / n) * sw2);
-        nev.add(n);
+    std::vector<Nm> N(nx);
+    for (const First &acc : first) {
+        Z.add(acc.Z);
+        varZ.add(acc.varZ);
+        wsq.add(acc.wsq);
+        nev.add(acc.nev);
+        for (int r = 0; r < nx; ++r)
+            N[r].add(acc.N[r]);
     }
     const double z = Z.v();  // Z exp(sigma)
     out->log_Z = std::log(z) - sig;
@@ -326,27 +381,42 @@ bfi_status finalize_records(int nx, int d, size_t nsub, const double *lo, const 
     out->Z_err = std::sqrt(std::max(varZ.v(), 0.0)) * std::exp(-sig);
     out->ess = wsq.v() > 0 ? z * z / wsq.v() : 0.0;
     out->n_evals = nev.v() * evals_per_sample;
-    for (int r = 0; r < nx; ++r) {
-        Nm N;
-        for (size_t s = 0; s < nsub; ++s) {
-            const double *rec = partials + s * rec_len;
-            N.add(V[s] * f1[s] * rec[4 + r] / rec[0]);
-        }
-        const double C = N.v() / z;
-        Nm var;
-        for (size_t s = 0; s < nsub; ++s) {
+    std::vector<double> C(nx);
+    for (int r = 0; r < nx; ++r)
+        C[r] = N[r].v() / z;
+
+    // delta method: per leaf Var N - 2 C Cov + C^2 Var Z for every r
+    std::vector<std::vector<Nm>> second(nchunks);
+    const double inv_z2 = z > 0 ? 1.0 / (z * z) : 0.0;
+    for_chunks(nchunks, [&](size_t c) {
+        std::vector<Nm> &var = second[c];
+        var.assign(nx, Nm{});
+        const size_t s1 = std::min(nsub, (c + 1) * kFinalizeChunk);
+        for (size_t s = c * kFinalizeChunk; s < s1; ++s) {
             const double *rec = partials + s * rec_len;
             const double n = rec[0], v2 = V[s] * V[s], nn = n * (n - 1.0);
             const double a = f1[s], a2 = a * a;
             const double sw = a * rec[2], sw2 = a2 * rec[3];
-            const double spw = a * rec[4 + r], spw2 = a2 * rec[4 + nx + r],
-                         spww = a2 * rec[4 + 2 * nx + r];
-            const double var_n = v2 * (spw2 - spw * spw / n) / nn;
             const double var_z = v2 * (sw2 - sw * sw / n) / nn;
-            const double cov = v2 * (spww - spw * sw / n) / nn;
-            var.add(var_n - 2.0 * C * cov + C * C * var_z);
+            double e = 0.0;
+            for (int r = 0; r < nx; ++r) {
+                const double spw = a * rec[4 + r], spw2 = a2 * rec[4 + nx + r],
+                             spww = a2 * rec[4 + 2 * nx + r];
+                const double var_n = v2 * (spw2 - spw * spw / n) / nn;
+                const double cov = v2 * (spww - spw * sw / n) / nn;
+                const double t = var_n - 2.0 * C[r] * cov + C[r] * C[r] * var_z;
+                var[r].add(t);
+                e += t;
+            }
+            if (leaf_var)
+                leaf_var[s] = std::max(e, 0.0) * inv_z2;
         }
-        out->C[r] = C;
+    });
+    for (int r = 0; r < nx; ++r) {
+        Nm var;
+        for (const auto &chunk : second)
+            var.add(chunk[r]);
+        out->C[r] = C[r];
         out->C_err[r] = std::sqrt(std::max(var.v(), 0.0)) / std::fabs(z);
     }
     return BFI_OK;

@@ -4,12 +4,15 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdint>
 #include <exception>
 #include <map>
 #include <new>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -125,15 +128,133 @@ struct TracePhases {
     TracePhases &operator=(const TracePhases &) = delete;
 };
 
+// Run body(chunk) for chunks 0 .. nchunks-1, on up to 16 host threads when
+// there are several (one GPU's share of the host); each chunk writes its own
+// outputs, so results do not depend on the number of threads.
+template <class F>
+void for_chunks(size_t nchunks, F &&body)
+{
+    const size_t hw = std::max<size_t>(1, std::thread::hardware_concurrency());
+    const size_t nthreads = std::min<size_t>({nchunks, hw, 16});
+    if (nthreads <= 1) {
+        for (size_t c = 0; c < nchunks; ++c)
+            body(c);
+        return;
+    }
+    std::atomic<size_t> next{0};
+    auto worker = [&]() {
+        for (size_t c = next++; c < nchunks; c = next++)
+            body(c);
+    };
+    std::vector<std::thread> pool;
+    pool.reserve(nthreads - 1);
+    for (size_t t = 1; t < nthreads; ++t)
+        pool.emplace_back(worker);
+    worker();
+    for (auto &th : pool)
+        th.join();
+}
+
+// Apply body(i) to i in [0, n) in parallel chunks of `grain` (serially when n
+// is below two grains).
+template <class F>
+void parallel_range(size_t n, size_t grain, F &&body)
+{
+    const size_t nchunks = (n + grain - 1) / grain;
+    for_chunks(nchunks, [&](size_t c) {
+        const size_t i1 = std::min(n, (c + 1) * grain);
+        for (size_t i = c * grain; i < i1; ++i)
+            body(i);
+    });
+}
+
 // Resolve a requested launch (zeros = tuned or default) for a lattice.
 bfi_launch resolve_launch(const bfi_context *ctx, const bfi_lattice &lat, int prec, bool split,
                           const bfi_launch *req);
 
 // Host finalize of partial records (see bfi_finalize).
 // evals_per_sample: integrand evaluations behind one record sample (2 for
-// antithetic pairs), for n_evals.
+// antithetic pairs), for n_evals.  leaf_var (nsub doubles, or NULL) gets each
+// subvolume's contribution to the variance of C, sum_r [Var N_s - 2 C Cov_s +
+// C^2 Var Z_s] / Z^2, clamped at 0.  Large lists are summed in parallel chunks
+// whose sums combine in a fixed order (the result does not depend on threads).
+// volumes (nsub doubles, or NULL): the products of the extents, when the caller
+// keeps them (they must equal the product over dimensions in order).
 bfi_status finalize_records(int nx, int d, size_t nsub, const double *lo, const double *hi,
-                            const double *partials, bfi_result *out, int evals_per_sample = 1);
+                            const double *partials, bfi_result *out, int evals_per_sample = 1,
+                            double *leaf_var = nullptr, const double *volumes = nullptr);
+
+// Evaluates work lists that change from call to call (adaptive rounds) with
+// resident buffers: entries are pushed into pinned staging, run() uploads them,
+// builds items and point maps on the device, drains them with the persistent
+// kernel, merges and downloads one record (and split statistics) per entry,
+// all as one captured graph updated in place from call to call.  Buffers grow
+// geometrically and are freed by the destructor.  Blocking on the context's
+// stream; not thread-safe.
+class ResidentEval {
+public:
+    ResidentEval() = default;
+    ~ResidentEval();
+    ResidentEval(const ResidentEval &) = delete;
+    ResidentEval &operator=(const ResidentEval &) = delete;
+    // split: accumulate split statistics (256-thread blocks, d <= 32)
+    bfi_status init(bfi_context *ctx, const bfi_lattice &lat, int prec, bool split,
+                    const bfi_launch *launch);
+    bfi_status reserve(size_t count);
+    // append one entry: samples [offset, offset + n) of stream `id` over [lo, hi)
+    bfi_status push(uint64_t id, uint64_t offset, uint64_t n, const double *lo, const double *hi);
+    // bulk form: stage(count) sizes the list, then set() fills entry i (entries
+    // may be set from several threads)
+    bfi_status stage(size_t count);
+    void set(size_t i, uint64_t id, uint64_t offset, uint64_t n, const double *lo,
+             const double *hi)
+    {
+        const size_t d = static_cast<size_t>(d_);
+        h_id_[i] = id;
+        h_off_[i] = offset;
+        h_n_[i] = n;
+        std::copy(lo, lo + d, h_lo_ + i * d);
+        std::copy(hi, hi + d, h_hi_ + i * d);
+    }
+    size_t size() const { return count_; }
+    // evaluate the pushed entries (then cleared): rec_out gets count x
+    // BFI_PARTIAL_LEN(nx) records, split_out count x BFI_SPLIT_LEN(d) (split
+    // only); device_ms the replay's duration from events around it
+    bfi_status run(uint64_t seed, double *rec_out, double *split_out, double *device_ms);
+    int instantiations() const { return instantiations_; }
+    int updates() const { return updates_; }
+
+private:
+    bfi_status enqueue(size_t nsub, uint64_t nitems, hipStream_t st);
+    void release();
+
+    bfi_context *ctx_ = nullptr;
+    bfi_lattice lat_{};
+    int prec_ = 0, d_ = 0, rec_len_ = 0, split_len_ = 0;
+    bool split_ = false;
+    bfi_launch launch_{};
+    uint64_t chunk_ = 0, resident_blocks_ = 0;
+    size_t count_ = 0;
+    // pinned staging
+    uint64_t *h_id_ = nullptr, *h_n_ = nullptr, *h_off_ = nullptr;
+    double *h_lo_ = nullptr, *h_hi_ = nullptr, *h_rec_ = nullptr, *h_split_ = nullptr;
+    EvalParams *h_params_ = nullptr;
+    size_t cap_h_sub_ = 0, cap_h_rec_ = 0, cap_h_split_ = 0, cap_params_ = 0;
+    // device
+    uint64_t *d_id_ = nullptr, *d_n_ = nullptr, *d_off_ = nullptr;
+    double *d_lo_ = nullptr, *d_hi_ = nullptr, *d_base64_ = nullptr, *d_scale64_ = nullptr;
+    float *d_base32_ = nullptr, *d_scale32_ = nullptr;
+    EvalParams *d_params_ = nullptr;
+    uint32_t *d_sub_first_ = nullptr, *d_head_ = nullptr;
+    WorkItem *d_items_ = nullptr;
+    double *d_item_rec_ = nullptr, *d_item_split_ = nullptr, *d_sub_rec_ = nullptr,
+           *d_sub_split_ = nullptr;
+    size_t cap_d_sub_[6] = {}, cap_d_map_[6] = {}, cap_d_items_[3] = {}, cap_dparams_ = 0,
+           cap_head_ = 0;
+    hipGraphExec_t exec_ = nullptr;
+    hipEvent_t ev_start_ = nullptr, ev_stop_ = nullptr;
+    int instantiations_ = 0, updates_ = 0;
+};
 
 // Take the device address of the allocation-free entry point's scratch array on
 // `device` (which must be current); once per device, later calls return at once.

@@ -239,3 +239,37 @@ def test_finalize_counts_two_evaluations_per_pair(bfi):
     with pytest.raises(bfi.BfiError) as e:
         bfi.bfi_finalize(bad, sv, p)
     assert e.value.name == "BFI_EINVAL"
+
+
+@pytest.mark.parametrize("k", [13, 15])
+def test_finalize_of_many_records_matches_oracle(bfi, k):
+    """Lists above one finalize chunk (8192 records) are summed in parallel
+    chunks: the result equals the oracle's finalize of the same records, and
+    shifted records give the same result as their rescaled plain copy."""
+    nx, d = 2, 4
+    sv = workloads.uniform_partition(d, 2.0, k, per_sub=10)
+    rng = np.random.default_rng(k)
+    m = len(sv)
+    rec = np.zeros((m, 4 + 3 * nx))
+    rec[:, 0] = rng.integers(2, 1000, m)
+    rec[:, 2] = rng.uniform(0.5, 2.0, m) * rec[:, 0]
+    rec[:, 3] = rec[:, 2] ** 2 / rec[:, 0] * rng.uniform(1.0, 3.0, m)
+    rec[:, 4:6] = rng.normal(size=(m, nx)) * rec[:, 2:3]
+    rec[:, 6:8] = rec[:, 4:6] ** 2 + rec[:, 3:4]
+    rec[:, 8:10] = rng.normal(size=(m, nx)) * rec[:, 3:4]
+    got = bfi.bfi_finalize(bfi.lattice(nx, 2), sv, rec)
+    want = oracle.finalize(nx, d, sv.lo, sv.hi, np.concatenate([rec[:, :1], rec[:, 2:]], 1))
+    assert got["Z"] == pytest.approx(want["Z"], rel=1e-13)
+    np.testing.assert_allclose(got["C"], want["C"], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(got["C_err"], want["C_err"], rtol=1e-10)
+    assert got["n_evals"] == want["n_evals"]
+    shifted = rec.copy()
+    shifted[:, 1] = rng.uniform(-3, 3, m)
+    f1 = np.exp(shifted[:, 1])
+    shifted[:, 2] *= f1
+    shifted[:, 4:6] *= f1[:, None]
+    shifted[:, 3] *= f1 ** 2
+    shifted[:, 6:10] *= (f1 ** 2)[:, None]
+    again = bfi.bfi_finalize(bfi.lattice(nx, 2), sv, shifted)
+    assert again["log_Z"] == pytest.approx(got["log_Z"], abs=1e-12)
+    np.testing.assert_allclose(again["C"], got["C"], rtol=1e-10, atol=1e-13)
