@@ -90,7 +90,7 @@ def parse():
                     help="oracle sample: first 2^k samples of every subvolume (default: about "
                          "2^29 x 20/d evaluations in all, 10-15 s on 16 host threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the Poisson serving run (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-max-samples-per-thread", type=int, default=0,
@@ -98,8 +98,10 @@ def parse():
     ap.add_argument("--adaptive-budget-log2", type=int, default=36,
                     help="evaluation budget of each adaptive 10x2 run (0 skips them)")
     ap.add_argument("--adaptive-target-budget-log2", type=int, default=40,
-                    help="budget of the time-to-target adaptive runs with the averaged "
-                         "observable (0 skips them)")
+                    help="budget of the holdout-confirmed time-to-target adaptive runs with the "
+                         "averaged observable (0 skips them)")
+    ap.add_argument("--adaptive-scale-budget-log2", type=int, default=39,
+                    help="budget of the large adaptive run (over a million leaves; 0 skips it)")
     ap.add_argument("--no-observable-leg", action="store_true",
                     help="skip the translation-averaged observable leg")
     ap.add_argument("--no-sampler-leg", action="store_true",
@@ -191,14 +193,17 @@ def run_form(bfi, torch, ctx, lat, sv, w, prec, steps, warmup, stream):
                                             "use_graph")}, "n_items": info["n_items"]}
 
 
-def serve_leg(bfi, ctx, seconds, rate, warmup_s=1.0, max_samples_per_thread=0):
+def serve_leg(bfi, ctx, seconds, rate, warmup_s=1.0, max_samples_per_thread=0, alone=50):
     """Poisson arrivals of correlation requests (lattice uniform over 4x2, 8x2,
     10x2, 16x4; nu log-uniform in [0.05, 2]; budgets 2^U(16,26)); FP32 form.
     Latency is submit-to-result as timed by the server; requests arriving in the
-    first `warmup_s` seconds are served but not counted."""
+    first `warmup_s` seconds are served but not counted.  Afterwards `alone`
+    requests sampled from the stream (numpy PCG64(2)) run again one at a time on
+    a fresh server: each result must be bit-identical to its result in the mix."""
     reqs = workloads.serving_requests(rate, seconds, seed=1)
-    srv = bfi.bfi_server_create(ctx, bfi.server_config(
-        memory_budget=8 << 30, max_requests=256, max_samples_per_thread=max_samples_per_thread))
+    cfg = bfi.server_config(memory_budget=8 << 30, max_requests=256,
+                            max_samples_per_thread=max_samples_per_thread)
+    srv = bfi.bfi_server_create(ctx, cfg)
     try:
         t0 = time.perf_counter()
         tickets = []
@@ -211,55 +216,89 @@ def serve_leg(bfi, ctx, seconds, rate, warmup_s=1.0, max_samples_per_thread=0):
             tickets.append(bfi.bfi_server_submit(srv, bfi.request(
                 bfi.lattice(r.nx, r.nt, nu=r.nu, D=r.D), "fp32", r.seed, r.box, r.split_log2,
                 r.budget)))
-        lat = [bfi.bfi_server_wait(srv, t, 120.0)[1] for t in tickets]
+        done = [bfi.bfi_server_wait(srv, t, 120.0) for t in tickets]
         t1 = time.perf_counter()
         st = bfi.bfi_server_stats_get(srv)
     finally:
         bfi.bfi_server_destroy(srv)
+    lat = [x[1] for x in done]
     counted = np.array([x for x, r in zip(lat, reqs) if r.arrival_s >= warmup_s])
     evals = sum(r.budget for r in reqs)
+    # the same requests alone: bit-identical results
+    pick = np.random.Generator(np.random.PCG64(2)).choice(len(reqs), size=min(alone, len(reqs)),
+                                                          replace=False)
+    same = 0
+    srv = bfi.bfi_server_create(ctx, cfg)
+    try:
+        for i in sorted(pick):
+            r = reqs[i]
+            t = bfi.bfi_server_submit(srv, bfi.request(
+                bfi.lattice(r.nx, r.nt, nu=r.nu, D=r.D), "fp32", r.seed, r.box, r.split_log2,
+                r.budget))
+            res = bfi.bfi_server_wait(srv, t, 120.0)[0]
+            mix = done[i][0]
+            same += int(res["log_Z"] == mix["log_Z"] and np.array_equal(res["C"], mix["C"])
+                        and np.array_equal(res["C_err"], mix["C_err"]))
+    finally:
+        bfi.bfi_server_destroy(srv)
+    if same != len(pick):
+        print(f"bench: WARNING: {len(pick) - same} of {len(pick)} requests differ alone vs mixed",
+              file=sys.stderr, flush=True)
     return {"requests": len(reqs), "counted": int(counted.size), "rate_hz": rate,
-            "seconds": seconds, "p50_ms": float(np.percentile(counted, 50) * 1e3),
+            "seconds": seconds, "warmup_seconds": warmup_s,
+            "p50_ms": float(np.percentile(counted, 50) * 1e3),
             "p99_ms": float(np.percentile(counted, 99) * 1e3),
             "max_ms": float(counted.max() * 1e3), "evals_per_s": evals / (t1 - t0),
             "gpu_busy_frac": st["busy_seconds"] / (t1 - t0), "steps": st["steps"],
-            "form": "fp32"}
+            "step_ms_mean": 1e3 * st["busy_seconds"] / max(st["steps"], 1),
+            "alone_vs_mixed_bit_identical": f"{same}/{len(pick)}", "form": "fp32"}
 
 
 def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0), observables=("anchor", "averaged"),
-                 forms=("fp32",), holdout_forms=()):
+                 forms=("fp32",), holdout_forms=(), confirm=False, target=1e-3):
     """10x2 lattice, D = 1, box [-4,4]^20: error-driven bisection from the
     1024-subvolume partition at 2^10 samples per leaf, per-leaf counts in
     [2^10, 2^22], target max_r sigma_C(r)/|C(0)| <= 1e-3 with an effective
     sample size of at least 100, in the given forms, budget 2^budget_log2
     evaluations per value of nu, each round at least 1/32 of it; split statistics
     from the first 2^16 samples of each leaf; the anchored product of the paper
-    and the translation-averaged one.  status BFI_OK: the target was met, and
-    `seconds` is the time to it.  For runs in `holdout_forms` the final partition
-    is also evaluated on a fresh pass (each leaf's stream continued over n more
-    samples, which no refinement decision has seen): `holdout_rel_err` is that
-    pass's max_r sigma_C(r)/|C(0)|, free of the selection that makes the stopping
-    estimate optimistic."""
+    and the translation-averaged one.  With `confirm`, the stop is confirmed on a
+    holdout pass (the leaves sampled afresh under a seed of their own, at most
+    one check per round): status BFI_OK then means a holdout pass met the target
+    and `seconds` is the time to it; BFI_EBUDGET reports the last holdout error.
+    Without it, BFI_OK means the running estimate met the target.  For runs in
+    `holdout_forms` the final partition is also evaluated on a fresh pass (each
+    leaf's stream continued over n more samples, which no refinement decision
+    has seen): `holdout_rel_err` is that pass's max_r sigma_C(r)/|C(0)|, free of
+    the selection that makes the stopping estimate optimistic."""
     out = []
     for form, observable, nu in itertools.product(forms, observables, nus):
-        cfg = bfi.adaptive_config(target_rel_err=1e-3, max_evals=1 << budget_log2,
+        cfg = bfi.adaptive_config(target_rel_err=target, max_evals=1 << budget_log2,
                                   n_min=1 << 10, n_max=1 << 22, split_log2=10,
                                   max_rounds=128, refine_fraction=0.5,
                                   round_evals=max(1 << 24, (1 << budget_log2) >> 5),
-                                  split_samples=1 << 16)
+                                  split_samples=1 << 16, holdout=confirm)
         t0 = time.perf_counter()
         r = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(10, 2, nu=nu, observable=observable),
                                        form, 1, -4.0, 4.0, cfg, leaf_capacity=1 << 22)
         dt = time.perf_counter() - t0
-        print(f"bench: adaptive {form} {observable} nu={nu}: {r['status']} "
-              f"rel_err {r['rel_err']:.3g} in {dt:.2f} s", file=sys.stderr, flush=True)
+        print(f"bench: adaptive {form} {observable} nu={nu} target {target:g}: {r['status']} "
+              f"rel_err {r['rel_err']:.3g} (holdout {r['holdout_rel_err']:.3g}) in {dt:.2f} s",
+              file=sys.stderr, flush=True)
         part = r["partition"]
         n = part.n
-        rec = {"form": form, "observable": observable, "nu": nu, "status": r["status"],
+        rec = {"form": form, "observable": observable, "nu": nu, "target": target,
+               "status": r["status"],
+               "stop": "holdout-confirmed" if confirm else "running estimate",
                "rel_err": r["rel_err"], "ess": r["ess"], "rounds": r["rounds"],
                "leaves": r["leaves"], "evals": r["evals"], "seconds": dt,
-               "evals_per_s": r["evals"] / dt, "leaf_n_min": int(n.min()),
-               "leaf_n_max": int(n.max()), "split_samples": cfg.split_samples}
+               "evals_per_s": r["evals"] / dt, "device_seconds": r["device_seconds"],
+               "leaf_n_min": int(n.min()), "leaf_n_max": int(n.max()),
+               "split_samples": cfg.split_samples}
+        if confirm:
+            rec["holdout_checks"] = r["holdout_checks"]
+            rec["holdout_used"] = r["holdout_used"]
+            rec["last_holdout_rel_err"] = r["holdout_rel_err"]
         if form in holdout_forms:
             lat = bfi.lattice(10, 2, nu=nu, observable=observable)
             fresh = bfi.Subvolumes(part.ids, part.lo, part.hi, n, n, lat.d)
@@ -271,6 +310,32 @@ def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0), observables=("ancho
                   flush=True)
         out.append(rec)
     return out
+
+
+def adaptive_scale_leg(bfi, ctx, budget_log2=39, n_max_log2=18, round_log2=34):
+    """A large adaptive 10x2 run (FP32 form, averaged observable, box [-4,4]^20):
+    from 1024 leaves at 2^10 samples, leaves capped at 2^n_max_log2 samples so
+    refinement splits, rounds of 2^round_log2 evaluations, to a budget of
+    2^budget_log2 -- over a million leaves.  Reports the whole run's rate and
+    the device's share of its wall time (events around each replay of the
+    captured round sequence)."""
+    cfg = bfi.adaptive_config(target_rel_err=1e-9, max_evals=1 << budget_log2, n_min=1 << 10,
+                              n_max=1 << n_max_log2, split_log2=10, max_rounds=1000,
+                              refine_fraction=0.5, round_evals=1 << round_log2,
+                              split_samples=1 << 16)
+    t0 = time.perf_counter()
+    r = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(10, 2, observable="averaged"), "fp32", 1,
+                                   -4.0, 4.0, cfg, leaf_capacity=1)
+    dt = time.perf_counter() - t0
+    print(f"bench: adaptive scale run: {r['leaves']} leaves, {r['evals']:.3g} evals in {dt:.2f} s "
+          f"(device {r['device_seconds']:.2f} s)", file=sys.stderr, flush=True)
+    return {"budget": 1 << budget_log2, "n_max": 1 << n_max_log2, "round_evals": 1 << round_log2,
+            "rounds": r["rounds"], "leaves": r["leaves"], "evals": r["evals"], "seconds": dt,
+            "evals_per_s": r["evals"] / dt, "device_seconds": r["device_seconds"],
+            "device_evals_per_s": r["evals"] / r["device_seconds"],
+            "wall_over_device": dt / r["device_seconds"],
+            "graph_instantiations": r["graph_instantiations"],
+            "graph_updates": r["graph_updates"], "form": "fp32", "observable": "averaged"}
 
 
 def host_path_leg(bfi, ctx, lat, sv, reps=3):
@@ -492,6 +557,14 @@ def main():
     # before the first form, so it overlaps no measured launch
     torch.zeros(1 << 20, device="cuda:0").sum().item()
     torch.cuda.synchronize()
+    # about a third of a second of matrix products first: the device leaves its
+    # idle clocks before any form is warmed up or timed
+    x = torch.randn(4096, 4096, device="cuda:0")
+    t_spin = time.perf_counter()
+    while time.perf_counter() - t_spin < 0.3:
+        x = torch.tanh(x @ x)
+        torch.cuda.synchronize()
+    del x
     forms = {}
     # the other form first: its steps bring the device to its running clocks, so
     # no early step of the headline form pays for the ramp (a replay of 17-49 ms
@@ -521,9 +594,20 @@ def main():
     if args.adaptive_target_budget_log2 > 0 and w.name == "burgers10x2":
         print(f"bench: adaptive 10x2 to target, averaged observable, budget "
               f"2^{args.adaptive_target_budget_log2} per nu", file=sys.stderr, flush=True)
+        # the workload's 1e-3 target, holdout-confirmed, FP32 form; and 1e-2 (which
+        # a holdout pass confirms within the budget) in both forms, for the time
+        # each form takes to the same confirmed error
         adaptive_target = adaptive_leg(bfi, ctx, args.adaptive_target_budget_log2,
-                                       observables=("averaged",), forms=("fp32", "fp64"),
-                                       holdout_forms=("fp32",))
+                                       observables=("averaged",), forms=("fp32",),
+                                       confirm=True, target=1e-3)
+        adaptive_target += adaptive_leg(bfi, ctx, args.adaptive_target_budget_log2,
+                                        observables=("averaged",), forms=("fp32", "fp64"),
+                                        confirm=True, target=1e-2)
+    adaptive_scale = None
+    if args.adaptive_scale_budget_log2 > 0 and w.name == "burgers10x2":
+        print(f"bench: adaptive scale run, budget 2^{args.adaptive_scale_budget_log2}",
+              file=sys.stderr, flush=True)
+        adaptive_scale = adaptive_scale_leg(bfi, ctx, args.adaptive_scale_budget_log2)
     if args.calibrate_copy_mib > 0:
         n = args.calibrate_copy_mib << 20
         x = torch.ones(n, dtype=torch.uint8, device="cuda:0")
@@ -616,12 +700,19 @@ def main():
         line["adaptive"] = adaptive
     if adaptive_target is not None:
         line["adaptive_to_target"] = adaptive_target
-        # time to the same error in both forms: FP64 seconds / FP32 seconds per nu
-        secs = {(a["form"], a["nu"]): a["seconds"] for a in adaptive_target
-                if a["status"] == "BFI_OK"}
-        line["fp32_speedup_at_target"] = {
-            str(nu): secs[("fp64", nu)] / secs[("fp32", nu)]
-            for (form, nu) in secs if form == "fp32" and ("fp64", nu) in secs}
+        # time to the same holdout-confirmed error in both forms, per nu: FP64
+        # seconds / FP32 seconds, only where both runs were confirmed
+        speedup = {}
+        for target in sorted({a["target"] for a in adaptive_target}):
+            secs = {(a["form"], a["nu"]): a["seconds"] for a in adaptive_target
+                    if a["target"] == target and a["status"] == "BFI_OK" and a.get("holdout_used")}
+            per_nu = {str(nu): secs[("fp64", nu)] / secs[("fp32", nu)]
+                      for (form, nu) in secs if form == "fp32" and ("fp64", nu) in secs}
+            if per_nu:
+                speedup[f"{target:g}"] = per_nu
+        line["fp32_speedup_at_target"] = speedup or None
+    if adaptive_scale is not None:
+        line["adaptive_scale"] = adaptive_scale
     if not args.no_cpu_baseline:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
         base, sub, rec = cpu_baseline(w, sv, args.cpu_samples_log2)

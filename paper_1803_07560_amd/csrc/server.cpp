@@ -63,10 +63,11 @@ struct Request {
     Clock::time_point t_submit, t_done;
 };
 
-// Byte layout of a request's device state.
+// Byte layout of a request's device state: the parts uploaded at admission
+// first (one contiguous image of `upload` bytes), then the records.
 struct Layout {
-    size_t params, base64, scale64, base32, scale32, ids, offsets, item_rec, sub_first, sub_rec,
-        total;
+    size_t params, base64, scale64, base32, scale32, ids, offsets, sub_first, upload, item_rec,
+        sub_rec, total;
 };
 
 Layout layout_of(size_t nsub, int d, size_t nitems, int rec_len)
@@ -85,11 +86,23 @@ Layout layout_of(size_t nsub, int d, size_t nitems, int rec_len)
     L.scale32 = take(nsub * d * 4);
     L.ids = take(nsub * 8);
     L.offsets = take(nsub * 8);
-    L.item_rec = take(nitems * rec_len * 8);
     L.sub_first = take((nsub + 1) * 4);
+    L.upload = o;
+    L.item_rec = take(nitems * rec_len * 8);
     L.sub_rec = take(nsub * rec_len * 8);
     L.total = o;
     return L;
+}
+
+// Device blocks come in power-of-two sizes from 64 KiB: a finished request's
+// block is kept for the next request of its size class instead of being freed,
+// so admission rarely calls hipMalloc; memory is accounted by block size.
+size_t block_size(size_t bytes)
+{
+    size_t c = size_t(64) << 10;
+    while (c < bytes)
+        c <<= 1;
+    return c;
 }
 
 bool terminal(State s) { return s == State::Done || s == State::Cancelled || s == State::Failed; }
@@ -114,11 +127,19 @@ struct bfi_server {
     hipStream_t stream = nullptr;              // copies, merges, first group
     hipStream_t group_streams[kStreams] = {};  // group g runs on group_streams[g % 4]
     hipEvent_t staged = nullptr;               // step items copied to the device
-    WorkItem *d_step = nullptr, *h_step = nullptr;
-    size_t step_cap = 0;
-    uint32_t *d_heads = nullptr;
+    // step buffer: kMaxGroups queue heads (zeros, copied with every step's
+    // items, so no kernel resets them), then the step's work items
     static constexpr int kMaxGroups = 64;
+    static constexpr size_t kHeadBytes = 256;
+    char *d_step = nullptr, *h_step = nullptr;
+    size_t step_cap = 0;  // work items
     std::map<TuneKey, std::pair<bfi_launch, uint32_t>> shapes;  // launch and grid
+    // cached device blocks by size class, and their total
+    std::map<size_t, std::vector<void *>> pool;
+    size_t pool_bytes = 0;
+    // pinned staging: admission images, and records of finished requests
+    char *h_stage = nullptr, *h_done = nullptr;
+    size_t stage_cap = 0, stage_used = 0, done_cap = 0;
 };
 
 namespace {
@@ -129,7 +150,7 @@ namespace {
 bfi_status shape_launch(bfi_server *srv, const bfi_lattice &lat, int prec, bfi_launch *l,
                         uint32_t *grid)
 {
-    const TuneKey key{lat.nx, lat.nt, prec + 2 * lat.observable + 4 * lat.antithetic};
+    const TuneKey key{lat.nx, lat.nt, prec, lat.antithetic, lat.observable};
     auto it = srv->shapes.find(key);
     if (it == srv->shapes.end()) {
         bfi_launch r = resolve_launch(srv->ctx, lat, prec, false, nullptr);
@@ -149,13 +170,63 @@ bfi_status shape_launch(bfi_server *srv, const bfi_lattice &lat, int prec, bfi_l
     return BFI_OK;
 }
 
+void pool_release(bfi_server *srv, size_t keep)
+{
+    for (auto it = srv->pool.rbegin(); it != srv->pool.rend() && srv->pool_bytes > keep; ++it) {
+        while (!it->second.empty() && srv->pool_bytes > keep) {
+            (void)hipFree(it->second.back());
+            it->second.pop_back();
+            srv->pool_bytes -= it->first;
+        }
+    }
+}
+
+hipError_t pool_take(bfi_server *srv, size_t bytes, void **out)
+{
+    auto it = srv->pool.find(bytes);
+    if (it != srv->pool.end() && !it->second.empty()) {
+        *out = it->second.back();
+        it->second.pop_back();
+        srv->pool_bytes -= bytes;
+        return hipSuccess;
+    }
+    hipError_t e = hipMalloc(out, bytes);
+    if (e == hipErrorOutOfMemory && srv->pool_bytes > 0) {
+        (void)hipGetLastError();
+        pool_release(srv, 0);
+        e = hipMalloc(out, bytes);
+    }
+    return e;
+}
+
 void free_device(bfi_server *srv, Request *r)
 {
     if (r->dmem) {
-        (void)hipFree(r->dmem);
+        // no kernel of the request is in flight here (steps are waited for)
+        srv->pool[r->bytes].push_back(r->dmem);
+        srv->pool_bytes += r->bytes;
         r->dmem = nullptr;
         srv->used_bytes -= r->bytes;
+        // the cache holds at most the budget's worth of blocks
+        if (srv->pool_bytes > srv->cfg.memory_budget)
+            pool_release(srv, srv->cfg.memory_budget / 2);
     }
+}
+
+// Pinned host buffer of at least `bytes`; its old contents are dropped.
+hipError_t grow_pinned(char **p, size_t *cap, size_t bytes)
+{
+    if (*cap >= bytes && *p)
+        return hipSuccess;
+    if (*p)
+        (void)hipHostFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    const size_t n = std::max(bytes, size_t(1) << 20);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(p), n, hipHostMallocDefault);
+    if (e == hipSuccess)
+        *cap = n;
+    return e;
 }
 
 void finish(bfi_server *srv, Request *r, State s, bfi_status st, const std::string &msg)
@@ -171,50 +242,54 @@ void finish(bfi_server *srv, Request *r, State s, bfi_status st, const std::stri
 }
 
 // Allocate and upload a request's device state.  Called with the lock held.
+// The uploaded parts are written into pinned staging as one image and copied
+// asynchronously on the server stream, ahead of any step that uses them.
 bfi_status admit_one(bfi_server *srv, Request *r)
 {
     const size_t nsub = r->subs.size();
     const int d = r->d;
     const Layout L = layout_of(nsub, d, r->items.size(), r->rec_len);
-    BFI_HIP(hipMalloc(&r->dmem, L.total));
-    r->bytes = L.total;
-    srv->used_bytes += L.total;
+    const size_t bytes = block_size(L.total);
+    BFI_HIP(pool_take(srv, bytes, &r->dmem));
+    r->bytes = bytes;
+    srv->used_bytes += bytes;
     char *base = static_cast<char *>(r->dmem);
-    std::vector<double> b64(nsub * d), s64(nsub * d);
-    std::vector<float> b32(nsub * d), s32(nsub * d);
+    if (srv->stage_used + L.upload > srv->stage_cap) {
+        // earlier images may still be in flight: wait for them before reusing
+        BFI_HIP(hipStreamSynchronize(srv->stream));
+        srv->stage_used = 0;
+        BFI_HIP(grow_pinned(&srv->h_stage, &srv->stage_cap, L.upload));
+    }
+    char *img = srv->h_stage + srv->stage_used;
+    srv->stage_used += align_up(L.upload);
+    auto *b64 = reinterpret_cast<double *>(img + L.base64);
+    auto *s64 = reinterpret_cast<double *>(img + L.scale64);
+    auto *b32 = reinterpret_cast<float *>(img + L.base32);
+    auto *s32 = reinterpret_cast<float *>(img + L.scale32);
     for (size_t i = 0; i < nsub * d; ++i) {
         s64[i] = (r->subs.hi[i] - r->subs.lo[i]) * 0x1p-32;
         b64[i] = r->subs.lo[i] + 0.5 * s64[i];
         s32[i] = static_cast<float>(s64[i]);
         b32[i] = static_cast<float>(b64[i]);
     }
-    EvalParams P{reinterpret_cast<double *>(base + L.base64),
-                 reinterpret_cast<double *>(base + L.scale64),
-                 reinterpret_cast<float *>(base + L.base32),
-                 reinterpret_cast<float *>(base + L.scale32),
-                 reinterpret_cast<uint64_t *>(base + L.ids),
-                 reinterpret_cast<uint64_t *>(base + L.offsets),
-                 make_coef(r->req.lat),
-                 static_cast<uint32_t>(r->req.seed),
-                 static_cast<uint32_t>(r->req.seed >> 32)};
+    const EvalParams P{reinterpret_cast<double *>(base + L.base64),
+                       reinterpret_cast<double *>(base + L.scale64),
+                       reinterpret_cast<float *>(base + L.base32),
+                       reinterpret_cast<float *>(base + L.scale32),
+                       reinterpret_cast<uint64_t *>(base + L.ids),
+                       reinterpret_cast<uint64_t *>(base + L.offsets),
+                       make_coef(r->req.lat),
+                       static_cast<uint32_t>(r->req.seed),
+                       static_cast<uint32_t>(r->req.seed >> 32)};
+    std::memcpy(img + L.params, &P, sizeof(P));
+    std::memcpy(img + L.ids, r->subs.id.data(), nsub * 8);
+    std::memcpy(img + L.offsets, r->subs.offset.data(), nsub * 8);
+    std::memcpy(img + L.sub_first, r->sub_first.data(), (nsub + 1) * 4);
+    BFI_HIP(hipMemcpyAsync(base, img, L.upload, hipMemcpyHostToDevice, srv->stream));
     r->d_params = reinterpret_cast<EvalParams *>(base + L.params);
     r->d_item_rec = reinterpret_cast<double *>(base + L.item_rec);
     r->d_sub_first = reinterpret_cast<uint32_t *>(base + L.sub_first);
     r->d_sub_rec = reinterpret_cast<double *>(base + L.sub_rec);
-    struct Up {
-        size_t at;
-        const void *src;
-        size_t bytes;
-    } ups[] = {{L.params, &P, sizeof(P)},
-               {L.base64, b64.data(), nsub * d * 8},
-               {L.scale64, s64.data(), nsub * d * 8},
-               {L.base32, b32.data(), nsub * d * 4},
-               {L.scale32, s32.data(), nsub * d * 4},
-               {L.ids, r->subs.id.data(), nsub * 8},
-               {L.offsets, r->subs.offset.data(), nsub * 8},
-               {L.sub_first, r->sub_first.data(), (nsub + 1) * 4}};
-    for (const Up &u : ups)
-        BFI_HIP(hipMemcpy(base + u.at, u.src, u.bytes, hipMemcpyHostToDevice));
     for (size_t i = 0; i < r->items.size(); ++i) {
         r->items[i].params = r->d_params;
         r->items[i].rec = r->d_item_rec + i * r->rec_len;
@@ -229,7 +304,7 @@ void admit(bfi_server *srv)
            static_cast<int32_t>(srv->admitted.size()) < srv->cfg.max_requests) {
         Request *r = srv->reqs.at(srv->pending.front()).get();
         const Layout L = layout_of(r->subs.size(), r->d, r->items.size(), r->rec_len);
-        if (srv->used_bytes + L.total > srv->cfg.memory_budget)
+        if (srv->used_bytes + block_size(L.total) > srv->cfg.memory_budget)
             break;  // first come, first served: wait for memory to free up
         srv->pending.pop_front();
         bfi_status s = admit_one(srv, r);
@@ -242,9 +317,13 @@ void admit(bfi_server *srv)
 }
 
 // Merge and finalize requests whose items are all done; release cancelled ones.
+// Every finished request's merge and record copy is enqueued first, then one
+// wait covers them all.
 void complete(bfi_server *srv)
 {
     std::vector<uint64_t> keep;
+    std::vector<Request *> ready;
+    size_t bytes = 0;
     for (uint64_t t : srv->admitted) {
         Request *r = srv->reqs.at(t).get();
         if (r->cancel && r->inflight == 0) {
@@ -255,7 +334,18 @@ void complete(bfi_server *srv)
             keep.push_back(t);
             continue;
         }
-        TraceRange trace("server: merge and finalize a request");
+        ready.push_back(r);
+        bytes += r->subs.size() * r->rec_len * sizeof(double);
+    }
+    srv->admitted.swap(keep);
+    if (ready.empty())
+        return;
+    TraceRange trace("server: merge and finalize finished requests");
+    hipError_t e = grow_pinned(&srv->h_done, &srv->done_cap, bytes);
+    std::vector<double *> host(ready.size());
+    size_t at = 0;
+    for (size_t i = 0; i < ready.size() && e == hipSuccess; ++i) {
+        Request *r = ready[i];
         MergeArgs m{};
         m.item_rec = r->d_item_rec;
         m.sub_first = r->d_sub_first;
@@ -263,29 +353,36 @@ void complete(bfi_server *srv)
         m.nsub = static_cast<uint32_t>(r->subs.size());
         m.nx = r->nx;
         m.d = r->d;
-        std::vector<double> sub(r->subs.size() * r->rec_len);
-        hipError_t e = launch_merge(m, srv->stream);
+        host[i] = reinterpret_cast<double *>(srv->h_done + at);
+        const size_t n = r->subs.size() * r->rec_len * sizeof(double);
+        at += n;
+        e = launch_merge(m, srv->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(sub.data(), r->d_sub_rec, sub.size() * sizeof(double),
-                               hipMemcpyDeviceToHost, srv->stream);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(srv->stream);
-        if (e != hipSuccess) {
+            e = hipMemcpyAsync(host[i], r->d_sub_rec, n, hipMemcpyDeviceToHost, srv->stream);
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(srv->stream);
+    if (e != hipSuccess) {
+        for (Request *r : ready)
             finish(srv, r, State::Failed, BFI_EDEVICE, hipGetErrorString(e));
-            continue;
-        }
+        return;
+    }
+    for (size_t i = 0; i < ready.size(); ++i) {
+        Request *r = ready[i];
+        const double *sub = host[i];
+        const size_t len = r->subs.size() * r->rec_len;
         // records that overflowed (an action beyond the range of the precision:
         // every subvolume has samples, so even the shift is finite in a sound
         // record) fail this request only
         bool finite = true;
-        for (size_t i = 0; i < sub.size() && finite; ++i)
-            finite = std::isfinite(sub[i]);
+        for (size_t k = 0; k < len && finite; ++k)
+            finite = std::isfinite(sub[k]);
         if (!finite) {
             finish(srv, r, State::Failed, BFI_EDEVICE, "non-finite sums");
             continue;
         }
         bfi_status s = finalize_records(r->nx, r->d, r->subs.size(), r->subs.lo.data(),
-                                        r->subs.hi.data(), sub.data(), &r->result,
+                                        r->subs.hi.data(), sub, &r->result,
                                         r->req.lat.antithetic ? 2 : 1);
         finite = std::isfinite(r->result.log_Z);
         for (int k = 0; k < r->nx; ++k)
@@ -297,7 +394,6 @@ void complete(bfi_server *srv)
         else
             finish(srv, r, State::Done, BFI_OK, "");
     }
-    srv->admitted.swap(keep);
 }
 
 struct StepEntry {
@@ -331,8 +427,8 @@ bfi_status run_step(bfi_server *srv, const std::vector<StepEntry> &entries)
                 continue;
             used[j] = true;
             const StepEntry &e = entries[j];
-            std::memcpy(srv->h_step + total, e.r->items.data() + e.first,
-                        e.count * sizeof(WorkItem));
+            std::memcpy(srv->h_step + bfi_server::kHeadBytes + total * sizeof(WorkItem),
+                        e.r->items.data() + e.first, e.count * sizeof(WorkItem));
             total += e.count;
             g.count += e.count;
         }
@@ -340,7 +436,9 @@ bfi_status run_step(bfi_server *srv, const std::vector<StepEntry> &entries)
     }
     if (groups.size() > static_cast<size_t>(bfi_server::kMaxGroups))
         return fail(BFI_EDEVICE, "too many shape groups in one step");
-    BFI_HIP(hipMemcpyAsync(srv->d_step, srv->h_step, total * sizeof(WorkItem),
+    // the copy carries the zeroed queue heads and the items
+    BFI_HIP(hipMemcpyAsync(srv->d_step, srv->h_step,
+                           bfi_server::kHeadBytes + total * sizeof(WorkItem),
                            hipMemcpyHostToDevice, srv->stream));
     BFI_HIP(hipEventRecord(srv->staged, srv->stream));
     const int nstreams = static_cast<int>(std::min<size_t>(groups.size(), bfi_server::kStreams));
@@ -349,11 +447,10 @@ bfi_status run_step(bfi_server *srv, const std::vector<StepEntry> &entries)
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const Group &g = groups[gi];
         hipStream_t st = srv->group_streams[gi % bfi_server::kStreams];
-        BFI_HIP(launch_reset_head(srv->d_heads + gi, st));
         McArgs a{};
-        a.items = srv->d_step + g.off;
+        a.items = reinterpret_cast<const WorkItem *>(srv->d_step + bfi_server::kHeadBytes) + g.off;
         a.item_split = nullptr;
-        a.queue_head = srv->d_heads + gi;
+        a.queue_head = reinterpret_cast<uint32_t *>(srv->d_step) + gi;
         a.nitems = static_cast<uint32_t>(g.count);
         a.samples_per_thread = static_cast<uint32_t>(g.launch.samples_per_thread);
         LaunchSpec spec{g.prec, g.launch.block, 0, 1,
@@ -500,11 +597,15 @@ bfi_status bfi_server_create(bfi_context *ctx, const bfi_server_config *cfg, bfi
         for (int k = 1; k < bfi_server::kStreams; ++k)
             BFI_HIP(hipStreamCreateWithFlags(&srv->group_streams[k], hipStreamNonBlocking));
         BFI_HIP(hipEventCreateWithFlags(&srv->staged, hipEventDisableTiming));
-        hipError_t e = hipMalloc(&srv->d_step, srv->step_cap * sizeof(WorkItem));
+        static_assert(bfi_server::kMaxGroups * sizeof(uint32_t) <= bfi_server::kHeadBytes,
+                      "queue heads fit the step buffer's head area");
+        const size_t step_bytes = bfi_server::kHeadBytes + srv->step_cap * sizeof(WorkItem);
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&srv->d_step), step_bytes);
         if (e == hipSuccess)
-            e = hipHostMalloc(&srv->h_step, srv->step_cap * sizeof(WorkItem), hipHostMallocDefault);
+            e = hipHostMalloc(reinterpret_cast<void **>(&srv->h_step), step_bytes,
+                              hipHostMallocDefault);
         if (e == hipSuccess)
-            e = hipMalloc(&srv->d_heads, bfi_server::kMaxGroups * sizeof(uint32_t));
+            std::memset(srv->h_step, 0, bfi_server::kHeadBytes);  // the heads stay zero
         if (e != hipSuccess) {
             if (srv->d_step)
                 (void)hipFree(srv->d_step);
@@ -562,10 +663,12 @@ bfi_status bfi_server_submit(bfi_server *srv, const bfi_request *req, uint64_t *
             const Layout need = layout_of(r->subs.size(), r->d, static_cast<size_t>(nitems),
                                           r->rec_len);
             std::lock_guard<std::mutex> lk(srv->mu);
-            if (need.total > srv->cfg.memory_budget) {
+            if (block_size(need.total) > srv->cfg.memory_budget) {
                 ++srv->stats.rejected;
-                return fail(BFI_EBUSY, "request needs %zu bytes of device state, budget is %llu",
-                            need.total, static_cast<unsigned long long>(srv->cfg.memory_budget));
+                return fail(BFI_EBUSY,
+                            "request needs a %zu-byte block of device state, budget is %llu",
+                            block_size(need.total),
+                            static_cast<unsigned long long>(srv->cfg.memory_budget));
             }
         }
         r->items.reserve(static_cast<size_t>(nitems));
@@ -676,9 +779,13 @@ bfi_status bfi_server_destroy(bfi_server *srv)
         (void)hipSetDevice(srv->ctx->device);
         for (auto &kv : srv->reqs)
             free_device(srv, kv.second.get());
+        pool_release(srv, 0);
         (void)hipFree(srv->d_step);
         (void)hipHostFree(srv->h_step);
-        (void)hipFree(srv->d_heads);
+        if (srv->h_stage)
+            (void)hipHostFree(srv->h_stage);
+        if (srv->h_done)
+            (void)hipHostFree(srv->h_done);
         for (int k = 0; k < bfi_server::kStreams; ++k)
             (void)hipStreamDestroy(srv->group_streams[k]);
         (void)hipEventDestroy(srv->staged);
