@@ -102,6 +102,14 @@ def lib():
         L.oracle_is_sums.argtypes = [latp, C.c_uint64, dp, dp, C.c_double, C.c_size_t, u64p, u64p,
                                      u64p, dp, C.c_int32]
         L.oracle_is_sums.restype = C.c_int
+        L.oracle_sph_volume.argtypes = [C.c_int32, C.c_double, C.c_double]
+        L.oracle_sph_volume.restype = C.c_double
+        L.oracle_sph_point.argtypes = [C.c_int32, C.c_uint64, C.c_uint64, C.c_double, C.c_double,
+                                       C.c_uint64, dp]
+        L.oracle_sph_point.restype = C.c_int
+        L.oracle_sph_sums.argtypes = [latp, C.c_uint64, C.c_double, C.c_size_t, u64p, dp, dp,
+                                      u64p, u64p, dp]
+        L.oracle_sph_sums.restype = C.c_int
         _lib = L
     return _lib
 
@@ -409,3 +417,47 @@ def integrate_is(lat: Lattice, seed: int, lo, hi, n_streams: int, budget: int,
     res["sums"] = s
     res["log_k"] = m["log_k"]
     return res
+
+
+# ------------------------------------------------ spherical coordinates
+
+def sph_volume(d: int, rho_lo: float, rho_hi: float) -> float:
+    v = lib().oracle_sph_volume(d, float(rho_lo), float(rho_hi))
+    if v < 0:
+        raise ValueError("oracle_sph_volume: invalid arguments")
+    return v
+
+
+def sph_point(d: int, seed: int, stream: int, rho_lo: float, rho_hi: float, index: int):
+    u = np.zeros(d)
+    if lib().oracle_sph_point(d, seed, stream, float(rho_lo), float(rho_hi), index,
+                              _ptr(u, C.c_double)) != 0:
+        raise ValueError("oracle_sph_point: invalid arguments")
+    return u
+
+
+def sph_sums(lat: Lattice, seed: int, box: float, ids, rho_lo, rho_hi, n, offset=0):
+    """Per-shell sums records of exp(-S) inside the cube [-box, box]^d."""
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    m = ids.shape[0]
+    rl = np.ascontiguousarray(np.broadcast_to(np.asarray(rho_lo, dtype=np.float64), (m,)))
+    rh = np.ascontiguousarray(np.broadcast_to(np.asarray(rho_hi, dtype=np.float64), (m,)))
+    n = np.ascontiguousarray(np.broadcast_to(np.asarray(n, dtype=np.uint64), (m,)))
+    offset = np.ascontiguousarray(np.broadcast_to(np.asarray(offset, dtype=np.uint64), (m,)))
+    out = np.zeros((m, sums_len(lat.nx)))
+    if lib().oracle_sph_sums(C.byref(lat), seed, float(box), m, _ptr(ids, C.c_uint64),
+                             _ptr(rl, C.c_double), _ptr(rh, C.c_double), _ptr(n, C.c_uint64),
+                             _ptr(offset, C.c_uint64), _ptr(out, C.c_double)) != 0:
+        raise ValueError("oracle_sph_sums: invalid arguments")
+    return out
+
+
+def sph_finalize(nx: int, d: int, rho_lo, rho_hi, sums_records) -> dict:
+    """finalize with shell volumes: each shell is passed as a 1-D 'box' of
+    length V (the finalize multiplies extents), padded with unit extents."""
+    rl, rh = np.atleast_1d(rho_lo), np.atleast_1d(rho_hi)
+    vol = np.array([sph_volume(d, a, b) for a, b in zip(rl, rh)])
+    lo = np.zeros((len(vol), d))
+    hi = np.ones((len(vol), d))
+    hi[:, 0] = vol
+    return finalize(nx, d, lo, hi, sums_records)

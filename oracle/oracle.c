@@ -878,3 +878,114 @@ int oracle_is_sums(const oracle_lattice *lat, uint64_t seed, const double *lo, c
     return run_sums(lat, seed, nstream, id, lo, hi, n, offset, sums, nthreads, 2,
                     gaussian_fraction, 0, 0);
 }
+
+/* ------------------------------------------------- spherical coordinates */
+
+/*
+ * Sampling in spherical coordinates (the paper's discussion proposes switching
+ * from cartesian to spherical coordinates to concentrate resolution where the
+ * subdivision needs it, on a shell about the origin).  The integration domain
+ * is still the cube [-B, B]^d; it is cut into radial shells rho_lo <= |u| <
+ * rho_hi about the origin (the outermost reaching the cube's corners,
+ * B sqrt(d)), and each shell is sampled uniformly in its own volume:
+ *   direction: omega = z / |z| with z_k independent standard normals, uniform on
+ *     the unit sphere (the normal density depends on |z| only);
+ *   radius: the volume of a shell element is proportional to rho^(d-1) d rho, so
+ *     with v uniform on (0, 1), rho^d = rho_lo^d + v (rho_hi^d - rho_lo^d), i.e.
+ *     rho = rho_hi (t + v (1 - t))^(1/d), t = (rho_lo / rho_hi)^d;
+ *   u = rho omega.
+ * A sample weighs exp(-S(u)) inside the cube and 0 outside; the shell's integral
+ * is its volume V = pi^(d/2) / Gamma(d/2 + 1) (rho_hi^d - rho_lo^d) times the
+ * mean weight, which is the record's finalize with V as the subvolume volume.
+ * Words: sample `index` of shell stream `id` takes W = 2 ceil(d/2) + 1 Philox
+ * words (counter (lo32 q, hi32 q, lo32 id, hi32 id), q = index * ceil(W/4) + j,
+ * key = seed): coordinate k's normal is the cosine (k even) or sine (k odd) of
+ * the Box-Muller pair of words 2 floor(k/2), 2 floor(k/2) + 1 (radius
+ * sqrt(-2 ln u1), angle 2 pi u2, u = (x + 1/2) 2^-32), and word 2 ceil(d/2)
+ * gives v = (x + 1/2) 2^-32.
+ */
+
+double oracle_sph_volume(int32_t d, double rho_lo, double rho_hi)
+{
+    if (d < 1 || !(rho_lo >= 0.0) || !(rho_hi > rho_lo) || !isfinite(rho_hi))
+        return -1.0;
+    /* unit-ball volume pi^(d/2) / Gamma(d/2 + 1), by logs; then the shell */
+    const double log_pi = 1.14472988584940017414342735135305871; /* ln pi */
+    const double log_unit = 0.5 * d * log_pi - lgamma(0.5 * d + 1.0);
+    const double t = pow(rho_lo / rho_hi, (double)d);
+    return exp(log_unit + d * log(rho_hi)) * (1.0 - t);
+}
+
+int oracle_sph_point(int32_t d, uint64_t seed, uint64_t id, double rho_lo, double rho_hi,
+                     uint64_t index, double *u)
+{
+    if (d < 1 || d > 64 || !u || !(rho_lo >= 0.0) || !(rho_hi > rho_lo) || !isfinite(rho_hi))
+        return -1;
+    const int32_t pairs = (d + 1) / 2, words = 2 * pairs + 1, nb = (words + 3) / 4;
+    uint32_t x[68];
+    for (int32_t j = 0; j < nb; ++j) {
+        const uint64_t q = index * (uint64_t)nb + (uint64_t)j;
+        const uint32_t ctr[4] = { (uint32_t)q, (uint32_t)(q >> 32), (uint32_t)id,
+                                  (uint32_t)(id >> 32) };
+        const uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+        oracle_philox4x32_10(ctr, key, x + 4 * j);
+    }
+    const double two_pi = 6.283185307179586476925286766559;
+    double norm2 = 0.0;
+    for (int32_t k = 0; k < d; ++k) {
+        const int32_t p = k / 2;
+        const double u1 = ((double)x[2 * p] + 0.5) * 0x1p-32;
+        const double u2 = ((double)x[2 * p + 1] + 0.5) * 0x1p-32;
+        const double r = sqrt(-2.0 * log(u1));
+        u[k] = (k % 2 == 0) ? r * cos(two_pi * u2) : r * sin(two_pi * u2);
+        norm2 += u[k] * u[k];
+    }
+    const double v = ((double)x[2 * pairs] + 0.5) * 0x1p-32;
+    const double t = pow(rho_lo / rho_hi, (double)d);
+    const double rho = rho_hi * pow(t + v * (1.0 - t), 1.0 / d);
+    const double f = rho / sqrt(norm2);
+    for (int32_t k = 0; k < d; ++k)
+        u[k] *= f;
+    return 0;
+}
+
+int oracle_sph_sums(const oracle_lattice *lat, uint64_t seed, double box, size_t nshell,
+                    const uint64_t *id, const double *rho_lo, const double *rho_hi,
+                    const uint64_t *n, const uint64_t *offset, double *sums)
+{
+    if (!lattice_ok(lat) || !(box > 0.0) || !isfinite(box) || (nshell && (!id || !rho_lo ||
+        !rho_hi || !n || !offset || !sums)) || lat->antithetic)
+        return -1;
+    const int32_t nx = lat->nx, d = nx * lat->nt, len = ORACLE_SUMS_LEN(nx);
+    if (nx > 64 || d > 64)
+        return -1;
+    double *u = (double *)malloc(sizeof(double) * (size_t)d);
+    double *p = (double *)malloc(sizeof(double) * (size_t)nx);
+    int rc = 0;
+    for (size_t s = 0; s < nshell && rc == 0; ++s) {
+        neumaier acc[3 + 3 * 64];
+        memset(acc, 0, sizeof(acc));
+        for (uint64_t i = 0; i < n[s] && rc == 0; ++i) {
+            rc = oracle_sph_point(d, seed, id[s], rho_lo[s], rho_hi[s], offset[s] + i, u);
+            int inside = 1;
+            for (int32_t k = 0; k < d; ++k)
+                inside = inside && fabs(u[k]) <= box;
+            const double w = inside ? exp(-oracle_action(lat, u)) : 0.0;
+            oracle_observable(lat, u, p);
+            nm_add(&acc[0], 1.0);
+            nm_add(&acc[1], w);
+            nm_add(&acc[2], w * w);
+            for (int32_t r = 0; r < nx; ++r) {
+                const double pw = p[r] * w;
+                nm_add(&acc[3 + r], pw);
+                nm_add(&acc[3 + nx + r], pw * pw);
+                nm_add(&acc[3 + 2 * nx + r], pw * w);
+            }
+        }
+        for (int32_t t = 0; t < len; ++t)
+            sums[s * (size_t)len + t] = nm_value(&acc[t]);
+    }
+    free(u);
+    free(p);
+    return rc;
+}

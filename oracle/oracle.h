@@ -186,6 +186,29 @@ int oracle_is_sums(const oracle_lattice *lat, uint64_t seed, const double *lo, c
                    double gaussian_fraction, size_t nstream, const uint64_t *id, const uint64_t *n,
                    const uint64_t *offset, double *sums, int32_t nthreads);
 
+/* Sampling in spherical coordinates over the cube [-box, box]^d, cut into
+ * radial shells rho_lo <= |u| < rho_hi (the paper's proposed change from
+ * cartesian to spherical coordinates).  Each shell is sampled uniformly in its
+ * volume: direction z/|z| from d standard normals, radius rho = rho_hi
+ * (t + v (1 - t))^(1/d) with t = (rho_lo/rho_hi)^d.  Words of sample `index` of
+ * stream `id`: W = 2 ceil(d/2) + 1 Philox words (counter (lo32 q, hi32 q,
+ * lo32 id, hi32 id), q = index * ceil(W/4) + j, key = seed); coordinate k's
+ * normal is the cosine (k even) or sine (k odd) of the Box-Muller pair of words
+ * 2 floor(k/2), 2 floor(k/2) + 1 (u = (x + 1/2) 2^-32, radius sqrt(-2 ln u1),
+ * angle 2 pi u2); v comes from word 2 ceil(d/2) the same way.
+ * oracle_sph_volume: the shell's volume pi^(d/2)/Gamma(d/2 + 1) (rho_hi^d -
+ *   rho_lo^d) (-1 on invalid arguments).
+ * oracle_sph_point: the point of one sample (d <= 64).
+ * oracle_sph_sums: per shell, the sums record (ORACLE_SUMS_LEN(nx)) of
+ *   w = exp(-S(u)) for u inside the cube (|u_k| <= box), 0 outside; finalize
+ *   with the shell volumes in place of box volumes. */
+double oracle_sph_volume(int32_t d, double rho_lo, double rho_hi);
+int oracle_sph_point(int32_t d, uint64_t seed, uint64_t id, double rho_lo, double rho_hi,
+                     uint64_t index, double *u);
+int oracle_sph_sums(const oracle_lattice *lat, uint64_t seed, double box, size_t nshell,
+                    const uint64_t *id, const double *rho_lo, const double *rho_hi,
+                    const uint64_t *n, const uint64_t *offset, double *sums);
+
 /* Plain Monte Carlo of the N-sphere integrand f(x) = sqrt(1 - |x|^2) (0 outside
  * the unit ball) over a box: out = [n, sum f, sum f^2, result, abserr]. */
 int oracle_nsphere(int32_t dim, uint64_t seed, uint64_t id, const double *lo, const double *hi,
