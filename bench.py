@@ -417,24 +417,30 @@ def antithetic_leg(bfi, torch, ctx, w, sv, steps, warmup, stream, accuracy_log2=
     return {"forms": forms, "error_at_equal_evals": boxes}
 
 
-def sampler_leg(bfi, ctx, w, budget_log2=28, alpha=0.9, repeats=3):
-    """The defensive Gaussian-proposal sampler against the plain one on the
-    10x2 lattice, same budget, FP32 form, on the benchmark box [-4,4]^20 and on
-    the paper's range [-1,1]^20: effective sample size (sum W)^2 / sum W^2,
-    wall time of the whole call (plan, kernel, finalize), and their ratio."""
+def sampler_leg(bfi, ctx, w, budget_log2=28, alpha=0.9, repeats=3, shells=64, pilot=0.125):
+    """The defensive Gaussian-proposal sampler and the sampler in spherical
+    coordinates (`shells` equal-width radial shells out to the cube's corners, a
+    pilot pass of `pilot` of the budget, then Neyman's allocation) against the
+    plain cartesian one on the 10x2 lattice, same budget, FP32 form, on the
+    benchmark box [-4,4]^20 and on the paper's range [-1,1]^20: effective
+    sample size (sum W)^2 / sum W^2, wall time of the whole call (plan, kernel,
+    finalize), and their ratio."""
     lat = bfi.lattice(w.nx, w.nt, nu=w.nu, D=w.D)
     budget = 1 << budget_log2
     out = []
     for B in (w.box, 1.0):
-        row = {"box": [-B, B], "evals": budget, "alpha": alpha}
-        for kind in ("plain", "gaussian_mixture"):
+        row = {"box": [-B, B], "evals": budget, "alpha": alpha, "shells": shells,
+               "pilot_fraction": pilot}
+        for kind in ("plain", "gaussian_mixture", "spherical"):
             best, res = None, None
             for _ in range(repeats):
                 t0 = time.perf_counter()
                 if kind == "plain":
                     res = bfi.bfi_integrate(ctx, lat, "fp32", 1, -B, B, w.split_log2, budget)
-                else:
+                elif kind == "gaussian_mixture":
                     res = bfi.bfi_integrate_is(ctx, lat, "fp32", 1, -B, B, budget, alpha, 256)
+                else:
+                    res = bfi.bfi_integrate_sph(ctx, lat, "fp32", 1, B, shells, budget, pilot)
                 dt = time.perf_counter() - t0
                 best = dt if best is None else min(best, dt)
             row[kind] = {"seconds": best, "evals_per_s": budget / best, "ess": res["ess"],
@@ -583,7 +589,7 @@ def main():
         pairs = antithetic_leg(bfi, torch, ctx, w, sv, args.steps, args.warmup, stream)
     sampler = None
     if not args.no_sampler_leg and w.nx * w.nt <= 32:
-        print("bench: Gaussian-proposal sampler", file=sys.stderr, flush=True)
+        print("bench: Gaussian-proposal and spherical samplers", file=sys.stderr, flush=True)
         sampler = sampler_leg(bfi, ctx, w)
     adaptive = None
     if args.adaptive_budget_log2 > 0:

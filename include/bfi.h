@@ -497,6 +497,62 @@ bfi_status bfi_debug_is_points(bfi_context *ctx, const bfi_lattice *lat, bfi_pre
                                const uint64_t *index, uint64_t n, double *u_out,
                                double *half_z2_out);
 
+/* Monte Carlo in spherical coordinates (the paper's discussion proposes
+ * switching from cartesian to spherical coordinates to concentrate resolution
+ * on the shell about the origin where the subdivision gathers).  The
+ * integration domain stays the cube [-box, box]^d; it is cut into radial
+ * shells rho_lo <= |u| < rho_hi about the origin, and each shell is sampled
+ * uniformly in its volume: direction z/|z| from d standard normals, radius
+ * rho = rho_hi (t + v (1 - t))^(1/d) with t = (rho_lo/rho_hi)^d and v uniform.
+ * A sample weighs exp(-S) inside the cube and 0 outside; a shell's integral is
+ * its volume pi^(d/2) / Gamma(d/2 + 1) (rho_hi^d - rho_lo^d) times the mean
+ * weight.  Words of sample i of stream `id`: W = 2 ceil(d/2) + 1 Philox words,
+ * block j with counter (lo32 q, hi32 q, lo32 id, hi32 id), q = i * ceil(W/4) + j,
+ * key = seed; coordinate k's normal is the cosine (k even) or sine (k odd) of
+ * the Box-Muller pair of words 2 floor(k/2), 2 floor(k/2) + 1 (u = (x + 1/2)
+ * 2^-32, radius sqrt(-2 ln u1), angle 2 pi u2); word 2 ceil(d/2) gives v.
+ * d <= 32, single points, BFI_FP64 or BFI_FP32_SHIFTED (BFI_FP64_SHIFTED:
+ * EUNSUPPORTED); both observables.
+ *
+ * A list of shells (host arrays, caller-owned): stream id, radii (0 <= rho_lo <
+ * rho_hi, finite), sample count (>= 2) and first sample index per shell. */
+typedef struct {
+    size_t count;
+    const uint64_t *id;
+    const double *rho_lo;
+    const double *rho_hi;
+    const uint64_t *n;
+    const uint64_t *offset;
+} bfi_shells;
+
+/* Per-shell partial records (count x BFI_PARTIAL_LEN(nx), host) of the weight
+ * exp(-S) 1_cube over each shell's samples.  Blocking.  launch: NULL or a
+ * shape (default 256 samples per thread, 256-thread persistent blocks).
+ * Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
+bfi_status bfi_sph_eval(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
+                        uint64_t seed, double box, const bfi_shells *shells,
+                        const bfi_launch *launch, double *partials);
+/* Z, C(r) and their errors from per-shell records, each shell weighted by its
+ * volume.  Host only.  Errors: EINVAL. */
+bfi_status bfi_sph_finalize(const bfi_lattice *lat, const bfi_shells *shells,
+                            const double *partials, bfi_result *out);
+/* Two-stage estimate over `nshells` equal-width shells from the centre to the
+ * cube's corners (rho up to box sqrt(d); shell s has stream id s + 1): a pilot
+ * pass of floor(pilot_fraction budget / nshells) samples per shell, then the
+ * rest of the budget allocated in proportion to shell volume times the pilot's
+ * standard deviation of the weight (Neyman's allocation), each shell continuing
+ * its stream after its pilot samples; records merged, finalized.  Errors:
+ * EINVAL (pilot below 2 samples per shell, bad fraction or count), and those
+ * of bfi_sph_eval. */
+bfi_status bfi_integrate_sph(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
+                             uint64_t seed, double box, int32_t nshells, uint64_t budget,
+                             double pilot_fraction, const bfi_launch *launch, bfi_result *out);
+/* Test hook: the points (n x d, host) of shell [rho_lo, rho_hi) of stream id
+ * at sample indices index[0 .. n-1], as the kernel computes them. */
+bfi_status bfi_debug_sph_points(bfi_context *ctx, const bfi_lattice *lat, bfi_precision prec,
+                                uint64_t seed, uint64_t id, double rho_lo, double rho_hi,
+                                uint64_t n, const uint64_t *index, double *out);
+
 /* Continuous-batching request server on one context.  Requests are admitted
  * while their device state fits `memory_budget` bytes and a slot is free; their
  * partial sums stay resident on the device; every scheduling step packs chunks

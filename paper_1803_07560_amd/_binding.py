@@ -97,6 +97,12 @@ class bfi_adaptive_stats(C.Structure):
                 ("graph_instantiations", C.c_int32), ("graph_updates", C.c_int32)]
 
 
+class bfi_shells(C.Structure):
+    _fields_ = [("count", C.c_size_t), ("id", C.POINTER(C.c_uint64)),
+                ("rho_lo", C.POINTER(C.c_double)), ("rho_hi", C.POINTER(C.c_double)),
+                ("n", C.POINTER(C.c_uint64)), ("offset", C.POINTER(C.c_uint64))]
+
+
 class bfi_server_config(C.Structure):
     _fields_ = [("memory_budget", C.c_uint64), ("max_requests", C.c_int32),
                 ("chunks_per_step", C.c_int32), ("max_pending", C.c_int32),
@@ -196,6 +202,14 @@ _SIGNATURES = {
     "bfi_debug_is_points": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, C.c_double, C.c_double,
                              C.c_uint64, _P(C.c_uint64), C.c_uint64, _P(C.c_double),
                              _P(C.c_double)], C.c_int),
+    "bfi_sph_eval": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, C.c_double, _P(bfi_shells),
+                      _P(bfi_launch), _P(C.c_double)], C.c_int),
+    "bfi_sph_finalize": ([_P(bfi_lattice), _P(bfi_shells), _P(C.c_double), _P(bfi_result)],
+                         C.c_int),
+    "bfi_integrate_sph": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, C.c_double, C.c_int32,
+                           C.c_uint64, C.c_double, _P(bfi_launch), _P(bfi_result)], C.c_int),
+    "bfi_debug_sph_points": ([_vp, _P(bfi_lattice), C.c_int, C.c_uint64, C.c_uint64, C.c_double,
+                              C.c_double, C.c_uint64, _P(C.c_uint64), _P(C.c_double)], C.c_int),
     "bfi_server_create": ([_vp, _P(bfi_server_config), _P(_vp)], C.c_int),
     "bfi_server_submit": ([_vp, _P(bfi_request), _P(C.c_uint64)], C.c_int),
     "bfi_server_poll": ([_vp, C.c_uint64, _P(bfi_result), _P(C.c_int32), _P(C.c_double)], C.c_int),
@@ -593,6 +607,59 @@ def bfi_debug_is_points(ctx, lat, prec, seed, box_lo, box_hi, stream, index):
                                       float(box_hi), int(stream), _u64p(idx), idx.shape[0],
                                       _dp(u), _dp(hz)), "bfi_debug_is_points")
     return u, hz
+
+
+class Shells:
+    """Owns contiguous arrays for a bfi_shells view (ids, radii, n, offset)."""
+
+    def __init__(self, ids, rho_lo, rho_hi, n, offset=0):
+        self.ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        m = self.ids.shape[0]
+        bc = lambda a, t: np.ascontiguousarray(np.broadcast_to(np.asarray(a, t), (m,)))  # noqa: E731
+        self.rho_lo, self.rho_hi = bc(rho_lo, np.float64), bc(rho_hi, np.float64)
+        self.n, self.offset = bc(n, np.uint64), bc(offset, np.uint64)
+        self.view = bfi_shells(m, _u64p(self.ids), _dp(self.rho_lo), _dp(self.rho_hi),
+                               _u64p(self.n), _u64p(self.offset))
+
+    def __len__(self):
+        return int(self.ids.shape[0])
+
+
+def bfi_sph_eval(ctx, lat, prec, seed, box, shells, launch_=None) -> np.ndarray:
+    sh = shells if isinstance(shells, Shells) else Shells(*shells)
+    part = np.zeros((len(sh), partial_len(lat.nx)))
+    _check(load().bfi_sph_eval(ctx, C.byref(lat), _prec(prec), int(seed), float(box),
+                               C.byref(sh.view), C.byref(launch_) if launch_ is not None else None,
+                               _dp(part)), "bfi_sph_eval")
+    return part
+
+
+def bfi_sph_finalize(lat, shells, partials) -> dict:
+    sh = shells if isinstance(shells, Shells) else Shells(*shells)
+    p = np.ascontiguousarray(partials, dtype=np.float64)
+    res = bfi_result()
+    _check(load().bfi_sph_finalize(C.byref(lat), C.byref(sh.view), _dp(p), C.byref(res)),
+           "bfi_sph_finalize")
+    return res.to_dict()
+
+
+def bfi_integrate_sph(ctx, lat, prec, seed, box, nshells, budget, pilot_fraction=0.125,
+                      launch_=None) -> dict:
+    res = bfi_result()
+    _check(load().bfi_integrate_sph(ctx, C.byref(lat), _prec(prec), int(seed), float(box),
+                                    int(nshells), int(budget), float(pilot_fraction),
+                                    C.byref(launch_) if launch_ is not None else None,
+                                    C.byref(res)), "bfi_integrate_sph")
+    return res.to_dict()
+
+
+def bfi_debug_sph_points(ctx, lat, prec, seed, sid, rho_lo, rho_hi, index) -> np.ndarray:
+    idx = np.ascontiguousarray(index, dtype=np.uint64)
+    out = np.zeros((idx.shape[0], lat.d))
+    _check(load().bfi_debug_sph_points(ctx, C.byref(lat), _prec(prec), int(seed), int(sid),
+                                       float(rho_lo), float(rho_hi), idx.shape[0], _u64p(idx),
+                                       _dp(out)), "bfi_debug_sph_points")
+    return out
 
 
 def server_config(memory_budget=1 << 30, max_requests=256, chunks_per_step=4,

@@ -28,7 +28,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "inclu
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops"]
 HOST_SOURCES = ["runtime.cpp", "tune.cpp", "adaptive.cpp", "server.cpp", "integrand.cpp",
-                "sampler.cpp", "resident.cpp"]
+                "sampler.cpp", "resident.cpp", "spherical.cpp"]
 
 
 def shapes() -> list[tuple[int, int]]:
@@ -67,6 +67,9 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         tasks.append([cc, *COMMON, *DEVICE, f"-DBFI_NX={nx}", f"-DBFI_NT={nt}", "-c",
                       os.path.join(CSRC, "is_kernels.hip"), "-o",
                       os.path.join(BUILD, f"is_{nx}x{nt}.o")])
+        tasks.append([cc, *COMMON, *DEVICE, f"-DBFI_NX={nx}", f"-DBFI_NT={nt}", "-c",
+                      os.path.join(CSRC, "sph_kernels.hip"), "-o",
+                      os.path.join(BUILD, f"sph_{nx}x{nt}.o")])
     for src in ("common_kernels.hip", "noalloc.hip"):
         tasks.append([cc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o",
                       os.path.join(BUILD, src.replace(".hip", ".o"))])

@@ -22,6 +22,7 @@
 
 #include "device.hpp"
 #include "is_internal.h"
+#include "normals.hpp"
 
 #ifndef BFI_NX
 #error "compile with -DBFI_NX=<nx> -DBFI_NT=<nt>"
@@ -186,30 +187,6 @@ struct Transform {
 
 // ------------------------------------------------------------- sampling
 
-// Box-Muller: a standard normal pair from two words, u = (x + 1/2) 2^-32,
-// radius sqrt(-2 ln u1), angle 2 pi u2.
-__device__ __forceinline__ void box_muller(uint32_t x1, uint32_t x2, double &zc, double &zs)
-{
-    const double u1 = __fma_rn(static_cast<double>(x1), 0x1p-32, 0x1p-33);
-    const double u2 = __fma_rn(static_cast<double>(x2), 0x1p-32, 0x1p-33);
-    const double r = sqrt(-2.0 * log(u1));
-    double s, c;
-    sincospi(2.0 * u2, &s, &c);
-    zc = r * c;
-    zs = r * s;
-}
-// FP32: hardware log2, square root and sine/cosine (whose argument is in
-// turns, so the angle 2 pi u2 is u2 itself)
-__device__ __forceinline__ void box_muller(uint32_t x1, uint32_t x2, float &zc, float &zs)
-{
-    const float u1 = __fmaf_rn(static_cast<float>(x1), 0x1p-32f, 0x1p-33f);
-    const float u2 = __fmaf_rn(static_cast<float>(x2), 0x1p-32f, 0x1p-33f);
-    constexpr float kMinus2Ln2 = -1.38629436111989061883f;
-    const float r = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(u1));
-    zc = r * __builtin_amdgcn_cosf(u2);
-    zs = r * __builtin_amdgcn_sinf(u2);
-}
-
 // log(exp(g1) + exp(g2)) with g2 possibly -inf
 __device__ __forceinline__ double log_add(double g1, double g2)
 {
@@ -243,7 +220,7 @@ __device__ __forceinline__ T gaussian_point(uint64_t index, uint32_t id_lo, uint
         if ((p & 1) == 0)
             dev::philox_block(q0 + (p >> 1), id_lo, id_hi, key_lo, key_hi, blk);
         T zc, zs;
-        box_muller(blk[2 * (p & 1)], blk[2 * (p & 1) + 1], zc, zs);
+        dev::box_muller(blk[2 * (p & 1)], blk[2 * (p & 1) + 1], zc, zs);
         const int j0 = 2 * p, j1 = 2 * p + 1;
         a[j0] = scale[j0] * zc;
         const T h0 = T(0.5) * zc * zc;

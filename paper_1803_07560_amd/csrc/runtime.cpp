@@ -91,6 +91,36 @@ hipError_t is_kernel_info(int nx, int nt, const LaunchSpec &spec, KernelInfo *in
     return hipErrorNotSupported;
 }
 
+hipError_t launch_sph(int nx, int nt, const LaunchSpec &spec, const SphArgs &args, hipStream_t st)
+{
+#define BFI_SPH_LAUNCH(NX, NT)                               \
+    if (nx == NX && nt == NT)                                \
+        return launch_sph_shape<NX, NT>(spec, args, st);
+    BFI_SHAPES(BFI_SPH_LAUNCH)
+#undef BFI_SPH_LAUNCH
+    return hipErrorNotSupported;
+}
+
+hipError_t sph_kernel_info(int nx, int nt, const LaunchSpec &spec, KernelInfo *info)
+{
+#define BFI_SPH_INFO(NX, NT)                                 \
+    if (nx == NX && nt == NT)                                \
+        return sph_kernel_info_shape<NX, NT>(spec, info);
+    BFI_SHAPES(BFI_SPH_INFO)
+#undef BFI_SPH_INFO
+    return hipErrorNotSupported;
+}
+
+hipError_t launch_sph_debug(int nx, int nt, const SphDebugArgs &args, hipStream_t st)
+{
+#define BFI_SPH_DEBUG(NX, NT)                                \
+    if (nx == NX && nt == NT)                                \
+        return launch_sph_debug_shape<NX, NT>(args, st);
+    BFI_SHAPES(BFI_SPH_DEBUG)
+#undef BFI_SPH_DEBUG
+    return hipErrorNotSupported;
+}
+
 hipError_t launch_is_debug(int nx, int nt, const IsDebugArgs &args, hipStream_t st)
 {
 #define BFI_IS_DEBUG(NX, NT)                                 \

@@ -21,6 +21,7 @@
 #include "bfi.h"
 #include "internal.h"
 #include "is_internal.h"
+#include "sph_internal.h"
 
 namespace bfi {
 
@@ -55,6 +56,10 @@ hipError_t kernel_info(int nx, int nt, const LaunchSpec &spec, KernelInfo *info)
 hipError_t launch_is(int nx, int nt, const LaunchSpec &spec, const IsArgs &args, hipStream_t st);
 hipError_t is_kernel_info(int nx, int nt, const LaunchSpec &spec, KernelInfo *info);
 hipError_t launch_is_debug(int nx, int nt, const IsDebugArgs &args, hipStream_t st);
+// Spherical-coordinate sampler kernels of shape (nx, nt).
+hipError_t launch_sph(int nx, int nt, const LaunchSpec &spec, const SphArgs &args, hipStream_t st);
+hipError_t sph_kernel_info(int nx, int nt, const LaunchSpec &spec, KernelInfo *info);
+hipError_t launch_sph_debug(int nx, int nt, const SphDebugArgs &args, hipStream_t st);
 bfi_status check_lattice(const bfi_lattice *lat);
 bfi_status check_subvolumes(const bfi_lattice *lat, const bfi_subvolumes *subs);
 ActionCoef make_coef(const bfi_lattice &lat);

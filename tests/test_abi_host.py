@@ -1,6 +1,7 @@
 """The C ABI library loads, exports every entry point ``include/bfi.h``
 declares, and its host-only logic (shape table, validation, finalize) agrees
 with the oracle.  No GPU: nothing here launches a kernel."""
+import math
 import os
 import re
 import subprocess
@@ -273,3 +274,21 @@ def test_finalize_of_many_records_matches_oracle(bfi, k):
     again = bfi.bfi_finalize(bfi.lattice(nx, 2), sv, shifted)
     assert again["log_Z"] == pytest.approx(got["log_Z"], abs=1e-12)
     np.testing.assert_allclose(again["C"], got["C"], rtol=1e-10, atol=1e-13)
+
+
+def test_sph_finalize_matches_oracle(bfi):
+    """bfi_sph_finalize weights each shell by its volume: on the oracle's own
+    records it gives the oracle's finalize with shell volumes (host only)."""
+    lat_o = oracle.lattice(3, 1)
+    edges = np.linspace(0.0, 2.0 * math.sqrt(3.0), 7)
+    ids = np.arange(1, 7, dtype=np.uint64)
+    s = oracle.sph_sums(lat_o, 4, 2.0, ids, edges[:-1], edges[1:], 3000)
+    ref = oracle.sph_finalize(3, 3, edges[:-1], edges[1:], s)
+    part = np.zeros((6, 4 + 9))
+    part[:, 0] = s[:, 0]
+    part[:, 2:] = s[:, 1:]
+    got = bfi.bfi_sph_finalize(bfi.lattice(3, 1), bfi.Shells(ids, edges[:-1], edges[1:], 3000),
+                               part)
+    assert got["Z"] == pytest.approx(ref["Z"], rel=1e-13)
+    np.testing.assert_allclose(got["C"], ref["C"], rtol=1e-12)
+    np.testing.assert_allclose(got["C_err"], ref["C_err"], rtol=1e-10)

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(ROOT, "paper_1803_07560_amd", "csrc")
 BUILD = os.path.join(ROOT, "paper_1803_07560_amd", "_build")
-HOST_SOURCES = ["runtime", "tune", "adaptive", "server", "integrand", "sampler", "resident"]
+HOST_SOURCES = ["runtime", "tune", "adaptive", "server", "integrand", "sampler", "resident",
+                "spherical"]
 # sanitizers for the host pass only (device code is never built with them)
 HOST_SAN = ("-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined "
             "-Xarch_host -fno-omit-frame-pointer").split()
@@ -29,6 +30,7 @@ def test_host_entry_points_under_asan_ubsan(tmp_path):
         pytest.skip("hipcc not available")
     device = sorted(glob.glob(os.path.join(BUILD, "shape_*.o")) +
                     glob.glob(os.path.join(BUILD, "is_*.o")) +
+                    glob.glob(os.path.join(BUILD, "sph_*.o")) +
                     [os.path.join(BUILD, "common_kernels.o"), os.path.join(BUILD, "noalloc.o")])
     if not all(os.path.exists(p) for p in device) or len(device) < 3:
         pytest.skip("library not built")
