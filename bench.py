@@ -47,27 +47,38 @@ PEAK_SLOTS = 256 * 64 * 2.4e9   # FP64-rate lane slots per second (= FP64 FMA/s)
 PEAK_FP64 = 78.6e12
 
 
-def valu_slots_per_eval(nx: int, nt: int, prec: str) -> float:
+def valu_slots_per_eval(nx: int, nt: int, prec: str, observable: str = "anchor") -> float:
     """FP64-rate lane slots one evaluation needs (algorithmic instruction counts):
       Philox4x32-10: per block 10 rounds x (2 wide 32x32 multiplies + 2 xor3)
       point map:     per variable one u32->float conversion and one fma
       action:        per site 6 (two sums/differences, three fma, one fma into S), + 1
       weight:        FP64 exp routine; FP32 form: multiply, exp2, widen to FP64
-      sums:          w, w^2 (2) + u_0 w (1) + per r: product, add, 2 fma (4)
-                     FP32 form: the product in FP32, then one widening per r"""
+      sums:          w, w^2 (2) + p_r scale x w (1) + per r: product, add, 2 fma (4)
+                     FP32 form: the product in FP32, then one widening per r
+      averaged observable: r = 0 .. nx/2 only; p_r = sum over the sites and time
+                     slices of u_m u_{m+r} (one fma per term, the pair at r = nx/2
+                     counted once and doubled)"""
     d, nb = nx * nt, (nx * nt + 3) // 4
+    avg = observable == "averaged"
+    nr = nx // 2 + 1 if avg else nx
+    f = SLOT["f64"] if prec == "fp64" else SLOT["f32"]
     philox = nb * 10 * (2 * SLOT["mul32"] + 2 * SLOT["logic32"])
     if prec == "fp64":
         mapping = d * (SLOT["cvt"] + SLOT["f64"])
         action = (6 * d + 1) * SLOT["f64"]
         weight = EXP64_OPS * SLOT["f64"]
-        sums = (3 + 4 * nx) * SLOT["f64"]
+        sums = (3 + 4 * nr) * SLOT["f64"]
     else:
         mapping = d * (SLOT["cvt"] * 0.5 + SLOT["f32"])   # u32->f32 is a 32-bit op
         action = (6 * d + 1) * SLOT["f32"]
         weight = SLOT["f32"] + SLOT["trans"] + SLOT["cvt"] + SLOT["f32"]  # (sigma-S)*log2e, exp2, widen, compare
-        sums = (2 + 3 * nx) * SLOT["f64"] + nx * (SLOT["f32"] + SLOT["cvt"]) + SLOT["f32"]
-    return philox + mapping + action + weight + sums
+        sums = (2 + 3 * nr) * SLOT["f64"] + nr * (SLOT["f32"] + SLOT["cvt"]) + SLOT["f32"]
+    observable_terms = 0.0
+    if avg:
+        half = nx % 2 == 0 and nx > 1
+        terms = sum(nx // 2 if half and 2 * r == nx else nx for r in range(nr))
+        observable_terms = (nt * terms + (1 if half else 0)) * f
+    return philox + mapping + action + weight + sums + observable_terms
 
 
 def fp64_flops_per_eval(nx: int, nt: int) -> float:
@@ -188,6 +199,7 @@ def run_form(bfi, torch, ctx, lat, sv, w, prec, steps, warmup, stream):
             "step_ms_each": [round(float(x), 3) for x in step_ms[:200]],
             "kernel_ms_each": [round(float(x), 3) for x in kernel_ms[:200]],
             "kernel_ms": float(np.mean(kernel_ms)), "kernel_ms_min": float(np.min(kernel_ms)),
+            "kernel_ms_median": float(np.median(kernel_ms)),
             "evals_per_step": evals, "result": res, "partials": part,
             "launch": {k: info[k] for k in ("samples_per_thread", "block", "persistent",
                                             "use_graph")}, "n_items": info["n_items"]}
@@ -368,8 +380,12 @@ def observable_leg(bfi, torch, ctx, w, sv, steps, warmup, stream, accuracy_log2=
     for prec in ("fp64", "fp32"):
         print(f"bench: averaged observable {prec}", file=sys.stderr, flush=True)
         f = run_form(bfi, torch, ctx, lat, sv, w, prec, steps, warmup, stream)
+        slots = valu_slots_per_eval(w.nx, w.nt, prec, "averaged")
+        rate = slots * f["evals_per_step"] / PEAK_SLOTS
         forms[prec] = {"evals_per_s": f["evals_per_s"], "ms_per_step": f["ms_per_step"],
-                       "kernel_ms": f["kernel_ms"]}
+                       "kernel_ms": f["kernel_ms"], "kernel_ms_median": f["kernel_ms_median"],
+                       "slots_per_eval": slots, "valu_frac": rate / (f["kernel_ms"] * 1e-3),
+                       "valu_frac_median": rate / (f["kernel_ms_median"] * 1e-3)}
     est = {}
     for obs in ("anchor", "averaged"):
         est[obs] = bfi.bfi_integrate(ctx, bfi.lattice(w.nx, w.nt, nu=w.nu, D=w.D, observable=obs),
@@ -670,7 +686,8 @@ def main():
         "forms": {p: {"evals_per_s": f["evals_per_s"], "ms_per_step": f["ms_per_step"],
                       "step_ms_median": f["step_ms_median"], "step_ms_max": f["step_ms_max"],
                       "step_ms_each": f["step_ms_each"], "kernel_ms_each": f["kernel_ms_each"],
-                      "kernel_ms": f["kernel_ms"], "kernel_evals_per_s":
+                      "kernel_ms": f["kernel_ms"], "kernel_ms_median": f["kernel_ms_median"],
+                      "kernel_evals_per_s":
                           f["evals_per_step"] / (f["kernel_ms"] * 1e-3),
                       "valu_frac": valu_slots_per_eval(w.nx, w.nt, p) * f["evals_per_step"] /
                           (f["kernel_ms"] * 1e-3) / PEAK_SLOTS,

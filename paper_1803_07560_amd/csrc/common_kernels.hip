@@ -74,7 +74,12 @@ __global__ void reset_head_kernel(uint32_t *head)
 // One block per subvolume; thread f merges field f over the subvolume's items
 // in item order with Neumaier compensation, after moving every item to the
 // smallest shift of the subvolume (factor exp(sigma_min - sigma_item) for
-// first-order sums, its square for second-order sums; 1 in FP64 form).
+// first-order sums, its square for second-order sums; 1 in FP64 form).  Items
+// are read kMergeBatch at a time, all loads of a batch issued before its
+// arithmetic (the sums keep item order), so that a subvolume of many items
+// is not one load latency per item.
+constexpr uint32_t kMergeBatch = 8;
+
 __global__ void __launch_bounds__(64) merge_kernel(MergeArgs m)
 {
     const uint32_t s = blockIdx.x;
@@ -86,8 +91,16 @@ __global__ void __launch_bounds__(64) merge_kernel(MergeArgs m)
     const uint32_t i0 = m.sub_first[s], i1 = m.sub_first[s + 1];
 
     double sigma = __builtin_inf();
-    for (uint32_t i = i0; i < i1; ++i)
-        sigma = fmin(sigma, m.item_rec[static_cast<size_t>(i) * rec_len + 1]);
+    for (uint32_t i = i0; i < i1; i += kMergeBatch) {
+        double sg[kMergeBatch];
+#pragma unroll
+        for (uint32_t j = 0; j < kMergeBatch; ++j)
+            sg[j] = i + j < i1 ? m.item_rec[static_cast<size_t>(i + j) * rec_len + 1]
+                               : __builtin_inf();
+#pragma unroll
+        for (uint32_t j = 0; j < kMergeBatch; ++j)
+            sigma = fmin(sigma, sg[j]);
+    }
     if (i0 == i1)
         sigma = 0.0;
 
@@ -101,17 +114,31 @@ __global__ void __launch_bounds__(64) merge_kernel(MergeArgs m)
         else
             order = (f - rec_len) < d ? 1 : 2;
         double sum = 0.0, comp = 0.0;
-        for (uint32_t i = i0; i < i1; ++i) {
-            const double *rec = m.item_rec + static_cast<size_t>(i) * rec_len;
-            double v = f < rec_len ? rec[f]
-                                   : m.item_split[static_cast<size_t>(i) * (2 * d) + (f - rec_len)];
-            if (order != 0) {
-                const double f1 = exp(sigma - rec[1]);
-                v *= order == 1 ? f1 : f1 * f1;
+        for (uint32_t i = i0; i < i1; i += kMergeBatch) {
+            double vb[kMergeBatch], sb[kMergeBatch];
+#pragma unroll
+            for (uint32_t j = 0; j < kMergeBatch; ++j) {
+                if (i + j < i1) {
+                    const double *rec = m.item_rec + static_cast<size_t>(i + j) * rec_len;
+                    vb[j] = f < rec_len ? rec[f]
+                                        : m.item_split[static_cast<size_t>(i + j) * (2 * d) +
+                                                       (f - rec_len)];
+                    sb[j] = rec[1];
+                }
             }
-            const double t = sum + v;
-            comp += fabs(sum) >= fabs(v) ? (sum - t) + v : (v - t) + sum;
-            sum = t;
+#pragma unroll
+            for (uint32_t j = 0; j < kMergeBatch; ++j) {
+                if (i + j < i1) {
+                    double v = vb[j];
+                    if (order != 0) {
+                        const double f1 = exp(sigma - sb[j]);
+                        v *= order == 1 ? f1 : f1 * f1;
+                    }
+                    const double t = sum + v;
+                    comp += fabs(sum) >= fabs(v) ? (sum - t) + v : (v - t) + sum;
+                    sum = t;
+                }
+            }
         }
         if (f < rec_len)
             out[f] = sum + comp;

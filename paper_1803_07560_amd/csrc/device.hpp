@@ -21,7 +21,30 @@ namespace dev {
 //   FmaSgprCoef: scalar moves rematerialize it in an SGPR pair before each step,
 //     which holds no VGPRs (the 16x4 kernels then do not spill) at the cost of
 //     those scalar moves.
+//   Coefficients sharing a low word (1/3! and 1/4!, 1/7! and 1/8!) would be
+//   held once and their pairs rebuilt with a copy per sample: FmaVgprCoef
+//   therefore holds each as a value of its own, made opaque once per object;
+//   FmaVgprConst leaves them constants the compiler may rematerialize, which
+//   costs those copies but no registers where pressure peaks elsewhere.
+}  // namespace dev
+}  // namespace bfi
+
+#define BFI_HD __device__
+#include "exp64.hpp"
+
+namespace bfi {
+namespace dev {
 struct FmaVgprCoef {
+    double c[12];
+    __device__ FmaVgprCoef()
+    {
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+            c[j] = expk::kInvFact[j];
+            asm volatile("" : "+v"(c[j]));
+        }
+    }
+    __device__ double coef(int j) const { return c[j]; }
     __device__ static double step(double a, double b, double c)
     {
         double d;
@@ -29,7 +52,15 @@ struct FmaVgprCoef {
         return d;
     }
 };
+struct FmaVgprConst {
+    __device__ static constexpr double coef(int j) { return expk::kInvFact[j]; }
+    __device__ static double step(double a, double b, double c)
+    {
+        return FmaVgprCoef::step(a, b, c);
+    }
+};
 struct FmaSgprCoef {
+    __device__ static constexpr double coef(int j) { return expk::kInvFact[j]; }
     __device__ static double step(double a, double b, double c)
     {
         double d;
@@ -39,9 +70,6 @@ struct FmaSgprCoef {
 };
 }  // namespace dev
 }  // namespace bfi
-
-#define BFI_HD __device__
-#include "exp64.hpp"
 
 namespace bfi {
 namespace dev {
@@ -122,13 +150,22 @@ __device__ __forceinline__ PhiloxItem philox_item(uint32_t c1, uint32_t id_lo, u
     return p;
 }
 
+// a * b + c in one instruction; the addend is a VGPR pair (one scalar operand
+// per instruction: b).
+__device__ __forceinline__ uint64_t mad_wide(uint32_t a, uint32_t b, uint64_t c)
+{
+    uint64_t r;
+    asm("v_mad_u64_u32 %0, vcc, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c) : "vcc");
+    return r;
+}
+
 // philox_block for counter (c0, c1, id_lo, id_hi) with the item's share `p`
-// (same c1, id and key): the same words, two wide multiplies and one xor fewer.
-__device__ __forceinline__ void philox_block_item(uint32_t c0, const PhiloxItem &p,
-                                                  uint32_t out[4])
+// (same c1, id and key), given round 0's product a0 = c0 * kPhiloxMulA: the
+// same words, two wide multiplies and one xor fewer.
+__device__ __forceinline__ void philox_rounds_item(uint64_t a0, const PhiloxItem &p,
+                                                   uint32_t out[4])
 {
     // round 0: only word 2's product depends on the block
-    const uint64_t a0 = mul_wide(c0, kPhiloxMulA);
     const uint32_t w2 = static_cast<uint32_t>(a0 >> 32) ^ p.x2_r0;
     const uint32_t w3 = static_cast<uint32_t>(a0);
     // round 1: word 0 and its product are the item's
@@ -159,6 +196,21 @@ __device__ __forceinline__ void philox_block_item(uint32_t c0, const PhiloxItem 
     out[1] = c1n;
     out[2] = c2n;
     out[3] = c3n;
+}
+
+__device__ __forceinline__ void philox_block_item(uint32_t c0, const PhiloxItem &p,
+                                                  uint32_t out[4])
+{
+    philox_rounds_item(mul_wide(c0, kPhiloxMulA), p, out);
+}
+
+// Block c0 = lo + j of a sample whose blocks lo .. lo + NB - 1 do not wrap in
+// 32 bits (the item keeps one upper word): (lo + j) A = lo A + j A, so the
+// counter's add rides in round 0's multiply as its addend `jA` = j A.
+__device__ __forceinline__ void philox_block_item_at(uint32_t lo, uint64_t jA,
+                                                     const PhiloxItem &p, uint32_t out[4])
+{
+    philox_rounds_item(mad_wide(lo, kPhiloxMulA, jA), p, out);
 }
 
 // Word -> coordinate: u = fma(x, scale, base), one rounding.

@@ -31,24 +31,26 @@ constexpr double kInvFact[12] = {
     0x1.27e4fb7789f5cp-22, 0x1.ae64567f544e4p-26, 0x1.1eed8eff8d898p-29, 0x1.6124613a86d09p-33};
 }  // namespace expk
 
-// The fused multiply-add of the polynomial steps; a caller may pass its own
-// (same arithmetic, another encoding), as the GPU kernels do.
+// The fused multiply-add of the polynomial steps and where its coefficients
+// come from; a caller may pass its own (same arithmetic, another encoding or
+// register class), as the GPU kernels do.
 struct BuiltinFma {
     BFI_HD static double step(double a, double b, double c) { return __builtin_fma(a, b, c); }
+    BFI_HD static constexpr double coef(int j) { return expk::kInvFact[j]; }
 };
 
 template <class Fma = BuiltinFma>
-BFI_HD inline double exp_weight(double x)
+BFI_HD inline double exp_weight(double x, const Fma &fma = Fma())
 {
     x = x < -746.0 ? -746.0 : x;
     const double k = __builtin_rint(x * expk::kInvLn2);
     double r = __builtin_fma(-k, expk::kLn2Hi, x);
     r = __builtin_fma(-k, expk::kLn2Lo, r);
-    double p = expk::kInvFact[11];
+    double p = fma.coef(11);
     for (int j = 10; j >= 0; --j)
-        p = Fma::step(p, r, expk::kInvFact[j]);
-    p = Fma::step(p, r, 1.0);
-    p = Fma::step(p, r, 1.0);
+        p = fma.step(p, r, fma.coef(j));
+    p = fma.step(p, r, 1.0);
+    p = fma.step(p, r, 1.0);
     return __builtin_ldexp(p, static_cast<int>(k));
 }
 }  // namespace bfi

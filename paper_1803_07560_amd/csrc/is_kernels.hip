@@ -439,10 +439,16 @@ __global__ void __launch_bounds__(BLOCK) is_kernel(IsArgs ia)
                 T u[D];
                 const T hz = gaussian_point<T, NX, NT>(first_index + local, id_lo, id_hi,
                                                        P.seed_lo, P.seed_hi, scale, uniform0, u);
-                bool inside = true;
+                // inside the cube: its smallest and largest coordinates
+                // (three-operand min/max; a short-circuit test per coordinate
+                // compiles to a chain of divergent branches)
+                T umin = u[0], umax = u[0];
 #pragma unroll
-                for (int j = 0; j < D; ++j)
-                    inside = inside && lo <= u[j] && u[j] <= hi;
+                for (int j = 1; j < D; ++j) {
+                    umin = fmin(umin, u[j]);
+                    umax = fmax(umax, u[j]);
+                }
+                const bool inside = lo <= umin && umax <= hi;
                 accumulate(u, hz, inside);
             }
         }

@@ -101,7 +101,18 @@ __global__ void __launch_bounds__(BLOCK)
     constexpr bool kHalfPair = AVG && NX % 2 == 0 && NX > 1;
     const T inv_sites = T(1) / T(D);
     // register class of the exponential's polynomial coefficients (FP64 weights)
-    using ExpFma = std::conditional_t<(D > 32), dev::FmaSgprCoef, dev::FmaVgprCoef>;
+    using ExpFma = std::conditional_t<
+        (D > 32 || PREC == kFP32Shifted), dev::FmaSgprCoef,
+        std::conditional_t<PAIR, dev::FmaVgprConst, dev::FmaVgprCoef>>;
+    const ExpFma efma;
+    // j * kPhiloxMulA for the blocks j >= 1 of a sample (see block_same_hi)
+    constexpr bool kFoldCounter = D <= 32 && !PAIR && !SPLIT;
+    uint64_t blk_add[kFoldCounter ? NB : 1];
+#pragma unroll
+    for (int j = 1; j < (kFoldCounter ? NB : 1); ++j) {
+        blk_add[j] = static_cast<uint64_t>(j) * dev::kPhiloxMulA;
+        asm volatile("" : "+v"(blk_add[j]));
+    }
     static_assert(!SPLIT || D <= 32, "split statistics keep one bit per dimension in 32 bits");
     static_assert(!PAIR || (!SPLIT && D <= kMaxPairD), "antithetic pairs: d <= 32, no split");
 
@@ -140,8 +151,15 @@ __global__ void __launch_bounds__(BLOCK)
         // block: keep them in scalar registers
         const WorkItem wi = dev::load_uniform(a.items + it);
         const EvalParams P = dev::load_uniform(wi.params);
-        const dev::Coef<T> coef(P.coef);
-        const bool mass = P.coef.half_m2 != 0.0;
+        dev::Coef<T> coef(P.coef);
+        // each site's fma(c_adv, difference, k_diag) may read one scalar
+        // operand: keep k_diag in a vector register for the whole item rather
+        // than copying it there once per sample
+        if constexpr (D <= 32 && !PAIR)
+            asm volatile("" : "+v"(coef.k_diag));
+        // the mass term is chosen once per item (a uniform branch around the
+        // sample loop), not per sample
+        const bool has_mass = P.coef.half_m2 != 0.0;
         const uint32_t seed_lo = P.seed_lo, seed_hi = P.seed_hi;
         const uint32_t s = wi.sub;
         const uint64_t id = P.ids[s];
@@ -211,9 +229,23 @@ __global__ void __launch_bounds__(BLOCK)
         const dev::PhiloxItem pitem = dev::philox_item(static_cast<uint32_t>(q_first >> 32),
                                                        id_lo, id_hi, seed_lo, seed_hi);
         const uint32_t q_first_lo = static_cast<uint32_t>(q_first);
+        // a sample's block j on the one-upper-word path: its counter's add
+        // folded into the first multiply (addends j A held in VGPR pairs) where
+        // registers allow (d <= 32, one configuration per thread, no split)
+        auto block_same_hi = [&](uint32_t lo, int j, uint32_t out[4]) {
+            if constexpr (kFoldCounter) {
+                if (j == 0)
+                    dev::philox_block_item(lo, pitem, out);
+                else
+                    dev::philox_block_item_at(lo, blk_add[j], pitem, out);
+            } else {
+                dev::philox_block_item(lo + static_cast<uint32_t>(j), pitem, out);
+            }
+        };
 
-        auto samples = [&](auto same_hi_tag) {
+        auto samples = [&](auto same_hi_tag, auto mass_tag) {
         constexpr bool kSameHi = decltype(same_hi_tag)::value;
+        const bool mass = static_cast<bool>(mass_tag);
         for (uint32_t k = 0; k < a.samples_per_thread; ++k) {
             const uint32_t local = k * BLOCK + tid;
             if (local >= wi.count)
@@ -236,8 +268,7 @@ __global__ void __launch_bounds__(BLOCK)
                         const int kk = l * NX + m;
                         if ((kk & 3) == 0) {
                             if constexpr (kSameHi)
-                                dev::philox_block_item(q0_lo + static_cast<uint32_t>(kk >> 2),
-                                                       pitem, wb);
+                                block_same_hi(q0_lo, kk >> 2, wb);
                             else
                                 dev::philox_block(q0 + (kk >> 2), id_lo, id_hi, seed_lo,
                                                   seed_hi, wb);
@@ -288,11 +319,11 @@ __global__ void __launch_bounds__(BLOCK)
                             rescale(exp(smin - sigma));
                             sigma = smin;
                         }
-                        wa = exp_weight<ExpFma>(sigma - sa);
-                        wbt = exp_weight<ExpFma>(sigma - sb);
+                        wa = exp_weight<ExpFma>(sigma - sa, efma);
+                        wbt = exp_weight<ExpFma>(sigma - sb, efma);
                     } else {
-                        wa = exp_weight<ExpFma>(-sa);
-                        wbt = exp_weight<ExpFma>(-sb);
+                        wa = exp_weight<ExpFma>(-sa, efma);
+                        wbt = exp_weight<ExpFma>(-sb, efma);
                     }
                     w = 0.5 * (wa + wbt);
                     const double ta = psa * wa, tb = psb * wbt;
@@ -351,8 +382,7 @@ __global__ void __launch_bounds__(BLOCK)
                     const int kk = l * NX + m;
                     if ((kk & 3) == 0) {
                         if constexpr (kSameHi)
-                            dev::philox_block_item(qs_lo + static_cast<uint32_t>(kk >> 2), pitem,
-                                                   blk);
+                            block_same_hi(qs_lo, kk >> 2, blk);
                         else
                             dev::philox_block(qs + (kk >> 2), id_lo, id_hi, seed_lo, seed_hi,
                                               blk);
@@ -444,9 +474,9 @@ __global__ void __launch_bounds__(BLOCK)
                         rescale(exp(S - sigma));
                         sigma = S;
                     }
-                    w = exp_weight<ExpFma>(sigma - S);
+                    w = exp_weight<ExpFma>(sigma - S, efma);
                 } else {
-                    w = exp_weight<ExpFma>(-S);
+                    w = exp_weight<ExpFma>(-S, efma);
                 }
                 const double t = pr_scale * w;
 #pragma unroll
@@ -487,10 +517,22 @@ __global__ void __launch_bounds__(BLOCK)
             }
         }
         };
+        // (pairs and lattices of more than 32 sites keep the run-time flag:
+        // duplicated sample loops raised their register pressure)
+        auto samples_mass = [&](auto same_hi_tag) {
+            if constexpr (PAIR || D > 32) {
+                samples(same_hi_tag, has_mass);
+            } else {
+                if (has_mass)
+                    samples(same_hi_tag, std::true_type{});
+                else
+                    samples(same_hi_tag, std::false_type{});
+            }
+        };
         if (same_hi)
-            samples(std::true_type{});
+            samples_mass(std::true_type{});
         else
-            samples(std::false_type{});
+            samples_mass(std::false_type{});
 
         // ---- reduction: wavefront butterflies, then waves in order through LDS
         Sig wave_sigma = Sig(0);

@@ -96,7 +96,8 @@ __global__ void __launch_bounds__(BLOCK) sph_kernel(SphArgs sa)
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     const T box = PREC == kFP64 ? static_cast<T>(sa.box64) : static_cast<T>(sa.box32);
     const T inv_sites = T(1) / T(D);
-    using ExpFma = dev::FmaVgprCoef;
+    using ExpFma = std::conditional_t<PREC == kFP32Shifted, dev::FmaSgprCoef, dev::FmaVgprCoef>;
+    const ExpFma efma;
 
     uint32_t it;
     if (a.queue_head) {
@@ -144,10 +145,14 @@ __global__ void __launch_bounds__(BLOCK) sph_kernel(SphArgs sa)
             T u[D];
             shell_point<T, D>(first_index + local, id_lo, id_hi, P.seed_lo, P.seed_hi, rho_hi, t,
                               u);
-            bool inside = true;
+            // inside the cube: the largest |u_j| (three-operand max; a
+            // short-circuit test per coordinate compiles to a chain of
+            // divergent branches)
+            T umax = fabs(u[0]);
 #pragma unroll
-            for (int j = 0; j < D; ++j)
-                inside = inside && fabs(u[j]) <= box;
+            for (int j = 1; j < D; ++j)
+                umax = fmax(umax, fabs(u[j]));
+            const bool inside = umax <= box;
             auto gen = [&](int l, T(&out)[NX], T) {
 #pragma unroll
                 for (int m = 0; m < NX; ++m)
@@ -178,7 +183,7 @@ __global__ void __launch_bounds__(BLOCK) sph_kernel(SphArgs sa)
             }
             double w;
             if constexpr (PREC == kFP64) {
-                w = inside ? exp_weight<ExpFma>(-S) : 0.0;
+                w = inside ? exp_weight<ExpFma>(-S, efma) : 0.0;
                 const double tw = pr_scale * w;
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
