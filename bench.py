@@ -324,17 +324,19 @@ def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0), observables=("ancho
     return out
 
 
-def adaptive_scale_leg(bfi, ctx, budget_log2=39, n_max_log2=18, round_log2=34):
+def adaptive_scale_leg(bfi, ctx, budget_log2=39, n_max_log2=18, round_log2=34,
+                       split_samples_log2=16):
     """A large adaptive 10x2 run (FP32 form, averaged observable, box [-4,4]^20):
     from 1024 leaves at 2^10 samples, leaves capped at 2^n_max_log2 samples so
-    refinement splits, rounds of 2^round_log2 evaluations, to a budget of
+    refinement splits, rounds of 2^round_log2 evaluations, the split statistics
+    over each leaf's first 2^split_samples_log2 samples, to a budget of
     2^budget_log2 -- over a million leaves.  Reports the whole run's rate and
     the device's share of its wall time (events around each replay of the
     captured round sequence)."""
     cfg = bfi.adaptive_config(target_rel_err=1e-9, max_evals=1 << budget_log2, n_min=1 << 10,
                               n_max=1 << n_max_log2, split_log2=10, max_rounds=1000,
                               refine_fraction=0.5, round_evals=1 << round_log2,
-                              split_samples=1 << 16)
+                              split_samples=1 << split_samples_log2)
     t0 = time.perf_counter()
     r = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(10, 2, observable="averaged"), "fp32", 1,
                                    -4.0, 4.0, cfg, leaf_capacity=1)
@@ -342,7 +344,7 @@ def adaptive_scale_leg(bfi, ctx, budget_log2=39, n_max_log2=18, round_log2=34):
     print(f"bench: adaptive scale run: {r['leaves']} leaves, {r['evals']:.3g} evals in {dt:.2f} s "
           f"(device {r['device_seconds']:.2f} s)", file=sys.stderr, flush=True)
     return {"budget": 1 << budget_log2, "n_max": 1 << n_max_log2, "round_evals": 1 << round_log2,
-            "rounds": r["rounds"], "leaves": r["leaves"], "evals": r["evals"], "seconds": dt,
+            "split_samples": 1 << split_samples_log2, "rounds": r["rounds"], "leaves": r["leaves"], "evals": r["evals"], "seconds": dt,
             "evals_per_s": r["evals"] / dt, "device_seconds": r["device_seconds"],
             "device_evals_per_s": r["evals"] / r["device_seconds"],
             "wall_over_device": dt / r["device_seconds"],
