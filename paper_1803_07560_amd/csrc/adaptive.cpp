@@ -73,8 +73,11 @@ bfi_status analyse(int nx, int d, size_t count, const double *lo, const double *
         e.resize(count);
     BFI_TRY(finalize_records(nx, d, count, lo, hi, partials, res, 1, e.data(), vol));
     out->resize(count);
-    for (size_t s = 0; s < count; ++s)
-        (*out)[s] = LeafAnalysis{e[s] >= 0.0 ? e[s] : 0.0, 0, 1.0};  // NaN ranks last
+    const double *ev = e.data();
+    LeafAnalysis *ov = out->data();
+    parallel_range(count, size_t(1) << 16, [ev, ov](size_t s) {
+        ov[s] = LeafAnalysis{ev[s] >= 0.0 ? ev[s] : 0.0, 0, 1.0};  // NaN ranks last
+    });
     return BFI_OK;
 }
 
@@ -259,6 +262,9 @@ size_t decide(std::vector<LeafAnalysis> &an, const SplitStats &st, const uint64_
     const size_t count = an.size();
     const double total = order.total();
     parallel_range(count, size_t(1) << 18, [&](size_t s) { action[s] = -1; });
+    // the ranks taken (in order, until their contributions reach the fraction);
+    // reading them gathers them into the ranking, so the per-leaf decisions
+    // below only read it and run in parallel
     double taken = 0.0;
     size_t i = 0;
     for (; i < count; ++i) {
@@ -268,8 +274,11 @@ size_t decide(std::vector<LeafAnalysis> &an, const SplitStats &st, const uint64_
         if (an[s].e <= 0.0 && i > 0)
             break;
         taken += an[s].e;
-        action[s] = leaf_action(an, st, s, ids[s], n[s], cfg);
     }
+    parallel_range(i, size_t(1) << 10, [&](size_t k) {
+        const size_t s = order[k];
+        action[s] = leaf_action(an, st, s, ids[s], n[s], cfg);
+    });
     return i;
 }
 
@@ -465,19 +474,32 @@ bfi_status eval_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, cons
         if (opos[w] >= 0)
             ev->without.set(static_cast<size_t>(opos[w]), work.id[w], cut[w], end - cut[w], lo, hi);
     });
+    // both replays prepared, then queued back to back: the plain pass runs while
+    // the host takes the split pass's records
+    {
+        TraceRange tr("adaptive: prepare and launch");
+        if (nw > 0)
+            BFI_TRY(ev->with.prepare(seed));
+        if (no > 0)
+            BFI_TRY(ev->without.prepare(seed));
+        if (nw > 0)
+            BFI_TRY(ev->with.launch());
+        if (no > 0)
+            BFI_TRY(ev->without.launch());
+    }
     if (nw > 0) {
         TraceRange tr("adaptive: samples with split statistics");
         ev->r_with.resize(static_cast<size_t>(nw) * rec_len);
         ev->sp_with.resize(static_cast<size_t>(nw) * split_len);
         double ms = 0.0;
-        BFI_TRY(ev->with.run(seed, ev->r_with.data(), ev->sp_with.data(), &ms));
+        BFI_TRY(ev->with.finish(ev->r_with.data(), ev->sp_with.data(), &ms));
         ev->device_ms += ms;
     }
     if (no > 0) {
         TraceRange tr("adaptive: samples through the plain kernel");
         ev->r_without.resize(static_cast<size_t>(no) * rec_len);
         double ms = 0.0;
-        BFI_TRY(ev->without.run(seed, ev->r_without.data(), nullptr, &ms));
+        BFI_TRY(ev->without.finish(ev->r_without.data(), nullptr, &ms));
         ev->device_ms += ms;
     }
     std::vector<int> first, second;
@@ -695,6 +717,27 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             // them all, refine further leaves in variance order (each at the current
             // factor; the next pass doubles again if one of them can still grow)
             size_t next_leaf = 0;
+            // the decisions of the next candidates in rank order, computed a batch
+            // at a time in parallel (each depends on its own leaf only) and taken
+            // up one by one below; ranks [pre_lo, pre_lo + pre.size())
+            std::vector<int32_t> pre;
+            size_t pre_lo = 0;
+            auto decision = [&](size_t rank) {
+                if (rank < pre_lo || rank >= pre_lo + pre.size()) {
+                    const size_t len = std::min(order.size() - rank,
+                                                std::max<size_t>(4096, 2 * pre.size()));
+                    for (size_t k = 0; k < len; ++k)
+                        (void)order[rank + k];  // gather the ranks first (serial)
+                    pre.assign(len, -1);
+                    pre_lo = rank;
+                    parallel_range(len, size_t(1) << 9, [&](size_t k) {
+                        const size_t s = order[rank + k];
+                        if (action[s] == -1)
+                            pre[k] = leaf_action(an, st, s, L.id[s], L.n[s], *cfg);
+                    });
+                }
+                return pre[rank - pre_lo];
+            };
             while (cfg->round_evals > 0 && planned < cfg->round_evals) {
                 if (growable > 0) {
                     f *= 2;
@@ -706,7 +749,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                 if (next_leaf == order.size())
                     break;
                 const size_t s = order[next_leaf];
-                action[s] = leaf_action(an, st, s, L.id[s], L.n[s], *cfg);
+                action[s] = decision(next_leaf);
                 if (action[s] < 0) {
                     action[s] = -2;  // neither split nor doubling possible: skip it
                     continue;

@@ -65,11 +65,15 @@ ResidentEval::~ResidentEval() { release(); }
 
 void ResidentEval::release()
 {
+    // a replay may still be queued (an error between launch and finish): let it
+    // end before its graph and buffers go
+    if (ctx_)
+        (void)hipStreamSynchronize(ctx_->stream);
     if (exec_)
         (void)hipGraphExecDestroy(exec_);
     exec_ = nullptr;
-    if (ctx_)
-        (void)hipStreamSynchronize(ctx_->stream);
+    prepared_ = 0;
+    launched_ = false;
     void *dev[] = {d_id_, d_n_, d_off_, d_lo_, d_hi_, d_base64_, d_scale64_, d_base32_, d_scale32_,
                    d_params_, d_sub_first_, d_items_, d_item_rec_, d_item_split_, d_sub_rec_,
                    d_sub_split_, d_head_};
@@ -174,8 +178,14 @@ bfi_status ResidentEval::push(uint64_t id, uint64_t offset, uint64_t n, const do
 
 bfi_status ResidentEval::run(uint64_t seed, double *rec_out, double *split_out, double *device_ms)
 {
-    if (device_ms)
-        *device_ms = 0.0;
+    BFI_TRY(prepare(seed));
+    BFI_TRY(launch());
+    return finish(rec_out, split_out, device_ms);
+}
+
+bfi_status ResidentEval::prepare(uint64_t seed)
+{
+    prepared_ = 0;
     const size_t nsub = count_;
     if (nsub == 0)
         return BFI_OK;
@@ -250,10 +260,36 @@ bfi_status ResidentEval::run(uint64_t seed, double *rec_out, double *split_out, 
         BFI_HIP(hipEventCreate(&ev_start_));
         BFI_HIP(hipEventCreate(&ev_stop_));
     }
+    prepared_ = nsub;
+    return BFI_OK;
+}
+
+bfi_status ResidentEval::launch()
+{
+    if (prepared_ == 0)
+        return BFI_OK;
+    hipStream_t st = ctx_->stream;
     BFI_HIP(hipEventRecord(ev_start_, st));
     BFI_HIP(hipGraphLaunch(exec_, st));
     BFI_HIP(hipEventRecord(ev_stop_, st));
-    BFI_HIP(hipStreamSynchronize(st));
+    launched_ = true;
+    return BFI_OK;
+}
+
+bfi_status ResidentEval::finish(double *rec_out, double *split_out, double *device_ms)
+{
+    if (device_ms)
+        *device_ms = 0.0;
+    const size_t nsub = prepared_;
+    if (nsub == 0) {
+        count_ = 0;
+        return BFI_OK;
+    }
+    if (!launched_)
+        return fail(BFI_EINVAL, "finish before launch");
+    launched_ = false;
+    prepared_ = 0;
+    BFI_HIP(hipEventSynchronize(ev_stop_));
     if (device_ms) {
         float ms = 0.0f;
         BFI_HIP(hipEventElapsedTime(&ms, ev_start_, ev_stop_));

@@ -226,6 +226,14 @@ public:
     // BFI_PARTIAL_LEN(nx) records, split_out count x BFI_SPLIT_LEN(d) (split
     // only); device_ms the replay's duration from events around it
     bfi_status run(uint64_t seed, double *rec_out, double *split_out, double *device_ms);
+    // the same in three steps, so that several evaluators' replays can be queued
+    // back to back on the context's stream (all prepared before any launch: a
+    // capture never begins while one of them is in flight) and the host reads
+    // one's records while the next runs: prepare captures (or updates) the
+    // replay, launch queues it, finish waits for it and copies the records out
+    bfi_status prepare(uint64_t seed);
+    bfi_status launch();
+    bfi_status finish(double *rec_out, double *split_out, double *device_ms);
     int instantiations() const { return instantiations_; }
     int updates() const { return updates_; }
 
@@ -259,6 +267,8 @@ private:
     hipGraphExec_t exec_ = nullptr;
     hipEvent_t ev_start_ = nullptr, ev_stop_ = nullptr;
     int instantiations_ = 0, updates_ = 0;
+    size_t prepared_ = 0;   // entries of the replay prepared and not yet finished
+    bool launched_ = false;
 };
 
 // Take the device address of the allocation-free entry point's scratch array on

@@ -197,6 +197,29 @@ def test_counter_upper_word_boundaries(bfi, ctx, nx, nt, obs):
                            oracle.finalize(nx, d, sv.lo, sv.hi, want), 1e-4, lat_o, sv, 11)
 
 
+@pytest.mark.parametrize("nx,nt,obs", [(4, 2, 0), (10, 2, 0), (10, 2, 1), (3, 1, 0), (16, 4, 0)])
+def test_mass_term_records_match_oracle(bfi, ctx, nx, nt, obs):
+    """The action's mass term (m2 > 0) through the Monte Carlo kernel, whose
+    sample loop is compiled with and without the term and chosen once per work
+    item (d <= 32; larger lattices keep a run-time flag): records against the
+    oracle in both forms, with m2 = 0 in the same sequence of calls."""
+    d = nx * nt
+    sv = workloads.random_partition(d, 2.0, 6, per_sub=1, seed=d + obs)
+    sv.n[:] = [2, 999, 64 * 16 + 3, 20_000, 5, 4096]
+    sv.offset[:] = [0, 7, 2**20, 0, 3, 2**33]
+    for m2 in (0.8, 0.0):
+        params = dict(nu=0.6, m2=m2, observable=obs)
+        print(f"mass term: {nx}x{nt} observable {obs} m2 {m2}", flush=True)
+        lat_o = oracle.lattice(nx, nt, **params)
+        want = oracle.sums(lat_o, 5, sv.ids, sv.lo, sv.hi, sv.n, sv.offset)
+        lat = bfi.lattice(nx, nt, **params)
+        got = bfi.bfi_eval(ctx, lat, F64, 5, sv, bfi.launch(16, 64, 1))
+        assert_sums_close(unshift(got, nx), want, nx, 1e-10)
+        got32 = bfi.bfi_eval(ctx, lat, F32, 5, sv, bfi.launch(16, 64, 1))
+        assert_result_close_l1(bfi.bfi_finalize(lat, sv, got32),
+                               oracle.finalize(nx, d, sv.lo, sv.hi, want), 1e-4, lat_o, sv, 5)
+
+
 @pytest.mark.parametrize("launch", [
     dict(samples_per_thread=1, block=64, persistent=0),
     dict(samples_per_thread=7, block=128, persistent=0),
