@@ -47,7 +47,8 @@ PEAK_SLOTS = 256 * 64 * 2.4e9   # FP64-rate lane slots per second (= FP64 FMA/s)
 PEAK_FP64 = 78.6e12
 
 
-def valu_slots_per_eval(nx: int, nt: int, prec: str, observable: str = "anchor") -> float:
+def valu_slots_per_eval(nx: int, nt: int, prec: str, observable: str = "anchor",
+                        pairs: bool = False) -> float:
     """FP64-rate lane slots one evaluation needs (algorithmic instruction counts):
       Philox4x32-10: per block 10 rounds x (2 wide 32x32 multiplies + 2 xor3)
       point map:     per variable one u32->float conversion and one fma
@@ -57,22 +58,33 @@ def valu_slots_per_eval(nx: int, nt: int, prec: str, observable: str = "anchor")
                      FP32 form: the product in FP32, then one widening per r
       averaged observable: r = 0 .. nx/2 only; p_r = sum over the sites and time
                      slices of u_m u_{m+r} (one fma per term, the pair at r = nx/2
-                     counted once and doubled)"""
+                     counted once and doubled)
+      antithetic pairs: one Philox evaluation per pair of points; per pair the
+                     two weights averaged, t = p_0 w for each point, per r the
+                     mean of the two products (product, fma, halving) and its
+                     three sums: FP64 3 + 3 nr per evaluation (FP32 form: the
+                     combination in FP32, one widening per r, 2.5 + 2.75 nr)"""
     d, nb = nx * nt, (nx * nt + 3) // 4
     avg = observable == "averaged"
     nr = nx // 2 + 1 if avg else nx
     f = SLOT["f64"] if prec == "fp64" else SLOT["f32"]
     philox = nb * 10 * (2 * SLOT["mul32"] + 2 * SLOT["logic32"])
+    if pairs:
+        philox /= 2
     if prec == "fp64":
         mapping = d * (SLOT["cvt"] + SLOT["f64"])
         action = (6 * d + 1) * SLOT["f64"]
         weight = EXP64_OPS * SLOT["f64"]
-        sums = (3 + 4 * nr) * SLOT["f64"]
+        sums = ((3 + 3 * nr) if pairs else (3 + 4 * nr)) * SLOT["f64"]
     else:
         mapping = d * (SLOT["cvt"] * 0.5 + SLOT["f32"])   # u32->f32 is a 32-bit op
         action = (6 * d + 1) * SLOT["f32"]
         weight = SLOT["f32"] + SLOT["trans"] + SLOT["cvt"] + SLOT["f32"]  # (sigma-S)*log2e, exp2, widen, compare
-        sums = (2 + 3 * nr) * SLOT["f64"] + nr * (SLOT["f32"] + SLOT["cvt"]) + SLOT["f32"]
+        if pairs:
+            sums = (1 + 1.5 * nr) * SLOT["f64"] + nr * (0.75 * SLOT["f32"] + 0.5 * SLOT["cvt"]) \
+                + 1.5 * SLOT["f32"]
+        else:
+            sums = (2 + 3 * nr) * SLOT["f64"] + nr * (SLOT["f32"] + SLOT["cvt"]) + SLOT["f32"]
     observable_terms = 0.0
     if avg:
         half = nx % 2 == 0 and nx > 1
@@ -81,11 +93,15 @@ def valu_slots_per_eval(nx: int, nt: int, prec: str, observable: str = "anchor")
     return philox + mapping + action + weight + sums + observable_terms
 
 
-def fp64_flops_per_eval(nx: int, nt: int) -> float:
+def fp64_flops_per_eval(nx: int, nt: int, pairs: bool = False) -> float:
     """FP64 floating-point operations (FMA = 2) of one FP64-form evaluation:
-    map 2d, action 10 per site + 1, exp ~30, sums 2 + 1 + 7 per r (+ w^2 fma)."""
+    map 2d, action 10 per site + 1, exp ~30, sums 2 + 1 + 7 per r (+ w^2 fma);
+    antithetic pairs: per pair the weights averaged (2), t of each point (2),
+    per r the halved mean of the products (4) and its sums (5), and w, w^2 (3),
+    i.e. 3.5 + 4.5 nx per evaluation."""
     d = nx * nt
-    return 2 * d + 10 * d + 1 + 30 + (1 + 2) + 1 + 7 * nx
+    sums = (3.5 + 4.5 * nx) if pairs else (1 + 2) + 1 + 7 * nx
+    return 2 * d + 10 * d + 1 + 30 + sums
 
 
 def parse():
@@ -416,8 +432,16 @@ def antithetic_leg(bfi, torch, ctx, w, sv, steps, warmup, stream, accuracy_log2=
     for prec in ("fp64", "fp32"):
         print(f"bench: antithetic pairs {prec}", file=sys.stderr, flush=True)
         f = run_form(bfi, torch, ctx, lat, half, w, prec, steps, warmup, stream)
+        rate = f["evals_per_step"] / (f["kernel_ms"] * 1e-3)
+        slots = valu_slots_per_eval(w.nx, w.nt, prec, pairs=True)
         forms[prec] = {"evals_per_s": f["evals_per_s"], "ms_per_step": f["ms_per_step"],
-                       "kernel_ms": f["kernel_ms"], "evals_per_step": f["evals_per_step"]}
+                       "kernel_ms": f["kernel_ms"], "kernel_ms_median": f["kernel_ms_median"],
+                       "evals_per_step": f["evals_per_step"], "slots_per_eval": slots,
+                       "valu_frac": slots * rate / PEAK_SLOTS}
+        if prec == "fp64":
+            flops = fp64_flops_per_eval(w.nx, w.nt, pairs=True)
+            forms[prec]["fp64_flops_per_eval"] = flops
+            forms[prec]["fp64_flop_frac"] = flops * rate / PEAK_FP64
     boxes = []
     for B, k in ((1.0, 6), (w.box, w.split_log2)):
         est = {}
