@@ -72,6 +72,43 @@ U32_PROBE(k_bitop3, "v_bitop3_b32 %0, %0, %1, %2 bitop3:0x96")
 U32_PROBE(k_add_u32, "v_add_u32 %0, %0, %1")
 FP_PROBE(k_fma64, double, "v_fma_f64 %0, %0, %1, %2")
 FP_PROBE(k_add64, double, "v_add_f64 %0, %0, %2")
+// operand forms of the FP64 fma: accumulator as the addend, the two-address
+// v_fmac_f64, a square, an inline-constant addend, the chain as the second
+// multiplicand; and the multiply
+FP_PROBE(k_fma64_acc, double, "v_fma_f64 %0, %1, %2, %0")
+FP_PROBE(k_fmac64, double, "v_fmac_f64 %0, %1, %2")
+FP_PROBE(k_fma64_sq, double, "v_fma_f64 %0, %0, %0, %1")
+FP_PROBE(k_fma64_k, double, "v_fma_f64 %0, %0, %1, 1.0")
+FP_PROBE(k_mul64, double, "v_mul_f64 %0, %0, %1")
+FP_PROBE(k_fma64_src1, double, "v_fma_f64 %0, %1, %0, %2")
+
+// A Horner step p = p r + c_j with the coefficient c_j changing every step
+// (twelve coefficients in registers), the chain value as the first or the
+// second multiplicand.
+#define HORNER_PROBE(NAME, ASM)                                                     \
+    __global__ void NAME(uint32_t *out, uint32_t s)                                 \
+    {                                                                               \
+        double v[kChains];                                                          \
+        for (int i = 0; i < kChains; ++i)                                           \
+            v[i] = 0.25 + static_cast<double>(threadIdx.x + i) * 1e-3;              \
+        const double r = 0.3 + 1e-9 * s;                                            \
+        double c[12];                                                               \
+        for (int j = 0; j < 12; ++j) {                                              \
+            c[j] = 1.0 / (j + 2 + s);                                               \
+            asm volatile("" : "+v"(c[j]));                                          \
+        }                                                                           \
+        for (int it = 0; it < kIters / 12; ++it) {                                  \
+            _Pragma("unroll") for (int j = 0; j < 12; ++j)                          \
+                _Pragma("unroll") for (int ch = 0; ch < kChains; ++ch)              \
+                    asm volatile(ASM : "+v"(v[ch]) : "v"(r), "v"(c[j]));           \
+        }                                                                           \
+        double t = 0;                                                               \
+        for (int i = 0; i < kChains; ++i)                                           \
+            t += v[i];                                                              \
+        out[blockIdx.x * blockDim.x + threadIdx.x] = static_cast<uint32_t>(t * 1e3); \
+    }
+HORNER_PROBE(k_horner_src0, "v_fma_f64 %0, %0, %1, %2")
+HORNER_PROBE(k_horner_src1, "v_fma_f64 %0, %1, %0, %2")
 FP_PROBE(k_fma32, float, "v_fma_f32 %0, %0, %1, %2")
 FP_PROBE(k_add32, float, "v_add_f32 %0, %0, %2")
 FP_PROBE(k_exp32, float, "v_exp_f32 %0, %0")
@@ -165,6 +202,12 @@ int main(int argc, char **argv)
     CHECK(hipMalloc(&out, sizeof(uint32_t) * block * blocks));
     const Entry probes[] = {
         {"v_fma_f64", k_fma64, 1},         {"v_add_f64", k_add64, 1},
+        {"v_fma_f64 (acc addend)", k_fma64_acc, 1}, {"v_fmac_f64", k_fmac64, 1},
+        {"v_fma_f64 (square)", k_fma64_sq, 1},
+        {"v_fma_f64 (const addend)", k_fma64_k, 1}, {"v_mul_f64", k_mul64, 1},
+        {"v_fma_f64 (chain in src1)", k_fma64_src1, 1},
+        {"Horner, chain in src0", k_horner_src0, 12.0 * (kIters / 12) / kIters},
+        {"Horner, chain in src1", k_horner_src1, 12.0 * (kIters / 12) / kIters},
         {"v_fma_f32", k_fma32, 1},         {"v_add_f32", k_add32, 1},
         {"v_mad_u64_u32", k_mad64, 1},     {"v_mul_lo_u32", k_mul_lo, 1},
         {"v_mul_hi_u32", k_mul_hi, 1},     {"v_xor_b32", k_xor, 1},
@@ -185,7 +228,7 @@ int main(int argc, char **argv)
             hipLaunchKernelGGL(p.fn, dim3(blocks), dim3(block), 0, 0, out, 3u);
     CHECK(hipGetLastError());
     CHECK(hipDeviceSynchronize());
-    std::printf("%-20s %12s %10s\n", "instruction", "Tops/s", "per CU-cycle");
+    std::printf("%-26s %12s %10s\n", "instruction", "Tops/s", "per CU-cycle");
     for (const Entry &p : probes) {
         hipLaunchKernelGGL(p.fn, dim3(blocks), dim3(block), 0, 0, out, 3u);
         CHECK(hipGetLastError());
@@ -201,7 +244,7 @@ int main(int argc, char **argv)
         const double ops = static_cast<double>(repeats) * blocks * block * kIters * kChains *
                            p.ops_per_iter;
         const double rate = ops / (ms * 1e-3);
-        std::printf("%-20s %12.3f %10.3f\n", p.name, rate / 1e12, rate / peak);
+        std::printf("%-26s %12.3f %10.3f\n", p.name, rate / 1e12, rate / peak);
     }
     CHECK(hipFree(out));
     return 0;
