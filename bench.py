@@ -16,6 +16,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload burgers10
 from __future__ import annotations
 
 import argparse
+import gc
 import itertools
 import json
 import math
@@ -189,9 +190,18 @@ def run_form(bfi, torch, ctx, lat, sv, w, prec, steps, warmup, stream):
             copied[b].synchronize()
             return bfi.bfi_finalize(lat, sv, host[b].numpy())
 
-        for i in range(warmup):
-            launch(i, False)
-            finish(i)
+        # collector paused from here to the end of the timed steps (a collection
+        # before the timed loop would idle the GPU and let its clock drop)
+        gc.collect()
+        gc.disable()
+        # warm-up in the timed loop's pattern (a copy overlapping the next
+        # launch, which the first time stalled that launch by ~6 ms)
+        if warmup > 0:
+            launch(0, False)
+            for i in range(1, warmup):
+                launch(i, False)
+                finish(i - 1)
+            finish(warmup - 1)
         torch.cuda.synchronize()
         step_end = []
         t0 = time.perf_counter()
@@ -207,6 +217,7 @@ def run_form(bfi, torch, ctx, lat, sv, w, prec, steps, warmup, stream):
         kernel_ms = [a.elapsed_time(b) for a, b in ev]
         part = host[(steps - 1) % 2].numpy().copy()
     finally:
+        gc.enable()
         bfi.bfi_plan_destroy(plan)
     evals = info["n_evals"]
     step_ms = 1e3 * np.diff(np.concatenate([[t0], step_end]))
