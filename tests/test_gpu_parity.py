@@ -202,7 +202,7 @@ def test_mass_term_records_match_oracle(bfi, ctx, nx, nt, obs):
     """The action's mass term (m2 > 0) through the Monte Carlo kernel, whose
     sample loop is compiled with and without the term and chosen once per work
     item (d <= 32; larger lattices keep a run-time flag): records against the
-    oracle in both forms, with m2 = 0 in the same sequence of calls."""
+    oracle in the three forms, with m2 = 0 in the same sequence of calls."""
     d = nx * nt
     sv = workloads.random_partition(d, 2.0, 6, per_sub=1, seed=d + obs)
     sv.n[:] = [2, 999, 64 * 16 + 3, 20_000, 5, 4096]
@@ -215,6 +215,10 @@ def test_mass_term_records_match_oracle(bfi, ctx, nx, nt, obs):
         lat = bfi.lattice(nx, nt, **params)
         got = bfi.bfi_eval(ctx, lat, F64, 5, sv, bfi.launch(16, 64, 1))
         assert_sums_close(unshift(got, nx), want, nx, 1e-10)
+        # the shifted FP64 form (nothing underflows on this machine: its records
+        # moved back to sigma = 0 are the plain sums)
+        got64s = bfi.bfi_eval(ctx, lat, "fp64s", 5, sv, bfi.launch(16, 64, 1))
+        assert_sums_close(unshift(got64s, nx), want, nx, 1e-10)
         got32 = bfi.bfi_eval(ctx, lat, F32, 5, sv, bfi.launch(16, 64, 1))
         assert_result_close_l1(bfi.bfi_finalize(lat, sv, got32),
                                oracle.finalize(nx, d, sv.lo, sv.hi, want), 1e-4, lat_o, sv, 5)
