@@ -27,7 +27,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "inclu
 # that it does not know the feature, which is harmless
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops"]
-HOST_SOURCES = ["runtime.cpp", "tune.cpp", "adaptive.cpp", "server.cpp", "integrand.cpp",
+HOST_SOURCES = ["host_pool.cpp", "runtime.cpp", "tune.cpp", "adaptive.cpp", "server.cpp", "integrand.cpp",
                 "sampler.cpp", "resident.cpp", "spherical.cpp"]
 
 

@@ -153,13 +153,16 @@ public:
         const size_t n = an.size();
         nchunks_ = (n + kChunk - 1) / kChunk;
         part_.assign(nchunks_, {});
+        bucket_.resize(n);
         std::vector<double> sums(nchunks_, 0.0);
         for_chunks(nchunks_, [&](size_t c) {
             part_[c].assign(kBuckets, 0);
             const size_t i1 = std::min(n, (c + 1) * kChunk);
             double sum = 0.0;
             for (size_t s = c * kChunk; s < i1; ++s) {
-                ++part_[c][bucket(an[s].e)];
+                const uint16_t b = bucket(an[s].e);
+                bucket_[s] = b;
+                ++part_[c][b];
                 sum += an[s].e;
             }
             sums[c] = sum;
@@ -188,17 +191,17 @@ public:
 
 private:
     static constexpr size_t kBuckets = size_t(1) << 15;  // sign bit 0: 15 top bits
-    static constexpr size_t kChunk = size_t(1) << 18;
+    static constexpr size_t kChunk = size_t(1) << 16;
     struct Key {
         double e;
         uint64_t id;
         size_t leaf;
     };
-    static size_t bucket(double e)
+    static uint16_t bucket(double e)
     {
         uint64_t bits;
         std::memcpy(&bits, &e, sizeof bits);
-        return static_cast<size_t>(bits >> 48);  // e >= 0 and not NaN (analyse)
+        return static_cast<uint16_t>(bits >> 48);  // e >= 0 and not NaN (analyse)
     }
     static bool before(const Key &x, const Key &y)
     {
@@ -231,7 +234,7 @@ private:
             }
             const size_t i1 = std::min(n, (c + 1) * kChunk);
             for (size_t s = c * kChunk; s < i1; ++s) {
-                const size_t b = bucket(an_[s].e);
+                const size_t b = bucket_[s];
                 if (b >= lo && b < hi)
                     keys_[at[hi - 1 - b]++] = Key{an_[s].e, ids_[s], s};
             }
@@ -247,6 +250,7 @@ private:
     const uint64_t *ids_;
     size_t nchunks_ = 0;
     std::vector<std::vector<uint32_t>> part_;  // per chunk: leaves per bucket
+    std::vector<uint16_t> bucket_;             // per leaf
     std::vector<uint32_t> hist_;
     std::vector<Key> keys_;
     double total_ = 0.0;
@@ -335,29 +339,6 @@ void record_fields(int nx, std::vector<int> *first, std::vector<int> *second)
     }
 }
 
-// An allocator whose default construction leaves elements uninitialized: the
-// leaf set and the round buffers write every element before reading it, so
-// growing them costs no fill.
-template <class T>
-struct NoInit : std::allocator<T> {
-    using std::allocator<T>::allocator;
-    template <class U>
-    struct rebind {
-        using other = NoInit<U>;
-    };
-    template <class U>
-    void construct(U *) noexcept
-    {
-    }
-    template <class U, class... A>
-    void construct(U *p, A &&...a)
-    {
-        ::new (static_cast<void *>(p)) U(std::forward<A>(a)...);
-    }
-};
-template <class T>
-using RawVec = std::vector<T, NoInit<T>>;
-
 // A growable array of trivially copyable elements on malloc/realloc: past the
 // allocator's mmap threshold, growth remaps pages instead of copying them, so a
 // leaf set of gigabytes grows without being copied; new elements are not
@@ -432,7 +413,6 @@ void merge_record(double *a, const double *b, int len, const std::vector<int> &f
 // kept from round to round; and the host buffers of their results.
 struct Evaluators {
     ResidentEval with, without;
-    RawVec<double> r_with, sp_with, r_without;
     // the round's work list results, kept between rounds so their pages are
     // mapped once (fresh buffers of this size would fault in every round)
     GrowArray<double> wrec, wsplit, wbase;
@@ -487,21 +467,21 @@ bfi_status eval_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, cons
         if (no > 0)
             BFI_TRY(ev->without.launch());
     }
+    // the records are read where the replays left them (pinned host memory)
     if (nw > 0) {
         TraceRange tr("adaptive: samples with split statistics");
-        ev->r_with.resize(static_cast<size_t>(nw) * rec_len);
-        ev->sp_with.resize(static_cast<size_t>(nw) * split_len);
         double ms = 0.0;
-        BFI_TRY(ev->with.finish(ev->r_with.data(), ev->sp_with.data(), &ms));
+        BFI_TRY(ev->with.finish(nullptr, nullptr, &ms));
         ev->device_ms += ms;
     }
     if (no > 0) {
         TraceRange tr("adaptive: samples through the plain kernel");
-        ev->r_without.resize(static_cast<size_t>(no) * rec_len);
         double ms = 0.0;
-        BFI_TRY(ev->without.finish(ev->r_without.data(), nullptr, &ms));
+        BFI_TRY(ev->without.finish(nullptr, nullptr, &ms));
         ev->device_ms += ms;
     }
+    const double *r_with = ev->with.records(), *sp_with = ev->with.split_records(),
+                 *r_without = ev->without.records();
     std::vector<int> first, second;
     record_fields(lat.nx, &first, &second);
     rec->resize(count * rec_len);
@@ -510,10 +490,10 @@ bfi_status eval_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, cons
     parallel_range(count, kGrain, [&](size_t w) {
         double *R = &(*rec)[w * rec_len], *B = &(*base)[w * rec_len], *P = &(*split)[w * split_len];
         if (wpos[w] >= 0) {
-            const double *r = &ev->r_with[static_cast<size_t>(wpos[w]) * rec_len];
+            const double *r = &r_with[static_cast<size_t>(wpos[w]) * rec_len];
             std::copy(r, r + rec_len, B);
             std::copy(r, r + rec_len, R);
-            const double *sp = &ev->sp_with[static_cast<size_t>(wpos[w]) * split_len];
+            const double *sp = &sp_with[static_cast<size_t>(wpos[w]) * split_len];
             std::copy(sp, sp + split_len, P);
         } else {
             std::fill(B, B + rec_len, 0.0);
@@ -521,7 +501,7 @@ bfi_status eval_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, cons
             std::fill(P, P + split_len, 0.0);
         }
         if (opos[w] >= 0)
-            merge_record(R, &ev->r_without[static_cast<size_t>(opos[w]) * rec_len], rec_len, first,
+            merge_record(R, &r_without[static_cast<size_t>(opos[w]) * rec_len], rec_len, first,
                          second);
     });
     return BFI_OK;
@@ -783,13 +763,30 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             // work list: children (fresh streams) and continuations, each refined
             // leaf's entries at a precomputed position, filled in parallel
             phase.next("adaptive: work list");
+            // entry offsets: counts per chunk of leaves, the chunks' starts in
+            // order, then each chunk's offsets from its start
             first_entry.resize(L.size());
-            size_t entries = 0;
-            for (size_t s = 0; s < L.size(); ++s) {
-                first_entry[s] = entries;
-                if (action[s] >= 0)
-                    entries += action[s] == 0 ? 1 : 2;
-            }
+            const size_t nfc = (L.size() + kGrain - 1) / kGrain;
+            std::vector<size_t> chunk_start(nfc + 1, 0);
+            auto entries_of = [&](size_t s) -> size_t {
+                return action[s] < 0 ? 0 : action[s] == 0 ? 1 : 2;
+            };
+            for_chunks(nfc, [&](size_t c) {
+                size_t k = 0;
+                for (size_t s = c * kGrain; s < std::min(L.size(), (c + 1) * kGrain); ++s)
+                    k += entries_of(s);
+                chunk_start[c + 1] = k;
+            });
+            for (size_t c = 0; c < nfc; ++c)
+                chunk_start[c + 1] += chunk_start[c];
+            const size_t entries = chunk_start[nfc];
+            for_chunks(nfc, [&](size_t c) {
+                size_t k = chunk_start[c];
+                for (size_t s = c * kGrain; s < std::min(L.size(), (c + 1) * kGrain); ++s) {
+                    first_entry[s] = k;
+                    k += entries_of(s);
+                }
+            });
             work.d = d;
             work.id.resize(entries);
             work.n.resize(entries);

@@ -14,6 +14,7 @@
 #include <sstream>
 #include <thread>
 
+
 namespace bfi {
 
 namespace {
@@ -341,19 +342,36 @@ bfi_status finalize_records(int nx, int d, size_t nsub, const double *lo, const 
     if (nsub == 0)
         return fail(BFI_EINVAL, "no subvolumes");
     const int rec_len = BFI_PARTIAL_LEN(nx);
-    // common shift: the smallest sigma of the subvolumes
+    const size_t nchunks = (nsub + kFinalizeChunk - 1) / kFinalizeChunk;
+    // common shift: the smallest sigma of the subvolumes; and the first
+    // subvolume with fewer than two samples, if any (per chunk, then in order)
+    struct Scan {
+        double sig;
+        size_t bad;
+    };
+    std::vector<Scan> scan(nchunks);
+    for_chunks(nchunks, [&](size_t c) {
+        Scan sc{std::numeric_limits<double>::infinity(), nsub};
+        const size_t s1 = std::min(nsub, (c + 1) * kFinalizeChunk);
+        for (size_t s = c * kFinalizeChunk; s < s1; ++s) {
+            sc.sig = std::min(sc.sig, partials[s * rec_len + 1]);
+            if (!(partials[s * rec_len] >= 2.0) && sc.bad == nsub)
+                sc.bad = s;
+        }
+        scan[c] = sc;
+    });
     double sig = std::numeric_limits<double>::infinity();
-    for (size_t s = 0; s < nsub; ++s) {
-        sig = std::min(sig, partials[s * rec_len + 1]);
-        if (!(partials[s * rec_len] >= 2.0))
-            return fail(BFI_EINVAL, "subvolume %zu has n = %g < 2", s, partials[s * rec_len]);
+    for (const Scan &sc : scan) {
+        if (sc.bad < nsub)
+            return fail(BFI_EINVAL, "subvolume %zu has n = %g < 2", sc.bad,
+                        partials[sc.bad * rec_len]);
+        sig = std::min(sig, sc.sig);
     }
     if (!std::isfinite(sig))
         return fail(BFI_EINVAL, "partial records carry no finite shift");
 
     // Two passes over the records, every distance r in the same pass; per-leaf
     // terms summed in fixed chunks of leaves, the chunk sums in chunk order.
-    const size_t nchunks = (nsub + kFinalizeChunk - 1) / kFinalizeChunk;
     // per-subvolume volumes and shift factors; the buffers stay with the thread,
     // so repeated finalizes of large lists (adaptive rounds) reuse their pages
     // (plain pointers below: the chunks run on worker threads, where the names

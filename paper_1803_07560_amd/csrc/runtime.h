@@ -14,11 +14,13 @@
 #include <string>
 #include <thread>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "bfi.h"
+#include "host_pool.h"
 #include "internal.h"
 #include "is_internal.h"
 #include "sph_internal.h"
@@ -133,46 +135,6 @@ struct TracePhases {
     TracePhases &operator=(const TracePhases &) = delete;
 };
 
-// Run body(chunk) for chunks 0 .. nchunks-1, on up to 16 host threads when
-// there are several (one GPU's share of the host); each chunk writes its own
-// outputs, so results do not depend on the number of threads.
-template <class F>
-void for_chunks(size_t nchunks, F &&body)
-{
-    const size_t hw = std::max<size_t>(1, std::thread::hardware_concurrency());
-    const size_t nthreads = std::min<size_t>({nchunks, hw, 16});
-    if (nthreads <= 1) {
-        for (size_t c = 0; c < nchunks; ++c)
-            body(c);
-        return;
-    }
-    std::atomic<size_t> next{0};
-    auto worker = [&]() {
-        for (size_t c = next++; c < nchunks; c = next++)
-            body(c);
-    };
-    std::vector<std::thread> pool;
-    pool.reserve(nthreads - 1);
-    for (size_t t = 1; t < nthreads; ++t)
-        pool.emplace_back(worker);
-    worker();
-    for (auto &th : pool)
-        th.join();
-}
-
-// Apply body(i) to i in [0, n) in parallel chunks of `grain` (serially when n
-// is below two grains).
-template <class F>
-void parallel_range(size_t n, size_t grain, F &&body)
-{
-    const size_t nchunks = (n + grain - 1) / grain;
-    for_chunks(nchunks, [&](size_t c) {
-        const size_t i1 = std::min(n, (c + 1) * grain);
-        for (size_t i = c * grain; i < i1; ++i)
-            body(i);
-    });
-}
-
 // Resolve a requested launch (zeros = tuned or default) for a lattice.
 bfi_launch resolve_launch(const bfi_context *ctx, const bfi_lattice &lat, int prec, bool split,
                           const bfi_launch *req);
@@ -234,6 +196,11 @@ public:
     bfi_status prepare(uint64_t seed);
     bfi_status launch();
     bfi_status finish(double *rec_out, double *split_out, double *device_ms);
+    // the last finished list's records and split statistics in the pinned
+    // buffers the replay copied them to (finish with NULL outputs skips the
+    // copy), valid until the next prepare
+    const double *records() const { return h_rec_; }
+    const double *split_records() const { return h_split_; }
     int instantiations() const { return instantiations_; }
     int updates() const { return updates_; }
 

@@ -32,6 +32,13 @@ namespace {
 // squares and their sums far from overflow) and rescales are rare.
 constexpr float kShiftGap = 64.0f;
 constexpr float kLog2e = 1.44269504088896340736f;
+// Split statistics in the FP32 form are summed per thread in FP32 (they steer
+// the choice of the split dimension and enter no estimate): sum of w, with w in
+// (0, e^64], and sum of (2^-40 w)^2, so that 2^20 terms at the largest weight
+// stay below FP32's maximum; weights below about e^-16 of the shift fall under
+// FP32's normal range in the second sum, far below its other terms.
+constexpr float kSplitWScale = 0x1p-40f;
+constexpr double kSplitW2Unscale = 0x1p80;
 
 template <int NX, int D, bool SPLIT, bool AVG>
 struct Fields {
@@ -72,19 +79,21 @@ struct Fields {
 // Waves per SIMD the register allocation must leave room for: without a floor
 // the compiler spends the whole register file of one wave on large lattices.
 // FP32-form antithetic pairs (two points in registers) are held to three waves
-// per SIMD, the occupancy of the single-point kernel; the FP32 form with split
-// statistics (2d more accumulators) to two (measured 1.4x faster than one wave;
-// the FP64 form spills too much at two).
-template <int NX, int NT, int PREC, bool SPLIT, bool PAIR>
+// per SIMD, the occupancy of the single-point kernel.  The FP32 form with split
+// statistics (2d more FP32 accumulators): three waves with the averaged
+// observable (a spill of about 30 registers, measured 4-10 % faster than two
+// waves without one), two with the anchored product (three spill twice as
+// much: 24 % slower); the FP64 form spills too much at two.
+template <int NX, int NT, int PREC, bool SPLIT, bool AVG, bool PAIR>
 constexpr int kMinWaves = NX * NT > 32             ? 2
                           : PREC != kFP32Shifted   ? 1
-                          : SPLIT                  ? 2
+                          : SPLIT                  ? (AVG ? 3 : 2)
                           : PAIR                   ? 3
                                                    : 1;
 
 template <int NX, int NT, int PREC, int BLOCK, bool SPLIT, bool AVG, bool PAIR>
 __global__ void __launch_bounds__(BLOCK)
-    __attribute__((amdgpu_waves_per_eu(kMinWaves<NX, NT, PREC, SPLIT, PAIR>))) mc_kernel(McArgs a)
+    __attribute__((amdgpu_waves_per_eu(kMinWaves<NX, NT, PREC, SPLIT, AVG, PAIR>))) mc_kernel(McArgs a)
 {
     using T = std::conditional_t<PREC == kFP32Shifted, float, double>;
     // the shift's type: FP32 in the FP32 form, FP64 in the shifted FP64 form
@@ -113,6 +122,7 @@ __global__ void __launch_bounds__(BLOCK)
         blk_add[j] = static_cast<uint64_t>(j) * dev::kPhiloxMulA;
         asm volatile("" : "+v"(blk_add[j]));
     }
+    constexpr bool kSplit32 = SPLIT && PREC == kFP32Shifted;
     static_assert(!SPLIT || D <= 32, "split statistics keep one bit per dimension in 32 bits");
     static_assert(!PAIR || (!SPLIT && D <= kMaxPairD), "antithetic pairs: d <= 32, no split");
 
@@ -204,10 +214,16 @@ __global__ void __launch_bounds__(BLOCK)
                 return T2{row[kk].x, row[kk].y};  // merged into one LDS read
         };
 
-        double acc[NF];
+        // FP64 accumulators, the split statistics' in FP32 in the FP32 form
+        constexpr int NA = kSplit32 ? F::kMain : NF;
+        double acc[NA];
 #pragma unroll
-        for (int i = 0; i < NF; ++i)
+        for (int i = 0; i < NA; ++i)
             acc[i] = 0.0;
+        float sacc[kSplit32 ? 2 * D : 1];
+#pragma unroll
+        for (int i = 0; i < (kSplit32 ? 2 * D : 1); ++i)
+            sacc[i] = 0.0f;
         // no sample yet: +inf (FP32 form), or the largest finite double (FP64
         // form), against which an infinite action still weighs exp(-inf) = 0
         Sig sigma = PREC == kFP64Shifted ? static_cast<Sig>(__DBL_MAX__)
@@ -216,8 +232,27 @@ __global__ void __launch_bounds__(BLOCK)
         auto rescale = [&](double f1) {
             const double f2 = f1 * f1;
 #pragma unroll
-            for (int i = 0; i < NF; ++i)
+            for (int i = 0; i < NA; ++i)
                 acc[i] *= F::order(i) == 1 ? f1 : f2;
+            if constexpr (kSplit32) {
+                // in FP64: f2 can lie below FP32's range while the product does not
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    sacc[k] = static_cast<float>(static_cast<double>(sacc[k]) * f1);
+                    sacc[D + k] = static_cast<float>(static_cast<double>(sacc[D + k]) * f2);
+                }
+            }
+        };
+        // accumulated field i as an FP64 value in the record's scale
+        auto acc_value = [&](int i) -> double {
+            if constexpr (kSplit32) {
+                if (i >= F::kMain) {
+                    const int k = i - F::kMain;
+                    return k < D ? static_cast<double>(sacc[k])
+                                 : static_cast<double>(sacc[k]) * kSplitW2Unscale;
+                }
+            }
+            return acc[i];
         };
 
         // counters of the item: q = (index) NB + block.  When they all share
@@ -466,6 +501,7 @@ __global__ void __launch_bounds__(BLOCK)
             }
 
             double w;
+            [[maybe_unused]] float w32 = 0.0f;
             if constexpr (PREC != kFP32Shifted) {
                 if constexpr (PREC == kFP64Shifted) {
                     if (S < sigma - static_cast<double>(kShiftGap)) {
@@ -493,7 +529,7 @@ __global__ void __launch_bounds__(BLOCK)
                     rescale(exp(static_cast<double>(S) - static_cast<double>(sigma)));
                     sigma = S;
                 }
-                const float w32 = __builtin_amdgcn_exp2f((sigma - S) * kLog2e);
+                w32 = __builtin_amdgcn_exp2f((sigma - S) * kLog2e);
                 w = static_cast<double>(w32);
                 const float t32 = pr_scale * w32;
 #pragma unroll
@@ -506,7 +542,16 @@ __global__ void __launch_bounds__(BLOCK)
             }
             acc[0] += w;
             acc[1] = __fma_rn(w, w, acc[1]);
-            if constexpr (SPLIT) {
+            if constexpr (kSplit32) {
+                const float ws = w32 * kSplitWScale;
+                const float w2s = ws * ws;
+#pragma unroll
+                for (int kk = 0; kk < D; ++kk) {
+                    const bool up = (upper >> kk) & 1u;
+                    sacc[kk] += up ? w32 : 0.0f;
+                    sacc[D + kk] += up ? w2s : 0.0f;
+                }
+            } else if constexpr (SPLIT) {
                 const double w2 = w * w;
 #pragma unroll
                 for (int kk = 0; kk < D; ++kk) {
@@ -545,7 +590,7 @@ __global__ void __launch_bounds__(BLOCK)
         }
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
-            const double v = dev::wave_sum(acc[i]);
+            const double v = dev::wave_sum(acc_value(i));
             if (lane == 0)
                 red[wave][i] = v;
         }

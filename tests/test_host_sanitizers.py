@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(ROOT, "paper_1803_07560_amd", "csrc")
 BUILD = os.path.join(ROOT, "paper_1803_07560_amd", "_build")
-HOST_SOURCES = ["runtime", "tune", "adaptive", "server", "integrand", "sampler", "resident",
+HOST_SOURCES = ["host_pool", "runtime", "tune", "adaptive", "server", "integrand", "sampler", "resident",
                 "spherical"]
 # sanitizers for the host pass only (device code is never built with them)
 HOST_SAN = ("-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined "
