@@ -38,6 +38,7 @@
 #include <type_traits>
 #include <limits>
 #include <numeric>
+#include <optional>
 
 #include "runtime.h"
 
@@ -410,24 +411,46 @@ void merge_record(double *a, const double *b, int len, const std::vector<int> &f
 
 // The two resident evaluators of a run: the kernel variant with split
 // statistics and the plain kernel, each with its buffers and captured graph
-// kept from round to round; and the host buffers of their results.
+// kept from round to round.
 struct Evaluators {
     ResidentEval with, without;
-    // the round's work list results, kept between rounds so their pages are
-    // mapped once (fresh buffers of this size would fault in every round)
-    GrowArray<double> wrec, wsplit, wbase;
     double device_ms = 0.0;  // replay time of every list so far
 };
+
+// The record of all of an entry's samples from the records of its two parts
+// (either may be absent).
+void combine_parts(double *R, const double *with, const double *plain, int rec_len,
+                   const std::vector<int> &first, const std::vector<int> &second)
+{
+    if (with)
+        std::copy(with, with + rec_len, R);
+    else
+        std::fill(R, R + rec_len, 0.0);
+    if (plain)
+        merge_record(R, plain, rec_len, first, second);
+}
+
+// Copy len values, or zeros when src is absent.
+void copy_or_zero(double *dst, const double *src, int len)
+{
+    if (src)
+        std::copy(src, src + len, dst);
+    else
+        std::fill(dst, dst + len, 0.0);
+}
 
 constexpr size_t kGrain = 2048;  // entries per chunk of the parallel host loops
 
 // Evaluate a work list on the device.  The samples below index `split_samples`
 // of each stream (all of them when 0) go through the kernel variant with split
-// statistics, the rest through the plain kernel.  Per entry: rec covers all its
-// samples, base and split the ones with statistics (count 0 and zeros if none).
+// statistics, the rest through the plain kernel.  Entry w's results go to
+// sink(w, with, split, plain), called in parallel over the entries: the record
+// and the split statistics of its samples below split_samples and the record of
+// the rest, each NULL if the entry has no such samples, read where the replays
+// left them (pinned host memory, valid until the next list).
+template <class Sink>
 bfi_status eval_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, const SubList &work,
-                     uint64_t split_samples, GrowArray<double> *rec, GrowArray<double> *split,
-                     GrowArray<double> *base)
+                     uint64_t split_samples, Sink &&sink)
 {
     const int d = lat.nx * lat.nt, rec_len = BFI_PARTIAL_LEN(lat.nx), split_len = BFI_SPLIT_LEN(d);
     const size_t count = work.size();
@@ -454,8 +477,7 @@ bfi_status eval_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, cons
         if (opos[w] >= 0)
             ev->without.set(static_cast<size_t>(opos[w]), work.id[w], cut[w], end - cut[w], lo, hi);
     });
-    // both replays prepared, then queued back to back: the plain pass runs while
-    // the host takes the split pass's records
+    // both replays prepared, then queued back to back on the stream
     {
         TraceRange tr("adaptive: prepare and launch");
         if (nw > 0)
@@ -467,7 +489,6 @@ bfi_status eval_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, cons
         if (no > 0)
             BFI_TRY(ev->without.launch());
     }
-    // the records are read where the replays left them (pinned host memory)
     if (nw > 0) {
         TraceRange tr("adaptive: samples with split statistics");
         double ms = 0.0;
@@ -482,27 +503,11 @@ bfi_status eval_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, cons
     }
     const double *r_with = ev->with.records(), *sp_with = ev->with.split_records(),
                  *r_without = ev->without.records();
-    std::vector<int> first, second;
-    record_fields(lat.nx, &first, &second);
-    rec->resize(count * rec_len);
-    split->resize(count * split_len);
-    base->resize(count * rec_len);
     parallel_range(count, kGrain, [&](size_t w) {
-        double *R = &(*rec)[w * rec_len], *B = &(*base)[w * rec_len], *P = &(*split)[w * split_len];
-        if (wpos[w] >= 0) {
-            const double *r = &r_with[static_cast<size_t>(wpos[w]) * rec_len];
-            std::copy(r, r + rec_len, B);
-            std::copy(r, r + rec_len, R);
-            const double *sp = &sp_with[static_cast<size_t>(wpos[w]) * split_len];
-            std::copy(sp, sp + split_len, P);
-        } else {
-            std::fill(B, B + rec_len, 0.0);
-            std::fill(R, R + rec_len, 0.0);
-            std::fill(P, P + split_len, 0.0);
-        }
-        if (opos[w] >= 0)
-            merge_record(R, &r_without[static_cast<size_t>(opos[w]) * rec_len], rec_len, first,
-                         second);
+        const size_t i = static_cast<size_t>(wpos[w]), o = static_cast<size_t>(opos[w]);
+        sink(w, wpos[w] >= 0 ? &r_with[i * rec_len] : nullptr,
+             wpos[w] >= 0 ? &sp_with[i * split_len] : nullptr,
+             opos[w] >= 0 ? &r_without[o * rec_len] : nullptr);
     });
     return BFI_OK;
 }
@@ -562,7 +567,16 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         Evaluators ev;
         BFI_TRY(ev.with.init(ctx, *lat, prec, true, launch));
         BFI_TRY(ev.without.init(ctx, *lat, prec, false, launch));
-        BFI_TRY(eval_list(&ev, *lat, seed, init, cfg->split_samples, &L.rec, &L.split, &L.base));
+        L.rec.resize(L.size() * rec_len);
+        L.split.resize(L.size() * split_len);
+        L.base.resize(L.size() * rec_len);
+        BFI_TRY(eval_list(&ev, *lat, seed, init, cfg->split_samples,
+                          [&](size_t w, const double *with, const double *sp, const double *plain) {
+                              combine_parts(&L.rec[w * rec_len], with, plain, rec_len, rec_first,
+                                            rec_second);
+                              copy_or_zero(&L.base[w * rec_len], with, rec_len);
+                              copy_or_zero(&L.split[w * split_len], sp, split_len);
+                          }));
 
         bfi_status status = BFI_OK;
         const double min_ess = cfg->min_ess > 0 ? cfg->min_ess : 100.0;
@@ -652,6 +666,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             phase.next("adaptive: decide and plan");
             const SplitStats st{d, rec_len, L.split.data(), L.base.data()};
             action.resize(L.size());
+            std::optional<TraceRange> sub(std::in_place, "adaptive: rank and decide");
             Ranking order(an, L.id.data());
             const size_t examined =
                 decide(an, st, L.id.data(), L.n.data(), *cfg, action.data(), order);
@@ -666,57 +681,95 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             // planned count of a refined leaf at scale factor f (within n_max):
             // children clamp(n, n_min, n_max) each, doubled leaves 2n, times f
             target.resize(L.size());  // new per-leaf (or per-child) count, refined leaves
-            auto leaf_target = [&](size_t s, uint64_t f) {
-                const uint64_t base = action[s] == 0 ? 2 * L.n[s]
-                                                      : std::min(std::max(L.n[s], cfg->n_min),
-                                                                 cfg->n_max);
+            // planned count of a leaf with action `act` and n samples at factor f
+            auto target_of = [&](int32_t act, uint64_t n, uint64_t f) {
+                const uint64_t base =
+                    act == 0 ? 2 * n : std::min(std::max(n, cfg->n_min), cfg->n_max);
                 const uint64_t cap = std::max(cfg->n_max, base);
                 return base > cap / f ? cap : std::max(base, std::min(base * f, cap));
             };
-            auto leaf_cost = [&](size_t s) {
-                return action[s] == 0 ? target[s] - L.n[s] : 2 * target[s];
+            auto cost_of = [](int32_t act, uint64_t n, uint64_t t) {
+                return act == 0 ? t - n : 2 * t;
             };
-            // refined leaves whose count would still grow at 2f
-            auto grows = [&](size_t s, uint64_t f) {
+            // whether the count would still grow at 2f
+            auto grows_of = [&](int32_t act, uint64_t n, uint64_t f, uint64_t t) {
                 return f <= std::numeric_limits<uint64_t>::max() / 2 &&
-                       leaf_target(s, 2 * f) > target[s];
+                       target_of(act, n, 2 * f) > t;
             };
             uint64_t f = 1, planned = 0;
             size_t growable = 0;
+            // every refined leaf at factor f: per-chunk integer sums, so the
+            // totals do not depend on the chunking
+            std::vector<uint64_t> chunk_planned;
+            std::vector<size_t> chunk_growable;
             auto plan_all = [&]() {
+                const size_t nr = refined.size(), nch = (nr + kGrain - 1) / kGrain;
+                chunk_planned.assign(nch, 0);
+                chunk_growable.assign(nch, 0);
+                for_chunks(nch, [&](size_t c) {
+                    uint64_t p = 0;
+                    size_t g = 0;
+                    for (size_t i = c * kGrain; i < std::min(nr, (c + 1) * kGrain); ++i) {
+                        const size_t s = refined[i];
+                        const uint64_t t = target_of(action[s], L.n[s], f);
+                        target[s] = t;
+                        p += cost_of(action[s], L.n[s], t);
+                        g += grows_of(action[s], L.n[s], f, t);
+                    }
+                    chunk_planned[c] = p;
+                    chunk_growable[c] = g;
+                });
                 planned = 0;
                 growable = 0;
-                for (size_t s : refined) {
-                    target[s] = leaf_target(s, f);
-                    planned += leaf_cost(s);
-                    growable += grows(s, f);
+                for (size_t c = 0; c < nch; ++c) {
+                    planned += chunk_planned[c];
+                    growable += chunk_growable[c];
                 }
             };
+            sub.reset();
+            sub.emplace("adaptive: work floor");
             plan_all();
             // work floor: scale the refined leaves by powers of two; once n_max caps
             // them all, refine further leaves in variance order (each at the current
             // factor; the next pass doubles again if one of them can still grow)
             size_t next_leaf = 0;
-            // the decisions of the next candidates in rank order, computed a batch
-            // at a time in parallel (each depends on its own leaf only) and taken
-            // up one by one below; ranks [pre_lo, pre_lo + pre.size())
-            std::vector<int32_t> pre;
-            size_t pre_lo = 0;
-            auto decision = [&](size_t rank) {
-                if (rank < pre_lo || rank >= pre_lo + pre.size()) {
-                    const size_t len = std::min(order.size() - rank,
-                                                std::max<size_t>(4096, 2 * pre.size()));
+            // the next candidates in rank order, a batch at a time: leaf, decision
+            // (each depends on its own leaf only; kHasAction for a leaf that
+            // decide() gave an action) and sample count, gathered in parallel so
+            // that the scan below reads them in order; ranks [batch_lo, + size).
+            // Which decisions a batch computes ahead changes no result.
+            constexpr int32_t kHasAction = std::numeric_limits<int32_t>::min();
+            struct Candidate {
+                size_t leaf;
+                int32_t act;
+                uint64_t n;
+            };
+            std::vector<Candidate> batch;
+            size_t batch_lo = 0;
+            auto candidate = [&](size_t rank) {
+                if (rank < batch_lo || rank >= batch_lo + batch.size()) {
+                    // a leaf adds at most 2 n_max samples (counts stay within n_max):
+                    // the round needs at least this many more leaves
+                    const uint64_t left = cfg->round_evals - planned;
+                    const uint64_t need = cfg->n_max <= std::numeric_limits<uint64_t>::max() / 2
+                                              ? left / (2 * cfg->n_max) + 1
+                                              : 1;
+                    const size_t len = static_cast<size_t>(std::min<uint64_t>(
+                        order.size() - rank, std::max<uint64_t>(4096, need)));
                     for (size_t k = 0; k < len; ++k)
                         (void)order[rank + k];  // gather the ranks first (serial)
-                    pre.assign(len, -1);
-                    pre_lo = rank;
+                    batch.resize(len);
+                    batch_lo = rank;
                     parallel_range(len, size_t(1) << 9, [&](size_t k) {
                         const size_t s = order[rank + k];
-                        if (action[s] == -1)
-                            pre[k] = leaf_action(an, st, s, L.id[s], L.n[s], *cfg);
+                        batch[k] = Candidate{
+                            s,
+                            action[s] == -1 ? leaf_action(an, st, s, L.id[s], L.n[s], *cfg)
+                                            : kHasAction,
+                            L.n[s]};
                     });
                 }
-                return pre[rank - pre_lo];
+                return batch[rank - batch_lo];
             };
             while (cfg->round_evals > 0 && planned < cfg->round_evals) {
                 if (growable > 0) {
@@ -724,24 +777,31 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                     plan_all();
                     continue;
                 }
-                while (next_leaf < order.size() && action[order[next_leaf]] != -1)
+                // only the leaf taken up here gets an action in this loop, so a
+                // batch's view of which leaves have one stays current
+                Candidate c{0, kHasAction, 0};
+                while (next_leaf < order.size() && (c = candidate(next_leaf)).act == kHasAction)
                     ++next_leaf;
                 if (next_leaf == order.size())
                     break;
-                const size_t s = order[next_leaf];
-                action[s] = decision(next_leaf);
-                if (action[s] < 0) {
+                ++next_leaf;
+                const size_t s = c.leaf;
+                if (c.act < 0) {
                     action[s] = -2;  // neither split nor doubling possible: skip it
                     continue;
                 }
+                action[s] = c.act;
                 refined.push_back(s);
-                target[s] = leaf_target(s, f);
-                planned += leaf_cost(s);
-                growable += grows(s, f);
+                const uint64_t t = target_of(c.act, c.n, f);
+                target[s] = t;
+                planned += cost_of(c.act, c.n, t);
+                growable += grows_of(c.act, c.n, f, t);
             }
             for (size_t i = 0; i < order.sorted(); ++i)
                 if (action[order[i]] == -2)
                     action[order[i]] = -1;
+            sub.reset();
+            sub.emplace("adaptive: budget trim");
             // trim to the evaluation budget in priority order (every refined leaf
             // lies in the part of the ranking read so far)
             uint64_t cost = 0;
@@ -755,6 +815,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                 else
                     cost += c;
             }
+            sub.reset();
             if (cost == 0) {
                 status = BFI_EBUDGET;
                 break;
@@ -824,23 +885,15 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                     origin[w] = {s, 1 + half};
                 }
             });
-            phase.next("adaptive: evaluate");
-            GrowArray<double> &wrec = ev.wrec, &wsplit = ev.wsplit, &wbase = ev.wbase;
-            BFI_TRY(eval_list(&ev, *lat, seed, work, cfg->split_samples, &wrec, &wsplit, &wbase));
-            evals += cost;
-
-            phase.next("adaptive: fold");
-            // fold the results into the leaf set in place: a doubled leaf merges
-            // its continuation, a split leaf becomes its lower child and its upper
-            // child is appended; every entry has its own destination, so the
-            // entries are folded in parallel
+            // destinations: a doubled leaf merges its continuation, a split leaf
+            // becomes its lower child and its upper child is appended; capacity
+            // grows geometrically and by remapping (an exact reserve, or a copying
+            // one, would move the whole leaf set, gigabytes at millions of leaves,
+            // every round)
             dst.resize(origin.size());
             size_t grown = L.size();
             for (size_t w = 0; w < origin.size(); ++w)
                 dst[w] = origin[w].kind == 2 ? grown++ : origin[w].leaf;
-            // capacity grows geometrically and by remapping: an exact reserve, or a
-            // copying one, would move the whole leaf set (gigabytes at millions of
-            // leaves) every round
             L.id.resize(grown);
             L.n.resize(grown);
             L.lo.resize(grown * d);
@@ -849,30 +902,38 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             L.split.resize(grown * split_len);
             L.base.resize(grown * rec_len);
             L.vol.resize(grown);
-            parallel_range(origin.size(), kGrain, [&](size_t w) {
-                const size_t s = dst[w];
-                const double *wr = &wrec[w * rec_len], *ws = &wsplit[w * split_len],
-                             *wb = &wbase[w * rec_len];
-                if (origin[w].kind == 0) {
-                    merge_shifted(&L.rec[s * rec_len], wr, 1, rec_first, rec_second, 0);
-                    if (wb[0] > 0) {
-                        // the continuation still lies below split_samples
-                        merge_shifted(&L.split[s * split_len], ws, 0, split_first, split_second,
-                                      -1);
-                        merge_shifted(&L.base[s * rec_len], wb, 1, rec_first, rec_second, 0);
+            phase.next("adaptive: evaluate and fold");
+            // the results go into the leaf set in place as each entry's records
+            // are read; every entry has its own destination
+            BFI_TRY(eval_list(
+                &ev, *lat, seed, work, cfg->split_samples,
+                [&](size_t w, const double *with, const double *sp, const double *plain) {
+                    const size_t s = dst[w];
+                    if (origin[w].kind == 0) {
+                        double R[BFI_PARTIAL_LEN(BFI_MAX_NX)];
+                        combine_parts(R, with, plain, rec_len, rec_first, rec_second);
+                        merge_shifted(&L.rec[s * rec_len], R, 1, rec_first, rec_second, 0);
+                        if (with && with[0] > 0) {
+                            // the continuation still lies below split_samples
+                            merge_shifted(&L.split[s * split_len], sp, 0, split_first,
+                                          split_second, -1);
+                            merge_shifted(&L.base[s * rec_len], with, 1, rec_first, rec_second,
+                                          0);
+                        }
+                        L.n[s] = target[s];
+                        return;
                     }
-                    L.n[s] = target[s];
-                    return;
-                }
-                L.id[s] = work.id[w];
-                L.n[s] = work.n[w];
-                std::copy(&work.lo[w * d], &work.lo[w * d] + d, &L.lo[s * d]);
-                std::copy(&work.hi[w * d], &work.hi[w * d] + d, &L.hi[s * d]);
-                L.vol[s] = box_volume(&L.lo[s * d], &L.hi[s * d], d);
-                std::copy(wr, wr + rec_len, &L.rec[s * rec_len]);
-                std::copy(ws, ws + split_len, &L.split[s * split_len]);
-                std::copy(wb, wb + rec_len, &L.base[s * rec_len]);
-            });
+                    L.id[s] = work.id[w];
+                    L.n[s] = work.n[w];
+                    std::copy(&work.lo[w * d], &work.lo[w * d] + d, &L.lo[s * d]);
+                    std::copy(&work.hi[w * d], &work.hi[w * d] + d, &L.hi[s * d]);
+                    L.vol[s] = box_volume(&L.lo[s * d], &L.hi[s * d], d);
+                    combine_parts(&L.rec[s * rec_len], with, plain, rec_len, rec_first,
+                                  rec_second);
+                    copy_or_zero(&L.split[s * split_len], sp, split_len);
+                    copy_or_zero(&L.base[s * rec_len], with, rec_len);
+                }));
+            evals += cost;
             ++rounds;
         }
 
