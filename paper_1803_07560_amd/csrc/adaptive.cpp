@@ -454,6 +454,7 @@ bfi_status eval_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, cons
 {
     const int d = lat.nx * lat.nt, rec_len = BFI_PARTIAL_LEN(lat.nx), split_len = BFI_SPLIT_LEN(d);
     const size_t count = work.size();
+    std::optional<TraceRange> stage_range(std::in_place, "adaptive: stage");
     // entry w's covered part [offset, min(end, P)) goes to the first list at
     // wpos[w], the rest to the second at opos[w] (-1: no such part)
     std::vector<int64_t> wpos(count, -1), opos(count, -1);
@@ -477,6 +478,7 @@ bfi_status eval_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, cons
         if (opos[w] >= 0)
             ev->without.set(static_cast<size_t>(opos[w]), work.id[w], cut[w], end - cut[w], lo, hi);
     });
+    stage_range.reset();
     // both replays prepared, then queued back to back on the stream
     {
         TraceRange tr("adaptive: prepare and launch");
@@ -503,6 +505,7 @@ bfi_status eval_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, cons
     }
     const double *r_with = ev->with.records(), *sp_with = ev->with.split_records(),
                  *r_without = ev->without.records();
+    TraceRange tr("adaptive: take the records");
     parallel_range(count, kGrain, [&](size_t w) {
         const size_t i = static_cast<size_t>(wpos[w]), o = static_cast<size_t>(opos[w]);
         sink(w, wpos[w] >= 0 ? &r_with[i * rec_len] : nullptr,
@@ -890,6 +893,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             // grows geometrically and by remapping (an exact reserve, or a copying
             // one, would move the whole leaf set, gigabytes at millions of leaves,
             // every round)
+            std::optional<TraceRange> grow_range(std::in_place, "adaptive: leaf set growth");
             dst.resize(origin.size());
             size_t grown = L.size();
             for (size_t w = 0; w < origin.size(); ++w)
@@ -902,6 +906,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             L.split.resize(grown * split_len);
             L.base.resize(grown * rec_len);
             L.vol.resize(grown);
+            grow_range.reset();
             phase.next("adaptive: evaluate and fold");
             // the results go into the leaf set in place as each entry's records
             // are read; every entry has its own destination
