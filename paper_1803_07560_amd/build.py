@@ -70,7 +70,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         tasks.append([cc, *COMMON, *DEVICE, f"-DBFI_NX={nx}", f"-DBFI_NT={nt}", "-c",
                       os.path.join(CSRC, "sph_kernels.hip"), "-o",
                       os.path.join(BUILD, f"sph_{nx}x{nt}.o")])
-    for src in ("common_kernels.hip", "noalloc.hip"):
+    for src in ("common_kernels.hip", "leaf_kernels.hip", "noalloc.hip"):
         tasks.append([cc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o",
                       os.path.join(BUILD, src.replace(".hip", ".o"))])
     for src in HOST_SOURCES:

@@ -57,28 +57,15 @@ double box_volume(const double *lo, const double *hi, int d)
     return v;
 }
 
-struct LeafAnalysis {
-    double e = 0.0;        // contribution to the variance of C
-    int best_dim = 0;      // j*
-    double gain = 1.0;     // (sigma_L + sigma_U)(j*) / (2 sigma)
-};
-
-// Contribution of every leaf to the variance of C, and the estimate itself
-// (both from the finalize's two passes over the records).
+// Contribution of every leaf to the variance of C (NaN counts 0), and the
+// estimate itself, from the finalize's two passes over host records.
 bfi_status analyse(int nx, int d, size_t count, const double *lo, const double *hi,
-                   const double *partials, std::vector<LeafAnalysis> *out, bfi_result *res,
-                   const double *vol = nullptr)
+                   const double *partials, std::vector<double> *e_out, bfi_result *res)
 {
-    thread_local std::vector<double> e;  // reused across rounds
-    if (e.size() < count)
-        e.resize(count);
-    BFI_TRY(finalize_records(nx, d, count, lo, hi, partials, res, 1, e.data(), vol));
-    out->resize(count);
-    const double *ev = e.data();
-    LeafAnalysis *ov = out->data();
-    parallel_range(count, size_t(1) << 16, [ev, ov](size_t s) {
-        ov[s] = LeafAnalysis{ev[s] >= 0.0 ? ev[s] : 0.0, 0, 1.0};  // NaN ranks last
-    });
+    e_out->resize(count);
+    BFI_TRY(finalize_records(nx, d, count, lo, hi, partials, res, 1, e_out->data()));
+    double *ev = e_out->data();
+    parallel_range(count, size_t(1) << 16, [ev](size_t s) { ev[s] = ev[s] >= 0.0 ? ev[s] : 0.0; });
     return BFI_OK;
 }
 
@@ -90,9 +77,15 @@ struct SplitStats {
     const double *split, *base;
 };
 
+struct SplitChoice {
+    int best_dim;  // j*
+    double gain;   // (sigma_L + sigma_U)(j*) / (2 sigma)
+};
+
 // j* and the gain of leaf s, in the shift of the covered samples (the split
-// record shares it).
-void split_choice(const SplitStats &st, size_t s, LeafAnalysis *a)
+// record shares it).  The device analysis of a run's leaves does the same
+// arithmetic (leaf_kernels.hip).
+SplitChoice split_choice(const SplitStats &st, size_t s)
 {
     const int d = st.d;
     const double *sp = st.split + s * BFI_SPLIT_LEN(d), *base = st.base + s * st.rec_len;
@@ -111,8 +104,7 @@ void split_choice(const SplitStats &st, size_t s, LeafAnalysis *a)
             best_j = j;
         }
     }
-    a->best_dim = best_j;
-    a->gain = sigma > 0 ? best / (2.0 * sigma) : 1.0;
+    return SplitChoice{best_j, sigma > 0 ? best / (2.0 * sigma) : 1.0};
 }
 
 double rel_err(const bfi_result &r)
@@ -125,18 +117,13 @@ double rel_err(const bfi_result &r)
 
 bool can_split(uint64_t id) { return id < (uint64_t(1) << 62); }
 
-// Action of refined leaf s: split along j* when that halves the spread well
+// Action of a refined leaf: split along j* when that halves the spread well
 // enough or doubling would exceed n_max, else double; -1 if neither is possible.
-// The split analysis is done here, for the leaves that are refined only.
-int32_t leaf_action(std::vector<LeafAnalysis> &an, const SplitStats &st, size_t s, uint64_t id,
-                    uint64_t n, const bfi_adaptive_config &cfg)
+int32_t action_of(const SplitChoice &c, uint64_t id, uint64_t n, const bfi_adaptive_config &cfg)
 {
     const bool doubling_ok = n <= cfg.n_max / 2;
-    if (can_split(id)) {
-        split_choice(st, s, &an[s]);
-        if (an[s].gain < kSplitGain || !doubling_ok)
-            return 1 + an[s].best_dim;
-    }
+    if (can_split(id) && (c.gain < kSplitGain || !doubling_ok))
+        return 1 + c.best_dim;
     return doubling_ok ? 0 : -1;
 }
 
@@ -149,9 +136,8 @@ int32_t leaf_action(std::vector<LeafAnalysis> &an, const SplitStats &st, size_t 
 // leaves never sorts the rest.
 class Ranking {
 public:
-    Ranking(const std::vector<LeafAnalysis> &an, const uint64_t *ids) : an_(an), ids_(ids)
+    Ranking(const double *e, size_t n, const uint64_t *ids) : e_(e), n_(n), ids_(ids)
     {
-        const size_t n = an.size();
         nchunks_ = (n + kChunk - 1) / kChunk;
         part_.assign(nchunks_, {});
         bucket_.resize(n);
@@ -161,10 +147,10 @@ public:
             const size_t i1 = std::min(n, (c + 1) * kChunk);
             double sum = 0.0;
             for (size_t s = c * kChunk; s < i1; ++s) {
-                const uint16_t b = bucket(an[s].e);
+                const uint16_t b = bucket(e[s]);
                 bucket_[s] = b;
                 ++part_[c][b];
-                sum += an[s].e;
+                sum += e[s];
             }
             sums[c] = sum;
         });
@@ -177,7 +163,7 @@ public:
             total_ += x;
         top_ = kBuckets;
     }
-    size_t size() const { return an_.size(); }
+    size_t size() const { return n_; }
     // sum of e over every leaf (per-chunk sums in chunk order)
     double total() const { return total_; }
     // the leaf at rank i
@@ -214,7 +200,7 @@ private:
     // parallel.
     void extend(size_t want)
     {
-        const size_t n = an_.size();
+        const size_t n = n_;
         const size_t target = std::min(n, std::max({want, 2 * keys_.size(), size_t(4096)}));
         size_t have = keys_.size(), lo = top_;
         while (lo > 0 && have < target)
@@ -237,7 +223,7 @@ private:
             for (size_t s = c * kChunk; s < i1; ++s) {
                 const size_t b = bucket_[s];
                 if (b >= lo && b < hi)
-                    keys_[at[hi - 1 - b]++] = Key{an_[s].e, ids_[s], s};
+                    keys_[at[hi - 1 - b]++] = Key{e_[s], ids_[s], s};
             }
         });
         for_chunks(span, [&](size_t k) {
@@ -247,7 +233,8 @@ private:
         });
         top_ = lo;
     }
-    const std::vector<LeafAnalysis> &an_;
+    const double *e_;
+    size_t n_;
     const uint64_t *ids_;
     size_t nchunks_ = 0;
     std::vector<std::vector<uint32_t>> part_;  // per chunk: leaves per bucket
@@ -259,12 +246,13 @@ private:
 };
 
 // Decide actions: -1 keep, 0 double, 1 + j split along j, for the leaves in
-// ranking order until their contributions reach refine_fraction of the total.
-// Returns the number of ranks examined; the refined leaves are among them.
-size_t decide(std::vector<LeafAnalysis> &an, const SplitStats &st, const uint64_t *ids,
-              const uint64_t *n, const bfi_adaptive_config &cfg, int32_t *action, Ranking &order)
+// ranking order until their contributions e reach refine_fraction of the
+// total; act(s) gives leaf s's action.  Returns the number of ranks examined;
+// the refined leaves are among them.
+template <class Act>
+size_t decide(const double *e, size_t count, Act &&act, const bfi_adaptive_config &cfg,
+              int32_t *action, Ranking &order)
 {
-    const size_t count = an.size();
     const double total = order.total();
     parallel_range(count, size_t(1) << 18, [&](size_t s) { action[s] = -1; });
     // the ranks taken (in order, until their contributions reach the fraction);
@@ -276,13 +264,13 @@ size_t decide(std::vector<LeafAnalysis> &an, const SplitStats &st, const uint64_
         const size_t s = order[i];
         if (i > 0 && taken >= cfg.refine_fraction * total)
             break;
-        if (an[s].e <= 0.0 && i > 0)
+        if (e[s] <= 0.0 && i > 0)
             break;
-        taken += an[s].e;
+        taken += e[s];
     }
     parallel_range(i, size_t(1) << 10, [&](size_t k) {
         const size_t s = order[k];
-        action[s] = leaf_action(an, st, s, ids[s], n[s], cfg);
+        action[s] = act(s);
     });
     return i;
 }
@@ -386,132 +374,318 @@ private:
     size_t n_ = 0, cap_ = 0;
 };
 
+// The host side of the leaf set: ids, sample counts, boxes and volumes.  The
+// records stay in device memory (DeviceLeaves).
 struct LeafSet {
     int d = 0, nx = 0;
     GrowArray<uint64_t> id, n;
-    // rec: all samples; split and base: split statistics and the record of the
-    // samples they cover (the first split_samples of the leaf's stream)
-    GrowArray<double> lo, hi, rec, split, base;
+    GrowArray<double> lo, hi;
     GrowArray<double> vol;  // product of the extents, computed once per leaf
     size_t size() const { return id.size(); }
 };
 
-// Merge record b into a when both may be empty (count 0: nothing to add).
-void merge_record(double *a, const double *b, int len, const std::vector<int> &first,
-                  const std::vector<int> &second)
+// Device buffer grown geometrically, keeping its first `keep` elements (copied
+// on the stream, which is then drained before the old buffer goes).
+template <class T>
+hipError_t grow_keep(T **p, size_t *cap, size_t need, size_t keep, hipStream_t st)
 {
-    if (b[0] == 0)
-        return;
-    if (a[0] == 0) {
-        std::copy(b, b + len, a);
-        return;
+    if (need <= *cap && *p)
+        return hipSuccess;
+    const size_t n = std::max<size_t>({need, 2 * *cap, 1024});
+    T *q = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&q), n * sizeof(T));
+    if (e != hipSuccess)
+        return e;
+    if (*p) {
+        if (keep > 0)
+            e = hipMemcpyAsync(q, *p, keep * sizeof(T), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            (void)hipFree(q);
+            return e;
+        }
+        (void)hipFree(*p);
     }
-    merge_shifted(a, b, 1, first, second, 0);
+    *p = q;
+    *cap = n;
+    return hipSuccess;
 }
 
-// The two resident evaluators of a run: the kernel variant with split
-// statistics and the plain kernel, each with its buffers and captured graph
-// kept from round to round.
-struct Evaluators {
-    ResidentEval with, without;
-    double device_ms = 0.0;  // replay time of every list so far
+// Pinned host buffer grown geometrically (contents not kept).
+template <class T>
+hipError_t grow_pinned_buf(T **p, size_t *cap, size_t need)
+{
+    if (need <= *cap && *p)
+        return hipSuccess;
+    const size_t n = std::max<size_t>({need, 2 * *cap, 1024});
+    if (*p)
+        (void)hipHostFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(p), n * sizeof(T), hipHostMallocDefault);
+    if (e == hipSuccess)
+        *cap = n;
+    return e;
+}
+
+// The leaves' records in device memory: per leaf the record of all its
+// samples, its split statistics and the record of the samples they cover, and
+// its volume.  A round's records are folded in on the device and every leaf is
+// analysed there (leaf_kernels.hip); the host reads back each leaf's
+// contribution e, split choice and gain, and the estimate's totals.  Buffers
+// grow geometrically; nothing is allocated in a round that adds no capacity.
+class DeviceLeaves {
+public:
+    DeviceLeaves(bfi_context *ctx, int nx, int d)
+        : ctx_(ctx), nx_(nx), d_(d), rec_len_(BFI_PARTIAL_LEN(nx)), split_len_(BFI_SPLIT_LEN(d))
+    {
+    }
+    DeviceLeaves(const DeviceLeaves &) = delete;
+    DeviceLeaves &operator=(const DeviceLeaves &) = delete;
+    ~DeviceLeaves()
+    {
+        (void)hipStreamSynchronize(ctx_->stream);
+        for (void *p : {static_cast<void *>(rec_), static_cast<void *>(split_),
+                        static_cast<void *>(base_), static_cast<void *>(vol_),
+                        static_cast<void *>(e_d_), static_cast<void *>(gain_d_),
+                        static_cast<void *>(best_d_), static_cast<void *>(scratch_),
+                        static_cast<void *>(totals_d_), static_cast<void *>(fold_d_)})
+            if (p)
+                (void)hipFree(p);
+        for (void *p : {static_cast<void *>(h_e_), static_cast<void *>(h_gain_),
+                        static_cast<void *>(h_best_), static_cast<void *>(h_totals_),
+                        static_cast<void *>(h_fold_)})
+            if (p)
+                (void)hipHostFree(p);
+        for (hipEvent_t ev : {ev_f0_, ev_f1_, ev_a0_, ev_a1_})
+            if (ev)
+                (void)hipEventDestroy(ev);
+    }
+    // room for n leaves; the first `keep` leaves' records are kept
+    bfi_status reserve(size_t n, size_t keep)
+    {
+        if (n > 0xFFFFFFFFull)
+            return fail(BFI_EINVAL, "more than 2^32 leaves");
+        if (n <= cap_ && rec_)
+            return BFI_OK;
+        // capacities in elements; every per-leaf buffer grows to the same count
+        // of leaves (cap_), so each is reallocated when the leaves outgrow it
+        hipStream_t st = ctx_->stream;
+        const size_t leaves = std::max<size_t>({n, 2 * cap_, 1024});
+        size_t c_rec = cap_ * rec_len_, c_split = cap_ * split_len_, c_base = cap_ * rec_len_,
+               c_vol = cap_;
+        BFI_HIP(grow_keep(&rec_, &c_rec, leaves * rec_len_, keep * rec_len_, st));
+        BFI_HIP(grow_keep(&split_, &c_split, leaves * split_len_, keep * split_len_, st));
+        BFI_HIP(grow_keep(&base_, &c_base, leaves * rec_len_, keep * rec_len_, st));
+        BFI_HIP(grow_keep(&vol_, &c_vol, leaves, keep, st));
+        size_t c_e = cap_, c_g = cap_, c_b = cap_;
+        BFI_HIP(grow_keep(&e_d_, &c_e, leaves, 0, st));
+        BFI_HIP(grow_keep(&gain_d_, &c_g, leaves, 0, st));
+        BFI_HIP(grow_keep(&best_d_, &c_b, leaves, 0, st));
+        cap_ = leaves;
+        return BFI_OK;
+    }
+    // pinned room for a round's fold entries
+    bfi_status stage_fold(size_t count)
+    {
+        BFI_HIP(grow_pinned_buf(&h_fold_, &cap_hfold_, count));
+        return BFI_OK;
+    }
+    FoldEntry *fold_entries() { return h_fold_; }
+    // fold entries [0, count) into the leaves, queued after the replays on the
+    // context's stream (their records: with_rec/with_split and plain_rec)
+    bfi_status fold(size_t count, const double *with_rec, const double *with_split,
+                    const double *plain_rec)
+    {
+        if (count == 0)
+            return BFI_OK;
+        if (count > 0xFFFFFFFFull)
+            return fail(BFI_EINVAL, "more than 2^32 entries in one round");
+        hipStream_t st = ctx_->stream;
+        BFI_TRY(events());
+        BFI_HIP(grow_keep(&fold_d_, &cap_dfold_, count, 0, st));
+        BFI_HIP(hipEventRecord(ev_f0_, st));
+        BFI_HIP(hipMemcpyAsync(fold_d_, h_fold_, count * sizeof(FoldEntry), hipMemcpyHostToDevice,
+                               st));
+        FoldArgs fa{fold_d_, static_cast<uint32_t>(count), with_rec, with_split, plain_rec,
+                    rec_,    split_,    base_,     vol_,      nx_,       d_};
+        BFI_HIP(launch_fold(fa, st));
+        BFI_HIP(hipEventRecord(ev_f1_, st));
+        folded_ = true;
+        return BFI_OK;
+    }
+    // analyse leaves [0, count): the estimate into res, each leaf's e, split
+    // choice and gain into host memory (e(), best(), gain()); device_ms gets the
+    // device time of the last fold and this analysis
+    bfi_status analyse(size_t count, bfi_result *res, double *device_ms)
+    {
+        if (count == 0 || count > 0xFFFFFFFFull)
+            return fail(BFI_EINVAL, "leaf count out of range");
+        hipStream_t st = ctx_->stream;
+        BFI_TRY(events());
+        BFI_HIP(grow_keep(&scratch_, &cap_scratch_,
+                          analysis_scratch_doubles(static_cast<uint32_t>(count), nx_), 0, st));
+        const size_t ntot = 1 + 4 + 2 * static_cast<size_t>(nx_);
+        BFI_HIP(grow_keep(&totals_d_, &cap_totals_, ntot, 0, st));
+        BFI_HIP(grow_pinned_buf(&h_totals_, &cap_htotals_, ntot));
+        BFI_HIP(grow_pinned_buf(&h_e_, &cap_he_, count));
+        BFI_HIP(grow_pinned_buf(&h_gain_, &cap_hg_, count));
+        BFI_HIP(grow_pinned_buf(&h_best_, &cap_hb_, count));
+        BFI_HIP(hipEventRecord(ev_a0_, st));
+        LeafAnalysisArgs la{rec_,   split_,   base_,     vol_,   static_cast<uint32_t>(count),
+                            nx_,    d_,       scratch_,  totals_d_, e_d_,
+                            gain_d_, best_d_};
+        BFI_HIP(launch_leaf_analysis(la, st));
+        BFI_HIP(hipMemcpyAsync(h_totals_, totals_d_, ntot * sizeof(double), hipMemcpyDeviceToHost,
+                               st));
+        BFI_HIP(hipMemcpyAsync(h_e_, e_d_, count * sizeof(double), hipMemcpyDeviceToHost, st));
+        BFI_HIP(hipMemcpyAsync(h_gain_, gain_d_, count * sizeof(double), hipMemcpyDeviceToHost, st));
+        BFI_HIP(hipMemcpyAsync(h_best_, best_d_, count * sizeof(int32_t), hipMemcpyDeviceToHost,
+                               st));
+        BFI_HIP(hipEventRecord(ev_a1_, st));
+        BFI_HIP(hipEventSynchronize(ev_a1_));
+        float ms = 0.0f;
+        BFI_HIP(hipEventElapsedTime(&ms, ev_a0_, ev_a1_));
+        if (device_ms)
+            *device_ms += ms;
+        if (folded_) {
+            BFI_HIP(hipEventElapsedTime(&ms, ev_f0_, ev_f1_));
+            if (device_ms)
+                *device_ms += ms;
+            folded_ = false;
+        }
+        // the estimate from the totals, as the finalize forms it
+        std::memset(res, 0, sizeof(*res));
+        res->nx = nx_;
+        const double *T = h_totals_;
+        const double sig = T[0], z = T[1];
+        if (!std::isfinite(sig))
+            return fail(BFI_EINVAL, "partial records carry no finite shift");
+        res->log_Z = std::log(z) - sig;
+        res->Z = std::exp(res->log_Z);
+        res->Z_err = std::sqrt(std::max(T[2], 0.0)) * std::exp(-sig);
+        res->ess = T[3] > 0 ? z * z / T[3] : 0.0;
+        res->n_evals = T[4];
+        for (int r = 0; r < nx_; ++r) {
+            res->C[r] = T[5 + r] / z;
+            res->C_err[r] = std::sqrt(std::max(T[5 + nx_ + r], 0.0)) / std::fabs(z);
+        }
+        return BFI_OK;
+    }
+    const double *e() const { return h_e_; }
+    const int32_t *best() const { return h_best_; }
+    const double *gain() const { return h_gain_; }
+
+private:
+    bfi_status events()
+    {
+        if (!ev_f0_)
+            for (hipEvent_t *ev : {&ev_f0_, &ev_f1_, &ev_a0_, &ev_a1_})
+                BFI_HIP(hipEventCreate(ev));
+        return BFI_OK;
+    }
+    bfi_context *ctx_;
+    int nx_, d_, rec_len_, split_len_;
+    size_t cap_ = 0;  // leaves
+    double *rec_ = nullptr, *split_ = nullptr, *base_ = nullptr, *vol_ = nullptr;
+    double *e_d_ = nullptr, *gain_d_ = nullptr, *scratch_ = nullptr, *totals_d_ = nullptr;
+    int32_t *best_d_ = nullptr;
+    FoldEntry *fold_d_ = nullptr, *h_fold_ = nullptr;
+    size_t cap_scratch_ = 0, cap_totals_ = 0, cap_dfold_ = 0, cap_hfold_ = 0;
+    double *h_e_ = nullptr, *h_gain_ = nullptr, *h_totals_ = nullptr;
+    int32_t *h_best_ = nullptr;
+    size_t cap_he_ = 0, cap_hg_ = 0, cap_hb_ = 0, cap_htotals_ = 0;
+    hipEvent_t ev_f0_ = nullptr, ev_f1_ = nullptr, ev_a0_ = nullptr, ev_a1_ = nullptr;
+    bool folded_ = false;
 };
 
-// The record of all of an entry's samples from the records of its two parts
-// (either may be absent).
-void combine_parts(double *R, const double *with, const double *plain, int rec_len,
-                   const std::vector<int> &first, const std::vector<int> &second)
-{
-    if (with)
-        std::copy(with, with + rec_len, R);
-    else
-        std::fill(R, R + rec_len, 0.0);
-    if (plain)
-        merge_record(R, plain, rec_len, first, second);
-}
-
-// Copy len values, or zeros when src is absent.
-void copy_or_zero(double *dst, const double *src, int len)
-{
-    if (src)
-        std::copy(src, src + len, dst);
-    else
-        std::fill(dst, dst + len, 0.0);
-}
+// The resident evaluators of a run: the kernel variant with split statistics
+// and the plain kernel, each with its buffers and captured graph kept from
+// round to round (records left in device memory for the fold), and a plain one
+// for holdout checks, whose records come back to the host.
+struct Evaluators {
+    ResidentEval with, without, holdout;
+    bool holdout_ready = false;
+    double device_ms = 0.0;  // device time of every list, fold and analysis so far
+};
 
 constexpr size_t kGrain = 2048;  // entries per chunk of the parallel host loops
 
-// Evaluate a work list on the device.  The samples below index `split_samples`
-// of each stream (all of them when 0) go through the kernel variant with split
-// statistics, the rest through the plain kernel.  Entry w's results go to
-// sink(w, with, split, plain), called in parallel over the entries: the record
-// and the split statistics of its samples below split_samples and the record of
-// the rest, each NULL if the entry has no such samples, read where the replays
-// left them (pinned host memory, valid until the next list).
-template <class Sink>
-bfi_status eval_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, const SubList &work,
-                     uint64_t split_samples, Sink &&sink)
-{
-    const int d = lat.nx * lat.nt, rec_len = BFI_PARTIAL_LEN(lat.nx), split_len = BFI_SPLIT_LEN(d);
-    const size_t count = work.size();
-    std::optional<TraceRange> stage_range(std::in_place, "adaptive: stage");
-    // entry w's covered part [offset, min(end, P)) goes to the first list at
-    // wpos[w], the rest to the second at opos[w] (-1: no such part)
-    std::vector<int64_t> wpos(count, -1), opos(count, -1);
-    std::vector<uint64_t> cut(count);
+// Where a work list's entries went: entry w's samples below split_samples are
+// row wpos[w] of the split-statistics pass, the rest row opos[w] of the plain
+// pass (-1: no such samples).
+struct ListPos {
+    std::vector<int64_t> wpos, opos;
     int64_t nw = 0, no = 0;
-    for (size_t w = 0; w < count; ++w) {
-        const uint64_t off = work.offset[w], end = off + work.n[w];
-        cut[w] = split_samples == 0 ? end : std::min(std::max(split_samples, off), end);
-        if (cut[w] > off)
-            wpos[w] = nw++;
-        if (end > cut[w])
-            opos[w] = no++;
-    }
-    BFI_TRY(ev->with.stage(static_cast<size_t>(nw)));
-    BFI_TRY(ev->without.stage(static_cast<size_t>(no)));
-    parallel_range(count, kGrain, [&](size_t w) {
-        const uint64_t off = work.offset[w], end = off + work.n[w];
-        const double *lo = &work.lo[w * d], *hi = &work.hi[w * d];
-        if (wpos[w] >= 0)
-            ev->with.set(static_cast<size_t>(wpos[w]), work.id[w], off, cut[w] - off, lo, hi);
-        if (opos[w] >= 0)
-            ev->without.set(static_cast<size_t>(opos[w]), work.id[w], cut[w], end - cut[w], lo, hi);
-    });
-    stage_range.reset();
-    // both replays prepared, then queued back to back on the stream
+};
+
+// Stage a work list and queue its two passes on the context's stream: the
+// samples below index `split_samples` of each stream (all of them when 0)
+// through the kernel variant with split statistics, the rest through the
+// plain kernel.
+bfi_status launch_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, const SubList &work,
+                       uint64_t split_samples, ListPos *pos)
+{
+    const int d = lat.nx * lat.nt;
+    const size_t count = work.size();
     {
-        TraceRange tr("adaptive: prepare and launch");
-        if (nw > 0)
-            BFI_TRY(ev->with.prepare(seed));
-        if (no > 0)
-            BFI_TRY(ev->without.prepare(seed));
-        if (nw > 0)
-            BFI_TRY(ev->with.launch());
-        if (no > 0)
-            BFI_TRY(ev->without.launch());
+        TraceRange tr("adaptive: stage");
+        pos->wpos.assign(count, -1);
+        pos->opos.assign(count, -1);
+        std::vector<uint64_t> cut(count);
+        int64_t nw = 0, no = 0;
+        for (size_t w = 0; w < count; ++w) {
+            const uint64_t off = work.offset[w], end = off + work.n[w];
+            cut[w] = split_samples == 0 ? end : std::min(std::max(split_samples, off), end);
+            if (cut[w] > off)
+                pos->wpos[w] = nw++;
+            if (end > cut[w])
+                pos->opos[w] = no++;
+        }
+        pos->nw = nw;
+        pos->no = no;
+        BFI_TRY(ev->with.stage(static_cast<size_t>(nw)));
+        BFI_TRY(ev->without.stage(static_cast<size_t>(no)));
+        parallel_range(count, kGrain, [&](size_t w) {
+            const uint64_t off = work.offset[w], end = off + work.n[w];
+            const double *lo = &work.lo[w * d], *hi = &work.hi[w * d];
+            if (pos->wpos[w] >= 0)
+                ev->with.set(static_cast<size_t>(pos->wpos[w]), work.id[w], off, cut[w] - off, lo,
+                             hi);
+            if (pos->opos[w] >= 0)
+                ev->without.set(static_cast<size_t>(pos->opos[w]), work.id[w], cut[w],
+                                end - cut[w], lo, hi);
+        });
     }
-    if (nw > 0) {
+    // both replays prepared, then queued back to back on the stream
+    TraceRange tr("adaptive: prepare and launch");
+    if (pos->nw > 0)
+        BFI_TRY(ev->with.prepare(seed));
+    if (pos->no > 0)
+        BFI_TRY(ev->without.prepare(seed));
+    if (pos->nw > 0)
+        BFI_TRY(ev->with.launch());
+    if (pos->no > 0)
+        BFI_TRY(ev->without.launch());
+    return BFI_OK;
+}
+
+// Wait for a list's passes (their replay times go to device_ms).
+bfi_status finish_list(Evaluators *ev, const ListPos &pos)
+{
+    if (pos.nw > 0) {
         TraceRange tr("adaptive: samples with split statistics");
         double ms = 0.0;
         BFI_TRY(ev->with.finish(nullptr, nullptr, &ms));
         ev->device_ms += ms;
     }
-    if (no > 0) {
+    if (pos.no > 0) {
         TraceRange tr("adaptive: samples through the plain kernel");
         double ms = 0.0;
         BFI_TRY(ev->without.finish(nullptr, nullptr, &ms));
         ev->device_ms += ms;
     }
-    const double *r_with = ev->with.records(), *sp_with = ev->with.split_records(),
-                 *r_without = ev->without.records();
-    TraceRange tr("adaptive: take the records");
-    parallel_range(count, kGrain, [&](size_t w) {
-        const size_t i = static_cast<size_t>(wpos[w]), o = static_cast<size_t>(opos[w]);
-        sink(w, wpos[w] >= 0 ? &r_with[i * rec_len] : nullptr,
-             wpos[w] >= 0 ? &sp_with[i * split_len] : nullptr,
-             opos[w] >= 0 ? &r_without[o * rec_len] : nullptr);
-    });
     return BFI_OK;
 }
 
@@ -542,13 +716,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         for (int k = 0; k < d; ++k)
             if (!std::isfinite(box_lo[k]) || !std::isfinite(box_hi[k]) || !(box_lo[k] < box_hi[k]))
                 return fail(BFI_EINVAL, "box dim %d: need finite lo < hi", k);
-        const int rec_len = BFI_PARTIAL_LEN(nx), split_len = BFI_SPLIT_LEN(d);
-        std::vector<int> rec_first, rec_second, split_first, split_second;
-        record_fields(nx, &rec_first, &rec_second);
-        for (int j = 0; j < d; ++j) {
-            split_first.push_back(1 + j);
-            split_second.push_back(1 + d + j);
-        }
+        const int rec_len = BFI_PARTIAL_LEN(nx);
 
         // initial uniform partition with n_min samples per leaf
         SubList init = uniform_split(d, box_lo, box_hi, cfg->split_log2, 0);
@@ -570,16 +738,24 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         Evaluators ev;
         BFI_TRY(ev.with.init(ctx, *lat, prec, true, launch));
         BFI_TRY(ev.without.init(ctx, *lat, prec, false, launch));
-        L.rec.resize(L.size() * rec_len);
-        L.split.resize(L.size() * split_len);
-        L.base.resize(L.size() * rec_len);
-        BFI_TRY(eval_list(&ev, *lat, seed, init, cfg->split_samples,
-                          [&](size_t w, const double *with, const double *sp, const double *plain) {
-                              combine_parts(&L.rec[w * rec_len], with, plain, rec_len, rec_first,
-                                            rec_second);
-                              copy_or_zero(&L.base[w * rec_len], with, rec_len);
-                              copy_or_zero(&L.split[w * split_len], sp, split_len);
-                          }));
+        ev.with.set_copy_records(false);
+        ev.without.set_copy_records(false);
+        DeviceLeaves DL(ctx, nx, d);
+        BFI_TRY(DL.reserve(L.size(), 0));
+        ListPos pos;
+        {
+            // every entry of the initial list becomes the leaf of its index
+            BFI_TRY(launch_list(&ev, *lat, seed, init, cfg->split_samples, &pos));
+            BFI_TRY(DL.stage_fold(init.size()));
+            FoldEntry *fe = DL.fold_entries();
+            parallel_range(init.size(), kGrain, [&](size_t w) {
+                fe[w] = FoldEntry{static_cast<uint32_t>(w), 1, static_cast<int32_t>(pos.wpos[w]),
+                                  static_cast<int32_t>(pos.opos[w]), L.vol[w]};
+            });
+            BFI_TRY(DL.fold(init.size(), ev.with.device_records(), ev.with.device_split_records(),
+                            ev.without.device_records()));
+            BFI_TRY(finish_list(&ev, pos));
+        }
 
         bfi_status status = BFI_OK;
         const double min_ess = cfg->min_ess > 0 ? cfg->min_ess : 100.0;
@@ -589,7 +765,6 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         double holdout_err = 0.0;
         double run_target = cfg->target_rel_err;  // tightened by failed holdout checks
         bfi_result res{};
-        std::vector<LeafAnalysis> an;
         auto report = [&](double running) {
             if (!cfg->progress)
                 return;
@@ -608,8 +783,10 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         std::vector<uint64_t> target;
         for (;;) {
             TracePhases phase("adaptive: analyse");
-            BFI_TRY(analyse(nx, d, L.size(), L.lo.data(), L.hi.data(), L.rec.data(), &an, &res,
-                            L.vol.data()));
+            BFI_TRY(DL.analyse(L.size(), &res, &ev.device_ms));
+            const double *e = DL.e();
+            const int32_t *best = DL.best();
+            const double *gain = DL.gain();
             report(rel_err(res));
             // stop check; with holdout, a failed check tightens the running target
             // and refinement goes on: the next check comes after at least one more
@@ -634,12 +811,16 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                         const uint64_t hseed =
                             seed + static_cast<uint64_t>(checks) * 0x9E3779B97F4A7C15ull;
                         std::vector<double> hrec(L.size() * rec_len);
-                        BFI_TRY(ev.without.stage(L.size()));
+                        if (!ev.holdout_ready) {
+                            BFI_TRY(ev.holdout.init(ctx, *lat, prec, false, launch));
+                            ev.holdout_ready = true;
+                        }
+                        BFI_TRY(ev.holdout.stage(L.size()));
                         parallel_range(L.size(), kGrain, [&](size_t s) {
-                            ev.without.set(s, L.id[s], 0, L.n[s], &L.lo[s * d], &L.hi[s * d]);
+                            ev.holdout.set(s, L.id[s], 0, L.n[s], &L.lo[s * d], &L.hi[s * d]);
                         });
                         double hms = 0.0;
-                        BFI_TRY(ev.without.run(hseed, hrec.data(), nullptr, &hms));
+                        BFI_TRY(ev.holdout.run(hseed, hrec.data(), nullptr, &hms));
                         ev.device_ms += hms;
                         evals += cost;
                         bfi_result hres{};
@@ -667,12 +848,14 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                 break;
             }
             phase.next("adaptive: decide and plan");
-            const SplitStats st{d, rec_len, L.split.data(), L.base.data()};
             action.resize(L.size());
+            // a leaf's action from its split choice (the device analysis made it)
+            auto act = [&](size_t s) {
+                return action_of(SplitChoice{best[s], gain[s]}, L.id[s], L.n[s], *cfg);
+            };
             std::optional<TraceRange> sub(std::in_place, "adaptive: rank and decide");
-            Ranking order(an, L.id.data());
-            const size_t examined =
-                decide(an, st, L.id.data(), L.n.data(), *cfg, action.data(), order);
+            Ranking order(e, L.size(), L.id.data());
+            const size_t examined = decide(e, L.size(), act, *cfg, action.data(), order);
             // the refined leaves in rank order (planning loops over these only)
             refined.clear();
             for (size_t i = 0; i < examined; ++i)
@@ -765,11 +948,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                     batch_lo = rank;
                     parallel_range(len, size_t(1) << 9, [&](size_t k) {
                         const size_t s = order[rank + k];
-                        batch[k] = Candidate{
-                            s,
-                            action[s] == -1 ? leaf_action(an, st, s, L.id[s], L.n[s], *cfg)
-                                            : kHasAction,
-                            L.n[s]};
+                        batch[k] = Candidate{s, action[s] == -1 ? act(s) : kHasAction, L.n[s]};
                     });
                 }
                 return batch[rank - batch_lo];
@@ -895,49 +1074,46 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             // every round)
             std::optional<TraceRange> grow_range(std::in_place, "adaptive: leaf set growth");
             dst.resize(origin.size());
-            size_t grown = L.size();
+            const size_t before = L.size();
+            size_t grown = before;
             for (size_t w = 0; w < origin.size(); ++w)
                 dst[w] = origin[w].kind == 2 ? grown++ : origin[w].leaf;
             L.id.resize(grown);
             L.n.resize(grown);
             L.lo.resize(grown * d);
             L.hi.resize(grown * d);
-            L.rec.resize(grown * rec_len);
-            L.split.resize(grown * split_len);
-            L.base.resize(grown * rec_len);
             L.vol.resize(grown);
+            BFI_TRY(DL.reserve(grown, before));
             grow_range.reset();
             phase.next("adaptive: evaluate and fold");
-            // the results go into the leaf set in place as each entry's records
-            // are read; every entry has its own destination
-            BFI_TRY(eval_list(
-                &ev, *lat, seed, work, cfg->split_samples,
-                [&](size_t w, const double *with, const double *sp, const double *plain) {
+            BFI_TRY(launch_list(&ev, *lat, seed, work, cfg->split_samples, &pos));
+            {
+                // while the device evaluates: the fold entries and the host side
+                // of the leaves (every entry has a leaf of its own)
+                TraceRange tr("adaptive: fold entries");
+                BFI_TRY(DL.stage_fold(origin.size()));
+                FoldEntry *fe = DL.fold_entries();
+                parallel_range(origin.size(), kGrain, [&](size_t w) {
                     const size_t s = dst[w];
+                    double vol = 0.0;
                     if (origin[w].kind == 0) {
-                        double R[BFI_PARTIAL_LEN(BFI_MAX_NX)];
-                        combine_parts(R, with, plain, rec_len, rec_first, rec_second);
-                        merge_shifted(&L.rec[s * rec_len], R, 1, rec_first, rec_second, 0);
-                        if (with && with[0] > 0) {
-                            // the continuation still lies below split_samples
-                            merge_shifted(&L.split[s * split_len], sp, 0, split_first,
-                                          split_second, -1);
-                            merge_shifted(&L.base[s * rec_len], with, 1, rec_first, rec_second,
-                                          0);
-                        }
                         L.n[s] = target[s];
-                        return;
+                    } else {
+                        L.id[s] = work.id[w];
+                        L.n[s] = work.n[w];
+                        std::copy(&work.lo[w * d], &work.lo[w * d] + d, &L.lo[s * d]);
+                        std::copy(&work.hi[w * d], &work.hi[w * d] + d, &L.hi[s * d]);
+                        vol = box_volume(&L.lo[s * d], &L.hi[s * d], d);
+                        L.vol[s] = vol;
                     }
-                    L.id[s] = work.id[w];
-                    L.n[s] = work.n[w];
-                    std::copy(&work.lo[w * d], &work.lo[w * d] + d, &L.lo[s * d]);
-                    std::copy(&work.hi[w * d], &work.hi[w * d] + d, &L.hi[s * d]);
-                    L.vol[s] = box_volume(&L.lo[s * d], &L.hi[s * d], d);
-                    combine_parts(&L.rec[s * rec_len], with, plain, rec_len, rec_first,
-                                  rec_second);
-                    copy_or_zero(&L.split[s * split_len], sp, split_len);
-                    copy_or_zero(&L.base[s * rec_len], with, rec_len);
-                }));
+                    fe[w] = FoldEntry{static_cast<uint32_t>(s), origin[w].kind,
+                                      static_cast<int32_t>(pos.wpos[w]),
+                                      static_cast<int32_t>(pos.opos[w]), vol};
+                });
+            }
+            BFI_TRY(DL.fold(origin.size(), ev.with.device_records(), ev.with.device_split_records(),
+                            ev.without.device_records()));
+            BFI_TRY(finish_list(&ev, pos));
             evals += cost;
             ++rounds;
         }
@@ -996,12 +1172,17 @@ bfi_status bfi_adaptive_decide(const bfi_lattice *lat, const bfi_subvolumes *lea
         if (!leaves->id || !leaves->lo || !leaves->hi || !leaves->n)
             return fail(BFI_EINVAL, "leaf arrays must be non-NULL");
         const int d = lat->nx * lat->nt;
-        std::vector<LeafAnalysis> an;
+        std::vector<double> e;
         bfi_result res;
-        BFI_TRY(analyse(lat->nx, d, leaves->count, leaves->lo, leaves->hi, partials, &an, &res));
+        BFI_TRY(analyse(lat->nx, d, leaves->count, leaves->lo, leaves->hi, partials, &e, &res));
         const SplitStats st{d, BFI_PARTIAL_LEN(lat->nx), split, split_base ? split_base : partials};
-        Ranking order(an, leaves->id);
-        decide(an, st, leaves->id, leaves->n, *cfg, action, order);
+        Ranking order(e.data(), e.size(), leaves->id);
+        decide(
+            e.data(), e.size(),
+            [&](size_t s) {
+                return action_of(split_choice(st, s), leaves->id[s], leaves->n[s], *cfg);
+            },
+            *cfg, action, order);
         return BFI_OK;
     });
 }

@@ -149,6 +149,57 @@ struct BuildArgs {
     int32_t d, rec_len;
 };
 
+// Leaf records of an adaptive run kept in device memory (leaf_kernels.hip).
+// Record layouts are those of bfi_eval: per leaf a partial record of the
+// Burgers layout (4 + 3 nx doubles: count, shift, sums), split statistics
+// (1 + 2d: shift, upper-half sums) and the record of the samples the split
+// statistics cover, plus the leaf's volume.
+//
+// Fold: a round's entries into the leaves.  Entry e's records are the rows
+// wpos (split-statistics pass: record and split statistics) and opos (plain
+// pass), -1 where it has no samples there; kind 0 merges them into leaf dst
+// (a doubled leaf continuing its stream), kinds 1 and 2 write leaf dst (the
+// children of a split leaf; vol is the child's volume).
+struct FoldEntry {
+    uint32_t dst;
+    int32_t kind;
+    int32_t wpos, opos;
+    double vol;
+};
+struct FoldArgs {
+    const FoldEntry *entries;
+    uint32_t count;
+    const double *with_rec, *with_split, *plain_rec;
+    double *leaf_rec, *leaf_split, *leaf_base, *leaf_vol;
+    int32_t nx, d;
+};
+hipError_t launch_fold(const FoldArgs &args, hipStream_t stream);
+
+// Analysis of every leaf for the adaptive driver, as bfi_finalize's two passes
+// over the records and the driver's split choice: the common shift (smallest
+// sigma), the totals of the first pass (Z, Var Z, sum of squared weights,
+// samples, N(r)), then per leaf its contribution e to the variance of C
+// (clamped at 0, NaN as 0), the dimension j* minimising sigma_lower +
+// sigma_upper of its split statistics and the gain (sigma_L + sigma_U)(j*) /
+// (2 sigma), and the totals of the second pass (the variance of C(r) before
+// the division by Z^2).  Per-block sums in a fixed tree order, the blocks'
+// sums in block order with Neumaier compensation: the result does not depend
+// on timing.  out_totals (host-visible) gets [sigma, 4 + nx first-pass totals,
+// nx second-pass totals]; e, best and gain one value per leaf.
+constexpr int kAnalysisBlock = 1024;
+constexpr int kMaxAnalysisNx = 32;
+struct LeafAnalysisArgs {
+    const double *rec, *split, *base, *vol;
+    uint32_t count;
+    int32_t nx, d;
+    double *scratch;     // analysis_scratch_doubles(count, nx) doubles
+    double *out_totals;  // 1 + 4 + 2 nx doubles
+    double *e, *gain;    // count each
+    int32_t *best;       // count
+};
+size_t analysis_scratch_doubles(uint32_t count, int nx);
+hipError_t launch_leaf_analysis(const LeafAnalysisArgs &args, hipStream_t stream);
+
 // Shape-independent kernels (common_kernels.hip).
 hipError_t launch_build_items(const BuildArgs &args, hipStream_t stream);
 hipError_t launch_reset_head(uint32_t *head, hipStream_t stream);

@@ -295,6 +295,9 @@ bfi_status ResidentEval::finish(double *rec_out, double *split_out, double *devi
         BFI_HIP(hipEventElapsedTime(&ms, ev_start_, ev_stop_));
         *device_ms = ms;
     }
+    if (rec_out || split_out)
+        if (!copy_records_)
+            return fail(BFI_EINVAL, "records kept on the device");
     if (rec_out)
         std::memcpy(rec_out, h_rec_, nsub * rec_len_ * sizeof(double));
     if (split_ && split_out)
@@ -337,6 +340,8 @@ bfi_status ResidentEval::enqueue(size_t nsub, uint64_t nitems, hipStream_t st)
     m.nx = lat_.nx;
     m.d = d_;
     BFI_HIP(launch_merge(m, st));
+    if (!copy_records_)
+        return BFI_OK;
     BFI_HIP(hipMemcpyAsync(h_rec_, d_sub_rec_, nsub * rec_len_ * 8, hipMemcpyDeviceToHost, st));
     if (split_)
         BFI_HIP(hipMemcpyAsync(h_split_, d_sub_split_, nsub * split_len_ * 8,

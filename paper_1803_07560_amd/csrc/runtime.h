@@ -201,6 +201,12 @@ public:
     // copy), valid until the next prepare
     const double *records() const { return h_rec_; }
     const double *split_records() const { return h_split_; }
+    // whether a replay copies its records to the host (default yes); without,
+    // they stay in device memory for a consumer queued after the replay on the
+    // context's stream, valid until the next prepare
+    void set_copy_records(bool on) { copy_records_ = on; }
+    const double *device_records() const { return d_sub_rec_; }
+    const double *device_split_records() const { return d_sub_split_; }
     int instantiations() const { return instantiations_; }
     int updates() const { return updates_; }
 
@@ -211,7 +217,7 @@ private:
     bfi_context *ctx_ = nullptr;
     bfi_lattice lat_{};
     int prec_ = 0, d_ = 0, rec_len_ = 0, split_len_ = 0;
-    bool split_ = false;
+    bool split_ = false, copy_records_ = true;
     bfi_launch launch_{};
     uint64_t chunk_ = 0, resident_blocks_ = 0;
     size_t count_ = 0;

@@ -31,7 +31,8 @@ def test_host_entry_points_under_asan_ubsan(tmp_path):
     device = sorted(glob.glob(os.path.join(BUILD, "shape_*.o")) +
                     glob.glob(os.path.join(BUILD, "is_*.o")) +
                     glob.glob(os.path.join(BUILD, "sph_*.o")) +
-                    [os.path.join(BUILD, "common_kernels.o"), os.path.join(BUILD, "noalloc.o")])
+                    [os.path.join(BUILD, "common_kernels.o"), os.path.join(BUILD, "leaf_kernels.o"),
+                     os.path.join(BUILD, "noalloc.o")])
     if not all(os.path.exists(p) for p in device) or len(device) < 3:
         pytest.skip("library not built")
     common = ["-O1", "-g", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
