@@ -294,7 +294,7 @@ def serve_leg(bfi, ctx, seconds, rate, warmup_s=1.0, max_samples_per_thread=0, a
 
 
 def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0), observables=("anchor", "averaged"),
-                 forms=("fp32",), holdout_forms=(), confirm=False, target=1e-3):
+                 forms=("fp32",), holdout_forms=(), confirm=False, target=1e-3, seeds=(1,)):
     """10x2 lattice, D = 1, box [-4,4]^20: error-driven bisection from the
     1024-subvolume partition at 2^10 samples per leaf, per-leaf counts in
     [2^10, 2^22], target max_r sigma_C(r)/|C(0)| <= 1e-3 with an effective
@@ -311,7 +311,7 @@ def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0), observables=("ancho
     has seen): `holdout_rel_err` is that pass's max_r sigma_C(r)/|C(0)|, free of
     the selection that makes the stopping estimate optimistic."""
     out = []
-    for form, observable, nu in itertools.product(forms, observables, nus):
+    for form, observable, nu, seed in itertools.product(forms, observables, nus, seeds):
         cfg = bfi.adaptive_config(target_rel_err=target, max_evals=1 << budget_log2,
                                   n_min=1 << 10, n_max=1 << 22, split_log2=10,
                                   max_rounds=128, refine_fraction=0.5,
@@ -319,14 +319,14 @@ def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0), observables=("ancho
                                   split_samples=1 << 16, holdout=confirm)
         t0 = time.perf_counter()
         r = bfi.bfi_integrate_adaptive(ctx, bfi.lattice(10, 2, nu=nu, observable=observable),
-                                       form, 1, -4.0, 4.0, cfg, leaf_capacity=1 << 22)
+                                       form, seed, -4.0, 4.0, cfg, leaf_capacity=1 << 22)
         dt = time.perf_counter() - t0
-        print(f"bench: adaptive {form} {observable} nu={nu} target {target:g}: {r['status']} "
+        print(f"bench: adaptive {form} {observable} nu={nu} seed {seed} target {target:g}: {r['status']} "
               f"rel_err {r['rel_err']:.3g} (holdout {r['holdout_rel_err']:.3g}) in {dt:.2f} s",
               file=sys.stderr, flush=True)
         part = r["partition"]
         n = part.n
-        rec = {"form": form, "observable": observable, "nu": nu, "target": target,
+        rec = {"form": form, "observable": observable, "nu": nu, "seed": seed, "target": target,
                "status": r["status"],
                "stop": "holdout-confirmed" if confirm else "running estimate",
                "rel_err": r["rel_err"], "ess": r["ess"], "rounds": r["rounds"],
@@ -341,7 +341,7 @@ def adaptive_leg(bfi, ctx, budget_log2, nus=(0.1, 0.5, 1.0), observables=("ancho
         if form in holdout_forms:
             lat = bfi.lattice(10, 2, nu=nu, observable=observable)
             fresh = bfi.Subvolumes(part.ids, part.lo, part.hi, n, n, lat.d)
-            h = bfi.bfi_finalize(lat, fresh, bfi.bfi_eval(ctx, lat, form, 1, fresh))
+            h = bfi.bfi_finalize(lat, fresh, bfi.bfi_eval(ctx, lat, form, seed, fresh))
             rec["holdout_rel_err"] = float(np.max(h["C_err"]) / abs(h["C"][0]))
             rec["holdout_ess"] = float(h["ess"])
             rec["holdout_C_dev"] = float(np.max(np.abs(h["C"] - r["C"])) / abs(r["C"][0]))
@@ -654,14 +654,16 @@ def main():
         print(f"bench: adaptive 10x2 to target, averaged observable, budget "
               f"2^{args.adaptive_target_budget_log2} per nu", file=sys.stderr, flush=True)
         # the workload's 1e-3 target, holdout-confirmed, FP32 form; and 1e-2 (which
-        # a holdout pass confirms within the budget) in both forms, for the time
-        # each form takes to the same confirmed error
+        # a holdout pass confirms within the budget) in both forms and two seeds,
+        # for the time each form takes to the same confirmed error (the rounds a
+        # run needs depend on when a holdout check first passes: one seed per nu
+        # measures that draw more than the forms)
         adaptive_target = adaptive_leg(bfi, ctx, args.adaptive_target_budget_log2,
                                        observables=("averaged",), forms=("fp32",),
                                        confirm=True, target=1e-3)
         adaptive_target += adaptive_leg(bfi, ctx, args.adaptive_target_budget_log2,
                                         observables=("averaged",), forms=("fp32", "fp64"),
-                                        confirm=True, target=1e-2)
+                                        confirm=True, target=1e-2, seeds=(1, 2))
     adaptive_scale = None
     if args.adaptive_scale_budget_log2 > 0 and w.name == "burgers10x2":
         print(f"bench: adaptive scale run, budget 2^{args.adaptive_scale_budget_log2}",
@@ -760,16 +762,22 @@ def main():
         line["adaptive"] = adaptive
     if adaptive_target is not None:
         line["adaptive_to_target"] = adaptive_target
-        # time to the same holdout-confirmed error in both forms, per nu: FP64
-        # seconds / FP32 seconds, only where both runs were confirmed
+        # time to the same holdout-confirmed error in both forms: FP64 seconds /
+        # FP32 seconds over every (nu, seed) that both forms confirmed, in total
+        # and per run
         speedup = {}
         for target in sorted({a["target"] for a in adaptive_target}):
-            secs = {(a["form"], a["nu"]): a["seconds"] for a in adaptive_target
+            secs = {(a["form"], a["nu"], a["seed"]): a["seconds"] for a in adaptive_target
                     if a["target"] == target and a["status"] == "BFI_OK" and a.get("holdout_used")}
-            per_nu = {str(nu): secs[("fp64", nu)] / secs[("fp32", nu)]
-                      for (form, nu) in secs if form == "fp32" and ("fp64", nu) in secs}
-            if per_nu:
-                speedup[f"{target:g}"] = per_nu
+            both = sorted((nu, sd) for (form, nu, sd) in secs
+                          if form == "fp32" and ("fp64", nu, sd) in secs)
+            if both:
+                t32 = sum(secs[("fp32", nu, sd)] for nu, sd in both)
+                t64 = sum(secs[("fp64", nu, sd)] for nu, sd in both)
+                speedup[f"{target:g}"] = {
+                    "total": t64 / t32, "runs": len(both),
+                    "per_run": {f"nu={nu} seed={sd}": secs[("fp64", nu, sd)] / secs[("fp32", nu, sd)]
+                                for nu, sd in both}}
         line["fp32_speedup_at_target"] = speedup or None
     if adaptive_scale is not None:
         line["adaptive_scale"] = adaptive_scale
