@@ -745,8 +745,8 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         ListPos pos;
         {
             // every entry of the initial list becomes the leaf of its index
-            BFI_TRY(launch_list(&ev, *lat, seed, init, cfg->split_samples, &pos));
             BFI_TRY(DL.stage_fold(init.size()));
+            BFI_TRY(launch_list(&ev, *lat, seed, init, cfg->split_samples, &pos));
             FoldEntry *fe = DL.fold_entries();
             parallel_range(init.size(), kGrain, [&](size_t w) {
                 fe[w] = FoldEntry{static_cast<uint32_t>(w), 1, static_cast<int32_t>(pos.wpos[w]),
@@ -1086,12 +1086,14 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             BFI_TRY(DL.reserve(grown, before));
             grow_range.reset();
             phase.next("adaptive: evaluate and fold");
+            // pinned room for the fold entries first: freeing a pinned buffer
+            // waits for the device, which must not happen behind the passes
+            BFI_TRY(DL.stage_fold(origin.size()));
             BFI_TRY(launch_list(&ev, *lat, seed, work, cfg->split_samples, &pos));
             {
                 // while the device evaluates: the fold entries and the host side
                 // of the leaves (every entry has a leaf of its own)
                 TraceRange tr("adaptive: fold entries");
-                BFI_TRY(DL.stage_fold(origin.size()));
                 FoldEntry *fe = DL.fold_entries();
                 parallel_range(origin.size(), kGrain, [&](size_t w) {
                     const size_t s = dst[w];
