@@ -78,11 +78,17 @@ def test_adaptive_10x2(bfi, ctx, nu):
     part = out["partition"]
     check_partition(part, 20, 4.0)
     assert part.n.min() >= 1 << 10 and part.n.max() <= 1 << 22
-    # one-pass re-evaluation of the final partition == merged round records
+    # one-pass re-evaluation of the final partition, finalized on the host ==
+    # the round records merged and analysed on the device (the second pass's
+    # error bars and the effective sample size too)
     again = bfi.bfi_eval(ctx, lat, "fp64", 1, part)
     res = bfi.bfi_finalize(lat, part, again)
     assert res["log_Z"] == pytest.approx(out["log_Z"], abs=1e-11)
     assert np.all(np.abs(res["C"] - out["C"]) <= 1e-9 * abs(res["C"][0]))
+    np.testing.assert_allclose(out["C_err"], res["C_err"], rtol=1e-8)
+    assert out["Z_err"] == pytest.approx(res["Z_err"], rel=1e-9)
+    assert out["ess"] == pytest.approx(res["ess"], rel=1e-9)
+    assert out["n_evals"] == res["n_evals"] == part.n.sum()
     # sampled leaves against the oracle
     pick = np.unique(np.linspace(0, len(part) - 1, 6).astype(int))
     ids, lo, hi, n = part.ids[pick], part.lo[pick], part.hi[pick], part.n[pick]
