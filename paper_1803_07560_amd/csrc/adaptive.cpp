@@ -24,7 +24,10 @@
 //      extra samples go where the variance is.
 // Rounds repeat until max_r sigma_C(r) / |C(0)| <= target, the evaluation budget
 // or the round limit is reached.  Every round's work list (uneven sample counts)
-// is drained by the persistent kernel through the device queue.
+// is drained by the persistent kernel through the device queue; the leaves'
+// records stay in device memory, where each round's records are folded into
+// them and step 1 runs (the host takes the decisions of steps 2-5 from each
+// leaf's e_s, j* and gain).
 //
 // The running estimate is judged on the samples that steered the refinement:
 // leaves whose samples happened to miss the rare large weights look quiet and
