@@ -870,23 +870,40 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             // planned count of a refined leaf at scale factor f (within n_max):
             // children clamp(n, n_min, n_max) each, doubled leaves 2n, times f
             target.resize(L.size());  // new per-leaf (or per-child) count, refined leaves
-            // planned count of a leaf with action `act` and n samples at factor f
-            auto target_of = [&](int32_t act, uint64_t n, uint64_t f) {
+            // planned count of a leaf with action `act` and n samples at factor
+            // f = 2^fs (a power of two: shifts, not divisions)
+            auto target_of = [&](int32_t act, uint64_t n, unsigned fs) {
                 const uint64_t base =
                     act == 0 ? 2 * n : std::min(std::max(n, cfg->n_min), cfg->n_max);
                 const uint64_t cap = std::max(cfg->n_max, base);
-                return base > cap / f ? cap : std::max(base, std::min(base * f, cap));
+                return base > (cap >> fs) ? cap : std::max(base, std::min(base << fs, cap));
             };
             auto cost_of = [](int32_t act, uint64_t n, uint64_t t) {
                 return act == 0 ? t - n : 2 * t;
             };
             // whether the count would still grow at 2f
-            auto grows_of = [&](int32_t act, uint64_t n, uint64_t f, uint64_t t) {
-                return f <= std::numeric_limits<uint64_t>::max() / 2 &&
-                       target_of(act, n, 2 * f) > t;
+            auto grows_of = [&](int32_t act, uint64_t n, unsigned fs, uint64_t t) {
+                return fs < 63 && target_of(act, n, fs + 1) > t;
             };
-            uint64_t f = 1, planned = 0;
+            unsigned fs = 0;
+            uint64_t planned = 0;
             size_t growable = 0;
+            // actions and counts of the leaves the work floor takes, in the order
+            // taken (refined[pending + i]); written to the leaves' arrays in parallel
+            // before they are read
+            std::vector<int32_t> pend_act;
+            std::vector<uint64_t> pend_target;
+            size_t pending = refined.size();
+            auto flush = [&]() {
+                parallel_range(pend_act.size(), kGrain, [&](size_t i) {
+                    const size_t s = refined[pending + i];
+                    action[s] = pend_act[i];
+                    target[s] = pend_target[i];
+                });
+                pending = refined.size();
+                pend_act.clear();
+                pend_target.clear();
+            };
             // every refined leaf at factor f: per-chunk integer sums, so the
             // totals do not depend on the chunking
             std::vector<uint64_t> chunk_planned;
@@ -900,10 +917,10 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                     size_t g = 0;
                     for (size_t i = c * kGrain; i < std::min(nr, (c + 1) * kGrain); ++i) {
                         const size_t s = refined[i];
-                        const uint64_t t = target_of(action[s], L.n[s], f);
+                        const uint64_t t = target_of(action[s], L.n[s], fs);
                         target[s] = t;
                         p += cost_of(action[s], L.n[s], t);
-                        g += grows_of(action[s], L.n[s], f, t);
+                        g += grows_of(action[s], L.n[s], fs, t);
                     }
                     chunk_planned[c] = p;
                     chunk_growable[c] = g;
@@ -958,33 +975,30 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             };
             while (cfg->round_evals > 0 && planned < cfg->round_evals) {
                 if (growable > 0) {
-                    f *= 2;
+                    ++fs;
+                    flush();
                     plan_all();
                     continue;
                 }
-                // only the leaf taken up here gets an action in this loop, so a
-                // batch's view of which leaves have one stays current
+                // the scan only moves forward and a batch holds ranks from the
+                // scan's position on, so its view of which leaves have an action
+                // (those decide() gave one) stays current
                 Candidate c{0, kHasAction, 0};
                 while (next_leaf < order.size() && (c = candidate(next_leaf)).act == kHasAction)
                     ++next_leaf;
                 if (next_leaf == order.size())
                     break;
                 ++next_leaf;
-                const size_t s = c.leaf;
-                if (c.act < 0) {
-                    action[s] = -2;  // neither split nor doubling possible: skip it
-                    continue;
-                }
-                action[s] = c.act;
-                refined.push_back(s);
-                const uint64_t t = target_of(c.act, c.n, f);
-                target[s] = t;
+                if (c.act < 0)
+                    continue;  // neither split nor doubling possible: skip it
+                refined.push_back(c.leaf);
+                const uint64_t t = target_of(c.act, c.n, fs);
+                pend_act.push_back(c.act);
+                pend_target.push_back(t);
                 planned += cost_of(c.act, c.n, t);
-                growable += grows_of(c.act, c.n, f, t);
+                growable += grows_of(c.act, c.n, fs, t);
             }
-            for (size_t i = 0; i < order.sorted(); ++i)
-                if (action[order[i]] == -2)
-                    action[order[i]] = -1;
+            flush();
             sub.reset();
             sub.emplace("adaptive: budget trim");
             // trim to the evaluation budget in priority order (every refined leaf
