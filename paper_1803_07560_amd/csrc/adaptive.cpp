@@ -648,6 +648,8 @@ bfi_status launch_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, co
         }
         pos->nw = nw;
         pos->no = no;
+        if (nw > std::numeric_limits<int32_t>::max() || no > std::numeric_limits<int32_t>::max())
+            return fail(BFI_EINVAL, "more than 2^31 entries in one pass");
         BFI_TRY(ev->with.stage(static_cast<size_t>(nw)));
         BFI_TRY(ev->without.stage(static_cast<size_t>(no)));
         parallel_range(count, kGrain, [&](size_t w) {
