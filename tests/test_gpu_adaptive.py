@@ -47,6 +47,34 @@ def test_adaptive_small_lattice_replays_on_oracle(bfi, ctx):
     assert out["rel_err"] == pytest.approx(rel, rel=1e-6)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_split_statistics_over_every_sample(bfi, ctx, prec):
+    """split_samples = 0: every entry of every round (doubled leaves' continuations
+    too) runs through the kernel variant with split statistics and the plain pass
+    is empty; a cut beyond every leaf's count is the same run, bit for bit; the
+    final partition replays on the oracle."""
+    nx, nt, B, nu = 3, 2, 2.0, 0.7
+    kw = dict(target_rel_err=1e-9, max_evals=1 << 22, n_min=512, n_max=1 << 14, split_log2=2,
+              max_rounds=10, refine_fraction=0.5)
+    lat = bfi.lattice(nx, nt, nu=nu)
+    a = bfi.bfi_integrate_adaptive(ctx, lat, prec, 3, -B, B,
+                                   bfi.adaptive_config(split_samples=0, **kw))
+    b = bfi.bfi_integrate_adaptive(ctx, lat, prec, 3, -B, B,
+                                   bfi.adaptive_config(split_samples=1 << 40, **kw))
+    assert a["rounds"] == b["rounds"] >= 3 and a["leaves"] == b["leaves"]
+    pa, pb = a["partition"], b["partition"]
+    assert np.array_equal(pa.ids, pb.ids) and np.array_equal(pa.n, pb.n)
+    assert a["Z"] == b["Z"] and np.array_equal(a["C"], b["C"])
+    assert np.array_equal(a["C_err"], b["C_err"])
+    check_partition(pa, nx * nt, B)
+    assert len(set(pa.n.tolist())) > 1  # doubled leaves: continuations with statistics
+    sums = oracle.sums(oracle.lattice(nx, nt, nu=nu), 3, pa.ids, pa.lo, pa.hi, pa.n, pa.offset)
+    ref = oracle.finalize(nx, nx * nt, pa.lo, pa.hi, sums)
+    tol = 1e-6 if prec == "fp64" else 1e-4
+    assert abs(a["Z"] - ref["Z"]) <= tol * ref["Z"]
+    assert np.all(np.abs(a["C"] - ref["C"]) <= tol * abs(ref["C"][0]))
+
+
 def test_adaptive_reaches_an_easy_target(bfi, ctx):
     """Flat weights (D huge): the error of C(0) falls as 1/sqrt(n), so a 2e-2
     target is reached well inside the budget."""
