@@ -178,6 +178,14 @@ public:
     }
     // ranks read so far (every rank below it is final)
     size_t sorted() const { return keys_.size(); }
+    // make ranks [0, n) readable in one extension (reading them one at a time
+    // grows the sorted part in doublings)
+    void gather(size_t n)
+    {
+        n = std::min(n, n_);
+        if (n > keys_.size())
+            extend(n);
+    }
 
 private:
     static constexpr size_t kBuckets = size_t(1) << 15;  // sign bit 0: 15 top bits
@@ -964,8 +972,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                                               : 1;
                     const size_t len = static_cast<size_t>(std::min<uint64_t>(
                         order.size() - rank, std::max<uint64_t>(4096, need)));
-                    for (size_t k = 0; k < len; ++k)
-                        (void)order[rank + k];  // gather the ranks first (serial)
+                    order.gather(rank + len);  // the ranks first (one extension)
                     batch.resize(len);
                     batch_lo = rank;
                     parallel_range(len, size_t(1) << 9, [&](size_t k) {
