@@ -547,17 +547,19 @@ __global__ void __launch_bounds__(BLOCK)
                 const float w2s = ws * ws;
 #pragma unroll
                 for (int kk = 0; kk < D; ++kk) {
-                    const bool up = (upper >> kk) & 1u;
-                    sacc[kk] += up ? w32 : 0.0f;
-                    sacc[D + kk] += up ? w2s : 0.0f;
+                    // the half as 0 or 1: one fused multiply-add adds w or
+                    // exactly nothing (finite w), as a select and an add would
+                    const float up = static_cast<float>((upper >> kk) & 1u);
+                    sacc[kk] = __builtin_fmaf(up, w32, sacc[kk]);
+                    sacc[D + kk] = __builtin_fmaf(up, w2s, sacc[D + kk]);
                 }
             } else if constexpr (SPLIT) {
                 const double w2 = w * w;
 #pragma unroll
                 for (int kk = 0; kk < D; ++kk) {
-                    const bool up = (upper >> kk) & 1u;
-                    acc[F::kMain + kk] += up ? w : 0.0;
-                    acc[F::kMain + D + kk] += up ? w2 : 0.0;
+                    const double up = static_cast<double>((upper >> kk) & 1u);
+                    acc[F::kMain + kk] = __fma_rn(up, w, acc[F::kMain + kk]);
+                    acc[F::kMain + D + kk] = __fma_rn(up, w2, acc[F::kMain + D + kk]);
                 }
             }
         }
