@@ -642,18 +642,37 @@ bfi_status launch_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, co
     const size_t count = work.size();
     {
         TraceRange tr("adaptive: stage");
-        pos->wpos.assign(count, -1);
-        pos->opos.assign(count, -1);
+        pos->wpos.resize(count);
+        pos->opos.resize(count);
         std::vector<uint64_t> cut(count);
-        int64_t nw = 0, no = 0;
-        for (size_t w = 0; w < count; ++w) {
-            const uint64_t off = work.offset[w], end = off + work.n[w];
-            cut[w] = split_samples == 0 ? end : std::min(std::max(split_samples, off), end);
-            if (cut[w] > off)
-                pos->wpos[w] = nw++;
-            if (end > cut[w])
-                pos->opos[w] = no++;
+        // rows in list order: each chunk counts its entries of either pass,
+        // then numbers them from the chunk's start
+        const size_t nch = (count + kGrain - 1) / kGrain;
+        std::vector<int64_t> cw(nch + 1, 0), co(nch + 1, 0);
+        for_chunks(nch, [&](size_t c) {
+            int64_t kw = 0, ko = 0;
+            for (size_t w = c * kGrain; w < std::min(count, (c + 1) * kGrain); ++w) {
+                const uint64_t off = work.offset[w], end = off + work.n[w];
+                cut[w] = split_samples == 0 ? end : std::min(std::max(split_samples, off), end);
+                kw += cut[w] > off;
+                ko += end > cut[w];
+            }
+            cw[c + 1] = kw;
+            co[c + 1] = ko;
+        });
+        for (size_t c = 0; c < nch; ++c) {
+            cw[c + 1] += cw[c];
+            co[c + 1] += co[c];
         }
+        for_chunks(nch, [&](size_t c) {
+            int64_t kw = cw[c], ko = co[c];
+            for (size_t w = c * kGrain; w < std::min(count, (c + 1) * kGrain); ++w) {
+                const uint64_t off = work.offset[w], end = off + work.n[w];
+                pos->wpos[w] = cut[w] > off ? kw++ : -1;
+                pos->opos[w] = end > cut[w] ? ko++ : -1;
+            }
+        });
+        const int64_t nw = cw[nch], no = co[nch];
         pos->nw = nw;
         pos->no = no;
         if (nw > std::numeric_limits<int32_t>::max() || no > std::numeric_limits<int32_t>::max())
@@ -1162,19 +1181,23 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
         }
         if (n_leaves)
             *n_leaves = L.size();
+        // the partition out, in parallel chunks (hundreds of megabytes at a
+        // million leaves, into pages the caller has mostly not touched yet)
         const size_t m = std::min(cap, L.size());
-        for (size_t s = 0; s < m; ++s) {
+        const size_t nout = (m + kGrain - 1) / kGrain;
+        for_chunks(nout, [&](size_t c) {
+            const size_t b = c * kGrain, e = std::min(m, b + kGrain);
             if (leaf_id)
-                leaf_id[s] = L.id[s];
+                std::memcpy(leaf_id + b, &L.id[b], (e - b) * sizeof(uint64_t));
             if (leaf_n)
-                leaf_n[s] = L.n[s];
+                std::memcpy(leaf_n + b, &L.n[b], (e - b) * sizeof(uint64_t));
             if (leaf_offset)
-                leaf_offset[s] = 0;
+                std::memset(leaf_offset + b, 0, (e - b) * sizeof(uint64_t));
             if (leaf_lo)
-                std::memcpy(leaf_lo + s * d, &L.lo[s * d], d * sizeof(double));
+                std::memcpy(leaf_lo + b * d, &L.lo[b * d], (e - b) * d * sizeof(double));
             if (leaf_hi)
-                std::memcpy(leaf_hi + s * d, &L.hi[s * d], d * sizeof(double));
-        }
+                std::memcpy(leaf_hi + b * d, &L.hi[b * d], (e - b) * d * sizeof(double));
+        });
         if (status == BFI_EBUDGET)
             fail(BFI_EBUDGET, "stopped after %d rounds at relative error %.3g (target %.3g)", rounds,
                  rel_err(res), cfg->target_rel_err);

@@ -213,11 +213,15 @@ bfi_status ResidentEval::prepare(uint64_t seed)
     BFI_HIP(grow_device(&d_items_, &cap_d_items_[0], nitems));
     BFI_HIP(grow_device(&d_item_rec_, &cap_d_items_[1], nitems * rec_len_));
     BFI_HIP(grow_device(&d_sub_rec_, &cap_d_sub_[4], nsub * rec_len_));
-    BFI_HIP(grow_pinned(&h_rec_, &cap_h_rec_, 0, nsub * rec_len_));
+    // pinned room for the records only when they come back (at a million
+    // leaves that is hundreds of megabytes, slow to pin)
+    if (copy_records_)
+        BFI_HIP(grow_pinned(&h_rec_, &cap_h_rec_, 0, nsub * rec_len_));
     if (split_) {
         BFI_HIP(grow_device(&d_item_split_, &cap_d_items_[2], nitems * 2 * d));
         BFI_HIP(grow_device(&d_sub_split_, &cap_d_sub_[5], nsub * split_len_));
-        BFI_HIP(grow_pinned(&h_split_, &cap_h_split_, 0, nsub * split_len_));
+        if (copy_records_)
+            BFI_HIP(grow_pinned(&h_split_, &cap_h_split_, 0, nsub * split_len_));
     }
     *h_params_ = EvalParams{d_base64_, d_scale64_, d_base32_, d_scale32_, d_id_, d_off_,
                             make_coef(lat_), static_cast<uint32_t>(seed),

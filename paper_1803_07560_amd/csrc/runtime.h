@@ -198,12 +198,12 @@ public:
     bfi_status finish(double *rec_out, double *split_out, double *device_ms);
     // the last finished list's records and split statistics in the pinned
     // buffers the replay copied them to (finish with NULL outputs skips the
-    // copy), valid until the next prepare
+    // copy), valid until the next prepare; with record copies on only
     const double *records() const { return h_rec_; }
     const double *split_records() const { return h_split_; }
-    // whether a replay copies its records to the host (default yes); without,
-    // they stay in device memory for a consumer queued after the replay on the
-    // context's stream, valid until the next prepare
+    // whether a replay copies its records to the host (default yes), set
+    // before prepare; without, they stay in device memory for a consumer queued
+    // after the replay on the context's stream, valid until the next prepare
     void set_copy_records(bool on) { copy_records_ = on; }
     const double *device_records() const { return d_sub_rec_; }
     const double *device_split_records() const { return d_sub_split_; }
