@@ -57,9 +57,16 @@ struct McArgs {
     uint32_t samples_per_thread;
 };
 
+// Block sizes the Monte Carlo kernels are compiled for (split statistics:
+// 256 only).
+inline bool mc_block_ok(int block)
+{
+    return block == 64 || block == 128 || block == 256 || block == 512 || block == 1024;
+}
+
 struct LaunchSpec {
     int prec;        // Precision
-    int block;       // 64, 128, 256
+    int block;       // 64, 128, 256, 512, 1024
     int split;       // 0/1
     int persistent;  // 0/1
     uint32_t grid;   // blocks

@@ -127,8 +127,8 @@ extern "C" bfi_status bfi_eval_noalloc(bfi_context *ctx, const bfi_lattice *lat,
             return fail(BFI_EDEVICE, "no scratch address for device %d", ctx->device);
 
         const bfi_launch l = resolve_launch(ctx, *lat, prec, split != nullptr, launch);
-        if (l.block != 64 && l.block != 128 && l.block != 256)
-            return fail(BFI_EINVAL, "block must be 64, 128 or 256 (got %d)", l.block);
+        if (!mc_block_ok(l.block))
+            return fail(BFI_EINVAL, "block must be 64, 128, 256, 512 or 1024 (got %d)", l.block);
         if (l.samples_per_thread < 1 || l.samples_per_thread > (1 << 20))
             return fail(BFI_EINVAL, "samples_per_thread out of range");
         const uint64_t chunk = static_cast<uint64_t>(l.samples_per_thread) * l.block;

@@ -114,8 +114,8 @@ bfi_status ResidentEval::init(bfi_context *ctx, const bfi_lattice &lat, int prec
     split_len_ = BFI_SPLIT_LEN(d_);
     launch_ = resolve_launch(ctx, lat, prec, split, launch);
     launch_.use_graph = 1;
-    if (launch_.block != 64 && launch_.block != 128 && launch_.block != 256)
-        return fail(BFI_EINVAL, "block must be 64, 128 or 256 (got %d)", launch_.block);
+    if (!mc_block_ok(launch_.block))
+        return fail(BFI_EINVAL, "block must be 64, 128, 256, 512 or 1024 (got %d)", launch_.block);
     if (launch_.samples_per_thread < 1 || launch_.samples_per_thread > (1 << 20))
         return fail(BFI_EINVAL, "samples_per_thread out of range");
     chunk_ = static_cast<uint64_t>(launch_.samples_per_thread) * launch_.block;

@@ -733,6 +733,10 @@ hipError_t dispatch_obs(const LaunchSpec &spec, Args &&...args)
             return by_prec<NX, NT, 128, false, AVG, PAIR, Op>(spec, args...);
         case 256:
             return by_prec<NX, NT, 256, false, AVG, PAIR, Op>(spec, args...);
+        case 512:
+            return by_prec<NX, NT, 512, false, AVG, PAIR, Op>(spec, args...);
+        case 1024:
+            return by_prec<NX, NT, 1024, false, AVG, PAIR, Op>(spec, args...);
         default:
             return hipErrorInvalidValue;
         }

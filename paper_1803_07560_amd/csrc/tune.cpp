@@ -1,7 +1,7 @@
 // Launch-shape autotuner and its JSON cache.
 //
 // Candidates: samples_per_thread K in {16, 32, ..., 1024} x block in
-// {64, 128, 256} x {one block per item, persistent queue}.  Each candidate runs
+// {64, 128, ..., 1024} x {one block per item, persistent queue}.  Each candidate runs
 // a resident plan over a uniform partition of [-4, 4]^d (1024 subvolumes, or
 // fewer for tiny budgets) once to warm up and three times under HIP events on
 // the context's stream; the fastest rate is kept for (nx, nt, precision, single
@@ -87,7 +87,7 @@ bfi_status bfi_autotune(bfi_context *ctx, const bfi_lattice *lat, bfi_precision 
                                      lat->antithetic ? evals_per_trial / 2 : evals_per_trial);
 
         const int Ks[] = {16, 32, 64, 128, 256, 512, 1024};
-        const int blocks[] = {64, 128, 256};
+        const int blocks[] = {64, 128, 256, 512, 1024};
         bfi_launch top{};
         double top_rate = -1.0;
         for (int persistent = 0; persistent <= 1; ++persistent)

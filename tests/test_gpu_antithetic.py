@@ -241,7 +241,7 @@ def test_pairs_tuned_apart(bfi, tmp_path):
         bfi.bfi_tune_save(tctx, path)
     finally:
         bfi.bfi_context_destroy(tctx)
-    assert got["samples_per_thread"] >= 16 and got["block"] in (64, 128, 256)
+    assert got["samples_per_thread"] >= 16 and got["block"] in (64, 128, 256, 512, 1024)
     entries = json.load(open(path))["entries"]
     mine = [e for e in entries if (e["nx"], e["nt"], e["prec"]) == (4, 2, 0)]
     assert sorted(e["pairs"] for e in mine) == [0, 1]

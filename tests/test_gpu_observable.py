@@ -69,7 +69,9 @@ def test_fp32_form(bfi, ctx, nx, nt, box):
 
 @pytest.mark.parametrize("launch", [dict(samples_per_thread=1, block=64, persistent=0),
                                     dict(samples_per_thread=64, block=256, persistent=1),
-                                    dict(samples_per_thread=16, block=128, persistent=1)])
+                                    dict(samples_per_thread=16, block=128, persistent=1),
+                                    dict(samples_per_thread=16, block=512, persistent=1),
+                                    dict(samples_per_thread=7, block=1024, persistent=0)])
 def test_launch_shapes(bfi, ctx, launch):
     sv = workloads.uniform_partition(20, 4.0, 4, per_sub=30_000)
     sv.n[3] = 17

@@ -231,6 +231,10 @@ def test_mass_term_records_match_oracle(bfi, ctx, nx, nt, obs):
     dict(samples_per_thread=64, block=256, persistent=1),
     dict(samples_per_thread=16, block=64, persistent=1),
     dict(samples_per_thread=256, block=128, persistent=1),
+    dict(samples_per_thread=3, block=512, persistent=0),
+    dict(samples_per_thread=64, block=512, persistent=1),
+    dict(samples_per_thread=5, block=1024, persistent=0),
+    dict(samples_per_thread=32, block=1024, persistent=1),
 ])
 def test_launch_shapes_agree(bfi, ctx, launch):
     nx, nt = 10, 2
@@ -238,6 +242,36 @@ def test_launch_shapes_agree(bfi, ctx, launch):
     sv.n[3] = 17
     lat_o, want, got = oracle_and_gpu(bfi, ctx, nx, nt, sv, 1, launch=bfi.launch(**launch))
     assert_sums_close(unshift(got, nx), want, nx, 1e-10)
+
+
+@pytest.mark.parametrize("block", [512, 1024])
+def test_large_blocks_every_form(bfi, ctx, block):
+    """512- and 1024-thread blocks (the 1024-thread kernels hold 128 registers
+    and spill): the FP64 forms within 1e-10 of the oracle's sums, the FP32 form
+    within its stated 1e-4, persistent and grid launches bit-identical."""
+    nx, nt = 10, 2
+    sv = workloads.random_partition(20, 4.0, 6, per_sub=50_000, seed=block)
+    sv.n[1] = 2
+    sv.n[4] = 3 * block * 8 + 5
+    lat_o = oracle.lattice(nx, nt)
+    want = oracle.sums(lat_o, 9, sv.ids, sv.lo, sv.hi, sv.n, sv.offset)
+    lat = bfi.lattice(nx, nt)
+    for prec in (F64, "fp64s"):
+        got = bfi.bfi_eval(ctx, lat, prec, 9, sv, bfi.launch(8, block, 1))
+        assert_sums_close(unshift(got, nx), want, nx, 1e-10)
+        grid = bfi.bfi_eval(ctx, lat, prec, 9, sv, bfi.launch(8, block, 0))
+        assert np.array_equal(grid, got)
+    got32 = bfi.bfi_eval(ctx, lat, F32, 9, sv, bfi.launch(8, block, 1))
+    assert_result_close_l1(bfi.bfi_finalize(lat, sv, got32),
+                           oracle.finalize(nx, 20, sv.lo, sv.hi, want), 1e-4, lat_o, sv, 9)
+    assert np.array_equal(bfi.bfi_eval(ctx, lat, F32, 9, sv, bfi.launch(8, block, 0)), got32)
+
+
+def test_block_sizes_outside_the_compiled_set_rejected(bfi, ctx):
+    sv = workloads.uniform_partition(8, 4.0, 2, per_sub=1000)
+    for block in (32, 192, 384, 2048):
+        with pytest.raises(bfi.BfiError):
+            bfi.bfi_eval(ctx, bfi.lattice(4, 2), F64, 1, sv, bfi.launch(16, block, 1))
 
 
 def test_persistent_equals_grid_bitwise(bfi, ctx):
