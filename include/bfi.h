@@ -134,8 +134,8 @@ typedef struct {
 typedef struct {
     int32_t samples_per_thread; /* K: samples each thread takes per work item */
     int32_t block;              /* threads per block: 64, 128, 256, 512 or 1024
-                                   (split statistics: 256; the N-sphere
-                                   sampler: 64, 128 or 256) */
+                                   (split statistics: 256; the Gaussian-proposal
+                                   and N-sphere samplers: 64, 128 or 256) */
     int32_t persistent;         /* 1: persistent kernel draining a device queue;
                                    0: one block per work item; -1: tuned */
     int32_t use_graph;          /* 1: replay a captured hipGraph (plans only) */

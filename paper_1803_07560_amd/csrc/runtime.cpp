@@ -574,6 +574,9 @@ bfi_status plan_build_core(bfi_context *ctx, int kind, const bfi_lattice &lat, i
     }
     if (!mc_block_ok(l.block))
         return fail(BFI_EINVAL, "block must be 64, 128, 256, 512 or 1024 (got %d)", l.block);
+    if (kind == 2 && l.block > 256)
+        return fail(BFI_EINVAL, "the Gaussian-proposal sampler takes blocks of 64, 128 or 256 "
+                                "threads (got %d)", l.block);
     if (l.samples_per_thread < 1 || l.samples_per_thread > (1 << 20))
         return fail(BFI_EINVAL, "samples_per_thread out of range");
     const uint64_t chunk = static_cast<uint64_t>(l.samples_per_thread) * l.block;

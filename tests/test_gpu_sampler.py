@@ -151,3 +151,14 @@ def test_invalid_arguments(bfi, ctx):
         with pytest.raises(bfi.BfiError) as e:
             bfi.bfi_integrate_is(ctx, lat, F64, 1, lo, hi, budget, alpha, 8)
         assert e.value.name == name
+
+
+def test_blocks_above_256_refused(bfi, ctx):
+    """The sampler's kernel is compiled for blocks of at most 256 threads."""
+    lat = bfi.lattice(4, 2)
+    ids = np.array([1, 2], np.uint64)
+    n = np.array([1000, 1000], np.uint64)
+    for block in (512, 1024):
+        with pytest.raises(bfi.BfiError) as e:
+            bfi.bfi_is_eval(ctx, lat, F64, 3, -3.0, 3.0, 0.9, ids, n, 0, bfi.launch(16, block, 1))
+        assert e.value.name == "BFI_EINVAL"
