@@ -974,14 +974,31 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             // that the scan below reads them in order; ranks [batch_lo, + size).
             // Which decisions a batch computes ahead changes no result.
             constexpr int32_t kHasAction = std::numeric_limits<int32_t>::min();
+            // with, for a leaf the floor may take, its count, cost and whether it
+            // would grow at twice the factor, all at factor 2^plan_fs (pure
+            // functions of the decision, n and the factor: computed with the
+            // batch, again for the batch's rest when the factor changes)
             struct Candidate {
                 size_t leaf;
                 int32_t act;
-                uint64_t n;
+                uint64_t n, t, cost;
+                bool grows;
             };
             std::vector<Candidate> batch;
             size_t batch_lo = 0;
-            auto candidate = [&](size_t rank) {
+            unsigned plan_fs = 0;
+            auto plan_batch = [&](size_t k0) {
+                parallel_range(batch.size() - k0, size_t(1) << 9, [&](size_t i) {
+                    Candidate &c = batch[k0 + i];
+                    if (c.act < 0)
+                        return;
+                    c.t = target_of(c.act, c.n, fs);
+                    c.cost = cost_of(c.act, c.n, c.t);
+                    c.grows = grows_of(c.act, c.n, fs, c.t);
+                });
+                plan_fs = fs;
+            };
+            auto candidate = [&](size_t rank) -> const Candidate & {
                 if (rank < batch_lo || rank >= batch_lo + batch.size()) {
                     // a leaf adds at most 2 n_max samples (counts stay within n_max):
                     // the round needs at least this many more leaves
@@ -996,8 +1013,12 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                     batch_lo = rank;
                     parallel_range(len, size_t(1) << 9, [&](size_t k) {
                         const size_t s = order[rank + k];
-                        batch[k] = Candidate{s, action[s] == -1 ? act(s) : kHasAction, L.n[s]};
+                        batch[k] = Candidate{s, action[s] == -1 ? act(s) : kHasAction, L.n[s],
+                                             0, 0, false};
                     });
+                    plan_batch(0);
+                } else if (plan_fs != fs) {
+                    plan_batch(rank - batch_lo);
                 }
                 return batch[rank - batch_lo];
             };
@@ -1011,36 +1032,40 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
                 // the scan only moves forward and a batch holds ranks from the
                 // scan's position on, so its view of which leaves have an action
                 // (those decide() gave one) stays current
-                Candidate c{0, kHasAction, 0};
-                while (next_leaf < order.size() && (c = candidate(next_leaf)).act == kHasAction)
+                const Candidate *c = nullptr;
+                while (next_leaf < order.size() && (c = &candidate(next_leaf))->act == kHasAction)
                     ++next_leaf;
                 if (next_leaf == order.size())
                     break;
                 ++next_leaf;
-                if (c.act < 0)
+                if (c->act < 0)
                     continue;  // neither split nor doubling possible: skip it
-                refined.push_back(c.leaf);
-                const uint64_t t = target_of(c.act, c.n, fs);
-                pend_act.push_back(c.act);
-                pend_target.push_back(t);
-                planned += cost_of(c.act, c.n, t);
-                growable += grows_of(c.act, c.n, fs, t);
+                refined.push_back(c->leaf);
+                pend_act.push_back(c->act);
+                pend_target.push_back(c->t);
+                planned += c->cost;
+                growable += c->grows;
             }
             flush();
             sub.reset();
             sub.emplace("adaptive: budget trim");
             // trim to the evaluation budget in priority order (every refined leaf
-            // lies in the part of the ranking read so far)
+            // lies in the part of the ranking read so far); `planned` is the
+            // plan's whole cost, so a plan within the budget needs no pass
             uint64_t cost = 0;
-            for (size_t i = 0; i < order.sorted(); ++i) {
-                const size_t s = order[i];
-                if (action[s] < 0)
-                    continue;
-                const uint64_t c = action[s] == 0 ? target[s] - L.n[s] : 2 * target[s];
-                if (evals + cost + c > cfg->max_evals)
-                    action[s] = -1;
-                else
-                    cost += c;
+            if (evals <= cfg->max_evals && planned <= cfg->max_evals - evals) {
+                cost = planned;
+            } else {
+                for (size_t i = 0; i < order.sorted(); ++i) {
+                    const size_t s = order[i];
+                    if (action[s] < 0)
+                        continue;
+                    const uint64_t c = action[s] == 0 ? target[s] - L.n[s] : 2 * target[s];
+                    if (evals + cost + c > cfg->max_evals)
+                        action[s] = -1;
+                    else
+                        cost += c;
+                }
             }
             sub.reset();
             if (cost == 0) {
