@@ -130,6 +130,52 @@ int32_t action_of(const SplitChoice &c, uint64_t id, uint64_t n, const bfi_adapt
     return doubling_ok ? 0 : -1;
 }
 
+// A growable array of trivially copyable elements on malloc/realloc: past the
+// allocator's mmap threshold, growth remaps pages instead of copying them, so a
+// leaf set of gigabytes grows without being copied; new elements are not
+// initialised.
+template <class T>
+class GrowArray {
+public:
+    GrowArray() = default;
+    GrowArray(const GrowArray &) = delete;
+    GrowArray &operator=(const GrowArray &) = delete;
+    ~GrowArray() { std::free(p_); }
+    size_t size() const { return n_; }
+    size_t capacity() const { return cap_; }
+    T *data() { return p_; }
+    const T *data() const { return p_; }
+    T &operator[](size_t i) { return p_[i]; }
+    const T &operator[](size_t i) const { return p_[i]; }
+    T *begin() { return p_; }
+    T *end() { return p_ + n_; }
+    const T *begin() const { return p_; }
+    const T *end() const { return p_ + n_; }
+    void resize(size_t n)
+    {
+        if (n > cap_) {
+            const size_t c = std::max(n, 2 * cap_);
+            void *q = std::realloc(p_, c * sizeof(T));
+            if (!q)
+                throw std::bad_alloc();
+            p_ = static_cast<T *>(q);
+            cap_ = c;
+        }
+        n_ = n;
+    }
+    template <class It>
+    void assign(It b, It e)
+    {
+        resize(static_cast<size_t>(e - b));
+        std::copy(b, e, p_);
+    }
+
+private:
+    static_assert(std::is_trivially_copyable<T>::value, "plain data only");
+    T *p_ = nullptr;
+    size_t n_ = 0, cap_ = 0;
+};
+
 // Leaves in ranking order (descending contribution e, ties by lower id), built
 // lazily: for e >= 0 the IEEE bit pattern orders like the value, so one
 // parallel pass counts the leaves per bucket of its top bits; a read at rank i
@@ -158,9 +204,12 @@ public:
             sums[c] = sum;
         });
         hist_.assign(kBuckets, 0);
-        for (const auto &h : part_)
-            for (size_t b = 0; b < kBuckets; ++b)
-                hist_[b] += h[b];
+        constexpr size_t kHistGrain = 1024;
+        for_chunks(kBuckets / kHistGrain, [&](size_t g) {
+            for (const auto &h : part_)
+                for (size_t b = g * kHistGrain; b < (g + 1) * kHistGrain; ++b)
+                    hist_[b] += h[b];
+        });
         total_ = 0.0;
         for (double x : sums)
             total_ += x;
@@ -211,6 +260,7 @@ private:
     // parallel.
     void extend(size_t want)
     {
+        TraceRange tr("adaptive: ranking extension");
         const size_t n = n_;
         const size_t target = std::min(n, std::max({want, 2 * keys_.size(), size_t(4096)}));
         size_t have = keys_.size(), lo = top_;
@@ -237,10 +287,21 @@ private:
                     keys_[at[hi - 1 - b]++] = Key{e_[s], ids_[s], s};
             }
         });
-        for_chunks(span, [&](size_t k) {
-            if (first[k + 1] - first[k] > 1)
-                std::sort(keys_.begin() + static_cast<std::ptrdiff_t>(first[k]),
-                          keys_.begin() + static_cast<std::ptrdiff_t>(first[k + 1]), before);
+        // each bucket sorted on its own, consecutive buckets in runs of about
+        // 1/64 of the keys per task (the top buckets are many and sparse)
+        const size_t per_run = std::max<size_t>((first[span] - start) / 64, 1024);
+        std::vector<size_t> run_first{0};
+        for (size_t k = 0, cnt = 0; k < span; ++k) {
+            cnt += first[k + 1] - first[k];
+            if (cnt >= per_run || k + 1 == span) {
+                run_first.push_back(k + 1);
+                cnt = 0;
+            }
+        }
+        for_chunks(run_first.size() - 1, [&](size_t r) {
+            for (size_t k = run_first[r]; k < run_first[r + 1]; ++k)
+                if (first[k + 1] - first[k] > 1)
+                    std::sort(keys_.begin() + first[k], keys_.begin() + first[k + 1], before);
         });
         top_ = lo;
     }
@@ -251,7 +312,7 @@ private:
     std::vector<std::vector<uint32_t>> part_;  // per chunk: leaves per bucket
     std::vector<uint16_t> bucket_;             // per leaf
     std::vector<uint32_t> hist_;
-    std::vector<Key> keys_;
+    GrowArray<Key> keys_;  // grown without initialising: the scatter writes every key
     double total_ = 0.0;
     size_t top_;  // buckets at or above it are in keys_
 };
@@ -338,52 +399,6 @@ void record_fields(int nx, std::vector<int> *first, std::vector<int> *second)
         second->push_back(4 + 2 * nx + r);
     }
 }
-
-// A growable array of trivially copyable elements on malloc/realloc: past the
-// allocator's mmap threshold, growth remaps pages instead of copying them, so a
-// leaf set of gigabytes grows without being copied; new elements are not
-// initialised.
-template <class T>
-class GrowArray {
-public:
-    GrowArray() = default;
-    GrowArray(const GrowArray &) = delete;
-    GrowArray &operator=(const GrowArray &) = delete;
-    ~GrowArray() { std::free(p_); }
-    size_t size() const { return n_; }
-    size_t capacity() const { return cap_; }
-    T *data() { return p_; }
-    const T *data() const { return p_; }
-    T &operator[](size_t i) { return p_[i]; }
-    const T &operator[](size_t i) const { return p_[i]; }
-    T *begin() { return p_; }
-    T *end() { return p_ + n_; }
-    const T *begin() const { return p_; }
-    const T *end() const { return p_ + n_; }
-    void resize(size_t n)
-    {
-        if (n > cap_) {
-            const size_t c = std::max(n, 2 * cap_);
-            void *q = std::realloc(p_, c * sizeof(T));
-            if (!q)
-                throw std::bad_alloc();
-            p_ = static_cast<T *>(q);
-            cap_ = c;
-        }
-        n_ = n;
-    }
-    template <class It>
-    void assign(It b, It e)
-    {
-        resize(static_cast<size_t>(e - b));
-        std::copy(b, e, p_);
-    }
-
-private:
-    static_assert(std::is_trivially_copyable<T>::value, "plain data only");
-    T *p_ = nullptr;
-    size_t n_ = 0, cap_ = 0;
-};
 
 // The host side of the leaf set: ids, sample counts, boxes and volumes.  The
 // records stay in device memory (DeviceLeaves).
@@ -1024,6 +1039,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             };
             while (cfg->round_evals > 0 && planned < cfg->round_evals) {
                 if (growable > 0) {
+                    TraceRange tr("adaptive: replan at twice the factor");
                     ++fs;
                     flush();
                     plan_all();
