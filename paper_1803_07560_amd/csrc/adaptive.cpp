@@ -1161,9 +1161,25 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             std::optional<TraceRange> grow_range(std::in_place, "adaptive: leaf set growth");
             dst.resize(origin.size());
             const size_t before = L.size();
-            size_t grown = before;
-            for (size_t w = 0; w < origin.size(); ++w)
-                dst[w] = origin[w].kind == 2 ? grown++ : origin[w].leaf;
+            // upper children numbered from `before` in list order: counts per
+            // chunk of entries, the chunks' starts, then each chunk's numbers
+            const size_t nwc = (origin.size() + kGrain - 1) / kGrain;
+            std::vector<size_t> upper_start(nwc + 1, 0);
+            for_chunks(nwc, [&](size_t c) {
+                size_t k = 0;
+                for (size_t w = c * kGrain; w < std::min(origin.size(), (c + 1) * kGrain); ++w)
+                    k += origin[w].kind == 2;
+                upper_start[c + 1] = k;
+            });
+            upper_start[0] = before;
+            for (size_t c = 0; c < nwc; ++c)
+                upper_start[c + 1] += upper_start[c];
+            for_chunks(nwc, [&](size_t c) {
+                size_t next = upper_start[c];
+                for (size_t w = c * kGrain; w < std::min(origin.size(), (c + 1) * kGrain); ++w)
+                    dst[w] = origin[w].kind == 2 ? next++ : origin[w].leaf;
+            });
+            const size_t grown = upper_start[nwc];
             L.id.resize(grown);
             L.n.resize(grown);
             L.lo.resize(grown * d);
