@@ -112,21 +112,25 @@ __device__ __forceinline__ size_t nblocks_of(uint32_t count)
     return (static_cast<size_t>(count) + kAnalysisBlock - 1) / kAnalysisBlock;
 }
 
-// Sum of v over the block in a fixed order: wavefront butterflies, then the
-// waves in order; thread 0 gets the sum.
-__device__ __forceinline__ double block_sum(double v, double *lds_waves)
+// A block's sums of several terms in a fixed order: each term's wavefront
+// butterflies (wave_part), then, after one barrier, thread j adds term j's
+// wave sums in wave order (block_parts_out).
+constexpr int kAnalysisWaves = kAnalysisBlock / 64;
+__device__ __forceinline__ void wave_part(double v, double (*lds)[kAnalysisWaves], int j)
 {
     const double s = dev::wave_sum(v);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0)
-        lds_waves[wave] = s;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int k = 0; k < kAnalysisBlock / 64; ++k)
-            t += lds_waves[k];
-    __syncthreads();
-    return t;
+    if ((threadIdx.x & 63) == 0)
+        lds[j][threadIdx.x >> 6] = s;
+}
+__device__ __forceinline__ void block_parts_out(const double (*lds)[kAnalysisWaves], int count,
+                                                double *part)
+{
+    if (static_cast<int>(threadIdx.x) < count) {
+        double t = 0.0;
+        for (int k = 0; k < kAnalysisWaves; ++k)
+            t += lds[threadIdx.x][k];
+        part[threadIdx.x] = t;
+    }
 }
 
 __global__ void __launch_bounds__(kAnalysisBlock) shift_kernel(LeafAnalysisArgs a)
@@ -174,7 +178,7 @@ __global__ void __launch_bounds__(kAnalysisBlock) shift_reduce_kernel(LeafAnalys
 
 __global__ void __launch_bounds__(kAnalysisBlock) first_pass_kernel(LeafAnalysisArgs a)
 {
-    __shared__ double lds[kAnalysisBlock / 64];
+    __shared__ double lds[4 + kMaxAnalysisNx][kAnalysisWaves];
     const size_t nb = nblocks_of(a.count);
     const int nx = a.nx, rec_len = 4 + 3 * nx, nt = 4 + nx;
     const double sig = a.scratch[nb * (1 + 4 + 2 * nx)];
@@ -205,10 +209,10 @@ __global__ void __launch_bounds__(kAnalysisBlock) first_pass_kernel(LeafAnalysis
             else
                 t = vol * aa * rec[j] / n;
         }
-        const double bt = block_sum(t, lds);
-        if (threadIdx.x == 0)
-            part[j] = bt;
+        wave_part(t, lds, j);
     }
+    __syncthreads();
+    block_parts_out(lds, nt, part);
 }
 
 // Neumaier sum of the blocks' partial sums in block order; thread j takes sum
@@ -283,7 +287,7 @@ __device__ void split_choice(const double *sp, const double *base, int d, int32_
 
 __global__ void __launch_bounds__(kAnalysisBlock) second_pass_kernel(LeafAnalysisArgs a)
 {
-    __shared__ double lds[kAnalysisBlock / 64];
+    __shared__ double lds[kMaxAnalysisNx][kAnalysisWaves];
     const size_t nb = nblocks_of(a.count);
     const int nx = a.nx, d = a.d, rec_len = 4 + 3 * nx, split_len = 1 + 2 * d;
     const double *scal = a.scratch + nb * (1 + 4 + 2 * nx);
@@ -316,10 +320,10 @@ __global__ void __launch_bounds__(kAnalysisBlock) second_pass_kernel(LeafAnalysi
             t = var_n - 2.0 * C * cov + C * C * var_z;
             e += t;
         }
-        const double bt = block_sum(t, lds);
-        if (threadIdx.x == 0)
-            part[r] = bt;
+        wave_part(t, lds, r);
     }
+    __syncthreads();
+    block_parts_out(lds, nx, part);
     if (!on)
         return;
     // the host's max(e, 0) / Z^2, read back as a contribution (NaN counts 0)
