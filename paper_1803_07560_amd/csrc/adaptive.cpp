@@ -1185,7 +1185,10 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             L.lo.resize(grown * d);
             L.hi.resize(grown * d);
             L.vol.resize(grown);
-            BFI_TRY(DL.reserve(grown, before));
+            {
+                TraceRange tr("adaptive: device leaf buffers");
+                BFI_TRY(DL.reserve(grown, before));
+            }
             grow_range.reset();
             phase.next("adaptive: evaluate and fold");
             // pinned room for the fold entries first: freeing a pinned buffer
