@@ -609,7 +609,7 @@ bfi_status bfi_server_stats_get(bfi_server *srv, bfi_server_stats *out);
 bfi_status bfi_server_destroy(bfi_server *srv);
 
 /* Autotuner: time candidate launch shapes (samples_per_thread in 16..1024 x
- * block x persistent) on a synthetic uniform partition of the lattice with about
+ * block in 64..1024 x persistent) on a synthetic uniform partition of the lattice with about
  * `evals_per_trial` evaluations, keep the fastest for (shape, precision, single
  * points or antithetic pairs, observable -- lat->antithetic, lat->observable) in
  * the context, and return it with its rate.  A plan without an entry of its own
