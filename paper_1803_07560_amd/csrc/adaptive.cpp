@@ -694,27 +694,40 @@ bfi_status launch_list(Evaluators *ev, const bfi_lattice &lat, uint64_t seed, co
             return fail(BFI_EINVAL, "more than 2^31 entries in one pass");
         BFI_TRY(ev->with.stage(static_cast<size_t>(nw)));
         BFI_TRY(ev->without.stage(static_cast<size_t>(no)));
+        // every entry of the split pass; the plain pass's counts only (its
+        // boxes are written while the split pass runs)
         parallel_range(count, kGrain, [&](size_t w) {
             const uint64_t off = work.offset[w], end = off + work.n[w];
-            const double *lo = &work.lo[w * d], *hi = &work.hi[w * d];
             if (pos->wpos[w] >= 0)
-                ev->with.set(static_cast<size_t>(pos->wpos[w]), work.id[w], off, cut[w] - off, lo,
-                             hi);
+                ev->with.set(static_cast<size_t>(pos->wpos[w]), work.id[w], off, cut[w] - off,
+                             &work.lo[w * d], &work.hi[w * d]);
             if (pos->opos[w] >= 0)
-                ev->without.set(static_cast<size_t>(pos->opos[w]), work.id[w], cut[w],
-                                end - cut[w], lo, hi);
+                ev->without.set_counts(static_cast<size_t>(pos->opos[w]), work.id[w], cut[w],
+                                       end - cut[w]);
         });
     }
-    // both replays prepared, then queued back to back on the stream
-    TraceRange tr("adaptive: prepare and launch");
-    if (pos->nw > 0)
-        BFI_TRY(ev->with.prepare(seed));
-    if (pos->no > 0)
-        BFI_TRY(ev->without.prepare(seed));
-    if (pos->nw > 0)
-        BFI_TRY(ev->with.launch());
-    if (pos->no > 0)
+    {
+        // both replays prepared (allocation, capture and update while the
+        // device is idle), the split pass queued first
+        TraceRange tr("adaptive: prepare and launch");
+        if (pos->nw > 0)
+            BFI_TRY(ev->with.prepare(seed));
+        if (pos->no > 0)
+            BFI_TRY(ev->without.prepare(seed));
+        if (pos->nw > 0)
+            BFI_TRY(ev->with.launch());
+    }
+    if (pos->no > 0) {
+        {
+            TraceRange tr("adaptive: plain pass boxes (while the split pass runs)");
+            parallel_range(count, kGrain, [&](size_t w) {
+                if (pos->opos[w] >= 0)
+                    ev->without.set_box(static_cast<size_t>(pos->opos[w]), &work.lo[w * d],
+                                        &work.hi[w * d]);
+            });
+        }
         BFI_TRY(ev->without.launch());
+    }
     return BFI_OK;
 }
 

@@ -176,10 +176,21 @@ public:
     void set(size_t i, uint64_t id, uint64_t offset, uint64_t n, const double *lo,
              const double *hi)
     {
-        const size_t d = static_cast<size_t>(d_);
+        set_counts(i, id, offset, n);
+        set_box(i, lo, hi);
+    }
+    // the two halves of set: prepare reads the counts; the boxes are read only
+    // when the replay copies them to the device, so they may be written after
+    // prepare and before launch
+    void set_counts(size_t i, uint64_t id, uint64_t offset, uint64_t n)
+    {
         h_id_[i] = id;
         h_off_[i] = offset;
         h_n_[i] = n;
+    }
+    void set_box(size_t i, const double *lo, const double *hi)
+    {
+        const size_t d = static_cast<size_t>(d_);
         std::copy(lo, lo + d, h_lo_ + i * d);
         std::copy(hi, hi + d, h_hi_ + i * d);
     }
