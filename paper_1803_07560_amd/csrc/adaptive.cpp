@@ -903,7 +903,9 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             }
             if (stop)
                 break;
-            if (rounds >= cfg->max_rounds) {
+            // every action costs samples (a doubling at least n, a split at least
+            // 2 n_min): with the budget spent the trim below would drop them all
+            if (rounds >= cfg->max_rounds || evals >= cfg->max_evals) {
                 status = BFI_EBUDGET;
                 break;
             }
