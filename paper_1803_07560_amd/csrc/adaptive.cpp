@@ -484,7 +484,7 @@ public:
                         static_cast<void *>(h_fold_)})
             if (p)
                 (void)hipHostFree(p);
-        for (hipEvent_t ev : {ev_f0_, ev_f1_, ev_a0_, ev_a1_})
+        for (hipEvent_t ev : {ev_f0_, ev_f1_, ev_a0_, ev_e_, ev_a1_})
             if (ev)
                 (void)hipEventDestroy(ev);
     }
@@ -566,21 +566,15 @@ public:
         BFI_HIP(hipMemcpyAsync(h_totals_, totals_d_, ntot * sizeof(double), hipMemcpyDeviceToHost,
                                st));
         BFI_HIP(hipMemcpyAsync(h_e_, e_d_, count * sizeof(double), hipMemcpyDeviceToHost, st));
+        BFI_HIP(hipEventRecord(ev_e_, st));
+        // the split choices come back while the host ranks the leaves by e
+        // (wait_choices before reading them)
         BFI_HIP(hipMemcpyAsync(h_gain_, gain_d_, count * sizeof(double), hipMemcpyDeviceToHost, st));
         BFI_HIP(hipMemcpyAsync(h_best_, best_d_, count * sizeof(int32_t), hipMemcpyDeviceToHost,
                                st));
         BFI_HIP(hipEventRecord(ev_a1_, st));
-        BFI_HIP(hipEventSynchronize(ev_a1_));
-        float ms = 0.0f;
-        BFI_HIP(hipEventElapsedTime(&ms, ev_a0_, ev_a1_));
-        if (device_ms)
-            *device_ms += ms;
-        if (folded_) {
-            BFI_HIP(hipEventElapsedTime(&ms, ev_f0_, ev_f1_));
-            if (device_ms)
-                *device_ms += ms;
-            folded_ = false;
-        }
+        choices_pending_ = true;
+        BFI_HIP(hipEventSynchronize(ev_e_));
         // the estimate from the totals, as the finalize forms it
         std::memset(res, 0, sizeof(*res));
         res->nx = nx_;
@@ -599,6 +593,26 @@ public:
         }
         return BFI_OK;
     }
+    // wait for the last analysis's split choices (best(), gain()); its device
+    // time, and the fold's before it, go to device_ms
+    bfi_status wait_choices(double *device_ms)
+    {
+        if (!choices_pending_)
+            return BFI_OK;
+        choices_pending_ = false;
+        BFI_HIP(hipEventSynchronize(ev_a1_));
+        float ms = 0.0f;
+        BFI_HIP(hipEventElapsedTime(&ms, ev_a0_, ev_a1_));
+        if (device_ms)
+            *device_ms += ms;
+        if (folded_) {
+            BFI_HIP(hipEventElapsedTime(&ms, ev_f0_, ev_f1_));
+            if (device_ms)
+                *device_ms += ms;
+            folded_ = false;
+        }
+        return BFI_OK;
+    }
     const double *e() const { return h_e_; }
     const int32_t *best() const { return h_best_; }
     const double *gain() const { return h_gain_; }
@@ -607,7 +621,7 @@ private:
     bfi_status events()
     {
         if (!ev_f0_)
-            for (hipEvent_t *ev : {&ev_f0_, &ev_f1_, &ev_a0_, &ev_a1_})
+            for (hipEvent_t *ev : {&ev_f0_, &ev_f1_, &ev_a0_, &ev_e_, &ev_a1_})
                 BFI_HIP(hipEventCreate(ev));
         return BFI_OK;
     }
@@ -622,7 +636,9 @@ private:
     double *h_e_ = nullptr, *h_gain_ = nullptr, *h_totals_ = nullptr;
     int32_t *h_best_ = nullptr;
     size_t cap_he_ = 0, cap_hg_ = 0, cap_hb_ = 0, cap_htotals_ = 0;
-    hipEvent_t ev_f0_ = nullptr, ev_f1_ = nullptr, ev_a0_ = nullptr, ev_a1_ = nullptr;
+    hipEvent_t ev_f0_ = nullptr, ev_f1_ = nullptr, ev_a0_ = nullptr, ev_e_ = nullptr,
+               ev_a1_ = nullptr;
+    bool choices_pending_ = false;
     bool folded_ = false;
 };
 
@@ -917,6 +933,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             };
             std::optional<TraceRange> sub(std::in_place, "adaptive: rank and decide");
             Ranking order(e, L.size(), L.id.data());
+            BFI_TRY(DL.wait_choices(&ev.device_ms));
             const size_t examined = decide(e, L.size(), act, *cfg, action.data(), order);
             // the refined leaves in rank order (planning loops over these only)
             refined.clear();
@@ -1240,6 +1257,7 @@ bfi_status bfi_integrate_adaptive(bfi_context *ctx, const bfi_lattice *lat, bfi_
             ++rounds;
         }
 
+        BFI_TRY(DL.wait_choices(&ev.device_ms));
         *out = res;
         if (stats) {
             stats->rounds = rounds;
